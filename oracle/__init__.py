@@ -1,0 +1,35 @@
+"""Plain FP64 CPU oracle for the adaptive-multigrid / LPT hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product path
+(``paper_1103_6031_amd``) never imports, calls or links anything here, and the
+oracle imports nothing from the product package: the two share no code.
+
+Everything is written from Hahn & Abel, "Multi-scale initial conditions for
+cosmological simulations" (MNRAS 2011):
+
+* ``stencil``  - Table 1 operators (7-point Laplacian, 4th-order gradient),
+                 restriction / injection of Section 3.2, periodic wrap.
+* ``periodic`` - the FAS V-cycle of Section 3.2 (nine steps, red-black
+                 Gauss-Seidel, nu1 = nu2 = 2) and the exact discrete periodic
+                 solve by eigenvalue division (Table 1 symbols).
+* ``zoom``     - the adaptive multigrid of Section 3.3: nested patches, ghost
+                 zones by polynomial interpolation parallel then normal to the
+                 face, flux matching with the Table 2 order-1 flux operator,
+                 composite residual, post-solve wide ghosts.
+* ``lpt``      - Section 3.1: first-order displacements from the gradient of
+                 the potential and the second-order source term tau.
+* ``dense``    - brute-force dense assembly of the periodic and composite
+                 linear systems for tiny grids (pins for the iterative solvers).
+
+Precision: float64 throughout.  Speed: slow by design (numpy whole-array
+operations, no blocking, no fusion).
+
+Readings taken where the paper is silent or ambiguous are listed in each
+module's header.  Parity unpinned: none of the functions here - every one is
+checked in ``tests/test_oracle_*.py`` against closed forms, Table 1 symbols,
+brute-force dense solves or invariants that do not reuse the oracle's own
+arithmetic.
+"""
+
+from . import stencil, periodic, lpt, zoom, dense  # noqa: F401
