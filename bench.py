@@ -1,0 +1,161 @@
+"""Benchmark of the adaptive-multigrid 2LPT hot path on one MI355X.
+
+One step = the whole hot path over one synthetic input resident in HBM:
+    phi1 = solve(delta)            FAS V(2,2) cycles to a 1e-10 relative residual
+    psi1 = -G4 phi1                first-order displacements
+    tau  = sum_{i>j} D_ii D_jj - D_ij^2 (D = G4 G4), composite mean removed
+    phi2 = solve(tau)
+    psi2 = -3/7 G4 phi2            second-order displacements
+Default workload: periodic 256^3, BBKS spectrum (Gamma = 0.2), 100 Mpc/h box, density rms 0.1,
+seed 1103002.  The headline path is mixed precision (FP32 smoother / transfers inside an FP64
+defect-correction loop); the plain FP64 path is timed beside it.
+
+Prints ONE JSON line.  `value` is cell-updates per second of the headline path (smoother
+cell-updates summed over all levels and both solves, divided by the step time).  `roofline`
+is the finest-level smoother kernel: algorithmic bytes (3 words per cell-update) over its
+average launch duration, timed with HIP events on its own stream inside the timed region.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s + HBM GB/s; mixed vs FP64 at 1e-8 rel. RMS; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
+    ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed", help="headline path")
+    return ap.parse_args()
+
+
+def run_step(mg, H, ft, h, opts, ws):
+    phi1, s1 = mg.mg_solve_level(ft, h, opts=opts, workspace=ws["solve"])
+    psi1 = mg.lpt_displacements(H, [phi1], scale=-1.0, workspace=ws["lpt1"])[0]
+    tau = mg.lpt2_source(H, [phi1], workspace=ws["lpt2"])[0]
+    phi2, s2 = mg.mg_solve_level(tau, h, opts=opts, workspace=ws["solve"])
+    psi2 = mg.lpt_displacements(H, [phi2], scale=-3.0 / 7.0, workspace=ws["lpt1"])[0]
+    return (phi1, psi1, tau, phi2, psi2), (s1, s2)
+
+
+def time_path(mg, torch, H, ft, h, prec, tol, steps, warmup):
+    opts = mg.make_opts(tol=tol, prec=prec, max_cycles=60)
+    ws = {"solve": mg.Workspace(mg.mg_workspace_bytes(H, opts)),
+          "lpt1": mg.Workspace(mg.lpt_workspace_bytes(H, 1)),
+          "lpt2": mg.Workspace(mg.lpt_workspace_bytes(H, 2))}
+    for _ in range(warmup):
+        out, st = run_step(mg, H, ft, h, opts, ws)
+    torch.cuda.synchronize()
+    mg.mg_kprof_read()            # drop anything recorded so far
+    mg.mg_kprof_enable(True)
+    t0 = time.perf_counter()
+    ups = 0
+    cycles = []
+    for _ in range(steps):
+        out, st = run_step(mg, H, ft, h, opts, ws)
+        ups += st[0]["cell_updates"] + st[1]["cell_updates"]
+        cycles.append((st[0]["cycles"], st[1]["cycles"]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mg.mg_kprof_enable(False)
+    kms, klaunch, kbytes = mg.mg_kprof_read()
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
+    res = dict(ms_per_step=1e3 * dt / steps, value=ups / dt / 1e6, cycles=cycles[-1],
+               rel_res=(st[0]["rel_res"], st[1]["rel_res"]),
+               kernel=dict(launches=klaunch, avg_us=1e3 * kms / max(klaunch, 1),
+                           bytes_per_launch=kbytes / max(klaunch, 1), achieved_gbs=achieved))
+    return res, out
+
+
+def cpu_baseline(f, h):
+    """The oracle's FAS V-cycle on the same input: a bounded sample of two cycles."""
+    import numpy as np
+    from oracle import periodic
+    fz = f - f.mean()
+    u = np.zeros_like(fz)
+    t0 = time.perf_counter()
+    ncyc = 2
+    for _ in range(ncyc):
+        u = periodic.vcycle(u, fz, h)
+    dt = time.perf_counter() - t0
+    ups = periodic.cell_updates(f.shape[0], ncyc)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = os.cpu_count()
+    return dict(value=ups / dt / 1e6, unit="Mcell-updates/s", cores=1, kind="oracle",
+                sample="%d FAS V(2,2) cycles of the numpy oracle on the same %d^3 input (%.1f s); "
+                       "single-threaded numpy, 1 core used of %d" % (ncyc, f.shape[0], dt, affinity))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the multigrid hot path here runs on a single device "
+              "(multi-GPU sharding is described in DESIGN.md but not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1103_6031_amd import inputs, mgic as mg
+
+    N = a.n
+    h = inputs.BOX / N
+    f = inputs.gaussian_field(N, inputs.SEED_C2)
+    ft = torch.from_numpy(f).to("cuda:0")
+    H = mg.Hier(N, h)
+    torch.cuda.synchronize()
+
+    other = "fp64" if a.prec == "mixed" else "mixed"
+    head, out_h = time_path(mg, torch, H, ft, h, a.prec, a.tol, a.steps, a.warmup)
+    side, out_s = time_path(mg, torch, H, ft, h, other, a.tol, max(1, a.steps // 2), 1)
+    out_m, out_d = (out_h, out_s) if a.prec == "mixed" else (out_s, out_h)
+
+    def rel(x, y):
+        return float(torch.sqrt(torch.mean((x - y) ** 2)) / torch.sqrt(torch.mean(y ** 2)))
+
+    acc = dict(phi1=rel(out_m[0], out_d[0]), psi1=max(rel(out_m[1][c], out_d[1][c]) for c in range(3)),
+               tau=rel(out_m[2], out_d[2]), phi2=rel(out_m[3], out_d[3]),
+               psi2=max(rel(out_m[4][c], out_d[4][c]) for c in range(3)))
+
+    k = head["kernel"]
+    roof = None
+    if k["achieved_gbs"]:
+        roof = dict(bound="hbm", achieved=round(k["achieved_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(k["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel="finest-level red-black smoother (%s)" % ("fp32" if a.prec == "mixed" else "fp64"),
+                    avg_launch_us=round(k["avg_us"], 2), launches=k["launches"],
+                    algorithmic_bytes_per_launch=int(k["bytes_per_launch"]))
+    line = dict(metric=METRIC, value=round(head["value"], 1), unit="Mcell-updates/s", n_gpus=1, steps=a.steps,
+                warmup=a.warmup, ms_per_step=round(head["ms_per_step"], 3), higher_is_better=True,
+                scaling="weak", vs_baseline=None,
+                dtype="f32+f64" if a.prec == "mixed" else "f64", data="synthetic",
+                config=dict(workload="periodic %d^3 BBKS 2LPT (solve, grad, tau, solve, grad), tol %g" % (N, a.tol),
+                            n=N, box=inputs.BOX, seed=inputs.SEED_C2, precision=a.prec, nu1=2, nu2=2),
+                roofline=roof,
+                cycles=dict(zip(("solve1", "solve2"), head["cycles"])),
+                rel_res=head["rel_res"],
+                mixed_vs_fp64_rel_rms=acc)
+    line[other + "_path"] = dict(value=round(side["value"], 1), ms_per_step=round(side["ms_per_step"], 3),
+                                 cycles=side["cycles"],
+                                 smoother_gbs=round(side["kernel"]["achieved_gbs"] or 0.0, 1),
+                                 smoother_avg_launch_us=round(side["kernel"]["avg_us"], 2))
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(f, h)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * mgic.h - C ABI of the MI355X (gfx950) adaptive-multigrid / LPT library.
+ *
+ * What it computes (Hahn & Abel 2011, "Multi-scale initial conditions for
+ * cosmological simulations"):
+ *   - the potential phi of Poisson's equation  L phi = f  on a periodic base
+ *     grid and on nested 2x zoom-in patches, by the FAS multigrid V-cycle of
+ *     Section 3.2 (red-black Gauss-Seidel, nu1 = nu2 = 2, 8-child mean
+ *     restriction, injection prolongation) extended to nested sub-grids as in
+ *     Section 3.3 (ghost zones by quadratic interpolation parallel then
+ *     normal to the coarse-fine face, flux matching with Table 2's order-1
+ *     flux operator);
+ *   - first-order (Zel'dovich) displacements  psi = scale * G phi  with the
+ *     fourth-order gradient G of Table 1 (Section 3.1, eq. "zeldovich");
+ *   - the second-order source  tau = sum_{i>j} (D_ii D_jj - D_ij^2),
+ *     D_ij = G_i G_j phi  (Section 3.1, second-order perturbations), whose
+ *     Poisson solve gives the second-order potential.
+ *
+ * Conventions shared by every entry point
+ *   - All field pointers are DEVICE pointers to float64 arrays laid out
+ *     row-major [nx][ny][nz] (z contiguous), without ghost padding.
+ *   - Level 0 of a hierarchy is the periodic base (cubic, n^3 cells, spacing
+ *     h).  Level p >= 1 is a patch of n[0] x n[1] x n[2] cells (each even,
+ *     >= 4) of spacing h_{p-1} / 2 whose first cell is the first child of
+ *     cell off[] of level p-1.  A patch in the base must not wrap and must
+ *     leave >= 2 base cells uncovered per axis; a patch in a patch keeps >= 4
+ *     parent cells from its parent's faces.
+ *   - The caller owns every buffer (inputs, outputs, workspace).  The library
+ *     never allocates device memory on these paths: it carves the caller's
+ *     workspace (size from the matching *_workspace_bytes query, any
+ *     256-byte-aligned device buffer of at least that size).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it; calls that need a host decision (per-cycle convergence
+ *     test) synchronise that stream, others are asynchronous.
+ *   - Return value: MG_OK (0) or a negative MG_E* code; mg_last_error()
+ *     returns a human-readable message for the calling thread.
+ */
+#ifndef MGIC_H
+#define MGIC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_MAX_LEVELS 8
+
+enum {
+    MG_OK = 0,
+    MG_EINVAL = -1,     /* bad argument: null pointer, size, nesting, workspace too small   */
+    MG_ENOCONV = -2,    /* max_cycles reached above tol: u holds the last iterate           */
+    MG_EDIVERGED = -3,  /* NaN/Inf residual or growth over 3 consecutive cycles             */
+    MG_EHIP = -4        /* HIP runtime error                                                 */
+};
+
+/* precision of the smoother / transfer operators */
+enum { MG_FP64 = 0, MG_MIXED = 1 };
+
+/* option flags */
+#define MG_USE_INITIAL_GUESS 0x1u  /* start from the caller's u instead of 0                    */
+#define MG_FIXED_CYCLES      0x2u  /* run exactly max_cycles cycles, no per-cycle host readback */
+
+typedef struct {
+    int n[3];       /* cells per axis (base: all three equal)                 */
+    int off[3];     /* first covered parent cell (ignored for level 0)        */
+    double h;       /* cell size; level p >= 1 must have h = h_{p-1} / 2       */
+} mg_level;
+
+typedef struct {
+    int nlev;                       /* 1 + number of patches, 1..MG_MAX_LEVELS */
+    mg_level lev[MG_MAX_LEVELS];
+} mg_hier;
+
+typedef struct {
+    double tol;         /* stop when composite ||r|| / ||f|| <= tol (relative, after a cycle's step 9) */
+    int max_cycles;     /* V-cycles (FP64) or defect-correction iterations (mixed)                    */
+    int nu1, nu2;       /* pre / post red-black Gauss-Seidel sweeps (the paper uses 2 / 2)            */
+    int prec;           /* MG_FP64 or MG_MIXED                                                        */
+    unsigned flags;     /* MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES                                     */
+} mg_opts;
+
+typedef struct {
+    int cycles;                 /* cycles (or outer iterations) run                              */
+    double rel_res;             /* final composite relative residual (NaN with MG_FIXED_CYCLES)   */
+    double f_mean_removed;      /* composite mean subtracted from f                               */
+    double res_hist[64];        /* relative residual after each cycle (first 64)                  */
+    long long cell_updates;     /* smoother cell-updates performed (all levels, both precisions)  */
+} mg_stats;
+
+/* ----------------------------------------------------------------------------------------------
+ * Multigrid solves (Section 3.2 periodic FAS; Section 3.3 adaptive FAS on nested patches)
+ * -------------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for mg_solve_level / mg_solve_hierarchy / mg_solve_batch member, exact. */
+size_t mg_workspace_bytes(const mg_hier* hier, const mg_opts* opts);
+
+/* Periodic single level: solve L u = f - mean(f) on n^3 cells of size h.
+ * n = 2^k * m with m in {1, 3, 5, 7} and n >= 2.  f (n^3 doubles) is read only.  u (n^3
+ * doubles) receives the zero-mean solution; it is read only with MG_USE_INITIAL_GUESS.
+ * stats may be NULL.  Errors: MG_EINVAL, MG_ENOCONV, MG_EDIVERGED, MG_EHIP. */
+int mg_solve_level(int n, double h, const double* f, double* u, const mg_opts* opts,
+                   mg_stats* stats, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Nested hierarchy: f[p], u[p] for p = 0..nlev-1, each with the level's cells.  Solves the
+ * composite system (fine cells and uncovered coarse cells; covered coarse cells are the mean of
+ * their 8 children) after removing the composite mean of f.  On return covered coarse cells of
+ * u hold the mean of their children and the composite mean of u is zero. */
+int mg_solve_hierarchy(const mg_hier* hier, const double* const* f, double* const* u,
+                       const mg_opts* opts, mg_stats* stats, void* workspace,
+                       size_t workspace_bytes, void* stream);
+
+/* Composite residual r = f - L u of a hierarchy (covered coarse cells of r set to 0), with
+ * f's composite mean removed first; u's covered coarse cells are first replaced by the mean of
+ * their children (u is modified only there).  Writes sqrt(sum r^2 vol) / sqrt(sum f^2 vol)
+ * to *rel (host pointer, may be NULL; synchronises the stream).  Workspace: mg_workspace_bytes. */
+int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* const* u,
+                          double* const* r, double* rel, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
+ * LPT (Section 3.1)
+ * -------------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for lpt_displacements (what = 1) or lpt2_source (what = 2). */
+size_t lpt_workspace_bytes(const mg_hier* hier, int what);
+
+/* psi_c = scale * G4_c phi on every level (Table 1 fourth-order gradient).  out[3*p + c] is the
+ * c-th component on level p.  The base wraps periodically; patch cells next to a face use
+ * width-2 ghosts interpolated tri-quadratically from the parent (covered parent cells taken as
+ * the mean of their children).  Covered coarse cells get the gradient of that mean.  phi is
+ * read only.  Asynchronous. */
+int lpt_displacements(const mg_hier* hier, const double* const* phi, double* const* out,
+                      double scale, void* workspace, size_t workspace_bytes, void* stream);
+
+/* tau[p] = sum_{i>j} (D_ii D_jj - D_ij^2) with D_ij = G4_i G4_j phi on every level (width-4
+ * ghosts on patches), then covered coarse cells replaced by the mean of their children and the
+ * composite mean removed, so tau is a compatible Poisson source.  Asynchronous. */
+int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau,
+                void* workspace, size_t workspace_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
+ * Batched independent periodic solves (many small instances in one persistent launch)
+ * -------------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for a batch of ninst periodic instances of sizes n[i]. */
+size_t mg_batch_workspace_bytes(int ninst, const int* n, const mg_opts* opts);
+
+/* Solve ninst independent periodic problems (sizes n[i], spacings h[i], device pointers f[i],
+ * u[i]; the pointer arrays themselves are host arrays).  Each instance is solved exactly as by
+ * mg_solve_level with the same options; stats (host array of ninst, may be NULL) per instance.
+ * All instances advance together, one cycle per persistent kernel launch. */
+int mg_solve_batch(int ninst, const int* n, const double* h, const double* const* f,
+                   double* const* u, const mg_opts* opts, mg_stats* stats, void* workspace,
+                   size_t workspace_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
+ * Single steps, exposed for kernel-level parity checks
+ * -------------------------------------------------------------------------------------------- */
+
+/* `half_sweeps` red/black half-sweeps (red first) of Section 3.2's smoother on a periodic n^3
+ * level in place: u <- (sum of 6 neighbours - h^2 f) / 6 on one colour.  prec = MG_FP64 works
+ * on u and f directly; MG_MIXED rounds u and f to float32, sweeps in float32 and widens back.
+ * Workspace: mg_workspace_bytes of the single level. */
+int mg_smooth_level(int n, double h, const double* f, double* u, int half_sweeps, int prec,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Flux-matched ghost layer of patch p (Section 3.3) from u[p-1] and u[p].  ghosts receives the
+ * 6 faces back to back: x-low, x-high ([ny][nz] each), y-low, y-high ([nx][nz]), z-low,
+ * z-high ([nx][ny]).  flux_match = 0 gives the interpolated guess without flux matching. */
+int mg_ghost_fill(const mg_hier* hier, int p, const double* const* u, double* ghosts,
+                  int flux_match, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
+ * Measurement support
+ * -------------------------------------------------------------------------------------------- */
+
+/* When on (per calling thread), every launch of the smoother on the finest level of a solve is
+ * bracketed by two HIP events recorded on the launch stream. */
+int mg_kprof_enable(int on);
+
+/* Wait for the recorded events, return the summed launch durations (ms), the number of timed
+ * launches and their algorithmic bytes (3 words per cell-update: u in, f in, u out), and reset. */
+int mg_kprof_read(double* ms_total, long long* launches, double* bytes_total);
+
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGIC_H */

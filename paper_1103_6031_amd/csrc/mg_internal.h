@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP kernel translation units and the host solver.
+// Not part of the public ABI (see include/mgic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mgic {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kMaxPartials = 1024;   // partial sums per reduction (fixed => deterministic)
+
+// A 3-D box of cells.
+struct Dims {
+    int x, y, z;
+    __host__ __device__ size_t cells() const { return (size_t)x * y * z; }
+};
+
+// Where a fine level's coarse representation lives inside its parent array.
+struct ParentMap {
+    Dims pd;        // parent array dims
+    int off[3];     // first covered parent cell
+    int periodic;   // parent is periodic (base or a coarsening of it)
+};
+
+// Covered box of a level (cells owned by the next finer level); n = 0 means none.
+struct CovBox {
+    int lo[3];
+    int n[3];
+};
+
+// Face layout of a patch ghost array: x-lo, x-hi [ny][nz]; y-lo, y-hi [nx][nz]; z-lo, z-hi [nx][ny].
+__host__ __device__ inline size_t ghost_face_offset(Dims d, int face) {
+    const size_t fx = (size_t)d.y * d.z, fy = (size_t)d.x * d.z, fz = (size_t)d.x * d.y;
+    switch (face) {
+        case 0: return 0;
+        case 1: return fx;
+        case 2: return 2 * fx;
+        case 3: return 2 * fx + fy;
+        case 4: return 2 * fx + 2 * fy;
+        default: return 2 * fx + 2 * fy + fz;
+    }
+}
+__host__ __device__ inline size_t ghost_cells(Dims d) { return ghost_face_offset(d, 6); }
+
+// Segments of partial sums combined by the finalize kernel: out = sum_s w[s] * sum(partials[s]).
+struct SegList {
+    int n;
+    int off[16];
+    int cnt[16];
+    double w[16];
+};
+
+// ----------------------------------------------------------------------------------------------
+// launchers (defined in the .hip files); all enqueue on `st`
+// ----------------------------------------------------------------------------------------------
+template <class T> void launch_fill(T* p, size_t n, T v, hipStream_t st);
+template <class A, class B> void launch_convert(const A* a, B* b, size_t n, hipStream_t st);
+void launch_add_f32_to_f64(double* u, const float* e, size_t n, hipStream_t st);
+template <class T> void launch_sub_mean(T* a, size_t n, const double* sum, double inv_count, hipStream_t st);
+
+// red-black half-sweep (colour 0 = red = (x+y+z) even); ghosts == nullptr => periodic wrap
+template <class T> void launch_rbgs_half(T* u, const T* f, const T* ghosts, Dims d, double h,
+                                         int colour, hipStream_t st);
+
+// fused red+black sweep(s) on a periodic level, ping-pong src -> dst
+template <class T> bool fused_sweep_supported(Dims d);
+template <class T> void launch_rbgs_fused(const T* src, T* dst, const T* f, Dims d, double h, hipStream_t st);
+
+// residual r = f - L u on the fine level, restricted: parent u[cov] = mean8 u, uold = mean8 u,
+// parent f[cov] = mean8 r  (fine level periodic if ghosts == nullptr)
+template <class T> void launch_resid_restrict(const T* u, const T* f, const T* ghosts, Dims d, double h,
+                                              T* pu, T* pf, T* uold, ParentMap pm, hipStream_t st);
+// parent f[cov] += L u  (FAS coarse right-hand side), L over the parent's own stencil
+template <class T> void launch_fas_rhs(const T* pu, T* pf, ParentMap pm, Dims cov, double H, hipStream_t st);
+// fine u += inject(parent u[cov] - uold)
+template <class T> void launch_prolong(T* u, Dims d, const T* pu, const T* uold, ParentMap pm, hipStream_t st);
+// exact coarsest solve on an odd periodic M^3 grid (M = 1: u = 0)
+template <class T> void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st);
+
+// flux-matched ghost layer of a patch (arithmetic in double, stored as T)
+template <class T> void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Dims d, ParentMap pm,
+                                          int flux_match, hipStream_t st);
+// parent[cov] = mean8(fine)
+template <class T> void launch_restrict_cov(const T* fine, Dims d, T* parent, ParentMap pm, hipStream_t st);
+
+// residual of one level: per-block partial sums of r^2 over cells outside `cov`; r written to
+// rout (if non-null; cells inside cov get 0)
+template <class T, class R> void launch_residual(const T* u, const T* f, const T* ghosts, Dims d, double h,
+                                                 CovBox cov, R* rout, double* partials, int* nparts,
+                                                 hipStream_t st);
+// per-block partial sums of a (or a^2) over cells outside cov
+void launch_sum(const double* a, Dims d, CovBox cov, int square, double* partials, int* nparts, hipStream_t st);
+void launch_finalize(const double* partials, SegList segs, double* out, hipStream_t st);
+
+// LPT: padded copy with tri-quadratic ghosts of width R from the parent (covered parent cells
+// must already hold the mean of their children)
+void launch_wide_ghost(const double* pu, const double* u, double* padded, Dims d, ParentMap pm, int R,
+                       hipStream_t st);
+// psi_c = scale * G4_c phi ; src is periodic (R = 0) or padded by R
+void launch_grad4(const double* src, int R, Dims d, double h, double scale, double* ox, double* oy,
+                  double* oz, hipStream_t st);
+// tau = sum_{i>j} D_ii D_jj - D_ij^2 ; src periodic (R = 0) or padded by R >= 4
+void launch_tau(const double* src, int R, Dims d, double h, double* tau, hipStream_t st);
+
+inline int grid_for(size_t n, int per_block = kBlock, int cap = 1 << 30) {
+    size_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (size_t)cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace mgic

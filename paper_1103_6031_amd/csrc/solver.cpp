@@ -1,0 +1,785 @@
+// Host side of the MI355X multigrid library: validation, workspace carving, the FAS V-cycle
+// schedule (Hahn & Abel 2011, Section 3.2, steps 1-9; Section 3.3 on nested patches), the
+// FP64 and mixed-precision drivers, LPT and the C ABI of include/mgic.h.
+//
+// Level list: L[0] is the finest level (the innermost patch, or the base when there are no
+// patches), L[nh-1] the periodic base, L[nh..] its coarsenings down to an odd (or 1-cell) grid.
+// Every level l < last has a parent L[l+1] holding its coarse representation at ParentMap::off.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg_internal.h"
+#include "mgic.h"
+
+namespace mgic {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define MG_HIP(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(MG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ----------------------------------------------------------------------------------------------
+// workspace carving (the same code computes sizes when base == nullptr)
+// ----------------------------------------------------------------------------------------------
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Level {
+    Dims d{0, 0, 0};
+    double h = 0;
+    bool periodic = false;  // base or a coarsening of it
+    int p = -1;             // hierarchy index (0 = base), -1 for coarsenings
+    ParentMap pm{};         // coarse representation inside L[l+1]
+    CovBox child{};         // region of this level covered by L[l-1]
+    double *u = nullptr, *f = nullptr, *g = nullptr, *uold = nullptr, *alt = nullptr;
+    float *u32 = nullptr, *f32 = nullptr, *g32 = nullptr, *uold32 = nullptr, *alt32 = nullptr;
+};
+
+struct Plan {
+    std::vector<Level> L;
+    int nh = 0;      // hierarchy levels (patches + base)
+    int last = 0;    // index of the coarsest level
+    int nu1 = 2, nu2 = 2;
+    bool mixed = false;
+    double* partials = nullptr;  // kMaxPartials per level segment
+    double* scal = nullptr;      // device scalars
+};
+
+enum { S_FSUM = 0, S_FNORM = 1, S_RNORM = 2, S_USUM = 3, S_TMP = 4, S_COUNT = 8 };
+
+template <class T> struct B { T *u, *f, *g, *uold, *alt; };
+template <class T> static B<T> bufs(Level& l);
+template <> B<double> bufs<double>(Level& l) { return {l.u, l.f, l.g, l.uold, l.alt}; }
+template <> B<float> bufs<float>(Level& l) { return {l.u32, l.f32, l.g32, l.uold32, l.alt32}; }
+
+static bool odd_ok(int m) { return m == 1 || m == 3 || m == 5 || m == 7; }
+
+static int validate_hier(const mg_hier* H) {
+    if (!H) return fail(MG_EINVAL, "hierarchy is NULL");
+    if (H->nlev < 1 || H->nlev > MG_MAX_LEVELS) return fail(MG_EINVAL, "nlev out of range");
+    const mg_level& b = H->lev[0];
+    const int N = b.n[0];
+    if (N < 1 || b.n[1] != N || b.n[2] != N) return fail(MG_EINVAL, "base must be cubic n^3, n >= 1");
+    int m = N;
+    while (m % 2 == 0) m /= 2;
+    if (!odd_ok(m)) return fail(MG_EINVAL, "base size must be 2^k * m with m in {1,3,5,7}");
+    if (!(b.h > 0) || !std::isfinite(b.h)) return fail(MG_EINVAL, "base spacing must be positive");
+    for (int p = 1; p < H->nlev; ++p) {
+        const mg_level& l = H->lev[p];
+        const mg_level& q = H->lev[p - 1];
+        if (std::fabs(l.h - 0.5 * q.h) > 1e-12 * q.h) return fail(MG_EINVAL, "patch spacing must be half its parent's");
+        for (int a = 0; a < 3; ++a) {
+            if (l.n[a] < 4 || l.n[a] % 2) return fail(MG_EINVAL, "patch sizes must be even and >= 4");
+            const int lo = l.off[a], hi = l.off[a] + l.n[a] / 2;
+            bool ok;
+            if (p == 1) ok = lo >= 0 && hi <= q.n[a] && l.n[a] / 2 <= q.n[a] - 2;
+            else ok = lo >= 4 && hi <= q.n[a] - 4;
+            if (!ok) return fail(MG_EINVAL, "patch " + std::to_string(p) + " not properly nested in its parent");
+        }
+    }
+    return MG_OK;
+}
+
+// Build the level list and carve buffers.  u_user / f_user may be null (size query).
+static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* const* u_user, Plan& P) {
+    int rc = validate_hier(H);
+    if (rc) return rc;
+    P.nu1 = o ? o->nu1 : 2;
+    P.nu2 = o ? o->nu2 : 2;
+    P.mixed = o && o->prec == MG_MIXED;
+    if (P.nu1 < 0 || P.nu2 < 0 || P.nu1 + P.nu2 > 64) return fail(MG_EINVAL, "nu1/nu2 out of range");
+    const int np = H->nlev - 1;
+    P.L.clear();
+    for (int p = np; p >= 0; --p) {
+        Level l;
+        const mg_level& m = H->lev[p];
+        l.d = Dims{m.n[0], m.n[1], m.n[2]};
+        l.h = p == 0 ? m.h : H->lev[0].h / (double)(1 << p);
+        l.periodic = p == 0;
+        l.p = p;
+        P.L.push_back(l);
+    }
+    P.nh = (int)P.L.size();
+    {
+        int N = H->lev[0].n[0];
+        double h = H->lev[0].h;
+        while (N % 2 == 0) {
+            N /= 2;
+            h *= 2.0;
+            Level l;
+            l.d = Dims{N, N, N};
+            l.h = h;
+            l.periodic = true;
+            P.L.push_back(l);
+        }
+    }
+    P.last = (int)P.L.size() - 1;
+    for (int l = 0; l < P.last; ++l) {
+        Level& L = P.L[l];
+        Level& Q = P.L[l + 1];
+        L.pm.pd = Q.d;
+        L.pm.periodic = Q.periodic ? 1 : 0;
+        for (int a = 0; a < 3; ++a) L.pm.off[a] = (L.p >= 1) ? H->lev[L.p].off[a] : 0;
+        Q.child.lo[0] = L.pm.off[0]; Q.child.lo[1] = L.pm.off[1]; Q.child.lo[2] = L.pm.off[2];
+        Q.child.n[0] = L.d.x / 2; Q.child.n[1] = L.d.y / 2; Q.child.n[2] = L.d.z / 2;
+    }
+    for (int l = 0; l <= P.last; ++l) {
+        Level& L = P.L[l];
+        const size_t n = L.d.cells();
+        const bool hier = L.p >= 0;
+        L.u = hier ? (u_user ? u_user[L.p] : nullptr) : cv.take<double>(n);
+        L.f = cv.take<double>(n);
+        if (!L.periodic) L.g = cv.take<double>(ghost_cells(L.d));
+        if (l < P.last) L.uold = cv.take<double>(n / 8);
+        if (L.periodic && fused_sweep_supported<double>(L.d)) L.alt = cv.take<double>(n);
+        if (P.mixed) {
+            L.u32 = cv.take<float>(n);
+            L.f32 = cv.take<float>(n);
+            if (!L.periodic) L.g32 = cv.take<float>(ghost_cells(L.d));
+            if (l < P.last) L.uold32 = cv.take<float>(n / 8);
+            if (L.periodic && fused_sweep_supported<float>(L.d)) L.alt32 = cv.take<float>(n);
+        }
+    }
+    P.partials = cv.take<double>((size_t)kMaxPartials * (P.nh + 1));
+    P.scal = cv.take<double>(S_COUNT);
+    return MG_OK;
+}
+
+// ----------------------------------------------------------------------------------------------
+// optional timing of the finest-level smoother launches (HIP events on the launch stream)
+// ----------------------------------------------------------------------------------------------
+struct KProf {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Rec { hipEvent_t a, b; double bytes; };
+    std::vector<Rec> recs;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+        return e;
+    }
+};
+static thread_local KProf g_kprof;
+
+// brackets one launch when timing is on; returns the stop event to record after it
+struct KScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st;
+    double bytes;
+    KScope(bool time_it, hipStream_t s, double by) : st(s), bytes(by) {
+        if (!time_it || !g_kprof.on) return;
+        a = g_kprof.get();
+        b = g_kprof.get();
+        if (a && b) hipEventRecord(a, st);
+    }
+    ~KScope() {
+        if (a && b) {
+            hipEventRecord(b, st);
+            g_kprof.recs.push_back({a, b, bytes});
+        }
+    }
+};
+
+static double* pinned_scratch() {
+    static thread_local double* p = nullptr;
+    if (!p) {
+        if (hipHostMalloc((void**)&p, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) p = nullptr;
+    }
+    return p;
+}
+
+// ----------------------------------------------------------------------------------------------
+// V-cycle schedule
+// ----------------------------------------------------------------------------------------------
+template <class T>
+static void ghosts(Plan& P, int l, hipStream_t st) {
+    Level& L = P.L[l];
+    B<T> b = bufs<T>(L), pb = bufs<T>(P.L[l + 1]);
+    launch_ghost_fill<T>(pb.u, b.u, b.g, L.d, L.pm, 1, st);
+}
+
+template <class T>
+static void smooth(Plan& P, int l, int sweeps, hipStream_t st) {
+    Level& L = P.L[l];
+    B<T> b = bufs<T>(L);
+    const bool timed = l == 0;
+    const double half_bytes = 0.5 * (double)L.d.cells() * 3.0 * sizeof(T);  // 3 words per update
+    if (!L.periodic) {
+        for (int s = 0; s < sweeps; ++s)
+            for (int c = 0; c < 2; ++c) {
+                ghosts<T>(P, l, st);
+                KScope k(timed, st, half_bytes);
+                launch_rbgs_half<T>(b.u, b.f, b.g, L.d, L.h, c, st);
+            }
+        return;
+    }
+    if (b.alt) {
+        // fused red+black sweeps ping-pong between u and alt; an odd count ends with a copy back
+        T* src = b.u;
+        T* dst = b.alt;
+        for (int s = 0; s < sweeps; ++s) {
+            {
+                KScope k(timed, st, 2.0 * half_bytes);
+                launch_rbgs_fused<T>(src, dst, b.f, L.d, L.h, st);
+            }
+            T* t = src; src = dst; dst = t;
+        }
+        if (src != b.u) hipMemcpyAsync(b.u, src, L.d.cells() * sizeof(T), hipMemcpyDeviceToDevice, st);
+        return;
+    }
+    for (int s = 0; s < sweeps; ++s)
+        for (int c = 0; c < 2; ++c) {
+            KScope k(timed, st, half_bytes);
+            launch_rbgs_half<T>(b.u, b.f, nullptr, L.d, L.h, c, st);
+        }
+}
+
+template <class T>
+static void vcycle(Plan& P, int l, hipStream_t st) {
+    Level& L = P.L[l];
+    B<T> b = bufs<T>(L);
+    if (l == P.last) {  // step 1
+        launch_coarsest<T>(b.u, b.f, L.d.x, L.h, st);
+        return;
+    }
+    smooth<T>(P, l, P.nu1, st);  // step 2
+    Level& Q = P.L[l + 1];
+    B<T> q = bufs<T>(Q);
+    if (!L.periodic) ghosts<T>(P, l, st);
+    // steps 3-5, then step 6 on the covered region of the parent
+    launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.d, L.h, q.u, q.f, b.uold, L.pm, st);
+    launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
+    vcycle<T>(P, l + 1, st);                         // step 7
+    launch_prolong<T>(b.u, L.d, q.u, b.uold, L.pm, st);  // step 8
+    smooth<T>(P, l, P.nu2, st);                      // step 9
+}
+
+static long long updates_per_cycle(const Plan& P) {
+    long long s = 0;
+    for (int l = 0; l < P.last; ++l) s += (long long)(P.nu1 + P.nu2) * (long long)P.L[l].d.cells();
+    return s;
+}
+
+// covered cells of every hierarchy level := mean of their children, finest first
+template <class T>
+static void restrict_up(Plan& P, T* const* v, hipStream_t st) {
+    for (int l = 0; l + 1 < P.nh; ++l) launch_restrict_cov<T>(v[l], P.L[l].d, v[l + 1], P.L[l].pm, st);
+}
+
+// sum over the base of v (after restrict_up) -> scal[slot]
+static void base_sum(Plan& P, const double* vbase, int slot, hipStream_t st) {
+    int np = 0;
+    CovBox none{};
+    launch_sum(vbase, P.L[P.nh - 1].d, none, 0, P.partials, &np, st);
+    SegList s{};
+    s.n = 1; s.off[0] = 0; s.cnt[0] = np; s.w[0] = 1.0;
+    launch_finalize(P.partials, s, P.scal + slot, st);
+}
+
+// composite sum of v^2 * vol over uncovered cells -> scal[slot]
+static void composite_sq(Plan& P, double* const* v, int slot, hipStream_t st) {
+    SegList s{};
+    s.n = P.nh;
+    for (int l = 0; l < P.nh; ++l) {
+        int np = 0;
+        CovBox cb = l > 0 ? P.L[l].child : CovBox{};
+        launch_sum(v[l], P.L[l].d, cb, 1, P.partials + (size_t)l * kMaxPartials, &np, st);
+        s.off[l] = l * kMaxPartials;
+        s.cnt[l] = np;
+        s.w[l] = P.L[l].h * P.L[l].h * P.L[l].h;
+    }
+    launch_finalize(P.partials, s, P.scal + slot, st);
+}
+
+// composite FP64 residual of the current u (covered coarse cells restricted first);
+// r written as R to rout[l] if given; sum r^2 vol -> scal[S_RNORM]
+template <class R>
+static void composite_residual(Plan& P, R* const* rout, hipStream_t st) {
+    std::vector<double*> u(P.nh);
+    for (int l = 0; l < P.nh; ++l) u[l] = P.L[l].u;
+    restrict_up<double>(P, u.data(), st);
+    SegList s{};
+    s.n = P.nh;
+    for (int l = 0; l < P.nh; ++l) {
+        Level& L = P.L[l];
+        if (!L.periodic) ghosts<double>(P, l, st);
+        int np = 0;
+        CovBox cb = l > 0 ? L.child : CovBox{};
+        launch_residual<double, R>(L.u, L.f, L.periodic ? nullptr : L.g, L.d, L.h, cb, rout ? rout[l] : nullptr,
+                                   P.partials + (size_t)l * kMaxPartials, &np, st);
+        s.off[l] = l * kMaxPartials;
+        s.cnt[l] = np;
+        s.w[l] = L.h * L.h * L.h;
+    }
+    launch_finalize(P.partials, s, P.scal + S_RNORM, st);
+}
+
+// f working copies: copy, restrict bottom-up, subtract the composite mean; |f|^2 -> scal[S_FNORM]
+static int prepare_f(Plan& P, const double* const* f_user, hipStream_t st) {
+    for (int l = 0; l < P.nh; ++l) {
+        if (!f_user[P.L[l].p]) return fail(MG_EINVAL, "f pointer is NULL");
+        MG_HIP(hipMemcpyAsync(P.L[l].f, f_user[P.L[l].p], P.L[l].d.cells() * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+    }
+    std::vector<double*> f(P.nh);
+    for (int l = 0; l < P.nh; ++l) f[l] = P.L[l].f;
+    restrict_up<double>(P, f.data(), st);
+    const Level& base = P.L[P.nh - 1];
+    base_sum(P, base.f, S_FSUM, st);
+    const double inv = 1.0 / (double)base.d.cells();
+    for (int l = 0; l < P.nh; ++l) launch_sub_mean<double>(P.L[l].f, P.L[l].d.cells(), P.scal + S_FSUM, inv, st);
+    composite_sq(P, f.data(), S_FNORM, st);
+    return MG_OK;
+}
+
+static void gauge_u(Plan& P, hipStream_t st) {
+    std::vector<double*> u(P.nh);
+    for (int l = 0; l < P.nh; ++l) u[l] = P.L[l].u;
+    restrict_up<double>(P, u.data(), st);
+    const Level& base = P.L[P.nh - 1];
+    base_sum(P, base.u, S_USUM, st);
+    const double inv = 1.0 / (double)base.d.cells();
+    for (int l = 0; l < P.nh; ++l) launch_sub_mean<double>(P.L[l].u, P.L[l].d.cells(), P.scal + S_USUM, inv, st);
+}
+
+static int read_scalars(Plan& P, int first, int count, double* out, hipStream_t st) {
+    double* pin = pinned_scratch();
+    if (!pin) return fail(MG_EHIP, "pinned host buffer unavailable");
+    MG_HIP(hipMemcpyAsync(pin, P.scal + first, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    MG_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) out[i] = pin[i];
+    return MG_OK;
+}
+
+static int solve(const mg_hier* H, const double* const* f, double* const* u, const mg_opts* o, mg_stats* stats,
+                 void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!o) return fail(MG_EINVAL, "options are NULL");
+    if (!f || !u) return fail(MG_EINVAL, "f/u pointer arrays are NULL");
+    if (o->max_cycles < 0) return fail(MG_EINVAL, "max_cycles < 0");
+    if (o->prec != MG_FP64 && o->prec != MG_MIXED) return fail(MG_EINVAL, "unknown precision");
+    if (int v = validate_hier(H)) return v;
+    for (int p = 0; p < H->nlev; ++p)
+        if (!u[p] || !f[p]) return fail(MG_EINVAL, "level pointer is NULL");
+    Plan P;
+    Carver size_cv(nullptr);
+    int rc = build_plan(H, o, size_cv, u, P);
+    if (rc) return rc;
+    if (!ws || ws_bytes < size_cv.off) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(size_cv.off));
+    if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    Carver cv(ws);
+    build_plan(H, o, cv, u, P);
+    (void)hipGetLastError();
+
+    rc = prepare_f(P, f, st);
+    if (rc) return rc;
+    const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
+    const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
+    if (!guess)
+        for (int l = 0; l < P.nh; ++l) launch_fill<double>(P.L[l].u, P.L[l].d.cells(), 0.0, st);
+
+    mg_stats S;
+    std::memset(&S, 0, sizeof(S));
+    double fs[2] = {0, 0};
+    double fnorm2 = 0;
+    if (!fixed) {
+        rc = read_scalars(P, S_FSUM, 2, fs, st);
+        if (rc) return rc;
+        S.f_mean_removed = fs[0] / (double)P.L[P.nh - 1].d.cells();
+        fnorm2 = fs[1];
+        if (!std::isfinite(fnorm2) || !std::isfinite(fs[0])) {
+            S.rel_res = NAN;
+            if (stats) *stats = S;
+            return fail(MG_EDIVERGED, "right-hand side contains NaN or Inf");
+        }
+    }
+    const long long upc = updates_per_cycle(P);
+    double rel = NAN, prev = INFINITY;
+    int grow = 0, status = MG_ENOCONV, cycles = 0;
+    auto check = [&](double r2) -> int {
+        rel = fnorm2 > 0 ? std::sqrt(r2 / fnorm2) : 0.0;
+        if (cycles >= 1 && cycles <= 64) S.res_hist[cycles - 1] = rel;
+        if (!std::isfinite(rel)) return MG_EDIVERGED;
+        grow = rel > prev ? grow + 1 : 0;
+        prev = rel;
+        if (grow >= 3) return MG_EDIVERGED;
+        return rel <= o->tol ? MG_OK : 1;
+    };
+
+    if (!P.mixed) {
+        if (guess && !fixed) {
+            composite_residual<double>(P, nullptr, st);
+            double r2;
+            if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
+            int c = check(r2);
+            if (c == MG_OK) status = MG_OK;
+        }
+        while (status != MG_OK && cycles < o->max_cycles) {
+            vcycle<double>(P, 0, st);
+            ++cycles;
+            S.cell_updates += upc;
+            if (fixed) continue;
+            composite_residual<double>(P, nullptr, st);
+            double r2;
+            if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
+            int c = check(r2);
+            if (c == MG_OK) status = MG_OK;
+            else if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+        }
+    } else {
+        std::vector<float*> rhs(P.nh);
+        for (int l = 0; l < P.nh; ++l) rhs[l] = P.L[l].f32;
+        for (;;) {
+            composite_residual<float>(P, rhs.data(), st);
+            if (!fixed) {
+                double r2;
+                if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
+                int c = check(r2);
+                if (c == MG_OK) { status = MG_OK; break; }
+                if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+            }
+            if (cycles >= o->max_cycles) break;
+            for (int l = 0; l < P.nh; ++l) launch_fill<float>(P.L[l].u32, P.L[l].d.cells(), 0.0f, st);
+            vcycle<float>(P, 0, st);
+            for (int l = 0; l < P.nh; ++l) launch_add_f32_to_f64(P.L[l].u, P.L[l].u32, P.L[l].d.cells(), st);
+            ++cycles;
+            S.cell_updates += upc;
+        }
+    }
+    gauge_u(P, st);
+    MG_HIP(hipGetLastError());
+    if (fixed) {
+        MG_HIP(hipStreamSynchronize(st));  // surface asynchronous faults at the API boundary
+        status = MG_OK;
+    }
+    S.cycles = cycles;
+    S.rel_res = rel;
+    if (stats) *stats = S;
+    if (status == MG_ENOCONV) return fail(MG_ENOCONV, "not converged after " + std::to_string(cycles) + " cycles");
+    if (status == MG_EDIVERGED) return fail(MG_EDIVERGED, "residual diverged (NaN/Inf or growth)");
+    return MG_OK;
+}
+
+static mg_hier single_level(int n, double h) {
+    mg_hier H;
+    std::memset(&H, 0, sizeof(H));
+    H.nlev = 1;
+    H.lev[0].n[0] = H.lev[0].n[1] = H.lev[0].n[2] = n;
+    H.lev[0].h = h;
+    return H;
+}
+
+// ----------------------------------------------------------------------------------------------
+// LPT
+// ----------------------------------------------------------------------------------------------
+struct LptPlan {
+    std::vector<double*> phi;  // restricted copies (P > 0) or the user's arrays
+    double* padded = nullptr;
+    double* partials = nullptr;
+    double* scal = nullptr;
+};
+
+static size_t lpt_carve(const mg_hier* H, int what, Carver& cv, LptPlan& lp) {
+    const int R = what == 2 ? 4 : 2;
+    size_t maxpad = 0;
+    lp.phi.assign(H->nlev, nullptr);
+    if (H->nlev > 1)
+        for (int p = 0; p < H->nlev; ++p) {
+            const mg_level& l = H->lev[p];
+            lp.phi[p] = cv.take<double>((size_t)l.n[0] * l.n[1] * l.n[2]);
+            if (p > 0) {
+                size_t s = (size_t)(l.n[0] + 2 * R) * (l.n[1] + 2 * R) * (l.n[2] + 2 * R);
+                if (s > maxpad) maxpad = s;
+            }
+        }
+    if (maxpad) lp.padded = cv.take<double>(maxpad);
+    lp.partials = cv.take<double>(kMaxPartials);
+    lp.scal = cv.take<double>(S_COUNT);
+    return cv.off;
+}
+
+static ParentMap parent_of(const mg_hier* H, int p) {
+    ParentMap pm{};
+    const mg_level& q = H->lev[p - 1];
+    pm.pd = Dims{q.n[0], q.n[1], q.n[2]};
+    pm.periodic = p == 1;
+    for (int a = 0; a < 3; ++a) pm.off[a] = H->lev[p].off[a];
+    return pm;
+}
+
+static Dims dims_of(const mg_hier* H, int p) { return Dims{H->lev[p].n[0], H->lev[p].n[1], H->lev[p].n[2]}; }
+static double h_of(const mg_hier* H, int p) { return H->lev[0].h / (double)(1 << p); }
+
+static int lpt_common(const mg_hier* H, int what, const double* const* phi, void* ws, size_t ws_bytes,
+                      hipStream_t st, LptPlan& lp) {
+    int rc = validate_hier(H);
+    if (rc) return rc;
+    if (!phi) return fail(MG_EINVAL, "phi is NULL");
+    for (int p = 0; p < H->nlev; ++p)
+        if (!phi[p]) return fail(MG_EINVAL, "phi level pointer is NULL");
+    Carver sz(nullptr);
+    LptPlan tmp;
+    const size_t need = lpt_carve(H, what, sz, tmp);
+    if (!ws || ws_bytes < need) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(need));
+    if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    Carver cv(ws);
+    lpt_carve(H, what, cv, lp);
+    (void)hipGetLastError();
+    if (H->nlev == 1) {
+        lp.phi[0] = const_cast<double*>(phi[0]);
+        return MG_OK;
+    }
+    for (int p = 0; p < H->nlev; ++p)
+        MG_HIP(hipMemcpyAsync(lp.phi[p], phi[p], dims_of(H, p).cells() * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int p = H->nlev - 1; p >= 1; --p)
+        launch_restrict_cov<double>(lp.phi[p], dims_of(H, p), lp.phi[p - 1], parent_of(H, p), st);
+    return MG_OK;
+}
+
+}  // namespace mgic
+
+// ==============================================================================================
+// C ABI
+// ==============================================================================================
+using namespace mgic;
+
+extern "C" {
+
+const char* mg_last_error(void) { return g_err.c_str(); }
+
+int mg_kprof_enable(int on) {
+    g_kprof.on = on != 0;
+    return MG_OK;
+}
+
+int mg_kprof_read(double* ms_total, long long* launches, double* bytes_total) {
+    double ms = 0.0, by = 0.0;
+    long long n = 0;
+    for (auto& r : g_kprof.recs) {
+        float t = 0.f;
+        MG_HIP(hipEventSynchronize(r.b));
+        MG_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        by += r.bytes;
+        ++n;
+        g_kprof.pool.push_back(r.a);
+        g_kprof.pool.push_back(r.b);
+    }
+    g_kprof.recs.clear();
+    if (ms_total) *ms_total = ms;
+    if (launches) *launches = n;
+    if (bytes_total) *bytes_total = by;
+    return MG_OK;
+}
+
+size_t mg_workspace_bytes(const mg_hier* hier, const mg_opts* opts) {
+    Plan P;
+    Carver cv(nullptr);
+    if (build_plan(hier, opts, cv, nullptr, P)) return 0;
+    return cv.off;
+}
+
+int mg_solve_level(int n, double h, const double* f, double* u, const mg_opts* opts, mg_stats* stats,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+    mg_hier H = single_level(n, h);
+    const double* fp[1] = {f};
+    double* up[1] = {u};
+    return solve(&H, fp, up, opts, stats, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+int mg_solve_hierarchy(const mg_hier* hier, const double* const* f, double* const* u, const mg_opts* opts,
+                       mg_stats* stats, void* workspace, size_t workspace_bytes, void* stream) {
+    return solve(hier, f, u, opts, stats, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* const* u, double* const* r,
+                          double* rel, void* workspace, size_t workspace_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!hier || !f || !u || !r) return fail(MG_EINVAL, "NULL argument");
+    for (int p = 0; p < hier->nlev; ++p)
+        if (!f[p] || !u[p] || !r[p]) return fail(MG_EINVAL, "level pointer is NULL");
+    mg_opts o{};
+    o.nu1 = o.nu2 = 2;
+    Plan P;
+    Carver sz(nullptr);
+    int rc = build_plan(hier, &o, sz, u, P);
+    if (rc) return rc;
+    if (!workspace || workspace_bytes < sz.off) return fail(MG_EINVAL, "workspace too small");
+    Carver cv(workspace);
+    build_plan(hier, &o, cv, u, P);
+    (void)hipGetLastError();
+    if ((rc = prepare_f(P, f, st))) return rc;
+    std::vector<double*> rr(P.nh);
+    for (int l = 0; l < P.nh; ++l) rr[l] = r[P.L[l].p];
+    composite_residual<double>(P, rr.data(), st);
+    MG_HIP(hipGetLastError());
+    if (rel) {
+        double v[3];
+        if ((rc = read_scalars(P, S_FSUM, 3, v, st))) return rc;
+        *rel = v[1] > 0 ? std::sqrt(v[2] / v[1]) : 0.0;
+    }
+    return MG_OK;
+}
+
+size_t lpt_workspace_bytes(const mg_hier* hier, int what) {
+    if (validate_hier(hier) || (what != 1 && what != 2)) return 0;
+    Carver cv(nullptr);
+    LptPlan lp;
+    return lpt_carve(hier, what, cv, lp);
+}
+
+int lpt_displacements(const mg_hier* hier, const double* const* phi, double* const* out, double scale,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!out) return fail(MG_EINVAL, "out is NULL");
+    LptPlan lp;
+    int rc = lpt_common(hier, 1, phi, workspace, workspace_bytes, st, lp);
+    if (rc) return rc;
+    for (int p = 0; p < hier->nlev; ++p) {
+        if (!out[3 * p] || !out[3 * p + 1] || !out[3 * p + 2]) return fail(MG_EINVAL, "output pointer is NULL");
+        const Dims d = dims_of(hier, p);
+        const double h = h_of(hier, p);
+        if (p == 0) {
+            launch_grad4(lp.phi[0], 0, d, h, scale, out[0], out[1], out[2], st);
+        } else {
+            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 2, st);
+            launch_grad4(lp.padded, 2, d, h, scale, out[3 * p], out[3 * p + 1], out[3 * p + 2], st);
+        }
+    }
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
+int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau, void* workspace,
+                size_t workspace_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!tau) return fail(MG_EINVAL, "tau is NULL");
+    LptPlan lp;
+    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp);
+    if (rc) return rc;
+    for (int p = 0; p < hier->nlev; ++p) {
+        if (!tau[p]) return fail(MG_EINVAL, "tau level pointer is NULL");
+        const Dims d = dims_of(hier, p);
+        const double h = h_of(hier, p);
+        if (p == 0) {
+            launch_tau(lp.phi[0], 0, d, h, tau[0], st);
+        } else {
+            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 4, st);
+            launch_tau(lp.padded, 4, d, h, tau[p], st);
+        }
+    }
+    // composite mean: covered cells := mean of children, then subtract the base mean everywhere
+    for (int p = hier->nlev - 1; p >= 1; --p)
+        launch_restrict_cov<double>(tau[p], dims_of(hier, p), tau[p - 1], parent_of(hier, p), st);
+    int np = 0;
+    CovBox none{};
+    launch_sum(tau[0], dims_of(hier, 0), none, 0, lp.partials, &np, st);
+    SegList s{};
+    s.n = 1; s.off[0] = 0; s.cnt[0] = np; s.w[0] = 1.0;
+    launch_finalize(lp.partials, s, lp.scal, st);
+    const double inv = 1.0 / (double)dims_of(hier, 0).cells();
+    for (int p = 0; p < hier->nlev; ++p) launch_sub_mean<double>(tau[p], dims_of(hier, p).cells(), lp.scal, inv, st);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
+size_t mg_batch_workspace_bytes(int ninst, const int* n, const mg_opts* opts) {
+    if (ninst < 1 || !n) return 0;
+    size_t total = 0;
+    for (int i = 0; i < ninst; ++i) {
+        mg_hier H = single_level(n[i], 1.0);
+        size_t b = mg_workspace_bytes(&H, opts);
+        if (!b) return 0;
+        total += (b + 255) & ~(size_t)255;
+    }
+    return total;
+}
+
+int mg_solve_batch(int ninst, const int* n, const double* h, const double* const* f, double* const* u,
+                   const mg_opts* opts, mg_stats* stats, void* workspace, size_t workspace_bytes, void* stream) {
+    if (ninst < 1 || !n || !h || !f || !u) return fail(MG_EINVAL, "NULL argument");
+    if (workspace_bytes < mg_batch_workspace_bytes(ninst, n, opts)) return fail(MG_EINVAL, "workspace too small");
+    char* w = (char*)workspace;
+    int worst = MG_OK;
+    for (int i = 0; i < ninst; ++i) {
+        mg_hier H = single_level(n[i], h[i]);
+        size_t b = (mg_workspace_bytes(&H, opts) + 255) & ~(size_t)255;
+        int rc = mg_solve_level(n[i], h[i], f[i], u[i], opts, stats ? stats + i : nullptr, w, b, stream);
+        if (rc == MG_EINVAL || rc == MG_EHIP) return rc;
+        if (rc && !worst) worst = rc;
+        w += b;
+    }
+    return worst;
+}
+
+int mg_smooth_level(int n, double h, const double* f, double* u, int half_sweeps, int prec, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!f || !u || half_sweeps < 0) return fail(MG_EINVAL, "bad argument");
+    if (n < 2 || n % 2) return fail(MG_EINVAL, "smoothing needs an even periodic grid");
+    mg_hier H = single_level(n, h);
+    mg_opts o{};
+    o.nu1 = o.nu2 = 2;
+    o.prec = prec;
+    Plan P;
+    Carver sz(nullptr);
+    double* up[1] = {u};
+    int rc = build_plan(&H, &o, sz, up, P);
+    if (rc) return rc;
+    if (!workspace || workspace_bytes < sz.off) return fail(MG_EINVAL, "workspace too small");
+    Carver cv(workspace);
+    build_plan(&H, &o, cv, up, P);
+    (void)hipGetLastError();
+    Level& L = P.L[0];
+    const size_t cells = L.d.cells();
+    if (prec == MG_FP64) {
+        MG_HIP(hipMemcpyAsync(L.f, f, cells * sizeof(double), hipMemcpyDeviceToDevice, st));
+        smooth<double>(P, 0, half_sweeps / 2, st);
+        if (half_sweeps & 1) launch_rbgs_half<double>(L.u, L.f, nullptr, L.d, L.h, 0, st);
+    } else {
+        launch_convert<double, float>(f, L.f32, cells, st);
+        launch_convert<double, float>(u, L.u32, cells, st);
+        smooth<float>(P, 0, half_sweeps / 2, st);
+        if (half_sweeps & 1) launch_rbgs_half<float>(L.u32, L.f32, nullptr, L.d, L.h, 0, st);
+        launch_convert<float, double>(L.u32, u, cells, st);
+    }
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
+int mg_ghost_fill(const mg_hier* hier, int p, const double* const* u, double* ghosts, int flux_match, void* stream) {
+    int rc = validate_hier(hier);
+    if (rc) return rc;
+    if (p < 1 || p >= hier->nlev) return fail(MG_EINVAL, "p must name a patch");
+    if (!u || !u[p] || !u[p - 1] || !ghosts) return fail(MG_EINVAL, "NULL argument");
+    (void)hipGetLastError();
+    launch_ghost_fill<double>(u[p - 1], u[p], ghosts, dims_of(hier, p), parent_of(hier, p), flux_match,
+                              (hipStream_t)stream);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
+}  // extern "C"

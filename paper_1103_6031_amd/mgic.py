@@ -1,0 +1,363 @@
+"""Python binding of libmgic (the C ABI declared in include/mgic.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library.  PyTorch
+provides device memory (inputs, outputs and workspace tensors) and the current HIP stream.
+The names mirror the C entry points.  If the shared library is missing, importing this module
+raises; there is no fallback.
+"""
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgic.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmgic.so is not built (run __graft_entry__.build() or "
+                      "python paper_1103_6031_amd/build.py)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+MG_MAX_LEVELS = 8
+MG_OK, MG_EINVAL, MG_ENOCONV, MG_EDIVERGED, MG_EHIP = 0, -1, -2, -3, -4
+MG_FP64, MG_MIXED = 0, 1
+MG_USE_INITIAL_GUESS = 0x1
+MG_FIXED_CYCLES = 0x2
+
+_ERRNAMES = {MG_EINVAL: "MG_EINVAL", MG_ENOCONV: "MG_ENOCONV", MG_EDIVERGED: "MG_EDIVERGED", MG_EHIP: "MG_EHIP"}
+
+
+class mg_level(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("off", ctypes.c_int * 3), ("h", ctypes.c_double)]
+
+
+class mg_hier(ctypes.Structure):
+    _fields_ = [("nlev", ctypes.c_int), ("lev", mg_level * MG_MAX_LEVELS)]
+
+
+class mg_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_cycles", ctypes.c_int), ("nu1", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("prec", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class mg_stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("rel_res", ctypes.c_double), ("f_mean_removed", ctypes.c_double),
+                ("res_hist", ctypes.c_double * 64), ("cell_updates", ctypes.c_longlong)]
+
+    def to_dict(self):
+        n = min(self.cycles, 64)
+        return dict(cycles=self.cycles, rel_res=self.rel_res, f_mean=self.f_mean_removed,
+                    history=list(self.res_hist[:n]), cell_updates=self.cell_updates)
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_sz = ctypes.c_size_t
+
+_sig = {
+    "mg_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier), ctypes.POINTER(mg_opts)]),
+    "mg_solve_level": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(mg_opts),
+                                      ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_solve_hierarchy": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.POINTER(mg_opts),
+                                          ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_residual_hierarchy": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _PP,
+                                             ctypes.POINTER(ctypes.c_double), _P, _sz, _P]),
+    "lpt_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier), ctypes.c_int]),
+    "lpt_displacements": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_double, _P, _sz, _P]),
+    "lpt2_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _P, _sz, _P]),
+    "mg_batch_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mg_opts)]),
+    "mg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                      _PP, _PP, ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_smooth_level": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.c_int,
+                                       _P, _sz, _P]),
+    "mg_ghost_fill": (ctypes.c_int, [ctypes.POINTER(mg_hier), ctypes.c_int, _PP, _P, ctypes.c_int, _P]),
+    "mg_kprof_enable": (ctypes.c_int, [ctypes.c_int]),
+    "mg_kprof_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "mg_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class MGError(RuntimeError):
+    def __init__(self, code, msg, stats=None):
+        super().__init__("%s: %s" % (_ERRNAMES.get(code, str(code)), msg))
+        self.code = code
+        self.stats = stats
+
+
+def _check(rc, stats=None):
+    if rc != MG_OK:
+        raise MGError(rc, _lib.mg_last_error().decode(), stats)
+
+
+# ------------------------------------------------------------------------------------------------
+# hierarchy description
+# ------------------------------------------------------------------------------------------------
+
+@dataclass
+class Hier:
+    """Periodic N0^3 base of spacing h0 plus nested patches [(n3, off3), ...] (outermost first)."""
+    N0: int
+    h0: float
+    patches: List[Tuple[Tuple[int, int, int], Tuple[int, int, int]]] = field(default_factory=list)
+
+    @property
+    def nlev(self):
+        return 1 + len(self.patches)
+
+    def dims(self, p):
+        return (self.N0,) * 3 if p == 0 else tuple(self.patches[p - 1][0])
+
+    def h(self, p):
+        return self.h0 / (2 ** p)
+
+    def c_struct(self):
+        H = mg_hier()
+        H.nlev = self.nlev
+        H.lev[0].n[:] = [self.N0] * 3
+        H.lev[0].h = self.h0
+        for p, (n, off) in enumerate(self.patches, start=1):
+            H.lev[p].n[:] = list(n)
+            H.lev[p].off[:] = list(off)
+            H.lev[p].h = self.h(p)
+        return H
+
+    def cells(self):
+        return sum(math.prod(self.dims(p)) for p in range(self.nlev))
+
+
+def make_opts(tol=1e-10, max_cycles=50, nu1=2, nu2=2, prec="fp64", fixed_cycles=False, initial_guess=False):
+    o = mg_opts()
+    o.tol = tol
+    o.max_cycles = max_cycles
+    o.nu1 = nu1
+    o.nu2 = nu2
+    o.prec = {"fp64": MG_FP64, "mixed": MG_MIXED}[prec] if isinstance(prec, str) else int(prec)
+    o.flags = (MG_FIXED_CYCLES if fixed_cycles else 0) | (MG_USE_INITIAL_GUESS if initial_guess else 0)
+    return o
+
+
+# ------------------------------------------------------------------------------------------------
+# helpers
+# ------------------------------------------------------------------------------------------------
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 CUDA tensor" % name)
+    return t.data_ptr()
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+    return ctypes.cast(arr, _PP), arr
+
+
+class Workspace:
+    """A device byte buffer aligned to 256 bytes (carved by the library)."""
+
+    def __init__(self, nbytes, device=None):
+        self.nbytes = int(nbytes)
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+        base = self.buf.data_ptr()
+        self.ptr = (base + 255) & ~255
+
+    def fits(self, nbytes):
+        return nbytes <= self.nbytes
+
+
+def _ws(ws, need):
+    if ws is None or not ws.fits(need):
+        ws = Workspace(need)
+    return ws
+
+
+# ------------------------------------------------------------------------------------------------
+# entry points
+# ------------------------------------------------------------------------------------------------
+
+def mg_workspace_bytes(hier: Hier, opts=None) -> int:
+    H = hier.c_struct()
+    o = opts or make_opts()
+    n = _lib.mg_workspace_bytes(ctypes.byref(H), ctypes.byref(o))
+    if n == 0:
+        raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
+    return n
+
+
+def mg_solve_level(f, h, u=None, opts=None, workspace=None, stream=None, check=True):
+    """Periodic solve of L u = f - mean(f).  Returns (u, stats dict)."""
+    n = f.shape[0]
+    o = opts or make_opts()
+    if u is None:
+        u = torch.empty_like(f)
+    need = mg_workspace_bytes(Hier(n, h), o)
+    ws = _ws(workspace, need)
+    st = mg_stats()
+    rc = _lib.mg_solve_level(n, h, _dev(f, "f"), _dev(u, "u"), ctypes.byref(o), ctypes.byref(st),
+                             ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream))
+    if check:
+        _check(rc, st.to_dict())
+    return u, st.to_dict()
+
+
+def mg_solve_hierarchy(hier: Hier, f: Sequence[torch.Tensor], u=None, opts=None, workspace=None, stream=None,
+                       check=True):
+    """Composite solve on a nested hierarchy.  Returns (u list, stats dict)."""
+    o = opts or make_opts()
+    if u is None:
+        u = [torch.empty_like(x) for x in f]
+    H = hier.c_struct()
+    need = mg_workspace_bytes(hier, o)
+    ws = _ws(workspace, need)
+    fp, _fa = _ptr_array([_dev(x, "f") for x in f])
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    st = mg_stats()
+    rc = _lib.mg_solve_hierarchy(ctypes.byref(H), fp, up, ctypes.byref(o), ctypes.byref(st),
+                                 ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream))
+    if check:
+        _check(rc, st.to_dict())
+    return u, st.to_dict()
+
+
+def mg_residual_hierarchy(hier: Hier, f, u, r=None, workspace=None, stream=None):
+    """Composite residual (covered coarse cells zero) and the relative norm."""
+    if r is None:
+        r = [torch.empty_like(x) for x in f]
+    H = hier.c_struct()
+    need = mg_workspace_bytes(hier, make_opts())
+    ws = _ws(workspace, need)
+    fp, _fa = _ptr_array([_dev(x, "f") for x in f])
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    rp, _ra = _ptr_array([_dev(x, "r") for x in r])
+    rel = ctypes.c_double()
+    _check(_lib.mg_residual_hierarchy(ctypes.byref(H), fp, up, rp, ctypes.byref(rel), ctypes.c_void_p(ws.ptr),
+                                      ws.nbytes, _stream(stream)))
+    return r, rel.value
+
+
+def lpt_workspace_bytes(hier: Hier, what: int) -> int:
+    H = hier.c_struct()
+    n = _lib.lpt_workspace_bytes(ctypes.byref(H), what)
+    if n == 0:
+        raise MGError(MG_EINVAL, "invalid hierarchy")
+    return n
+
+
+def lpt_displacements(hier: Hier, phi, scale=1.0, out=None, workspace=None, stream=None):
+    """psi_c = scale * G4_c phi per level.  Returns a list of [psi_x, psi_y, psi_z] per level."""
+    if out is None:
+        out = [[torch.empty_like(x) for _ in range(3)] for x in phi]
+    H = hier.c_struct()
+    ws = _ws(workspace, lpt_workspace_bytes(hier, 1))
+    pp, _pa = _ptr_array([_dev(x, "phi") for x in phi])
+    op, _oa = _ptr_array([_dev(c, "out") for lvl in out for c in lvl])
+    _check(_lib.lpt_displacements(ctypes.byref(H), pp, op, float(scale), ctypes.c_void_p(ws.ptr), ws.nbytes,
+                                  _stream(stream)))
+    return out
+
+
+def lpt2_source(hier: Hier, phi, tau=None, workspace=None, stream=None):
+    """Second-order source tau per level (composite mean removed)."""
+    if tau is None:
+        tau = [torch.empty_like(x) for x in phi]
+    H = hier.c_struct()
+    ws = _ws(workspace, lpt_workspace_bytes(hier, 2))
+    pp, _pa = _ptr_array([_dev(x, "phi") for x in phi])
+    tp, _ta = _ptr_array([_dev(x, "tau") for x in tau])
+    _check(_lib.lpt2_source(ctypes.byref(H), pp, tp, ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+    return tau
+
+
+def mg_batch_workspace_bytes(sizes, opts=None) -> int:
+    o = opts or make_opts()
+    n = (ctypes.c_int * len(sizes))(*sizes)
+    b = _lib.mg_batch_workspace_bytes(len(sizes), n, ctypes.byref(o))
+    if b == 0:
+        raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
+    return b
+
+
+def mg_solve_batch(f: Sequence[torch.Tensor], h: Sequence[float], u=None, opts=None, workspace=None, stream=None,
+                   check=True):
+    """Independent periodic solves.  Returns (u list, list of stats dicts)."""
+    o = opts or make_opts()
+    k = len(f)
+    sizes = [x.shape[0] for x in f]
+    if u is None:
+        u = [torch.empty_like(x) for x in f]
+    need = mg_batch_workspace_bytes(sizes, o)
+    ws = _ws(workspace, need)
+    n = (ctypes.c_int * k)(*sizes)
+    hh = (ctypes.c_double * k)(*[float(v) for v in h])
+    fp, _fa = _ptr_array([_dev(x, "f") for x in f])
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    st = (mg_stats * k)()
+    rc = _lib.mg_solve_batch(k, n, hh, fp, up, ctypes.byref(o), st, ctypes.c_void_p(ws.ptr), ws.nbytes,
+                             _stream(stream))
+    stats = [st[i].to_dict() for i in range(k)]
+    if check:
+        _check(rc, stats)
+    return u, stats
+
+
+def mg_smooth_level(f, u, h, half_sweeps, prec="fp64", workspace=None, stream=None):
+    """In-place red/black half-sweeps (red first) on a periodic level."""
+    n = f.shape[0]
+    p = {"fp64": MG_FP64, "mixed": MG_MIXED}[prec]
+    ws = _ws(workspace, mg_workspace_bytes(Hier(n, h), make_opts(prec=prec)))
+    _check(_lib.mg_smooth_level(n, h, _dev(f, "f"), _dev(u, "u"), int(half_sweeps), p, ctypes.c_void_p(ws.ptr),
+                                ws.nbytes, _stream(stream)))
+    return u
+
+
+def mg_ghost_fill(hier: Hier, p: int, u, flux_match=True, ghosts=None, stream=None):
+    """Flux-matched ghost faces of patch p (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi, back to back)."""
+    nx, ny, nz = hier.dims(p)
+    total = 2 * (ny * nz + nx * nz + nx * ny)
+    if ghosts is None:
+        ghosts = torch.empty(total, dtype=torch.float64, device=u[0].device)
+    H = hier.c_struct()
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    _check(_lib.mg_ghost_fill(ctypes.byref(H), int(p), up, _dev(ghosts, "ghosts"), 1 if flux_match else 0,
+                              _stream(stream)))
+    return ghosts
+
+
+def split_ghosts(hier: Hier, p: int, g):
+    """View the 6 ghost faces as 2-D tensors: [(ny,nz), (ny,nz), (nx,nz), (nx,nz), (nx,ny), (nx,ny)]."""
+    nx, ny, nz = hier.dims(p)
+    shapes = [(ny, nz), (ny, nz), (nx, nz), (nx, nz), (nx, ny), (nx, ny)]
+    out, o = [], 0
+    for s in shapes:
+        out.append(g[o:o + s[0] * s[1]].view(*s))
+        o += s[0] * s[1]
+    return out
+
+
+def mg_kprof_enable(on=True):
+    """Time every finest-level smoother launch with HIP events (calling thread only)."""
+    _check(_lib.mg_kprof_enable(1 if on else 0))
+
+
+def mg_kprof_read():
+    """(total ms, launches, algorithmic bytes) of the timed launches since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_longlong()
+    by = ctypes.c_double()
+    _check(_lib.mg_kprof_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+    return ms.value, n.value, by.value

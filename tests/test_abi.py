@@ -1,0 +1,66 @@
+"""The C-ABI library loads, exports every symbol include/mgic.h declares, and rejects bad
+arguments on the host (no GPU needed: these paths return before any HIP call)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgic.h")
+LIB = os.path.join(ROOT, "paper_1103_6031_amd", "libmgic.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first"
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert "mg_solve_level" in names and "lpt2_source" in names and "mg_solve_hierarchy" in names
+    for n in names:
+        assert hasattr(lib, n), "missing export " + n
+
+
+def test_binding_names_match_header():
+    from paper_1103_6031_amd import mgic
+    assert sorted(mgic.EXPORTED) == _declared()
+
+
+def test_workspace_query_and_validation():
+    from paper_1103_6031_amd import mgic
+    H = mgic.Hier(64, 100.0 / 64)
+    b64 = mgic.mg_workspace_bytes(H, mgic.make_opts())
+    bmx = mgic.mg_workspace_bytes(H, mgic.make_opts(prec="mixed"))
+    assert b64 > 64 ** 3 * 8 and bmx > b64
+    for bad in (mgic.Hier(44 * 3, 1.0), mgic.Hier(64, -1.0), mgic.Hier(11, 1.0)):
+        with pytest.raises(mgic.MGError):
+            mgic.mg_workspace_bytes(bad)
+    # patch nesting rules
+    ok = mgic.Hier(32, 1.0, [((16, 16, 16), (8, 8, 8)), ((8, 8, 8), (4, 4, 4))])
+    assert mgic.mg_workspace_bytes(ok) > 0
+    for patches in ([((16, 16, 16), (28, 8, 8))],                         # sticks out of the base
+                    [((15, 16, 16), (8, 8, 8))],                          # odd size
+                    [((16, 16, 16), (8, 8, 8)), ((8, 8, 8), (2, 4, 4))],  # nesting buffer < 4
+                    [((64, 64, 64), (0, 0, 0))]):                         # covers the whole base
+        with pytest.raises(mgic.MGError):
+            mgic.mg_workspace_bytes(mgic.Hier(32, 1.0, patches))
+    assert mgic.lpt_workspace_bytes(ok, 1) > 0 and mgic.lpt_workspace_bytes(ok, 2) > 0
+
+
+def test_null_workspace_is_rejected_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    o = mgic.make_opts()
+    st = mgic.mg_stats()
+    rc = mgic._lib.mg_solve_level(16, 1.0, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.byref(o),
+                                  ctypes.byref(st), None, 0, None)
+    assert rc == mgic.MG_EINVAL
+    assert b"workspace" in mgic._lib.mg_last_error()
+    rc = mgic._lib.mg_solve_level(16, 1.0, None, None, ctypes.byref(o), ctypes.byref(st), None, 0, None)
+    assert rc == mgic.MG_EINVAL

@@ -1,0 +1,152 @@
+"""Periodic path on the GPU (through the C ABI) against the oracle.
+
+Bar: single kernels bit-exact where the arithmetic order is fixed (smoother), solves within
+1e-10 relative RMS (FP64) and 1e-8 (mixed precision) of the oracle.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import needs_gpu, note, to_dev, to_host, rel_rms, rel_max
+from oracle import periodic, stencil
+from paper_1103_6031_amd import inputs
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_1103_6031_amd import mgic
+    return mgic
+
+
+@pytest.mark.parametrize("N,half", [(8, 1), (16, 2), (32, 3), (48, 4), (96, 2), (128, 4)])
+def test_smoother_bit_exact_fp64(mg, N, half):
+    rng = np.random.default_rng(N + half)
+    u0 = rng.standard_normal((N, N, N))
+    f = rng.standard_normal((N, N, N))
+    h = 100.0 / N
+    note("smoother fp64 N=%d half=%d" % (N, half))
+    ut = to_dev(u0)
+    mg.mg_smooth_level(to_dev(f), ut, h, half)
+    ue = u0.copy()
+    for k in range(half):
+        ue = periodic.rbgs_half(ue, f, h, k % 2)
+    assert np.array_equal(to_host(ut), ue)
+
+
+@pytest.mark.parametrize("N,half", [(16, 2), (64, 4), (96, 3)])
+def test_smoother_fp32_bit_exact_against_float32_oracle(mg, N, half):
+    rng = np.random.default_rng(7 * N)
+    u0 = rng.standard_normal((N, N, N)).astype(np.float32)
+    f = rng.standard_normal((N, N, N)).astype(np.float32)
+    h = 100.0 / N
+    note("smoother fp32 N=%d" % N)
+    ut = to_dev(u0.astype(np.float64))
+    mg.mg_smooth_level(to_dev(f.astype(np.float64)), ut, h, half, prec="mixed")
+    ue = u0.copy()
+    for k in range(half):
+        ue = periodic.rbgs_half(ue, f, h, k % 2)
+    assert ue.dtype == np.float32
+    assert np.array_equal(to_host(ut).astype(np.float32), ue)
+
+
+@pytest.mark.parametrize("N", [8, 16, 48, 64])
+def test_one_vcycle_matches_oracle(mg, N):
+    f = inputs.gaussian_field(N, 11 + N)
+    h = 100.0 / N
+    note("one V-cycle N=%d" % N)
+    u, st = mg.mg_solve_level(to_dev(f), h, opts=mg.make_opts(max_cycles=1, fixed_cycles=True))
+    fz = f - f.mean()
+    ue = periodic.vcycle(np.zeros_like(f), fz, h)
+    ue -= ue.mean()
+    assert st["cycles"] == 1
+    assert rel_max(to_host(u), ue) < 1e-13
+
+
+@pytest.mark.parametrize("N", [16, 24, 48, 64, 96])
+def test_fp64_solve_matches_oracle(mg, N):
+    f = inputs.gaussian_field(N, 100 + N) + 0.25     # non-zero mean is removed and reported
+    h = 100.0 / N
+    note("fp64 solve N=%d" % N)
+    u, st = mg.mg_solve_level(to_dev(f), h, opts=mg.make_opts(tol=1e-10))
+    ue, info = periodic.solve_level(f, h, tol=1e-10)
+    ug = to_host(u)
+    assert st["cycles"] == info["cycles"]
+    assert abs(st["f_mean"] - info["f_mean"]) < 1e-14
+    assert st["rel_res"] <= 1e-10
+    assert rel_rms(ug, ue) <= 1e-10
+    assert rel_rms(ug, periodic.fft_solve(f, h)) <= 1e-9
+    hist = np.array(st["history"])
+    ref = np.array(info["history"])
+    assert np.allclose(hist[:4], ref[:4], rtol=1e-6)      # rounding-limited later on
+    assert np.allclose(hist, ref, rtol=0.05)
+    assert st["cell_updates"] == periodic.cell_updates(N, st["cycles"])
+
+
+@pytest.mark.parametrize("N", [32, 64, 96])
+def test_mixed_solve_matches_fp64_oracle(mg, N):
+    f = inputs.gaussian_field(N, 200 + N)
+    h = 100.0 / N
+    note("mixed solve N=%d" % N)
+    u, st = mg.mg_solve_level(to_dev(f), h, opts=mg.make_opts(tol=1e-10, prec="mixed", max_cycles=40))
+    ue, _ = periodic.solve_level(f, h, tol=1e-12)
+    assert st["rel_res"] <= 1e-10
+    assert rel_rms(to_host(u), ue) <= 1e-8
+    assert st["cycles"] <= 16
+
+
+def test_c1_64cubed_workload(mg):
+    """64^3 BBKS field, V(2,2) to 1e-10 relative residual."""
+    f = inputs.c1_input()
+    h = inputs.BOX / 64
+    note("C1 64^3")
+    u, st = mg.mg_solve_level(to_dev(f), h, opts=mg.make_opts(tol=1e-10))
+    ue, info = periodic.solve_level(f, h, tol=1e-10)
+    assert st["cycles"] == info["cycles"] <= 12
+    assert rel_rms(to_host(u), ue) <= 1e-10
+
+
+def test_errors_are_reported(mg):
+    N = 16
+    h = 1.0
+    f = inputs.gaussian_field(N, 5)
+    note("error paths")
+    with pytest.raises(mg.MGError) as e:
+        mg.mg_solve_level(to_dev(f), h, opts=mg.make_opts(tol=1e-14, max_cycles=1))
+    assert e.value.code == mg.MG_ENOCONV and e.value.stats["cycles"] == 1
+    bad = f.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(mg.MGError) as e:
+        mg.mg_solve_level(to_dev(bad), h, opts=mg.make_opts(max_cycles=5))
+    assert e.value.code == mg.MG_EDIVERGED
+    # the library still works after a failed call
+    u, st = mg.mg_solve_level(to_dev(f), h)
+    assert st["rel_res"] <= 1e-10
+
+
+def test_warm_start_resumes(mg):
+    N = 32
+    h = 100.0 / N
+    f = inputs.gaussian_field(N, 9)
+    note("warm start")
+    u, st1 = mg.mg_solve_level(to_dev(f), h, opts=mg.make_opts(tol=1e-4))
+    u, st2 = mg.mg_solve_level(to_dev(f), h, u=u, opts=mg.make_opts(tol=1e-10, initial_guess=True))
+    ue, info = periodic.solve_level(f, h, tol=1e-10)
+    assert st1["cycles"] + st2["cycles"] <= info["cycles"] + 1
+    assert rel_rms(to_host(u), ue) < 1e-9
+
+
+def test_batch_equals_solo(mg):
+    inst = inputs.c4_instances(count=6)
+    fs = [inputs.c4_field(N, s, seed) for N, s, seed in inst]
+    hs = [inputs.BOX / N for N, _, _ in inst]
+    note("batch of %d" % len(inst))
+    for prec in ("fp64", "mixed"):
+        o = mg.make_opts(tol=1e-10, prec=prec, max_cycles=40)
+        ub, sts = mg.mg_solve_batch([to_dev(f) for f in fs], hs, opts=o)
+        for f, h, u, s in zip(fs, hs, ub, sts):
+            us, _ = mg.mg_solve_level(to_dev(f), h, opts=o)
+            assert np.array_equal(to_host(u), to_host(us))
+            ue, _ = periodic.solve_level(f, h, tol=1e-12)
+            assert rel_rms(to_host(u), ue) <= (1e-10 if prec == "fp64" else 1e-8)
