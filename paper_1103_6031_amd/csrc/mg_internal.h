@@ -39,7 +39,8 @@ __host__ __device__ inline size_t ghost_face_offset(Dims d, int face) {
         case 2: return 2 * fx;
         case 3: return 2 * fx + fy;
         case 4: return 2 * fx + 2 * fy;
-        default: return 2 * fx + 2 * fy + fz;
+        case 5: return 2 * fx + 2 * fy + fz;
+        default: return 2 * fx + 2 * fy + 2 * fz;  // face 6: total size of the 6 faces
     }
 }
 __host__ __device__ inline size_t ghost_cells(Dims d) { return ghost_face_offset(d, 6); }
