@@ -7,7 +7,8 @@
 //
 // Sources are either periodic n^3 arrays (R = 0: indices wrap) or arrays padded by R ghost cells
 // on every side.  The gradient is evaluated as ((u[-2] - 8 u[-1]) + 8 u[+1]) - u[+2], / (12 h),
-// then scaled.
+// then scaled.  tau takes two passes: psi_j = G4_j phi is stored (extended by 2 cells on
+// patches), then D_ij = G4_i psi_j is evaluated per cell.
 
 #include "mg_internal.h"
 
@@ -53,30 +54,37 @@ __global__ void k_grad4(Src s, double h, double scale, double* __restrict__ ox, 
     oz[t] = scale * g4(s, x, y, z, 2, den);
 }
 
-// D_ij = G4_i (G4_j phi): the inner gradient is evaluated at the four outer stencil points
-__device__ __forceinline__ double d2(const Src& s, int x, int y, int z, int i, int j, double den) {
-    const int ex = i == 0, ey = i == 1, ez = i == 2;
-    double acc = g4(s, x - 2 * ex, y - 2 * ey, z - 2 * ez, j, den);
-    acc = acc + (-8.0) * g4(s, x - ex, y - ey, z - ez, j, den);
-    acc = acc + 8.0 * g4(s, x + ex, y + ey, z + ez, j, den);
-    acc = acc + (-1.0) * g4(s, x + 2 * ex, y + 2 * ey, z + 2 * ez, j, den);
-    return acc / den;
+// psi_j = G4_j phi on the interior extended by e cells (e <= R - 2), unscaled; output arrays
+// are (d + 2e)^3, padded by e
+__global__ void k_psi(Src s, int e, double h, double* __restrict__ p0, double* __restrict__ p1,
+                      double* __restrict__ p2) {
+    const Dims od{s.d.x + 2 * e, s.d.y + 2 * e, s.d.z + 2 * e};
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (t >= od.cells()) return;
+    const int z = (int)(t % od.z) - e;
+    const int y = (int)((t / od.z) % od.y) - e;
+    const int x = (int)(t / ((size_t)od.z * od.y)) - e;
+    const double den = 12.0 * h;
+    p0[t] = g4(s, x, y, z, 0, den);
+    p1[t] = g4(s, x, y, z, 1, den);
+    p2[t] = g4(s, x, y, z, 2, den);
 }
 
-__global__ void k_tau(Src s, double h, double* __restrict__ tau) {
-    const Dims d = s.d;
+// tau = sum_{i>j} D_ii D_jj - D_ij^2 with D_ij = G4_i psi_j; psi periodic (e = 0) or padded by e
+__global__ void k_tau_psi(Src q0, Src q1, Src q2, double h, double* __restrict__ tau) {
+    const Dims d = q0.d;
     const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (t >= d.cells()) return;
     const int z = (int)(t % d.z);
     const int y = (int)((t / d.z) % d.y);
     const int x = (int)(t / ((size_t)d.z * d.y));
     const double den = 12.0 * h;
-    const double Dxx = d2(s, x, y, z, 0, 0, den);
-    const double Dyy = d2(s, x, y, z, 1, 1, den);
-    const double Dzz = d2(s, x, y, z, 2, 2, den);
-    const double Dyx = d2(s, x, y, z, 1, 0, den);
-    const double Dzx = d2(s, x, y, z, 2, 0, den);
-    const double Dzy = d2(s, x, y, z, 2, 1, den);
+    const double Dxx = g4(q0, x, y, z, 0, den);
+    const double Dyy = g4(q1, x, y, z, 1, den);
+    const double Dzz = g4(q2, x, y, z, 2, den);
+    const double Dyx = g4(q0, x, y, z, 1, den);
+    const double Dzx = g4(q0, x, y, z, 2, den);
+    const double Dzy = g4(q1, x, y, z, 2, den);
     double acc = 0.0;
     acc = acc + (Dyy * Dxx - Dyx * Dyx);
     acc = acc + (Dzz * Dxx - Dzx * Dzx);
@@ -139,8 +147,14 @@ void launch_grad4(const double* src, int R, Dims d, double h, double scale, doub
     k_grad4<<<grid_for(d.cells()), kBlock, 0, st>>>(Src{src, R, d}, h, scale, ox, oy, oz);
 }
 
-void launch_tau(const double* src, int R, Dims d, double h, double* tau, hipStream_t st) {
-    k_tau<<<grid_for(d.cells()), kBlock, 0, st>>>(Src{src, R, d}, h, tau);
+void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st) {
+    const int e = R >= 2 ? R - 2 : 0;
+    const Dims od{d.x + 2 * e, d.y + 2 * e, d.z + 2 * e};
+    double* p0 = psi;
+    double* p1 = psi + od.cells();
+    double* p2 = psi + 2 * od.cells();
+    k_psi<<<grid_for(od.cells()), kBlock, 0, st>>>(Src{src, R, d}, e, h, p0, p1, p2);
+    k_tau_psi<<<grid_for(d.cells()), kBlock, 0, st>>>(Src{p0, e, d}, Src{p1, e, d}, Src{p2, e, d}, h, tau);
 }
 
 }  // namespace mgic

@@ -9,53 +9,94 @@
 // Section 3.3: restriction / prolongation only on the region a level shares with the next finer
 // one; patches take their boundary values from ghost zones (see k_ghost_fill).
 //
-// Layout: every level is a row-major [x][y][z] array (z contiguous).  A patch's ghost layer is
-// 6 face arrays back to back (mgic::ghost_face_offset).  Compiled with -ffp-contract=off so the
-// arithmetic order written here is the order executed.
+// Storage (mgic::Lay): every level is [x][y][z] by rows of z.  Periodic levels with an even z
+// extent use the colour-split row layout: the red cells ((x+y+z) even) of a row first, in
+// increasing z, then its black cells.  A red/black half-sweep then reads and writes unit-stride
+// runs only, and the 8 children of a coarse cell sit at the same position Z of both halves of 4
+// fine rows.  Patches (natural rows) keep a separate ghost layer of 6 faces.
+// Compiled with -ffp-contract=off so the arithmetic order written here is the order executed.
 
 #include "mg_internal.h"
 
 namespace mgic {
 
-// ----------------------------------------------------------------------------------------------
-// neighbour access
-// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-template <class T, bool GH>
-__device__ __forceinline__ T neighbour_sum(const T* __restrict__ u, const T* __restrict__ g, Dims d,
-                                           int x, int y, int z, size_t i) {
-    const size_t sx = (size_t)d.y * d.z;
-    const size_t sy = (size_t)d.z;
-    T xm, xp, ym, yp, zm, zp;
-    if constexpr (GH) {
-        xm = x > 0 ? u[i - sx] : g[ghost_face_offset(d, 0) + (size_t)y * d.z + z];
-        xp = x < d.x - 1 ? u[i + sx] : g[ghost_face_offset(d, 1) + (size_t)y * d.z + z];
-        ym = y > 0 ? u[i - sy] : g[ghost_face_offset(d, 2) + (size_t)x * d.z + z];
-        yp = y < d.y - 1 ? u[i + sy] : g[ghost_face_offset(d, 3) + (size_t)x * d.z + z];
-        zm = z > 0 ? u[i - 1] : g[ghost_face_offset(d, 4) + (size_t)x * d.y + y];
-        zp = z < d.z - 1 ? u[i + 1] : g[ghost_face_offset(d, 5) + (size_t)x * d.y + y];
-    } else {
-        xm = u[x > 0 ? i - sx : i + (size_t)(d.x - 1) * sx];
-        xp = u[x < d.x - 1 ? i + sx : i - (size_t)(d.x - 1) * sx];
-        ym = u[y > 0 ? i - sy : i + (size_t)(d.y - 1) * sy];
-        yp = u[y < d.y - 1 ? i + sy : i - (size_t)(d.y - 1) * sy];
-        zm = u[z > 0 ? i - 1 : i + (size_t)(d.z - 1)];
-        zp = u[z < d.z - 1 ? i + 1 : i - (size_t)(d.z - 1)];
+__device__ __forceinline__ size_t lidx(const Lay& L, int x, int y, int z) {
+    const size_t row = (size_t)x * L.d.y + y;
+    if (!L.split) return row * L.d.z + z;
+    return row * L.d.z + (((x + y + z) & 1) ? (size_t)(L.d.z >> 1) : 0) + (z >> 1);
+}
+
+// coordinates of storage position i
+__device__ __forceinline__ void ldecode(const Lay& L, size_t i64, int& x, int& y, int& z) {
+    const unsigned i = (unsigned)i64;   // 32-bit division: every level has fewer than 2^31 cells
+    const unsigned row = i / (unsigned)L.d.z;
+    const int p = (int)(i - row * (unsigned)L.d.z);
+    y = (int)(row % (unsigned)L.d.y);
+    x = (int)(row / (unsigned)L.d.y);
+    if (!L.split) {
+        z = p;
+        return;
     }
+    const int nzh = L.d.z >> 1;
+    const int col = p >= nzh;
+    z = 2 * (p - col * nzh) + ((x + y + col) & 1);
+}
+
+// ((x- + x+) + (y- + y+)) + (z- + z+) on a periodic level in any layout
+template <class T>
+__device__ __forceinline__ T nsum_periodic(const T* __restrict__ u, const Lay& L, int x, int y, int z) {
+    const T xm = u[lidx(L, wrap(x - 1, L.d.x), y, z)], xp = u[lidx(L, wrap(x + 1, L.d.x), y, z)];
+    const T ym = u[lidx(L, x, wrap(y - 1, L.d.y), z)], yp = u[lidx(L, x, wrap(y + 1, L.d.y), z)];
+    const T zm = u[lidx(L, x, y, wrap(z - 1, L.d.z))], zp = u[lidx(L, x, y, wrap(z + 1, L.d.z))];
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
-__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// the same on a patch (natural rows) whose outside neighbours come from the ghost faces
+template <class T>
+__device__ __forceinline__ T nsum_ghost(const T* __restrict__ u, const T* __restrict__ g, Dims d, int x, int y,
+                                        int z) {
+    const size_t sx = (size_t)d.y * d.z, sy = (size_t)d.z;
+    const size_t i = ((size_t)x * d.y + y) * d.z + z;
+    const T xm = x > 0 ? u[i - sx] : g[ghost_face_offset(d, 0) + (size_t)y * d.z + z];
+    const T xp = x < d.x - 1 ? u[i + sx] : g[ghost_face_offset(d, 1) + (size_t)y * d.z + z];
+    const T ym = y > 0 ? u[i - sy] : g[ghost_face_offset(d, 2) + (size_t)x * d.z + z];
+    const T yp = y < d.y - 1 ? u[i + sy] : g[ghost_face_offset(d, 3) + (size_t)x * d.z + z];
+    const T zm = z > 0 ? u[i - 1] : g[ghost_face_offset(d, 4) + (size_t)x * d.y + y];
+    const T zp = z < d.z - 1 ? u[i + 1] : g[ghost_face_offset(d, 5) + (size_t)x * d.y + y];
+    return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
 
+template <class T, bool GH>
+__device__ __forceinline__ T nsum(const T* __restrict__ u, const T* __restrict__ g, const Lay& L, int x, int y,
+                                  int z) {
+    if constexpr (GH) return nsum_ghost<T>(u, g, L.d, x, y, z);
+    else return nsum_periodic<T>(u, L, x, y, z);
+}
+
+// index of covered cell (X,Y,Z) (relative to the covered box) in the parent array
 __device__ __forceinline__ size_t pidx(const ParentMap& pm, int X, int Y, int Z) {
-    // parent index of covered cell (X,Y,Z) relative to the covered box (wraps on periodic parents)
     int a = pm.off[0] + X, b = pm.off[1] + Y, c = pm.off[2] + Z;
-    if (pm.periodic) { a = wrap(a, pm.pd.x); b = wrap(b, pm.pd.y); c = wrap(c, pm.pd.z); }
-    return ((size_t)a * pm.pd.y + b) * pm.pd.z + c;
+    if (pm.periodic) {
+        a = wrap(a, pm.pd.x);
+        b = wrap(b, pm.pd.y);
+        c = wrap(c, pm.pd.z);
+    }
+    return lidx(Lay{pm.pd, pm.split}, a, b, c);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Renumber them
+// so that every XCD works on one contiguous eighth of the grid, keeping neighbouring rows and
+// planes in the same L2.
+__device__ __forceinline__ size_t xcd_block() {
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    if (nb % 8u) return b;
+    return (size_t)(b % 8u) * (nb / 8u) + b / 8u;
 }
 
 // ----------------------------------------------------------------------------------------------
-// deterministic block reduction (wave64 shuffle, then the 4 waves in order)
+// deterministic block reduction (wave64 shuffle, then the waves in order)
 // ----------------------------------------------------------------------------------------------
 
 __device__ double block_sum(double v) {
@@ -81,10 +122,15 @@ __global__ void k_fill(T* __restrict__ p, size_t n, T v) {
         p[i] = v;
 }
 
+// dst (layout ld) = src (layout ls), converting the element type
 template <class A, class B>
-__global__ void k_convert(const A* __restrict__ a, B* __restrict__ b, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        b[i] = (B)a[i];
+__global__ void k_relayout(const A* __restrict__ src, Lay ls, B* __restrict__ dst, Lay ld) {
+    const size_t n = ld.d.cells();
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        ldecode(ld, i, x, y, z);
+        dst[i] = (B)src[lidx(ls, x, y, z)];
+    }
 }
 
 __global__ void k_add_f32(double* __restrict__ u, const float* __restrict__ e, size_t n) {
@@ -100,48 +146,53 @@ __global__ void k_sub_mean(T* __restrict__ a, size_t n, const double* __restrict
 }
 
 // ----------------------------------------------------------------------------------------------
-// red-black Gauss-Seidel half-sweep: one thread per cell of the colour
+// per-cell bodies shared by the grid-wide kernels and the single-workgroup tail kernel (so both
+// produce the same bits)
 // ----------------------------------------------------------------------------------------------
 
-template <class T, bool GH>
-__global__ void k_rbgs_half(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Dims d,
-                            T h2, int colour) {
-    const int nzh = d.z >> 1;
-    const size_t total = (size_t)d.x * d.y * nzh;
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int zh = (int)(t % nzh);
-    const size_t r = t / nzh;
-    const int y = (int)(r % d.y);
-    const int x = (int)(r / d.y);
-    const int z = 2 * zh + ((x + y + colour) & 1);
-    const size_t i = ((size_t)x * d.y + y) * d.z + z;
-    const T s = neighbour_sum<T, GH>(u, g, d, x, y, z, i);
-    u[i] = (s - h2 * f[i]) / T(6);
+// split-layout half-sweep of the cell t of `colour` (t = (row, j) over rows of nz/2 cells).
+// Indices are 32-bit: every level fits in 2^31 cells.
+template <class T>
+__device__ __forceinline__ void cell_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Dims d, T h2,
+                                                int colour, unsigned t) {
+    const unsigned nzh = (unsigned)d.z >> 1;
+    const unsigned j = t % nzh;
+    const unsigned row = t / nzh;
+    const int y = (int)(row % (unsigned)d.y);
+    const int x = (int)(row / (unsigned)d.y);
+    const int q = (x + y + colour) & 1;          // z parity of this colour in the row
+    const unsigned own = colour ? nzh : 0u, oth = colour ? 0u : nzh;
+    const unsigned rs = (unsigned)d.z;
+    const unsigned rxm = ((unsigned)wrap(x - 1, d.x) * d.y + y) * rs, rxp = ((unsigned)wrap(x + 1, d.x) * d.y + y) * rs;
+    const unsigned rym = ((unsigned)x * d.y + wrap(y - 1, d.y)) * rs, ryp = ((unsigned)x * d.y + wrap(y + 1, d.y)) * rs;
+    const unsigned r0 = row * rs;
+    // the cell is z = 2j + q; its z-neighbours are the other colour's entries (z-1)/2, (z+1)/2
+    const unsigned jm = (unsigned)wrap((int)j - 1 + q, (int)nzh), jp = (unsigned)wrap((int)j + q, (int)nzh);
+    const T xm = u[rxm + oth + j], xp = u[rxp + oth + j];
+    const T ym = u[rym + oth + j], yp = u[ryp + oth + j];
+    const T zm = u[r0 + oth + jm], zp = u[r0 + oth + jp];
+    const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
+    u[r0 + own + j] = (s - h2 * f[r0 + own + j]) / T(6);
 }
 
-// ----------------------------------------------------------------------------------------------
-// residual + restriction (steps 3-5), one thread per covered coarse cell
-// ----------------------------------------------------------------------------------------------
-
+// residual + restriction of the covered coarse cell t (steps 3-5)
 template <class T, bool GH>
-__global__ void k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g,
-                                 Dims d, T h2, T* __restrict__ pu, T* __restrict__ pf, T* __restrict__ uold,
-                                 ParentMap pm) {
-    const Dims c{d.x >> 1, d.y >> 1, d.z >> 1};
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (t >= c.cells()) return;
-    const int Z = (int)(t % c.z);
-    const int Y = (int)((t / c.z) % c.y);
-    const int X = (int)(t / ((size_t)c.z * c.y));
+__device__ __forceinline__ void cell_resid_restrict(const T* __restrict__ u, const T* __restrict__ f,
+                                                    const T* __restrict__ g, const Lay& L, T h2,
+                                                    T* __restrict__ pu, T* __restrict__ pf,
+                                                    T* __restrict__ uold, const ParentMap& pm, unsigned t) {
+    const unsigned cz = (unsigned)L.d.z >> 1, cy = (unsigned)L.d.y >> 1;
+    const int Z = (int)(t % cz);
+    const int Y = (int)((t / cz) % cy);
+    const int X = (int)(t / (cz * cy));
     T su = T(0), sr = T(0);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int e = 0; e < 2; ++e) {
                 const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + e;
-                const size_t i = ((size_t)x * d.y + y) * d.z + z;
+                const size_t i = lidx(L, x, y, z);
                 const T ui = u[i];
-                const T s = neighbour_sum<T, GH>(u, g, d, x, y, z, i);
+                const T s = nsum<T, GH>(u, g, L, x, y, z);
                 const T lap = (s - T(6) * ui) / h2;
                 sr = sr + (f[i] - lap);
                 su = su + ui;
@@ -153,41 +204,36 @@ __global__ void k_resid_restrict(const T* __restrict__ u, const T* __restrict__ 
     uold[t] = uc;
 }
 
-// step 6: parent f[cov] += L u over the parent's stencil
+// step 6 for covered cell t: parent f += L u over the parent's own (periodic-wrapped) stencil
 template <class T>
-__global__ void k_fas_rhs(const T* __restrict__ pu, T* __restrict__ pf, ParentMap pm, Dims cov, T H2) {
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (t >= cov.cells()) return;
-    const int Z = (int)(t % cov.z);
-    const int Y = (int)((t / cov.z) % cov.y);
-    const int X = (int)(t / ((size_t)cov.z * cov.y));
-    const int a = pm.off[0] + X, b = pm.off[1] + Y, c = pm.off[2] + Z;
-    const Dims d = pm.pd;
-    const size_t i = ((size_t)wrap(a, d.x) * d.y + wrap(b, d.y)) * d.z + wrap(c, d.z);
-    const T s = neighbour_sum<T, false>(pu, nullptr, d, wrap(a, d.x), wrap(b, d.y), wrap(c, d.z), i);
+__device__ __forceinline__ void cell_fas(const T* __restrict__ pu, T* __restrict__ pf, const ParentMap& pm,
+                                         Dims cov, T H2, unsigned t) {
+    const int Z = (int)(t % (unsigned)cov.z);
+    const int Y = (int)((t / (unsigned)cov.z) % (unsigned)cov.y);
+    const int X = (int)(t / ((unsigned)cov.z * cov.y));
+    const Lay P{pm.pd, pm.split};
+    const int a = wrap(pm.off[0] + X, pm.pd.x), b = wrap(pm.off[1] + Y, pm.pd.y), c = wrap(pm.off[2] + Z, pm.pd.z);
+    const size_t i = lidx(P, a, b, c);
+    const T s = nsum_periodic<T>(pu, P, a, b, c);
     pf[i] = pf[i] + (s - T(6) * pu[i]) / H2;
 }
 
-// step 8: u += inject(parent u[cov] - uold)
+// step 8 for the fine cell at storage position t: u += parent u[cov] - uold
 template <class T>
-__global__ void k_prolong(T* __restrict__ u, Dims d, const T* __restrict__ pu, const T* __restrict__ uold,
-                          ParentMap pm) {
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (t >= d.cells()) return;
-    const int z = (int)(t % d.z);
-    const int y = (int)((t / d.z) % d.y);
-    const int x = (int)(t / ((size_t)d.z * d.y));
+__device__ __forceinline__ void cell_prolong(T* __restrict__ u, const Lay& L, const T* __restrict__ pu,
+                                             const T* __restrict__ uold, const ParentMap& pm, unsigned t) {
+    int x, y, z;
+    ldecode(L, t, x, y, z);
     const int X = x >> 1, Y = y >> 1, Z = z >> 1;
-    const size_t o = ((size_t)X * (d.y >> 1) + Y) * (d.z >> 1) + Z;
+    const size_t o = ((size_t)X * (L.d.y >> 1) + Y) * (L.d.z >> 1) + Z;
     u[t] = u[t] + (pu[pidx(pm, X, Y, Z)] - uold[o]);
 }
 
-// step 1: exact zero-mean solve on an odd periodic M^3 grid by its discrete Green's function,
+// step 1 on an odd periodic M^3 grid (M <= 7) by one workgroup: the discrete Green's function
 // G(d) = M^-3 sum_{m != 0} cos(2 pi m.d / M) / lambda(m), lambda the 7-point symbol (Table 1).
+// G and F are workgroup arrays of at least M^3 doubles.
 template <class T>
-__global__ void k_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, double h) {
-    __shared__ double G[343];
-    __shared__ double F[343];
+__device__ void block_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, double h, double* G, double* F) {
     const int n3 = M * M * M;
     if (M == 1) {
         if (threadIdx.x == 0) u[0] = T(0);
@@ -221,6 +267,158 @@ __global__ void k_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, do
 }
 
 // ----------------------------------------------------------------------------------------------
+// grid-wide kernels
+// ----------------------------------------------------------------------------------------------
+
+// periodic level in the colour-split layout: V consecutive cells of a half-row per thread
+template <class T, int V>
+__global__ void k_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Dims d, T h2, int colour) {
+    const unsigned total = (unsigned)d.x * d.y * ((unsigned)d.z >> 1);
+    const unsigned base = (unsigned)xcd_block() * blockDim.x * V + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const unsigned t = base + v * blockDim.x;   // each of the V passes is unit-stride over the wave
+        if (t < total) cell_rbgs_split<T>(u, f, d, h2, colour, t);
+    }
+}
+
+// patch (natural rows, ghost faces): one thread per cell of the colour
+template <class T>
+__global__ void k_rbgs_ghost(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Dims d, T h2,
+                             int colour) {
+    const unsigned nzh = (unsigned)d.z >> 1;
+    const unsigned total = (unsigned)d.x * d.y * nzh;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int zh = (int)(t % nzh);
+    const unsigned r = t / nzh;
+    const int y = (int)(r % (unsigned)d.y);
+    const int x = (int)(r / (unsigned)d.y);
+    const int z = 2 * zh + ((x + y + colour) & 1);
+    const size_t i = ((size_t)x * d.y + y) * d.z + z;
+    const T s = nsum_ghost<T>(u, g, d, x, y, z);
+    u[i] = (s - h2 * f[i]) / T(6);
+}
+
+template <class T, bool GH>
+__global__ void k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g,
+                                 Lay L, T h2, T* __restrict__ pu, T* __restrict__ pf, T* __restrict__ uold,
+                                 ParentMap pm) {
+    const unsigned n = (unsigned)(L.d.x >> 1) * (L.d.y >> 1) * (L.d.z >> 1);
+    const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
+    if (t < n) cell_resid_restrict<T, GH>(u, f, g, L, h2, pu, pf, uold, pm, t);
+}
+
+template <class T>
+__global__ void k_fas_rhs(const T* __restrict__ pu, T* __restrict__ pf, ParentMap pm, Dims cov, T H2) {
+    const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
+    if (t < (unsigned)cov.cells()) cell_fas<T>(pu, pf, pm, cov, H2, t);
+}
+
+template <class T>
+__global__ void k_prolong(T* __restrict__ u, Lay L, const T* __restrict__ pu, const T* __restrict__ uold,
+                          ParentMap pm) {
+    const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
+    if (t < (unsigned)L.d.cells()) cell_prolong<T>(u, L, pu, uold, pm, t);
+}
+
+template <class T>
+__global__ void k_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, double h) {
+    __shared__ double G[343];
+    __shared__ double F[343];
+    block_coarsest<T>(u, f, M, h, G, F);
+}
+
+// ----------------------------------------------------------------------------------------------
+// tail: the whole V-cycle below a small level, run by one workgroup in one launch, with every
+// level of it held in LDS.  As separate kernels these levels are launch-bound; here each step is
+// a loop of the workgroup's threads over a level's cells with a barrier between steps.  The
+// first level's u and f are read from global memory and its u is written back at the end.
+// ----------------------------------------------------------------------------------------------
+
+template <class T>
+__host__ __device__ inline size_t tail_lds_bytes(const TailPlan<T>& tp) {
+    size_t off = 0;
+    for (int k = 0; k < tp.n; ++k) {
+        const size_t c = tp.lev[k].lay.d.cells();
+        off += 2 * c * sizeof(T);
+        if (k + 1 < tp.n) off += (c / 8) * sizeof(T);
+        off = (off + 15) & ~(size_t)15;
+    }
+    return off + 2 * 343 * sizeof(double);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* U[kTailMaxLevels];
+    T* F[kTailMaxLevels];
+    T* O[kTailMaxLevels];
+    size_t off = 0;
+    for (int k = 0; k < tp.n; ++k) {
+        const size_t c = tp.lev[k].lay.d.cells();
+        U[k] = (T*)(smem + off);
+        off += c * sizeof(T);
+        F[k] = (T*)(smem + off);
+        off += c * sizeof(T);
+        O[k] = (T*)(smem + off);
+        if (k + 1 < tp.n) off += (c / 8) * sizeof(T);
+        off = (off + 15) & ~(size_t)15;
+    }
+    double* G = (double*)(smem + off);
+    double* Gf = G + 343;
+    const unsigned nt = blockDim.x;
+    {
+        const unsigned n0 = (unsigned)tp.lev[0].lay.d.cells();
+        for (unsigned t = threadIdx.x; t < n0; t += nt) {
+            U[0][t] = tp.lev[0].u[t];
+            F[0][t] = tp.lev[0].f[t];
+        }
+        __syncthreads();
+    }
+    // descent: smooth, restrict, FAS right-hand side
+    for (int l = 0; l + 1 < tp.n; ++l) {
+        const Lay A = tp.lev[l].lay, Bl = tp.lev[l + 1].lay;
+        const T h2 = (T)(tp.lev[l].h * tp.lev[l].h);
+        const unsigned half = (unsigned)A.d.cells() >> 1;
+        for (int s = 0; s < tp.nu1; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for (unsigned t = threadIdx.x; t < half; t += nt) cell_rbgs_split<T>(U[l], F[l], A.d, h2, c, t);
+                __syncthreads();
+            }
+        const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
+        const unsigned nc = (unsigned)A.d.cells() >> 3;
+        for (unsigned t = threadIdx.x; t < nc; t += nt)
+            cell_resid_restrict<T, false>(U[l], F[l], (const T*)nullptr, A, h2, U[l + 1], F[l + 1], O[l], pm, t);
+        __syncthreads();
+        const T H2 = (T)(tp.lev[l + 1].h * tp.lev[l + 1].h);
+        for (unsigned t = threadIdx.x; t < nc; t += nt) cell_fas<T>(U[l + 1], F[l + 1], pm, Bl.d, H2, t);
+        __syncthreads();
+    }
+    {
+        const int c = tp.n - 1;
+        block_coarsest<T>(U[c], F[c], tp.lev[c].lay.d.x, tp.lev[c].h, G, Gf);
+        __syncthreads();
+    }
+    // ascent: correct, smooth
+    for (int l = tp.n - 2; l >= 0; --l) {
+        const Lay A = tp.lev[l].lay, Bl = tp.lev[l + 1].lay;
+        const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
+        const unsigned n = (unsigned)A.d.cells();
+        for (unsigned t = threadIdx.x; t < n; t += nt) cell_prolong<T>(U[l], A, U[l + 1], O[l], pm, t);
+        __syncthreads();
+        const T h2 = (T)(tp.lev[l].h * tp.lev[l].h);
+        for (int s = 0; s < tp.nu2; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_rbgs_split<T>(U[l], F[l], A.d, h2, c, t);
+                __syncthreads();
+            }
+    }
+    const unsigned n0 = (unsigned)tp.lev[0].lay.d.cells();
+    for (unsigned t = threadIdx.x; t < n0; t += nt) tp.lev[0].u[t] = U[0][t];
+}
+
+// ----------------------------------------------------------------------------------------------
 // coarse-fine ghost zones with flux matching (Section 3.3, Table 2 order-1 flux), one thread per
 // 2x2 group of fine face cells sharing a parent C.  For the low-x face and fine cell (0, j, k):
 //   a  = quadratic interpolation in the outside parent layer at the child's transverse position
@@ -244,10 +442,18 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
                  gz = (size_t)(d.x / 2) * (d.y / 2);
     size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     int face;
-    if (t < 2 * gx) face = (int)(t / gx), t %= gx;
-    else if ((t -= 2 * gx) < 2 * gy) face = 2 + (int)(t / gy), t %= gy;
-    else if ((t -= 2 * gy) < 2 * gz) face = 4 + (int)(t / gz), t %= gz;
-    else return;
+    if (t < 2 * gx) {
+        face = (int)(t / gx);
+        t %= gx;
+    } else if ((t -= 2 * gx) < 2 * gy) {
+        face = 2 + (int)(t / gy);
+        t %= gy;
+    } else if ((t -= 2 * gy) < 2 * gz) {
+        face = 4 + (int)(t / gz);
+        t %= gz;
+    } else {
+        return;
+    }
     const int a = face >> 1, side = face & 1;
     const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
     const int nc2 = n[c] / 2;
@@ -256,6 +462,7 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
     const int i0 = side ? n[a] - 1 : 0, i1 = side ? n[a] - 2 : 1;
     const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
     const int pdim[3] = {pm.pd.x, pm.pd.y, pm.pd.z};
+    const Lay PL{pm.pd, pm.split};
     // 3x3 outside coarse layer around O
     double L[3][3];
     for (int db = 0; db < 3; ++db)
@@ -264,14 +471,16 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
             q[a] = on;
             q[b] = pm.off[b] + J + db - 1;
             q[c] = pm.off[c] + K + dc - 1;
-            if (pm.periodic) for (int k = 0; k < 3; ++k) q[k] = wrap(q[k], pdim[k]);
-            L[db][dc] = (double)pu[((size_t)q[0] * pdim[1] + q[1]) * pdim[2] + q[2]];
+            if (pm.periodic)
+                for (int k = 0; k < 3; ++k) q[k] = wrap(q[k], pdim[k]);
+            L[db][dc] = (double)pu[lidx(PL, q[0], q[1], q[2])];
         }
     double u0[2][2], u1[2][2], g0[2][2];
     for (int jb = 0; jb < 2; ++jb)
         for (int kc = 0; kc < 2; ++kc) {
             int p0[3], p1[3];
-            p0[a] = i0; p1[a] = i1;
+            p0[a] = i0;
+            p1[a] = i1;
             p0[b] = p1[b] = 2 * J + jb;
             p0[c] = p1[c] = 2 * K + kc;
             u0[jb][kc] = (double)u[((size_t)p0[0] * d.y + p0[1]) * d.z + p0[2]];
@@ -302,9 +511,9 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
 
 // parent[cov] = mean8(fine), bottom-up composite restriction
 template <class T>
-__global__ void k_restrict_cov(const T* __restrict__ v, Dims d, T* __restrict__ pv, ParentMap pm) {
-    const Dims c{d.x >> 1, d.y >> 1, d.z >> 1};
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+__global__ void k_restrict_cov(const T* __restrict__ v, Lay L, T* __restrict__ pv, ParentMap pm) {
+    const Dims c{L.d.x >> 1, L.d.y >> 1, L.d.z >> 1};
+    const size_t t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= c.cells()) return;
     const int Z = (int)(t % c.z);
     const int Y = (int)((t / c.z) % c.y);
@@ -312,7 +521,7 @@ __global__ void k_restrict_cov(const T* __restrict__ v, Dims d, T* __restrict__ 
     T s = T(0);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
-            for (int e = 0; e < 2; ++e) s = s + v[((size_t)(2 * X + a) * d.y + (2 * Y + b)) * d.z + (2 * Z + e)];
+            for (int e = 0; e < 2; ++e) s = s + v[lidx(L, 2 * X + a, 2 * Y + b, 2 * Z + e)];
     pv[pidx(pm, X, Y, Z)] = s * T(0.125);
 }
 
@@ -326,31 +535,29 @@ __device__ __forceinline__ bool in_box(const CovBox& cb, int x, int y, int z) {
 }
 
 template <class T, class R, bool GH>
-__global__ void k_residual(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Dims d,
-                           T h2, CovBox cb, R* __restrict__ rout, double* __restrict__ partials) {
+__global__ void k_residual(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Lay L,
+                           T h2, CovBox cb, R* __restrict__ rout, Lay LR, double* __restrict__ partials) {
     double acc = 0.0;
-    const size_t n = d.cells();
+    const size_t n = L.d.cells();
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int z = (int)(i % d.z);
-        const int y = (int)((i / d.z) % d.y);
-        const int x = (int)(i / ((size_t)d.z * d.y));
-        const T s = neighbour_sum<T, GH>(u, g, d, x, y, z, i);
+        int x, y, z;
+        ldecode(L, i, x, y, z);
+        const T s = nsum<T, GH>(u, g, L, x, y, z);
         const T r = f[i] - (s - T(6) * u[i]) / h2;
         const bool cov = in_box(cb, x, y, z);
         if (!cov) acc += (double)r * (double)r;
-        if (rout) rout[i] = cov ? R(0) : (R)r;
+        if (rout) rout[lidx(LR, x, y, z)] = cov ? R(0) : (R)r;
     }
     const double bs = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
-__global__ void k_sum(const double* __restrict__ a, Dims d, CovBox cb, int square, double* __restrict__ partials) {
+__global__ void k_sum(const double* __restrict__ a, Lay L, CovBox cb, int square, double* __restrict__ partials) {
     double acc = 0.0;
-    const size_t n = d.cells();
+    const size_t n = L.d.cells();
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int z = (int)(i % d.z);
-        const int y = (int)((i / d.z) % d.y);
-        const int x = (int)(i / ((size_t)d.z * d.y));
+        int x, y, z;
+        ldecode(L, i, x, y, z);
         if (in_box(cb, x, y, z)) continue;
         const double v = a[i];
         acc += square ? v * v : v;
@@ -379,11 +586,11 @@ void launch_fill(T* p, size_t n, T v, hipStream_t st) {
     k_fill<T><<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(p, n, v);
 }
 template <class A, class B>
-void launch_convert(const A* a, B* b, size_t n, hipStream_t st) {
-    k_convert<A, B><<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(a, b, n);
+void launch_relayout(const A* src, Lay ls, B* dst, Lay ld, hipStream_t st) {
+    k_relayout<A, B><<<grid_for(ld.d.cells(), kBlock, 8192), kBlock, 0, st>>>(src, ls, dst, ld);
 }
 void launch_add_f32_to_f64(double* u, const float* e, size_t n, hipStream_t st) {
-    k_add_f32<<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(u, e, n);
+    k_add_f32<<<grid_for(n, kBlock, 8192), kBlock, 0, st>>>(u, e, n);
 }
 template <class T>
 void launch_sub_mean(T* a, size_t n, const double* sum, double inv_count, hipStream_t st) {
@@ -391,24 +598,41 @@ void launch_sub_mean(T* a, size_t n, const double* sum, double inv_count, hipStr
 }
 
 template <class T>
-void launch_rbgs_half(T* u, const T* f, const T* ghosts, Dims d, double h, int colour, hipStream_t st) {
-    const size_t n = (size_t)d.x * d.y * (d.z / 2);
+void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h, int colour, hipStream_t st) {
+    const size_t n = (size_t)L.d.x * L.d.y * (L.d.z / 2);
     const T h2 = (T)(h * h);
     if (ghosts)
-        k_rbgs_half<T, true><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, d, h2, colour);
+        k_rbgs_ghost<T><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L.d, h2, colour);
+    else if (n >= (size_t)kBlock * 64 * 2)
+        k_rbgs_split<T, 2><<<grid_for((n + 1) / 2), kBlock, 0, st>>>(u, f, L.d, h2, colour);
     else
-        k_rbgs_half<T, false><<<grid_for(n), kBlock, 0, st>>>(u, f, nullptr, d, h2, colour);
+        k_rbgs_split<T, 1><<<grid_for(n), kBlock, 0, st>>>(u, f, L.d, h2, colour);
 }
 
 template <class T>
-void launch_resid_restrict(const T* u, const T* f, const T* ghosts, Dims d, double h, T* pu, T* pf, T* uold,
+void launch_tail(const TailPlan<T>& tp, hipStream_t st) {
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+        attr = true;
+    }
+    k_tail<T><<<1, kTailThreads, tail_lds_bytes(tp), st>>>(tp);
+}
+
+template <class T>
+size_t tail_lds_size(const TailPlan<T>& tp) {
+    return tail_lds_bytes(tp);
+}
+
+template <class T>
+void launch_resid_restrict(const T* u, const T* f, const T* ghosts, Lay L, double h, T* pu, T* pf, T* uold,
                            ParentMap pm, hipStream_t st) {
-    const size_t n = (size_t)(d.x / 2) * (d.y / 2) * (d.z / 2);
+    const size_t n = (size_t)(L.d.x / 2) * (L.d.y / 2) * (L.d.z / 2);
     const T h2 = (T)(h * h);
     if (ghosts)
-        k_resid_restrict<T, true><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, d, h2, pu, pf, uold, pm);
+        k_resid_restrict<T, true><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, pu, pf, uold, pm);
     else
-        k_resid_restrict<T, false><<<grid_for(n), kBlock, 0, st>>>(u, f, nullptr, d, h2, pu, pf, uold, pm);
+        k_resid_restrict<T, false><<<grid_for(n), kBlock, 0, st>>>(u, f, nullptr, L, h2, pu, pf, uold, pm);
 }
 
 template <class T>
@@ -417,8 +641,8 @@ void launch_fas_rhs(const T* pu, T* pf, ParentMap pm, Dims cov, double H, hipStr
 }
 
 template <class T>
-void launch_prolong(T* u, Dims d, const T* pu, const T* uold, ParentMap pm, hipStream_t st) {
-    k_prolong<T><<<grid_for(d.cells()), kBlock, 0, st>>>(u, d, pu, uold, pm);
+void launch_prolong(T* u, Lay L, const T* pu, const T* uold, ParentMap pm, hipStream_t st) {
+    k_prolong<T><<<grid_for(L.d.cells()), kBlock, 0, st>>>(u, L, pu, uold, pm);
 }
 
 template <class T>
@@ -433,26 +657,26 @@ void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Dims d, ParentMap pm,
 }
 
 template <class T>
-void launch_restrict_cov(const T* fine, Dims d, T* parent, ParentMap pm, hipStream_t st) {
-    const size_t n = (size_t)(d.x / 2) * (d.y / 2) * (d.z / 2);
-    k_restrict_cov<T><<<grid_for(n), kBlock, 0, st>>>(fine, d, parent, pm);
+void launch_restrict_cov(const T* fine, Lay L, T* parent, ParentMap pm, hipStream_t st) {
+    const size_t n = (size_t)(L.d.x / 2) * (L.d.y / 2) * (L.d.z / 2);
+    k_restrict_cov<T><<<grid_for(n), kBlock, 0, st>>>(fine, L, parent, pm);
 }
 
 template <class T, class R>
-void launch_residual(const T* u, const T* f, const T* ghosts, Dims d, double h, CovBox cov, R* rout,
+void launch_residual(const T* u, const T* f, const T* ghosts, Lay L, double h, CovBox cov, R* rout, Lay LR,
                      double* partials, int* nparts, hipStream_t st) {
-    const int g = grid_for(d.cells(), kBlock, kMaxPartials);
+    const int g = grid_for(L.d.cells(), kBlock, kMaxPartials);
     const T h2 = (T)(h * h);
     if (ghosts)
-        k_residual<T, R, true><<<g, kBlock, 0, st>>>(u, f, ghosts, d, h2, cov, rout, partials);
+        k_residual<T, R, true><<<g, kBlock, 0, st>>>(u, f, ghosts, L, h2, cov, rout, LR, partials);
     else
-        k_residual<T, R, false><<<g, kBlock, 0, st>>>(u, f, nullptr, d, h2, cov, rout, partials);
+        k_residual<T, R, false><<<g, kBlock, 0, st>>>(u, f, nullptr, L, h2, cov, rout, LR, partials);
     *nparts = g;
 }
 
-void launch_sum(const double* a, Dims d, CovBox cov, int square, double* partials, int* nparts, hipStream_t st) {
-    const int g = grid_for(d.cells(), kBlock, kMaxPartials);
-    k_sum<<<g, kBlock, 0, st>>>(a, d, cov, square, partials);
+void launch_sum(const double* a, Lay L, CovBox cov, int square, double* partials, int* nparts, hipStream_t st) {
+    const int g = grid_for(L.d.cells(), kBlock, kMaxPartials);
+    k_sum<<<g, kBlock, 0, st>>>(a, L, cov, square, partials);
     *nparts = g;
 }
 
@@ -463,25 +687,27 @@ void launch_finalize(const double* partials, SegList segs, double* out, hipStrea
 // explicit instantiations
 template void launch_fill<double>(double*, size_t, double, hipStream_t);
 template void launch_fill<float>(float*, size_t, float, hipStream_t);
-template void launch_convert<double, float>(const double*, float*, size_t, hipStream_t);
-template void launch_convert<float, double>(const float*, double*, size_t, hipStream_t);
-template void launch_convert<double, double>(const double*, double*, size_t, hipStream_t);
+template void launch_relayout<double, float>(const double*, Lay, float*, Lay, hipStream_t);
+template void launch_relayout<float, double>(const float*, Lay, double*, Lay, hipStream_t);
+template void launch_relayout<double, double>(const double*, Lay, double*, Lay, hipStream_t);
 template void launch_sub_mean<double>(double*, size_t, const double*, double, hipStream_t);
-#define MGIC_INST(T)                                                                                          \
-    template void launch_rbgs_half<T>(T*, const T*, const T*, Dims, double, int, hipStream_t);                \
-    template void launch_resid_restrict<T>(const T*, const T*, const T*, Dims, double, T*, T*, T*, ParentMap, \
-                                           hipStream_t);                                                      \
-    template void launch_fas_rhs<T>(const T*, T*, ParentMap, Dims, double, hipStream_t);                      \
-    template void launch_prolong<T>(T*, Dims, const T*, const T*, ParentMap, hipStream_t);                    \
-    template void launch_coarsest<T>(T*, const T*, int, double, hipStream_t);                                 \
-    template void launch_ghost_fill<T>(const T*, const T*, T*, Dims, ParentMap, int, hipStream_t);            \
-    template void launch_restrict_cov<T>(const T*, Dims, T*, ParentMap, hipStream_t);
+#define MGIC_INST(T)                                                                                        \
+    template void launch_rbgs_half<T>(T*, const T*, const T*, Lay, double, int, hipStream_t);               \
+    template void launch_resid_restrict<T>(const T*, const T*, const T*, Lay, double, T*, T*, T*, ParentMap, \
+                                           hipStream_t);                                                    \
+    template void launch_fas_rhs<T>(const T*, T*, ParentMap, Dims, double, hipStream_t);                    \
+    template void launch_prolong<T>(T*, Lay, const T*, const T*, ParentMap, hipStream_t);                   \
+    template void launch_coarsest<T>(T*, const T*, int, double, hipStream_t);                               \
+    template void launch_ghost_fill<T>(const T*, const T*, T*, Dims, ParentMap, int, hipStream_t);          \
+    template void launch_restrict_cov<T>(const T*, Lay, T*, ParentMap, hipStream_t);                \
+    template void launch_tail<T>(const TailPlan<T>&, hipStream_t);                                   \
+    template size_t tail_lds_size<T>(const TailPlan<T>&);
 MGIC_INST(double)
 MGIC_INST(float)
 #undef MGIC_INST
-template void launch_residual<double, double>(const double*, const double*, const double*, Dims, double, CovBox,
-                                              double*, double*, int*, hipStream_t);
-template void launch_residual<double, float>(const double*, const double*, const double*, Dims, double, CovBox,
-                                             float*, double*, int*, hipStream_t);
+template void launch_residual<double, double>(const double*, const double*, const double*, Lay, double, CovBox,
+                                              double*, Lay, double*, int*, hipStream_t);
+template void launch_residual<double, float>(const double*, const double*, const double*, Lay, double, CovBox,
+                                             float*, Lay, double*, int*, hipStream_t);
 
 }  // namespace mgic

@@ -17,11 +17,19 @@ struct Dims {
     __host__ __device__ size_t cells() const { return (size_t)x * y * z; }
 };
 
+// Storage of one level: natural rows, or the colour-split rows of periodic levels (each row of
+// z holds its red cells, (x+y+z) even, in increasing z, then its black cells).
+struct Lay {
+    Dims d;
+    int split;
+};
+
 // Where a fine level's coarse representation lives inside its parent array.
 struct ParentMap {
     Dims pd;        // parent array dims
     int off[3];     // first covered parent cell
     int periodic;   // parent is periodic (base or a coarsening of it)
+    int split;      // parent stored in the colour-split layout
 };
 
 // Covered box of a level (cells owned by the next finer level); n = 0 means none.
@@ -45,6 +53,25 @@ __host__ __device__ inline size_t ghost_face_offset(Dims d, int face) {
 }
 __host__ __device__ inline size_t ghost_cells(Dims d) { return ghost_face_offset(d, 6); }
 
+// One periodic level of the single-workgroup tail V-cycle (lev[0] finest, lev[n-1] coarsest).
+constexpr int kTailThreads = 1024;
+constexpr size_t kTailMaxCells = 16 * 16 * 16;   // levels at or below this size join the tail
+constexpr size_t kTailMaxLds = 160 * 1024;        // LDS one gfx950 workgroup may hold
+constexpr int kTailMaxLevels = 8;
+template <class T>
+struct TailLevel {
+    T* u;
+    T* f;
+    T* uold;    // unused: the tail keeps its restricted copies in LDS
+    Lay lay;    // colour-split except the odd (or single-cell) coarsest level
+    double h;
+};
+template <class T>
+struct TailPlan {
+    int n, nu1, nu2;
+    TailLevel<T> lev[kTailMaxLevels];
+};
+
 // Segments of partial sums combined by the finalize kernel: out = sum_s w[s] * sum(partials[s]).
 struct SegList {
     int n;
@@ -57,26 +84,26 @@ struct SegList {
 // launchers (defined in the .hip files); all enqueue on `st`
 // ----------------------------------------------------------------------------------------------
 template <class T> void launch_fill(T* p, size_t n, T v, hipStream_t st);
-template <class A, class B> void launch_convert(const A* a, B* b, size_t n, hipStream_t st);
+template <class A, class B> void launch_relayout(const A* src, Lay ls, B* dst, Lay ld, hipStream_t st);
 void launch_add_f32_to_f64(double* u, const float* e, size_t n, hipStream_t st);
 template <class T> void launch_sub_mean(T* a, size_t n, const double* sum, double inv_count, hipStream_t st);
 
-// red-black half-sweep (colour 0 = red = (x+y+z) even); ghosts == nullptr => periodic wrap
-template <class T> void launch_rbgs_half(T* u, const T* f, const T* ghosts, Dims d, double h,
+// red-black half-sweep (colour 0 = red = (x+y+z) even); ghosts == nullptr => periodic level in
+// the colour-split layout, else a patch in natural rows with its ghost faces
+template <class T> void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h,
                                          int colour, hipStream_t st);
-
-// fused red+black sweep(s) on a periodic level, ping-pong src -> dst
-template <class T> bool fused_sweep_supported(Dims d);
-template <class T> void launch_rbgs_fused(const T* src, T* dst, const T* f, Dims d, double h, hipStream_t st);
 
 // residual r = f - L u on the fine level, restricted: parent u[cov] = mean8 u, uold = mean8 u,
 // parent f[cov] = mean8 r  (fine level periodic if ghosts == nullptr)
-template <class T> void launch_resid_restrict(const T* u, const T* f, const T* ghosts, Dims d, double h,
+template <class T> void launch_resid_restrict(const T* u, const T* f, const T* ghosts, Lay L, double h,
                                               T* pu, T* pf, T* uold, ParentMap pm, hipStream_t st);
 // parent f[cov] += L u  (FAS coarse right-hand side), L over the parent's own stencil
 template <class T> void launch_fas_rhs(const T* pu, T* pf, ParentMap pm, Dims cov, double H, hipStream_t st);
 // fine u += inject(parent u[cov] - uold)
-template <class T> void launch_prolong(T* u, Dims d, const T* pu, const T* uold, ParentMap pm, hipStream_t st);
+template <class T> void launch_prolong(T* u, Lay L, const T* pu, const T* uold, ParentMap pm, hipStream_t st);
+// V-cycle over all levels of a tail plan in one single-workgroup launch
+template <class T> void launch_tail(const TailPlan<T>& tp, hipStream_t st);
+template <class T> size_t tail_lds_size(const TailPlan<T>& tp);
 // exact coarsest solve on an odd periodic M^3 grid (M = 1: u = 0)
 template <class T> void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st);
 
@@ -84,15 +111,15 @@ template <class T> void launch_coarsest(T* u, const T* f, int M, double h, hipSt
 template <class T> void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Dims d, ParentMap pm,
                                           int flux_match, hipStream_t st);
 // parent[cov] = mean8(fine)
-template <class T> void launch_restrict_cov(const T* fine, Dims d, T* parent, ParentMap pm, hipStream_t st);
+template <class T> void launch_restrict_cov(const T* fine, Lay L, T* parent, ParentMap pm, hipStream_t st);
 
 // residual of one level: per-block partial sums of r^2 over cells outside `cov`; r written to
 // rout (if non-null; cells inside cov get 0)
-template <class T, class R> void launch_residual(const T* u, const T* f, const T* ghosts, Dims d, double h,
-                                                 CovBox cov, R* rout, double* partials, int* nparts,
+template <class T, class R> void launch_residual(const T* u, const T* f, const T* ghosts, Lay L, double h,
+                                                 CovBox cov, R* rout, Lay LR, double* partials, int* nparts,
                                                  hipStream_t st);
 // per-block partial sums of a (or a^2) over cells outside cov
-void launch_sum(const double* a, Dims d, CovBox cov, int square, double* partials, int* nparts, hipStream_t st);
+void launch_sum(const double* a, Lay L, CovBox cov, int square, double* partials, int* nparts, hipStream_t st);
 void launch_finalize(const double* partials, SegList segs, double* out, hipStream_t st);
 
 // LPT: padded copy with tri-quadratic ghosts of width R from the parent (covered parent cells
@@ -102,8 +129,9 @@ void launch_wide_ghost(const double* pu, const double* u, double* padded, Dims d
 // psi_c = scale * G4_c phi ; src is periodic (R = 0) or padded by R
 void launch_grad4(const double* src, int R, Dims d, double h, double scale, double* ox, double* oy,
                   double* oz, hipStream_t st);
-// tau = sum_{i>j} D_ii D_jj - D_ij^2 ; src periodic (R = 0) or padded by R >= 4
-void launch_tau(const double* src, int R, Dims d, double h, double* tau, hipStream_t st);
+// tau = sum_{i>j} D_ii D_jj - D_ij^2 ; src periodic (R = 0) or padded by R >= 4; psi is scratch
+// for 3 arrays of (d + 2(R-2))^3 (d^3 when periodic)
+void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st);
 
 inline int grid_for(size_t n, int per_block = kBlock, int cap = 1 << 30) {
     size_t g = (n + per_block - 1) / per_block;

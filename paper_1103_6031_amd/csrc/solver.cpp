@@ -52,10 +52,12 @@ struct Level {
     double h = 0;
     bool periodic = false;  // base or a coarsening of it
     int p = -1;             // hierarchy index (0 = base), -1 for coarsenings
+    Lay lay{};              // storage: colour-split rows on even periodic levels, else natural
     ParentMap pm{};         // coarse representation inside L[l+1]
     CovBox child{};         // region of this level covered by L[l-1]
-    double *u = nullptr, *f = nullptr, *g = nullptr, *uold = nullptr, *alt = nullptr;
-    float *u32 = nullptr, *f32 = nullptr, *g32 = nullptr, *uold32 = nullptr, *alt32 = nullptr;
+    double* u_user = nullptr;  // caller's array of a hierarchy level (natural rows)
+    double *u = nullptr, *f = nullptr, *g = nullptr, *uold = nullptr;   // working arrays (lay)
+    float *u32 = nullptr, *f32 = nullptr, *g32 = nullptr, *uold32 = nullptr;
 };
 
 struct Plan {
@@ -63,6 +65,7 @@ struct Plan {
     int nh = 0;      // hierarchy levels (patches + base)
     int last = 0;    // index of the coarsest level
     int nu1 = 2, nu2 = 2;
+    int tail = -1;   // first level of the single-workgroup tail V-cycle (-1: none)
     bool mixed = false;
     double* partials = nullptr;  // kMaxPartials per level segment
     double* scal = nullptr;      // device scalars
@@ -70,10 +73,10 @@ struct Plan {
 
 enum { S_FSUM = 0, S_FNORM = 1, S_RNORM = 2, S_USUM = 3, S_TMP = 4, S_COUNT = 8 };
 
-template <class T> struct B { T *u, *f, *g, *uold, *alt; };
+template <class T> struct B { T *u, *f, *g, *uold; };
 template <class T> static B<T> bufs(Level& l);
-template <> B<double> bufs<double>(Level& l) { return {l.u, l.f, l.g, l.uold, l.alt}; }
-template <> B<float> bufs<float>(Level& l) { return {l.u32, l.f32, l.g32, l.uold32, l.alt32}; }
+template <> B<double> bufs<double>(Level& l) { return {l.u, l.f, l.g, l.uold}; }
+template <> B<float> bufs<float>(Level& l) { return {l.u32, l.f32, l.g32, l.uold32}; }
 
 static bool odd_ok(int m) { return m == 1 || m == 3 || m == 5 || m == 7; }
 
@@ -87,6 +90,7 @@ static int validate_hier(const mg_hier* H) {
     while (m % 2 == 0) m /= 2;
     if (!odd_ok(m)) return fail(MG_EINVAL, "base size must be 2^k * m with m in {1,3,5,7}");
     if (!(b.h > 0) || !std::isfinite(b.h)) return fail(MG_EINVAL, "base spacing must be positive");
+    if ((long long)N * N * N >= (1ll << 31)) return fail(MG_EINVAL, "base has 2^31 cells or more");
     for (int p = 1; p < H->nlev; ++p) {
         const mg_level& l = H->lev[p];
         const mg_level& q = H->lev[p - 1];
@@ -99,6 +103,7 @@ static int validate_hier(const mg_hier* H) {
             else ok = lo >= 4 && hi <= q.n[a] - 4;
             if (!ok) return fail(MG_EINVAL, "patch " + std::to_string(p) + " not properly nested in its parent");
         }
+        if ((long long)l.n[0] * l.n[1] * l.n[2] >= (1ll << 31)) return fail(MG_EINVAL, "patch has 2^31 cells or more");
     }
     return MG_OK;
 }
@@ -137,11 +142,13 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
         }
     }
     P.last = (int)P.L.size() - 1;
+    for (auto& L : P.L) L.lay = Lay{L.d, (L.periodic && L.d.z % 2 == 0) ? 1 : 0};
     for (int l = 0; l < P.last; ++l) {
         Level& L = P.L[l];
         Level& Q = P.L[l + 1];
         L.pm.pd = Q.d;
         L.pm.periodic = Q.periodic ? 1 : 0;
+        L.pm.split = Q.lay.split;
         for (int a = 0; a < 3; ++a) L.pm.off[a] = (L.p >= 1) ? H->lev[L.p].off[a] : 0;
         Q.child.lo[0] = L.pm.off[0]; Q.child.lo[1] = L.pm.off[1]; Q.child.lo[2] = L.pm.off[2];
         Q.child.n[0] = L.d.x / 2; Q.child.n[1] = L.d.y / 2; Q.child.n[2] = L.d.z / 2;
@@ -150,19 +157,24 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
         Level& L = P.L[l];
         const size_t n = L.d.cells();
         const bool hier = L.p >= 0;
-        L.u = hier ? (u_user ? u_user[L.p] : nullptr) : cv.take<double>(n);
+        if (hier) L.u_user = u_user ? u_user[L.p] : nullptr;
+        L.u = (hier && !L.lay.split) ? L.u_user : cv.take<double>(n);
         L.f = cv.take<double>(n);
         if (!L.periodic) L.g = cv.take<double>(ghost_cells(L.d));
         if (l < P.last) L.uold = cv.take<double>(n / 8);
-        if (L.periodic && fused_sweep_supported<double>(L.d)) L.alt = cv.take<double>(n);
         if (P.mixed) {
             L.u32 = cv.take<float>(n);
             L.f32 = cv.take<float>(n);
             if (!L.periodic) L.g32 = cv.take<float>(ghost_cells(L.d));
             if (l < P.last) L.uold32 = cv.take<float>(n / 8);
-            if (L.periodic && fused_sweep_supported<float>(L.d)) L.alt32 = cv.take<float>(n);
         }
     }
+    // the small periodic levels at the bottom run as one single-workgroup launch
+    for (int l = 0; l <= P.last; ++l)
+        if (P.L[l].periodic && P.L[l].d.cells() <= kTailMaxCells && P.last - l < kTailMaxLevels) {
+            P.tail = l;
+            break;
+        }
     P.partials = cv.take<double>((size_t)kMaxPartials * (P.nh + 1));
     P.scal = cv.take<double>(S_COUNT);
     return MG_OK;
@@ -228,33 +240,11 @@ static void smooth(Plan& P, int l, int sweeps, hipStream_t st) {
     B<T> b = bufs<T>(L);
     const bool timed = l == 0;
     const double half_bytes = 0.5 * (double)L.d.cells() * 3.0 * sizeof(T);  // 3 words per update
-    if (!L.periodic) {
-        for (int s = 0; s < sweeps; ++s)
-            for (int c = 0; c < 2; ++c) {
-                ghosts<T>(P, l, st);
-                KScope k(timed, st, half_bytes);
-                launch_rbgs_half<T>(b.u, b.f, b.g, L.d, L.h, c, st);
-            }
-        return;
-    }
-    if (b.alt) {
-        // fused red+black sweeps ping-pong between u and alt; an odd count ends with a copy back
-        T* src = b.u;
-        T* dst = b.alt;
-        for (int s = 0; s < sweeps; ++s) {
-            {
-                KScope k(timed, st, 2.0 * half_bytes);
-                launch_rbgs_fused<T>(src, dst, b.f, L.d, L.h, st);
-            }
-            T* t = src; src = dst; dst = t;
-        }
-        if (src != b.u) hipMemcpyAsync(b.u, src, L.d.cells() * sizeof(T), hipMemcpyDeviceToDevice, st);
-        return;
-    }
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < 2; ++c) {
+            if (!L.periodic) ghosts<T>(P, l, st);
             KScope k(timed, st, half_bytes);
-            launch_rbgs_half<T>(b.u, b.f, nullptr, L.d, L.h, c, st);
+            launch_rbgs_half<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, c, st);
         }
 }
 
@@ -262,6 +252,18 @@ template <class T>
 static void vcycle(Plan& P, int l, hipStream_t st) {
     Level& L = P.L[l];
     B<T> b = bufs<T>(L);
+    if (l == P.tail) {  // this level and all below: one launch
+        TailPlan<T> tp{};
+        tp.n = P.last - l + 1;
+        tp.nu1 = P.nu1;
+        tp.nu2 = P.nu2;
+        for (int k = 0; k < tp.n; ++k) {
+            B<T> c = bufs<T>(P.L[l + k]);
+            tp.lev[k] = TailLevel<T>{c.u, c.f, c.uold, P.L[l + k].lay, P.L[l + k].h};
+        }
+        launch_tail<T>(tp, st);
+        return;
+    }
     if (l == P.last) {  // step 1
         launch_coarsest<T>(b.u, b.f, L.d.x, L.h, st);
         return;
@@ -271,10 +273,10 @@ static void vcycle(Plan& P, int l, hipStream_t st) {
     B<T> q = bufs<T>(Q);
     if (!L.periodic) ghosts<T>(P, l, st);
     // steps 3-5, then step 6 on the covered region of the parent
-    launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.d, L.h, q.u, q.f, b.uold, L.pm, st);
+    launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, q.u, q.f, b.uold, L.pm, st);
     launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
     vcycle<T>(P, l + 1, st);                         // step 7
-    launch_prolong<T>(b.u, L.d, q.u, b.uold, L.pm, st);  // step 8
+    launch_prolong<T>(b.u, L.lay, q.u, b.uold, L.pm, st);  // step 8
     smooth<T>(P, l, P.nu2, st);                      // step 9
 }
 
@@ -287,14 +289,14 @@ static long long updates_per_cycle(const Plan& P) {
 // covered cells of every hierarchy level := mean of their children, finest first
 template <class T>
 static void restrict_up(Plan& P, T* const* v, hipStream_t st) {
-    for (int l = 0; l + 1 < P.nh; ++l) launch_restrict_cov<T>(v[l], P.L[l].d, v[l + 1], P.L[l].pm, st);
+    for (int l = 0; l + 1 < P.nh; ++l) launch_restrict_cov<T>(v[l], P.L[l].lay, v[l + 1], P.L[l].pm, st);
 }
 
 // sum over the base of v (after restrict_up) -> scal[slot]
 static void base_sum(Plan& P, const double* vbase, int slot, hipStream_t st) {
     int np = 0;
     CovBox none{};
-    launch_sum(vbase, P.L[P.nh - 1].d, none, 0, P.partials, &np, st);
+    launch_sum(vbase, P.L[P.nh - 1].lay, none, 0, P.partials, &np, st);
     SegList s{};
     s.n = 1; s.off[0] = 0; s.cnt[0] = np; s.w[0] = 1.0;
     launch_finalize(P.partials, s, P.scal + slot, st);
@@ -307,7 +309,7 @@ static void composite_sq(Plan& P, double* const* v, int slot, hipStream_t st) {
     for (int l = 0; l < P.nh; ++l) {
         int np = 0;
         CovBox cb = l > 0 ? P.L[l].child : CovBox{};
-        launch_sum(v[l], P.L[l].d, cb, 1, P.partials + (size_t)l * kMaxPartials, &np, st);
+        launch_sum(v[l], P.L[l].lay, cb, 1, P.partials + (size_t)l * kMaxPartials, &np, st);
         s.off[l] = l * kMaxPartials;
         s.cnt[l] = np;
         s.w[l] = P.L[l].h * P.L[l].h * P.L[l].h;
@@ -316,9 +318,10 @@ static void composite_sq(Plan& P, double* const* v, int slot, hipStream_t st) {
 }
 
 // composite FP64 residual of the current u (covered coarse cells restricted first);
-// r written as R to rout[l] if given; sum r^2 vol -> scal[S_RNORM]
+// r written as R to rout[l] if given (natural rows if rout_natural, else the level's layout);
+// sum r^2 vol -> scal[S_RNORM]
 template <class R>
-static void composite_residual(Plan& P, R* const* rout, hipStream_t st) {
+static void composite_residual(Plan& P, R* const* rout, bool rout_natural, hipStream_t st) {
     std::vector<double*> u(P.nh);
     for (int l = 0; l < P.nh; ++l) u[l] = P.L[l].u;
     restrict_up<double>(P, u.data(), st);
@@ -329,8 +332,9 @@ static void composite_residual(Plan& P, R* const* rout, hipStream_t st) {
         if (!L.periodic) ghosts<double>(P, l, st);
         int np = 0;
         CovBox cb = l > 0 ? L.child : CovBox{};
-        launch_residual<double, R>(L.u, L.f, L.periodic ? nullptr : L.g, L.d, L.h, cb, rout ? rout[l] : nullptr,
-                                   P.partials + (size_t)l * kMaxPartials, &np, st);
+        const Lay LR = rout_natural ? Lay{L.d, 0} : L.lay;
+        launch_residual<double, R>(L.u, L.f, L.periodic ? nullptr : L.g, L.lay, L.h, cb, rout ? rout[l] : nullptr,
+                                   LR, P.partials + (size_t)l * kMaxPartials, &np, st);
         s.off[l] = l * kMaxPartials;
         s.cnt[l] = np;
         s.w[l] = L.h * L.h * L.h;
@@ -342,8 +346,7 @@ static void composite_residual(Plan& P, R* const* rout, hipStream_t st) {
 static int prepare_f(Plan& P, const double* const* f_user, hipStream_t st) {
     for (int l = 0; l < P.nh; ++l) {
         if (!f_user[P.L[l].p]) return fail(MG_EINVAL, "f pointer is NULL");
-        MG_HIP(hipMemcpyAsync(P.L[l].f, f_user[P.L[l].p], P.L[l].d.cells() * sizeof(double),
-                              hipMemcpyDeviceToDevice, st));
+        launch_relayout<double, double>(f_user[P.L[l].p], Lay{P.L[l].d, 0}, P.L[l].f, P.L[l].lay, st);
     }
     std::vector<double*> f(P.nh);
     for (int l = 0; l < P.nh; ++l) f[l] = P.L[l].f;
@@ -398,8 +401,11 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     if (rc) return rc;
     const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
     const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
-    if (!guess)
-        for (int l = 0; l < P.nh; ++l) launch_fill<double>(P.L[l].u, P.L[l].d.cells(), 0.0, st);
+    for (int l = 0; l < P.nh; ++l) {
+        Level& L = P.L[l];
+        if (!guess) launch_fill<double>(L.u, L.d.cells(), 0.0, st);
+        else if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, Lay{L.d, 0}, L.u, L.lay, st);
+    }
 
     mg_stats S;
     std::memset(&S, 0, sizeof(S));
@@ -431,7 +437,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
 
     if (!P.mixed) {
         if (guess && !fixed) {
-            composite_residual<double>(P, nullptr, st);
+            composite_residual<double>(P, nullptr, false, st);
             double r2;
             if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
             int c = check(r2);
@@ -442,7 +448,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             ++cycles;
             S.cell_updates += upc;
             if (fixed) continue;
-            composite_residual<double>(P, nullptr, st);
+            composite_residual<double>(P, nullptr, false, st);
             double r2;
             if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
             int c = check(r2);
@@ -453,7 +459,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
         std::vector<float*> rhs(P.nh);
         for (int l = 0; l < P.nh; ++l) rhs[l] = P.L[l].f32;
         for (;;) {
-            composite_residual<float>(P, rhs.data(), st);
+            composite_residual<float>(P, rhs.data(), false, st);
             if (!fixed) {
                 double r2;
                 if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
@@ -470,6 +476,10 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
         }
     }
     gauge_u(P, st);
+    for (int l = 0; l < P.nh; ++l) {
+        Level& L = P.L[l];
+        if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, Lay{L.d, 0}, st);
+    }
     MG_HIP(hipGetLastError());
     if (fixed) {
         MG_HIP(hipStreamSynchronize(st));  // surface asynchronous faults at the API boundary
@@ -498,6 +508,7 @@ static mg_hier single_level(int n, double h) {
 struct LptPlan {
     std::vector<double*> phi;  // restricted copies (P > 0) or the user's arrays
     double* padded = nullptr;
+    double* psi = nullptr;     // tau scratch: 3 gradient fields
     double* partials = nullptr;
     double* scal = nullptr;
 };
@@ -516,6 +527,15 @@ static size_t lpt_carve(const mg_hier* H, int what, Carver& cv, LptPlan& lp) {
             }
         }
     if (maxpad) lp.padded = cv.take<double>(maxpad);
+    if (what == 2) {
+        size_t m = (size_t)H->lev[0].n[0] * H->lev[0].n[1] * H->lev[0].n[2];
+        for (int p = 1; p < H->nlev; ++p) {
+            const mg_level& l = H->lev[p];
+            const size_t s = (size_t)(l.n[0] + 4) * (l.n[1] + 4) * (l.n[2] + 4);
+            if (s > m) m = s;
+        }
+        lp.psi = cv.take<double>(3 * m);
+    }
     lp.partials = cv.take<double>(kMaxPartials);
     lp.scal = cv.take<double>(S_COUNT);
     return cv.off;
@@ -555,7 +575,7 @@ static int lpt_common(const mg_hier* H, int what, const double* const* phi, void
     for (int p = 0; p < H->nlev; ++p)
         MG_HIP(hipMemcpyAsync(lp.phi[p], phi[p], dims_of(H, p).cells() * sizeof(double), hipMemcpyDeviceToDevice, st));
     for (int p = H->nlev - 1; p >= 1; --p)
-        launch_restrict_cov<double>(lp.phi[p], dims_of(H, p), lp.phi[p - 1], parent_of(H, p), st);
+        launch_restrict_cov<double>(lp.phi[p], Lay{dims_of(H, p), 0}, lp.phi[p - 1], parent_of(H, p), st);
     return MG_OK;
 }
 
@@ -632,9 +652,17 @@ int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* c
     build_plan(hier, &o, cv, u, P);
     (void)hipGetLastError();
     if ((rc = prepare_f(P, f, st))) return rc;
+    for (int l = 0; l < P.nh; ++l) {
+        Level& L = P.L[l];
+        if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, Lay{L.d, 0}, L.u, L.lay, st);
+    }
     std::vector<double*> rr(P.nh);
     for (int l = 0; l < P.nh; ++l) rr[l] = r[P.L[l].p];
-    composite_residual<double>(P, rr.data(), st);
+    composite_residual<double>(P, rr.data(), true, st);
+    for (int l = 0; l < P.nh; ++l) {
+        Level& L = P.L[l];
+        if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, Lay{L.d, 0}, st);
+    }
     MG_HIP(hipGetLastError());
     if (rel) {
         double v[3];
@@ -685,18 +713,18 @@ int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* ta
         const Dims d = dims_of(hier, p);
         const double h = h_of(hier, p);
         if (p == 0) {
-            launch_tau(lp.phi[0], 0, d, h, tau[0], st);
+            launch_tau(lp.phi[0], 0, d, h, tau[0], lp.psi, st);
         } else {
             launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 4, st);
-            launch_tau(lp.padded, 4, d, h, tau[p], st);
+            launch_tau(lp.padded, 4, d, h, tau[p], lp.psi, st);
         }
     }
     // composite mean: covered cells := mean of children, then subtract the base mean everywhere
     for (int p = hier->nlev - 1; p >= 1; --p)
-        launch_restrict_cov<double>(tau[p], dims_of(hier, p), tau[p - 1], parent_of(hier, p), st);
+        launch_restrict_cov<double>(tau[p], Lay{dims_of(hier, p), 0}, tau[p - 1], parent_of(hier, p), st);
     int np = 0;
     CovBox none{};
-    launch_sum(tau[0], dims_of(hier, 0), none, 0, lp.partials, &np, st);
+    launch_sum(tau[0], Lay{dims_of(hier, 0), 0}, none, 0, lp.partials, &np, st);
     SegList s{};
     s.n = 1; s.off[0] = 0; s.cnt[0] = np; s.w[0] = 1.0;
     launch_finalize(lp.partials, s, lp.scal, st);
@@ -754,17 +782,19 @@ int mg_smooth_level(int n, double h, const double* f, double* u, int half_sweeps
     build_plan(&H, &o, cv, up, P);
     (void)hipGetLastError();
     Level& L = P.L[0];
-    const size_t cells = L.d.cells();
+    const Lay nat{L.d, 0};
     if (prec == MG_FP64) {
-        MG_HIP(hipMemcpyAsync(L.f, f, cells * sizeof(double), hipMemcpyDeviceToDevice, st));
+        launch_relayout<double, double>(f, nat, L.f, L.lay, st);
+        launch_relayout<double, double>(u, nat, L.u, L.lay, st);
         smooth<double>(P, 0, half_sweeps / 2, st);
-        if (half_sweeps & 1) launch_rbgs_half<double>(L.u, L.f, nullptr, L.d, L.h, 0, st);
+        if (half_sweeps & 1) launch_rbgs_half<double>(L.u, L.f, nullptr, L.lay, L.h, 0, st);
+        launch_relayout<double, double>(L.u, L.lay, u, nat, st);
     } else {
-        launch_convert<double, float>(f, L.f32, cells, st);
-        launch_convert<double, float>(u, L.u32, cells, st);
+        launch_relayout<double, float>(f, nat, L.f32, L.lay, st);
+        launch_relayout<double, float>(u, nat, L.u32, L.lay, st);
         smooth<float>(P, 0, half_sweeps / 2, st);
-        if (half_sweeps & 1) launch_rbgs_half<float>(L.u32, L.f32, nullptr, L.d, L.h, 0, st);
-        launch_convert<float, double>(L.u32, u, cells, st);
+        if (half_sweeps & 1) launch_rbgs_half<float>(L.u32, L.f32, nullptr, L.lay, L.h, 0, st);
+        launch_relayout<float, double>(L.u32, L.lay, u, nat, st);
     }
     MG_HIP(hipGetLastError());
     return MG_OK;
