@@ -22,34 +22,13 @@ namespace mgic {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-__device__ __forceinline__ size_t lidx(const Lay& L, int x, int y, int z) {
-    const size_t row = (size_t)x * L.d.y + y;
-    if (!L.split) return row * L.d.z + z;
-    return row * L.d.z + (((x + y + z) & 1) ? (size_t)(L.d.z >> 1) : 0) + (z >> 1);
-}
-
-// coordinates of storage position i
-__device__ __forceinline__ void ldecode(const Lay& L, size_t i64, int& x, int& y, int& z) {
-    const unsigned i = (unsigned)i64;   // 32-bit division: every level has fewer than 2^31 cells
-    const unsigned row = i / (unsigned)L.d.z;
-    const int p = (int)(i - row * (unsigned)L.d.z);
-    y = (int)(row % (unsigned)L.d.y);
-    x = (int)(row / (unsigned)L.d.y);
-    if (!L.split) {
-        z = p;
-        return;
-    }
-    const int nzh = L.d.z >> 1;
-    const int col = p >= nzh;
-    z = 2 * (p - col * nzh) + ((x + y + col) & 1);
-}
 
 // ((x- + x+) + (y- + y+)) + (z- + z+) on a periodic level in any layout
 template <class T>
-__device__ __forceinline__ T nsum_periodic(const T* __restrict__ u, const Lay& L, int x, int y, int z) {
-    const T xm = u[lidx(L, wrap(x - 1, L.d.x), y, z)], xp = u[lidx(L, wrap(x + 1, L.d.x), y, z)];
-    const T ym = u[lidx(L, x, wrap(y - 1, L.d.y), z)], yp = u[lidx(L, x, wrap(y + 1, L.d.y), z)];
-    const T zm = u[lidx(L, x, y, wrap(z - 1, L.d.z))], zp = u[lidx(L, x, y, wrap(z + 1, L.d.z))];
+__device__ __forceinline__ T nsum_periodic(const T* __restrict__ u, Dims d, int sp, int x, int y, int z) {
+    const T xm = u[lidx(d, sp, wrap(x - 1, d.x), y, z)], xp = u[lidx(d, sp, wrap(x + 1, d.x), y, z)];
+    const T ym = u[lidx(d, sp, x, wrap(y - 1, d.y), z)], yp = u[lidx(d, sp, x, wrap(y + 1, d.y), z)];
+    const T zm = u[lidx(d, sp, x, y, wrap(z - 1, d.z))], zp = u[lidx(d, sp, x, y, wrap(z + 1, d.z))];
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
@@ -72,7 +51,7 @@ template <class T, bool GH>
 __device__ __forceinline__ T nsum(const T* __restrict__ u, const T* __restrict__ g, const Lay& L, int x, int y,
                                   int z) {
     if constexpr (GH) return nsum_ghost<T>(u, g, L.d, x, y, z);
-    else return nsum_periodic<T>(u, L, x, y, z);
+    else return nsum_periodic<T>(u, L.d, L.split, x, y, z);
 }
 
 // index of covered cell (X,Y,Z) (relative to the covered box) in the parent array
@@ -83,7 +62,7 @@ __device__ __forceinline__ size_t pidx(const ParentMap& pm, int X, int Y, int Z)
         b = wrap(b, pm.pd.y);
         c = wrap(c, pm.pd.z);
     }
-    return lidx(Lay{pm.pd, pm.split}, a, b, c);
+    return lidx(pm.pd, pm.split, a, b, c);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Renumber them
@@ -153,13 +132,15 @@ __global__ void k_sub_mean(T* __restrict__ a, size_t n, const double* __restrict
 // split-layout half-sweep of the cell t of `colour` (t = (row, j) over rows of nz/2 cells).
 // Indices are 32-bit: every level fits in 2^31 cells.
 template <class T>
-__device__ __forceinline__ void cell_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Dims d, T h2,
+__device__ __forceinline__ void cell_rbgs_split(T* __restrict__ u, const T* __restrict__ f, const Lay& L, T h2,
                                                 int colour, unsigned t) {
+    const Dims d = L.d;
     const unsigned nzh = (unsigned)d.z >> 1;
-    const unsigned j = t % nzh;
-    const unsigned row = t / nzh;
-    const int y = (int)(row % (unsigned)d.y);
-    const int x = (int)(row / (unsigned)d.y);
+    const unsigned row = L.dzh.div(t);
+    const unsigned j = t - row * nzh;
+    const unsigned xq = L.dy.div(row);
+    const int y = (int)(row - xq * (unsigned)d.y);
+    const int x = (int)xq;
     const int q = (x + y + colour) & 1;          // z parity of this colour in the row
     const unsigned own = colour ? nzh : 0u, oth = colour ? 0u : nzh;
     const unsigned rs = (unsigned)d.z;
@@ -180,11 +161,10 @@ template <class T, bool GH>
 __device__ __forceinline__ void cell_resid_restrict(const T* __restrict__ u, const T* __restrict__ f,
                                                     const T* __restrict__ g, const Lay& L, T h2,
                                                     T* __restrict__ pu, T* __restrict__ pf,
-                                                    T* __restrict__ uold, const ParentMap& pm, unsigned t) {
-    const unsigned cz = (unsigned)L.d.z >> 1, cy = (unsigned)L.d.y >> 1;
-    const int Z = (int)(t % cz);
-    const int Y = (int)((t / cz) % cy);
-    const int X = (int)(t / (cz * cy));
+                                                    T* __restrict__ uold, const ParentMap& pm, const Lay& C,
+                                                    unsigned t) {
+    int X, Y, Z;
+    ldecode(C, t, X, Y, Z);   // C: the covered box (natural order)
     T su = T(0), sr = T(0);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
@@ -207,14 +187,12 @@ __device__ __forceinline__ void cell_resid_restrict(const T* __restrict__ u, con
 // step 6 for covered cell t: parent f += L u over the parent's own (periodic-wrapped) stencil
 template <class T>
 __device__ __forceinline__ void cell_fas(const T* __restrict__ pu, T* __restrict__ pf, const ParentMap& pm,
-                                         Dims cov, T H2, unsigned t) {
-    const int Z = (int)(t % (unsigned)cov.z);
-    const int Y = (int)((t / (unsigned)cov.z) % (unsigned)cov.y);
-    const int X = (int)(t / ((unsigned)cov.z * cov.y));
-    const Lay P{pm.pd, pm.split};
+                                         const Lay& C, T H2, unsigned t) {
+    int X, Y, Z;
+    ldecode(C, t, X, Y, Z);   // C: the covered box (natural order)
     const int a = wrap(pm.off[0] + X, pm.pd.x), b = wrap(pm.off[1] + Y, pm.pd.y), c = wrap(pm.off[2] + Z, pm.pd.z);
-    const size_t i = lidx(P, a, b, c);
-    const T s = nsum_periodic<T>(pu, P, a, b, c);
+    const size_t i = lidx(pm.pd, pm.split, a, b, c);
+    const T s = nsum_periodic<T>(pu, pm.pd, pm.split, a, b, c);
     pf[i] = pf[i] + (s - T(6) * pu[i]) / H2;
 }
 
@@ -272,28 +250,30 @@ __device__ void block_coarsest(T* __restrict__ u, const T* __restrict__ f, int M
 
 // periodic level in the colour-split layout: V consecutive cells of a half-row per thread
 template <class T, int V>
-__global__ void k_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Dims d, T h2, int colour) {
-    const unsigned total = (unsigned)d.x * d.y * ((unsigned)d.z >> 1);
+__global__ void k_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Lay L, T h2, int colour) {
+    const unsigned total = (unsigned)L.d.x * L.d.y * ((unsigned)L.d.z >> 1);
     const unsigned base = (unsigned)xcd_block() * blockDim.x * V + threadIdx.x;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const unsigned t = base + v * blockDim.x;   // each of the V passes is unit-stride over the wave
-        if (t < total) cell_rbgs_split<T>(u, f, d, h2, colour, t);
+        if (t < total) cell_rbgs_split<T>(u, f, L, h2, colour, t);
     }
 }
 
 // patch (natural rows, ghost faces): one thread per cell of the colour
 template <class T>
-__global__ void k_rbgs_ghost(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Dims d, T h2,
+__global__ void k_rbgs_ghost(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Lay L, T h2,
                              int colour) {
+    const Dims d = L.d;
     const unsigned nzh = (unsigned)d.z >> 1;
     const unsigned total = (unsigned)d.x * d.y * nzh;
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int zh = (int)(t % nzh);
-    const unsigned r = t / nzh;
-    const int y = (int)(r % (unsigned)d.y);
-    const int x = (int)(r / (unsigned)d.y);
+    const unsigned r = L.dzh.div(t);
+    const int zh = (int)(t - r * nzh);
+    const unsigned xq = L.dy.div(r);
+    const int y = (int)(r - xq * (unsigned)d.y);
+    const int x = (int)xq;
     const int z = 2 * zh + ((x + y + colour) & 1);
     const size_t i = ((size_t)x * d.y + y) * d.z + z;
     const T s = nsum_ghost<T>(u, g, d, x, y, z);
@@ -303,16 +283,16 @@ __global__ void k_rbgs_ghost(T* __restrict__ u, const T* __restrict__ f, const T
 template <class T, bool GH>
 __global__ void k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g,
                                  Lay L, T h2, T* __restrict__ pu, T* __restrict__ pf, T* __restrict__ uold,
-                                 ParentMap pm) {
-    const unsigned n = (unsigned)(L.d.x >> 1) * (L.d.y >> 1) * (L.d.z >> 1);
+                                 ParentMap pm, Lay C) {
+    const unsigned n = (unsigned)C.d.cells();
     const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
-    if (t < n) cell_resid_restrict<T, GH>(u, f, g, L, h2, pu, pf, uold, pm, t);
+    if (t < n) cell_resid_restrict<T, GH>(u, f, g, L, h2, pu, pf, uold, pm, C, t);
 }
 
 template <class T>
-__global__ void k_fas_rhs(const T* __restrict__ pu, T* __restrict__ pf, ParentMap pm, Dims cov, T H2) {
+__global__ void k_fas_rhs(const T* __restrict__ pu, T* __restrict__ pf, ParentMap pm, Lay C, T H2) {
     const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
-    if (t < (unsigned)cov.cells()) cell_fas<T>(pu, pf, pm, cov, H2, t);
+    if (t < (unsigned)C.d.cells()) cell_fas<T>(pu, pf, pm, C, H2, t);
 }
 
 template <class T>
@@ -383,16 +363,18 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
         const unsigned half = (unsigned)A.d.cells() >> 1;
         for (int s = 0; s < tp.nu1; ++s)
             for (int c = 0; c < 2; ++c) {
-                for (unsigned t = threadIdx.x; t < half; t += nt) cell_rbgs_split<T>(U[l], F[l], A.d, h2, c, t);
+                for (unsigned t = threadIdx.x; t < half; t += nt) cell_rbgs_split<T>(U[l], F[l], A, h2, c, t);
                 __syncthreads();
             }
         const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
+        Lay C = Bl;   // the coarse level is the whole covered box, decoded in natural order
+        C.split = 0;
         const unsigned nc = (unsigned)A.d.cells() >> 3;
         for (unsigned t = threadIdx.x; t < nc; t += nt)
-            cell_resid_restrict<T, false>(U[l], F[l], (const T*)nullptr, A, h2, U[l + 1], F[l + 1], O[l], pm, t);
+            cell_resid_restrict<T, false>(U[l], F[l], (const T*)nullptr, A, h2, U[l + 1], F[l + 1], O[l], pm, C, t);
         __syncthreads();
         const T H2 = (T)(tp.lev[l + 1].h * tp.lev[l + 1].h);
-        for (unsigned t = threadIdx.x; t < nc; t += nt) cell_fas<T>(U[l + 1], F[l + 1], pm, Bl.d, H2, t);
+        for (unsigned t = threadIdx.x; t < nc; t += nt) cell_fas<T>(U[l + 1], F[l + 1], pm, C, H2, t);
         __syncthreads();
     }
     {
@@ -410,7 +392,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
         const T h2 = (T)(tp.lev[l].h * tp.lev[l].h);
         for (int s = 0; s < tp.nu2; ++s)
             for (int c = 0; c < 2; ++c) {
-                for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_rbgs_split<T>(U[l], F[l], A.d, h2, c, t);
+                for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_rbgs_split<T>(U[l], F[l], A, h2, c, t);
                 __syncthreads();
             }
     }
@@ -462,7 +444,7 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
     const int i0 = side ? n[a] - 1 : 0, i1 = side ? n[a] - 2 : 1;
     const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
     const int pdim[3] = {pm.pd.x, pm.pd.y, pm.pd.z};
-    const Lay PL{pm.pd, pm.split};
+
     // 3x3 outside coarse layer around O
     double L[3][3];
     for (int db = 0; db < 3; ++db)
@@ -473,7 +455,7 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
             q[c] = pm.off[c] + K + dc - 1;
             if (pm.periodic)
                 for (int k = 0; k < 3; ++k) q[k] = wrap(q[k], pdim[k]);
-            L[db][dc] = (double)pu[lidx(PL, q[0], q[1], q[2])];
+            L[db][dc] = (double)pu[lidx(pm.pd, pm.split, q[0], q[1], q[2])];
         }
     double u0[2][2], u1[2][2], g0[2][2];
     for (int jb = 0; jb < 2; ++jb)
@@ -602,11 +584,11 @@ void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h, int co
     const size_t n = (size_t)L.d.x * L.d.y * (L.d.z / 2);
     const T h2 = (T)(h * h);
     if (ghosts)
-        k_rbgs_ghost<T><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L.d, h2, colour);
+        k_rbgs_ghost<T><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, colour);
     else if (n >= (size_t)kBlock * 64 * 2)
-        k_rbgs_split<T, 2><<<grid_for((n + 1) / 2), kBlock, 0, st>>>(u, f, L.d, h2, colour);
+        k_rbgs_split<T, 2><<<grid_for((n + 1) / 2), kBlock, 0, st>>>(u, f, L, h2, colour);
     else
-        k_rbgs_split<T, 1><<<grid_for(n), kBlock, 0, st>>>(u, f, L.d, h2, colour);
+        k_rbgs_split<T, 1><<<grid_for(n), kBlock, 0, st>>>(u, f, L, h2, colour);
 }
 
 template <class T>
@@ -627,17 +609,18 @@ size_t tail_lds_size(const TailPlan<T>& tp) {
 template <class T>
 void launch_resid_restrict(const T* u, const T* f, const T* ghosts, Lay L, double h, T* pu, T* pf, T* uold,
                            ParentMap pm, hipStream_t st) {
-    const size_t n = (size_t)(L.d.x / 2) * (L.d.y / 2) * (L.d.z / 2);
+    const Lay C = mklay(Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, 0);
+    const size_t n = C.d.cells();
     const T h2 = (T)(h * h);
     if (ghosts)
-        k_resid_restrict<T, true><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, pu, pf, uold, pm);
+        k_resid_restrict<T, true><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, pu, pf, uold, pm, C);
     else
-        k_resid_restrict<T, false><<<grid_for(n), kBlock, 0, st>>>(u, f, nullptr, L, h2, pu, pf, uold, pm);
+        k_resid_restrict<T, false><<<grid_for(n), kBlock, 0, st>>>(u, f, nullptr, L, h2, pu, pf, uold, pm, C);
 }
 
 template <class T>
 void launch_fas_rhs(const T* pu, T* pf, ParentMap pm, Dims cov, double H, hipStream_t st) {
-    k_fas_rhs<T><<<grid_for(cov.cells()), kBlock, 0, st>>>(pu, pf, pm, cov, (T)(H * H));
+    k_fas_rhs<T><<<grid_for(cov.cells()), kBlock, 0, st>>>(pu, pf, pm, mklay(cov, 0), (T)(H * H));
 }
 
 template <class T>

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "fastdiv.h"
+
 namespace mgic {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
@@ -19,10 +21,46 @@ struct Dims {
 
 // Storage of one level: natural rows, or the colour-split rows of periodic levels (each row of
 // z holds its red cells, (x+y+z) even, in increasing z, then its black cells).
+// The dividers are always derived from d by the constructor, so a Lay can never decode with
+// stale constants; device code that only needs indices uses (Dims, split) directly.
 struct Lay {
-    Dims d;
-    int split;
+    Dims d{1, 1, 1};
+    int split = 0;
+    FastDiv dz, dy, dzh;   // division by d.z, d.y and d.z / 2
+
+    Lay() = default;
+    __host__ __device__ Lay(Dims d_, int split_)
+        : d(d_), split(split_), dz((unsigned)d_.z), dy((unsigned)d_.y),
+          dzh((unsigned)(d_.z > 1 ? d_.z / 2 : 1)) {}
 };
+inline Lay mklay(Dims d, int split) { return Lay(d, split); }
+
+// storage position of cell (x, y, z)
+__host__ __device__ __forceinline__ size_t lidx(Dims d, int split, int x, int y, int z) {
+    const size_t row = (size_t)x * d.y + y;
+    if (!split) return row * d.z + z;
+    return row * d.z + (((x + y + z) & 1) ? (size_t)(d.z >> 1) : 0) + (z >> 1);
+}
+__host__ __device__ __forceinline__ size_t lidx(const Lay& L, int x, int y, int z) {
+    return lidx(L.d, L.split, x, y, z);
+}
+
+// coordinates of storage position i (every level has fewer than 2^31 cells)
+__host__ __device__ __forceinline__ void ldecode(const Lay& L, size_t i64, int& x, int& y, int& z) {
+    const unsigned i = (unsigned)i64;
+    const unsigned row = L.dz.div(i);
+    const int p = (int)(i - row * (unsigned)L.d.z);
+    const unsigned xq = L.dy.div(row);
+    y = (int)(row - xq * (unsigned)L.d.y);
+    x = (int)xq;
+    if (!L.split) {
+        z = p;
+        return;
+    }
+    const int nzh = L.d.z >> 1;
+    const int col = p >= nzh;
+    z = 2 * (p - col * nzh) + ((x + y + col) & 1);
+}
 
 // Where a fine level's coarse representation lives inside its parent array.
 struct ParentMap {

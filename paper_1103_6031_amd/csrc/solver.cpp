@@ -142,7 +142,7 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
         }
     }
     P.last = (int)P.L.size() - 1;
-    for (auto& L : P.L) L.lay = Lay{L.d, (L.periodic && L.d.z % 2 == 0) ? 1 : 0};
+    for (auto& L : P.L) L.lay = mklay(L.d, (L.periodic && L.d.z % 2 == 0) ? 1 : 0);
     for (int l = 0; l < P.last; ++l) {
         Level& L = P.L[l];
         Level& Q = P.L[l + 1];
@@ -332,7 +332,7 @@ static void composite_residual(Plan& P, R* const* rout, bool rout_natural, hipSt
         if (!L.periodic) ghosts<double>(P, l, st);
         int np = 0;
         CovBox cb = l > 0 ? L.child : CovBox{};
-        const Lay LR = rout_natural ? Lay{L.d, 0} : L.lay;
+        const Lay LR = rout_natural ? mklay(L.d, 0) : L.lay;
         launch_residual<double, R>(L.u, L.f, L.periodic ? nullptr : L.g, L.lay, L.h, cb, rout ? rout[l] : nullptr,
                                    LR, P.partials + (size_t)l * kMaxPartials, &np, st);
         s.off[l] = l * kMaxPartials;
@@ -346,7 +346,7 @@ static void composite_residual(Plan& P, R* const* rout, bool rout_natural, hipSt
 static int prepare_f(Plan& P, const double* const* f_user, hipStream_t st) {
     for (int l = 0; l < P.nh; ++l) {
         if (!f_user[P.L[l].p]) return fail(MG_EINVAL, "f pointer is NULL");
-        launch_relayout<double, double>(f_user[P.L[l].p], Lay{P.L[l].d, 0}, P.L[l].f, P.L[l].lay, st);
+        launch_relayout<double, double>(f_user[P.L[l].p], mklay(P.L[l].d, 0), P.L[l].f, P.L[l].lay, st);
     }
     std::vector<double*> f(P.nh);
     for (int l = 0; l < P.nh; ++l) f[l] = P.L[l].f;
@@ -404,7 +404,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     for (int l = 0; l < P.nh; ++l) {
         Level& L = P.L[l];
         if (!guess) launch_fill<double>(L.u, L.d.cells(), 0.0, st);
-        else if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, Lay{L.d, 0}, L.u, L.lay, st);
+        else if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, mklay(L.d, 0), L.u, L.lay, st);
     }
 
     mg_stats S;
@@ -478,7 +478,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     gauge_u(P, st);
     for (int l = 0; l < P.nh; ++l) {
         Level& L = P.L[l];
-        if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, Lay{L.d, 0}, st);
+        if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, mklay(L.d, 0), st);
     }
     MG_HIP(hipGetLastError());
     if (fixed) {
@@ -575,7 +575,7 @@ static int lpt_common(const mg_hier* H, int what, const double* const* phi, void
     for (int p = 0; p < H->nlev; ++p)
         MG_HIP(hipMemcpyAsync(lp.phi[p], phi[p], dims_of(H, p).cells() * sizeof(double), hipMemcpyDeviceToDevice, st));
     for (int p = H->nlev - 1; p >= 1; --p)
-        launch_restrict_cov<double>(lp.phi[p], Lay{dims_of(H, p), 0}, lp.phi[p - 1], parent_of(H, p), st);
+        launch_restrict_cov<double>(lp.phi[p], mklay(dims_of(H, p), 0), lp.phi[p - 1], parent_of(H, p), st);
     return MG_OK;
 }
 
@@ -654,14 +654,14 @@ int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* c
     if ((rc = prepare_f(P, f, st))) return rc;
     for (int l = 0; l < P.nh; ++l) {
         Level& L = P.L[l];
-        if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, Lay{L.d, 0}, L.u, L.lay, st);
+        if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, mklay(L.d, 0), L.u, L.lay, st);
     }
     std::vector<double*> rr(P.nh);
     for (int l = 0; l < P.nh; ++l) rr[l] = r[P.L[l].p];
     composite_residual<double>(P, rr.data(), true, st);
     for (int l = 0; l < P.nh; ++l) {
         Level& L = P.L[l];
-        if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, Lay{L.d, 0}, st);
+        if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, mklay(L.d, 0), st);
     }
     MG_HIP(hipGetLastError());
     if (rel) {
@@ -721,10 +721,10 @@ int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* ta
     }
     // composite mean: covered cells := mean of children, then subtract the base mean everywhere
     for (int p = hier->nlev - 1; p >= 1; --p)
-        launch_restrict_cov<double>(tau[p], Lay{dims_of(hier, p), 0}, tau[p - 1], parent_of(hier, p), st);
+        launch_restrict_cov<double>(tau[p], mklay(dims_of(hier, p), 0), tau[p - 1], parent_of(hier, p), st);
     int np = 0;
     CovBox none{};
-    launch_sum(tau[0], Lay{dims_of(hier, 0), 0}, none, 0, lp.partials, &np, st);
+    launch_sum(tau[0], mklay(dims_of(hier, 0), 0), none, 0, lp.partials, &np, st);
     SegList s{};
     s.n = 1; s.off[0] = 0; s.cnt[0] = np; s.w[0] = 1.0;
     launch_finalize(lp.partials, s, lp.scal, st);
@@ -782,7 +782,7 @@ int mg_smooth_level(int n, double h, const double* f, double* u, int half_sweeps
     build_plan(&H, &o, cv, up, P);
     (void)hipGetLastError();
     Level& L = P.L[0];
-    const Lay nat{L.d, 0};
+    const Lay nat(L.d, 0);
     if (prec == MG_FP64) {
         launch_relayout<double, double>(f, nat, L.f, L.lay, st);
         launch_relayout<double, double>(u, nat, L.u, L.lay, st);
