@@ -2,6 +2,7 @@
 
 Every source under csrc/ is compiled for gfx950 only, with FP contraction off (the arithmetic
 order written in the kernels is the order executed) and packed FP32 instructions disabled.
+`build(out=..., defines=[...])` produces variant builds (e.g. -DMGIC_NO_XCD) for A/B timing.
 """
 
 import os
@@ -13,7 +14,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgic.so")
-OBJDIR = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -24,29 +24,31 @@ FLAGS = [
 SOURCES = ["k_multigrid.hip", "k_lpt.hip", "solver.cpp"]
 
 
-def _compile(src):
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+def _compile(args):
+    src, objdir, defines = args
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
     return obj
 
 
-def build(verbose=True):
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose=True, out=LIB, defines=()):
+    objdir = os.path.join(ROOT, "_build", "_".join(defines) if defines else "default")
+    os.makedirs(objdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(_compile, [(s, objdir, list(defines)) for s in SOURCES]))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -65,14 +65,12 @@ __device__ __forceinline__ size_t pidx(const ParentMap& pm, int X, int Y, int Z)
     return lidx(pm.pd, pm.split, a, b, c);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Renumber them
-// so that every XCD works on one contiguous eighth of the grid, keeping neighbouring rows and
-// planes in the same L2.
-__device__ __forceinline__ size_t xcd_block() {
-    const unsigned nb = gridDim.x, b = blockIdx.x;
-    if (nb % 8u) return b;
-    return (size_t)(b % 8u) * (nb / 8u) + b / 8u;
-}
+
+// Reduction kernels stride over the whole array, kRedV independent cells per thread per pass.
+// (Measured on MI355X: giving each block one contiguous chunk instead was no faster.)
+__device__ __forceinline__ unsigned red_lo(unsigned) { return blockIdx.x * blockDim.x * kRedV; }
+__device__ __forceinline__ unsigned red_hi(unsigned n) { return n; }
+__device__ __forceinline__ unsigned red_stride() { return gridDim.x * blockDim.x * kRedV; }
 
 // ----------------------------------------------------------------------------------------------
 // deterministic block reduction (wave64 shuffle, then the waves in order)
@@ -521,7 +519,12 @@ __global__ void k_residual(const T* __restrict__ u, const T* __restrict__ f, con
                            T h2, CovBox cb, R* __restrict__ rout, Lay LR, double* __restrict__ partials) {
     double acc = 0.0;
     const size_t n = L.d.cells();
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
+#pragma unroll
+    for (int v = 0; v < kRedV; ++v) {
+        const unsigned i = b0 + v * blockDim.x;
+        if (i >= hi) break;
         int x, y, z;
         ldecode(L, i, x, y, z);
         const T s = nsum<T, GH>(u, g, L, x, y, z);
@@ -534,15 +537,110 @@ __global__ void k_residual(const T* __restrict__ u, const T* __restrict__ f, con
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
+// the same on a colour-split periodic level, r written in the same layout; neighbour rows are
+// addressed directly (identical arithmetic, so identical bits)
+template <class T, class R>
+__global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ f, Lay L, T h2, CovBox cb,
+                                 R* __restrict__ rout, double* __restrict__ partials) {
+    const Dims d = L.d;
+    const unsigned n = (unsigned)d.cells(), nz = (unsigned)d.z, nzh = nz >> 1;
+    double acc = 0.0;
+    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
+#pragma unroll
+    for (int v = 0; v < kRedV; ++v) {
+        const unsigned t = b0 + v * blockDim.x;
+        if (t >= hi) break;
+        const unsigned row = L.dz.div(t);
+        const unsigned p = t - row * nz;
+        const unsigned col = p >= nzh;
+        const unsigned j = p - col * nzh;
+        const unsigned xq = L.dy.div(row);
+        const int y = (int)(row - xq * (unsigned)d.y), x = (int)xq;
+        const int q = (x + y + (int)col) & 1;
+        const unsigned oth = col ? 0u : nzh;
+        const unsigned rxm = ((unsigned)wrap(x - 1, d.x) * d.y + y) * nz, rxp = ((unsigned)wrap(x + 1, d.x) * d.y + y) * nz;
+        const unsigned rym = ((unsigned)x * d.y + wrap(y - 1, d.y)) * nz, ryp = ((unsigned)x * d.y + wrap(y + 1, d.y)) * nz;
+        const unsigned r0 = row * nz;
+        const unsigned jm = (unsigned)wrap((int)j - 1 + q, (int)nzh), jp = (unsigned)wrap((int)j + q, (int)nzh);
+        const T s = ((u[rxm + oth + j] + u[rxp + oth + j]) + (u[rym + oth + j] + u[ryp + oth + j])) +
+                    (u[r0 + oth + jm] + u[r0 + oth + jp]);
+        const T r = f[t] - (s - T(6) * u[t]) / h2;
+        const bool cov = in_box(cb, x, y, 2 * (int)j + q);
+        if (!cov) acc += (double)r * (double)r;
+        if (rout) rout[t] = cov ? R(0) : (R)r;
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// One outer step of the mixed-precision defect correction on a colour-split periodic level:
+//   v   = u_in + (double) e_in          (the pending FP32 correction; e_in == nullptr: none)
+//   r   = f - L v                        (FP64, same arithmetic as k_residual_split)
+//   u_out = v,  rhs = (float) r,  e_out = the first red half-sweep of the next inner cycle from
+//   e = 0, i.e. (0 - h^2 rhs) / 6 on red cells and 0 on black cells.
+// v is formed on the fly for the 7 stencil points, so u_out / e_out must not alias the inputs.
+__global__ void k_outer_split(const double* __restrict__ u_in, const float* __restrict__ e_in,
+                              const double* __restrict__ f, double* __restrict__ u_out, float* __restrict__ rhs,
+                              float* __restrict__ e_out, Lay L, double h2, float h2f,
+                              double* __restrict__ partials) {
+    const Dims d = L.d;
+    const unsigned n = (unsigned)d.cells(), nz = (unsigned)d.z, nzh = nz >> 1;
+    double acc = 0.0;
+    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
+#pragma unroll
+    for (int v = 0; v < kRedV; ++v) {
+        const unsigned t = b0 + v * blockDim.x;
+        if (t >= hi) break;
+        const unsigned row = L.dz.div(t);
+        const unsigned p = t - row * nz;
+        const unsigned col = p >= nzh;
+        const unsigned j = p - col * nzh;
+        const unsigned xq = L.dy.div(row);
+        const int y = (int)(row - xq * (unsigned)d.y), x = (int)xq;
+        const int q = (x + y + (int)col) & 1;
+        const unsigned oth = col ? 0u : nzh;
+        const unsigned rxm = ((unsigned)wrap(x - 1, d.x) * d.y + y) * nz, rxp = ((unsigned)wrap(x + 1, d.x) * d.y + y) * nz;
+        const unsigned rym = ((unsigned)x * d.y + wrap(y - 1, d.y)) * nz, ryp = ((unsigned)x * d.y + wrap(y + 1, d.y)) * nz;
+        const unsigned r0 = row * nz;
+        const unsigned jm = (unsigned)wrap((int)j - 1 + q, (int)nzh), jp = (unsigned)wrap((int)j + q, (int)nzh);
+        auto V = [&](unsigned i) { return e_in ? u_in[i] + (double)e_in[i] : u_in[i]; };
+        const double c0 = V(t);
+        const double s = ((V(rxm + oth + j) + V(rxp + oth + j)) + (V(rym + oth + j) + V(ryp + oth + j))) +
+                         (V(r0 + oth + jm) + V(r0 + oth + jp));
+        const double r = f[t] - (s - 6.0 * c0) / h2;
+        acc += r * r;
+        const float rf = (float)r;
+        u_out[t] = c0;
+        rhs[t] = rf;
+        e_out[t] = col ? 0.0f : (0.0f - h2f * rf) / 6.0f;
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+void launch_outer_split(const double* u_in, const float* e_in, const double* f, double* u_out, float* rhs,
+                        float* e_out, Lay L, double h, double* partials, int* nparts, hipStream_t st) {
+    const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
+    k_outer_split<<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h * h, (float)(h * h), partials);
+    *nparts = g;
+}
+
 __global__ void k_sum(const double* __restrict__ a, Lay L, CovBox cb, int square, double* __restrict__ partials) {
     double acc = 0.0;
     const size_t n = L.d.cells();
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
+#pragma unroll
+    for (int v = 0; v < kRedV; ++v) {
+        const unsigned i = b0 + v * blockDim.x;
+        if (i >= hi) break;
         int x, y, z;
         ldecode(L, i, x, y, z);
         if (in_box(cb, x, y, z)) continue;
-        const double v = a[i];
-        acc += square ? v * v : v;
+        const double av = a[i];
+        acc += square ? av * av : av;
     }
     const double bs = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
@@ -648,17 +746,19 @@ void launch_restrict_cov(const T* fine, Lay L, T* parent, ParentMap pm, hipStrea
 template <class T, class R>
 void launch_residual(const T* u, const T* f, const T* ghosts, Lay L, double h, CovBox cov, R* rout, Lay LR,
                      double* partials, int* nparts, hipStream_t st) {
-    const int g = grid_for(L.d.cells(), kBlock, kMaxPartials);
+    const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
     const T h2 = (T)(h * h);
     if (ghosts)
         k_residual<T, R, true><<<g, kBlock, 0, st>>>(u, f, ghosts, L, h2, cov, rout, LR, partials);
+    else if (L.split && (!rout || LR.split))
+        k_residual_split<T, R><<<g, kBlock, 0, st>>>(u, f, L, h2, cov, rout, partials);
     else
         k_residual<T, R, false><<<g, kBlock, 0, st>>>(u, f, nullptr, L, h2, cov, rout, LR, partials);
     *nparts = g;
 }
 
 void launch_sum(const double* a, Lay L, CovBox cov, int square, double* partials, int* nparts, hipStream_t st) {
-    const int g = grid_for(L.d.cells(), kBlock, kMaxPartials);
+    const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
     k_sum<<<g, kBlock, 0, st>>>(a, L, cov, square, partials);
     *nparts = g;
 }

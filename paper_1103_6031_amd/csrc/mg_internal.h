@@ -11,7 +11,8 @@
 namespace mgic {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
-constexpr int kMaxPartials = 1024;   // partial sums per reduction (fixed => deterministic)
+constexpr int kMaxPartials = 4096;   // partial sums per reduction (fixed => deterministic)
+constexpr int kRedV = 4;             // cells per thread per pass in the reduction kernels
 
 // A 3-D box of cells.
 struct Dims {
@@ -61,6 +62,13 @@ __host__ __device__ __forceinline__ void ldecode(const Lay& L, size_t i64, int& 
     const int col = p >= nzh;
     z = 2 * (p - col * nzh) + ((x + y + col) & 1);
 }
+
+// Block numbering of the grid kernels.  Workgroups go round-robin over the 8 XCDs; measured on
+// MI355X, renumbering them so that each XCD sweeps one contiguous eighth of a level (to keep
+// neighbour rows in one L2) was slower for every stencil here (e.g. the FP64 half-sweep at 256^3
+// by 9%), so blocks keep the dispatch order.
+__device__ __forceinline__ size_t xcd_block() { return blockIdx.x; }
+__device__ __forceinline__ size_t lpt_block() { return blockIdx.x; }
 
 // Where a fine level's coarse representation lives inside its parent array.
 struct ParentMap {
@@ -156,6 +164,11 @@ template <class T> void launch_restrict_cov(const T* fine, Lay L, T* parent, Par
 template <class T, class R> void launch_residual(const T* u, const T* f, const T* ghosts, Lay L, double h,
                                                  CovBox cov, R* rout, Lay LR, double* partials, int* nparts,
                                                  hipStream_t st);
+// fused outer step of the mixed-precision defect correction on a colour-split periodic level:
+// u_out = u_in + e_in, rhs = (float)(f - L u_out), e_out = first red half-sweep from e = 0;
+// per-block partial sums of r^2
+void launch_outer_split(const double* u_in, const float* e_in, const double* f, double* u_out, float* rhs,
+                        float* e_out, Lay L, double h, double* partials, int* nparts, hipStream_t st);
 // per-block partial sums of a (or a^2) over cells outside cov
 void launch_sum(const double* a, Lay L, CovBox cov, int square, double* partials, int* nparts, hipStream_t st);
 void launch_finalize(const double* partials, SegList segs, double* out, hipStream_t st);

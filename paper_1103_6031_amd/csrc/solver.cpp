@@ -58,6 +58,8 @@ struct Level {
     double* u_user = nullptr;  // caller's array of a hierarchy level (natural rows)
     double *u = nullptr, *f = nullptr, *g = nullptr, *uold = nullptr;   // working arrays (lay)
     float *u32 = nullptr, *f32 = nullptr, *g32 = nullptr, *uold32 = nullptr;
+    double* ualt = nullptr;  // second u of the fused mixed-precision outer step (ping-pong)
+    float* ealt = nullptr;   // second e of the same
 };
 
 struct Plan {
@@ -167,6 +169,10 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
             L.f32 = cv.take<float>(n);
             if (!L.periodic) L.g32 = cv.take<float>(ghost_cells(L.d));
             if (l < P.last) L.uold32 = cv.take<float>(n / 8);
+            if (l == 0 && P.nh == 1 && L.lay.split && n > kTailMaxCells) {
+                L.ualt = cv.take<double>(n);
+                L.ealt = cv.take<float>(n);
+            }
         }
     }
     // the small periodic levels at the bottom run as one single-workgroup launch
@@ -235,13 +241,14 @@ static void ghosts(Plan& P, int l, hipStream_t st) {
 }
 
 template <class T>
-static void smooth(Plan& P, int l, int sweeps, hipStream_t st) {
+static void smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_red = false) {
     Level& L = P.L[l];
     B<T> b = bufs<T>(L);
     const bool timed = l == 0;
     const double half_bytes = 0.5 * (double)L.d.cells() * 3.0 * sizeof(T);  // 3 words per update
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < 2; ++c) {
+            if (skip_first_red && s == 0 && c == 0) continue;  // already done by the fused outer step
             if (!L.periodic) ghosts<T>(P, l, st);
             KScope k(timed, st, half_bytes);
             launch_rbgs_half<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, c, st);
@@ -249,7 +256,7 @@ static void smooth(Plan& P, int l, int sweeps, hipStream_t st) {
 }
 
 template <class T>
-static void vcycle(Plan& P, int l, hipStream_t st) {
+static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) {
     Level& L = P.L[l];
     B<T> b = bufs<T>(L);
     if (l == P.tail) {  // this level and all below: one launch
@@ -268,7 +275,7 @@ static void vcycle(Plan& P, int l, hipStream_t st) {
         launch_coarsest<T>(b.u, b.f, L.d.x, L.h, st);
         return;
     }
-    smooth<T>(P, l, P.nu1, st);  // step 2
+    smooth<T>(P, l, P.nu1, st, skip_first_red);  // step 2
     Level& Q = P.L[l + 1];
     B<T> q = bufs<T>(Q);
     if (!L.periodic) ghosts<T>(P, l, st);
@@ -454,6 +461,33 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             int c = check(r2);
             if (c == MG_OK) status = MG_OK;
             else if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+        }
+    } else if (P.L[0].ualt) {
+        // single periodic level: the correction update, the FP64 residual, the FP32 right-hand
+        // side and the first red half-sweep of the next inner cycle are one kernel
+        Level& L = P.L[0];
+        bool pending = false;
+        for (;;) {
+            int np = 0;
+            launch_outer_split(L.u, pending ? L.u32 : nullptr, L.f, L.ualt, L.f32, L.ealt, L.lay, L.h, P.partials,
+                               &np, st);
+            std::swap(L.u, L.ualt);
+            std::swap(L.u32, L.ealt);
+            SegList sg{};
+            sg.n = 1; sg.off[0] = 0; sg.cnt[0] = np; sg.w[0] = L.h * L.h * L.h;
+            launch_finalize(P.partials, sg, P.scal + S_RNORM, st);
+            if (!fixed) {
+                double r2;
+                if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
+                int c = check(r2);
+                if (c == MG_OK) { status = MG_OK; break; }
+                if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+            }
+            if (cycles >= o->max_cycles) break;
+            vcycle<float>(P, 0, st, /*skip_first_red=*/true);
+            pending = true;
+            ++cycles;
+            S.cell_updates += upc;
         }
     } else {
         std::vector<float*> rhs(P.nh);

@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmgic.so")
+LIB_PATH = os.environ.get("MGIC_LIB") or os.path.join(_HERE, "libmgic.so")   # MGIC_LIB: another build
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmgic.so is not built (run __graft_entry__.build() or "
