@@ -13,7 +13,9 @@ defect-correction loop); the plain FP64 path is timed beside it.
 Prints ONE JSON line.  `value` is cell-updates per second of the headline path (smoother
 cell-updates summed over all levels and both solves, divided by the step time).  `roofline`
 is the finest-level smoother kernel: algorithmic bytes (3 words per cell-update) over its
-average launch duration, timed with HIP events on its own stream inside the timed region.
+average launch duration, timed with HIP events on its own stream inside the timed region;
+`traffic` is its HBM bytes per launch from the recorded rocprofv3 counter passes (null when the
+kernel sources no longer match the ones the counters were taken on).
 """
 
 import argparse
@@ -38,7 +40,41 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed", help="headline path")
+    ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 V-cycles per FP64 correction (0: library default)")
+    ap.add_argument("--pmc-calib", action="store_true",
+                    help="after the timed steps, run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
+
+
+# HBM traffic of the finest-level smoother, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# recorded under profiles/; it stands only while the kernel sources hash to the recorded value.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rbgs_split_f32_256.md")
+KERNEL_SOURCES = ("k_multigrid.hip", "mg_internal.h", "fastdiv.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    hsh = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1103_6031_amd", "csrc", name), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch from the recorded counter passes, or None if absent or stale."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith(("#", "`", " ")))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run_step(mg, H, ft, h, opts, ws):
@@ -50,8 +86,8 @@ def run_step(mg, H, ft, h, opts, ws):
     return (phi1, psi1, tau, phi2, psi2), (s1, s2)
 
 
-def time_path(mg, torch, H, ft, h, prec, tol, steps, warmup):
-    opts = mg.make_opts(tol=tol, prec=prec, max_cycles=60)
+def time_path(mg, torch, H, ft, h, prec, tol, steps, warmup, inner=0):
+    opts = mg.make_opts(tol=tol, prec=prec, max_cycles=60, inner=inner)
     ws = {"solve": mg.Workspace(mg.mg_workspace_bytes(H, opts)),
           "lpt1": mg.Workspace(mg.lpt_workspace_bytes(H, 1)),
           "lpt2": mg.Workspace(mg.lpt_workspace_bytes(H, 2))}
@@ -119,7 +155,7 @@ def main():
     torch.cuda.synchronize()
 
     other = "fp64" if a.prec == "mixed" else "mixed"
-    head, out_h = time_path(mg, torch, H, ft, h, a.prec, a.tol, a.steps, a.warmup)
+    head, out_h = time_path(mg, torch, H, ft, h, a.prec, a.tol, a.steps, a.warmup, a.inner)
     side, out_s = time_path(mg, torch, H, ft, h, other, a.tol, max(1, a.steps // 2), 1)
     out_m, out_d = (out_h, out_s) if a.prec == "mixed" else (out_s, out_h)
 
@@ -133,8 +169,10 @@ def main():
     k = head["kernel"]
     roof = None
     if k["achieved_gbs"]:
+        traffic = recorded_traffic() if (a.prec == "mixed" and N == 256) else None
         roof = dict(bound="hbm", achieved=round(k["achieved_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(k["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else int(traffic),
                     kernel="finest-level red-black smoother (%s)" % ("fp32" if a.prec == "mixed" else "fp64"),
                     avg_launch_us=round(k["avg_us"], 2), launches=k["launches"],
                     algorithmic_bytes_per_launch=int(k["bytes_per_launch"]))
@@ -152,6 +190,15 @@ def main():
                                  cycles=side["cycles"],
                                  smoother_gbs=round(side["kernel"]["achieved_gbs"] or 0.0, 1),
                                  smoother_avg_launch_us=round(side["kernel"]["avg_us"], 2))
+    if a.inner:
+        line["config"]["inner"] = a.inner
+    if a.pmc_calib:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f, h)
     print(json.dumps(line), flush=True)

@@ -74,17 +74,19 @@ typedef struct {
 
 typedef struct {
     double tol;         /* stop when composite ||r|| / ||f|| <= tol (relative, after a cycle's step 9) */
-    int max_cycles;     /* V-cycles (FP64) or defect-correction iterations (mixed)                    */
+    int max_cycles;     /* V-cycles at most (FP64 cycles, or FP32 inner cycles when mixed)            */
     int nu1, nu2;       /* pre / post red-black Gauss-Seidel sweeps (the paper uses 2 / 2)            */
     int prec;           /* MG_FP64 or MG_MIXED                                                        */
     unsigned flags;     /* MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES                                     */
+    int inner;          /* mixed only: FP32 V-cycles per FP64 correction step; 0 = default (2)        */
 } mg_opts;
 
 typedef struct {
-    int cycles;                 /* cycles (or outer iterations) run                              */
+    int cycles;                 /* V-cycles run (both precisions)                                */
     double rel_res;             /* final composite relative residual (NaN with MG_FIXED_CYCLES)   */
     double f_mean_removed;      /* composite mean subtracted from f                               */
-    double res_hist[64];        /* relative residual after each cycle (first 64)                  */
+    double res_hist[64];        /* res_hist[c-1]: relative residual after c cycles (first 64);   */
+                                /* NaN where none was formed (mixed: one per `inner` cycles)      */
     long long cell_updates;     /* smoother cell-updates performed (all levels, both precisions)  */
 } mg_stats;
 

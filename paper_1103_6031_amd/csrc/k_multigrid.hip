@@ -300,6 +300,30 @@ __global__ void k_prolong(T* __restrict__ u, Lay L, const T* __restrict__ pu, co
     if (t < (unsigned)L.d.cells()) cell_prolong<T>(u, L, pu, uold, pm, t);
 }
 
+// step 8 on the black cells of a colour-split level only: when a red half-sweep follows, it
+// overwrites every red cell without reading it, so correcting the red cells would be dead work
+template <class T>
+__device__ __forceinline__ void cell_prolong_black(T* __restrict__ u, const Lay& L, const T* __restrict__ pu,
+                                                   const T* __restrict__ uold, const ParentMap& pm, unsigned t) {
+    const unsigned nzh = (unsigned)L.d.z >> 1;
+    const unsigned row = L.dzh.div(t);
+    const unsigned j = t - row * nzh;
+    const unsigned xq = L.dy.div(row);
+    const int y = (int)(row - xq * (unsigned)L.d.y), x = (int)xq;
+    const int z = 2 * (int)j + ((x + y + 1) & 1);
+    const size_t i = (size_t)row * L.d.z + nzh + j;
+    const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+    const size_t o = ((size_t)X * (L.d.y >> 1) + Y) * (L.d.z >> 1) + Z;
+    u[i] = u[i] + (pu[pidx(pm, X, Y, Z)] - uold[o]);
+}
+
+template <class T>
+__global__ void k_prolong_black(T* __restrict__ u, Lay L, const T* __restrict__ pu, const T* __restrict__ uold,
+                                ParentMap pm) {
+    const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
+    if (t < (unsigned)(L.d.cells() >> 1)) cell_prolong_black<T>(u, L, pu, uold, pm, t);
+}
+
 template <class T>
 __global__ void k_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, double h) {
     __shared__ double G[343];
@@ -315,42 +339,21 @@ __global__ void k_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, do
 // ----------------------------------------------------------------------------------------------
 
 template <class T>
-__host__ __device__ inline size_t tail_lds_bytes(const TailPlan<T>& tp) {
-    size_t off = 0;
-    for (int k = 0; k < tp.n; ++k) {
-        const size_t c = tp.lev[k].lay.d.cells();
-        off += 2 * c * sizeof(T);
-        if (k + 1 < tp.n) off += (c / 8) * sizeof(T);
-        off = (off + 15) & ~(size_t)15;
-    }
-    return off + 2 * 343 * sizeof(double);
-}
-
-template <class T>
 __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
     extern __shared__ __align__(16) unsigned char smem[];
-    T* U[kTailMaxLevels];
-    T* F[kTailMaxLevels];
-    T* O[kTailMaxLevels];
-    size_t off = 0;
-    for (int k = 0; k < tp.n; ++k) {
-        const size_t c = tp.lev[k].lay.d.cells();
-        U[k] = (T*)(smem + off);
-        off += c * sizeof(T);
-        F[k] = (T*)(smem + off);
-        off += c * sizeof(T);
-        O[k] = (T*)(smem + off);
-        if (k + 1 < tp.n) off += (c / 8) * sizeof(T);
-        off = (off + 15) & ~(size_t)15;
-    }
-    double* G = (double*)(smem + off);
+    auto U = [&](int k) { return (T*)(smem + tp.lev[k].lds_u); };
+    auto F = [&](int k) { return (T*)(smem + tp.lev[k].lds_f); };
+    auto O = [&](int k) { return (T*)(smem + tp.lev[k].lds_o); };
+    double* G = (double*)(smem + tp.lds_bytes - 2 * 343 * sizeof(double));
     double* Gf = G + 343;
     const unsigned nt = blockDim.x;
     {
         const unsigned n0 = (unsigned)tp.lev[0].lay.d.cells();
+        T* U0 = U(0);
+        T* F0 = F(0);
         for (unsigned t = threadIdx.x; t < n0; t += nt) {
-            U[0][t] = tp.lev[0].u[t];
-            F[0][t] = tp.lev[0].f[t];
+            U0[t] = tp.lev[0].u[t];
+            F0[t] = tp.lev[0].f[t];
         }
         __syncthreads();
     }
@@ -361,7 +364,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
         const unsigned half = (unsigned)A.d.cells() >> 1;
         for (int s = 0; s < tp.nu1; ++s)
             for (int c = 0; c < 2; ++c) {
-                for (unsigned t = threadIdx.x; t < half; t += nt) cell_rbgs_split<T>(U[l], F[l], A, h2, c, t);
+                for (unsigned t = threadIdx.x; t < half; t += nt) cell_rbgs_split<T>(U(l), F(l), A, h2, c, t);
                 __syncthreads();
             }
         const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
@@ -369,15 +372,15 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
         C.split = 0;
         const unsigned nc = (unsigned)A.d.cells() >> 3;
         for (unsigned t = threadIdx.x; t < nc; t += nt)
-            cell_resid_restrict<T, false>(U[l], F[l], (const T*)nullptr, A, h2, U[l + 1], F[l + 1], O[l], pm, C, t);
+            cell_resid_restrict<T, false>(U(l), F(l), (const T*)nullptr, A, h2, U(l + 1), F(l + 1), O(l), pm, C, t);
         __syncthreads();
         const T H2 = (T)(tp.lev[l + 1].h * tp.lev[l + 1].h);
-        for (unsigned t = threadIdx.x; t < nc; t += nt) cell_fas<T>(U[l + 1], F[l + 1], pm, C, H2, t);
+        for (unsigned t = threadIdx.x; t < nc; t += nt) cell_fas<T>(U(l + 1), F(l + 1), pm, C, H2, t);
         __syncthreads();
     }
     {
         const int c = tp.n - 1;
-        block_coarsest<T>(U[c], F[c], tp.lev[c].lay.d.x, tp.lev[c].h, G, Gf);
+        block_coarsest<T>(U(c), F(c), tp.lev[c].lay.d.x, tp.lev[c].h, G, Gf);
         __syncthreads();
     }
     // ascent: correct, smooth
@@ -385,17 +388,20 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
         const Lay A = tp.lev[l].lay, Bl = tp.lev[l + 1].lay;
         const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
         const unsigned n = (unsigned)A.d.cells();
-        for (unsigned t = threadIdx.x; t < n; t += nt) cell_prolong<T>(U[l], A, U[l + 1], O[l], pm, t);
+        if (tp.nu2 > 0 && A.split)   // red cells are rewritten unread by the first red half-sweep
+            for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_prolong_black<T>(U(l), A, U(l + 1), O(l), pm, t);
+        else
+            for (unsigned t = threadIdx.x; t < n; t += nt) cell_prolong<T>(U(l), A, U(l + 1), O(l), pm, t);
         __syncthreads();
         const T h2 = (T)(tp.lev[l].h * tp.lev[l].h);
         for (int s = 0; s < tp.nu2; ++s)
             for (int c = 0; c < 2; ++c) {
-                for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_rbgs_split<T>(U[l], F[l], A, h2, c, t);
+                for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_rbgs_split<T>(U(l), F(l), A, h2, c, t);
                 __syncthreads();
             }
     }
     const unsigned n0 = (unsigned)tp.lev[0].lay.d.cells();
-    for (unsigned t = threadIdx.x; t < n0; t += nt) tp.lev[0].u[t] = U[0][t];
+    for (unsigned t = threadIdx.x; t < n0; t += nt) tp.lev[0].u[t] = U(0)[t];
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -578,7 +584,7 @@ __global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ 
 //   v   = u_in + (double) e_in          (the pending FP32 correction; e_in == nullptr: none)
 //   r   = f - L v                        (FP64, same arithmetic as k_residual_split)
 //   u_out = v,  rhs = (float) r,  e_out = the first red half-sweep of the next inner cycle from
-//   e = 0, i.e. (0 - h^2 rhs) / 6 on red cells and 0 on black cells.
+//   e = 0, i.e. (0 - h^2 rhs) / 6 on red cells; black entries are not written.
 // v is formed on the fly for the 7 stencil points, so u_out / e_out must not alias the inputs.
 __global__ void k_outer_split(const double* __restrict__ u_in, const float* __restrict__ e_in,
                               const double* __restrict__ f, double* __restrict__ u_out, float* __restrict__ rhs,
@@ -614,7 +620,9 @@ __global__ void k_outer_split(const double* __restrict__ u_in, const float* __re
         const float rf = (float)r;
         u_out[t] = c0;
         rhs[t] = rf;
-        e_out[t] = col ? 0.0f : (0.0f - h2f * rf) / 6.0f;
+        // black entries of e_out are left as they are: the black half-sweep that follows writes
+        // every one of them before anything reads them
+        if (!col) e_out[t] = (0.0f - h2f * rf) / 6.0f;
     }
     const double bs = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
@@ -696,12 +704,7 @@ void launch_tail(const TailPlan<T>& tp, hipStream_t st) {
         hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
         attr = true;
     }
-    k_tail<T><<<1, kTailThreads, tail_lds_bytes(tp), st>>>(tp);
-}
-
-template <class T>
-size_t tail_lds_size(const TailPlan<T>& tp) {
-    return tail_lds_bytes(tp);
+    k_tail<T><<<1, kTailThreads, tp.lds_bytes, st>>>(tp);
 }
 
 template <class T>
@@ -722,8 +725,11 @@ void launch_fas_rhs(const T* pu, T* pf, ParentMap pm, Dims cov, double H, hipStr
 }
 
 template <class T>
-void launch_prolong(T* u, Lay L, const T* pu, const T* uold, ParentMap pm, hipStream_t st) {
-    k_prolong<T><<<grid_for(L.d.cells()), kBlock, 0, st>>>(u, L, pu, uold, pm);
+void launch_prolong(T* u, Lay L, const T* pu, const T* uold, ParentMap pm, int black_only, hipStream_t st) {
+    if (black_only && L.split)
+        k_prolong_black<T><<<grid_for(L.d.cells() >> 1), kBlock, 0, st>>>(u, L, pu, uold, pm);
+    else
+        k_prolong<T><<<grid_for(L.d.cells()), kBlock, 0, st>>>(u, L, pu, uold, pm);
 }
 
 template <class T>
@@ -779,12 +785,11 @@ template void launch_sub_mean<double>(double*, size_t, const double*, double, hi
     template void launch_resid_restrict<T>(const T*, const T*, const T*, Lay, double, T*, T*, T*, ParentMap, \
                                            hipStream_t);                                                    \
     template void launch_fas_rhs<T>(const T*, T*, ParentMap, Dims, double, hipStream_t);                    \
-    template void launch_prolong<T>(T*, Lay, const T*, const T*, ParentMap, hipStream_t);                   \
+    template void launch_prolong<T>(T*, Lay, const T*, const T*, ParentMap, int, hipStream_t);                   \
     template void launch_coarsest<T>(T*, const T*, int, double, hipStream_t);                               \
     template void launch_ghost_fill<T>(const T*, const T*, T*, Dims, ParentMap, int, hipStream_t);          \
     template void launch_restrict_cov<T>(const T*, Lay, T*, ParentMap, hipStream_t);                \
-    template void launch_tail<T>(const TailPlan<T>&, hipStream_t);                                   \
-    template size_t tail_lds_size<T>(const TailPlan<T>&);
+    template void launch_tail<T>(const TailPlan<T>&, hipStream_t);
 MGIC_INST(double)
 MGIC_INST(float)
 #undef MGIC_INST

@@ -106,17 +106,37 @@ constexpr size_t kTailMaxLds = 160 * 1024;        // LDS one gfx950 workgroup ma
 constexpr int kTailMaxLevels = 8;
 template <class T>
 struct TailLevel {
-    T* u;
+    T* u;       // the level's global arrays (only level 0's are read and written)
     T* f;
-    T* uold;    // unused: the tail keeps its restricted copies in LDS
     Lay lay;    // colour-split except the odd (or single-cell) coarsest level
     double h;
+    unsigned lds_u, lds_f, lds_o;   // byte offsets in LDS of u, f and the restricted copy (uold)
 };
 template <class T>
 struct TailPlan {
     int n, nu1, nu2;
+    unsigned lds_bytes;             // total LDS, including the coarsest solver's 2 x 343 doubles
     TailLevel<T> lev[kTailMaxLevels];
 };
+// Places every tail level in LDS (u, f, then the copy of the restricted u of the next level),
+// 16-byte aligned; the coarsest solver's tables follow.  Offsets live in the plan so that the
+// kernel forms its pointers with scalar arithmetic instead of indexing a private array.
+template <class T>
+inline unsigned tail_assign_lds(TailPlan<T>& tp) {
+    size_t off = 0;
+    for (int k = 0; k < tp.n; ++k) {
+        const size_t c = tp.lev[k].lay.d.cells();
+        tp.lev[k].lds_u = (unsigned)off;
+        off += c * sizeof(T);
+        tp.lev[k].lds_f = (unsigned)off;
+        off += c * sizeof(T);
+        tp.lev[k].lds_o = (unsigned)off;
+        if (k + 1 < tp.n) off += (c / 8) * sizeof(T);
+        off = (off + 15) & ~(size_t)15;
+    }
+    tp.lds_bytes = (unsigned)(off + 2 * 343 * sizeof(double));
+    return tp.lds_bytes;
+}
 
 // Segments of partial sums combined by the finalize kernel: out = sum_s w[s] * sum(partials[s]).
 struct SegList {
@@ -145,11 +165,12 @@ template <class T> void launch_resid_restrict(const T* u, const T* f, const T* g
                                               T* pu, T* pf, T* uold, ParentMap pm, hipStream_t st);
 // parent f[cov] += L u  (FAS coarse right-hand side), L over the parent's own stencil
 template <class T> void launch_fas_rhs(const T* pu, T* pf, ParentMap pm, Dims cov, double H, hipStream_t st);
-// fine u += inject(parent u[cov] - uold)
-template <class T> void launch_prolong(T* u, Lay L, const T* pu, const T* uold, ParentMap pm, hipStream_t st);
+// fine u += inject(parent u[cov] - uold); black_only on a colour-split level corrects the black
+// cells only (valid when a red half-sweep follows: it rewrites every red cell unread)
+template <class T> void launch_prolong(T* u, Lay L, const T* pu, const T* uold, ParentMap pm, int black_only,
+                                       hipStream_t st);
 // V-cycle over all levels of a tail plan in one single-workgroup launch
 template <class T> void launch_tail(const TailPlan<T>& tp, hipStream_t st);
-template <class T> size_t tail_lds_size(const TailPlan<T>& tp);
 // exact coarsest solve on an odd periodic M^3 grid (M = 1: u = 0)
 template <class T> void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st);
 
@@ -165,7 +186,7 @@ template <class T, class R> void launch_residual(const T* u, const T* f, const T
                                                  CovBox cov, R* rout, Lay LR, double* partials, int* nparts,
                                                  hipStream_t st);
 // fused outer step of the mixed-precision defect correction on a colour-split periodic level:
-// u_out = u_in + e_in, rhs = (float)(f - L u_out), e_out = first red half-sweep from e = 0;
+// u_out = u_in + e_in, rhs = (float)(f - L u_out), red e_out = first red half-sweep from e = 0;
 // per-block partial sums of r^2
 void launch_outer_split(const double* u_in, const float* e_in, const double* f, double* u_out, float* rhs,
                         float* e_out, Lay L, double h, double* partials, int* nparts, hipStream_t st);

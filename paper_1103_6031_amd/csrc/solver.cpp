@@ -266,8 +266,9 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
         tp.nu2 = P.nu2;
         for (int k = 0; k < tp.n; ++k) {
             B<T> c = bufs<T>(P.L[l + k]);
-            tp.lev[k] = TailLevel<T>{c.u, c.f, c.uold, P.L[l + k].lay, P.L[l + k].h};
+            tp.lev[k] = TailLevel<T>{c.u, c.f, P.L[l + k].lay, P.L[l + k].h, 0, 0, 0};
         }
+        tail_assign_lds(tp);
         launch_tail<T>(tp, st);
         return;
     }
@@ -283,7 +284,7 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
     launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, q.u, q.f, b.uold, L.pm, st);
     launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
     vcycle<T>(P, l + 1, st);                         // step 7
-    launch_prolong<T>(b.u, L.lay, q.u, b.uold, L.pm, st);  // step 8
+    launch_prolong<T>(b.u, L.lay, q.u, b.uold, L.pm, P.nu2 > 0, st);  // step 8
     smooth<T>(P, l, P.nu2, st);                      // step 9
 }
 
@@ -391,6 +392,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     if (!f || !u) return fail(MG_EINVAL, "f/u pointer arrays are NULL");
     if (o->max_cycles < 0) return fail(MG_EINVAL, "max_cycles < 0");
     if (o->prec != MG_FP64 && o->prec != MG_MIXED) return fail(MG_EINVAL, "unknown precision");
+    if (o->inner < 0 || o->inner > 16) return fail(MG_EINVAL, "inner cycles out of range (0..16)");
     if (int v = validate_hier(H)) return v;
     for (int p = 0; p < H->nlev; ++p)
         if (!u[p] || !f[p]) return fail(MG_EINVAL, "level pointer is NULL");
@@ -416,6 +418,10 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
 
     mg_stats S;
     std::memset(&S, 0, sizeof(S));
+    for (double& v : S.res_hist) v = NAN;
+    // FP32 inner cycles per FP64 correction: each inner cycle contracts the error about tenfold,
+    // far above FP32 round-off, so two of them per correction halve the FP64 residual passes
+    const int inner = o->inner > 0 ? o->inner : 2;
     double fs[2] = {0, 0};
     double fnorm2 = 0;
     if (!fixed) {
@@ -484,10 +490,12 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
                 if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
             }
             if (cycles >= o->max_cycles) break;
-            vcycle<float>(P, 0, st, /*skip_first_red=*/true);
+            for (int k = 0; k < inner && cycles < o->max_cycles; ++k) {
+                vcycle<float>(P, 0, st, /*skip_first_red=*/k == 0);
+                ++cycles;
+                S.cell_updates += upc;
+            }
             pending = true;
-            ++cycles;
-            S.cell_updates += upc;
         }
     } else {
         std::vector<float*> rhs(P.nh);
@@ -503,10 +511,12 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             }
             if (cycles >= o->max_cycles) break;
             for (int l = 0; l < P.nh; ++l) launch_fill<float>(P.L[l].u32, P.L[l].d.cells(), 0.0f, st);
-            vcycle<float>(P, 0, st);
+            for (int k = 0; k < inner && cycles < o->max_cycles; ++k) {
+                vcycle<float>(P, 0, st);
+                ++cycles;
+                S.cell_updates += upc;
+            }
             for (int l = 0; l < P.nh; ++l) launch_add_f32_to_f64(P.L[l].u, P.L[l].u32, P.L[l].d.cells(), st);
-            ++cycles;
-            S.cell_updates += upc;
         }
     }
     gauge_u(P, st);

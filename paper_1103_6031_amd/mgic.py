@@ -41,7 +41,7 @@ class mg_hier(ctypes.Structure):
 
 class mg_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_cycles", ctypes.c_int), ("nu1", ctypes.c_int),
-                ("nu2", ctypes.c_int), ("prec", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("nu2", ctypes.c_int), ("prec", ctypes.c_int), ("flags", ctypes.c_uint), ("inner", ctypes.c_int)]
 
 
 class mg_stats(ctypes.Structure):
@@ -136,8 +136,10 @@ class Hier:
         return sum(math.prod(self.dims(p)) for p in range(self.nlev))
 
 
-def make_opts(tol=1e-10, max_cycles=50, nu1=2, nu2=2, prec="fp64", fixed_cycles=False, initial_guess=False):
+def make_opts(tol=1e-10, max_cycles=50, nu1=2, nu2=2, prec="fp64", fixed_cycles=False, initial_guess=False,
+              inner=0):
     o = mg_opts()
+    o.inner = inner
     o.tol = tol
     o.max_cycles = max_cycles
     o.nu1 = nu1
