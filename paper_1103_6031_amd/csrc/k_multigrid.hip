@@ -16,6 +16,8 @@
 // fine rows.  Patches (natural rows) keep a separate ghost layer of 6 faces.
 // Compiled with -ffp-contract=off so the arithmetic order written here is the order executed.
 
+#include <hip/hip_ext.h>
+
 #include "mg_internal.h"
 
 namespace mgic {
@@ -686,15 +688,19 @@ void launch_sub_mean(T* a, size_t n, const double* sum, double inv_count, hipStr
 }
 
 template <class T>
-void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h, int colour, hipStream_t st) {
+void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h, int colour, hipStream_t st,
+                      hipEvent_t ev0, hipEvent_t ev1) {
     const size_t n = (size_t)L.d.x * L.d.y * (L.d.z / 2);
     const T h2 = (T)(h * h);
     if (ghosts)
-        k_rbgs_ghost<T><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, colour);
+        hipExtLaunchKernelGGL(k_rbgs_ghost<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, ghosts, L,
+                              h2, colour);
     else if (n >= (size_t)kBlock * 64 * 2)
-        k_rbgs_split<T, 2><<<grid_for((n + 1) / 2), kBlock, 0, st>>>(u, f, L, h2, colour);
+        hipExtLaunchKernelGGL(k_rbgs_split<T, 2>, dim3(grid_for((n + 1) / 2)), dim3(kBlock), 0, st, ev0, ev1, 0, u,
+                              f, L, h2, colour);
     else
-        k_rbgs_split<T, 1><<<grid_for(n), kBlock, 0, st>>>(u, f, L, h2, colour);
+        hipExtLaunchKernelGGL(k_rbgs_split<T, 1>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, L, h2,
+                              colour);
 }
 
 template <class T>
@@ -781,7 +787,8 @@ template void launch_relayout<float, double>(const float*, Lay, double*, Lay, hi
 template void launch_relayout<double, double>(const double*, Lay, double*, Lay, hipStream_t);
 template void launch_sub_mean<double>(double*, size_t, const double*, double, hipStream_t);
 #define MGIC_INST(T)                                                                                        \
-    template void launch_rbgs_half<T>(T*, const T*, const T*, Lay, double, int, hipStream_t);               \
+    template void launch_rbgs_half<T>(T*, const T*, const T*, Lay, double, int, hipStream_t, hipEvent_t,      \
+                                      hipEvent_t);               \
     template void launch_resid_restrict<T>(const T*, const T*, const T*, Lay, double, T*, T*, T*, ParentMap, \
                                            hipStream_t);                                                    \
     template void launch_fas_rhs<T>(const T*, T*, ParentMap, Dims, double, hipStream_t);                    \

@@ -156,8 +156,11 @@ template <class T> void launch_sub_mean(T* a, size_t n, const double* sum, doubl
 
 // red-black half-sweep (colour 0 = red = (x+y+z) even); ghosts == nullptr => periodic level in
 // the colour-split layout, else a patch in natural rows with its ghost faces
+// ev0 / ev1 (both null, or both events): stamped by the dispatch itself at the kernel's start and
+// end, so their elapsed time is the kernel's own duration
 template <class T> void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h,
-                                         int colour, hipStream_t st);
+                                         int colour, hipStream_t st, hipEvent_t ev0 = nullptr,
+                                         hipEvent_t ev1 = nullptr);
 
 // residual r = f - L u on the fine level, restricted: parent u[cov] = mean8 u, uold = mean8 u,
 // parent f[cov] = mean8 r  (fine level periodic if ghosts == nullptr)

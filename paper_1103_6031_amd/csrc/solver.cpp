@@ -203,22 +203,17 @@ struct KProf {
 };
 static thread_local KProf g_kprof;
 
-// brackets one launch when timing is on; returns the stop event to record after it
-struct KScope {
+// start / stop events for one timed launch (both null when timing is off)
+struct KEvents {
     hipEvent_t a = nullptr, b = nullptr;
-    hipStream_t st;
-    double bytes;
-    KScope(bool time_it, hipStream_t s, double by) : st(s), bytes(by) {
+    KEvents(bool time_it) {
         if (!time_it || !g_kprof.on) return;
         a = g_kprof.get();
         b = g_kprof.get();
-        if (a && b) hipEventRecord(a, st);
+        if (!a || !b) a = b = nullptr;
     }
-    ~KScope() {
-        if (a && b) {
-            hipEventRecord(b, st);
-            g_kprof.recs.push_back({a, b, bytes});
-        }
+    void done(double bytes) {
+        if (a) g_kprof.recs.push_back({a, b, bytes});
     }
 };
 
@@ -250,8 +245,9 @@ static void smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_r
         for (int c = 0; c < 2; ++c) {
             if (skip_first_red && s == 0 && c == 0) continue;  // already done by the fused outer step
             if (!L.periodic) ghosts<T>(P, l, st);
-            KScope k(timed, st, half_bytes);
-            launch_rbgs_half<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, c, st);
+            KEvents ev(timed);
+            launch_rbgs_half<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, c, st, ev.a, ev.b);
+            ev.done(half_bytes);
         }
 }
 
