@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance leg")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed", help="headline path")
     ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 V-cycles per FP64 correction (0: library default)")
     ap.add_argument("--pmc-calib", action="store_true",
@@ -113,6 +114,43 @@ def time_path(mg, torch, H, ft, h, prec, tol, steps, warmup, inner=0):
                kernel=dict(launches=klaunch, avg_us=1e3 * kms / max(klaunch, 1),
                            bytes_per_launch=kbytes / max(klaunch, 1), achieved_gbs=achieved))
     return res, out
+
+
+def time_batch(mg, torch, reps):
+    """64 independent periodic instances (sizes in {32,48,64,96,128}^3, power-law spectra): one
+    batched mixed-precision solve against the same instances solved one after another."""
+    from paper_1103_6031_amd import inputs
+    inst = inputs.c4_instances()
+    sizes = [N for N, _, _ in inst]
+    hs = [inputs.BOX / N for N in sizes]
+    fs = [torch.from_numpy(inputs.c4_field(N, s, seed)).to("cuda:0") for N, s, seed in inst]
+    o = mg.make_opts(tol=1e-10, prec="mixed", max_cycles=40)
+    ws = mg.Workspace(mg.mg_batch_workspace_bytes(sizes, o))
+    u = [torch.empty_like(f) for f in fs]
+    mg.mg_solve_batch(fs, hs, u=u, opts=o, workspace=ws)     # warm-up (autotuning, graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = mg.mg_solve_batch(fs, hs, u=u, opts=o, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ups = sum(s["cell_updates"] for s in st)
+    wss = mg.Workspace(max(mg.mg_workspace_bytes(mg.Hier(N, 1.0), o) for N in set(sizes)))
+    us = [torch.empty_like(f) for f in fs]
+    for f, h, x in zip(fs, hs, us):
+        mg.mg_solve_level(f, h, u=x, opts=o, workspace=wss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f, h, x in zip(fs, hs, us):
+        mg.mg_solve_level(f, h, u=x, opts=o, workspace=wss)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t0
+    same = all(bool(torch.equal(a, b)) for a, b in zip(u, us))
+    cyc = [s["cycles"] for s in st]
+    return dict(workload="64 periodic instances, sizes {32,48,64,96,128}^3, P=k^n, n in [-2.5,-1.5], mixed, tol 1e-10",
+                cells=int(sum(N ** 3 for N in sizes)), ms_per_solve=round(dt * 1e3, 3),
+                value=round(ups / dt / 1e6, 1), unit="Mcell-updates/s", cycles=[min(cyc), max(cyc)],
+                sequential_ms=round(dts * 1e3, 3), speedup=round(dts / dt, 2), bit_identical_to_solo=same)
 
 
 def cpu_baseline(f, h):
@@ -192,6 +230,8 @@ def main():
                                  smoother_avg_launch_us=round(side["kernel"]["avg_us"], 2))
     if a.inner:
         line["config"]["inner"] = a.inner
+    if not a.no_batch:
+        line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
     if a.pmc_calib:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)

@@ -60,6 +60,7 @@ enum { MG_FP64 = 0, MG_MIXED = 1 };
 /* option flags */
 #define MG_USE_INITIAL_GUESS 0x1u  /* start from the caller's u instead of 0                    */
 #define MG_FIXED_CYCLES      0x2u  /* run exactly max_cycles cycles, no per-cycle host readback */
+#define MG_NO_GRAPH          0x4u  /* mg_solve_batch: launch directly instead of replaying graphs */
 
 typedef struct {
     int n[3];       /* cells per axis (base: all three equal)                 */

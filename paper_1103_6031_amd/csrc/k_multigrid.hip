@@ -68,11 +68,12 @@ __device__ __forceinline__ size_t pidx(const ParentMap& pm, int X, int Y, int Z)
 }
 
 
-// Reduction kernels stride over the whole array, kRedV independent cells per thread per pass.
-// (Measured on MI355X: giving each block one contiguous chunk instead was no faster.)
-__device__ __forceinline__ unsigned red_lo(unsigned) { return blockIdx.x * blockDim.x * kRedV; }
-__device__ __forceinline__ unsigned red_hi(unsigned n) { return n; }
-__device__ __forceinline__ unsigned red_stride() { return gridDim.x * blockDim.x * kRedV; }
+// Reduction kernels stride over the whole array, kRedV independent cells per thread per pass;
+// blk / nblk are the block's index and the block count of its array (the grid of a plain launch,
+// the instance's share of a batched one).  (Measured on MI355X: giving each block one contiguous
+// chunk instead was no faster.)
+__device__ __forceinline__ unsigned red_lo(unsigned blk) { return blk * blockDim.x * kRedV; }
+__device__ __forceinline__ unsigned red_stride(unsigned nblk) { return nblk * blockDim.x * kRedV; }
 
 // ----------------------------------------------------------------------------------------------
 // deterministic block reduction (wave64 shuffle, then the waves in order)
@@ -250,14 +251,20 @@ __device__ void block_coarsest(T* __restrict__ u, const T* __restrict__ f, int M
 
 // periodic level in the colour-split layout: V consecutive cells of a half-row per thread
 template <class T, int V>
-__global__ void k_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Lay L, T h2, int colour) {
+__device__ __forceinline__ void body_rbgs_split(T* __restrict__ u, const T* __restrict__ f, const Lay& L, T h2,
+                                                int colour, unsigned blk) {
     const unsigned total = (unsigned)L.d.x * L.d.y * ((unsigned)L.d.z >> 1);
-    const unsigned base = (unsigned)xcd_block() * blockDim.x * V + threadIdx.x;
+    const unsigned base = blk * blockDim.x * V + threadIdx.x;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const unsigned t = base + v * blockDim.x;   // each of the V passes is unit-stride over the wave
         if (t < total) cell_rbgs_split<T>(u, f, L, h2, colour, t);
     }
+}
+
+template <class T, int V>
+__global__ void k_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Lay L, T h2, int colour) {
+    body_rbgs_split<T, V>(u, f, L, h2, colour, (unsigned)xcd_block());
 }
 
 // patch (natural rows, ghost faces): one thread per cell of the colour
@@ -341,7 +348,7 @@ __global__ void k_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, do
 // ----------------------------------------------------------------------------------------------
 
 template <class T>
-__global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
+__device__ void body_tail(const TailPlan<T>& tp) {
     extern __shared__ __align__(16) unsigned char smem[];
     auto U = [&](int k) { return (T*)(smem + tp.lev[k].lds_u); };
     auto F = [&](int k) { return (T*)(smem + tp.lev[k].lds_f); };
@@ -404,6 +411,11 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
     }
     const unsigned n0 = (unsigned)tp.lev[0].lay.d.cells();
     for (unsigned t = threadIdx.x; t < n0; t += nt) tp.lev[0].u[t] = U(0)[t];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
+    body_tail<T>(tp);
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -523,11 +535,12 @@ __device__ __forceinline__ bool in_box(const CovBox& cb, int x, int y, int z) {
 }
 
 template <class T, class R, bool GH>
-__global__ void k_residual(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Lay L,
-                           T h2, CovBox cb, R* __restrict__ rout, Lay LR, double* __restrict__ partials) {
+__device__ __forceinline__ double body_residual(const T* __restrict__ u, const T* __restrict__ f,
+                                                const T* __restrict__ g, const Lay& L, T h2, const CovBox& cb,
+                                                R* __restrict__ rout, const Lay& LR, unsigned blk, unsigned nblk) {
     double acc = 0.0;
     const size_t n = L.d.cells();
-    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
     for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV; ++v) {
@@ -541,19 +554,26 @@ __global__ void k_residual(const T* __restrict__ u, const T* __restrict__ f, con
         if (!cov) acc += (double)r * (double)r;
         if (rout) rout[lidx(LR, x, y, z)] = cov ? R(0) : (R)r;
     }
-    const double bs = block_sum(acc);
+    return acc;
+}
+
+template <class T, class R, bool GH>
+__global__ void k_residual(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Lay L,
+                           T h2, CovBox cb, R* __restrict__ rout, Lay LR, double* __restrict__ partials) {
+    const double bs = block_sum(body_residual<T, R, GH>(u, f, g, L, h2, cb, rout, LR, blockIdx.x, gridDim.x));
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
 // the same on a colour-split periodic level, r written in the same layout; neighbour rows are
 // addressed directly (identical arithmetic, so identical bits)
 template <class T, class R>
-__global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ f, Lay L, T h2, CovBox cb,
-                                 R* __restrict__ rout, double* __restrict__ partials) {
+__device__ __forceinline__ double body_residual_split(const T* __restrict__ u, const T* __restrict__ f,
+                                                      const Lay& L, T h2, const CovBox& cb, R* __restrict__ rout,
+                                                      unsigned blk, unsigned nblk) {
     const Dims d = L.d;
     const unsigned n = (unsigned)d.cells(), nz = (unsigned)d.z, nzh = nz >> 1;
     double acc = 0.0;
-    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
     for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV; ++v) {
@@ -578,7 +598,13 @@ __global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ 
         if (!cov) acc += (double)r * (double)r;
         if (rout) rout[t] = cov ? R(0) : (R)r;
     }
-    const double bs = block_sum(acc);
+    return acc;
+}
+
+template <class T, class R>
+__global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ f, Lay L, T h2, CovBox cb,
+                                 R* __restrict__ rout, double* __restrict__ partials) {
+    const double bs = block_sum(body_residual_split<T, R>(u, f, L, h2, cb, rout, blockIdx.x, gridDim.x));
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
@@ -588,14 +614,14 @@ __global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ 
 //   u_out = v,  rhs = (float) r,  e_out = the first red half-sweep of the next inner cycle from
 //   e = 0, i.e. (0 - h^2 rhs) / 6 on red cells; black entries are not written.
 // v is formed on the fly for the 7 stencil points, so u_out / e_out must not alias the inputs.
-__global__ void k_outer_split(const double* __restrict__ u_in, const float* __restrict__ e_in,
-                              const double* __restrict__ f, double* __restrict__ u_out, float* __restrict__ rhs,
-                              float* __restrict__ e_out, Lay L, double h2, float h2f,
-                              double* __restrict__ partials) {
+__device__ __forceinline__ double body_outer_split(const double* __restrict__ u_in, const float* __restrict__ e_in,
+                                                   const double* __restrict__ f, double* __restrict__ u_out,
+                                                   float* __restrict__ rhs, float* __restrict__ e_out,
+                                                   const Lay& L, double h2, float h2f, unsigned blk, unsigned nblk) {
     const Dims d = L.d;
     const unsigned n = (unsigned)d.cells(), nz = (unsigned)d.z, nzh = nz >> 1;
     double acc = 0.0;
-    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
     for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV; ++v) {
@@ -626,7 +652,14 @@ __global__ void k_outer_split(const double* __restrict__ u_in, const float* __re
         // every one of them before anything reads them
         if (!col) e_out[t] = (0.0f - h2f * rf) / 6.0f;
     }
-    const double bs = block_sum(acc);
+    return acc;
+}
+
+__global__ void k_outer_split(const double* __restrict__ u_in, const float* __restrict__ e_in,
+                              const double* __restrict__ f, double* __restrict__ u_out, float* __restrict__ rhs,
+                              float* __restrict__ e_out, Lay L, double h2, float h2f,
+                              double* __restrict__ partials) {
+    const double bs = block_sum(body_outer_split(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blockIdx.x, gridDim.x));
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
@@ -637,10 +670,11 @@ void launch_outer_split(const double* u_in, const float* e_in, const double* f, 
     *nparts = g;
 }
 
-__global__ void k_sum(const double* __restrict__ a, Lay L, CovBox cb, int square, double* __restrict__ partials) {
+__device__ __forceinline__ double body_sum(const double* __restrict__ a, const Lay& L, const CovBox& cb, int square,
+                                           unsigned blk, unsigned nblk) {
     double acc = 0.0;
     const size_t n = L.d.cells();
-    const unsigned lo = red_lo((unsigned)n), hi = red_hi((unsigned)n), stride = red_stride();
+    const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
     for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV; ++v) {
@@ -652,18 +686,26 @@ __global__ void k_sum(const double* __restrict__ a, Lay L, CovBox cb, int square
         const double av = a[i];
         acc += square ? av * av : av;
     }
-    const double bs = block_sum(acc);
+    return acc;
+}
+
+__global__ void k_sum(const double* __restrict__ a, Lay L, CovBox cb, int square, double* __restrict__ partials) {
+    const double bs = block_sum(body_sum(a, L, cb, square, blockIdx.x, gridDim.x));
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// w * sum(partials[0..cnt)), added to total on thread 0, in a fixed order
+__device__ __forceinline__ void body_finalize_seg(const double* __restrict__ partials, int cnt, double w,
+                                                  double& total) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) acc += partials[i];
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) total += w * bs;
 }
 
 __global__ void k_finalize(const double* __restrict__ partials, SegList segs, double* __restrict__ out) {
     double total = 0.0;
-    for (int s = 0; s < segs.n; ++s) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < segs.cnt[s]; i += blockDim.x) acc += partials[segs.off[s] + i];
-        const double bs = block_sum(acc);
-        if (threadIdx.x == 0) total += segs.w[s] * bs;
-    }
+    for (int s = 0; s < segs.n; ++s) body_finalize_seg(partials + segs.off[s], segs.cnt[s], segs.w[s], total);
     if (threadIdx.x == 0) out[0] = total;
 }
 
@@ -779,6 +821,215 @@ void launch_finalize(const double* partials, SegList segs, double* out, hipStrea
     k_finalize<<<1, kBlock, 0, st>>>(partials, segs, out);
 }
 
+// ----------------------------------------------------------------------------------------------
+// batched kernels: one launch covers the same step of many independent instances.  A block
+// finds its instance by binary search over the segment table (block-uniform, so scalar loads)
+// and then runs the plain kernel's body with its block index inside the instance.
+// ----------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ const BSeg& seg_of(const BSeg* __restrict__ segs, int nseg, unsigned& lb) {
+    const unsigned b = blockIdx.x;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].blk0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    lb = b - segs[lo].blk0;
+    return segs[lo];
+}
+
+template <class T, int V>
+__global__ void kb_rbgs(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active, int colour) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L;
+    body_rbgs_split<T, V>((T*)s.a[0], (const T*)s.a[1], L, (T)(s.h * s.h), colour, lb);
+}
+
+template <class T>
+__global__ void kb_resid_restrict(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L, C = s.C;
+    const ParentMap pm = s.pm;
+    const unsigned t = lb * blockDim.x + threadIdx.x;
+    if (t < (unsigned)C.d.cells())
+        cell_resid_restrict<T, false>((const T*)s.a[0], (const T*)s.a[1], nullptr, L, (T)(s.h * s.h), (T*)s.a[2],
+                                      (T*)s.a[3], (T*)s.a[4], pm, C, t);
+}
+
+template <class T>
+__global__ void kb_fas(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay C = s.C;
+    const ParentMap pm = s.pm;
+    const unsigned t = lb * blockDim.x + threadIdx.x;
+    if (t < (unsigned)C.d.cells()) cell_fas<T>((const T*)s.a[0], (T*)s.a[1], pm, C, (T)(s.h * s.h), t);
+}
+
+template <class T, bool BLACK>
+__global__ void kb_prolong(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L;
+    const ParentMap pm = s.pm;
+    const unsigned t = lb * blockDim.x + threadIdx.x;
+    if constexpr (BLACK) {
+        if (t < (unsigned)(L.d.cells() >> 1))
+            cell_prolong_black<T>((T*)s.a[0], L, (const T*)s.a[1], (const T*)s.a[2], pm, t);
+    } else {
+        if (t < (unsigned)L.d.cells()) cell_prolong<T>((T*)s.a[0], L, (const T*)s.a[1], (const T*)s.a[2], pm, t);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTailThreads) kb_tail(const TailPlan<T>* __restrict__ plans,
+                                                        const int* __restrict__ active) {
+    const TailPlan<T>& tp = plans[blockIdx.x];
+    if (!active[tp.inst]) return;
+    body_tail<T>(tp);
+}
+
+__global__ void kb_outer(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active, int has_e) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L;
+    const double acc = body_outer_split((const double*)s.a[0], has_e ? (const float*)s.a[1] : nullptr,
+                                        (const double*)s.a[2], (double*)s.a[3], (float*)s.a[4], (float*)s.a[5], L,
+                                        s.h * s.h, (float)(s.h * s.h), lb, s.nblk);
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) s.part[lb] = bs;
+}
+
+__global__ void kb_residual(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L;
+    const CovBox none{};
+    const double acc = body_residual_split<double, double>((const double*)s.a[0], (const double*)s.a[1], L,
+                                                           s.h * s.h, none, nullptr, lb, s.nblk);
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) s.part[lb] = bs;
+}
+
+__global__ void kb_sum(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active, int square) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L;
+    const CovBox none{};
+    const double bs = block_sum(body_sum((const double*)s.a[0], L, none, square, lb, s.nblk));
+    if (threadIdx.x == 0) s.part[lb] = bs;
+}
+
+__global__ void kb_finalize(const BFin* __restrict__ fins, const int* __restrict__ active) {
+    if (!active[blockIdx.x]) return;
+    const BFin& f = fins[blockIdx.x];
+    double total = 0.0;
+    body_finalize_seg(f.part, f.cnt, f.w, total);
+    if (threadIdx.x == 0) f.out[0] = total;
+}
+
+// grid-stride loops over one instance's cells with its own blocks
+__global__ void kb_sub_mean(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    double* a = (double*)s.a[0];
+    const double m = ((const double*)s.a[1])[0] * s.h;
+    const size_t n = s.L.d.cells();
+    for (size_t i = lb * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)s.nblk * blockDim.x) a[i] = a[i] - m;
+}
+
+__global__ void kb_relayout(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay ls = s.L, ld = s.C;
+    const double* src = (const double*)s.a[0];
+    double* dst = (double*)s.a[1];
+    const size_t n = ld.d.cells();
+    for (size_t i = lb * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)s.nblk * blockDim.x) {
+        int x, y, z;
+        ldecode(ld, i, x, y, z);
+        dst[i] = src[lidx(ls, x, y, z)];
+    }
+}
+
+template <class T>
+__global__ void kb_zero(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    T* p = (T*)s.a[0];
+    const size_t n = s.L.d.cells();
+    for (size_t i = lb * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)s.nblk * blockDim.x) p[i] = T(0);
+}
+
+template <class T>
+void launch_b_rbgs(const BSeg* segs, int nseg, unsigned grid, int block, int V, const int* active, int colour,
+                   hipStream_t st) {
+    switch (V) {
+        case 1: kb_rbgs<T, 1><<<grid, block, 0, st>>>(segs, nseg, active, colour); break;
+        case 2: kb_rbgs<T, 2><<<grid, block, 0, st>>>(segs, nseg, active, colour); break;
+        default: kb_rbgs<T, 4><<<grid, block, 0, st>>>(segs, nseg, active, colour); break;
+    }
+}
+template <class T>
+void launch_b_resid_restrict(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_resid_restrict<T><<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+template <class T>
+void launch_b_fas(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_fas<T><<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+template <class T>
+void launch_b_prolong(const BSeg* segs, int nseg, unsigned grid, const int* active, int black_only, hipStream_t st) {
+    if (black_only) kb_prolong<T, true><<<grid, kBlock, 0, st>>>(segs, nseg, active);
+    else kb_prolong<T, false><<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+void batch_kernel_setup() {
+    static bool done = false;
+    if (done) return;
+    hipFuncSetAttribute((const void*)kb_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+    hipFuncSetAttribute((const void*)kb_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+    done = true;
+}
+template <class T>
+void launch_b_tail(const TailPlan<T>* plans, int n, unsigned lds_bytes, const int* active, hipStream_t st) {
+    kb_tail<T><<<n, kTailThreads, lds_bytes, st>>>(plans, active);
+}
+void launch_b_outer(const BSeg* segs, int nseg, unsigned grid, const int* active, int has_e, hipStream_t st) {
+    kb_outer<<<grid, kBlock, 0, st>>>(segs, nseg, active, has_e);
+}
+void launch_b_residual(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_residual<<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+void launch_b_sum(const BSeg* segs, int nseg, unsigned grid, const int* active, int square, hipStream_t st) {
+    kb_sum<<<grid, kBlock, 0, st>>>(segs, nseg, active, square);
+}
+void launch_b_finalize(const BFin* fins, int n, const int* active, hipStream_t st) {
+    kb_finalize<<<n, kBlock, 0, st>>>(fins, active);
+}
+void launch_b_sub_mean(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_sub_mean<<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+void launch_b_relayout(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_relayout<<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+template <class T>
+void launch_b_zero(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_zero<T><<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+
 // explicit instantiations
 template void launch_fill<double>(double*, size_t, double, hipStream_t);
 template void launch_fill<float>(float*, size_t, float, hipStream_t);
@@ -800,6 +1051,16 @@ template void launch_sub_mean<double>(double*, size_t, const double*, double, hi
 MGIC_INST(double)
 MGIC_INST(float)
 #undef MGIC_INST
+#define MGIC_BINST(T)                                                                                         \
+    template void launch_b_rbgs<T>(const BSeg*, int, unsigned, int, int, const int*, int, hipStream_t);         \
+    template void launch_b_resid_restrict<T>(const BSeg*, int, unsigned, const int*, hipStream_t);             \
+    template void launch_b_fas<T>(const BSeg*, int, unsigned, const int*, hipStream_t);                        \
+    template void launch_b_prolong<T>(const BSeg*, int, unsigned, const int*, int, hipStream_t);               \
+    template void launch_b_tail<T>(const TailPlan<T>*, int, unsigned, const int*, hipStream_t);                \
+    template void launch_b_zero<T>(const BSeg*, int, unsigned, const int*, hipStream_t);
+MGIC_BINST(double)
+MGIC_BINST(float)
+#undef MGIC_BINST
 template void launch_residual<double, double>(const double*, const double*, const double*, Lay, double, CovBox,
                                               double*, Lay, double*, int*, hipStream_t);
 template void launch_residual<double, float>(const double*, const double*, const double*, Lay, double, CovBox,

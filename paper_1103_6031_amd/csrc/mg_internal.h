@@ -115,6 +115,7 @@ struct TailLevel {
 template <class T>
 struct TailPlan {
     int n, nu1, nu2;
+    int inst;                       // batched launches: the instance (index of its active flag)
     unsigned lds_bytes;             // total LDS, including the coarsest solver's 2 x 343 doubles
     TailLevel<T> lev[kTailMaxLevels];
 };
@@ -208,11 +209,67 @@ void launch_grad4(const double* src, int R, Dims d, double h, double scale, doub
 // for 3 arrays of (d + 2(R-2))^3 (d^3 when periodic)
 void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st);
 
+// ----------------------------------------------------------------------------------------------
+// batched launches: many independent periodic instances in one grid
+// ----------------------------------------------------------------------------------------------
+// One instance's share of a batched launch: blocks [blk0, blk0 + nblk) of the grid do exactly
+// what a plain launch of nblk blocks does on that instance alone (same cells per block, same
+// reduction striding), so every instance gets the bits of its own solo solve.
+struct BSeg {
+    int inst;           // instance: index of its active flag
+    unsigned blk0;      // first block of the segment
+    unsigned nblk;      // blocks of the segment
+    Lay L;              // the instance's level
+    Lay C;              // transfers: the covered coarse box, natural order; relayout: destination
+    ParentMap pm;       // transfers: the coarse representation inside the parent
+    double h;           // level spacing (FAS right-hand side: the parent's; mean removal: 1/cells)
+    void* a[6];         // arrays, listed per batched kernel
+    double* part;       // reductions: nblk partial sums of this instance
+};
+// per-instance finalize of a batched reduction: *out = w * sum(part[0..cnt)), one block each
+struct BFin {
+    const double* part;
+    int cnt;
+    double w;
+    double* out;
+};
+
 inline int grid_for(size_t n, int per_block = kBlock, int cap = 1 << 30) {
     size_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
     if (g > (size_t)cap) g = cap;
     return (int)g;
 }
+
+// batched launchers; `active` (device, one int per instance) skips finished instances.
+// rbgs: a = {u, f}, colour as given; block threads, V cells per thread
+template <class T> void launch_b_rbgs(const BSeg* segs, int nseg, unsigned grid, int block, int V, const int* active,
+                                      int colour, hipStream_t st);
+// a = {u, f, pu, pf, uold}: residual + restriction (steps 3-5)
+template <class T> void launch_b_resid_restrict(const BSeg* segs, int nseg, unsigned grid, const int* active,
+                                                hipStream_t st);
+// a = {pu, pf}: FAS right-hand side (step 6), h = the parent's spacing
+template <class T> void launch_b_fas(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
+// a = {u, pu, uold}: step 8 (black cells only if black_only)
+template <class T> void launch_b_prolong(const BSeg* segs, int nseg, unsigned grid, const int* active,
+                                         int black_only, hipStream_t st);
+// sets the batched kernels' function attributes (LDS size); call before any graph capture
+void batch_kernel_setup();
+// the single-workgroup tails of n instances, one workgroup each
+template <class T> void launch_b_tail(const TailPlan<T>* plans, int n, unsigned lds_bytes, const int* active,
+                                      hipStream_t st);
+// a = {u_in, e_in, f, u_out, rhs, e_out}: fused mixed-precision outer step (e_in unused if !has_e)
+void launch_b_outer(const BSeg* segs, int nseg, unsigned grid, const int* active, int has_e, hipStream_t st);
+// a = {u, f}: FP64 residual partial sums
+void launch_b_residual(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
+// a = {v}: partial sums of v (square: of v^2)
+void launch_b_sum(const BSeg* segs, int nseg, unsigned grid, const int* active, int square, hipStream_t st);
+void launch_b_finalize(const BFin* fins, int n, const int* active, hipStream_t st);
+// a = {v, sum}: v -= sum * h  (h holds 1 / cells)
+void launch_b_sub_mean(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
+// a = {src, dst}: dst (layout C) = src (layout L)
+void launch_b_relayout(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
+// a = {p}: p = 0 over L's cells
+template <class T> void launch_b_zero(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
 
 }  // namespace mgic

@@ -8,8 +8,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -619,6 +622,753 @@ static int lpt_common(const mg_hier* H, int what, const double* const* phi, void
     return MG_OK;
 }
 
+// ----------------------------------------------------------------------------------------------
+// batched periodic solves
+//
+// Every instance keeps its own plan and workspace slice, exactly as a solo mg_solve_level would
+// carve it.  The V-cycles of all instances run together: depth d of the schedule is level d of
+// every instance whose single-workgroup tail starts below d, so one launch per step and depth
+// covers them all; the tails of all instances are one launch of one workgroup each.  Each
+// instance sees the same operations in the same order as its solo solve, and every batched
+// kernel gives a block the same cells (and reduction striding) it has in a solo launch, so the
+// results are bit-identical to mg_solve_level.  The fixed launch sequences are captured once as
+// HIP graphs per workspace and batch shape and replayed for every cycle; a device flag per
+// instance retires converged instances without changing the graphs.
+// ----------------------------------------------------------------------------------------------
+
+struct BLaunch {
+    int off = 0, n = 0;      // segments [off, off + n) of the table
+    unsigned grid = 0;       // blocks (sum of the segments' nblk)
+    int block = kBlock, V = 1;
+};
+
+struct SmoothShape {
+    int block = kBlock, V = 1;
+};
+
+enum { F_FSUM = 0, F_FNORM = 1, F_RNORM = 2, F_USUM = 3, F_COUNT = 4 };
+
+struct BatchPlan {
+    std::vector<int> ids;        // caller's index of each batched instance
+    std::vector<Plan> P;
+    int D = 0;                   // depths of grid levels (above every instance's tail)
+    bool mixed = false;
+    // static tables: [0] float, [1] double; float tables by parity of the finest correction buffer
+    std::vector<BSeg> segs;
+    std::vector<BLaunch> sm[2][2], rr[2][2], fas[2][2], pr[2][2];
+    BLaunch outer[2], resid, sumf;
+    std::vector<TailPlan<float>> tpf;
+    std::vector<TailPlan<double>> tpd;
+    unsigned lds_f = 0, lds_d = 0;
+    std::vector<BFin> fins;      // F_COUNT tables of n entries
+    // device side (in the workspace)
+    BSeg* segs_dev = nullptr;
+    size_t segs_cap = 0;         // table capacity (segments)
+    TailPlan<float>* tpf_dev = nullptr;
+    TailPlan<double>* tpd_dev = nullptr;
+    BFin* fins_dev = nullptr;
+    int* active_dev = nullptr;
+    double* bscal = nullptr;     // n * S_COUNT scalars
+    // ping-pong buffers of the finest level: A = the plan's u / u32, B = ualt / ealt
+    std::vector<double*> Au, Bu;
+    std::vector<float*> Ae, Be;
+};
+
+static bool batchable(int n) { return n % 2 == 0 && (size_t)n * n * n > kTailMaxCells; }
+
+static BLaunch add_launch(std::vector<BSeg>& tab, std::vector<BSeg> segs, int block = kBlock, int V = 1) {
+    BLaunch L;
+    L.off = (int)tab.size();
+    L.n = (int)segs.size();
+    L.block = block;
+    L.V = V;
+    unsigned b = 0;
+    for (auto& s : segs) {
+        s.blk0 = b;
+        b += s.nblk;
+        tab.push_back(s);
+    }
+    L.grid = b;
+    return L;
+}
+
+static unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+static unsigned red_blocks(size_t cells) { return (unsigned)grid_for(cells, kBlock * kRedV, kMaxPartials); }
+
+static BSeg seg0(int inst, unsigned nblk) {
+    BSeg s{};
+    s.inst = inst;
+    s.nblk = nblk;
+    s.L = Lay(Dims{1, 1, 1}, 0);
+    s.C = Lay(Dims{1, 1, 1}, 0);
+    return s;
+}
+
+template <class T> static T* ubuf(Level& L);
+template <> double* ubuf<double>(Level& L) { return L.u; }
+template <> float* ubuf<float>(Level& L) { return L.u32; }
+
+// the V-cycle tables of precision T (ti = 0 float, 1 double); fine_u replaces level 0's u
+template <class T>
+static void vcycle_tables(BatchPlan& B, int ti, int par, const std::vector<T*>& fine_u,
+                          const std::vector<SmoothShape>& shape) {
+    auto& tab = B.segs;
+    const int n = (int)B.P.size();
+    B.sm[ti][par].assign(B.D, BLaunch{});
+    B.rr[ti][par].assign(B.D, BLaunch{});
+    B.fas[ti][par].assign(B.D, BLaunch{});
+    B.pr[ti][par].assign(B.D, BLaunch{});
+    for (int d = 0; d < B.D; ++d) {
+        std::vector<BSeg> sm, rr, fa, pr;
+        const SmoothShape sh = shape[d];
+        for (int i = 0; i < n; ++i) {
+            Plan& P = B.P[i];
+            if (d >= P.tail) continue;
+            Level& L = P.L[d];
+            Level& Q = P.L[d + 1];
+            ::mgic::B<T> b = bufs<T>(L), q = bufs<T>(Q);
+            T* u = d == 0 ? fine_u[i] : b.u;
+            const size_t cells = L.d.cells();
+            const Lay C(Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, 0);
+            BSeg s = seg0(i, cdiv(cells / 2, (size_t)sh.block * sh.V));
+            s.L = L.lay;
+            s.h = L.h;
+            s.a[0] = u;
+            s.a[1] = b.f;
+            sm.push_back(s);
+            s = seg0(i, cdiv(C.d.cells(), kBlock));
+            s.L = L.lay;
+            s.C = C;
+            s.pm = L.pm;
+            s.h = L.h;
+            s.a[0] = u; s.a[1] = b.f; s.a[2] = q.u; s.a[3] = q.f; s.a[4] = b.uold;
+            rr.push_back(s);
+            s = seg0(i, cdiv(C.d.cells(), kBlock));
+            s.C = C;
+            s.pm = L.pm;
+            s.h = Q.h;
+            s.a[0] = q.u; s.a[1] = q.f;
+            fa.push_back(s);
+            s = seg0(i, cdiv(B.P[i].nu2 > 0 ? cells / 2 : cells, kBlock));
+            s.L = L.lay;
+            s.pm = L.pm;
+            s.a[0] = u; s.a[1] = q.u; s.a[2] = b.uold;
+            pr.push_back(s);
+        }
+        B.sm[ti][par][d] = add_launch(tab, sm, sh.block, sh.V);
+        B.rr[ti][par][d] = add_launch(tab, rr);
+        B.fas[ti][par][d] = add_launch(tab, fa);
+        B.pr[ti][par][d] = add_launch(tab, pr);
+    }
+}
+
+template <class T>
+static std::vector<TailPlan<T>> tail_plans(BatchPlan& B, unsigned& lds) {
+    std::vector<TailPlan<T>> v;
+    lds = 0;
+    for (int i = 0; i < (int)B.P.size(); ++i) {
+        Plan& P = B.P[i];
+        TailPlan<T> tp{};
+        tp.n = P.last - P.tail + 1;
+        tp.nu1 = P.nu1;
+        tp.nu2 = P.nu2;
+        tp.inst = i;
+        for (int k = 0; k < tp.n; ++k) {
+            ::mgic::B<T> c = bufs<T>(P.L[P.tail + k]);
+            tp.lev[k] = TailLevel<T>{c.u, c.f, P.L[P.tail + k].lay, P.L[P.tail + k].h, 0, 0, 0};
+        }
+        lds = std::max(lds, tail_assign_lds(tp));
+        v.push_back(tp);
+    }
+    return v;
+}
+
+// size of the batch region after the instance slices (segment capacity for the static tables
+// plus the per-call ones)
+static size_t batch_segs_cap(const BatchPlan& B) {
+    return (size_t)(12 * B.D + 12) * B.P.size() + 16;
+}
+
+// build plans (cv == null: sizes only); returns bytes of the whole workspace or 0 on error
+static size_t batch_layout(int ninst, const int* n, const double* h, const mg_opts* o, char* ws, BatchPlan& B,
+                           std::vector<size_t>& slice, std::vector<size_t>& slice_bytes) {
+    size_t off = 0;
+    slice.assign(ninst, 0);
+    slice_bytes.assign(ninst, 0);
+    B.ids.clear();
+    B.P.clear();
+    B.mixed = o && o->prec == MG_MIXED;
+    for (int i = 0; i < ninst; ++i) {
+        mg_hier H = single_level(n[i], h ? h[i] : 1.0);
+        Plan P;
+        Carver cv(nullptr);
+        if (build_plan(&H, o, cv, nullptr, P)) return 0;
+        slice[i] = off;
+        slice_bytes[i] = (cv.off + 255) & ~(size_t)255;
+        off += slice_bytes[i];
+        if (batchable(n[i])) {
+            Plan Q;
+            Carver c2(ws ? ws + slice[i] : nullptr);
+            build_plan(&H, o, c2, nullptr, Q);
+            B.ids.push_back(i);
+            B.P.push_back(Q);
+        }
+    }
+    B.D = 0;
+    for (auto& P : B.P) B.D = std::max(B.D, P.tail);
+    B.segs_cap = batch_segs_cap(B);
+    const size_t ni = B.P.size();
+    Carver cv(ws ? ws + off : nullptr);
+    B.segs_dev = cv.take<BSeg>(B.segs_cap);
+    B.tpf_dev = cv.take<TailPlan<float>>(ni);
+    B.tpd_dev = cv.take<TailPlan<double>>(ni);
+    B.fins_dev = cv.take<BFin>(F_COUNT * ni);
+    B.active_dev = cv.take<int>(ni + 1);
+    B.bscal = cv.take<double>((ni + 1) * S_COUNT);
+    return off + cv.off;
+}
+
+// ---- autotuning of the batched smoother: block size and cells per thread, per depth ----------
+static std::mutex g_tune_mu;
+static std::map<std::string, std::vector<SmoothShape>> g_tune;
+
+static std::string batch_key(const BatchPlan& B, int ti) {
+    std::string k = std::to_string(ti) + ":" + std::to_string(B.P.empty() ? 0 : B.P[0].nu1) + ":";
+    for (auto& P : B.P) k += std::to_string(P.L[0].d.x) + ",";
+    return k;
+}
+
+static const SmoothShape kShapes[] = {{256, 1}, {256, 2}, {256, 4}, {128, 2}, {128, 4}, {512, 1}, {512, 2}};
+
+template <class T>
+static int tune_smoother(BatchPlan& B, int ti, hipStream_t st, std::vector<SmoothShape>& out) {
+    const std::string key = batch_key(B, ti);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            out = it->second;
+            return MG_OK;
+        }
+    }
+    out.assign(B.D, SmoothShape{});
+    const int n = (int)B.P.size();
+    std::vector<int> ones(n + 1, 1);
+    MG_HIP(hipMemcpyAsync(B.active_dev, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    hipEvent_t e0, e1;
+    MG_HIP(hipEventCreate(&e0));
+    MG_HIP(hipEventCreate(&e1));
+    for (int d = 0; d < B.D; ++d) {
+        float best = 1e30f;
+        for (const SmoothShape& sh : kShapes) {
+            std::vector<BSeg> tab, segs;
+            for (int i = 0; i < n; ++i) {
+                Plan& P = B.P[i];
+                if (d >= P.tail) continue;
+                Level& L = P.L[d];
+                BSeg s = seg0(i, cdiv(L.d.cells() / 2, (size_t)sh.block * sh.V));
+                s.L = L.lay;
+                s.h = L.h;
+                s.a[0] = ubuf<T>(L);
+                s.a[1] = bufs<T>(L).f;
+                segs.push_back(s);
+            }
+            BLaunch la = add_launch(tab, segs, sh.block, sh.V);
+            MG_HIP(hipMemcpyAsync(B.segs_dev, tab.data(), tab.size() * sizeof(BSeg), hipMemcpyHostToDevice, st));
+            for (int r = 0; r < 2; ++r)
+                launch_b_rbgs<T>(B.segs_dev, la.n, la.grid, la.block, la.V, B.active_dev, r & 1, st);
+            MG_HIP(hipEventRecord(e0, st));
+            const int reps = 6;
+            for (int r = 0; r < reps; ++r)
+                launch_b_rbgs<T>(B.segs_dev, la.n, la.grid, la.block, la.V, B.active_dev, r & 1, st);
+            MG_HIP(hipEventRecord(e1, st));
+            MG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                out[d] = sh;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    MG_HIP(hipGetLastError());
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = out;
+    return MG_OK;
+}
+
+// ---- graphs ------------------------------------------------------------------------------------
+// Instantiated graphs live until the thread ends; they are deliberately not destroyed at exit,
+// when the HIP runtime may already be gone.
+struct GraphCache {
+    std::map<std::string, hipGraphExec_t> exec;
+    hipStream_t cap = nullptr;  // capture stream (capture is illegal on the null stream)
+};
+static thread_local GraphCache g_graphs;
+
+// runs `body` on st, or replays its graph (captured on first use under `key`)
+template <class F>
+static int run_graph(bool use_graph, const std::string& key, hipStream_t st, F body) {
+    if (!use_graph) {
+        body(st);
+        MG_HIP(hipGetLastError());
+        return MG_OK;
+    }
+    auto it = g_graphs.exec.find(key);
+    if (it == g_graphs.exec.end()) {
+        if (!g_graphs.cap) MG_HIP(hipStreamCreateWithFlags(&g_graphs.cap, hipStreamNonBlocking));
+        if (g_graphs.exec.size() >= 256) {
+            for (auto& kv : g_graphs.exec) (void)hipGraphExecDestroy(kv.second);
+            g_graphs.exec.clear();
+        }
+        MG_HIP(hipStreamBeginCapture(g_graphs.cap, hipStreamCaptureModeThreadLocal));
+        body(g_graphs.cap);
+        hipGraph_t g = nullptr;
+        MG_HIP(hipStreamEndCapture(g_graphs.cap, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        MG_HIP(e);
+        it = g_graphs.exec.emplace(key, ex).first;
+    }
+    MG_HIP(hipGraphLaunch(it->second, st));
+    return MG_OK;
+}
+
+// pinned host mirror of the batch scalars and flags; reallocation drops the cached graphs that
+// copy into it
+static thread_local double* g_bpin = nullptr;
+static thread_local size_t g_bpin_n = 0;
+static double* batch_pinned(size_t n) {
+    if (n <= g_bpin_n) return g_bpin;
+    for (auto& kv : g_graphs.exec) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.exec.clear();
+    if (g_bpin) (void)hipHostFree(g_bpin);
+    g_bpin = nullptr;
+    g_bpin_n = 0;
+    size_t cap = 1024;
+    while (cap < n) cap *= 2;
+    if (hipHostMalloc((void**)&g_bpin, cap * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
+    g_bpin_n = cap;
+    return g_bpin;
+}
+
+// one batched V-cycle of precision T (ti: 0 float, 1 double) with the tables of parity par
+template <class T>
+static void b_vcycle(BatchPlan& B, int ti, int par, bool skip_first_red, hipStream_t st) {
+    const int* act = B.active_dev;
+    BSeg* sd = B.segs_dev;
+    for (int d = 0; d < B.D; ++d) {
+        const BLaunch& sm = B.sm[ti][par][d];
+        for (int s = 0; s < B.P[0].nu1; ++s)
+            for (int c = 0; c < 2; ++c) {
+                if (skip_first_red && d == 0 && s == 0 && c == 0) continue;
+                if (sm.n) launch_b_rbgs<T>(sd + sm.off, sm.n, sm.grid, sm.block, sm.V, act, c, st);
+            }
+        const BLaunch& rr = B.rr[ti][par][d];
+        if (rr.n) launch_b_resid_restrict<T>(sd + rr.off, rr.n, rr.grid, act, st);
+        const BLaunch& fa = B.fas[ti][par][d];
+        if (fa.n) launch_b_fas<T>(sd + fa.off, fa.n, fa.grid, act, st);
+    }
+    if (ti == 0) launch_b_tail<float>(B.tpf_dev, (int)B.P.size(), B.lds_f, act, st);
+    else launch_b_tail<double>(B.tpd_dev, (int)B.P.size(), B.lds_d, act, st);
+    for (int d = B.D - 1; d >= 0; --d) {
+        const BLaunch& pr = B.pr[ti][par][d];
+        if (pr.n) launch_b_prolong<T>(sd + pr.off, pr.n, pr.grid, act, B.P[0].nu2 > 0, st);
+        const BLaunch& sm = B.sm[ti][par][d];
+        for (int s = 0; s < B.P[0].nu2; ++s)
+            for (int c = 0; c < 2; ++c)
+                if (sm.n) launch_b_rbgs<T>(sd + sm.off, sm.n, sm.grid, sm.block, sm.V, act, c, st);
+    }
+}
+
+struct InstState {
+    int cycles = 0, status = 1 /* running */, grow = 0, par = 0;
+    double rel = NAN, prev = INFINITY, fnorm2 = 0;
+    bool active = true;
+    bool early = false;   // stopped before the first cycle (non-finite source): u is not written
+};
+
+static int solve_batch(int ninst, const int* n, const double* h, const double* const* f, double* const* u,
+                       const mg_opts* o, mg_stats* stats, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (ninst < 1 || !n || !h || !f || !u || !o) return fail(MG_EINVAL, "NULL argument");
+    if (o->max_cycles < 0) return fail(MG_EINVAL, "max_cycles < 0");
+    if (o->prec != MG_FP64 && o->prec != MG_MIXED) return fail(MG_EINVAL, "unknown precision");
+    if (o->inner < 0 || o->inner > 16) return fail(MG_EINVAL, "inner cycles out of range (0..16)");
+    for (int i = 0; i < ninst; ++i)
+        if (!f[i] || !u[i]) return fail(MG_EINVAL, "instance pointer is NULL");
+    BatchPlan B;
+    std::vector<size_t> slice, sbytes;
+    const size_t need = batch_layout(ninst, n, h, o, nullptr, B, slice, sbytes);
+    if (!need) return MG_EINVAL;   // build_plan reported the reason
+    if (!ws || ws_bytes < need) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(need));
+    if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    batch_layout(ninst, n, h, o, (char*)ws, B, slice, sbytes);
+    (void)hipGetLastError();
+    int worst = MG_OK;
+    // instances outside the batched schedule (tiny or odd grids) are solved on their own
+    std::vector<char> in_batch(ninst, 0);
+    for (int i : B.ids) in_batch[i] = 1;
+    for (int i = 0; i < ninst; ++i) {
+        if (in_batch[i]) continue;
+        mg_hier H = single_level(n[i], h[i]);
+        const double* fp[1] = {f[i]};
+        double* up[1] = {u[i]};
+        const int rc = solve(&H, fp, up, o, stats ? stats + i : nullptr, (char*)ws + slice[i], sbytes[i], st);
+        if (rc == MG_EINVAL || rc == MG_EHIP) return rc;
+        if (rc && !worst) worst = rc;
+    }
+    const int ni = (int)B.P.size();
+    if (!ni) return worst;
+    const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
+    const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
+    const bool use_graph = (o->flags & MG_NO_GRAPH) == 0;
+    const int inner = o->inner > 0 ? o->inner : 2;
+    B.mixed = o->prec == MG_MIXED;
+    batch_kernel_setup();   // function attributes must be set outside any graph capture
+    for (int i = 0; i < ni; ++i) {
+        Level& L = B.P[i].L[0];
+        B.Au.push_back(L.u);
+        B.Bu.push_back(L.ualt);
+        B.Ae.push_back(L.u32);
+        B.Be.push_back(L.ealt);
+    }
+    // autotuned smoother shapes (timed on the workspace before anything in it matters)
+    std::vector<SmoothShape> shf, shd;
+    int rc;
+    if (B.mixed) {
+        if ((rc = tune_smoother<float>(B, 0, st, shf))) return rc;
+    } else {
+        if ((rc = tune_smoother<double>(B, 1, st, shd))) return rc;
+    }
+    // static tables
+    B.segs.clear();
+    if (B.mixed) {
+        vcycle_tables<float>(B, 0, 0, B.Be, shf);   // after an even outer step e lives in B
+        vcycle_tables<float>(B, 0, 1, B.Ae, shf);
+        B.tpf = tail_plans<float>(B, B.lds_f);
+        for (int par = 0; par < 2; ++par) {
+            std::vector<BSeg> v;
+            for (int i = 0; i < ni; ++i) {
+                Level& L = B.P[i].L[0];
+                BSeg s = seg0(i, red_blocks(L.d.cells()));
+                s.L = L.lay;
+                s.h = L.h;
+                s.part = B.P[i].partials;
+                s.a[0] = par ? B.Bu[i] : B.Au[i];
+                s.a[1] = par ? B.Be[i] : B.Ae[i];
+                s.a[2] = L.f;
+                s.a[3] = par ? B.Au[i] : B.Bu[i];
+                s.a[4] = L.f32;
+                s.a[5] = par ? B.Ae[i] : B.Be[i];
+                v.push_back(s);
+            }
+            B.outer[par] = add_launch(B.segs, v);
+        }
+    } else {
+        std::vector<double*> fu(ni);
+        for (int i = 0; i < ni; ++i) fu[i] = B.Au[i];
+        vcycle_tables<double>(B, 1, 0, fu, shd);
+        B.tpd = tail_plans<double>(B, B.lds_d);
+        std::vector<BSeg> v;
+        for (int i = 0; i < ni; ++i) {
+            Level& L = B.P[i].L[0];
+            BSeg s = seg0(i, red_blocks(L.d.cells()));
+            s.L = L.lay;
+            s.h = L.h;
+            s.part = B.P[i].partials;
+            s.a[0] = L.u;
+            s.a[1] = L.f;
+            v.push_back(s);
+        }
+        B.resid = add_launch(B.segs, v);
+    }
+    {
+        std::vector<BSeg> v;
+        for (int i = 0; i < ni; ++i) {
+            Level& L = B.P[i].L[0];
+            BSeg s = seg0(i, red_blocks(L.d.cells()));
+            s.L = L.lay;
+            s.part = B.P[i].partials;
+            s.a[0] = L.f;
+            v.push_back(s);
+        }
+        B.sumf = add_launch(B.segs, v);
+    }
+    B.fins.assign((size_t)F_COUNT * ni, BFin{});
+    for (int i = 0; i < ni; ++i) {
+        Level& L = B.P[i].L[0];
+        const double h3 = L.h * L.h * L.h;
+        const int cnt = (int)red_blocks(L.d.cells());
+        double* sc = B.bscal + (size_t)i * S_COUNT;
+        B.fins[F_FSUM * ni + i] = BFin{B.P[i].partials, cnt, 1.0, sc + S_FSUM};
+        B.fins[F_FNORM * ni + i] = BFin{B.P[i].partials, cnt, h3, sc + S_FNORM};
+        B.fins[F_RNORM * ni + i] = BFin{B.P[i].partials, cnt, h3, sc + S_RNORM};
+        B.fins[F_USUM * ni + i] = BFin{B.P[i].partials, cnt, 1.0, sc + S_USUM};
+    }
+    // per-call tables: input and output conversions, initial guess, gauge (user pointers)
+    std::vector<BSeg> fin_rel, sub_f, uinit;
+    for (int i = 0; i < ni; ++i) {
+        Level& L = B.P[i].L[0];
+        const int id = B.ids[i];
+        const size_t cells = L.d.cells();
+        BSeg s = seg0(i, (unsigned)grid_for(cells, kBlock, 8192));
+        s.L = Lay(L.d, 0);
+        s.C = L.lay;
+        s.a[0] = (void*)f[id];
+        s.a[1] = L.f;
+        fin_rel.push_back(s);
+        s = seg0(i, (unsigned)grid_for(cells, kBlock, 4096));
+        s.L = L.lay;
+        s.h = 1.0 / (double)cells;
+        s.a[0] = L.f;
+        s.a[1] = B.bscal + (size_t)i * S_COUNT + S_FSUM;
+        sub_f.push_back(s);
+        if (guess) {
+            s = seg0(i, (unsigned)grid_for(cells, kBlock, 8192));
+            s.L = Lay(L.d, 0);
+            s.C = L.lay;
+            s.a[0] = u[id];
+            s.a[1] = B.Au[i];
+        } else {
+            s = seg0(i, (unsigned)grid_for(cells, kBlock, 4096));
+            s.L = L.lay;
+            s.a[0] = B.Au[i];
+        }
+        uinit.push_back(s);
+    }
+    const BLaunch la_frel = add_launch(B.segs, fin_rel);
+    const BLaunch la_subf = add_launch(B.segs, sub_f);
+    const BLaunch la_uinit = add_launch(B.segs, uinit);
+    const size_t out_off = B.segs.size();   // output tables are filled in at the end
+    if (out_off + 3 * (size_t)ni > B.segs_cap) return fail(MG_EINVAL, "internal: batch table overflow");
+
+    double* pin = batch_pinned((size_t)(ni + 1) * S_COUNT + ni + 1);
+    if (!pin) return fail(MG_EHIP, "pinned host buffer unavailable");
+    int* pflags = (int*)(pin + (size_t)(ni + 1) * S_COUNT);
+    MG_HIP(hipMemcpyAsync(B.segs_dev, B.segs.data(), B.segs.size() * sizeof(BSeg), hipMemcpyHostToDevice, st));
+    if (!B.tpf.empty())
+        MG_HIP(hipMemcpyAsync(B.tpf_dev, B.tpf.data(), B.tpf.size() * sizeof(TailPlan<float>), hipMemcpyHostToDevice, st));
+    if (!B.tpd.empty())
+        MG_HIP(hipMemcpyAsync(B.tpd_dev, B.tpd.data(), B.tpd.size() * sizeof(TailPlan<double>), hipMemcpyHostToDevice, st));
+    MG_HIP(hipMemcpyAsync(B.fins_dev, B.fins.data(), B.fins.size() * sizeof(BFin), hipMemcpyHostToDevice, st));
+    std::vector<InstState> S(ni);
+    std::vector<int> sent(ni, -1);
+    // device flags follow S[i].active; the pinned source is rewritten only after the stream has
+    // drained, since an earlier upload may still be reading it
+    auto upload_flags = [&]() -> int {
+        bool same = true;
+        for (int i = 0; i < ni; ++i) same = same && sent[i] == (S[i].active ? 1 : 0);
+        if (same) return MG_OK;
+        MG_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < ni; ++i) pflags[i] = sent[i] = S[i].active ? 1 : 0;
+        MG_HIP(hipMemcpyAsync(B.active_dev, pflags, ni * sizeof(int), hipMemcpyHostToDevice, st));
+        return MG_OK;
+    };
+    if ((rc = upload_flags())) return rc;
+    BSeg* sd = B.segs_dev;
+    const int* act = B.active_dev;
+    const size_t nscal = (size_t)ni * S_COUNT;
+
+    // source preparation (a1): working copy, mean, mean removal, norm
+    launch_b_relayout(sd + la_frel.off, la_frel.n, la_frel.grid, act, st);
+    launch_b_sum(sd + B.sumf.off, B.sumf.n, B.sumf.grid, act, 0, st);
+    launch_b_finalize(B.fins_dev + F_FSUM * ni, ni, act, st);
+    launch_b_sub_mean(sd + la_subf.off, la_subf.n, la_subf.grid, act, st);
+    launch_b_sum(sd + B.sumf.off, B.sumf.n, B.sumf.grid, act, 1, st);
+    launch_b_finalize(B.fins_dev + F_FNORM * ni, ni, act, st);
+    if (guess) launch_b_relayout(sd + la_uinit.off, la_uinit.n, la_uinit.grid, act, st);
+    else launch_b_zero<double>(sd + la_uinit.off, la_uinit.n, la_uinit.grid, act, st);
+    MG_HIP(hipMemcpyAsync(pin, B.bscal, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
+    MG_HIP(hipStreamSynchronize(st));
+    std::vector<mg_stats> out(ni);
+    for (int i = 0; i < ni; ++i) {
+        std::memset(&out[i], 0, sizeof(mg_stats));
+        for (double& v : out[i].res_hist) v = NAN;
+        const double fsum = pin[(size_t)i * S_COUNT + S_FSUM], fn2 = pin[(size_t)i * S_COUNT + S_FNORM];
+        out[i].f_mean_removed = fixed ? 0.0 : fsum / (double)B.P[i].L[0].d.cells();
+        S[i].fnorm2 = fn2;
+        if (!fixed && (!std::isfinite(fn2) || !std::isfinite(fsum))) {
+            S[i].status = MG_EDIVERGED;
+            S[i].active = false;
+            S[i].early = true;
+        }
+    }
+    if ((rc = upload_flags())) return rc;
+
+    auto check = [&](int i, double r2) -> int {
+        InstState& s = S[i];
+        s.rel = s.fnorm2 > 0 ? std::sqrt(r2 / s.fnorm2) : 0.0;
+        if (s.cycles >= 1 && s.cycles <= 64) out[i].res_hist[s.cycles - 1] = s.rel;
+        if (!std::isfinite(s.rel)) return MG_EDIVERGED;
+        s.grow = s.rel > s.prev ? s.grow + 1 : 0;
+        s.prev = s.rel;
+        if (s.grow >= 3) return MG_EDIVERGED;
+        return s.rel <= o->tol ? MG_OK : 1;
+    };
+    auto any_active = [&]() {
+        for (auto& s : S)
+            if (s.active) return true;
+        return false;
+    };
+    // residual readback and convergence decisions of the active instances
+    auto decide = [&](int par) {
+        for (int i = 0; i < ni; ++i) {
+            if (!S[i].active) continue;
+            S[i].par = par;
+            if (!fixed) {
+                const int c = check(i, pin[(size_t)i * S_COUNT + S_RNORM]);
+                if (c != 1) {
+                    S[i].status = c;
+                    S[i].active = false;
+                    continue;
+                }
+            }
+            if (S[i].cycles >= o->max_cycles) {
+                S[i].status = fixed ? MG_OK : MG_ENOCONV;
+                S[i].active = false;
+            }
+        }
+    };
+    const std::string wkey = std::to_string((uintptr_t)ws) + "|" + batch_key(B, B.mixed ? 0 : 1) + "|" +
+                             std::to_string(o->nu2) + "|" + std::to_string(inner) + "|" +
+                             std::to_string(B.segs.size()) + "|" + (fixed ? "f" : "c");
+    if (B.mixed) {
+        bool first = true;
+        int par = 0;
+        while (any_active()) {
+            const std::string k = wkey + (first ? "|outer0" : (par ? "|outer1" : "|outer2"));
+            rc = run_graph(use_graph, k, st, [&](hipStream_t s) {
+                const BLaunch& ol = B.outer[par];
+                launch_b_outer(sd + ol.off, ol.n, ol.grid, act, first ? 0 : 1, s);
+                launch_b_finalize(B.fins_dev + F_RNORM * ni, ni, act, s);
+                (void)hipMemcpyAsync(pin, B.bscal, nscal * sizeof(double), hipMemcpyDeviceToHost, s);
+            });
+            if (rc) return rc;
+            if (!fixed) MG_HIP(hipStreamSynchronize(st));
+            decide(par);
+            if (!any_active()) break;
+            if ((rc = upload_flags())) return rc;
+            int cyc = 0;
+            for (auto& s : S)
+                if (s.active) cyc = s.cycles;
+            const int nin = std::min(inner, o->max_cycles - cyc);
+            rc = run_graph(use_graph && nin == inner, wkey + "|inner" + std::to_string(par), st, [&](hipStream_t s) {
+                for (int k = 0; k < nin; ++k) b_vcycle<float>(B, 0, par, k == 0, s);
+            });
+            if (rc) return rc;
+            for (int i = 0; i < ni; ++i)
+                if (S[i].active) {
+                    S[i].cycles += nin;
+                    out[i].cell_updates += (long long)nin * updates_per_cycle(B.P[i]);
+                }
+            first = false;
+            par ^= 1;
+        }
+    } else {
+        if (guess && !fixed) {
+            launch_b_residual(sd + B.resid.off, B.resid.n, B.resid.grid, act, st);
+            launch_b_finalize(B.fins_dev + F_RNORM * ni, ni, act, st);
+            MG_HIP(hipMemcpyAsync(pin, B.bscal, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
+            MG_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < ni; ++i)
+                if (S[i].active && check(i, pin[(size_t)i * S_COUNT + S_RNORM]) == MG_OK) {
+                    S[i].status = MG_OK;
+                    S[i].active = false;
+                }
+            if ((rc = upload_flags())) return rc;
+        }
+        for (int i = 0; i < ni; ++i)
+            if (S[i].active && S[i].cycles >= o->max_cycles) {
+                S[i].status = fixed ? MG_OK : MG_ENOCONV;
+                S[i].active = false;
+            }
+        if ((rc = upload_flags())) return rc;
+        while (any_active()) {
+            rc = run_graph(use_graph, wkey + "|cycle64", st, [&](hipStream_t s) {
+                b_vcycle<double>(B, 1, 0, false, s);
+                if (!fixed) {
+                    launch_b_residual(sd + B.resid.off, B.resid.n, B.resid.grid, act, s);
+                    launch_b_finalize(B.fins_dev + F_RNORM * ni, ni, act, s);
+                    (void)hipMemcpyAsync(pin, B.bscal, nscal * sizeof(double), hipMemcpyDeviceToHost, s);
+                }
+            });
+            if (rc) return rc;
+            if (!fixed) MG_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < ni; ++i)
+                if (S[i].active) {
+                    ++S[i].cycles;
+                    out[i].cell_updates += updates_per_cycle(B.P[i]);
+                }
+            decide(0);
+            if ((rc = upload_flags())) return rc;
+        }
+    }
+    // gauge (zero mean) and conversion back, for every instance that reached the loop
+    std::vector<BSeg> osum, osub, orel;
+    for (int i = 0; i < ni; ++i) {
+        S[i].active = !S[i].early;
+        Level& L = B.P[i].L[0];
+        double* uf = !B.mixed ? L.u : (S[i].par ? B.Au[i] : B.Bu[i]);
+        const size_t cells = L.d.cells();
+        BSeg s = seg0(i, red_blocks(cells));
+        s.L = L.lay;
+        s.part = B.P[i].partials;
+        s.a[0] = uf;
+        osum.push_back(s);
+        s = seg0(i, (unsigned)grid_for(cells, kBlock, 4096));
+        s.L = L.lay;
+        s.h = 1.0 / (double)cells;
+        s.a[0] = uf;
+        s.a[1] = B.bscal + (size_t)i * S_COUNT + S_USUM;
+        osub.push_back(s);
+        s = seg0(i, (unsigned)grid_for(cells, kBlock, 8192));
+        s.L = L.lay;
+        s.C = Lay(L.d, 0);
+        s.a[0] = uf;
+        s.a[1] = u[B.ids[i]];
+        orel.push_back(s);
+    }
+    std::vector<BSeg> tail_tab(B.segs.begin(), B.segs.begin() + out_off);
+    const BLaunch la_osum = add_launch(tail_tab, osum);
+    const BLaunch la_osub = add_launch(tail_tab, osub);
+    const BLaunch la_orel = add_launch(tail_tab, orel);
+    MG_HIP(hipMemcpyAsync(sd + out_off, tail_tab.data() + out_off, (tail_tab.size() - out_off) * sizeof(BSeg),
+                          hipMemcpyHostToDevice, st));
+    if ((rc = upload_flags())) return rc;
+    launch_b_sum(sd + la_osum.off, la_osum.n, la_osum.grid, act, 0, st);
+    launch_b_finalize(B.fins_dev + F_USUM * ni, ni, act, st);
+    launch_b_sub_mean(sd + la_osub.off, la_osub.n, la_osub.grid, act, st);
+    launch_b_relayout(sd + la_orel.off, la_orel.n, la_orel.grid, act, st);
+    MG_HIP(hipGetLastError());
+    MG_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < ni; ++i) {
+        out[i].cycles = S[i].cycles;
+        out[i].rel_res = S[i].rel;
+        if (stats) stats[B.ids[i]] = out[i];
+    }
+    // the first failure in instance order decides the return code
+    std::vector<int> code(ninst, MG_OK);
+    for (int i = 0; i < ni; ++i) code[B.ids[i]] = S[i].status;
+    for (int i = 0; i < ninst; ++i)
+        if (in_batch[i] && code[i] != MG_OK && !worst) worst = code[i];
+    if (worst == MG_ENOCONV) return fail(MG_ENOCONV, "an instance did not converge within max_cycles");
+    if (worst == MG_EDIVERGED) return fail(MG_EDIVERGED, "an instance diverged (NaN/Inf or growth)");
+    return worst;
+}
+
+static size_t batch_bytes(int ninst, const int* n, const mg_opts* o) {
+    if (ninst < 1 || !n) return 0;
+    BatchPlan B;
+    std::vector<double> h(ninst, 1.0);
+    std::vector<size_t> slice, sbytes;
+    mg_opts oo{};
+    if (o) oo = *o;
+    return batch_layout(ninst, n, h.data(), o ? &oo : nullptr, nullptr, B, slice, sbytes);
+}
+
 }  // namespace mgic
 
 // ==============================================================================================
@@ -775,32 +1525,12 @@ int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* ta
 }
 
 size_t mg_batch_workspace_bytes(int ninst, const int* n, const mg_opts* opts) {
-    if (ninst < 1 || !n) return 0;
-    size_t total = 0;
-    for (int i = 0; i < ninst; ++i) {
-        mg_hier H = single_level(n[i], 1.0);
-        size_t b = mg_workspace_bytes(&H, opts);
-        if (!b) return 0;
-        total += (b + 255) & ~(size_t)255;
-    }
-    return total;
+    return batch_bytes(ninst, n, opts);
 }
 
 int mg_solve_batch(int ninst, const int* n, const double* h, const double* const* f, double* const* u,
                    const mg_opts* opts, mg_stats* stats, void* workspace, size_t workspace_bytes, void* stream) {
-    if (ninst < 1 || !n || !h || !f || !u) return fail(MG_EINVAL, "NULL argument");
-    if (workspace_bytes < mg_batch_workspace_bytes(ninst, n, opts)) return fail(MG_EINVAL, "workspace too small");
-    char* w = (char*)workspace;
-    int worst = MG_OK;
-    for (int i = 0; i < ninst; ++i) {
-        mg_hier H = single_level(n[i], h[i]);
-        size_t b = (mg_workspace_bytes(&H, opts) + 255) & ~(size_t)255;
-        int rc = mg_solve_level(n[i], h[i], f[i], u[i], opts, stats ? stats + i : nullptr, w, b, stream);
-        if (rc == MG_EINVAL || rc == MG_EHIP) return rc;
-        if (rc && !worst) worst = rc;
-        w += b;
-    }
-    return worst;
+    return solve_batch(ninst, n, h, f, u, opts, stats, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 int mg_smooth_level(int n, double h, const double* f, double* u, int half_sweeps, int prec, void* workspace,

@@ -27,6 +27,7 @@ MG_OK, MG_EINVAL, MG_ENOCONV, MG_EDIVERGED, MG_EHIP = 0, -1, -2, -3, -4
 MG_FP64, MG_MIXED = 0, 1
 MG_USE_INITIAL_GUESS = 0x1
 MG_FIXED_CYCLES = 0x2
+MG_NO_GRAPH = 0x4
 
 _ERRNAMES = {MG_EINVAL: "MG_EINVAL", MG_ENOCONV: "MG_ENOCONV", MG_EDIVERGED: "MG_EDIVERGED", MG_EHIP: "MG_EHIP"}
 
@@ -137,7 +138,7 @@ class Hier:
 
 
 def make_opts(tol=1e-10, max_cycles=50, nu1=2, nu2=2, prec="fp64", fixed_cycles=False, initial_guess=False,
-              inner=0):
+              inner=0, graph=True):
     o = mg_opts()
     o.inner = inner
     o.tol = tol
@@ -145,7 +146,8 @@ def make_opts(tol=1e-10, max_cycles=50, nu1=2, nu2=2, prec="fp64", fixed_cycles=
     o.nu1 = nu1
     o.nu2 = nu2
     o.prec = {"fp64": MG_FP64, "mixed": MG_MIXED}[prec] if isinstance(prec, str) else int(prec)
-    o.flags = (MG_FIXED_CYCLES if fixed_cycles else 0) | (MG_USE_INITIAL_GUESS if initial_guess else 0)
+    o.flags = ((MG_FIXED_CYCLES if fixed_cycles else 0) | (MG_USE_INITIAL_GUESS if initial_guess else 0)
+               | (0 if graph else MG_NO_GRAPH))
     return o
 
 
