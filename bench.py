@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance leg")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests of the serving trace (Poisson, 20/s); 0 skips the serving leg")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed", help="headline path")
     ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 V-cycles per FP64 correction (0: library default)")
     ap.add_argument("--pmc-calib", action="store_true",
@@ -181,6 +183,13 @@ def main():
               "(multi-GPU sharding is described in DESIGN.md but not built); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    serve_host = None
+    if a.serve_requests > 0:
+        # the serving trace's densities are made by worker processes before this process
+        # touches the GPU
+        from paper_1103_6031_amd import serve
+        reqs = serve.trace(a.serve_requests, 20.0)
+        serve_host = serve.host_fields(reqs, workers=8)
     import numpy as np
     import torch
     from paper_1103_6031_amd import inputs, mgic as mg
@@ -232,6 +241,11 @@ def main():
         line["config"]["inner"] = a.inner
     if not a.no_batch:
         line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
+    if serve_host is not None:
+        summary, _, _ = serve.serve_trace(reqs, slots=4, budget_gb=16.0, prec="mixed", host=serve_host)
+        line["serving_c5"] = dict(workload="%d requests, Poisson 20/s, base {64,128,256}^3 with 0-3 patches of "
+                                           "{64,96,128}^3, 1LPT/2LPT 50/50, mixed, tol 1e-10" % len(reqs),
+                                  **summary)
     if a.pmc_calib:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)

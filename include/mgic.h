@@ -146,13 +146,23 @@ int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* ta
  * Batched independent periodic solves (many small instances in one persistent launch)
  * -------------------------------------------------------------------------------------------- */
 
-/* Workspace bytes for a batch of ninst periodic instances of sizes n[i]. */
+/* Workspace bytes for a batch of ninst periodic instances of sizes n[i] (exact; independent of
+ * the spacings). */
 size_t mg_batch_workspace_bytes(int ninst, const int* n, const mg_opts* opts);
 
 /* Solve ninst independent periodic problems (sizes n[i], spacings h[i], device pointers f[i],
- * u[i]; the pointer arrays themselves are host arrays).  Each instance is solved exactly as by
- * mg_solve_level with the same options; stats (host array of ninst, may be NULL) per instance.
- * All instances advance together, one cycle per persistent kernel launch. */
+ * u[i]; the pointer arrays themselves are host arrays).  Each instance's result, cycle count and
+ * residual history are bit-identical to mg_solve_level with the same options; stats (host array
+ * of ninst, may be NULL) per instance.  Instances with even n and n^3 > 16^3 share batched
+ * launches: one launch per V-cycle step and level depth for all of them, and one launch that
+ * runs the small-level tails of all of them (one workgroup each).  These launch sequences are
+ * captured as HIP graphs on first use for a workspace and batch shape and replayed every cycle
+ * (MG_NO_GRAPH: launched directly); converged instances are switched off by a device flag.
+ * Other instances are solved one by one in the same call.  The smoother's block size and cells
+ * per thread are chosen per level depth by timing candidates once per batch shape and process.
+ * Synchronises the stream at least once per FP64 correction (mixed) or cycle (FP64).
+ * Returns the first failure in instance order (MG_ENOCONV / MG_EDIVERGED; all instances are
+ * still solved and their stats filled), or MG_EINVAL / MG_EHIP. */
 int mg_solve_batch(int ninst, const int* n, const double* h, const double* const* f,
                    double* const* u, const mg_opts* opts, mg_stats* stats, void* workspace,
                    size_t workspace_bytes, void* stream);

@@ -1,0 +1,297 @@
+"""Continuous-batching request loop for initial-condition solves on one GPU.
+
+Requests arrive over time (Poisson arrivals in the synthetic trace), each asking for the
+displacement fields of one hierarchy: a periodic base N0^3 with 0-3 nested 2x patches, first
+order (solve + gradient) or second order (+ tau, second solve, gradient).  The server
+
+* admits a request as soon as a worker slot is free and its device-memory footprint (the
+  library's exact workspace sizes plus the request's input and output fields) fits in what is
+  left of the memory budget; admission is first come, first served;
+* runs each admitted request on its own HIP stream (one stream per slot, default priority), so
+  requests that arrive while others are running overlap with them on the device; the library's
+  entry points release the interpreter lock while they run;
+* frees the request's memory and slot on completion and records its latency (completion time
+  minus arrival time, queueing included).
+
+The scheduler (``Server``) is independent of the work it runs: it takes an executor callable and
+a footprint callable, which is how the CPU tests drive it.  ``GpuExecutor`` runs the real path
+through the C-ABI library.
+"""
+
+import argparse
+import json
+import math
+import os
+import queue
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Tuple
+
+
+@dataclass
+class Request:
+    id: int
+    t: float                      # arrival offset in seconds from the start of the run
+    N0: int
+    patches: List[Tuple[Tuple[int, int, int], Tuple[int, int, int]]] = field(default_factory=list)
+    order: int = 1                # 1: first-order LPT; 2: second order
+    scale: float = 1.0            # amplitude factor of this request's density
+
+
+@dataclass
+class Record:
+    id: int
+    arrival: float
+    admitted: float = math.nan
+    done: float = math.nan
+    footprint: int = 0
+    cell_updates: int = 0
+    error: Optional[str] = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+    @property
+    def queued(self):
+        return self.admitted - self.arrival
+
+
+def percentile(values, q):
+    """Nearest-rank percentile (q in [0, 100]) of a non-empty sequence."""
+    v = sorted(values)
+    k = max(1, int(math.ceil(q / 100.0 * len(v))))
+    return v[k - 1]
+
+
+class Server:
+    """Admission by slots and memory budget, one worker thread (and stream) per slot."""
+
+    def __init__(self, executor: Callable, footprint: Callable[[Request], int], slots: int = 4,
+                 budget_bytes: int = 16 << 30, clock: Callable[[], float] = time.perf_counter):
+        if slots < 1:
+            raise ValueError("slots must be >= 1")
+        self.executor = executor
+        self.footprint = footprint
+        self.slots = slots
+        self.budget = int(budget_bytes)
+        self.clock = clock
+        self.peak_bytes = 0
+        self.peak_inflight = 0
+
+    def run(self, requests: List[Request]) -> Dict[int, Record]:
+        reqs = sorted(requests, key=lambda r: (r.t, r.id))
+        recs = {r.id: Record(r.id, r.t) for r in reqs}
+        for r in reqs:
+            recs[r.id].footprint = int(self.footprint(r))
+            if recs[r.id].footprint > self.budget:
+                raise ValueError("request %d needs %d bytes, more than the whole budget %d"
+                                 % (r.id, recs[r.id].footprint, self.budget))
+        work: "queue.Queue" = queue.Queue()
+        done: "queue.Queue" = queue.Queue()
+        t0 = self.clock()
+
+        def worker(slot):
+            while True:
+                item = work.get()
+                if item is None:
+                    return
+                try:
+                    ups = self.executor(item, slot)
+                    done.put((item.id, self.clock() - t0, int(ups or 0), None))
+                except Exception as e:  # reported per request; the loop keeps serving
+                    done.put((item.id, self.clock() - t0, 0, "%s: %s" % (type(e).__name__, e)))
+
+        threads = [threading.Thread(target=worker, args=(s,), daemon=True) for s in range(self.slots)]
+        for th in threads:
+            th.start()
+        pending: deque = deque()
+        nxt = 0
+        free_slots, free_mem, inflight = self.slots, self.budget, 0
+        finished = 0
+        try:
+            while finished < len(reqs):
+                now = self.clock() - t0
+                while nxt < len(reqs) and reqs[nxt].t <= now:
+                    pending.append(reqs[nxt])
+                    nxt += 1
+                while pending and free_slots > 0 and recs[pending[0].id].footprint <= free_mem:
+                    r = pending.popleft()
+                    free_slots -= 1
+                    free_mem -= recs[r.id].footprint
+                    inflight += 1
+                    self.peak_bytes = max(self.peak_bytes, self.budget - free_mem)
+                    self.peak_inflight = max(self.peak_inflight, inflight)
+                    recs[r.id].admitted = self.clock() - t0
+                    work.put(r)
+                timeout = None
+                if nxt < len(reqs):
+                    timeout = max(0.0, reqs[nxt].t - (self.clock() - t0))
+                try:
+                    rid, t_done, ups, err = done.get(timeout=timeout)
+                except queue.Empty:
+                    continue
+                rec = recs[rid]
+                rec.done, rec.cell_updates, rec.error = t_done, ups, err
+                free_slots += 1
+                free_mem += rec.footprint
+                inflight -= 1
+                finished += 1
+        finally:
+            for _ in threads:
+                work.put(None)
+            for th in threads:
+                th.join()
+        return recs
+
+
+def summarize(recs: Dict[int, Record], server: Server) -> dict:
+    ok = [r for r in recs.values() if r.error is None]
+    lat = [r.latency for r in ok]
+    span = max(r.done for r in recs.values()) - min(r.arrival for r in recs.values())
+    ups = sum(r.cell_updates for r in ok)
+    out = dict(requests=len(recs), failed=len(recs) - len(ok), slots=server.slots,
+               budget_gb=round(server.budget / 2 ** 30, 3), peak_admitted_gb=round(server.peak_bytes / 2 ** 30, 3),
+               peak_inflight=server.peak_inflight, makespan_s=round(span, 3))
+    if lat:
+        q = [r.queued for r in ok]
+        out.update(p50_ms=round(1e3 * percentile(lat, 50), 2), p99_ms=round(1e3 * percentile(lat, 99), 2),
+                   mean_ms=round(1e3 * sum(lat) / len(lat), 2), max_ms=round(1e3 * max(lat), 2),
+                   queue_p99_ms=round(1e3 * percentile(q, 99), 2),
+                   req_per_s=round(len(ok) / span, 2) if span > 0 else None,
+                   mcell_updates_per_s=round(ups / span / 1e6, 1) if span > 0 else None)
+    return out
+
+
+# ------------------------------------------------------------------------------------------------
+# the GPU executor
+# ------------------------------------------------------------------------------------------------
+
+def hier_of(req: Request):
+    from . import inputs, mgic
+    return mgic.Hier(req.N0, inputs.BOX / req.N0, [(tuple(n), tuple(o)) for n, o in req.patches])
+
+
+def footprint_bytes(req: Request, prec="mixed") -> int:
+    """Device bytes one request holds while it runs: solve and LPT workspaces plus its fields
+    (density, potential, 3 displacement components per level; for second order also tau, the
+    second potential and its 3 displacement components)."""
+    from . import mgic
+    H = hier_of(req)
+    o = mgic.make_opts(prec=prec)
+    cells = sum(int(H.dims(p)[0]) * int(H.dims(p)[1]) * int(H.dims(p)[2]) for p in range(H.nlev))
+    fields = 5 + (5 if req.order == 2 else 0)
+    ws = mgic.mg_workspace_bytes(H, o) + mgic.lpt_workspace_bytes(H, req.order)
+    return int(ws + 8 * fields * cells + (1 << 20) * H.nlev)
+
+
+class GpuExecutor:
+    """Runs a request's LPT chain on the slot's stream; keeps selected outputs for checks."""
+
+    def __init__(self, fields: Dict[tuple, list], slots: int, prec="mixed", tol=1e-10, keep=()):
+        import torch
+        from . import mgic
+        self.torch, self.mg = torch, mgic
+        self.fields = fields           # shape key -> list of device tensors (one per level)
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.opts = mgic.make_opts(tol=tol, prec=prec, max_cycles=60)
+        self.keep = set(keep)
+        self.outputs: Dict[int, list] = {}
+        self.lock = threading.Lock()
+
+    def __call__(self, req: Request, slot: int) -> int:
+        torch, mg = self.torch, self.mg
+        st = self.streams[slot]
+        H = hier_of(req)
+        with torch.cuda.stream(st):
+            f = [x * req.scale for x in self.fields[shape_key(req)]]
+            phi, s1 = mg.mg_solve_hierarchy(H, f, opts=self.opts, stream=st)
+            psi = mg.lpt_displacements(H, phi, scale=-1.0, stream=st)
+            ups = s1["cell_updates"]
+            out = [phi, psi]
+            if req.order == 2:
+                tau = mg.lpt2_source(H, phi, stream=st)
+                phi2, s2 = mg.mg_solve_hierarchy(H, tau, opts=self.opts, stream=st)
+                psi2 = mg.lpt_displacements(H, phi2, scale=-3.0 / 7.0, stream=st)
+                ups += s2["cell_updates"]
+                out += [phi2, psi2]
+            st.synchronize()
+        if req.id in self.keep:
+            with self.lock:
+                self.outputs[req.id] = [[t.cpu() for t in (lv if isinstance(lv, list) else [lv])] for part in out
+                                        for lv in part]
+        return ups
+
+
+def shape_key(req: Request) -> tuple:
+    return (req.N0, tuple((tuple(n), tuple(o)) for n, o in req.patches))
+
+
+def _gen_fields(args):
+    from . import inputs
+    N0, patches, seed = args
+    return inputs.nested_fields(N0, [(tuple(n), tuple(o)) for n, o in patches], seed)
+
+
+def trace(count=600, rate=20.0, seed=None) -> List[Request]:
+    """The synthetic serving trace: Poisson arrivals, bases {64,128,256}^3 with 0-3 centred patches
+    of {64,96,128}^3, first or second order 50/50, a per-request amplitude factor in [0.95, 1.05]."""
+    import numpy as np
+    from . import inputs
+    raw = inputs.c5_requests(count=count, rate=rate) if seed is None else inputs.c5_requests(count, rate, seed)
+    out = []
+    for q in raw:
+        s = 1.0 + 0.05 * (2.0 * np.random.default_rng(q["seed"]).random() - 1.0)
+        out.append(Request(q["id"], q["t"], q["N0"], [(tuple(n), tuple(o)) for n, o in q["patches"]], q["order"], s))
+    return out
+
+
+def host_fields(reqs: List[Request], workers: int = 8) -> Dict[tuple, list]:
+    """One nested density per distinct hierarchy shape (seeded from the shape), as host arrays.
+    Call it before the process touches the GPU when workers > 1 (it starts worker processes)."""
+    keys = sorted({shape_key(r) for r in reqs})
+    jobs = [(k[0], [list(map(list, p)) for p in k[1]], 1103500 + i) for i, k in enumerate(keys)]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, len(jobs)), mp_context=mp.get_context("spawn")) as ex:
+            arrays = list(ex.map(_gen_fields, jobs))
+    else:
+        arrays = [_gen_fields(j) for j in jobs]
+    return dict(zip(keys, arrays))
+
+
+def device_fields(host: Dict[tuple, list]) -> Dict[tuple, list]:
+    import torch
+    return {k: [torch.from_numpy(a).to("cuda:0") for a in arr] for k, arr in host.items()}
+
+
+def serve_trace(reqs: List[Request], slots=4, budget_gb=16.0, prec="mixed", workers=8, keep=(), host=None):
+    fields = device_fields(host if host is not None else host_fields(reqs, workers))
+    ex = GpuExecutor(fields, slots, prec=prec, keep=keep)
+    # first launches (function attributes, code loading) happen outside the measured run
+    w = min(reqs, key=lambda r: (r.N0, len(r.patches)))
+    ex(Request(-1, 0.0, w.N0, w.patches, 2, 1.0), 0)
+    srv = Server(ex, lambda r: footprint_bytes(r, prec), slots=slots, budget_bytes=int(budget_gb * 2 ** 30))
+    recs = srv.run(reqs)
+    return summarize(recs, srv), recs, ex
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=16.0)
+    ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
+    a = ap.parse_args()
+    reqs = trace(a.requests, a.rate)
+    summary, _, _ = serve_trace(reqs, a.slots, a.budget_gb, a.prec, a.workers)
+    print(json.dumps(summary), flush=True)
+
+
+if __name__ == "__main__":
+    main()
