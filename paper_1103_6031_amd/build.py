@@ -2,7 +2,7 @@
 
 Every source under csrc/ is compiled for gfx950 only, with FP contraction off (the arithmetic
 order written in the kernels is the order executed) and packed FP32 instructions disabled.
-`build(out=..., defines=[...])` produces variant builds (e.g. -DMGIC_NO_XCD) for A/B timing.
+`build(out=..., csrc=...)` builds a variant library from another source directory (A/B timing).
 """
 
 import os
@@ -19,27 +19,31 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wall", "-Wno-unused-function",
+    "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
 ]
 SOURCES = ["k_multigrid.hip", "k_lpt.hip", "solver.cpp"]
 
 
 def _compile(args):
-    src, objdir, defines = args
+    src, objdir, defines, csrc = args
     obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ([HIPCC] + FLAGS + ["-I" + csrc] + ["-D" + d for d in defines] + lang +
+           ["-c", os.path.join(csrc, src), "-o", obj])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
     return obj
 
 
-def build(verbose=True, out=LIB, defines=()):
-    objdir = os.path.join(ROOT, "_build", "_".join(defines) if defines else "default")
+def build(verbose=True, out=LIB, defines=(), csrc=CSRC):
+    tag = "_".join(defines) if defines else "default"
+    if csrc != CSRC:
+        tag += "_" + os.path.basename(os.path.dirname(os.path.abspath(csrc)))
+    objdir = os.path.join(ROOT, "_build", tag)
     os.makedirs(objdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, [(s, objdir, list(defines)) for s in SOURCES]))
+        objs = list(ex.map(_compile, [(s, objdir, list(defines), csrc) for s in SOURCES]))
     tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

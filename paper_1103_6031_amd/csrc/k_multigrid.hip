@@ -749,7 +749,7 @@ template <class T>
 void launch_tail(const TailPlan<T>& tp, hipStream_t st) {
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+        (void)hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
         attr = true;
     }
     k_tail<T><<<1, kTailThreads, tp.lds_bytes, st>>>(tp);
@@ -999,8 +999,8 @@ void launch_b_prolong(const BSeg* segs, int nseg, unsigned grid, const int* acti
 void batch_kernel_setup() {
     static bool done = false;
     if (done) return;
-    hipFuncSetAttribute((const void*)kb_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
-    hipFuncSetAttribute((const void*)kb_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+    (void)hipFuncSetAttribute((const void*)kb_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+    (void)hipFuncSetAttribute((const void*)kb_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
     done = true;
 }
 template <class T>
