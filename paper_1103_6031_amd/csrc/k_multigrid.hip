@@ -18,6 +18,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "mg_internal.h"
 
 namespace mgic {
@@ -34,25 +36,25 @@ __device__ __forceinline__ T nsum_periodic(const T* __restrict__ u, Dims d, int 
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
-// the same on a patch (natural rows) whose outside neighbours come from the ghost faces
+// the same on a patch (in its layout, natural or colour-split) whose outside neighbours come from
+// the ghost faces
 template <class T>
-__device__ __forceinline__ T nsum_ghost(const T* __restrict__ u, const T* __restrict__ g, Dims d, int x, int y,
+__device__ __forceinline__ T nsum_ghost(const T* __restrict__ u, const T* __restrict__ g, const Lay& L, int x, int y,
                                         int z) {
-    const size_t sx = (size_t)d.y * d.z, sy = (size_t)d.z;
-    const size_t i = ((size_t)x * d.y + y) * d.z + z;
-    const T xm = x > 0 ? u[i - sx] : g[ghost_face_offset(d, 0) + (size_t)y * d.z + z];
-    const T xp = x < d.x - 1 ? u[i + sx] : g[ghost_face_offset(d, 1) + (size_t)y * d.z + z];
-    const T ym = y > 0 ? u[i - sy] : g[ghost_face_offset(d, 2) + (size_t)x * d.z + z];
-    const T yp = y < d.y - 1 ? u[i + sy] : g[ghost_face_offset(d, 3) + (size_t)x * d.z + z];
-    const T zm = z > 0 ? u[i - 1] : g[ghost_face_offset(d, 4) + (size_t)x * d.y + y];
-    const T zp = z < d.z - 1 ? u[i + 1] : g[ghost_face_offset(d, 5) + (size_t)x * d.y + y];
+    const Dims d = L.d;
+    const T xm = x > 0 ? u[lidx(L, x - 1, y, z)] : g[ghost_face_offset(d, 0) + (size_t)y * d.z + z];
+    const T xp = x < d.x - 1 ? u[lidx(L, x + 1, y, z)] : g[ghost_face_offset(d, 1) + (size_t)y * d.z + z];
+    const T ym = y > 0 ? u[lidx(L, x, y - 1, z)] : g[ghost_face_offset(d, 2) + (size_t)x * d.z + z];
+    const T yp = y < d.y - 1 ? u[lidx(L, x, y + 1, z)] : g[ghost_face_offset(d, 3) + (size_t)x * d.z + z];
+    const T zm = z > 0 ? u[lidx(L, x, y, z - 1)] : g[ghost_face_offset(d, 4) + (size_t)x * d.y + y];
+    const T zp = z < d.z - 1 ? u[lidx(L, x, y, z + 1)] : g[ghost_face_offset(d, 5) + (size_t)x * d.y + y];
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
 template <class T, bool GH>
 __device__ __forceinline__ T nsum(const T* __restrict__ u, const T* __restrict__ g, const Lay& L, int x, int y,
                                   int z) {
-    if constexpr (GH) return nsum_ghost<T>(u, g, L.d, x, y, z);
+    if constexpr (GH) return nsum_ghost<T>(u, g, L, x, y, z);
     else return nsum_periodic<T>(u, L.d, L.split, x, y, z);
 }
 
@@ -167,17 +169,32 @@ __device__ __forceinline__ void cell_resid_restrict(const T* __restrict__ u, con
     int X, Y, Z;
     ldecode(C, t, X, Y, Z);   // C: the covered box (natural order)
     T su = T(0), sr = T(0);
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int e = 0; e < 2; ++e) {
-                const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + e;
-                const size_t i = lidx(L, x, y, z);
-                const T ui = u[i];
-                const T s = nsum<T, GH>(u, g, L, x, y, z);
-                const T lap = (s - T(6) * ui) / h2;
-                sr = sr + (f[i] - lap);
-                su = su + ui;
-            }
+    if constexpr (GH) {
+        // the ghost-face neighbour sums are branchy: unrolling all 8 children spills registers;
+        // the children are taken in the same (a, b, e) order as below
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const int x = 2 * X + (k >> 2), y = 2 * Y + ((k >> 1) & 1), z = 2 * Z + (k & 1);
+            const size_t i = lidx(L, x, y, z);
+            const T ui = u[i];
+            const T s = nsum<T, GH>(u, g, L, x, y, z);
+            const T lap = (s - T(6) * ui) / h2;
+            sr = sr + (f[i] - lap);
+            su = su + ui;
+        }
+    } else {
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int e = 0; e < 2; ++e) {
+                    const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + e;
+                    const size_t i = lidx(L, x, y, z);
+                    const T ui = u[i];
+                    const T s = nsum<T, GH>(u, g, L, x, y, z);
+                    const T lap = (s - T(6) * ui) / h2;
+                    sr = sr + (f[i] - lap);
+                    su = su + ui;
+                }
+    }
     const T uc = su * T(0.125);
     const size_t P = pidx(pm, X, Y, Z);
     pu[P] = uc;
@@ -267,7 +284,9 @@ __global__ void k_rbgs_split(T* __restrict__ u, const T* __restrict__ f, Lay L, 
     body_rbgs_split<T, V>(u, f, L, h2, colour, (unsigned)xcd_block());
 }
 
-// patch (natural rows, ghost faces): one thread per cell of the colour
+// patch in the colour-split layout with ghost faces: one thread per cell of the colour, the cell
+// (x, y, j) of a row is z = 2j + ((x + y + colour) & 1); neighbours inside the patch are the other
+// colour's entries of the neighbour rows, outside ones come from the ghost faces
 template <class T>
 __global__ void k_rbgs_ghost(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Lay L, T h2,
                              int colour) {
@@ -276,15 +295,25 @@ __global__ void k_rbgs_ghost(T* __restrict__ u, const T* __restrict__ f, const T
     const unsigned total = (unsigned)d.x * d.y * nzh;
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const unsigned r = L.dzh.div(t);
-    const int zh = (int)(t - r * nzh);
-    const unsigned xq = L.dy.div(r);
-    const int y = (int)(r - xq * (unsigned)d.y);
+    const unsigned row = L.dzh.div(t);
+    const unsigned j = t - row * nzh;
+    const unsigned xq = L.dy.div(row);
+    const int y = (int)(row - xq * (unsigned)d.y);
     const int x = (int)xq;
-    const int z = 2 * zh + ((x + y + colour) & 1);
-    const size_t i = ((size_t)x * d.y + y) * d.z + z;
-    const T s = nsum_ghost<T>(u, g, d, x, y, z);
-    u[i] = (s - h2 * f[i]) / T(6);
+    const int q = (x + y + colour) & 1;
+    const int z = 2 * (int)j + q;
+    const unsigned own = colour ? nzh : 0u, oth = colour ? 0u : nzh;
+    const unsigned rs = (unsigned)d.z;
+    const unsigned r0 = row * rs;
+    const T xm = x > 0 ? u[r0 - (unsigned)d.y * rs + oth + j] : g[ghost_face_offset(d, 0) + (size_t)y * d.z + z];
+    const T xp = x < d.x - 1 ? u[r0 + (unsigned)d.y * rs + oth + j] : g[ghost_face_offset(d, 1) + (size_t)y * d.z + z];
+    const T ym = y > 0 ? u[r0 - rs + oth + j] : g[ghost_face_offset(d, 2) + (size_t)x * d.z + z];
+    const T yp = y < d.y - 1 ? u[r0 + rs + oth + j] : g[ghost_face_offset(d, 3) + (size_t)x * d.z + z];
+    // z-neighbours z -+ 1 are the other colour's entries (z - 1) / 2 and (z + 1) / 2
+    const T zm = z > 0 ? u[r0 + oth + (unsigned)((z - 1) >> 1)] : g[ghost_face_offset(d, 4) + (size_t)x * d.y + y];
+    const T zp = z < d.z - 1 ? u[r0 + oth + (unsigned)((z + 1) >> 1)] : g[ghost_face_offset(d, 5) + (size_t)x * d.y + y];
+    const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
+    u[r0 + own + j] = (s - h2 * f[r0 + own + j]) / T(6);
 }
 
 template <class T, bool GH>
@@ -347,31 +376,49 @@ __global__ void k_coarsest(T* __restrict__ u, const T* __restrict__ f, int M, do
 // first level's u and f are read from global memory and its u is written back at the end.
 // ----------------------------------------------------------------------------------------------
 
+// Copy of a block-uniform value whose 32-bit words are marked wave-uniform, so that the compiler
+// keeps it in scalar registers even when it was read from LDS or global memory.
+template <class S>
+__device__ __forceinline__ S uniform(const S& v) {
+    static_assert(sizeof(S) % 4 == 0, "uniform() copies 32-bit words");
+    int w[sizeof(S) / 4];
+    __builtin_memcpy(w, &v, sizeof(S));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(S) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    S out;
+    __builtin_memcpy(&out, w, sizeof(S));
+    return out;
+}
+
 template <class T>
 __device__ void body_tail(const TailPlan<T>& tp) {
     extern __shared__ __align__(16) unsigned char smem[];
-    auto U = [&](int k) { return (T*)(smem + tp.lev[k].lds_u); };
-    auto F = [&](int k) { return (T*)(smem + tp.lev[k].lds_f); };
-    auto O = [&](int k) { return (T*)(smem + tp.lev[k].lds_o); };
-    double* G = (double*)(smem + tp.lds_bytes - 2 * 343 * sizeof(double));
+    auto U = [&](int k) { return (T*)(smem + uniform(tp.lev[k].lds_u)); };
+    auto F = [&](int k) { return (T*)(smem + uniform(tp.lev[k].lds_f)); };
+    auto O = [&](int k) { return (T*)(smem + uniform(tp.lev[k].lds_o)); };
+    double* G = (double*)(smem + uniform(tp.lds_bytes) - 2 * 343 * sizeof(double));
     double* Gf = G + 343;
     const unsigned nt = blockDim.x;
     {
-        const unsigned n0 = (unsigned)tp.lev[0].lay.d.cells();
+        const unsigned n0 = (unsigned)uniform(tp.lev[0].lay.d).cells();
         T* U0 = U(0);
         T* F0 = F(0);
+        const T* u0g = uniform(tp.lev[0].u);
+        const T* f0g = uniform(tp.lev[0].f);
         for (unsigned t = threadIdx.x; t < n0; t += nt) {
-            U0[t] = tp.lev[0].u[t];
-            F0[t] = tp.lev[0].f[t];
+            U0[t] = u0g[t];
+            F0[t] = f0g[t];
         }
         __syncthreads();
     }
     // descent: smooth, restrict, FAS right-hand side
-    for (int l = 0; l + 1 < tp.n; ++l) {
-        const Lay A = tp.lev[l].lay, Bl = tp.lev[l + 1].lay;
-        const T h2 = (T)(tp.lev[l].h * tp.lev[l].h);
+    const int nlev = uniform(tp.n), nu1 = uniform(tp.nu1), nu2 = uniform(tp.nu2);
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const Lay A = uniform(tp.lev[l].lay), Bl = uniform(tp.lev[l + 1].lay);
+        const double hl = uniform(tp.lev[l].h);
+        const T h2 = (T)(hl * hl);
         const unsigned half = (unsigned)A.d.cells() >> 1;
-        for (int s = 0; s < tp.nu1; ++s)
+        for (int s = 0; s < nu1; ++s)
             for (int c = 0; c < 2; ++c) {
                 for (unsigned t = threadIdx.x; t < half; t += nt) cell_rbgs_split<T>(U(l), F(l), A, h2, c, t);
                 __syncthreads();
@@ -383,34 +430,37 @@ __device__ void body_tail(const TailPlan<T>& tp) {
         for (unsigned t = threadIdx.x; t < nc; t += nt)
             cell_resid_restrict<T, false>(U(l), F(l), (const T*)nullptr, A, h2, U(l + 1), F(l + 1), O(l), pm, C, t);
         __syncthreads();
-        const T H2 = (T)(tp.lev[l + 1].h * tp.lev[l + 1].h);
+        const double hc = uniform(tp.lev[l + 1].h);
+        const T H2 = (T)(hc * hc);
         for (unsigned t = threadIdx.x; t < nc; t += nt) cell_fas<T>(U(l + 1), F(l + 1), pm, C, H2, t);
         __syncthreads();
     }
     {
-        const int c = tp.n - 1;
-        block_coarsest<T>(U(c), F(c), tp.lev[c].lay.d.x, tp.lev[c].h, G, Gf);
+        const int c = nlev - 1;
+        block_coarsest<T>(U(c), F(c), uniform(tp.lev[c].lay.d).x, uniform(tp.lev[c].h), G, Gf);
         __syncthreads();
     }
     // ascent: correct, smooth
-    for (int l = tp.n - 2; l >= 0; --l) {
-        const Lay A = tp.lev[l].lay, Bl = tp.lev[l + 1].lay;
+    for (int l = nlev - 2; l >= 0; --l) {
+        const Lay A = uniform(tp.lev[l].lay), Bl = uniform(tp.lev[l + 1].lay);
         const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
         const unsigned n = (unsigned)A.d.cells();
-        if (tp.nu2 > 0 && A.split)   // red cells are rewritten unread by the first red half-sweep
+        if (nu2 > 0 && A.split)   // red cells are rewritten unread by the first red half-sweep
             for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_prolong_black<T>(U(l), A, U(l + 1), O(l), pm, t);
         else
             for (unsigned t = threadIdx.x; t < n; t += nt) cell_prolong<T>(U(l), A, U(l + 1), O(l), pm, t);
         __syncthreads();
-        const T h2 = (T)(tp.lev[l].h * tp.lev[l].h);
-        for (int s = 0; s < tp.nu2; ++s)
+        const double hl = uniform(tp.lev[l].h);
+        const T h2 = (T)(hl * hl);
+        for (int s = 0; s < nu2; ++s)
             for (int c = 0; c < 2; ++c) {
                 for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_rbgs_split<T>(U(l), F(l), A, h2, c, t);
                 __syncthreads();
             }
     }
-    const unsigned n0 = (unsigned)tp.lev[0].lay.d.cells();
-    for (unsigned t = threadIdx.x; t < n0; t += nt) tp.lev[0].u[t] = U(0)[t];
+    const unsigned n0 = (unsigned)uniform(tp.lev[0].lay.d).cells();
+    T* u0out = uniform(tp.lev[0].u);
+    for (unsigned t = threadIdx.x; t < n0; t += nt) u0out[t] = U(0)[t];
 }
 
 template <class T>
@@ -435,29 +485,17 @@ __device__ __forceinline__ void w2(double t, double w[3]) {
 }
 
 template <class T>
-__global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, T* __restrict__ g, Dims d,
+__global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, T* __restrict__ g, Lay LF,
                              ParentMap pm, int flux_match) {
+    const Dims d = LF.d;
     const int n[3] = {d.x, d.y, d.z};
-    const size_t gx = (size_t)(d.y / 2) * (d.z / 2), gy = (size_t)(d.x / 2) * (d.z / 2),
-                 gz = (size_t)(d.x / 2) * (d.y / 2);
-    size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    int face;
-    if (t < 2 * gx) {
-        face = (int)(t / gx);
-        t %= gx;
-    } else if ((t -= 2 * gx) < 2 * gy) {
-        face = 2 + (int)(t / gy);
-        t %= gy;
-    } else if ((t -= 2 * gy) < 2 * gz) {
-        face = 4 + (int)(t / gz);
-        t %= gz;
-    } else {
-        return;
-    }
+    const int face = (int)blockIdx.y;
     const int a = face >> 1, side = face & 1;
     const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
-    const int nc2 = n[c] / 2;
-    const int J = (int)(t / nc2), K = (int)(t % nc2);
+    const unsigned nc2 = (unsigned)n[c] / 2;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ((unsigned)n[b] / 2) * nc2) return;
+    const int J = (int)(t / nc2), K = (int)(t - (unsigned)J * nc2);
     // fine interior layers and the outside coarse layer along the face normal
     const int i0 = side ? n[a] - 1 : 0, i1 = side ? n[a] - 2 : 1;
     const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
@@ -483,8 +521,8 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
             p1[a] = i1;
             p0[b] = p1[b] = 2 * J + jb;
             p0[c] = p1[c] = 2 * K + kc;
-            u0[jb][kc] = (double)u[((size_t)p0[0] * d.y + p0[1]) * d.z + p0[2]];
-            u1[jb][kc] = (double)u[((size_t)p1[0] * d.y + p1[1]) * d.z + p1[2]];
+            u0[jb][kc] = (double)u[lidx(LF, p0[0], p0[1], p0[2])];
+            u1[jb][kc] = (double)u[lidx(LF, p1[0], p1[1], p1[2])];
             double wb[3], wc[3];
             w2(jb ? 0.25 : -0.25, wb);
             w2(kc ? 0.25 : -0.25, wc);
@@ -786,9 +824,11 @@ void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st) {
 }
 
 template <class T>
-void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Dims d, ParentMap pm, int flux_match, hipStream_t st) {
-    const size_t n = 2 * ((size_t)(d.y / 2) * (d.z / 2) + (size_t)(d.x / 2) * (d.z / 2) + (size_t)(d.x / 2) * (d.y / 2));
-    k_ghost_fill<T><<<grid_for(n), kBlock, 0, st>>>(pu, u, ghosts, d, pm, flux_match);
+void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Lay L, ParentMap pm, int flux_match, hipStream_t st) {
+    const Dims d = L.d;
+    const size_t most = std::max({(size_t)(d.y / 2) * (d.z / 2), (size_t)(d.x / 2) * (d.z / 2),
+                                  (size_t)(d.x / 2) * (d.y / 2)});
+    k_ghost_fill<T><<<dim3(grid_for(most), 6), kBlock, 0, st>>>(pu, u, ghosts, L, pm, flux_match);
 }
 
 template <class T>
@@ -888,12 +928,20 @@ __global__ void kb_prolong(const BSeg* __restrict__ segs, int nseg, const int* _
     }
 }
 
+// Each workgroup first copies its plan into LDS and body_tail marks every field it takes from
+// the plan as wave-uniform (read from global memory with a run-time level index, the plan was
+// pulled into vector registers and spilled; this way a few words still spill on FP64).
 template <class T>
 __global__ void __launch_bounds__(kTailThreads) kb_tail(const TailPlan<T>* __restrict__ plans,
                                                         const int* __restrict__ active) {
-    const TailPlan<T>& tp = plans[blockIdx.x];
-    if (!active[tp.inst]) return;
-    body_tail<T>(tp);
+    __shared__ __align__(16) unsigned char raw[sizeof(TailPlan<T>)];
+    static_assert(sizeof(TailPlan<T>) % 4 == 0, "plan copied as 32-bit words");
+    const unsigned* src = (const unsigned*)(plans + blockIdx.x);
+    for (unsigned w = threadIdx.x; w < sizeof(TailPlan<T>) / 4; w += blockDim.x) ((unsigned*)raw)[w] = src[w];
+    __syncthreads();
+    const TailPlan<T>& sp = *reinterpret_cast<const TailPlan<T>*>(raw);
+    if (!active[uniform(sp.inst)]) return;
+    body_tail<T>(sp);
 }
 
 __global__ void kb_outer(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active, int has_e) {
@@ -996,12 +1044,18 @@ void launch_b_prolong(const BSeg* segs, int nseg, unsigned grid, const int* acti
     if (black_only) kb_prolong<T, true><<<grid, kBlock, 0, st>>>(segs, nseg, active);
     else kb_prolong<T, false><<<grid, kBlock, 0, st>>>(segs, nseg, active);
 }
-void batch_kernel_setup() {
+hipError_t batch_kernel_setup() {
     static bool done = false;
-    if (done) return;
-    (void)hipFuncSetAttribute((const void*)kb_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
-    (void)hipFuncSetAttribute((const void*)kb_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
-    done = true;
+    if (done) return hipSuccess;
+    // kb_tail holds its plan in static LDS besides the dynamic levels; it asks for the bound on
+    // what a tail plan needs, not for the whole workgroup LDS
+    hipError_t e = hipFuncSetAttribute((const void*)kb_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kTailLdsBound);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)kb_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kTailLdsBound);
+    if (e == hipSuccess) done = true;
+    return e;
 }
 template <class T>
 void launch_b_tail(const TailPlan<T>* plans, int n, unsigned lds_bytes, const int* active, hipStream_t st) {
@@ -1045,7 +1099,7 @@ template void launch_sub_mean<double>(double*, size_t, const double*, double, hi
     template void launch_fas_rhs<T>(const T*, T*, ParentMap, Dims, double, hipStream_t);                    \
     template void launch_prolong<T>(T*, Lay, const T*, const T*, ParentMap, int, hipStream_t);                   \
     template void launch_coarsest<T>(T*, const T*, int, double, hipStream_t);                               \
-    template void launch_ghost_fill<T>(const T*, const T*, T*, Dims, ParentMap, int, hipStream_t);          \
+    template void launch_ghost_fill<T>(const T*, const T*, T*, Lay, ParentMap, int, hipStream_t);            \
     template void launch_restrict_cov<T>(const T*, Lay, T*, ParentMap, hipStream_t);                \
     template void launch_tail<T>(const TailPlan<T>&, hipStream_t);
 MGIC_INST(double)

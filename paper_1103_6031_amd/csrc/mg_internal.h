@@ -103,6 +103,7 @@ __host__ __device__ inline size_t ghost_cells(Dims d) { return ghost_face_offset
 constexpr int kTailThreads = 1024;
 constexpr size_t kTailMaxCells = 16 * 16 * 16;   // levels at or below this size join the tail
 constexpr size_t kTailMaxLds = 160 * 1024;        // LDS one gfx950 workgroup may hold
+constexpr size_t kTailLdsBound = 96 * 1024;       // dynamic LDS any tail plan needs (levels <= 16^3)
 constexpr int kTailMaxLevels = 8;
 template <class T>
 struct TailLevel {
@@ -179,7 +180,7 @@ template <class T> void launch_tail(const TailPlan<T>& tp, hipStream_t st);
 template <class T> void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st);
 
 // flux-matched ghost layer of a patch (arithmetic in double, stored as T)
-template <class T> void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Dims d, ParentMap pm,
+template <class T> void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Lay L, ParentMap pm,
                                           int flux_match, hipStream_t st);
 // parent[cov] = mean8(fine)
 template <class T> void launch_restrict_cov(const T* fine, Lay L, T* parent, ParentMap pm, hipStream_t st);
@@ -254,7 +255,7 @@ template <class T> void launch_b_fas(const BSeg* segs, int nseg, unsigned grid, 
 template <class T> void launch_b_prolong(const BSeg* segs, int nseg, unsigned grid, const int* active,
                                          int black_only, hipStream_t st);
 // sets the batched kernels' function attributes (LDS size); call before any graph capture
-void batch_kernel_setup();
+hipError_t batch_kernel_setup();
 // the single-workgroup tails of n instances, one workgroup each
 template <class T> void launch_b_tail(const TailPlan<T>* plans, int n, unsigned lds_bytes, const int* active,
                                       hipStream_t st);

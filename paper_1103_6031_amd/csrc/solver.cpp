@@ -28,10 +28,15 @@ static int fail(int code, const std::string& msg) {
     return code;
 }
 
+// on failure the runtime's last-error state is cleared as well, so that a failed call here is
+// not reported again by the caller's next, unrelated HIP call
 #define MG_HIP(call)                                                                           \
     do {                                                                                       \
         hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess) return fail(MG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+        if (e_ != hipSuccess) {                                                                \
+            (void)hipGetLastError();                                                           \
+            return fail(MG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
+        }                                                                                      \
     } while (0)
 
 // ----------------------------------------------------------------------------------------------
@@ -147,7 +152,9 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
         }
     }
     P.last = (int)P.L.size() - 1;
-    for (auto& L : P.L) L.lay = mklay(L.d, (L.periodic && L.d.z % 2 == 0) ? 1 : 0);
+    // colour-split rows wherever a level has even rows (periodic levels above the odd coarsest,
+    // and every patch)
+    for (auto& L : P.L) L.lay = mklay(L.d, L.d.z % 2 == 0 ? 1 : 0);
     for (int l = 0; l < P.last; ++l) {
         Level& L = P.L[l];
         Level& Q = P.L[l + 1];
@@ -235,7 +242,7 @@ template <class T>
 static void ghosts(Plan& P, int l, hipStream_t st) {
     Level& L = P.L[l];
     B<T> b = bufs<T>(L), pb = bufs<T>(P.L[l + 1]);
-    launch_ghost_fill<T>(pb.u, b.u, b.g, L.d, L.pm, 1, st);
+    launch_ghost_fill<T>(pb.u, b.u, b.g, L.lay, L.pm, 1, st);
 }
 
 template <class T>
@@ -283,7 +290,9 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
     launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, q.u, q.f, b.uold, L.pm, st);
     launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
     vcycle<T>(P, l + 1, st);                         // step 7
-    launch_prolong<T>(b.u, L.lay, q.u, b.uold, L.pm, P.nu2 > 0, st);  // step 8
+    // black cells only where nothing reads the red ones before the red half-sweep rewrites them:
+    // a patch's ghost fill reads both colours of its first two layers
+    launch_prolong<T>(b.u, L.lay, q.u, b.uold, L.pm, P.nu2 > 0 && L.periodic, st);  // step 8
     smooth<T>(P, l, P.nu2, st);                      // step 9
 }
 
@@ -1027,7 +1036,7 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
     const bool use_graph = (o->flags & MG_NO_GRAPH) == 0;
     const int inner = o->inner > 0 ? o->inner : 2;
     B.mixed = o->prec == MG_MIXED;
-    batch_kernel_setup();   // function attributes must be set outside any graph capture
+    MG_HIP(batch_kernel_setup());   // function attributes must be set outside any graph capture
     for (int i = 0; i < ni; ++i) {
         Level& L = B.P[i].L[0];
         B.Au.push_back(L.u);
@@ -1049,6 +1058,7 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         vcycle_tables<float>(B, 0, 0, B.Be, shf);   // after an even outer step e lives in B
         vcycle_tables<float>(B, 0, 1, B.Ae, shf);
         B.tpf = tail_plans<float>(B, B.lds_f);
+        if (B.lds_f > kTailLdsBound) return fail(MG_EINVAL, "internal: tail LDS above its bound");
         for (int par = 0; par < 2; ++par) {
             std::vector<BSeg> v;
             for (int i = 0; i < ni; ++i) {
@@ -1072,6 +1082,7 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         for (int i = 0; i < ni; ++i) fu[i] = B.Au[i];
         vcycle_tables<double>(B, 1, 0, fu, shd);
         B.tpd = tail_plans<double>(B, B.lds_d);
+        if (B.lds_d > kTailLdsBound) return fail(MG_EINVAL, "internal: tail LDS above its bound");
         std::vector<BSeg> v;
         for (int i = 0; i < ni; ++i) {
             Level& L = B.P[i].L[0];
@@ -1576,7 +1587,7 @@ int mg_ghost_fill(const mg_hier* hier, int p, const double* const* u, double* gh
     if (p < 1 || p >= hier->nlev) return fail(MG_EINVAL, "p must name a patch");
     if (!u || !u[p] || !u[p - 1] || !ghosts) return fail(MG_EINVAL, "NULL argument");
     (void)hipGetLastError();
-    launch_ghost_fill<double>(u[p - 1], u[p], ghosts, dims_of(hier, p), parent_of(hier, p), flux_match,
+    launch_ghost_fill<double>(u[p - 1], u[p], ghosts, Lay(dims_of(hier, p), 0), parent_of(hier, p), flux_match,
                               (hipStream_t)stream);
     MG_HIP(hipGetLastError());
     return MG_OK;
