@@ -139,19 +139,39 @@ __device__ __forceinline__ void cell_rbgs_split(T* __restrict__ u, const T* __re
                                                 int colour, unsigned t) {
     const Dims d = L.d;
     const unsigned nzh = (unsigned)d.z >> 1;
-    const unsigned row = L.dzh.div(t);
-    const unsigned j = t - row * nzh;
-    const unsigned xq = L.dy.div(row);
-    const int y = (int)(row - xq * (unsigned)d.y);
-    const int x = (int)xq;
-    const int q = (x + y + colour) & 1;          // z parity of this colour in the row
+    unsigned j, r0, rxm, rxp, rym, ryp, jm, jp;
+    int q;                                       // z parity of this colour in the row
+    if (L.pow2) {   // power-of-two level: the same indices by shifts and masks
+        const unsigned lzh = (unsigned)L.lgz - 1, mx = (unsigned)d.x - 1, my = (unsigned)d.y - 1;
+        const unsigned row = t >> lzh;
+        j = t & (nzh - 1);
+        const unsigned x = row >> L.lgy, y = row & my;
+        q = (int)((x + y + (unsigned)colour) & 1u);
+        r0 = row << L.lgz;
+        rxm = ((((x - 1) & mx) << L.lgy) | y) << L.lgz;
+        rxp = ((((x + 1) & mx) << L.lgy) | y) << L.lgz;
+        rym = ((x << L.lgy) | ((y - 1) & my)) << L.lgz;
+        ryp = ((x << L.lgy) | ((y + 1) & my)) << L.lgz;
+        jm = (j - 1 + (unsigned)q) & (nzh - 1);
+        jp = (j + (unsigned)q) & (nzh - 1);
+    } else {
+        const unsigned row = L.dzh.div(t);
+        j = t - row * nzh;
+        const unsigned xq = L.dy.div(row);
+        const int y = (int)(row - xq * (unsigned)d.y);
+        const int x = (int)xq;
+        q = (x + y + colour) & 1;
+        const unsigned rs = (unsigned)d.z;
+        rxm = ((unsigned)wrap(x - 1, d.x) * d.y + y) * rs;
+        rxp = ((unsigned)wrap(x + 1, d.x) * d.y + y) * rs;
+        rym = ((unsigned)x * d.y + wrap(y - 1, d.y)) * rs;
+        ryp = ((unsigned)x * d.y + wrap(y + 1, d.y)) * rs;
+        r0 = row * rs;
+        // the cell is z = 2j + q; its z-neighbours are the other colour's entries (z-1)/2, (z+1)/2
+        jm = (unsigned)wrap((int)j - 1 + q, (int)nzh);
+        jp = (unsigned)wrap((int)j + q, (int)nzh);
+    }
     const unsigned own = colour ? nzh : 0u, oth = colour ? 0u : nzh;
-    const unsigned rs = (unsigned)d.z;
-    const unsigned rxm = ((unsigned)wrap(x - 1, d.x) * d.y + y) * rs, rxp = ((unsigned)wrap(x + 1, d.x) * d.y + y) * rs;
-    const unsigned rym = ((unsigned)x * d.y + wrap(y - 1, d.y)) * rs, ryp = ((unsigned)x * d.y + wrap(y + 1, d.y)) * rs;
-    const unsigned r0 = row * rs;
-    // the cell is z = 2j + q; its z-neighbours are the other colour's entries (z-1)/2, (z+1)/2
-    const unsigned jm = (unsigned)wrap((int)j - 1 + q, (int)nzh), jp = (unsigned)wrap((int)j + q, (int)nzh);
     const T xm = u[rxm + oth + j], xp = u[rxp + oth + j];
     const T ym = u[rym + oth + j], yp = u[ryp + oth + j];
     const T zm = u[r0 + oth + jm], zp = u[r0 + oth + jp];
@@ -563,6 +583,54 @@ __global__ void k_restrict_cov(const T* __restrict__ v, Lay L, T* __restrict__ p
     pv[pidx(pm, X, Y, Z)] = s * T(0.125);
 }
 
+// Storage position t of a colour-split periodic level (either colour): its coordinates and the
+// storage rows of its six neighbours, wrapped.  Power-of-two levels use shifts and masks.
+struct SplitNb {
+    unsigned j, col, oth, r0, rxm, rxp, rym, ryp, jm, jp;
+    int x, y, q;
+};
+__device__ __forceinline__ SplitNb split_nb(const Lay& L, unsigned t) {
+    const Dims d = L.d;
+    const unsigned nz = (unsigned)d.z, nzh = nz >> 1;
+    SplitNb c;
+    unsigned row, p;
+    if (L.pow2) {
+        row = t >> L.lgz;
+        p = t & (nz - 1);
+        c.x = (int)(row >> L.lgy);
+        c.y = (int)(row & ((unsigned)d.y - 1));
+    } else {
+        row = L.dz.div(t);
+        p = t - row * nz;
+        const unsigned xq = L.dy.div(row);
+        c.y = (int)(row - xq * (unsigned)d.y);
+        c.x = (int)xq;
+    }
+    c.col = p >= nzh;
+    c.j = p - c.col * nzh;
+    c.q = (c.x + c.y + (int)c.col) & 1;
+    c.oth = c.col ? 0u : nzh;
+    if (L.pow2) {
+        const unsigned mx = (unsigned)d.x - 1, my = (unsigned)d.y - 1, x = (unsigned)c.x, y = (unsigned)c.y;
+        c.r0 = row << L.lgz;
+        c.rxm = ((((x - 1) & mx) << L.lgy) | y) << L.lgz;
+        c.rxp = ((((x + 1) & mx) << L.lgy) | y) << L.lgz;
+        c.rym = ((x << L.lgy) | ((y - 1) & my)) << L.lgz;
+        c.ryp = ((x << L.lgy) | ((y + 1) & my)) << L.lgz;
+        c.jm = (c.j - 1 + (unsigned)c.q) & (nzh - 1);
+        c.jp = (c.j + (unsigned)c.q) & (nzh - 1);
+    } else {
+        c.r0 = row * nz;
+        c.rxm = ((unsigned)wrap(c.x - 1, d.x) * d.y + c.y) * nz;
+        c.rxp = ((unsigned)wrap(c.x + 1, d.x) * d.y + c.y) * nz;
+        c.rym = ((unsigned)c.x * d.y + wrap(c.y - 1, d.y)) * nz;
+        c.ryp = ((unsigned)c.x * d.y + wrap(c.y + 1, d.y)) * nz;
+        c.jm = (unsigned)wrap((int)c.j - 1 + c.q, (int)nzh);
+        c.jp = (unsigned)wrap((int)c.j + c.q, (int)nzh);
+    }
+    return c;
+}
+
 // ----------------------------------------------------------------------------------------------
 // residual of a level with optional output, partial sums of r^2 outside the covered box
 // ----------------------------------------------------------------------------------------------
@@ -617,18 +685,10 @@ __device__ __forceinline__ double body_residual_split(const T* __restrict__ u, c
     for (int v = 0; v < kRedV; ++v) {
         const unsigned t = b0 + v * blockDim.x;
         if (t >= hi) break;
-        const unsigned row = L.dz.div(t);
-        const unsigned p = t - row * nz;
-        const unsigned col = p >= nzh;
-        const unsigned j = p - col * nzh;
-        const unsigned xq = L.dy.div(row);
-        const int y = (int)(row - xq * (unsigned)d.y), x = (int)xq;
-        const int q = (x + y + (int)col) & 1;
-        const unsigned oth = col ? 0u : nzh;
-        const unsigned rxm = ((unsigned)wrap(x - 1, d.x) * d.y + y) * nz, rxp = ((unsigned)wrap(x + 1, d.x) * d.y + y) * nz;
-        const unsigned rym = ((unsigned)x * d.y + wrap(y - 1, d.y)) * nz, ryp = ((unsigned)x * d.y + wrap(y + 1, d.y)) * nz;
-        const unsigned r0 = row * nz;
-        const unsigned jm = (unsigned)wrap((int)j - 1 + q, (int)nzh), jp = (unsigned)wrap((int)j + q, (int)nzh);
+        const SplitNb c = split_nb(L, t);
+        const unsigned j = c.j, col = c.col, oth = c.oth, r0 = c.r0, rxm = c.rxm, rxp = c.rxp, rym = c.rym,
+                       ryp = c.ryp, jm = c.jm, jp = c.jp;
+        const int x = c.x, y = c.y, q = c.q;
         const T s = ((u[rxm + oth + j] + u[rxp + oth + j]) + (u[rym + oth + j] + u[ryp + oth + j])) +
                     (u[r0 + oth + jm] + u[r0 + oth + jp]);
         const T r = f[t] - (s - T(6) * u[t]) / h2;
@@ -665,18 +725,10 @@ __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_
     for (int v = 0; v < kRedV; ++v) {
         const unsigned t = b0 + v * blockDim.x;
         if (t >= hi) break;
-        const unsigned row = L.dz.div(t);
-        const unsigned p = t - row * nz;
-        const unsigned col = p >= nzh;
-        const unsigned j = p - col * nzh;
-        const unsigned xq = L.dy.div(row);
-        const int y = (int)(row - xq * (unsigned)d.y), x = (int)xq;
-        const int q = (x + y + (int)col) & 1;
-        const unsigned oth = col ? 0u : nzh;
-        const unsigned rxm = ((unsigned)wrap(x - 1, d.x) * d.y + y) * nz, rxp = ((unsigned)wrap(x + 1, d.x) * d.y + y) * nz;
-        const unsigned rym = ((unsigned)x * d.y + wrap(y - 1, d.y)) * nz, ryp = ((unsigned)x * d.y + wrap(y + 1, d.y)) * nz;
-        const unsigned r0 = row * nz;
-        const unsigned jm = (unsigned)wrap((int)j - 1 + q, (int)nzh), jp = (unsigned)wrap((int)j + q, (int)nzh);
+        const SplitNb c = split_nb(L, t);
+        const unsigned j = c.j, col = c.col, oth = c.oth, r0 = c.r0, rxm = c.rxm, rxp = c.rxp, rym = c.rym,
+                       ryp = c.ryp, jm = c.jm, jp = c.jp;
+        const int x = c.x, y = c.y, q = c.q;
         auto V = [&](unsigned i) { return e_in ? u_in[i] + (double)e_in[i] : u_in[i]; };
         const double c0 = V(t);
         const double s = ((V(rxm + oth + j) + V(rxp + oth + j)) + (V(rym + oth + j) + V(ryp + oth + j))) +
@@ -775,6 +827,9 @@ void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h, int co
     if (ghosts)
         hipExtLaunchKernelGGL(k_rbgs_ghost<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, ghosts, L,
                               h2, colour);
+    else if (sizeof(T) == 4 && n >= ((size_t)1 << 22))   // measured: 4 cells per thread for FP32 at 256^3+
+        hipExtLaunchKernelGGL(k_rbgs_split<T, 4>, dim3(grid_for((n + 3) / 4)), dim3(kBlock), 0, st, ev0, ev1, 0, u,
+                              f, L, h2, colour);
     else if (n >= (size_t)kBlock * 64 * 2)
         hipExtLaunchKernelGGL(k_rbgs_split<T, 2>, dim3(grid_for((n + 1) / 2)), dim3(kBlock), 0, st, ev0, ev1, 0, u,
                               f, L, h2, colour);

@@ -24,15 +24,27 @@ struct Dims {
 // z holds its red cells, (x+y+z) even, in increasing z, then its black cells).
 // The dividers are always derived from d by the constructor, so a Lay can never decode with
 // stale constants; device code that only needs indices uses (Dims, split) directly.
+__host__ __device__ inline int log2_exact(int n) {   // log2 n if n is a power of two, else -1
+    if (n < 1 || (n & (n - 1))) return -1;
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
 struct Lay {
     Dims d{1, 1, 1};
     int split = 0;
     FastDiv dz, dy, dzh;   // division by d.z, d.y and d.z / 2
+    int lgx = -1, lgy = -1, lgz = -1;   // log2 of the dims (-1: not a power of two)
+    int pow2 = 0;                       // all three dims are powers of two and d.z >= 2
 
     Lay() = default;
     __host__ __device__ Lay(Dims d_, int split_)
         : d(d_), split(split_), dz((unsigned)d_.z), dy((unsigned)d_.y),
-          dzh((unsigned)(d_.z > 1 ? d_.z / 2 : 1)) {}
+          dzh((unsigned)(d_.z > 1 ? d_.z / 2 : 1)), lgx(log2_exact(d_.x)), lgy(log2_exact(d_.y)),
+          lgz(log2_exact(d_.z)) {
+        pow2 = lgx >= 0 && lgy >= 0 && lgz >= 1;
+    }
 };
 inline Lay mklay(Dims d, int split) { return Lay(d, split); }
 
@@ -43,17 +55,31 @@ __host__ __device__ __forceinline__ size_t lidx(Dims d, int split, int x, int y,
     return row * d.z + (((x + y + z) & 1) ? (size_t)(d.z >> 1) : 0) + (z >> 1);
 }
 __host__ __device__ __forceinline__ size_t lidx(const Lay& L, int x, int y, int z) {
+    if (L.pow2) {   // shifts instead of multiplies (every level fits in 2^31 cells)
+        const unsigned row = ((unsigned)x << L.lgy) | (unsigned)y;
+        if (!L.split) return (size_t)((row << L.lgz) | (unsigned)z);
+        return (size_t)((row << L.lgz) + (((x + y + z) & 1) ? (1u << (L.lgz - 1)) : 0u) + ((unsigned)z >> 1));
+    }
     return lidx(L.d, L.split, x, y, z);
 }
 
 // coordinates of storage position i (every level has fewer than 2^31 cells)
 __host__ __device__ __forceinline__ void ldecode(const Lay& L, size_t i64, int& x, int& y, int& z) {
     const unsigned i = (unsigned)i64;
-    const unsigned row = L.dz.div(i);
-    const int p = (int)(i - row * (unsigned)L.d.z);
-    const unsigned xq = L.dy.div(row);
-    y = (int)(row - xq * (unsigned)L.d.y);
-    x = (int)xq;
+    unsigned row;
+    int p;
+    if (L.pow2) {
+        row = i >> L.lgz;
+        p = (int)(i & ((1u << L.lgz) - 1));
+        x = (int)(row >> L.lgy);
+        y = (int)(row & ((1u << L.lgy) - 1));
+    } else {
+        row = L.dz.div(i);
+        p = (int)(i - row * (unsigned)L.d.z);
+        const unsigned xq = L.dy.div(row);
+        y = (int)(row - xq * (unsigned)L.d.y);
+        x = (int)xq;
+    }
     if (!L.split) {
         z = p;
         return;
