@@ -128,7 +128,7 @@ __global__ void k_wide_ghost(const double* __restrict__ pu, const double* __rest
         w[a][1] = 1.0 - tt * tt;
         w[a][2] = 0.5 * tt * (tt + 1.0);
     }
-    const int pdim[3] = {pm.pd.x, pm.pd.y, pm.pd.z};
+    const int pdim[3] = {pm.pl.d.x, pm.pl.d.y, pm.pl.d.z};
     // interpolate along x, then y, then z (tensor product)
     double az = 0.0;
     for (int dz = 0; dz < 3; ++dz) {

@@ -62,11 +62,11 @@ __device__ __forceinline__ T nsum(const T* __restrict__ u, const T* __restrict__
 __device__ __forceinline__ size_t pidx(const ParentMap& pm, int X, int Y, int Z) {
     int a = pm.off[0] + X, b = pm.off[1] + Y, c = pm.off[2] + Z;
     if (pm.periodic) {
-        a = wrap(a, pm.pd.x);
-        b = wrap(b, pm.pd.y);
-        c = wrap(c, pm.pd.z);
+        a = wrap(a, pm.pl.d.x);
+        b = wrap(b, pm.pl.d.y);
+        c = wrap(c, pm.pl.d.z);
     }
-    return lidx(pm.pd, pm.split, a, b, c);
+    return lidx(pm.pl.d, pm.pl.split, a, b, c);
 }
 
 
@@ -228,9 +228,9 @@ __device__ __forceinline__ void cell_fas(const T* __restrict__ pu, T* __restrict
                                          const Lay& C, T H2, unsigned t) {
     int X, Y, Z;
     ldecode(C, t, X, Y, Z);   // C: the covered box (natural order)
-    const int a = wrap(pm.off[0] + X, pm.pd.x), b = wrap(pm.off[1] + Y, pm.pd.y), c = wrap(pm.off[2] + Z, pm.pd.z);
-    const size_t i = lidx(pm.pd, pm.split, a, b, c);
-    const T s = nsum_periodic<T>(pu, pm.pd, pm.split, a, b, c);
+    const int a = wrap(pm.off[0] + X, pm.pl.d.x), b = wrap(pm.off[1] + Y, pm.pl.d.y), c = wrap(pm.off[2] + Z, pm.pl.d.z);
+    const size_t i = lidx(pm.pl.d, pm.pl.split, a, b, c);
+    const T s = nsum_periodic<T>(pu, pm.pl.d, pm.pl.split, a, b, c);
     pf[i] = pf[i] + (s - T(6) * pu[i]) / H2;
 }
 
@@ -443,7 +443,7 @@ __device__ void body_tail(const TailPlan<T>& tp) {
                 for (unsigned t = threadIdx.x; t < half; t += nt) cell_rbgs_split<T>(U(l), F(l), A, h2, c, t);
                 __syncthreads();
             }
-        const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
+        const ParentMap pm(Bl, 0, 0, 0, 1);
         Lay C = Bl;   // the coarse level is the whole covered box, decoded in natural order
         C.split = 0;
         const unsigned nc = (unsigned)A.d.cells() >> 3;
@@ -463,7 +463,7 @@ __device__ void body_tail(const TailPlan<T>& tp) {
     // ascent: correct, smooth
     for (int l = nlev - 2; l >= 0; --l) {
         const Lay A = uniform(tp.lev[l].lay), Bl = uniform(tp.lev[l + 1].lay);
-        const ParentMap pm{Bl.d, {0, 0, 0}, 1, Bl.split};
+        const ParentMap pm(Bl, 0, 0, 0, 1);
         const unsigned n = (unsigned)A.d.cells();
         if (nu2 > 0 && A.split)   // red cells are rewritten unread by the first red half-sweep
             for (unsigned t = threadIdx.x; t < n >> 1; t += nt) cell_prolong_black<T>(U(l), A, U(l + 1), O(l), pm, t);
@@ -519,7 +519,7 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
     // fine interior layers and the outside coarse layer along the face normal
     const int i0 = side ? n[a] - 1 : 0, i1 = side ? n[a] - 2 : 1;
     const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
-    const int pdim[3] = {pm.pd.x, pm.pd.y, pm.pd.z};
+    const int pdim[3] = {pm.pl.d.x, pm.pl.d.y, pm.pl.d.z};
 
     // 3x3 outside coarse layer around O
     double L[3][3];
@@ -531,7 +531,7 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
             q[c] = pm.off[c] + K + dc - 1;
             if (pm.periodic)
                 for (int k = 0; k < 3; ++k) q[k] = wrap(q[k], pdim[k]);
-            L[db][dc] = (double)pu[lidx(pm.pd, pm.split, q[0], q[1], q[2])];
+            L[db][dc] = (double)pu[lidx(pm.pl.d, pm.pl.split, q[0], q[1], q[2])];
         }
     double u0[2][2], u1[2][2], g0[2][2];
     for (int jb = 0; jb < 2; ++jb)

@@ -96,13 +96,18 @@ __host__ __device__ __forceinline__ void ldecode(const Lay& L, size_t i64, int& 
 __device__ __forceinline__ size_t xcd_block() { return blockIdx.x; }
 __device__ __forceinline__ size_t lpt_block() { return blockIdx.x; }
 
-// Where a fine level's coarse representation lives inside its parent array.
+// Where a fine level's coarse representation lives inside its parent array.  Built only by the
+// constructor from the parent's layout, so its dims, storage and fast-index data agree.
 struct ParentMap {
-    Dims pd;        // parent array dims
-    int off[3];     // first covered parent cell
-    int periodic;   // parent is periodic (base or a coarsening of it)
-    int split;      // parent stored in the colour-split layout
+    Lay pl;             // parent array: dims, storage (natural or colour-split), index data
+    int off[3] = {0, 0, 0};   // first covered parent cell
+    int periodic = 0;   // parent is periodic (base or a coarsening of it)
+
+    ParentMap() = default;
+    __host__ __device__ ParentMap(const Lay& parent, int o0, int o1, int o2, int per)
+        : pl(parent), off{o0, o1, o2}, periodic(per) {}
 };
+
 
 // Covered box of a level (cells owned by the next finer level); n = 0 means none.
 struct CovBox {

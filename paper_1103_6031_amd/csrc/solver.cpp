@@ -158,10 +158,8 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
     for (int l = 0; l < P.last; ++l) {
         Level& L = P.L[l];
         Level& Q = P.L[l + 1];
-        L.pm.pd = Q.d;
-        L.pm.periodic = Q.periodic ? 1 : 0;
-        L.pm.split = Q.lay.split;
-        for (int a = 0; a < 3; ++a) L.pm.off[a] = (L.p >= 1) ? H->lev[L.p].off[a] : 0;
+        const int* o = L.p >= 1 ? H->lev[L.p].off : nullptr;
+        L.pm = ParentMap(Q.lay, o ? o[0] : 0, o ? o[1] : 0, o ? o[2] : 0, Q.periodic ? 1 : 0);
         Q.child.lo[0] = L.pm.off[0]; Q.child.lo[1] = L.pm.off[1]; Q.child.lo[2] = L.pm.off[2];
         Q.child.n[0] = L.d.x / 2; Q.child.n[1] = L.d.y / 2; Q.child.n[2] = L.d.z / 2;
     }
@@ -594,12 +592,9 @@ static size_t lpt_carve(const mg_hier* H, int what, Carver& cv, LptPlan& lp) {
 }
 
 static ParentMap parent_of(const mg_hier* H, int p) {
-    ParentMap pm{};
     const mg_level& q = H->lev[p - 1];
-    pm.pd = Dims{q.n[0], q.n[1], q.n[2]};
-    pm.periodic = p == 1;
-    for (int a = 0; a < 3; ++a) pm.off[a] = H->lev[p].off[a];
-    return pm;
+    const int* o = H->lev[p].off;
+    return ParentMap(Lay(Dims{q.n[0], q.n[1], q.n[2]}, 0), o[0], o[1], o[2], p == 1 ? 1 : 0);
 }
 
 static Dims dims_of(const mg_hier* H, int p) { return Dims{H->lev[p].n[0], H->lev[p].n[1], H->lev[p].n[2]}; }
