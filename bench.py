@@ -82,8 +82,8 @@ def recorded_traffic():
 
 def run_step(mg, H, ft, h, opts, ws):
     phi1, s1 = mg.mg_solve_level(ft, h, opts=opts, workspace=ws["solve"])
-    psi1 = mg.lpt_displacements(H, [phi1], scale=-1.0, workspace=ws["lpt1"])[0]
-    tau = mg.lpt2_source(H, [phi1], workspace=ws["lpt2"])[0]
+    psi1, tau = mg.lpt_displacements_and_source(H, [phi1], scale=-1.0, workspace=ws["lpt2"])
+    psi1, tau = psi1[0], tau[0]
     phi2, s2 = mg.mg_solve_level(tau, h, opts=opts, workspace=ws["solve"])
     psi2 = mg.lpt_displacements(H, [phi2], scale=-3.0 / 7.0, workspace=ws["lpt1"])[0]
     return (phi1, psi1, tau, phi2, psi2), (s1, s2)

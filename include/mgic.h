@@ -142,6 +142,15 @@ int lpt_displacements(const mg_hier* hier, const double* const* phi, double* con
 int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau,
                 void* workspace, size_t workspace_bytes, void* stream);
 
+/* Both of the above in one call (Section 3.1): out as lpt_displacements with this scale, tau as
+ * lpt2_source.  On the periodic base the second derivatives are taken from out itself,
+ * D_ij = G4_i out_j / scale, which saves one pass over the base; with scale = +-1 tau is
+ * bit-identical to lpt2_source's, otherwise it differs by rounding.  scale must be finite and
+ * non-zero.  Workspace: lpt_workspace_bytes(hier, 2).  Asynchronous. */
+int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, double* const* out,
+                                 double scale, double* const* tau, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
 /* ----------------------------------------------------------------------------------------------
  * Batched independent periodic solves (many small instances in one persistent launch)
  * -------------------------------------------------------------------------------------------- */

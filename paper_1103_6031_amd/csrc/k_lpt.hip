@@ -85,9 +85,12 @@ __global__ void k_psi(Src<PAD> s, Lay B, int e, double h, double* __restrict__ p
     p2[t] = g4(s, x, y, z, 2, den);
 }
 
-// tau = sum_{i>j} D_ii D_jj - D_ij^2 with D_ij = G4_i psi_j; psi periodic or padded by e
+// tau = sum_{i>j} D_ii D_jj - D_ij^2 with D_ij = G4_i psi_j; psi periodic or padded by e.  When
+// psi is a scaled gradient s G4 phi, post = 1 / s^2 brings tau back to the one of phi (post = 1:
+// not applied, so s = +-1 gives the same bits as psi = G4 phi)
 template <bool PAD>
-__global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h, double* __restrict__ tau) {
+__global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h, double post,
+                          double* __restrict__ tau) {
     const unsigned t = (unsigned)lpt_block() * blockDim.x + threadIdx.x;
     if (t >= (unsigned)B.d.cells()) return;
     int x, y, z;
@@ -103,7 +106,7 @@ __global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h
     acc = acc + (Dyy * Dxx - Dyx * Dyx);
     acc = acc + (Dzz * Dxx - Dzx * Dzx);
     acc = acc + (Dzz * Dyy - Dzy * Dzy);
-    tau[t] = acc;
+    tau[t] = post == 1.0 ? acc : acc * post;
 }
 
 // padded copy of a patch with width-R tri-quadratic ghosts from its parent
@@ -173,12 +176,19 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
     if (R == 0) {
         k_psi<false><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<false>{src, 0, d}, E, 0, h, p0, p1, p2);
         k_tau_psi<false><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{p0, 0, d}, Src<false>{p1, 0, d},
-                                                                 Src<false>{p2, 0, d}, B, h, tau);
+                                                                 Src<false>{p2, 0, d}, B, h, 1.0, tau);
     } else {
         k_psi<true><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, E, e, h, p0, p1, p2);
         k_tau_psi<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{p0, e, d}, Src<true>{p1, e, d},
-                                                                Src<true>{p2, e, d}, B, h, tau);
+                                                                Src<true>{p2, e, d}, B, h, 1.0, tau);
     }
+}
+
+void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
+                         double* tau, hipStream_t st) {
+    const Lay B(d, 0);
+    k_tau_psi<false><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{g0, 0, d}, Src<false>{g1, 0, d},
+                                                             Src<false>{g2, 0, d}, B, h, post, tau);
 }
 
 }  // namespace mgic

@@ -240,6 +240,10 @@ void launch_grad4(const double* src, int R, Dims d, double h, double scale, doub
 // tau = sum_{i>j} D_ii D_jj - D_ij^2 ; src periodic (R = 0) or padded by R >= 4; psi is scratch
 // for 3 arrays of (d + 2(R-2))^3 (d^3 when periodic)
 void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st);
+// tau on a periodic level from the three components g_c = s G4_c phi of a scaled gradient
+// (post = 1 / s^2)
+void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
+                          double* tau, hipStream_t st);
 
 // ----------------------------------------------------------------------------------------------
 // batched launches: many independent periodic instances in one grid

@@ -1497,18 +1497,20 @@ int lpt_displacements(const mg_hier* hier, const double* const* phi, double* con
     return MG_OK;
 }
 
-int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau, void* workspace,
-                size_t workspace_bytes, void* stream) {
-    hipStream_t st = (hipStream_t)stream;
-    if (!tau) return fail(MG_EINVAL, "tau is NULL");
-    LptPlan lp;
-    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp);
-    if (rc) return rc;
+}  // extern "C"
+
+namespace mgic {
+// tau on every level (composite mean removed); on the base from base_grad (s G4 phi, post =
+// 1 / s^2) when given, else from phi
+static int tau_levels(const mg_hier* hier, LptPlan& lp, double* const* tau, double* const* base_grad, double post,
+                      hipStream_t st) {
     for (int p = 0; p < hier->nlev; ++p) {
         if (!tau[p]) return fail(MG_EINVAL, "tau level pointer is NULL");
         const Dims d = dims_of(hier, p);
         const double h = h_of(hier, p);
-        if (p == 0) {
+        if (p == 0 && base_grad) {
+            launch_tau_from_grad(base_grad[0], base_grad[1], base_grad[2], d, h, post, tau[0], st);
+        } else if (p == 0) {
             launch_tau(lp.phi[0], 0, d, h, tau[0], lp.psi, st);
         } else {
             launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 4, st);
@@ -1528,6 +1530,41 @@ int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* ta
     for (int p = 0; p < hier->nlev; ++p) launch_sub_mean<double>(tau[p], dims_of(hier, p).cells(), lp.scal, inv, st);
     MG_HIP(hipGetLastError());
     return MG_OK;
+}
+}  // namespace mgic
+
+extern "C" {
+
+int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau, void* workspace,
+                size_t workspace_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!tau) return fail(MG_EINVAL, "tau is NULL");
+    LptPlan lp;
+    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp);
+    if (rc) return rc;
+    return tau_levels(hier, lp, tau, nullptr, 1.0, st);
+}
+
+int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, double* const* out, double scale,
+                                 double* const* tau, void* workspace, size_t workspace_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!out || !tau) return fail(MG_EINVAL, "out or tau is NULL");
+    if (!(scale != 0.0) || !std::isfinite(scale)) return fail(MG_EINVAL, "scale must be finite and non-zero");
+    LptPlan lp;
+    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp);
+    if (rc) return rc;
+    for (int p = 0; p < hier->nlev; ++p) {
+        if (!out[3 * p] || !out[3 * p + 1] || !out[3 * p + 2]) return fail(MG_EINVAL, "output pointer is NULL");
+        const Dims d = dims_of(hier, p);
+        const double h = h_of(hier, p);
+        if (p == 0) {
+            launch_grad4(lp.phi[0], 0, d, h, scale, out[0], out[1], out[2], st);
+        } else {
+            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 2, st);
+            launch_grad4(lp.padded, 2, d, h, scale, out[3 * p], out[3 * p + 1], out[3 * p + 2], st);
+        }
+    }
+    return tau_levels(hier, lp, tau, out, 1.0 / (scale * scale), st);
 }
 
 size_t mg_batch_workspace_bytes(int ninst, const int* n, const mg_opts* opts) {

@@ -70,6 +70,8 @@ _sig = {
     "lpt_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier), ctypes.c_int]),
     "lpt_displacements": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_double, _P, _sz, _P]),
     "lpt2_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _P, _sz, _P]),
+    "lpt_displacements_and_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_double, _PP, _P,
+                                                    _sz, _P]),
     "mg_batch_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mg_opts)]),
     "mg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                       _PP, _PP, ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
@@ -285,6 +287,23 @@ def lpt2_source(hier: Hier, phi, tau=None, workspace=None, stream=None):
     tp, _ta = _ptr_array([_dev(x, "tau") for x in tau])
     _check(_lib.lpt2_source(ctypes.byref(H), pp, tp, ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
     return tau
+
+
+def lpt_displacements_and_source(hier: Hier, phi, scale=1.0, out=None, tau=None, workspace=None, stream=None):
+    """Displacements (as lpt_displacements) and tau (as lpt2_source) in one call.
+    Returns (list of [psi_x, psi_y, psi_z] per level, list of tau per level)."""
+    if out is None:
+        out = [[torch.empty_like(x) for _ in range(3)] for x in phi]
+    if tau is None:
+        tau = [torch.empty_like(x) for x in phi]
+    H = hier.c_struct()
+    ws = _ws(workspace, lpt_workspace_bytes(hier, 2))
+    pp, _pa = _ptr_array([_dev(x, "phi") for x in phi])
+    op, _oa = _ptr_array([_dev(c, "out") for lvl in out for c in lvl])
+    tp, _ta = _ptr_array([_dev(x, "tau") for x in tau])
+    _check(_lib.lpt_displacements_and_source(ctypes.byref(H), pp, op, float(scale), tp, ctypes.c_void_p(ws.ptr),
+                                             ws.nbytes, _stream(stream)))
+    return out, tau
 
 
 def mg_batch_workspace_bytes(sizes, opts=None) -> int:

@@ -90,3 +90,30 @@ def test_plane_wave_tau_vanishes_on_gpu(mg):
     note("plane wave tau")
     t = mg.lpt2_source(mg.Hier(N, 1.0), [to_dev(phi)])[0]
     assert np.max(np.abs(to_host(t))) < 1e-13
+
+
+@pytest.mark.parametrize("layout", ["periodic", "deep"])
+def test_displacements_and_source_in_one_call(mg, layout):
+    """psi and tau from the combined entry point equal the separate calls: bit for bit with
+    scale -1, within rounding with another scale."""
+    if layout == "periodic":
+        N = 32
+        Hg = mg.Hier(N, 100.0 / N)
+        phi = [to_dev(inputs.gaussian_field(N, 41))]
+    else:
+        patches = [((16, 16, 16), (4, 4, 4)), ((12, 12, 16), (4, 4, 4))]
+        Hg = mg.Hier(16, 100.0 / 16, patches)
+        f = inputs.nested_fields(16, patches, 43)
+        phi, _ = mg.mg_solve_hierarchy(Hg, [to_dev(a) for a in f], opts=mg.make_opts(tol=1e-12, max_cycles=60))
+    note("combined displacements and tau, %s" % layout)
+    for scale, exact in ((-1.0, True), (-3.0 / 7.0, False)):
+        psi, tau = mg.lpt_displacements_and_source(Hg, phi, scale=scale)
+        psi_s = mg.lpt_displacements(Hg, phi, scale=scale)
+        tau_s = mg.lpt2_source(Hg, phi)
+        for p in range(Hg.nlev):
+            for c in range(3):
+                assert np.array_equal(to_host(psi[p][c]), to_host(psi_s[p][c]))
+            if exact:
+                assert np.array_equal(to_host(tau[p]), to_host(tau_s[p]))
+            else:
+                assert rel_max(to_host(tau[p]), to_host(tau_s[p])) <= 1e-13
