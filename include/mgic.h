@@ -79,7 +79,8 @@ typedef struct {
     int nu1, nu2;       /* pre / post red-black Gauss-Seidel sweeps (the paper uses 2 / 2)            */
     int prec;           /* MG_FP64 or MG_MIXED                                                        */
     unsigned flags;     /* MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES                                     */
-    int inner;          /* mixed only: FP32 V-cycles per FP64 correction step; 0 = default (2)        */
+    int inner;          /* mixed only: FP32 V-cycles per FP64 correction (1..16); 0 = chosen per      */
+                        /* correction from the measured contraction, at most 3                      */
 } mg_opts;
 
 typedef struct {

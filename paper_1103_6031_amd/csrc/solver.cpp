@@ -392,6 +392,22 @@ static int read_scalars(Plan& P, int first, int count, double* out, hipStream_t 
     return MG_OK;
 }
 
+// FP32 inner cycles for the next FP64 correction of the mixed-precision solve.  opt > 0 fixes the
+// count.  Otherwise (the default) it is chosen from the residuals: each inner cycle contracts the
+// error roughly tenfold, far above FP32 round-off, so up to kInnerMax cycles run per correction;
+// once two corrections have been measured, the observed contraction per cycle, rho, predicts how
+// many cycles bring rel below tol, and no more than that many run.  The rule reads only the
+// residual history, so a batched solve makes the same choices as a solo one.
+constexpr int kInnerMax = 3;
+static int inner_count(int opt, bool fixed, double rel, double prev_rel, int prev_n, double tol) {
+    if (opt > 0) return opt;
+    if (fixed || prev_n <= 0 || !(prev_rel > 0) || !(rel > 0) || !std::isfinite(rel) || !(tol > 0)) return kInnerMax;
+    const double rho = std::pow(rel / prev_rel, 1.0 / prev_n);
+    if (!(rho > 0) || rho >= 0.5) return kInnerMax;
+    const double m = std::ceil(std::log(tol / rel) / std::log(rho));
+    return (int)std::min<double>(kInnerMax, std::max(1.0, m));
+}
+
 static int solve(const mg_hier* H, const double* const* f, double* const* u, const mg_opts* o, mg_stats* stats,
                  void* ws, size_t ws_bytes, hipStream_t st) {
     if (!o) return fail(MG_EINVAL, "options are NULL");
@@ -425,9 +441,8 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     mg_stats S;
     std::memset(&S, 0, sizeof(S));
     for (double& v : S.res_hist) v = NAN;
-    // FP32 inner cycles per FP64 correction: each inner cycle contracts the error about tenfold,
-    // far above FP32 round-off, so two of them per correction halve the FP64 residual passes
-    const int inner = o->inner > 0 ? o->inner : 2;
+    double check_prev = NAN;   // relative residual at the previous FP64 correction
+    int last_inner = 0;        // inner cycles run since it
     double fs[2] = {0, 0};
     double fnorm2 = 0;
     if (!fixed) {
@@ -496,9 +511,13 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
                 if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
             }
             if (cycles >= o->max_cycles) break;
-            for (int k = 0; k < inner && cycles < o->max_cycles; ++k) {
+            const int nin = inner_count(o->inner, fixed, rel, check_prev, last_inner, o->tol);
+            check_prev = rel;
+            last_inner = 0;
+            for (int k = 0; k < nin && cycles < o->max_cycles; ++k) {
                 vcycle<float>(P, 0, st, /*skip_first_red=*/k == 0);
                 ++cycles;
+                ++last_inner;
                 S.cell_updates += upc;
             }
             pending = true;
@@ -517,9 +536,13 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             }
             if (cycles >= o->max_cycles) break;
             for (int l = 0; l < P.nh; ++l) launch_fill<float>(P.L[l].u32, P.L[l].d.cells(), 0.0f, st);
-            for (int k = 0; k < inner && cycles < o->max_cycles; ++k) {
+            const int nin = inner_count(o->inner, fixed, rel, check_prev, last_inner, o->tol);
+            check_prev = rel;
+            last_inner = 0;
+            for (int k = 0; k < nin && cycles < o->max_cycles; ++k) {
                 vcycle<float>(P, 0, st);
                 ++cycles;
+                ++last_inner;
                 S.cell_updates += upc;
             }
             for (int l = 0; l < P.nh; ++l) launch_add_f32_to_f64(P.L[l].u, P.L[l].u32, P.L[l].d.cells(), st);
@@ -991,6 +1014,8 @@ static void b_vcycle(BatchPlan& B, int ti, int par, bool skip_first_red, hipStre
 struct InstState {
     int cycles = 0, status = 1 /* running */, grow = 0, par = 0;
     double rel = NAN, prev = INFINITY, fnorm2 = 0;
+    double check_prev = NAN;   // mixed: relative residual at the previous FP64 correction
+    int last_inner = 0;        // mixed: inner cycles run since it
     bool active = true;
     bool early = false;   // stopped before the first cycle (non-finite source): u is not written
 };
@@ -1029,7 +1054,6 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
     const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
     const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
     const bool use_graph = (o->flags & MG_NO_GRAPH) == 0;
-    const int inner = o->inner > 0 ? o->inner : 2;
     B.mixed = o->prec == MG_MIXED;
     MG_HIP(batch_kernel_setup());   // function attributes must be set outside any graph capture
     for (int i = 0; i < ni; ++i) {
@@ -1239,7 +1263,7 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         }
     };
     const std::string wkey = std::to_string((uintptr_t)ws) + "|" + batch_key(B, B.mixed ? 0 : 1) + "|" +
-                             std::to_string(o->nu2) + "|" + std::to_string(inner) + "|" +
+                             std::to_string(o->nu2) + "|" +
                              std::to_string(B.segs.size()) + "|" + (fixed ? "f" : "c");
     if (B.mixed) {
         bool first = true;
@@ -1256,20 +1280,34 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
             if (!fixed) MG_HIP(hipStreamSynchronize(st));
             decide(par);
             if (!any_active()) break;
+            // inner cycles per instance by the same rule as a solo solve; the k-th cycle of the
+            // round runs on the instances that asked for more than k (one graph per cycle)
+            std::vector<int> nin(ni, 0);
+            std::vector<char> solving(ni, 0);
+            int rounds = 0;
+            for (int i = 0; i < ni; ++i) {
+                solving[i] = S[i].active;
+                if (!S[i].active) continue;
+                nin[i] = std::min(inner_count(o->inner, fixed, S[i].rel, S[i].check_prev, S[i].last_inner, o->tol),
+                                  o->max_cycles - S[i].cycles);
+                S[i].check_prev = S[i].rel;
+                S[i].last_inner = nin[i];
+                rounds = std::max(rounds, nin[i]);
+            }
+            for (int k = 0; k < rounds; ++k) {
+                for (int i = 0; i < ni; ++i) S[i].active = solving[i] && k < nin[i];
+                if ((rc = upload_flags())) return rc;
+                rc = run_graph(use_graph, wkey + "|vc" + std::to_string(par) + (k == 0 ? "f" : "n"), st,
+                               [&](hipStream_t s) { b_vcycle<float>(B, 0, par, k == 0, s); });
+                if (rc) return rc;
+                for (int i = 0; i < ni; ++i)
+                    if (S[i].active) {
+                        ++S[i].cycles;
+                        out[i].cell_updates += updates_per_cycle(B.P[i]);
+                    }
+            }
+            for (int i = 0; i < ni; ++i) S[i].active = solving[i];
             if ((rc = upload_flags())) return rc;
-            int cyc = 0;
-            for (auto& s : S)
-                if (s.active) cyc = s.cycles;
-            const int nin = std::min(inner, o->max_cycles - cyc);
-            rc = run_graph(use_graph && nin == inner, wkey + "|inner" + std::to_string(par), st, [&](hipStream_t s) {
-                for (int k = 0; k < nin; ++k) b_vcycle<float>(B, 0, par, k == 0, s);
-            });
-            if (rc) return rc;
-            for (int i = 0; i < ni; ++i)
-                if (S[i].active) {
-                    S[i].cycles += nin;
-                    out[i].cell_updates += (long long)nin * updates_per_cycle(B.P[i]);
-                }
             first = false;
             par ^= 1;
         }
