@@ -784,6 +784,70 @@ __global__ void k_sum(const double* __restrict__ a, Lay L, CovBox cb, int square
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
+// Fused passes of the source preparation and of the final gauge on a level (natural user rows
+// <-> the level's layout).  The reductions stride exactly like body_sum over the level array, so
+// their partial sums have the same bits as a separate copy followed by body_sum.
+// dst (layout L) = src (natural rows); partial sums of the copied values
+__device__ __forceinline__ double body_relayout_sum(const double* __restrict__ src, double* __restrict__ dst,
+                                                    const Lay& L, unsigned blk, unsigned nblk) {
+    double acc = 0.0;
+    const unsigned n = (unsigned)L.d.cells();
+    const unsigned lo = red_lo(blk), stride = red_stride(nblk);
+    for (unsigned b0 = lo + threadIdx.x; b0 < n; b0 += stride)
+#pragma unroll
+    for (int v = 0; v < kRedV; ++v) {
+        const unsigned i = b0 + v * blockDim.x;
+        if (i >= n) break;
+        int x, y, z;
+        ldecode(L, i, x, y, z);
+        const double av = src[lidx(L.d, 0, x, y, z)];
+        dst[i] = av;
+        acc += av;
+    }
+    return acc;
+}
+// a -= sum * inv (as k_sub_mean); partial sums of the new values squared
+__device__ __forceinline__ double body_submean_sumsq(double* __restrict__ a, const Lay& L,
+                                                     const double* __restrict__ sum, double inv, unsigned blk,
+                                                     unsigned nblk) {
+    const double m = sum[0] * inv;
+    double acc = 0.0;
+    const unsigned n = (unsigned)L.d.cells();
+    const unsigned lo = red_lo(blk), stride = red_stride(nblk);
+    for (unsigned b0 = lo + threadIdx.x; b0 < n; b0 += stride)
+#pragma unroll
+    for (int v = 0; v < kRedV; ++v) {
+        const unsigned i = b0 + v * blockDim.x;
+        if (i >= n) break;
+        const double av = a[i] - m;
+        a[i] = av;
+        acc += av * av;
+    }
+    return acc;
+}
+
+__global__ void k_relayout_sum(const double* __restrict__ src, double* __restrict__ dst, Lay L,
+                               double* __restrict__ partials) {
+    const double bs = block_sum(body_relayout_sum(src, dst, L, blockIdx.x, gridDim.x));
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+__global__ void k_submean_sumsq(double* __restrict__ a, Lay L, const double* __restrict__ sum, double inv,
+                                double* __restrict__ partials) {
+    const double bs = block_sum(body_submean_sumsq(a, L, sum, inv, blockIdx.x, gridDim.x));
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+// dst (layout LD) = src (layout LS) - sum * inv: the copy back of the gauge's mean removal
+__global__ void k_relayout_sub(const double* __restrict__ src, Lay LS, double* __restrict__ dst, Lay LD,
+                               const double* __restrict__ sum, double inv) {
+    const double m = sum[0] * inv;
+    const size_t n = LD.d.cells();
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        ldecode(LD, i, x, y, z);
+        dst[i] = src[lidx(LS, x, y, z)] - m;
+    }
+}
+
 // w * sum(partials[0..cnt)), added to total on thread 0, in a fixed order
 __device__ __forceinline__ void body_finalize_seg(const double* __restrict__ partials, int cnt, double w,
                                                   double& total) {
@@ -910,6 +974,22 @@ void launch_sum(const double* a, Lay L, CovBox cov, int square, double* partials
     const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
     k_sum<<<g, kBlock, 0, st>>>(a, L, cov, square, partials);
     *nparts = g;
+}
+
+void launch_relayout_sum(const double* src, double* dst, Lay L, double* partials, int* nparts, hipStream_t st) {
+    const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
+    k_relayout_sum<<<g, kBlock, 0, st>>>(src, dst, L, partials);
+    *nparts = g;
+}
+void launch_submean_sumsq(double* a, Lay L, const double* sum, double inv, double* partials, int* nparts,
+                          hipStream_t st) {
+    const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
+    k_submean_sumsq<<<g, kBlock, 0, st>>>(a, L, sum, inv, partials);
+    *nparts = g;
+}
+void launch_relayout_sub(const double* src, Lay ls, double* dst, Lay ld, const double* sum, double inv,
+                         hipStream_t st) {
+    k_relayout_sub<<<grid_for(ld.d.cells(), kBlock, 8192), kBlock, 0, st>>>(src, ls, dst, ld, sum, inv);
 }
 
 void launch_finalize(const double* partials, SegList segs, double* out, hipStream_t st) {
@@ -1041,6 +1121,25 @@ __global__ void kb_finalize(const BFin* __restrict__ fins, const int* __restrict
     if (threadIdx.x == 0) f.out[0] = total;
 }
 
+// a = {src (natural rows), dst (layout L)}: the copy-in with its sum
+__global__ void kb_relayout_sum(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L;
+    const double bs = block_sum(body_relayout_sum((const double*)s.a[0], (double*)s.a[1], L, lb, s.nblk));
+    if (threadIdx.x == 0) s.part[lb] = bs;
+}
+// a = {array (layout L), sum}, h = 1 / cells: mean removal with the sum of squares
+__global__ void kb_submean_sumsq(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay L = s.L;
+    const double bs = block_sum(body_submean_sumsq((double*)s.a[0], L, (const double*)s.a[1], s.h, lb, s.nblk));
+    if (threadIdx.x == 0) s.part[lb] = bs;
+}
+
 // grid-stride loops over one instance's cells with its own blocks
 __global__ void kb_sub_mean(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
     unsigned lb;
@@ -1050,6 +1149,23 @@ __global__ void kb_sub_mean(const BSeg* __restrict__ segs, int nseg, const int* 
     const double m = ((const double*)s.a[1])[0] * s.h;
     const size_t n = s.L.d.cells();
     for (size_t i = lb * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)s.nblk * blockDim.x) a[i] = a[i] - m;
+}
+
+// a = {src (layout L), dst (layout C), sum}, h = 1 / cells: the copy back with the mean removed
+__global__ void kb_relayout_sub(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
+    unsigned lb;
+    const BSeg& s = seg_of(segs, nseg, lb);
+    if (!active[s.inst]) return;
+    const Lay ls = s.L, ld = s.C;
+    const double* src = (const double*)s.a[0];
+    double* dst = (double*)s.a[1];
+    const double m = ((const double*)s.a[2])[0] * s.h;
+    const size_t n = ld.d.cells();
+    for (size_t i = lb * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)s.nblk * blockDim.x) {
+        int x, y, z;
+        ldecode(ld, i, x, y, z);
+        dst[i] = src[lidx(ls, x, y, z)] - m;
+    }
 }
 
 __global__ void kb_relayout(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active) {
@@ -1130,6 +1246,15 @@ void launch_b_finalize(const BFin* fins, int n, const int* active, hipStream_t s
 }
 void launch_b_sub_mean(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
     kb_sub_mean<<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+void launch_b_relayout_sum(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_relayout_sum<<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+void launch_b_submean_sumsq(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_submean_sumsq<<<grid, kBlock, 0, st>>>(segs, nseg, active);
+}
+void launch_b_relayout_sub(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
+    kb_relayout_sub<<<grid, kBlock, 0, st>>>(segs, nseg, active);
 }
 void launch_b_relayout(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
     kb_relayout<<<grid, kBlock, 0, st>>>(segs, nseg, active);

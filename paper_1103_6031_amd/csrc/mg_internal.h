@@ -229,6 +229,13 @@ void launch_outer_split(const double* u_in, const float* e_in, const double* f, 
 // per-block partial sums of a (or a^2) over cells outside cov
 void launch_sum(const double* a, Lay L, CovBox cov, int square, double* partials, int* nparts, hipStream_t st);
 void launch_finalize(const double* partials, SegList segs, double* out, hipStream_t st);
+// fused passes (partials as launch_sum over the level array): dst (layout L) = src (natural) with
+// the sum of the values; a -= sum * inv with the sum of squares; dst (ld) = src (ls) - sum * inv
+void launch_relayout_sum(const double* src, double* dst, Lay L, double* partials, int* nparts, hipStream_t st);
+void launch_submean_sumsq(double* a, Lay L, const double* sum, double inv, double* partials, int* nparts,
+                          hipStream_t st);
+void launch_relayout_sub(const double* src, Lay ls, double* dst, Lay ld, const double* sum, double inv,
+                         hipStream_t st);
 
 // LPT: padded copy with tri-quadratic ghosts of width R from the parent (covered parent cells
 // must already hold the mean of their children)
@@ -305,6 +312,11 @@ void launch_b_finalize(const BFin* fins, int n, const int* active, hipStream_t s
 void launch_b_sub_mean(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
 // a = {src, dst}: dst (layout C) = src (layout L)
 void launch_b_relayout(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
+// the fused passes of launch_relayout_sum / launch_submean_sumsq / launch_relayout_sub per segment:
+// a = {src natural, dst}; a = {array, sum} with h = 1 / cells; a = {src, dst, sum} with h = 1 / cells
+void launch_b_relayout_sum(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
+void launch_b_submean_sumsq(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
+void launch_b_relayout_sub(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
 // a = {p}: p = 0 over L's cells
 template <class T> void launch_b_zero(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
 

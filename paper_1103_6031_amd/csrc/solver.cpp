@@ -358,6 +358,22 @@ static void composite_residual(Plan& P, R* const* rout, bool rout_natural, hipSt
 
 // f working copies: copy, restrict bottom-up, subtract the composite mean; |f|^2 -> scal[S_FNORM]
 static int prepare_f(Plan& P, const double* const* f_user, hipStream_t st) {
+    if (P.nh == 1 && P.L[0].lay.split) {
+        // one periodic level: copy-in with the sum, then mean removal with the sum of squares
+        // (the same partial sums, so the same bits, as the separate passes below)
+        Level& L = P.L[0];
+        if (!f_user[0]) return fail(MG_EINVAL, "f pointer is NULL");
+        int np = 0;
+        launch_relayout_sum(f_user[0], L.f, L.lay, P.partials, &np, st);
+        SegList s{};
+        s.n = 1; s.off[0] = 0; s.cnt[0] = np; s.w[0] = 1.0;
+        launch_finalize(P.partials, s, P.scal + S_FSUM, st);
+        launch_submean_sumsq(L.f, L.lay, P.scal + S_FSUM, 1.0 / (double)L.d.cells(), P.partials, &np, st);
+        s.cnt[0] = np;
+        s.w[0] = L.h * L.h * L.h;
+        launch_finalize(P.partials, s, P.scal + S_FNORM, st);
+        return MG_OK;
+    }
     for (int l = 0; l < P.nh; ++l) {
         if (!f_user[P.L[l].p]) return fail(MG_EINVAL, "f pointer is NULL");
         launch_relayout<double, double>(f_user[P.L[l].p], mklay(P.L[l].d, 0), P.L[l].f, P.L[l].lay, st);
@@ -548,10 +564,17 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             for (int l = 0; l < P.nh; ++l) launch_add_f32_to_f64(P.L[l].u, P.L[l].u32, P.L[l].d.cells(), st);
         }
     }
-    gauge_u(P, st);
-    for (int l = 0; l < P.nh; ++l) {
-        Level& L = P.L[l];
-        if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, mklay(L.d, 0), st);
+    if (P.nh == 1 && P.L[0].u != P.L[0].u_user) {
+        // one periodic level: its sum, then the copy back with the mean removed
+        Level& L = P.L[0];
+        base_sum(P, L.u, S_USUM, st);
+        launch_relayout_sub(L.u, L.lay, L.u_user, mklay(L.d, 0), P.scal + S_USUM, 1.0 / (double)L.d.cells(), st);
+    } else {
+        gauge_u(P, st);
+        for (int l = 0; l < P.nh; ++l) {
+            Level& L = P.L[l];
+            if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, mklay(L.d, 0), st);
+        }
     }
     MG_HIP(hipGetLastError());
     if (fixed) {
@@ -683,7 +706,7 @@ struct BatchPlan {
     // static tables: [0] float, [1] double; float tables by parity of the finest correction buffer
     std::vector<BSeg> segs;
     std::vector<BLaunch> sm[2][2], rr[2][2], fas[2][2], pr[2][2];
-    BLaunch outer[2], resid, sumf;
+    BLaunch outer[2], resid;
     std::vector<TailPlan<float>> tpf;
     std::vector<TailPlan<double>> tpd;
     unsigned lds_f = 0, lds_d = 0;
@@ -1115,18 +1138,6 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         }
         B.resid = add_launch(B.segs, v);
     }
-    {
-        std::vector<BSeg> v;
-        for (int i = 0; i < ni; ++i) {
-            Level& L = B.P[i].L[0];
-            BSeg s = seg0(i, red_blocks(L.d.cells()));
-            s.L = L.lay;
-            s.part = B.P[i].partials;
-            s.a[0] = L.f;
-            v.push_back(s);
-        }
-        B.sumf = add_launch(B.segs, v);
-    }
     B.fins.assign((size_t)F_COUNT * ni, BFin{});
     for (int i = 0; i < ni; ++i) {
         Level& L = B.P[i].L[0];
@@ -1144,15 +1155,16 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         Level& L = B.P[i].L[0];
         const int id = B.ids[i];
         const size_t cells = L.d.cells();
-        BSeg s = seg0(i, (unsigned)grid_for(cells, kBlock, 8192));
-        s.L = Lay(L.d, 0);
-        s.C = L.lay;
+        BSeg s = seg0(i, red_blocks(cells));      // copy-in with the sum (as the solo solve)
+        s.L = L.lay;
+        s.part = B.P[i].partials;
         s.a[0] = (void*)f[id];
         s.a[1] = L.f;
         fin_rel.push_back(s);
-        s = seg0(i, (unsigned)grid_for(cells, kBlock, 4096));
+        s = seg0(i, red_blocks(cells));           // mean removal with the sum of squares
         s.L = L.lay;
         s.h = 1.0 / (double)cells;
+        s.part = B.P[i].partials;
         s.a[0] = L.f;
         s.a[1] = B.bscal + (size_t)i * S_COUNT + S_FSUM;
         sub_f.push_back(s);
@@ -1203,11 +1215,9 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
     const size_t nscal = (size_t)ni * S_COUNT;
 
     // source preparation (a1): working copy, mean, mean removal, norm
-    launch_b_relayout(sd + la_frel.off, la_frel.n, la_frel.grid, act, st);
-    launch_b_sum(sd + B.sumf.off, B.sumf.n, B.sumf.grid, act, 0, st);
+    launch_b_relayout_sum(sd + la_frel.off, la_frel.n, la_frel.grid, act, st);
     launch_b_finalize(B.fins_dev + F_FSUM * ni, ni, act, st);
-    launch_b_sub_mean(sd + la_subf.off, la_subf.n, la_subf.grid, act, st);
-    launch_b_sum(sd + B.sumf.off, B.sumf.n, B.sumf.grid, act, 1, st);
+    launch_b_submean_sumsq(sd + la_subf.off, la_subf.n, la_subf.grid, act, st);
     launch_b_finalize(B.fins_dev + F_FNORM * ni, ni, act, st);
     if (guess) launch_b_relayout(sd + la_uinit.off, la_uinit.n, la_uinit.grid, act, st);
     else launch_b_zero<double>(sd + la_uinit.off, la_uinit.n, la_uinit.grid, act, st);
@@ -1351,7 +1361,7 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         }
     }
     // gauge (zero mean) and conversion back, for every instance that reached the loop
-    std::vector<BSeg> osum, osub, orel;
+    std::vector<BSeg> osum, orel;
     for (int i = 0; i < ni; ++i) {
         S[i].active = !S[i].early;
         Level& L = B.P[i].L[0];
@@ -1362,30 +1372,24 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         s.part = B.P[i].partials;
         s.a[0] = uf;
         osum.push_back(s);
-        s = seg0(i, (unsigned)grid_for(cells, kBlock, 4096));
-        s.L = L.lay;
-        s.h = 1.0 / (double)cells;
-        s.a[0] = uf;
-        s.a[1] = B.bscal + (size_t)i * S_COUNT + S_USUM;
-        osub.push_back(s);
-        s = seg0(i, (unsigned)grid_for(cells, kBlock, 8192));
+        s = seg0(i, (unsigned)grid_for(cells, kBlock, 8192));   // copy back with the mean removed
         s.L = L.lay;
         s.C = Lay(L.d, 0);
+        s.h = 1.0 / (double)cells;
         s.a[0] = uf;
         s.a[1] = u[B.ids[i]];
+        s.a[2] = B.bscal + (size_t)i * S_COUNT + S_USUM;
         orel.push_back(s);
     }
     std::vector<BSeg> tail_tab(B.segs.begin(), B.segs.begin() + out_off);
     const BLaunch la_osum = add_launch(tail_tab, osum);
-    const BLaunch la_osub = add_launch(tail_tab, osub);
     const BLaunch la_orel = add_launch(tail_tab, orel);
     MG_HIP(hipMemcpyAsync(sd + out_off, tail_tab.data() + out_off, (tail_tab.size() - out_off) * sizeof(BSeg),
                           hipMemcpyHostToDevice, st));
     if ((rc = upload_flags())) return rc;
     launch_b_sum(sd + la_osum.off, la_osum.n, la_osum.grid, act, 0, st);
     launch_b_finalize(B.fins_dev + F_USUM * ni, ni, act, st);
-    launch_b_sub_mean(sd + la_osub.off, la_osub.n, la_osub.grid, act, st);
-    launch_b_relayout(sd + la_orel.off, la_orel.n, la_orel.grid, act, st);
+    launch_b_relayout_sub(sd + la_orel.off, la_orel.n, la_orel.grid, act, st);
     MG_HIP(hipGetLastError());
     MG_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < ni; ++i) {
