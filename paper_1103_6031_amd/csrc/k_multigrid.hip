@@ -707,7 +707,9 @@ __global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ 
 }
 
 // One outer step of the mixed-precision defect correction on a colour-split periodic level:
-//   v   = u_in + (double) e_in          (the pending FP32 correction; e_in == nullptr: none)
+//   v   = u_in + (double) e_in          (the pending FP32 correction; e_in == nullptr: none;
+//                                        u_in == nullptr: v = 0, the first step of a zero start,
+//                                        which then streams f only)
 //   r   = f - L v                        (FP64, same arithmetic as k_residual_split)
 //   u_out = v,  rhs = (float) r,  e_out = the first red half-sweep of the next inner cycle from
 //   e = 0, i.e. (0 - h^2 rhs) / 6 on red cells; black entries are not written.
@@ -729,10 +731,13 @@ __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_
         const unsigned j = c.j, col = c.col, oth = c.oth, r0 = c.r0, rxm = c.rxm, rxp = c.rxp, rym = c.rym,
                        ryp = c.ryp, jm = c.jm, jp = c.jp;
         const int x = c.x, y = c.y, q = c.q;
-        auto V = [&](unsigned i) { return e_in ? u_in[i] + (double)e_in[i] : u_in[i]; };
-        const double c0 = V(t);
-        const double s = ((V(rxm + oth + j) + V(rxp + oth + j)) + (V(rym + oth + j) + V(ryp + oth + j))) +
-                         (V(r0 + oth + jm) + V(r0 + oth + jp));
+        double c0 = 0.0, s = 0.0;   // u_in == nullptr: a zero start, whose stencil sums are +0 exactly
+        if (u_in) {
+            auto V = [&](unsigned i) { return e_in ? u_in[i] + (double)e_in[i] : u_in[i]; };
+            c0 = V(t);
+            s = ((V(rxm + oth + j) + V(rxp + oth + j)) + (V(rym + oth + j) + V(ryp + oth + j))) +
+                (V(r0 + oth + jm) + V(r0 + oth + jp));
+        }
         const double r = f[t] - (s - 6.0 * c0) / h2;
         acc += r * r;
         const float rf = (float)r;
@@ -1079,12 +1084,13 @@ __global__ void __launch_bounds__(kTailThreads) kb_tail(const TailPlan<T>* __res
     body_tail<T>(sp);
 }
 
-__global__ void kb_outer(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active, int has_e) {
+__global__ void kb_outer(const BSeg* __restrict__ segs, int nseg, const int* __restrict__ active, int has_e,
+                         int zero_u) {
     unsigned lb;
     const BSeg& s = seg_of(segs, nseg, lb);
     if (!active[s.inst]) return;
     const Lay L = s.L;
-    const double acc = body_outer_split((const double*)s.a[0], has_e ? (const float*)s.a[1] : nullptr,
+    const double acc = body_outer_split(zero_u ? nullptr : (const double*)s.a[0], has_e ? (const float*)s.a[1] : nullptr,
                                         (const double*)s.a[2], (double*)s.a[3], (float*)s.a[4], (float*)s.a[5], L,
                                         s.h * s.h, (float)(s.h * s.h), lb, s.nblk);
     const double bs = block_sum(acc);
@@ -1232,8 +1238,9 @@ template <class T>
 void launch_b_tail(const TailPlan<T>* plans, int n, unsigned lds_bytes, const int* active, hipStream_t st) {
     kb_tail<T><<<n, kTailThreads, lds_bytes, st>>>(plans, active);
 }
-void launch_b_outer(const BSeg* segs, int nseg, unsigned grid, const int* active, int has_e, hipStream_t st) {
-    kb_outer<<<grid, kBlock, 0, st>>>(segs, nseg, active, has_e);
+void launch_b_outer(const BSeg* segs, int nseg, unsigned grid, const int* active, int has_e, int zero_u,
+                    hipStream_t st) {
+    kb_outer<<<grid, kBlock, 0, st>>>(segs, nseg, active, has_e, zero_u);
 }
 void launch_b_residual(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st) {
     kb_residual<<<grid, kBlock, 0, st>>>(segs, nseg, active);

@@ -223,7 +223,7 @@ template <class T, class R> void launch_residual(const T* u, const T* f, const T
                                                  hipStream_t st);
 // fused outer step of the mixed-precision defect correction on a colour-split periodic level:
 // u_out = u_in + e_in, rhs = (float)(f - L u_out), red e_out = first red half-sweep from e = 0;
-// per-block partial sums of r^2
+// per-block partial sums of r^2.  u_in == nullptr: u_in = 0 (not read), e_in must be null too
 void launch_outer_split(const double* u_in, const float* e_in, const double* f, double* u_out, float* rhs,
                         float* e_out, Lay L, double h, double* partials, int* nparts, hipStream_t st);
 // per-block partial sums of a (or a^2) over cells outside cov
@@ -301,8 +301,10 @@ hipError_t batch_kernel_setup();
 // the single-workgroup tails of n instances, one workgroup each
 template <class T> void launch_b_tail(const TailPlan<T>* plans, int n, unsigned lds_bytes, const int* active,
                                       hipStream_t st);
-// a = {u_in, e_in, f, u_out, rhs, e_out}: fused mixed-precision outer step (e_in unused if !has_e)
-void launch_b_outer(const BSeg* segs, int nseg, unsigned grid, const int* active, int has_e, hipStream_t st);
+// a = {u_in, e_in, f, u_out, rhs, e_out}: fused mixed-precision outer step (e_in unused if !has_e;
+// zero_u: u_in is taken as zero and not read)
+void launch_b_outer(const BSeg* segs, int nseg, unsigned grid, const int* active, int has_e, int zero_u,
+                    hipStream_t st);
 // a = {u, f}: FP64 residual partial sums
 void launch_b_residual(const BSeg* segs, int nseg, unsigned grid, const int* active, hipStream_t st);
 // a = {v}: partial sums of v (square: of v^2)

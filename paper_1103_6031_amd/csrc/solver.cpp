@@ -448,8 +448,12 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     if (rc) return rc;
     const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
     const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
+    // a zero start of the fused mixed-precision path needs no fill: its first outer step takes
+    // u as zero without reading it and writes the zero iterate itself
+    const bool zero_start = !guess && P.mixed && P.L[0].ualt;
     for (int l = 0; l < P.nh; ++l) {
         Level& L = P.L[l];
+        if (zero_start) continue;
         if (!guess) launch_fill<double>(L.u, L.d.cells(), 0.0, st);
         else if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, mklay(L.d, 0), L.u, L.lay, st);
     }
@@ -512,8 +516,8 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
         bool pending = false;
         for (;;) {
             int np = 0;
-            launch_outer_split(L.u, pending ? L.u32 : nullptr, L.f, L.ualt, L.f32, L.ealt, L.lay, L.h, P.partials,
-                               &np, st);
+            launch_outer_split((zero_start && !pending) ? nullptr : L.u, pending ? L.u32 : nullptr, L.f, L.ualt, L.f32,
+                               L.ealt, L.lay, L.h, P.partials, &np, st);
             std::swap(L.u, L.ualt);
             std::swap(L.u32, L.ealt);
             SegList sg{};
@@ -1219,8 +1223,9 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
     launch_b_finalize(B.fins_dev + F_FSUM * ni, ni, act, st);
     launch_b_submean_sumsq(sd + la_subf.off, la_subf.n, la_subf.grid, act, st);
     launch_b_finalize(B.fins_dev + F_FNORM * ni, ni, act, st);
+    // a zero start of the mixed path needs no fill (its first outer step takes u as zero)
     if (guess) launch_b_relayout(sd + la_uinit.off, la_uinit.n, la_uinit.grid, act, st);
-    else launch_b_zero<double>(sd + la_uinit.off, la_uinit.n, la_uinit.grid, act, st);
+    else if (!B.mixed) launch_b_zero<double>(sd + la_uinit.off, la_uinit.n, la_uinit.grid, act, st);
     MG_HIP(hipMemcpyAsync(pin, B.bscal, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
     MG_HIP(hipStreamSynchronize(st));
     std::vector<mg_stats> out(ni);
@@ -1279,10 +1284,10 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         bool first = true;
         int par = 0;
         while (any_active()) {
-            const std::string k = wkey + (first ? "|outer0" : (par ? "|outer1" : "|outer2"));
+            const std::string k = wkey + (first ? (guess ? "|outer0g" : "|outer0z") : (par ? "|outer1" : "|outer2"));
             rc = run_graph(use_graph, k, st, [&](hipStream_t s) {
                 const BLaunch& ol = B.outer[par];
-                launch_b_outer(sd + ol.off, ol.n, ol.grid, act, first ? 0 : 1, s);
+                launch_b_outer(sd + ol.off, ol.n, ol.grid, act, first ? 0 : 1, (first && !guess) ? 1 : 0, s);
                 launch_b_finalize(B.fins_dev + F_RNORM * ni, ni, act, s);
                 (void)hipMemcpyAsync(pin, B.bscal, nscal * sizeof(double), hipMemcpyDeviceToHost, s);
             });
