@@ -1,0 +1,239 @@
+// Fused small-level kernels of the FAS V-cycle (Section 3.2) for the periodic coarsenings that
+// are power-of-two cubes of 32^3 and 64^3 cells.
+//
+// As one-step kernels each such level costs eleven launches per cycle (FAS right-hand side,
+// 2 nu1 half-sweeps, residual + restriction, prolongation, 2 nu2 half-sweeps), and at these sizes
+// every launch costs about its dispatch latency.  Here one workgroup per 8^3 tile holds the tile
+// and a halo in LDS and runs a whole leg of the cycle there:
+//   pre:  FAS right-hand side (step 6 of the parent), nu1 red-black sweeps (step 2), residual and
+//         restriction (steps 3-5) of the tile;
+//   post: coarse-grid correction (step 8), nu2 red-black sweeps (step 9) of the tile.
+// A half-sweep of a cell needs its neighbours' previous values, so after each half-sweep the
+// region that is still exact shrinks by one cell; the halo is as deep as the number of
+// half-sweeps (plus one for the residual stencil), and the halo cells are computed redundantly
+// by the neighbouring tiles.  Every value is formed by the same operations in the same order as
+// in the one-step kernels, so the results are bit-identical to them.  Workgroups read the level's
+// arrays and write a second copy (no workgroup reads what another writes).
+
+#include "mg_internal.h"
+
+namespace mgic {
+
+constexpr int kTile = 8;            // tile edge (cells)
+constexpr int kFusedThreads = 512;  // one thread per tile cell
+
+// position of (x, y, z) in a colour-split power-of-two cube of edge 2^lg
+__device__ __forceinline__ unsigned sidx(int lg, unsigned x, unsigned y, unsigned z) {
+    return ((((x << lg) | y) << lg) + (((x + y + z) & 1u) << (lg - 1))) + (z >> 1);
+}
+
+// Loops over the cells of a region: each thread takes the cells t = threadIdx.x + r * 512; every
+// pass first forms all its values (an index past the end is clamped to the last cell, so every
+// load stays inside the arrays) and only then stores them, so that the loads of all passes are in
+// flight together.
+template <int N>
+struct Passes {
+    static constexpr int n = (N + kFusedThreads - 1) / kFusedThreads;
+    __device__ static int cell(int r) {
+        const int t = (int)threadIdx.x + r * kFusedThreads;
+        return t < N ? t : N - 1;
+    }
+    __device__ static bool live(int r) { return N % kFusedThreads == 0 || (int)threadIdx.x + r * kFusedThreads < N; }
+};
+
+// one red-black half-sweep of `colour` over the cells of [k, S - k)^3 of an S^3 LDS region of u
+// (origin parity p0: the cell (i, j, m) has colour (i + j + m + p0) & 1); f is the (S - 2)^3
+// region one cell inside it.  The cells of one colour read only the other colour, so all new
+// values are formed before any is stored.
+template <class T, int S, int k>
+__device__ __forceinline__ void lds_half_sweep(T* su, const T* sf, T h2, int colour, int p0) {
+    constexpr int W = S - 2 * k, Wh = W / 2, SF = S - 2;
+    using Pp = Passes<W * W * Wh>;
+    T v[Pp::n];
+    int at[Pp::n];
+#pragma unroll
+    for (int r = 0; r < Pp::n; ++r) {
+        const int t = Pp::cell(r);
+        const int row = t / Wh, m = t - row * Wh;
+        const int i = k + row / W, j = k + row % W;
+        const int q = (i + j + k + p0 + colour) & 1;
+        const int z = k + 2 * m + q;
+        const int c = (i * S + j) * S + z;
+        const T s = ((su[c - S * S] + su[c + S * S]) + (su[c - S] + su[c + S])) + (su[c - 1] + su[c + 1]);
+        v[r] = (s - h2 * sf[((i - 1) * SF + (j - 1)) * SF + (z - 1)]) / T(6);
+        at[r] = c;
+    }
+#pragma unroll
+    for (int r = 0; r < Pp::n; ++r)
+        if (Pp::live(r)) su[at[r]] = v[r];
+}
+
+template <class T, int S, int k, int kend>
+__device__ __forceinline__ void lds_sweeps(T* su, const T* sf, T h2, int p0) {
+    if constexpr (k <= kend) {
+        lds_half_sweep<T, S, k>(su, sf, h2, (k - 1) & 1, p0);   // red (0) first
+        __syncthreads();
+        lds_sweeps<T, S, k + 1, kend>(su, sf, h2, p0);
+    }
+}
+
+// v[S^3 region with origin o - R] = a[cell] (periodic wrap), into LDS
+template <class T, int S>
+__device__ __forceinline__ void load_region(T* dst, const T* __restrict__ a, int lg, int ox, int oy, int oz, int R) {
+    using Pp = Passes<S * S * S>;
+    const unsigned msk = (1u << lg) - 1;
+    T v[Pp::n];
+#pragma unroll
+    for (int r = 0; r < Pp::n; ++r) {
+        const int t = Pp::cell(r);
+        const int i = t / (S * S), j = (t / S) % S, m = t % S;
+        v[r] = a[sidx(lg, (unsigned)(ox - R + i) & msk, (unsigned)(oy - R + j) & msk, (unsigned)(oz - R + m) & msk)];
+    }
+#pragma unroll
+    for (int r = 0; r < Pp::n; ++r)
+        if (Pp::live(r)) dst[(int)threadIdx.x + r * kFusedThreads] = v[r];
+}
+
+// pre leg on level (edge 2^lg): u, f are the level's arrays as the parent's restriction left
+// them; uo, fo receive the smoothed u and the FAS right-hand side of this tile; pu, pf, uold the
+// restricted u, the restricted residual and its copy for the coarse level (edge 2^(lg-1))
+template <class T, int NU>
+__global__ void __launch_bounds__(kFusedThreads)
+k_level_pre(const T* __restrict__ u, const T* __restrict__ f, T* __restrict__ uo, T* __restrict__ fo,
+            T* __restrict__ pu, T* __restrict__ pf, T* __restrict__ uold, int lg, T h2) {
+    constexpr int R = 2 * NU + 1;      // u halo: 2 nu1 half-sweeps + the residual stencil
+    constexpr int S = kTile + 2 * R, SF = S - 2;
+    __shared__ T su[S * S * S];
+    __shared__ T sf[SF * SF * SF];
+    const int lt = lg - 3;
+    const unsigned b = blockIdx.x;
+    const int ox = (int)(b >> (2 * lt)) * kTile, oy = (int)((b >> lt) & ((1u << lt) - 1)) * kTile,
+              oz = (int)(b & ((1u << lt) - 1)) * kTile;
+    load_region<T, S>(su, u, lg, ox, oy, oz, R);
+    load_region<T, SF>(sf, f, lg, ox, oy, oz, R - 1);
+    __syncthreads();
+    // FAS right-hand side on the f region: f += L u (u here is the restricted fine u)
+    {
+        using Pp = Passes<SF * SF * SF>;
+        T v[Pp::n];
+#pragma unroll
+        for (int r = 0; r < Pp::n; ++r) {
+            const int t = Pp::cell(r);
+            const int i = t / (SF * SF), j = (t / SF) % SF, m = t % SF;
+            const int c = ((i + 1) * S + (j + 1)) * S + (m + 1);
+            const T s = ((su[c - S * S] + su[c + S * S]) + (su[c - S] + su[c + S])) + (su[c - 1] + su[c + 1]);
+            v[r] = sf[t] + (s - T(6) * su[c]) / h2;
+        }
+#pragma unroll
+        for (int r = 0; r < Pp::n; ++r)
+            if (Pp::live(r)) sf[(int)threadIdx.x + r * kFusedThreads] = v[r];
+    }
+    __syncthreads();
+    lds_sweeps<T, S, 1, 2 * NU>(su, sf, h2, R & 1);
+    // residual and restriction of the tile's 4^3 coarse cells: each thread one child, the 8
+    // children of a coarse cell in 8 neighbouring lanes, summed in the order (a, b, e)
+    {
+        const int t = threadIdx.x, ch = t & 7, cc = t >> 3;
+        const int X = cc >> 4, Y = (cc >> 2) & 3, Z = cc & 3;
+        const int x = 2 * X + (ch >> 2), y = 2 * Y + ((ch >> 1) & 1), z = 2 * Z + (ch & 1);
+        const int c = ((x + R) * S + (y + R)) * S + (z + R);
+        const T ui = su[c];
+        const T fi = sf[((x + R - 1) * SF + (y + R - 1)) * SF + (z + R - 1)];
+        const T s = ((su[c - S * S] + su[c + S * S]) + (su[c - S] + su[c + S])) + (su[c - 1] + su[c + 1]);
+        const T lap = (s - T(6) * ui) / h2;
+        const T r = fi - lap;
+        const int lane0 = (int)(threadIdx.x & 63) & ~7;
+        T sr = T(0), sum_u = T(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            sr = sr + __shfl(r, lane0 + q, 64);
+            sum_u = sum_u + __shfl(ui, lane0 + q, 64);
+        }
+        if (ch == 0) {
+            const unsigned Xg = (unsigned)(ox / 2 + X), Yg = (unsigned)(oy / 2 + Y), Zg = (unsigned)(oz / 2 + Z);
+            const int lc = lg - 1;
+            const T uc = sum_u * T(0.125);
+            const unsigned P = sidx(lc, Xg, Yg, Zg);
+            pu[P] = uc;
+            pf[P] = sr * T(0.125);
+            uold[(((Xg << lc) | Yg) << lc) | Zg] = uc;
+        }
+        // the tile itself: smoothed u and the FAS right-hand side
+        const unsigned g = sidx(lg, (unsigned)(ox + x), (unsigned)(oy + y), (unsigned)(oz + z));
+        uo[g] = ui;
+        fo[g] = fi;
+    }
+}
+
+// post leg: u = ui + (uc[parent] - uold[parent]) over the tile and a halo of 2 nu2 cells, then
+// nu2 red-black sweeps; the tile is written to uout.  fi is the FAS right-hand side of the level.
+template <class T, int NU>
+__global__ void __launch_bounds__(kFusedThreads)
+k_level_post(const T* __restrict__ ui, const T* __restrict__ fi, const T* __restrict__ uc,
+             const T* __restrict__ uold, T* __restrict__ uout, int lg, T h2) {
+    constexpr int R = 2 * NU;
+    constexpr int S = kTile + 2 * R, SF = S - 2;
+    __shared__ T su[S * S * S];
+    __shared__ T sf[SF * SF * SF];
+    const int lt = lg - 3, lc = lg - 1;
+    const unsigned b = blockIdx.x, msk = (1u << lg) - 1;
+    const int ox = (int)(b >> (2 * lt)) * kTile, oy = (int)((b >> lt) & ((1u << lt) - 1)) * kTile,
+              oz = (int)(b & ((1u << lt) - 1)) * kTile;
+    {
+        using Pp = Passes<S * S * S>;
+        T v[Pp::n];
+#pragma unroll
+        for (int r = 0; r < Pp::n; ++r) {
+            const int t = Pp::cell(r);
+            const int i = t / (S * S), j = (t / S) % S, m = t % S;
+            const unsigned x = (unsigned)(ox - R + i) & msk, y = (unsigned)(oy - R + j) & msk,
+                           z = (unsigned)(oz - R + m) & msk;
+            const unsigned X = x >> 1, Y = y >> 1, Z = z >> 1;
+            v[r] = ui[sidx(lg, x, y, z)] + (uc[sidx(lc, X, Y, Z)] - uold[(((X << lc) | Y) << lc) | Z]);
+        }
+#pragma unroll
+        for (int r = 0; r < Pp::n; ++r)
+            if (Pp::live(r)) su[(int)threadIdx.x + r * kFusedThreads] = v[r];
+    }
+    load_region<T, SF>(sf, fi, lg, ox, oy, oz, R - 1);
+    __syncthreads();
+    lds_sweeps<T, S, 1, 2 * NU>(su, sf, h2, R & 1);
+    {
+        const int t = threadIdx.x;
+        const int x = t >> 6, y = (t >> 3) & 7, z = t & 7;
+        uout[sidx(lg, (unsigned)(ox + x), (unsigned)(oy + y), (unsigned)(oz + z))] = su[((x + R) * S + (y + R)) * S + (z + R)];
+    }
+}
+
+bool level_fusable(int n, int nu1, int nu2) {
+    return (n == 32 || n == 64) && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
+}
+
+template <class T>
+void launch_level_pre(const T* u, const T* f, T* uo, T* fo, T* pu, T* pf, T* uold, int n, double h, int nu1,
+                      hipStream_t st) {
+    const int lg = __builtin_ctz((unsigned)n);
+    const unsigned tiles = 1u << (3 * (lg - 3));
+    const T h2 = (T)(h * h);
+    if (nu1 == 1) k_level_pre<T, 1><<<tiles, kFusedThreads, 0, st>>>(u, f, uo, fo, pu, pf, uold, lg, h2);
+    else k_level_pre<T, 2><<<tiles, kFusedThreads, 0, st>>>(u, f, uo, fo, pu, pf, uold, lg, h2);
+}
+
+template <class T>
+void launch_level_post(const T* ui, const T* fi, const T* uc, const T* uold, T* uout, int n, double h, int nu2,
+                       hipStream_t st) {
+    const int lg = __builtin_ctz((unsigned)n);
+    const unsigned tiles = 1u << (3 * (lg - 3));
+    const T h2 = (T)(h * h);
+    if (nu2 == 1) k_level_post<T, 1><<<tiles, kFusedThreads, 0, st>>>(ui, fi, uc, uold, uout, lg, h2);
+    else k_level_post<T, 2><<<tiles, kFusedThreads, 0, st>>>(ui, fi, uc, uold, uout, lg, h2);
+}
+
+#define MG_INST(T)                                                                                      \
+    template void launch_level_pre<T>(const T*, const T*, T*, T*, T*, T*, T*, int, double, int, hipStream_t); \
+    template void launch_level_post<T>(const T*, const T*, const T*, const T*, T*, int, double, int, hipStream_t);
+MG_INST(float)
+MG_INST(double)
+#undef MG_INST
+
+}  // namespace mgic

@@ -430,6 +430,18 @@ __device__ void body_tail(const TailPlan<T>& tp) {
             F0[t] = f0g[t];
         }
         __syncthreads();
+        if (uniform(tp.fas0)) {   // the parent's step 6 on this level: f += L u
+            const Lay A = uniform(tp.lev[0].lay);
+            const double h0 = uniform(tp.lev[0].h);
+            const T H2 = (T)(h0 * h0);
+            for (unsigned t = threadIdx.x; t < n0; t += nt) {
+                int x, y, z;
+                ldecode(A, t, x, y, z);
+                const T s = nsum_periodic<T>(U0, A.d, A.split, x, y, z);
+                F0[t] = F0[t] + (s - T(6) * U0[t]) / H2;
+            }
+            __syncthreads();
+        }
     }
     // descent: smooth, restrict, FAS right-hand side
     const int nlev = uniform(tp.n), nu1 = uniform(tp.nu1), nu2 = uniform(tp.nu2);
@@ -486,6 +498,158 @@ __device__ void body_tail(const TailPlan<T>& tp) {
 template <class T>
 __global__ void __launch_bounds__(kTailThreads) k_tail(TailPlan<T> tp) {
     body_tail<T>(tp);
+}
+
+// The same tail when every level but the single-cell coarsest is a colour-split power-of-two cube
+// (the coarsenings of a power-of-two base).  Positions and periodic neighbour sums are formed by
+// shifts and masks of the edge's log2, and the residual + restriction takes one thread per fine
+// cell: the 8 children of a coarse cell sit in 8 neighbouring lanes and are summed by lane
+// shuffles in the same (a, b, e) order.  The operations on every value are those of body_tail,
+// so the bits are the same; only the index arithmetic and the work split differ.
+__device__ __forceinline__ unsigned p2pos(int lg, unsigned x, unsigned y, unsigned z) {
+    if (lg == 0) return 0u;   // the single-cell coarsest level
+    return ((((x << lg) | y) << lg) + (((x + y + z) & 1u) << (lg - 1))) + (z >> 1);
+}
+
+template <class T>
+__device__ __forceinline__ T p2nsum(const T* u, int lg, unsigned x, unsigned y, unsigned z) {
+    const unsigned m = (1u << lg) - 1;
+    const T xm = u[p2pos(lg, (x - 1) & m, y, z)], xp = u[p2pos(lg, (x + 1) & m, y, z)];
+    const T ym = u[p2pos(lg, x, (y - 1) & m, z)], yp = u[p2pos(lg, x, (y + 1) & m, z)];
+    const T zm = u[p2pos(lg, x, y, (z - 1) & m)], zp = u[p2pos(lg, x, y, (z + 1) & m)];
+    return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
+
+template <class T>
+__device__ void body_tail_p2(const TailPlan<T>& tp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    auto U = [&](int k) { return (T*)(smem + uniform(tp.lev[k].lds_u)); };
+    auto F = [&](int k) { return (T*)(smem + uniform(tp.lev[k].lds_f)); };
+    auto O = [&](int k) { return (T*)(smem + uniform(tp.lev[k].lds_o)); };
+    const unsigned nt = blockDim.x, tid = threadIdx.x;
+    const int nlev = uniform(tp.n), nu1 = uniform(tp.nu1), nu2 = uniform(tp.nu2);
+    const int lg0 = uniform(tp.lev[0].lay.lgx);
+    {
+        const unsigned n0 = 1u << (3 * lg0);
+        T* U0 = U(0);
+        T* F0 = F(0);
+        const T* u0g = uniform(tp.lev[0].u);
+        const T* f0g = uniform(tp.lev[0].f);
+        for (unsigned t = tid; t < n0; t += nt) {
+            U0[t] = u0g[t];
+            F0[t] = f0g[t];
+        }
+        __syncthreads();
+        if (uniform(tp.fas0)) {   // the parent's step 6 on this level: f += L u
+            const Lay A = uniform(tp.lev[0].lay);
+            const double h0 = uniform(tp.lev[0].h);
+            const T H2 = (T)(h0 * h0);
+            for (unsigned t = tid; t < n0; t += nt) {
+                int x, y, z;
+                ldecode(A, t, x, y, z);
+                const T s = p2nsum<T>(U0, lg0, (unsigned)x, (unsigned)y, (unsigned)z);
+                F0[t] = F0[t] + (s - T(6) * U0[t]) / H2;
+            }
+            __syncthreads();
+        }
+    }
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const Lay A = uniform(tp.lev[l].lay);
+        const int lg = lg0 - l, lc = lg - 1;
+        const double hl = uniform(tp.lev[l].h);
+        const T h2 = (T)(hl * hl);
+        const unsigned n = 1u << (3 * lg), half = n >> 1, mc = (1u << lc) - 1;
+        T* u = U(l);
+        T* f = F(l);
+        T* pu = U(l + 1);
+        T* pf = F(l + 1);
+        T* uo = O(l);
+        for (int s = 0; s < nu1; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for (unsigned t = tid; t < half; t += nt) cell_rbgs_split<T>(u, f, A, h2, c, t);
+                __syncthreads();
+            }
+        for (unsigned base = 0; base < n; base += nt) {   // every lane of a wave takes part in the shuffles
+            const unsigned t = base + tid, ch = t & 7, cc = t >> 3;
+            const bool act = t < n;
+            const unsigned X = cc >> (2 * lc), Y = (cc >> lc) & mc, Z = cc & mc;
+            const unsigned x = 2 * X + (ch >> 2), y = 2 * Y + ((ch >> 1) & 1), z = 2 * Z + (ch & 1);
+            T r = T(0), ui = T(0);
+            if (act) {
+                const unsigned i = p2pos(lg, x, y, z);
+                ui = u[i];
+                const T sn = p2nsum<T>(u, lg, x, y, z);
+                const T lap = (sn - T(6) * ui) / h2;
+                r = f[i] - lap;
+            }
+            const int lane0 = (int)(tid & 63) & ~7;
+            T sr = T(0), su = T(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                sr = sr + __shfl(r, lane0 + q, 64);
+                su = su + __shfl(ui, lane0 + q, 64);
+            }
+            if (act && ch == 0) {
+                const T uc = su * T(0.125);
+                const unsigned P = p2pos(lc, X, Y, Z);
+                pu[P] = uc;
+                pf[P] = sr * T(0.125);
+                uo[cc] = uc;
+            }
+        }
+        __syncthreads();
+        const double hc = uniform(tp.lev[l + 1].h);
+        const T H2 = (T)(hc * hc);
+        for (unsigned t = tid; t < (n >> 3); t += nt) {
+            const unsigned X = t >> (2 * lc), Y = (t >> lc) & mc, Z = t & mc;
+            const unsigned i = p2pos(lc, X, Y, Z);
+            const T sn = p2nsum<T>(pu, lc, X, Y, Z);
+            pf[i] = pf[i] + (sn - T(6) * pu[i]) / H2;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) U(nlev - 1)[0] = T(0);   // step 1 on the single-cell coarsest level
+    __syncthreads();
+    for (int l = nlev - 2; l >= 0; --l) {
+        const Lay A = uniform(tp.lev[l].lay);
+        const int lg = lg0 - l, lc = lg - 1;
+        const unsigned n = 1u << (3 * lg), m = (1u << lg) - 1, nzh = 1u << (lg - 1);
+        T* u = U(l);
+        const T* pu = U(l + 1);
+        const T* uo = O(l);
+        if (nu2 > 0) {   // red cells are rewritten unread by the first red half-sweep
+            for (unsigned t = tid; t < (n >> 1); t += nt) {
+                const unsigned row = t >> (lg - 1), j = t & (nzh - 1);
+                const unsigned x = row >> lg, y = row & m, z = 2 * j + ((x + y + 1) & 1);
+                const unsigned i = (row << lg) + nzh + j;
+                const unsigned X = x >> 1, Y = y >> 1, Z = z >> 1;
+                u[i] = u[i] + (pu[p2pos(lc, X, Y, Z)] - uo[(((X << lc) | Y) << lc) | Z]);
+            }
+        } else {
+            for (unsigned t = tid; t < n; t += nt) {
+                int x, y, z;
+                ldecode(A, t, x, y, z);
+                const unsigned X = (unsigned)x >> 1, Y = (unsigned)y >> 1, Z = (unsigned)z >> 1;
+                u[t] = u[t] + (pu[p2pos(lc, X, Y, Z)] - uo[(((X << lc) | Y) << lc) | Z]);
+            }
+        }
+        __syncthreads();
+        const double hl = uniform(tp.lev[l].h);
+        const T h2 = (T)(hl * hl);
+        for (int s = 0; s < nu2; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for (unsigned t = tid; t < (n >> 1); t += nt) cell_rbgs_split<T>(u, F(l), A, h2, c, t);
+                __syncthreads();
+            }
+    }
+    const unsigned n0 = 1u << (3 * lg0);
+    T* u0out = uniform(tp.lev[0].u);
+    for (unsigned t = tid; t < n0; t += nt) u0out[t] = U(0)[t];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_p2(TailPlan<T> tp) {
+    body_tail_p2<T>(tp);
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -912,9 +1076,17 @@ void launch_tail(const TailPlan<T>& tp, hipStream_t st) {
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+        (void)hipFuncSetAttribute((const void*)k_tail_p2<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kTailMaxLds);
         attr = true;
     }
-    k_tail<T><<<1, kTailThreads, tp.lds_bytes, st>>>(tp);
+    bool p2 = tp.n >= 2 && tp.lev[tp.n - 1].lay.d.cells() == 1;
+    for (int k = 0; p2 && k + 1 < tp.n; ++k) {
+        const Lay& A = tp.lev[k].lay;
+        p2 = A.pow2 && A.split && A.d.x == A.d.y && A.d.y == A.d.z && A.lgx == tp.lev[0].lay.lgx - k;
+    }
+    if (p2) k_tail_p2<T><<<1, kTailThreads, tp.lds_bytes, st>>>(tp);
+    else k_tail<T><<<1, kTailThreads, tp.lds_bytes, st>>>(tp);
 }
 
 template <class T>

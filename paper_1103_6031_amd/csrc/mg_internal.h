@@ -148,6 +148,7 @@ template <class T>
 struct TailPlan {
     int n, nu1, nu2;
     int inst;                       // batched launches: the instance (index of its active flag)
+    int fas0;                       // 1: level 0's f still lacks the FAS term L u (step 6), add it first
     unsigned lds_bytes;             // total LDS, including the coarsest solver's 2 x 343 doubles
     TailLevel<T> lev[kTailMaxLevels];
 };
@@ -207,6 +208,15 @@ template <class T> void launch_prolong(T* u, Lay L, const T* pu, const T* uold, 
                                        hipStream_t st);
 // V-cycle over all levels of a tail plan in one single-workgroup launch
 template <class T> void launch_tail(const TailPlan<T>& tp, hipStream_t st);
+// fused pre / post legs of a periodic power-of-two coarsening of edge n (32 or 64), one workgroup
+// per 8^3 tile (bit-identical to the one-step kernels)
+bool level_fusable(int n, int nu1, int nu2);
+template <class T>
+void launch_level_pre(const T* u, const T* f, T* uo, T* fo, T* pu, T* pf, T* uold, int n, double h, int nu1,
+                      hipStream_t st);
+template <class T>
+void launch_level_post(const T* ui, const T* fi, const T* uc, const T* uold, T* uout, int n, double h, int nu2,
+                       hipStream_t st);
 // exact coarsest solve on an odd periodic M^3 grid (M = 1: u = 0)
 template <class T> void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st);
 

@@ -68,6 +68,10 @@ struct Level {
     float *u32 = nullptr, *f32 = nullptr, *g32 = nullptr, *uold32 = nullptr;
     double* ualt = nullptr;  // second u of the fused mixed-precision outer step (ping-pong)
     float* ealt = nullptr;   // second e of the same
+    // second u and f of a coarsening run by the fused tile kernels (written by the pre leg)
+    bool fusable = false;
+    double *ua = nullptr, *fa = nullptr;
+    float *ua32 = nullptr, *fa32 = nullptr;
 };
 
 struct Plan {
@@ -83,10 +87,10 @@ struct Plan {
 
 enum { S_FSUM = 0, S_FNORM = 1, S_RNORM = 2, S_USUM = 3, S_TMP = 4, S_COUNT = 8 };
 
-template <class T> struct B { T *u, *f, *g, *uold; };
+template <class T> struct B { T *u, *f, *g, *uold, *ua, *fa; };
 template <class T> static B<T> bufs(Level& l);
-template <> B<double> bufs<double>(Level& l) { return {l.u, l.f, l.g, l.uold}; }
-template <> B<float> bufs<float>(Level& l) { return {l.u32, l.f32, l.g32, l.uold32}; }
+template <> B<double> bufs<double>(Level& l) { return {l.u, l.f, l.g, l.uold, l.ua, l.fa}; }
+template <> B<float> bufs<float>(Level& l) { return {l.u32, l.f32, l.g32, l.uold32, l.ua32, l.fa32}; }
 
 static bool odd_ok(int m) { return m == 1 || m == 3 || m == 5 || m == 7; }
 
@@ -119,7 +123,8 @@ static int validate_hier(const mg_hier* H) {
 }
 
 // Build the level list and carve buffers.  u_user / f_user may be null (size query).
-static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* const* u_user, Plan& P) {
+static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* const* u_user, Plan& P,
+                      bool fuse = true) {
     int rc = validate_hier(H);
     if (rc) return rc;
     P.nu1 = o ? o->nu1 : 2;
@@ -188,6 +193,25 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
         if (P.L[l].periodic && P.L[l].d.cells() <= kTailMaxCells && P.last - l < kTailMaxLevels) {
             P.tail = l;
             break;
+        }
+    // coarsenings (below the base: their whole box is the restriction of the finer level) that
+    // are power-of-two cubes of 32^3 or 64^3 run as two fused tile launches per cycle; their
+    // second arrays are reserved whatever nu1 / nu2 are, so that the workspace size depends on
+    // the shapes and the precision only
+    if (fuse)
+        for (int l = 1; l < P.last; ++l) {
+            Level& L = P.L[l];
+            const int n = L.d.x;
+            if (L.p >= 0 || !L.periodic || L.d.y != n || L.d.z != n || !level_fusable(n, 1, 1)) continue;
+            L.fusable = true;
+            const size_t c = L.d.cells();
+            if (P.mixed) {
+                L.ua32 = cv.take<float>(c);
+                L.fa32 = cv.take<float>(c);
+            } else {
+                L.ua = cv.take<double>(c);
+                L.fa = cv.take<double>(c);
+            }
         }
     P.partials = cv.take<double>((size_t)kMaxPartials * (P.nh + 1));
     P.scal = cv.take<double>(S_COUNT);
@@ -259,6 +283,14 @@ static void smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_r
         }
 }
 
+// level l runs as the two fused tile launches (its arrays for them are reserved and the sweep
+// counts fit the kernels' halos)
+template <class T>
+static bool fused(Plan& P, int l) {
+    Level& L = P.L[l];
+    return L.fusable && bufs<T>(L).ua && level_fusable(L.d.x, P.nu1, P.nu2);
+}
+
 template <class T>
 static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) {
     Level& L = P.L[l];
@@ -268,6 +300,7 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
         tp.n = P.last - l + 1;
         tp.nu1 = P.nu1;
         tp.nu2 = P.nu2;
+        tp.fas0 = l > 0 && fused<T>(P, l - 1);   // a fused parent leaves step 6 to this level
         for (int k = 0; k < tp.n; ++k) {
             B<T> c = bufs<T>(P.L[l + k]);
             tp.lev[k] = TailLevel<T>{c.u, c.f, P.L[l + k].lay, P.L[l + k].h, 0, 0, 0};
@@ -280,13 +313,20 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
         launch_coarsest<T>(b.u, b.f, L.d.x, L.h, st);
         return;
     }
-    smooth<T>(P, l, P.nu1, st, skip_first_red);  // step 2
     Level& Q = P.L[l + 1];
     B<T> q = bufs<T>(Q);
+    if (fused<T>(P, l)) {
+        // step 6 of the parent and steps 2-5 in one launch, step 7, steps 8-9 in one launch
+        launch_level_pre<T>(b.u, b.f, b.ua, b.fa, q.u, q.f, b.uold, L.d.x, L.h, P.nu1, st);
+        vcycle<T>(P, l + 1, st);
+        launch_level_post<T>(b.ua, b.fa, q.u, b.uold, b.u, L.d.x, L.h, P.nu2, st);
+        return;
+    }
+    smooth<T>(P, l, P.nu1, st, skip_first_red);  // step 2
     if (!L.periodic) ghosts<T>(P, l, st);
-    // steps 3-5, then step 6 on the covered region of the parent
+    // steps 3-5, then step 6 on the covered region of the parent (a fused parent does its own)
     launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, q.u, q.f, b.uold, L.pm, st);
-    launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
+    if (!fused<T>(P, l + 1)) launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
     vcycle<T>(P, l + 1, st);                         // step 7
     // black cells only where nothing reads the red ones before the red half-sweep rewrites them:
     // a patch's ghost fill reads both colours of its first two layers
@@ -856,14 +896,15 @@ static size_t batch_layout(int ninst, const int* n, const double* h, const mg_op
         mg_hier H = single_level(n[i], h ? h[i] : 1.0);
         Plan P;
         Carver cv(nullptr);
-        if (build_plan(&H, o, cv, nullptr, P)) return 0;
+        // batched instances run the one-step kernels (no fused levels); the others are solo solves
+        if (build_plan(&H, o, cv, nullptr, P, !batchable(n[i]))) return 0;
         slice[i] = off;
         slice_bytes[i] = (cv.off + 255) & ~(size_t)255;
         off += slice_bytes[i];
         if (batchable(n[i])) {
             Plan Q;
             Carver c2(ws ? ws + slice[i] : nullptr);
-            build_plan(&H, o, c2, nullptr, Q);
+            build_plan(&H, o, c2, nullptr, Q, false);
             B.ids.push_back(i);
             B.P.push_back(Q);
         }

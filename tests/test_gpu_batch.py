@@ -63,6 +63,23 @@ def test_batch_bit_identical_to_solo(mg, prec, graph):
             _same_stats(s, ss)
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("nu", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1)])
+def test_fused_levels_match_one_step_kernels(mg, prec, nu):
+    """Solo solves run the 64^3 and 32^3 coarsenings as fused tile launches, batched instances
+    run the one-step kernels: the bits must agree for every sweep count the fused kernels take,
+    and for one they do not take (both sides then run the one-step kernels)."""
+    sizes = [64, 128]
+    fs, hs = _fields(sizes, seed0=950)
+    o = mg.make_opts(prec=prec, max_cycles=4, fixed_cycles=True, nu1=nu[0], nu2=nu[1])
+    note("fused levels %s nu=%s" % (prec, nu))
+    ub, sts = mg.mg_solve_batch([to_dev(f) for f in fs], hs, opts=o)
+    for N, f, h, u, s in zip(sizes, fs, hs, ub, sts):
+        us, ss = mg.mg_solve_level(to_dev(f), h, opts=o)
+        assert np.array_equal(to_host(u), to_host(us)), N
+        _same_stats(s, ss)
+
+
 def test_batch_graph_equals_direct_repeated(mg):
     sizes = [64, 32, 96, 48]
     fs, hs = _fields(sizes, seed0=700)

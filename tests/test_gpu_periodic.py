@@ -51,7 +51,7 @@ def test_smoother_fp32_bit_exact_against_float32_oracle(mg, N, half):
     assert np.array_equal(to_host(ut).astype(np.float32), ue)
 
 
-@pytest.mark.parametrize("N", [8, 16, 48, 64])
+@pytest.mark.parametrize("N", [8, 16, 48, 64, 128])   # 64 and 128 take the fused 64^3 / 32^3 levels
 def test_one_vcycle_matches_oracle(mg, N):
     f = inputs.gaussian_field(N, 11 + N)
     h = 100.0 / N
