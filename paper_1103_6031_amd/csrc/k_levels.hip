@@ -205,6 +205,143 @@ k_level_post(const T* __restrict__ ui, const T* __restrict__ fi, const T* __rest
     }
 }
 
+// ----------------------------------------------------------------------------------------------
+// One-step transfer kernels for periodic colour-split power-of-two cubes (the larger levels of a
+// power-of-two base), with the same arithmetic as the generic ones and coalesced accesses: the
+// lanes of a wave take consecutive coarse cells Z of a row, whose fine cells sit at consecutive
+// positions of the fine half-rows.
+// ----------------------------------------------------------------------------------------------
+
+// steps 3-5 for the coarse cell t = (X, Y, Z) (natural order): the 8 children's residuals and
+// values summed in the order (a, b, e).  The children and their neighbours span the fine rows
+// (2X + a, 2Y + b) at z = 2Z - 1 .. 2Z + 2, and the rows one step outside in x and in y at
+// z = 2Z, 2Z + 1; in a row whose even-z cells are colour p, z = 2Z and 2Z + 2 are entries Z and
+// Z + 1 of half p, z = 2Z - 1 and 2Z + 1 entries Z - 1 and Z of the other half.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_resid_restrict_p2(const T* __restrict__ u, const T* __restrict__ f, int lg, T h2, T* __restrict__ pu,
+                    T* __restrict__ pf, T* __restrict__ uold) {
+    const int lc = lg - 1;
+    const unsigned nc = 1u << lc, mc = nc - 1, m = (1u << lg) - 1, nzh = nc;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 1u << (3 * lc)) return;
+    const unsigned X = t >> (2 * lc), Y = (t >> lc) & mc, Z = t & mc;
+    const unsigned x0 = 2 * X, y0 = 2 * Y;
+    const unsigned Zm = (Z - 1) & mc, Zp = (Z + 1) & mc;
+    auto rowb = [&](unsigned x, unsigned y) { return (((x & m) << lg) | (y & m)) << lg; };
+    auto half = [&](unsigned x, unsigned y, unsigned zpar) {   // offset of the half holding parity zpar
+        return ((x + y + zpar) & 1u) * nzh;
+    };
+    // central rows (a, b): values at z0 - 1, z0, z0 + 1, z0 + 2 and f at z0, z0 + 1
+    T cm[2][2], c0[2][2], c1[2][2], c2[2][2], f0[2][2], f1[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const unsigned x = x0 + a, y = y0 + b, rb = rowb(x, y);
+            const unsigned he = half(x, y, 0), ho = half(x, y, 1);
+            cm[a][b] = u[rb + ho + Zm];
+            c0[a][b] = u[rb + he + Z];
+            c1[a][b] = u[rb + ho + Z];
+            c2[a][b] = u[rb + he + Zp];
+            f0[a][b] = f[rb + he + Z];
+            f1[a][b] = f[rb + ho + Z];
+        }
+    // face rows: x0 - 1 and x0 + 2 (for b = 0, 1), y0 - 1 and y0 + 2 (for a = 0, 1), at z0, z0 + 1
+    T xf[2][2][2], yf[2][2][2];   // [side][b or a][e]
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            {
+                const unsigned x = sd ? x0 + 2 : x0 - 1, y = y0 + k, rb = rowb(x, y);
+                xf[sd][k][0] = u[rb + half(x, y, 0) + Z];
+                xf[sd][k][1] = u[rb + half(x, y, 1) + Z];
+            }
+            {
+                const unsigned x = x0 + k, y = sd ? y0 + 2 : y0 - 1, rb = rowb(x, y);
+                yf[sd][k][0] = u[rb + half(x, y, 0) + Z];
+                yf[sd][k][1] = u[rb + half(x, y, 1) + Z];
+            }
+        }
+    auto val = [&](int a, int b, int e) { return e ? c1[a][b] : c0[a][b]; };
+    T sr = T(0), su = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const T ui = val(a, b, e);
+                const T xm = a ? val(0, b, e) : xf[0][b][e];
+                const T xp = a ? xf[1][b][e] : val(1, b, e);
+                const T ym = b ? val(a, 0, e) : yf[0][a][e];
+                const T yp = b ? yf[1][a][e] : val(a, 1, e);
+                const T zm = e ? c0[a][b] : cm[a][b];
+                const T zp = e ? c2[a][b] : c1[a][b];
+                const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
+                const T lap = (s - T(6) * ui) / h2;
+                sr = sr + ((e ? f1[a][b] : f0[a][b]) - lap);
+                su = su + ui;
+            }
+    const T uc = su * T(0.125);
+    const unsigned P = sidx(lc, X, Y, Z);
+    pu[P] = uc;
+    pf[P] = sr * T(0.125);
+    uold[t] = uc;
+}
+
+// step 8 on the black cells: the black cell (row, j) of a fine row lies in the parent (X, Y, j)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_prolong_black_p2(T* __restrict__ u, int lg, const T* __restrict__ pu, const T* __restrict__ uold) {
+    const int lc = lg - 1;
+    const unsigned nzh = 1u << lc, m = (1u << lg) - 1;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 1u << (3 * lg - 1)) return;
+    const unsigned row = t >> lc, j = t & (nzh - 1);
+    const unsigned x = row >> lg, y = row & m;
+    const unsigned X = x >> 1, Y = y >> 1;
+    const unsigned i = (row << lg) + nzh + j;
+    u[i] = u[i] + (pu[sidx(lc, X, Y, j)] - uold[(((X << lc) | Y) << lc) | j]);
+}
+
+// step 6 on a whole periodic coarse level (edge 2^lg): f += L u for the cell t (natural order)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_fas_rhs_p2(const T* __restrict__ pu, T* __restrict__ pf, int lg, T H2) {
+    const unsigned m = (1u << lg) - 1;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 1u << (3 * lg)) return;
+    const unsigned x = t >> (2 * lg), y = (t >> lg) & m, z = t & m;
+    const unsigned i = sidx(lg, x, y, z);
+    const T s = ((pu[sidx(lg, (x - 1) & m, y, z)] + pu[sidx(lg, (x + 1) & m, y, z)]) +
+                 (pu[sidx(lg, x, (y - 1) & m, z)] + pu[sidx(lg, x, (y + 1) & m, z)])) +
+                (pu[sidx(lg, x, y, (z - 1) & m)] + pu[sidx(lg, x, y, (z + 1) & m)]);
+    pf[i] = pf[i] + (s - T(6) * pu[i]) / H2;
+}
+
+template <class T>
+void launch_resid_restrict_p2(const T* u, const T* f, int n, double h, T* pu, T* pf, T* uold, hipStream_t st) {
+    const int lg = __builtin_ctz((unsigned)n);
+    const unsigned cells = 1u << (3 * (lg - 1));
+    k_resid_restrict_p2<T><<<(cells + 255) / 256, 256, 0, st>>>(u, f, lg, (T)(h * h), pu, pf, uold);
+}
+
+template <class T>
+void launch_prolong_black_p2(T* u, int n, const T* pu, const T* uold, hipStream_t st) {
+    const int lg = __builtin_ctz((unsigned)n);
+    const unsigned cells = 1u << (3 * lg - 1);
+    k_prolong_black_p2<T><<<(cells + 255) / 256, 256, 0, st>>>(u, lg, pu, uold);
+}
+
+template <class T>
+void launch_fas_rhs_p2(const T* pu, T* pf, int n, double H, hipStream_t st) {
+    const int lg = __builtin_ctz((unsigned)n);
+    const unsigned cells = 1u << (3 * lg);
+    k_fas_rhs_p2<T><<<(cells + 255) / 256, 256, 0, st>>>(pu, pf, lg, (T)(H * H));
+}
+
 bool level_fusable(int n, int nu1, int nu2) {
     return (n == 32 || n == 64) && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
 }
@@ -230,6 +367,9 @@ void launch_level_post(const T* ui, const T* fi, const T* uc, const T* uold, T* 
 }
 
 #define MG_INST(T)                                                                                      \
+    template void launch_resid_restrict_p2<T>(const T*, const T*, int, double, T*, T*, T*, hipStream_t);      \
+    template void launch_prolong_black_p2<T>(T*, int, const T*, const T*, hipStream_t);                       \
+    template void launch_fas_rhs_p2<T>(const T*, T*, int, double, hipStream_t);                               \
     template void launch_level_pre<T>(const T*, const T*, T*, T*, T*, T*, T*, int, double, int, hipStream_t); \
     template void launch_level_post<T>(const T*, const T*, const T*, const T*, T*, int, double, int, hipStream_t);
 MG_INST(float)

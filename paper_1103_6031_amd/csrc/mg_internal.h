@@ -211,6 +211,12 @@ template <class T> void launch_tail(const TailPlan<T>& tp, hipStream_t st);
 // fused pre / post legs of a periodic power-of-two coarsening of edge n (32 or 64), one workgroup
 // per 8^3 tile (bit-identical to the one-step kernels)
 bool level_fusable(int n, int nu1, int nu2);
+// steps 3-5, 8 (black cells) and 6 on periodic colour-split power-of-two cubes of edge n (the
+// coarse level of edge n / 2 for the first two), with the arithmetic of the generic kernels
+template <class T>
+void launch_resid_restrict_p2(const T* u, const T* f, int n, double h, T* pu, T* pf, T* uold, hipStream_t st);
+template <class T> void launch_prolong_black_p2(T* u, int n, const T* pu, const T* uold, hipStream_t st);
+template <class T> void launch_fas_rhs_p2(const T* pu, T* pf, int n, double H, hipStream_t st);
 template <class T>
 void launch_level_pre(const T* u, const T* f, T* uo, T* fo, T* pu, T* pf, T* uold, int n, double h, int nu1,
                       hipStream_t st);

@@ -291,6 +291,14 @@ static bool fused(Plan& P, int l) {
     return L.fusable && bufs<T>(L).ua && level_fusable(L.d.x, P.nu1, P.nu2);
 }
 
+// a periodic colour-split power-of-two cube with a colour-split parent: its transfers take the
+// power-of-two kernels
+static bool p2lev(const Level& L) {
+    const Lay& A = L.lay;
+    return L.periodic && A.pow2 && A.split && A.d.x == A.d.y && A.d.y == A.d.z && A.d.x >= 4 &&
+           L.pm.off[0] == 0 && L.pm.off[1] == 0 && L.pm.off[2] == 0;
+}
+
 template <class T>
 static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) {
     Level& L = P.L[l];
@@ -325,12 +333,18 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
     smooth<T>(P, l, P.nu1, st, skip_first_red);  // step 2
     if (!L.periodic) ghosts<T>(P, l, st);
     // steps 3-5, then step 6 on the covered region of the parent (a fused parent does its own)
-    launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, q.u, q.f, b.uold, L.pm, st);
-    if (!fused<T>(P, l + 1)) launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
+    const bool p2 = p2lev(L);
+    if (p2) launch_resid_restrict_p2<T>(b.u, b.f, L.d.x, L.h, q.u, q.f, b.uold, st);
+    else launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, q.u, q.f, b.uold, L.pm, st);
+    if (!fused<T>(P, l + 1)) {
+        if (p2 && Q.lay.pow2 && Q.lay.split) launch_fas_rhs_p2<T>(q.u, q.f, Q.d.x, Q.h, st);
+        else launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
+    }
     vcycle<T>(P, l + 1, st);                         // step 7
     // black cells only where nothing reads the red ones before the red half-sweep rewrites them:
     // a patch's ghost fill reads both colours of its first two layers
-    launch_prolong<T>(b.u, L.lay, q.u, b.uold, L.pm, P.nu2 > 0 && L.periodic, st);  // step 8
+    if (p2 && P.nu2 > 0) launch_prolong_black_p2<T>(b.u, L.d.x, q.u, b.uold, st);  // step 8
+    else launch_prolong<T>(b.u, L.lay, q.u, b.uold, L.pm, P.nu2 > 0 && L.periodic, st);
     smooth<T>(P, l, P.nu2, st);                      // step 9
 }
 
