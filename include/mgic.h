@@ -198,9 +198,12 @@ int mg_ghost_fill(const mg_hier* hier, int p, const double* const* u, double* gh
  * Measurement support
  * -------------------------------------------------------------------------------------------- */
 
-/* When on (per calling thread), every launch of the smoother on the finest level of a solve is
- * bracketed by two HIP events recorded on the launch stream. */
-int mg_kprof_enable(int on);
+/* period > 0 (per calling thread): every period-th launch of the smoother on the finest level of
+ * a solve (the first, then every period-th after it) is stamped by two HIP events recorded by the
+ * dispatch itself on the launch stream; 1 times every launch, 0 switches timing off.  Each timed
+ * launch costs several microseconds of extra dispatch work, so a period above 1 keeps that out
+ * of the work being timed.  Negative periods are rejected (MG_EINVAL). */
+int mg_kprof_enable(int period);
 
 /* Wait for the recorded events, return the summed launch durations (ms), the number of timed
  * launches and their algorithmic bytes (3 words per cell-update: u in, f in, u out), and reset. */

@@ -223,6 +223,7 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
 // ----------------------------------------------------------------------------------------------
 struct KProf {
     bool on = false;
+    long long period = 1, count = 0;   // time the launches with count % period == 0
     std::vector<hipEvent_t> pool;
     struct Rec { hipEvent_t a, b; double bytes; };
     std::vector<Rec> recs;
@@ -240,6 +241,7 @@ struct KEvents {
     hipEvent_t a = nullptr, b = nullptr;
     KEvents(bool time_it) {
         if (!time_it || !g_kprof.on) return;
+        if (g_kprof.count++ % g_kprof.period) return;
         a = g_kprof.get();
         b = g_kprof.get();
         if (!a || !b) a = b = nullptr;
@@ -1488,8 +1490,11 @@ extern "C" {
 
 const char* mg_last_error(void) { return g_err.c_str(); }
 
-int mg_kprof_enable(int on) {
-    g_kprof.on = on != 0;
+int mg_kprof_enable(int period) {
+    if (period < 0) return fail(MG_EINVAL, "kernel timing period < 0");
+    g_kprof.on = period != 0;
+    g_kprof.period = period > 0 ? period : 1;
+    g_kprof.count = 0;
     return MG_OK;
 }
 

@@ -372,9 +372,10 @@ def split_ghosts(hier: Hier, p: int, g):
     return out
 
 
-def mg_kprof_enable(on=True):
-    """Time every finest-level smoother launch with HIP events (calling thread only)."""
-    _check(_lib.mg_kprof_enable(1 if on else 0))
+def mg_kprof_enable(on=True, period=1):
+    """Time every period-th finest-level smoother launch with dispatch-stamped HIP events
+    (calling thread only); on=False switches timing off."""
+    _check(_lib.mg_kprof_enable(int(period) if on else 0))
 
 
 def mg_kprof_read():

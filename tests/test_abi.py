@@ -64,3 +64,24 @@ def test_null_workspace_is_rejected_before_any_device_work():
     assert b"workspace" in mgic._lib.mg_last_error()
     rc = mgic._lib.mg_solve_level(16, 1.0, None, None, ctypes.byref(o), ctypes.byref(st), None, 0, None)
     assert rc == mgic.MG_EINVAL
+
+
+def test_workspace_size_depends_on_shapes_and_precision_only():
+    # the second arrays of the fused 64^3 / 32^3 coarsenings are reserved whatever the sweep
+    # counts are, so a workspace sized once serves every nu1 / nu2
+    from paper_1103_6031_amd import mgic
+    H = mgic.Hier(128, 100.0 / 128)
+    for prec in ("fp64", "mixed"):
+        sizes = {mgic.mg_workspace_bytes(H, mgic.make_opts(prec=prec, nu1=a, nu2=b)) for a, b in ((1, 1), (2, 2), (3, 1), (0, 4))}
+        assert len(sizes) == 1, (prec, sizes)
+
+
+def test_kernel_timing_period_is_validated():
+    from paper_1103_6031_amd import mgic
+    for period in (0, 1, 9):
+        assert mgic._lib.mg_kprof_enable(period) == mgic.MG_OK
+    assert mgic._lib.mg_kprof_enable(-1) == mgic.MG_EINVAL
+    assert b"period" in mgic._lib.mg_last_error()
+    mgic._lib.mg_kprof_enable(0)
+    ms, n, by = mgic.mg_kprof_read()   # nothing recorded: no device work
+    assert n == 0 and ms == 0.0 and by == 0.0
