@@ -126,7 +126,8 @@ int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* c
  * LPT (Section 3.1)
  * -------------------------------------------------------------------------------------------- */
 
-/* Workspace bytes for lpt_displacements (what = 1) or lpt2_source (what = 2). */
+/* Workspace bytes for lpt_displacements (what = 1) or lpt2_source (what = 2).  The LPT calls
+ * below need a base of at least 2^3 cells (MG_EINVAL otherwise). */
 size_t lpt_workspace_bytes(const mg_hier* hier, int what);
 
 /* psi_c = scale * G4_c phi on every level (Table 1 fourth-order gradient).  out[3*p + c] is the

@@ -109,6 +109,108 @@ __global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h
     tau[t] = post == 1.0 ? acc : acc * post;
 }
 
+// ----------------------------------------------------------------------------------------------
+// Periodic natural-order arrays, by groups of rows: one workgroup per (x, 8 consecutive y), each
+// thread one z walking the 8 rows with the y-stencil values in a register window.  The blocks of
+// one x plane are spread over the XCDs in turn, so with one block per row every row would be
+// fetched into the L2 of each XCD whose rows are its y-neighbours; by groups, only the 4 halo rows
+// of a group are shared with the two neighbouring groups, and the blocks of x-neighbouring planes
+// (ng blocks apart) land on the same XCD whenever ng is a multiple of 8.  Same arithmetic as
+// g4 (bit-identical results).
+// ----------------------------------------------------------------------------------------------
+constexpr int kRowsY = 8;
+
+__device__ __forceinline__ double g4v(double m2, double m1, double p1, double p2, double den) {
+    double acc = m2;
+    acc = acc + (-8.0) * m1;
+    acc = acc + 8.0 * p1;
+    acc = acc + (-1.0) * p2;
+    return acc / den;
+}
+
+__device__ __forceinline__ unsigned wrap1(int a, int n) { return (unsigned)(a < 0 ? a + n : (a >= n ? a - n : a)); }
+
+struct RowGroup {
+    unsigned x, y0, pl[5], rowy[kRowsY + 4];   // x; first row; planes x-2..x+2; rows y0-2..y0+9 (wrapped)
+};
+
+__device__ __forceinline__ RowGroup row_group(Dims d) {
+    RowGroup r;
+    const unsigned ng = (unsigned)(d.y + kRowsY - 1) / kRowsY;
+    r.x = blockIdx.x / ng;
+    r.y0 = (blockIdx.x - r.x * ng) * kRowsY;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) r.pl[i] = wrap1((int)r.x - 2 + i, d.x) * (unsigned)d.y;
+#pragma unroll
+    for (int i = 0; i < kRowsY + 4; ++i) r.rowy[i] = wrap1((int)r.y0 - 2 + i, d.y);
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_grad4_rows(const double* __restrict__ p, Dims d, double h, double scale,
+                                                    double* __restrict__ ox, double* __restrict__ oy,
+                                                    double* __restrict__ oz) {
+    const RowGroup g = row_group(d);
+    const double den = 12.0 * h;
+    const unsigned nz = (unsigned)d.z;
+    for (int z = threadIdx.x; z < d.z; z += blockDim.x) {
+        const unsigned zm2 = wrap1(z - 2, d.z), zm1 = wrap1(z - 1, d.z), zp1 = wrap1(z + 1, d.z), zp2 = wrap1(z + 2, d.z);
+        double w[kRowsY + 4];
+#pragma unroll
+        for (int i = 0; i < kRowsY + 4; ++i) w[i] = p[(g.pl[2] + g.rowy[i]) * nz + z];
+#pragma unroll
+        for (int k = 0; k < kRowsY; ++k) {
+            const unsigned y = g.rowy[k + 2];
+            const unsigned rc = (g.pl[2] + y) * nz;
+            const double gx = g4v(p[(g.pl[0] + y) * nz + z], p[(g.pl[1] + y) * nz + z], p[(g.pl[3] + y) * nz + z],
+                                  p[(g.pl[4] + y) * nz + z], den);
+            const double gy = g4v(w[k], w[k + 1], w[k + 3], w[k + 4], den);
+            const double gz = g4v(p[rc + zm2], p[rc + zm1], p[rc + zp1], p[rc + zp2], den);
+            if (g.y0 + k < (unsigned)d.y) {
+                ox[rc + z] = scale * gx;
+                oy[rc + z] = scale * gy;
+                oz[rc + z] = scale * gz;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_tau_rows(const double* __restrict__ q0, const double* __restrict__ q1,
+                                                  const double* __restrict__ q2, Dims d, double h, double post,
+                                                  double* __restrict__ tau) {
+    const RowGroup g = row_group(d);
+    const double den = 12.0 * h;
+    const unsigned nz = (unsigned)d.z;
+    for (int z = threadIdx.x; z < d.z; z += blockDim.x) {
+        const unsigned zm2 = wrap1(z - 2, d.z), zm1 = wrap1(z - 1, d.z), zp1 = wrap1(z + 1, d.z), zp2 = wrap1(z + 2, d.z);
+        double w0[kRowsY + 4], w1[kRowsY + 4];
+#pragma unroll
+        for (int i = 0; i < kRowsY + 4; ++i) {
+            w0[i] = q0[(g.pl[2] + g.rowy[i]) * nz + z];
+            w1[i] = q1[(g.pl[2] + g.rowy[i]) * nz + z];
+        }
+#pragma unroll
+        for (int k = 0; k < kRowsY; ++k) {
+            const unsigned y = g.rowy[k + 2];
+            const unsigned rc = (g.pl[2] + y) * nz;
+            const double Dxx = g4v(q0[(g.pl[0] + y) * nz + z], q0[(g.pl[1] + y) * nz + z], q0[(g.pl[3] + y) * nz + z],
+                                   q0[(g.pl[4] + y) * nz + z], den);
+            const double Dyy = g4v(w1[k], w1[k + 1], w1[k + 3], w1[k + 4], den);
+            const double Dzz = g4v(q2[rc + zm2], q2[rc + zm1], q2[rc + zp1], q2[rc + zp2], den);
+            const double Dyx = g4v(w0[k], w0[k + 1], w0[k + 3], w0[k + 4], den);
+            const double Dzx = g4v(q0[rc + zm2], q0[rc + zm1], q0[rc + zp1], q0[rc + zp2], den);
+            const double Dzy = g4v(q1[rc + zm2], q1[rc + zm1], q1[rc + zp1], q1[rc + zp2], den);
+            double acc = 0.0;
+            acc = acc + (Dyy * Dxx - Dyx * Dyx);
+            acc = acc + (Dzz * Dxx - Dzx * Dzx);
+            acc = acc + (Dzz * Dyy - Dzy * Dzy);
+            if (g.y0 + k < (unsigned)d.y) tau[rc + z] = post == 1.0 ? acc : acc * post;
+        }
+    }
+}
+
+static unsigned rows_grid(Dims d) { return (unsigned)d.x * (unsigned)((d.y + kRowsY - 1) / kRowsY); }
+static unsigned rows_block(Dims d) { return d.z >= 256 ? 256u : (unsigned)((d.z + 63) / 64 * 64); }
+
 // padded copy of a patch with width-R tri-quadratic ghosts from its parent
 __global__ void k_wide_ghost(const double* __restrict__ pu, const double* __restrict__ u, double* __restrict__ out,
                              Dims d, ParentMap pm, int R, Lay B) {
@@ -161,7 +263,7 @@ void launch_grad4(const double* src, int R, Dims d, double h, double scale, doub
                   hipStream_t st) {
     const Lay B(d, 0);
     if (R == 0)
-        k_grad4<false><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{src, 0, d}, B, h, scale, ox, oy, oz);
+        k_grad4_rows<<<rows_grid(d), rows_block(d), 0, st>>>(src, d, h, scale, ox, oy, oz);
     else
         k_grad4<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, B, h, scale, ox, oy, oz);
 }
@@ -175,8 +277,7 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
     double* p2 = psi + 2 * E.d.cells();
     if (R == 0) {
         k_psi<false><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<false>{src, 0, d}, E, 0, h, p0, p1, p2);
-        k_tau_psi<false><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{p0, 0, d}, Src<false>{p1, 0, d},
-                                                                 Src<false>{p2, 0, d}, B, h, 1.0, tau);
+        k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(p0, p1, p2, d, h, 1.0, tau);
     } else {
         k_psi<true><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, E, e, h, p0, p1, p2);
         k_tau_psi<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{p0, e, d}, Src<true>{p1, e, d},
@@ -186,9 +287,7 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
 
 void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
                          double* tau, hipStream_t st) {
-    const Lay B(d, 0);
-    k_tau_psi<false><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{g0, 0, d}, Src<false>{g1, 0, d},
-                                                             Src<false>{g2, 0, d}, B, h, post, tau);
+    k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(g0, g1, g2, d, h, post, tau);
 }
 
 }  // namespace mgic

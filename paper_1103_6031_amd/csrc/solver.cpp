@@ -710,6 +710,8 @@ static int lpt_common(const mg_hier* H, int what, const double* const* phi, void
                       hipStream_t st, LptPlan& lp) {
     int rc = validate_hier(H);
     if (rc) return rc;
+    // the periodic stencils wrap an offset of up to 2 cells once
+    if (H->lev[0].n[0] < 2) return fail(MG_EINVAL, "LPT needs a base of at least 2^3 cells");
     if (!phi) return fail(MG_EINVAL, "phi is NULL");
     for (int p = 0; p < H->nlev; ++p)
         if (!phi[p]) return fail(MG_EINVAL, "phi level pointer is NULL");

@@ -85,3 +85,12 @@ def test_kernel_timing_period_is_validated():
     mgic._lib.mg_kprof_enable(0)
     ms, n, by = mgic.mg_kprof_read()   # nothing recorded: no device work
     assert n == 0 and ms == 0.0 and by == 0.0
+
+
+def test_lpt_rejects_a_single_cell_base_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    H = mgic.Hier(1, 1.0).c_struct()
+    ptrs = (ctypes.c_void_p * 3)(16, 16, 16)
+    rc = mgic._lib.lpt_displacements(ctypes.byref(H), ptrs, ptrs, -1.0, ctypes.c_void_p(256), 1 << 20, None)
+    assert rc == mgic.MG_EINVAL
+    assert b"2^3" in mgic._lib.mg_last_error()

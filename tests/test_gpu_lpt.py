@@ -16,7 +16,9 @@ def mg():
     return mgic
 
 
-@pytest.mark.parametrize("N", [8, 16, 48])
+# 2: the smallest base (stencil offsets wrap once); 20: a partial group of rows in the row-group
+# kernels; 64: 8 groups per plane
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 20, 48, 64])
 def test_periodic_grad_and_tau_bit_exact(mg, N):
     rng = np.random.default_rng(N)
     phi = rng.standard_normal((N, N, N))
