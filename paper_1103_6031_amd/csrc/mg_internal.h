@@ -217,6 +217,12 @@ template <class T>
 void launch_resid_restrict_p2(const T* u, const T* f, int n, double h, T* pu, T* pf, T* uold, hipStream_t st);
 template <class T> void launch_prolong_black_p2(T* u, int n, const T* pu, const T* uold, hipStream_t st);
 template <class T> void launch_fas_rhs_p2(const T* pu, T* pf, int n, double H, hipStream_t st);
+// red-black half-sweep with 16-byte accesses on a periodic colour-split power-of-two level whose
+// half-rows hold a multiple of 16 bytes (rbgs_vec_ok); same bits as launch_rbgs_half
+bool rbgs_vec_ok(const Lay& L, size_t elem);
+template <class T>
+void launch_rbgs_vec(T* u, const T* f, const Lay& L, double h, int colour, hipStream_t st, hipEvent_t ev0,
+                     hipEvent_t ev1);
 template <class T>
 void launch_level_pre(const T* u, const T* f, T* uo, T* fo, T* pu, T* pf, T* uold, int n, double h, int nu1,
                       hipStream_t st);

@@ -280,7 +280,10 @@ static void smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_r
             if (skip_first_red && s == 0 && c == 0) continue;  // already done by the fused outer step
             if (!L.periodic) ghosts<T>(P, l, st);
             KEvents ev(timed);
-            launch_rbgs_half<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, c, st, ev.a, ev.b);
+            if (L.periodic && rbgs_vec_ok(L.lay, sizeof(T)))
+                launch_rbgs_vec<T>(b.u, b.f, L.lay, L.h, c, st, ev.a, ev.b);
+            else
+                launch_rbgs_half<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, c, st, ev.a, ev.b);
             ev.done(half_bytes);
         }
 }

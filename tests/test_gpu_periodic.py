@@ -20,7 +20,9 @@ def mg():
     return mgic
 
 
-@pytest.mark.parametrize("N,half", [(8, 1), (16, 2), (32, 3), (48, 4), (96, 2), (128, 4)])
+# power-of-two sizes take the 16-byte-access half-sweep (4: one run is the whole half-row, its
+# z-edge wraps onto itself), 48 and 96 the scalar one
+@pytest.mark.parametrize("N,half", [(4, 2), (8, 1), (16, 2), (32, 3), (48, 4), (96, 2), (128, 4)])
 def test_smoother_bit_exact_fp64(mg, N, half):
     rng = np.random.default_rng(N + half)
     u0 = rng.standard_normal((N, N, N))
@@ -35,7 +37,7 @@ def test_smoother_bit_exact_fp64(mg, N, half):
     assert np.array_equal(to_host(ut), ue)
 
 
-@pytest.mark.parametrize("N,half", [(16, 2), (64, 4), (96, 3)])
+@pytest.mark.parametrize("N,half", [(4, 2), (8, 2), (16, 2), (64, 4), (96, 3), (256, 2)])
 def test_smoother_fp32_bit_exact_against_float32_oracle(mg, N, half):
     rng = np.random.default_rng(7 * N)
     u0 = rng.standard_normal((N, N, N)).astype(np.float32)
