@@ -878,6 +878,10 @@ __global__ void k_residual_split(const T* __restrict__ u, const T* __restrict__ 
 //   u_out = v,  rhs = (float) r,  e_out = the first red half-sweep of the next inner cycle from
 //   e = 0, i.e. (0 - h^2 rhs) / 6 on red cells; black entries are not written.
 // v is formed on the fly for the 7 stencil points, so u_out / e_out must not alias the inputs.
+// pairs of cells need half-rows of even length (then no pair straddles two half-rows, and the
+// 16-byte accesses are aligned)
+__host__ __device__ __forceinline__ bool outer_pairs(const Lay& L) { return ((L.d.z >> 1) & 1) == 0; }
+
 // HU: u_in is read (false: a zero start, v = 0); HE: e_in is added.  The three cases are separate
 // instantiations: with the choice made per load at run time the kernel measured 193 against
 // 167 us at 256^3.
@@ -920,14 +924,97 @@ __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_
     return acc;
 }
 
+// The same on pairs of cells: a thread takes the cells t, t + 1 (t even; half-rows have an even
+// length here, so both lie in one half-row) and reads every stencil run as a 16-byte u and an
+// 8-byte e vector, plus the one z-neighbour entry outside the pair.  Each block covers the same
+// cells as in body_outer_split (so batched and solo launches agree); within a block the partial
+// sum takes the cells pair by pair.
+template <bool HU, bool HE>
+__device__ __forceinline__ double body_outer_pairs(const double* __restrict__ u_in, const float* __restrict__ e_in,
+                                                   const double* __restrict__ f, double* __restrict__ u_out,
+                                                   float* __restrict__ rhs, float* __restrict__ e_out,
+                                                   const Lay& L, double h2, float h2f, unsigned blk, unsigned nblk) {
+    const unsigned n = (unsigned)L.d.cells(), nzh = (unsigned)L.d.z >> 1;
+    double acc = 0.0;
+    const unsigned lo = red_lo(blk), stride = red_stride(nblk);
+    for (unsigned p0 = lo; p0 < n; p0 += stride)
+#pragma unroll
+    for (int v = 0; v < kRedV / 2; ++v) {
+        const unsigned t = p0 + 2 * (threadIdx.x + v * blockDim.x);
+        if (t >= n) break;
+        const SplitNb c = split_nb(L, t);
+        const unsigned j = c.j, oth = c.oth, r0 = c.r0, q = (unsigned)c.q;
+        double c0[2] = {0.0, 0.0}, s[2] = {0.0, 0.0};   // a zero start: the stencil sums are +0 exactly
+        if constexpr (HU) {
+            // values of v = u (+ e) at positions i, i + 1 of a run
+            auto V2 = [&](unsigned i, double* out) {
+                const double2 a = *(const double2*)(u_in + i);
+                if constexpr (HE) {
+                    const float2 b = *(const float2*)(e_in + i);
+                    out[0] = a.x + (double)b.x;
+                    out[1] = a.y + (double)b.y;
+                } else {
+                    out[0] = a.x;
+                    out[1] = a.y;
+                }
+            };
+            auto V1 = [&](unsigned i) {
+                if constexpr (HE) return u_in[i] + (double)e_in[i];
+                else return u_in[i];
+            };
+            double xm[2], xp[2], ym[2], yp[2], cz[2];
+            V2(t, c0);
+            V2(c.rxm + oth + j, xm);
+            V2(c.rxp + oth + j, xp);
+            V2(c.rym + oth + j, ym);
+            V2(c.ryp + oth + j, yp);
+            V2(r0 + oth + j, cz);   // the other colour's entries j, j + 1 of this row
+            // cell j + k sits at z = 2(j + k) + q; its z-neighbours are the other colour's entries
+            // j + k - 1 + q and j + k + q
+            const unsigned je = q ? (j + 2 >= nzh ? j + 2 - nzh : j + 2) : (j == 0 ? nzh - 1 : j - 1);
+            const double edge = V1(r0 + oth + je);
+            const double zm0 = q ? cz[0] : edge, zp0 = q ? cz[1] : cz[0];
+            const double zm1 = q ? cz[1] : cz[0], zp1 = q ? edge : cz[1];
+            s[0] = ((xm[0] + xp[0]) + (ym[0] + yp[0])) + (zm0 + zp0);
+            s[1] = ((xm[1] + xp[1]) + (ym[1] + yp[1])) + (zm1 + zp1);
+        }
+        const double2 fv = *(const double2*)(f + t);
+        const double r0v = fv.x - (s[0] - 6.0 * c0[0]) / h2;
+        const double r1v = fv.y - (s[1] - 6.0 * c0[1]) / h2;
+        acc += r0v * r0v;
+        acc += r1v * r1v;
+        const float rf0 = (float)r0v, rf1 = (float)r1v;
+        *(double2*)(u_out + t) = double2{c0[0], c0[1]};
+        *(float2*)(rhs + t) = float2{rf0, rf1};
+        // black entries of e_out are left as they are (see body_outer_split)
+        if (!c.col) *(float2*)(e_out + t) = float2{(0.0f - h2f * rf0) / 6.0f, (0.0f - h2f * rf1) / 6.0f};
+    }
+    return acc;
+}
+
 __device__ __forceinline__ double body_outer_split_any(const double* __restrict__ u_in,
                                                        const float* __restrict__ e_in, const double* __restrict__ f,
                                                        double* __restrict__ u_out, float* __restrict__ rhs,
                                                        float* __restrict__ e_out, const Lay& L, double h2, float h2f,
                                                        unsigned blk, unsigned nblk) {
+    if (outer_pairs(L)) {
+        if (!u_in) return body_outer_pairs<false, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
+        if (e_in) return body_outer_pairs<true, true>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
+        return body_outer_pairs<true, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
+    }
     if (!u_in) return body_outer_split<false, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
     if (e_in) return body_outer_split<true, true>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
     return body_outer_split<true, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
+}
+
+template <bool HU, bool HE>
+__global__ void k_outer_pairs(const double* __restrict__ u_in, const float* __restrict__ e_in,
+                              const double* __restrict__ f, double* __restrict__ u_out, float* __restrict__ rhs,
+                              float* __restrict__ e_out, Lay L, double h2, float h2f,
+                              double* __restrict__ partials) {
+    const double bs =
+        block_sum(body_outer_pairs<HU, HE>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blockIdx.x, gridDim.x));
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
 template <bool HU, bool HE>
@@ -945,7 +1032,11 @@ void launch_outer_split(const double* u_in, const float* e_in, const double* f, 
     const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
     const double h2 = h * h;
     const float h2f = (float)(h * h);
-    if (!u_in) k_outer_split<false, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
+    if (outer_pairs(L)) {
+        if (!u_in) k_outer_pairs<false, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
+        else if (e_in) k_outer_pairs<true, true><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
+        else k_outer_pairs<true, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
+    } else if (!u_in) k_outer_split<false, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
     else if (e_in) k_outer_split<true, true><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
     else k_outer_split<true, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
     *nparts = g;
