@@ -885,7 +885,7 @@ __host__ __device__ __forceinline__ bool outer_pairs(const Lay& L) { return ((L.
 // HU: u_in is read (false: a zero start, v = 0); HE: e_in is added.  The three cases are separate
 // instantiations: with the choice made per load at run time the kernel measured 193 against
 // 167 us at 256^3.
-template <bool HU, bool HE>
+template <bool HU, bool HE, bool WU = HU || HE>
 __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_in, const float* __restrict__ e_in,
                                                    const double* __restrict__ f, double* __restrict__ u_out,
                                                    float* __restrict__ rhs, float* __restrict__ e_out,
@@ -903,10 +903,11 @@ __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_
         const unsigned j = c.j, col = c.col, oth = c.oth, r0 = c.r0, rxm = c.rxm, rxp = c.rxp, rym = c.rym,
                        ryp = c.ryp, jm = c.jm, jp = c.jp;
         double c0 = 0.0, s = 0.0;   // a zero start: the stencil sums are +0 exactly
-        if constexpr (HU) {
+        if constexpr (HU || HE) {
             auto V = [&](unsigned i) {
-                if constexpr (HE) return u_in[i] + (double)e_in[i];
-                else return u_in[i];
+                if constexpr (HU && HE) return u_in[i] + (double)e_in[i];
+                else if constexpr (HU) return u_in[i];
+                else return 0.0 + (double)e_in[i];   // u taken as +0 (the same bits as u = +0 read)
             };
             c0 = V(t);
             s = ((V(rxm + oth + j) + V(rxp + oth + j)) + (V(rym + oth + j) + V(ryp + oth + j))) +
@@ -915,7 +916,7 @@ __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_
         const double r = f[t] - (s - 6.0 * c0) / h2;
         acc += r * r;
         const float rf = (float)r;
-        u_out[t] = c0;
+        if constexpr (WU) u_out[t] = c0;   // WU = false: a zero start leaves the zero iterate implicit
         rhs[t] = rf;
         // black entries of e_out are left as they are: the black half-sweep that follows writes
         // every one of them before anything reads them
@@ -929,7 +930,7 @@ __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_
 // 8-byte e vector, plus the one z-neighbour entry outside the pair.  Each block covers the same
 // cells as in body_outer_split (so batched and solo launches agree); within a block the partial
 // sum takes the cells pair by pair.
-template <bool HU, bool HE>
+template <bool HU, bool HE, bool WU = HU || HE>
 __device__ __forceinline__ double body_outer_pairs(const double* __restrict__ u_in, const float* __restrict__ e_in,
                                                    const double* __restrict__ f, double* __restrict__ u_out,
                                                    float* __restrict__ rhs, float* __restrict__ e_out,
@@ -945,22 +946,28 @@ __device__ __forceinline__ double body_outer_pairs(const double* __restrict__ u_
         const SplitNb c = split_nb(L, t);
         const unsigned j = c.j, oth = c.oth, r0 = c.r0, q = (unsigned)c.q;
         double c0[2] = {0.0, 0.0}, s[2] = {0.0, 0.0};   // a zero start: the stencil sums are +0 exactly
-        if constexpr (HU) {
-            // values of v = u (+ e) at positions i, i + 1 of a run
+        if constexpr (HU || HE) {
+            // values of v = u (+ e) at positions i, i + 1 of a run (u taken as +0 without HU)
             auto V2 = [&](unsigned i, double* out) {
-                const double2 a = *(const double2*)(u_in + i);
-                if constexpr (HE) {
+                if constexpr (HU && HE) {
+                    const double2 a = *(const double2*)(u_in + i);
                     const float2 b = *(const float2*)(e_in + i);
                     out[0] = a.x + (double)b.x;
                     out[1] = a.y + (double)b.y;
-                } else {
+                } else if constexpr (HU) {
+                    const double2 a = *(const double2*)(u_in + i);
                     out[0] = a.x;
                     out[1] = a.y;
+                } else {
+                    const float2 b = *(const float2*)(e_in + i);
+                    out[0] = 0.0 + (double)b.x;
+                    out[1] = 0.0 + (double)b.y;
                 }
             };
             auto V1 = [&](unsigned i) {
-                if constexpr (HE) return u_in[i] + (double)e_in[i];
-                else return u_in[i];
+                if constexpr (HU && HE) return u_in[i] + (double)e_in[i];
+                else if constexpr (HU) return u_in[i];
+                else return 0.0 + (double)e_in[i];
             };
             double xm[2], xp[2], ym[2], yp[2], cz[2];
             V2(t, c0);
@@ -984,7 +991,7 @@ __device__ __forceinline__ double body_outer_pairs(const double* __restrict__ u_
         acc += r0v * r0v;
         acc += r1v * r1v;
         const float rf0 = (float)r0v, rf1 = (float)r1v;
-        *(double2*)(u_out + t) = double2{c0[0], c0[1]};
+        if constexpr (WU) *(double2*)(u_out + t) = double2{c0[0], c0[1]};
         *(float2*)(rhs + t) = float2{rf0, rf1};
         // black entries of e_out are left as they are (see body_outer_split)
         if (!c.col) *(float2*)(e_out + t) = float2{(0.0f - h2f * rf0) / 6.0f, (0.0f - h2f * rf1) / 6.0f};
@@ -998,32 +1005,32 @@ __device__ __forceinline__ double body_outer_split_any(const double* __restrict_
                                                        float* __restrict__ e_out, const Lay& L, double h2, float h2f,
                                                        unsigned blk, unsigned nblk) {
     if (outer_pairs(L)) {
-        if (!u_in) return body_outer_pairs<false, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
+        if (!u_in) return body_outer_pairs<false, false, true>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
         if (e_in) return body_outer_pairs<true, true>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
         return body_outer_pairs<true, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
     }
-    if (!u_in) return body_outer_split<false, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
+    if (!u_in) return body_outer_split<false, false, true>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
     if (e_in) return body_outer_split<true, true>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
     return body_outer_split<true, false>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blk, nblk);
 }
 
-template <bool HU, bool HE>
+template <bool HU, bool HE, bool WU>
 __global__ void k_outer_pairs(const double* __restrict__ u_in, const float* __restrict__ e_in,
                               const double* __restrict__ f, double* __restrict__ u_out, float* __restrict__ rhs,
                               float* __restrict__ e_out, Lay L, double h2, float h2f,
                               double* __restrict__ partials) {
     const double bs =
-        block_sum(body_outer_pairs<HU, HE>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blockIdx.x, gridDim.x));
+        block_sum(body_outer_pairs<HU, HE, WU>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blockIdx.x, gridDim.x));
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
-template <bool HU, bool HE>
+template <bool HU, bool HE, bool WU>
 __global__ void k_outer_split(const double* __restrict__ u_in, const float* __restrict__ e_in,
                               const double* __restrict__ f, double* __restrict__ u_out, float* __restrict__ rhs,
                               float* __restrict__ e_out, Lay L, double h2, float h2f,
                               double* __restrict__ partials) {
     const double bs =
-        block_sum(body_outer_split<HU, HE>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blockIdx.x, gridDim.x));
+        block_sum(body_outer_split<HU, HE, WU>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, blockIdx.x, gridDim.x));
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
@@ -1032,13 +1039,19 @@ void launch_outer_split(const double* u_in, const float* e_in, const double* f, 
     const int g = grid_for(L.d.cells(), kBlock * kRedV, kMaxPartials);
     const double h2 = h * h;
     const float h2f = (float)(h * h);
+#define MG_OUTER(K, HU, HE) K<HU, HE, HU || HE><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials)
     if (outer_pairs(L)) {
-        if (!u_in) k_outer_pairs<false, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
-        else if (e_in) k_outer_pairs<true, true><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
-        else k_outer_pairs<true, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
-    } else if (!u_in) k_outer_split<false, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
-    else if (e_in) k_outer_split<true, true><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
-    else k_outer_split<true, false><<<g, kBlock, 0, st>>>(u_in, e_in, f, u_out, rhs, e_out, L, h2, h2f, partials);
+        if (u_in && e_in) MG_OUTER(k_outer_pairs, true, true);
+        else if (u_in) MG_OUTER(k_outer_pairs, true, false);
+        else if (e_in) MG_OUTER(k_outer_pairs, false, true);
+        else MG_OUTER(k_outer_pairs, false, false);
+    } else {
+        if (u_in && e_in) MG_OUTER(k_outer_split, true, true);
+        else if (u_in) MG_OUTER(k_outer_split, true, false);
+        else if (e_in) MG_OUTER(k_outer_split, false, true);
+        else MG_OUTER(k_outer_split, false, false);
+    }
+#undef MG_OUTER
     *nparts = g;
 }
 

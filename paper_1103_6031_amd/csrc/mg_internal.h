@@ -245,7 +245,9 @@ template <class T, class R> void launch_residual(const T* u, const T* f, const T
                                                  hipStream_t st);
 // fused outer step of the mixed-precision defect correction on a colour-split periodic level:
 // u_out = u_in + e_in, rhs = (float)(f - L u_out), red e_out = first red half-sweep from e = 0;
-// per-block partial sums of r^2.  u_in == nullptr: u_in = 0 (not read), e_in must be null too
+// per-block partial sums of r^2.  u_in == nullptr: u_in taken as +0 (not read); if e_in is null
+// as well (the first step of a zero start), u_out is not written either - the caller keeps the
+// zero iterate implicit and passes u_in == nullptr again with the next correction
 void launch_outer_split(const double* u_in, const float* e_in, const double* f, double* u_out, float* rhs,
                         float* e_out, Lay L, double h, double* partials, int* nparts, hipStream_t st);
 // per-block partial sums of a (or a^2) over cells outside cov

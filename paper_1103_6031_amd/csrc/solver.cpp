@@ -573,10 +573,12 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
         // side and the first red half-sweep of the next inner cycle are one kernel
         Level& L = P.L[0];
         bool pending = false;
+        bool u_zero = zero_start;   // the iterate is +0 and not stored (a zero start, before its first correction)
         for (;;) {
             int np = 0;
-            launch_outer_split((zero_start && !pending) ? nullptr : L.u, pending ? L.u32 : nullptr, L.f, L.ualt, L.f32,
-                               L.ealt, L.lay, L.h, P.partials, &np, st);
+            launch_outer_split(u_zero ? nullptr : L.u, pending ? L.u32 : nullptr, L.f, L.ualt, L.f32, L.ealt, L.lay,
+                               L.h, P.partials, &np, st);
+            if (pending) u_zero = false;   // this step stored u = 0 + e
             std::swap(L.u, L.ualt);
             std::swap(L.u32, L.ealt);
             SegList sg{};
@@ -601,6 +603,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             }
             pending = true;
         }
+        if (u_zero) launch_fill<double>(L.u, L.d.cells(), 0.0, st);   // stopped before any correction
     } else {
         std::vector<float*> rhs(P.nh);
         for (int l = 0; l < P.nh; ++l) rhs[l] = P.L[l].f32;

@@ -154,3 +154,20 @@ def test_batch_equals_solo(mg):
             assert np.array_equal(to_host(u), to_host(us))
             ue, _ = periodic.solve_level(f, h, tol=1e-12)
             assert rel_rms(to_host(u), ue) <= (1e-10 if prec == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("N", [32, 64])
+def test_mixed_zero_start_stopping_at_once_returns_zero(mg, N):
+    # the first outer step of a zero start leaves u = 0 implicit: a solve that stops right there
+    # (a constant f is zero once its mean is removed; or no cycle allowed) must still return 0
+    h = 100.0 / N
+    note("mixed zero start, immediate stop, N=%d" % N)
+    f = np.full((N, N, N), 2.5)
+    u, st = mg.mg_solve_level(to_dev(f), h, opts=mg.make_opts(tol=1e-10, prec="mixed", max_cycles=40))
+    assert st["cycles"] == 0 and st["f_mean"] == 2.5
+    assert np.array_equal(to_host(u), np.zeros_like(f))
+    g = inputs.gaussian_field(N, 4242)
+    u0 = to_dev(np.full((N, N, N), 7.0))   # the output array starts non-zero
+    u, st = mg.mg_solve_level(to_dev(g), h, u=u0, opts=mg.make_opts(prec="mixed", max_cycles=0, fixed_cycles=True))
+    assert st["cycles"] == 0
+    assert np.array_equal(to_host(u), np.zeros_like(g))
