@@ -415,10 +415,14 @@ void launch_rbgs_vec(T* u, const T* f, const Lay& L, double h, int colour, hipSt
     constexpr int W = Vec16<T>::W;
     const unsigned chunks = (unsigned)(L.d.cells() / 2 / W);
     const T h2 = (T)(h * h);
-    constexpr int CH = sizeof(T) == 8 ? 2 : 1;   // measured at 256^3: FP32 best at 1 run per thread, FP64 at 2
-    const unsigned blocks = (chunks + 256 * CH - 1) / (256 * CH);
-    hipExtLaunchKernelGGL(k_rbgs_vec<T, CH>, dim3(blocks), dim3(256), 0, st, ev0, ev1, 0, u, f, L.lgx, L.lgy, L.lgz,
-                          h2, colour);
+    // measured: 1 run per thread is best for FP32 at 128^3 and 256^3 and for FP64 at 128^3; FP64
+    // at 256^3 and above is 5% faster with 2
+    if (sizeof(T) == 8 && chunks >= (1u << 22))
+        hipExtLaunchKernelGGL(k_rbgs_vec<T, 2>, dim3((chunks + 511) / 512), dim3(256), 0, st, ev0, ev1, 0, u, f, L.lgx,
+                              L.lgy, L.lgz, h2, colour);
+    else
+        hipExtLaunchKernelGGL(k_rbgs_vec<T, 1>, dim3((chunks + 255) / 256), dim3(256), 0, st, ev0, ev1, 0, u, f, L.lgx,
+                              L.lgy, L.lgz, h2, colour);
 }
 
 bool level_fusable(int n, int nu1, int nu2) {
