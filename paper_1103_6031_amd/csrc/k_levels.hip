@@ -404,6 +404,99 @@ k_rbgs_vec(T* __restrict__ u, const T* __restrict__ f, int lgx, int lgy, int lgz
     }
 }
 
+// The first red half-sweep after the coarse-grid correction (step 8 then step 9), in one pass:
+// the correction u += pu[parent] - uold[parent] of the black cells is only ever read by this
+// half-sweep (the black half-sweep after it rewrites every black cell without reading it), so it
+// is applied here to each black value as it is read, and never stored.  A black cell (row, j) of
+// the fine level lies in the parent (x >> 1, y >> 1, j); the parents of a run of W black cells are
+// W consecutive Z of one coarse row: a vector of uold (natural order) and two half-vectors of pu
+// (colour-split order, even and odd Z in the two halves).  Same arithmetic as k_prolong_black_p2
+// followed by k_rbgs_vec, so the same bits.
+// d[k] = pu - uold for the parents (X, Y, j0 + k) of a run of W black cells
+template <class T>
+__device__ __forceinline__ void corr_delta(const T* __restrict__ pu, const T* __restrict__ uold, int lc, unsigned X,
+                                           unsigned Y, unsigned j0, T* d) {
+    constexpr int W = Vec16<T>::W;
+    const unsigned nch = (1u << lc) >> 1;
+    const unsigned rb = ((X << lc) | Y) << lc;
+    const unsigned he = ((X + Y) & 1u) * nch, ho = nch - he;   // halves holding even / odd Z
+    const typename Vec16<T>::type o = *(const typename Vec16<T>::type*)(uold + rb + j0);
+    if constexpr (W == 4) {
+        const float2 pe = *(const float2*)(pu + rb + he + (j0 >> 1)), po = *(const float2*)(pu + rb + ho + (j0 >> 1));
+        d[0] = pe.x - o.x;
+        d[1] = po.x - o.y;
+        d[2] = pe.y - o.z;
+        d[3] = po.y - o.w;
+    } else {
+        d[0] = pu[rb + he + (j0 >> 1)] - o.x;
+        d[1] = pu[rb + ho + (j0 >> 1)] - o.y;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+k_rbgs_vec_corr(T* __restrict__ u, const T* __restrict__ f, int lgx, int lgy, int lgz, T h2,
+                const T* __restrict__ pu, const T* __restrict__ uold) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
+    const unsigned lzh = (unsigned)lgz - 1, nzh = 1u << lzh, mx = (1u << lgx) - 1, my = (1u << lgy) - 1;
+    const int lc = lgz - 1;                        // the coarse level is a cube of edge 2^(lgz - 1)
+    const unsigned chunks = 1u << (lgx + lgy + lzh - __builtin_ctz(W));
+    const unsigned ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= chunks) return;
+    const unsigned t = ch * W, row = t >> lzh, j0 = t & (nzh - 1);
+    const unsigned x = row >> lgy, y = row & my;
+    const unsigned q = (x + y) & 1u;              // z parity of red cells in the row
+    const unsigned r0 = row << lgz;
+    const unsigned xm = (x - 1) & mx, xp = (x + 1) & mx, ym = (y - 1) & my, yp = (y + 1) & my;
+    // the black runs read are those of rows x-1, x+1, y-1, y+1 and the own row; their parents lie in
+    // the own parent row (X, Y) and in one more row along x (for x-1 if x is even, else x+1) and
+    // one along y, so three correction runs cover all five
+    const unsigned X = x >> 1, Y = y >> 1;
+    T dO[W], dX[W], dY[W];
+    corr_delta<T>(pu, uold, lc, X, Y, j0, dO);
+    corr_delta<T>(pu, uold, lc, ((x & 1u) ? xp : xm) >> 1, Y, j0, dX);
+    corr_delta<T>(pu, uold, lc, X, ((y & 1u) ? yp : ym) >> 1, j0, dY);
+    auto run = [&](unsigned xr, unsigned yr, const T* d, T* c) {
+        const V v = *(const V*)(u + (((xr << lgy) | yr) << lgz) + nzh + j0);
+#pragma unroll
+        for (int k = 0; k < W; ++k) c[k] = lane<T>(v, k) + d[k];
+    };
+    T XM[W], XP[W], YM[W], YP[W], C[W];
+    run(xm, y, (x & 1u) ? dO : dX, XM);
+    run(xp, y, (x & 1u) ? dX : dO, XP);
+    run(x, ym, (y & 1u) ? dO : dY, YM);
+    run(x, yp, (y & 1u) ? dY : dO, YP);
+    run(x, y, dO, C);
+    // the one black entry of the own row outside the run (j0 - 1 or j0 + W, by parity), corrected
+    const unsigned je = q ? ((j0 + W) & (nzh - 1)) : ((j0 - 1) & (nzh - 1));
+    T edge;
+    {
+        const unsigned ncz = 1u << lc, rb = ((X << lc) | Y) << lc;
+        edge = u[r0 + nzh + je] + (pu[rb + ((X + Y + je) & 1u) * (ncz >> 1) + (je >> 1)] - uold[rb + je]);
+    }
+    const V F = *(const V*)(f + r0 + j0);
+    T out[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const T zm = q ? C[k] : (k == 0 ? edge : C[k - 1]);
+        const T zp = q ? (k == W - 1 ? edge : C[k + 1]) : C[k];
+        const T s = ((XM[k] + XP[k]) + (YM[k] + YP[k])) + (zm + zp);
+        out[k] = (s - h2 * lane<T>(F, k)) / T(6);
+    }
+    V o;
+    if constexpr (W == 4) o = V{out[0], out[1], out[2], out[3]};
+    else o = V{out[0], out[1]};
+    *(V*)(u + r0 + j0) = o;
+}
+
+template <class T>
+void launch_rbgs_vec_corr(T* u, const T* f, const Lay& L, double h, const T* pu, const T* uold, hipStream_t st) {
+    constexpr int W = Vec16<T>::W;
+    const unsigned chunks = (unsigned)(L.d.cells() / 2 / W);
+    k_rbgs_vec_corr<T><<<(chunks + 255) / 256, 256, 0, st>>>(u, f, L.lgx, L.lgy, L.lgz, (T)(h * h), pu, uold);
+}
+
 bool rbgs_vec_ok(const Lay& L, size_t elem) {
     const unsigned W = 16u / (unsigned)elem;
     return L.pow2 && L.split && L.lgz >= 1 && ((1u << (L.lgz - 1)) % W) == 0;
@@ -454,6 +547,7 @@ void launch_level_post(const T* ui, const T* fi, const T* uc, const T* uold, T* 
     template void launch_prolong_black_p2<T>(T*, int, const T*, const T*, hipStream_t);                       \
     template void launch_fas_rhs_p2<T>(const T*, T*, int, double, hipStream_t);                               \
     template void launch_rbgs_vec<T>(T*, const T*, const Lay&, double, int, hipStream_t, hipEvent_t, hipEvent_t); \
+    template void launch_rbgs_vec_corr<T>(T*, const T*, const Lay&, double, const T*, const T*, hipStream_t);     \
     template void launch_level_pre<T>(const T*, const T*, T*, T*, T*, T*, T*, int, double, int, hipStream_t); \
     template void launch_level_post<T>(const T*, const T*, const T*, const T*, T*, int, double, int, hipStream_t);
 MG_INST(float)

@@ -220,6 +220,11 @@ template <class T> void launch_fas_rhs_p2(const T* pu, T* pf, int n, double H, h
 // red-black half-sweep with 16-byte accesses on a periodic colour-split power-of-two level whose
 // half-rows hold a multiple of 16 bytes (rbgs_vec_ok); same bits as launch_rbgs_half
 bool rbgs_vec_ok(const Lay& L, size_t elem);
+// step 8 on the black cells and the first red half-sweep of step 9 in one pass (the corrected
+// black values are read, not stored: the black half-sweep after it rewrites them); pu is the
+// coarse level's u, uold this level's restricted copy; periodic power-of-two cube, rbgs_vec_ok
+template <class T>
+void launch_rbgs_vec_corr(T* u, const T* f, const Lay& L, double h, const T* pu, const T* uold, hipStream_t st);
 template <class T>
 void launch_rbgs_vec(T* u, const T* f, const Lay& L, double h, int colour, hipStream_t st, hipEvent_t ev0,
                      hipEvent_t ev1);
