@@ -223,6 +223,9 @@ bool rbgs_vec_ok(const Lay& L, size_t elem);
 // step 8 on the black cells and the first red half-sweep of step 9 in one pass (the corrected
 // black values are read, not stored: the black half-sweep after it rewrites them); pu is the
 // coarse level's u, uold this level's restricted copy; periodic power-of-two cube, rbgs_vec_ok
+// step 6 on a whole periodic colour-split power-of-two cube of edge n with 16-byte runs (both
+// colours of a run per thread; half-rows a multiple of 16 bytes); same bits as launch_fas_rhs_p2
+template <class T> void launch_fas_vec(const T* pu, T* pf, int n, double H, hipStream_t st);
 template <class T>
 void launch_rbgs_vec_corr(T* u, const T* f, const Lay& L, double h, const T* pu, const T* uold, hipStream_t st);
 template <class T>

@@ -347,7 +347,8 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
     if (p2) launch_resid_restrict_p2<T>(b.u, b.f, L.d.x, L.h, q.u, q.f, b.uold, st);
     else launch_resid_restrict<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, q.u, q.f, b.uold, L.pm, st);
     if (!fused<T>(P, l + 1)) {
-        if (p2 && Q.lay.pow2 && Q.lay.split) launch_fas_rhs_p2<T>(q.u, q.f, Q.d.x, Q.h, st);
+        if (p2 && Q.lay.pow2 && Q.lay.split && rbgs_vec_ok(Q.lay, sizeof(T))) launch_fas_vec<T>(q.u, q.f, Q.d.x, Q.h, st);
+        else if (p2 && Q.lay.pow2 && Q.lay.split) launch_fas_rhs_p2<T>(q.u, q.f, Q.d.x, Q.h, st);
         else launch_fas_rhs<T>(q.u, q.f, L.pm, Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, Q.h, st);
     }
     vcycle<T>(P, l + 1, st);                         // step 7

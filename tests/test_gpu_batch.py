@@ -80,6 +80,22 @@ def test_fused_levels_match_one_step_kernels(mg, prec, nu):
         _same_stats(s, ss)
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_full_size_instance_bit_identical(mg, prec):
+    """A 256^3 instance: the solo solve takes the power-of-two kernels at 256^3 and 128^3 (16-byte
+    half-sweeps, the correction folded into the first red half-sweep, the FAS right-hand side by
+    runs, the residual-restriction by 4x4x4 neighbourhoods), the batched one the generic kernels."""
+    sizes = [256, 32]
+    fs, hs = _fields(sizes, seed0=990)
+    o = mg.make_opts(prec=prec, max_cycles=3, fixed_cycles=True)
+    note("256^3 instance, batch vs solo, %s" % prec)
+    ub, sts = mg.mg_solve_batch([to_dev(f) for f in fs], hs, opts=o)
+    for N, f, h, u, s in zip(sizes, fs, hs, ub, sts):
+        us, ss = mg.mg_solve_level(to_dev(f), h, opts=o)
+        assert np.array_equal(to_host(u), to_host(us)), N
+        _same_stats(s, ss)
+
+
 def test_batch_graph_equals_direct_repeated(mg):
     sizes = [64, 32, 96, 48]
     fs, hs = _fields(sizes, seed0=700)
