@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance leg")
+    ap.add_argument("--no-c1c3", action="store_true", help="skip the 64^3 solve and zoom-hierarchy legs")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests of the serving trace (Poisson, 20/s); 0 skips the serving leg")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed", help="headline path")
@@ -162,6 +163,75 @@ def time_batch(mg, torch, reps):
                 sequential_ms=round(dts * 1e3, 3), speedup=round(dts / dt, 2), bit_identical_to_solo=same)
 
 
+def time_c1(mg, torch, reps=10):
+    """The 64^3 periodic workload: FP64 V(2,2) solve to a 1e-10 relative residual, then psi = -G4 phi;
+    median of `reps` repeats after 2 warm-ups, each from a fresh zero start."""
+    from paper_1103_6031_amd import inputs
+    N = 64
+    h = inputs.BOX / N
+    H = mg.Hier(N, h)
+    ft = torch.from_numpy(inputs.c1_input()).to("cuda:0")
+    o = mg.make_opts(tol=1e-10, prec="fp64", max_cycles=60)
+    ws = mg.Workspace(mg.mg_workspace_bytes(H, o))
+    wl = mg.Workspace(mg.lpt_workspace_bytes(H, 1))
+    u = torch.empty_like(ft)
+    ts, tl = [], []
+    for i in range(reps + 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = mg.mg_solve_level(ft, h, u=u, opts=o, workspace=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mg.lpt_displacements(H, [u], scale=-1.0, workspace=wl)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if i >= 2:
+            ts.append(t1 - t0)
+            tl.append(t2 - t0)
+    ms = 1e3 * sorted(ts)[len(ts) // 2]
+    return dict(workload="periodic 64^3 BBKS, FP64 V(2,2) to rel. residual 1e-10, then psi = -G4 phi",
+                ms_per_solve=round(ms, 3), ms_with_displacements=round(1e3 * sorted(tl)[len(tl) // 2], 3),
+                cycles=st["cycles"], rel_res=st["rel_res"],
+                value=round(st["cell_updates"] / (ms * 1e-3) / 1e6, 1), unit="Mcell-updates/s", repeats=reps)
+
+
+def time_c3(mg, torch, reps=3):
+    """The zoom hierarchy: 128^3 base with three centred 128^3 patches, the 2LPT chain (solve,
+    displacements, tau, solve, displacements) in both precisions."""
+    from paper_1103_6031_amd import inputs
+    patches, fl = inputs.c3_input()
+    H = mg.Hier(128, inputs.BOX / 128, patches)
+    f = [torch.from_numpy(a).to("cuda:0") for a in fl]
+    wl1 = mg.Workspace(mg.lpt_workspace_bytes(H, 1))
+    wl2 = mg.Workspace(mg.lpt_workspace_bytes(H, 2))
+    res = dict(workload="128^3 base + 3 nested 128^3 patches (1024^3 effective), 2LPT, tol 1e-10",
+               cells=int(128 ** 3 * 4))
+    for prec in ("mixed", "fp64"):
+        o = mg.make_opts(tol=1e-10, prec=prec, max_cycles=60)
+        ws = mg.Workspace(mg.mg_workspace_bytes(H, o))
+
+        def step():
+            phi, s1 = mg.mg_solve_hierarchy(H, f, opts=o, workspace=ws)
+            mg.lpt_displacements(H, phi, scale=-1.0, workspace=wl1)
+            tau = mg.lpt2_source(H, phi, workspace=wl2)
+            phi2, s2 = mg.mg_solve_hierarchy(H, tau, opts=o, workspace=ws)
+            mg.lpt_displacements(H, phi2, scale=-3.0 / 7.0, workspace=wl1)
+            return s1, s2
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s1, s2 = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[prec] = dict(ms_per_step=round(dt * 1e3, 3), cycles=[s1["cycles"], s2["cycles"]],
+                         rel_res=[s1["rel_res"], s2["rel_res"]],
+                         value=round((s1["cell_updates"] + s2["cell_updates"]) / dt / 1e6, 1),
+                         unit="Mcell-updates/s")
+    return res
+
+
 def cpu_baseline(f, h):
     """The oracle's FAS V-cycle on the same input: a bounded sample of two cycles."""
     import numpy as np
@@ -246,6 +316,9 @@ def main():
                                  smoother_avg_launch_us=round(side["kernel"]["avg_us"], 2))
     if a.inner:
         line["config"]["inner"] = a.inner
+    if not a.no_c1c3:
+        line["solve_c1"] = time_c1(mg, torch)
+        line["zoom_c3"] = time_c3(mg, torch)
     if not a.no_batch:
         line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
     if serve_host is not None:
