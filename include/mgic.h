@@ -80,7 +80,7 @@ typedef struct {
     int prec;           /* MG_FP64 or MG_MIXED                                                        */
     unsigned flags;     /* MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES                                     */
     int inner;          /* mixed only: FP32 V-cycles per FP64 correction (1..16); 0 = chosen per      */
-                        /* correction from the measured contraction, at most 3                      */
+                        /* correction from the measured contraction, at most 4                      */
 } mg_opts;
 
 typedef struct {
