@@ -257,8 +257,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the multigrid hot path here runs on a single device "
-              "(multi-GPU sharding is described in DESIGN.md but not built); run with --gpus 1",
-              file=sys.stderr)
+              "(sharding across GPUs is not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     serve_host = None
     if a.serve_requests > 0:
