@@ -1,5 +1,5 @@
 // Fused small-level kernels of the FAS V-cycle (Section 3.2) for the periodic coarsenings that
-// are power-of-two cubes of 32^3 and 64^3 cells.
+// are power-of-two cubes of 16^3, 32^3 and 64^3 cells.
 //
 // As one-step kernels each such level costs eleven launches per cycle (FAS right-hand side,
 // 2 nu1 half-sweeps, residual + restriction, prolongation, 2 nu2 half-sweeps), and at these sizes
@@ -570,7 +570,7 @@ void launch_rbgs_vec(T* u, const T* f, const Lay& L, double h, int colour, hipSt
 }
 
 bool level_fusable(int n, int nu1, int nu2) {
-    return (n == 32 || n == 64) && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
+    return (n == 16 || n == 32 || n == 64) && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
 }
 
 template <class T>

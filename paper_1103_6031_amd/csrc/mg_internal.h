@@ -208,7 +208,7 @@ template <class T> void launch_prolong(T* u, Lay L, const T* pu, const T* uold, 
                                        hipStream_t st);
 // V-cycle over all levels of a tail plan in one single-workgroup launch
 template <class T> void launch_tail(const TailPlan<T>& tp, hipStream_t st);
-// fused pre / post legs of a periodic power-of-two coarsening of edge n (32 or 64), one workgroup
+// fused pre / post legs of a periodic power-of-two coarsening of edge n (16, 32 or 64), one workgroup
 // per 8^3 tile (bit-identical to the one-step kernels)
 bool level_fusable(int n, int nu1, int nu2);
 // steps 3-5, 8 (black cells) and 6 on periodic colour-split power-of-two cubes of edge n (the

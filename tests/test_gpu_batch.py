@@ -66,10 +66,11 @@ def test_batch_bit_identical_to_solo(mg, prec, graph):
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 @pytest.mark.parametrize("nu", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1)])
 def test_fused_levels_match_one_step_kernels(mg, prec, nu):
-    """Solo solves run the 64^3 and 32^3 coarsenings as fused tile launches, batched instances
-    run the one-step kernels: the bits must agree for every sweep count the fused kernels take,
-    and for one they do not take (both sides then run the one-step kernels)."""
-    sizes = [64, 128]
+    """Solo solves run the 64^3, 32^3 and 16^3 coarsenings as fused tile launches (and the LDS
+    tail from 8^3), batched instances run the one-step kernels and a tail from 16^3: the bits must
+    agree for every sweep count the fused kernels take, and for one they do not take (both sides
+    then run the one-step kernels)."""
+    sizes = [32, 64, 128]
     fs, hs = _fields(sizes, seed0=950)
     o = mg.make_opts(prec=prec, max_cycles=4, fixed_cycles=True, nu1=nu[0], nu2=nu[1])
     note("fused levels %s nu=%s" % (prec, nu))
