@@ -945,47 +945,53 @@ __device__ __forceinline__ double body_outer_pairs(const double* __restrict__ u_
         if (t >= n) break;
         const SplitNb c = split_nb(L, t);
         const unsigned j = c.j, oth = c.oth, r0 = c.r0, q = (unsigned)c.q;
+        // every load of the pair is issued before the first value is formed (a scheduling barrier
+        // keeps the compiler from interleaving them with the arithmetic: measured, the waits
+        // between groups of loads cost more than the registers the early loads hold)
+        const double2 fv = *(const double2*)(f + t);
         double c0[2] = {0.0, 0.0}, s[2] = {0.0, 0.0};   // a zero start: the stencil sums are +0 exactly
         if constexpr (HU || HE) {
-            // values of v = u (+ e) at positions i, i + 1 of a run (u taken as +0 without HU)
-            auto V2 = [&](unsigned i, double* out) {
-                if constexpr (HU && HE) {
-                    const double2 a = *(const double2*)(u_in + i);
-                    const float2 b = *(const float2*)(e_in + i);
-                    out[0] = a.x + (double)b.x;
-                    out[1] = a.y + (double)b.y;
-                } else if constexpr (HU) {
-                    const double2 a = *(const double2*)(u_in + i);
-                    out[0] = a.x;
-                    out[1] = a.y;
-                } else {
-                    const float2 b = *(const float2*)(e_in + i);
-                    out[0] = 0.0 + (double)b.x;
-                    out[1] = 0.0 + (double)b.y;
-                }
+            // runs at positions i, i + 1: the cell pair itself, the x and y neighbour rows and the
+            // other colour's entries j, j + 1 of this row; then the z-neighbour outside the pair.
+            // Cell j + k sits at z = 2(j + k) + q; its z-neighbours are the other colour's entries
+            // j + k - 1 + q and j + k + q.
+            const unsigned ix[6] = {t, c.rxm + oth + j, c.rxp + oth + j, c.rym + oth + j, c.ryp + oth + j,
+                                    r0 + oth + j};
+            const unsigned jn = q ? j + 2 : j + nzh - 1;
+            const unsigned ie = r0 + oth + (jn >= nzh ? jn - nzh : jn);
+            double2 ua[6];
+            float2 ea[6];
+            double ue = 0.0;
+            float ee = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                if constexpr (HU) ua[k] = *(const double2*)(u_in + ix[k]);
+                if constexpr (HE) ea[k] = *(const float2*)(e_in + ix[k]);
+            }
+            if constexpr (HU) ue = u_in[ie];
+            if constexpr (HE) ee = e_in[ie];
+            __builtin_amdgcn_sched_barrier(0);
+            // v = u (+ e), u taken as +0 without HU (the same bits as u = +0 read)
+            auto V = [&](double a, float b) {
+                if constexpr (HU && HE) return a + (double)b;
+                else if constexpr (HU) return a;
+                else return 0.0 + (double)b;
             };
-            auto V1 = [&](unsigned i) {
-                if constexpr (HU && HE) return u_in[i] + (double)e_in[i];
-                else if constexpr (HU) return u_in[i];
-                else return 0.0 + (double)e_in[i];
-            };
-            double xm[2], xp[2], ym[2], yp[2], cz[2];
-            V2(t, c0);
-            V2(c.rxm + oth + j, xm);
-            V2(c.rxp + oth + j, xp);
-            V2(c.rym + oth + j, ym);
-            V2(c.ryp + oth + j, yp);
-            V2(r0 + oth + j, cz);   // the other colour's entries j, j + 1 of this row
-            // cell j + k sits at z = 2(j + k) + q; its z-neighbours are the other colour's entries
-            // j + k - 1 + q and j + k + q
-            const unsigned je = q ? (j + 2 >= nzh ? j + 2 - nzh : j + 2) : (j == 0 ? nzh - 1 : j - 1);
-            const double edge = V1(r0 + oth + je);
+            double w[6][2];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                w[k][0] = V(HU ? ua[k].x : 0.0, HE ? ea[k].x : 0.0f);
+                w[k][1] = V(HU ? ua[k].y : 0.0, HE ? ea[k].y : 0.0f);
+            }
+            const double edge = V(ue, ee);
+            c0[0] = w[0][0];
+            c0[1] = w[0][1];
+            const double* cz = w[5];
             const double zm0 = q ? cz[0] : edge, zp0 = q ? cz[1] : cz[0];
             const double zm1 = q ? cz[1] : cz[0], zp1 = q ? edge : cz[1];
-            s[0] = ((xm[0] + xp[0]) + (ym[0] + yp[0])) + (zm0 + zp0);
-            s[1] = ((xm[1] + xp[1]) + (ym[1] + yp[1])) + (zm1 + zp1);
+            s[0] = ((w[1][0] + w[2][0]) + (w[3][0] + w[4][0])) + (zm0 + zp0);
+            s[1] = ((w[1][1] + w[2][1]) + (w[3][1] + w[4][1])) + (zm1 + zp1);
         }
-        const double2 fv = *(const double2*)(f + t);
         const double r0v = fv.x - (s[0] - 6.0 * c0[0]) / h2;
         const double r1v = fv.y - (s[1] - 6.0 * c0[1]) / h2;
         acc += r0v * r0v;
