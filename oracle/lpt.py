@@ -18,6 +18,11 @@ Readings:
 * The diagonal terms of the paper's double sum cancel, so
   tau = sum_{i>j} ( D_ii D_jj - D_ij^2 ).  ``tau_paper_form`` evaluates the
   paper's double sum literally; tests check the two agree.
+* LLA baryon density (Section 5.3): rho / rho_bar = 1 / det(I + dL/dq) at the Lagrangian
+  position, with dL_i/dq_j taken by the same fourth-order gradient (the paper does not name the
+  stencil; this is the one the displacements use).  The paper's mass renormalisation
+  "rho -> rho + rho~" is read as shifting every cell by the difference between rho_bar and the
+  measured mean density, i.e. the returned overdensity has zero (composite) mean.
 * Sign and normalisation of the displacements are garbled in the paper (the
   first-order equation carries D_+^{-1}, the second-order one D_+ and
   D_2 ~ +3/7 D_+^2).  The library therefore returns scale * G phi and the
@@ -60,3 +65,31 @@ def tau_paper_form(phi, h):
         for j in range(3):
             s = s + (D[i][j] ** 2 - D[i][i] * D[j][j])
     return -0.5 * s
+
+
+# ----------------------------------------------------------------------------- LLA baryon density
+
+def lla_jacobian(L, h):
+    """J[i][j] = dL_i/dq_j by Table 1's fourth-order gradient (periodic); L is (3, ...)."""
+    return [[grad4(L[i], h, j) for j in range(3)] for i in range(3)]
+
+
+def lla_ratio(J):
+    """rho / rho_bar = 1 / det(delta_ij + J_ij) per cell (Section 5.3, eq. gasdens), with the
+    determinant taken by numpy's LU routine on the stacked 3 x 3 matrices."""
+    M = np.stack([np.stack(row, axis=-1) for row in J], axis=-2)   # (..., 3, 3), M[..., i, j] = J_ij
+    M = M + np.eye(3)
+    return 1.0 / np.linalg.det(M)
+
+
+def lla_density(L, h, renorm=True):
+    """Baryon overdensity rho/rho_bar - 1 of the local Lagrangian approximation (Section 5.3).
+
+    L: displacement field x - q, shape (3, n, n, n), periodic.  With renorm, the measured mean
+    overdensity is subtracted so that mass is conserved (the paper's a-posteriori correction,
+    read as an additive shift of every cell by the deviation of the mean density from rho_bar).
+    """
+    d = lla_ratio(lla_jacobian(L, h)) - 1.0
+    if renorm:
+        d = d - float(np.mean(d))
+    return d

@@ -383,3 +383,29 @@ def tau_hierarchy(H, phi):
             out.append(_tau_padded(wide_ghosted(H, phi, p, 4), H.h[p], 4))
     out, _ = composite_zero_mean(H, out)
     return out
+
+
+def lla_hierarchy(H, L, renorm=True):
+    """LLA baryon overdensity 1 / det(I + dL/dq) - 1 on every level (Section 5.3).
+
+    L[p] is the displacement of level p, shape (3, *n_p).  Each component is restricted bottom-up
+    (covered cells := mean of their children), the patches take width-2 ghosts of it from their
+    parent (as the displacements do), and the Jacobian is the fourth-order gradient.  With renorm,
+    the composite mean of the overdensity (covered cells restricted from the finer level first)
+    is removed from every level.
+    """
+    from .lpt import lla_ratio
+    comps = [[np.array(L[p][c], dtype=np.float64) for p in range(H.P + 1)] for c in range(3)]
+    for c in range(3):
+        restrict_bottom_up(H, comps[c])
+    out = []
+    for p in range(H.P + 1):
+        if p == 0:
+            J = [[grad4(comps[i][0], H.h[0], j) for j in range(3)] for i in range(3)]
+        else:
+            vp = [wide_ghosted(H, comps[i], p, 2) for i in range(3)]
+            J = [[_grad_padded(vp[i], H.h[p], j, 2) for j in range(3)] for i in range(3)]
+        out.append(lla_ratio(J) - 1.0)
+    if renorm:
+        out, _ = composite_zero_mean(H, out)
+    return out
