@@ -195,6 +195,31 @@ def time_c1(mg, torch, reps=10):
                 value=round(st["cell_updates"] / (ms * 1e-3) / 1e6, 1), unit="Mcell-updates/s", repeats=reps)
 
 
+def time_lla(mg, torch, H, psi1, psi2, reps=10):
+    """LLA baryon overdensity (Section 5.3) of the step's first- plus second-order displacements:
+    median of `reps` calls after 2 warm-ups, HIP events on the launch stream.  Model bytes per
+    cell: 6 displacement reads + 1 write (56 B), then the renormalisation's sum (8 B) and
+    subtraction (16 B)."""
+    ws = mg.Workspace(mg.lpt_workspace_bytes(H, 3))
+    delta = torch.empty_like(psi1[0])
+    ts = []
+    for i in range(reps + 2):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mg.lpt_lla_density(H, [psi1], [psi2], delta=[delta], workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        if i >= 2:
+            ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    cells = psi1[0].numel()
+    return dict(workload="LLA baryon overdensity 1/det(I + dL/dq) - 1 of psi1 + psi2, %d^3, renormalised"
+                % round(cells ** (1 / 3)), ms_per_call=round(ms, 3), value=round(cells / (ms * 1e-3) / 1e6, 1),
+                unit="Mcells/s", model_bytes_per_cell=80, model_gbs=round(80 * cells / (ms * 1e-3) / 1e9, 1),
+                delta_min=float(delta.min()), delta_max=float(delta.max()), repeats=reps)
+
+
 def time_c3(mg, torch, reps=3):
     """The zoom hierarchy: 128^3 base with three centred 128^3 patches, the 2LPT chain (solve,
     displacements, tau, solve, displacements) in both precisions."""
@@ -315,6 +340,7 @@ def main():
                                  smoother_avg_launch_us=round(side["kernel"]["avg_us"], 2))
     if a.inner:
         line["config"]["inner"] = a.inner
+    line["lla"] = time_lla(mg, torch, H, out_h[1], out_h[4])
     if not a.no_c1c3:
         line["solve_c1"] = time_c1(mg, torch)
         line["zoom_c3"] = time_c3(mg, torch)

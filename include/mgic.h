@@ -126,8 +126,8 @@ int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* c
  * LPT (Section 3.1)
  * -------------------------------------------------------------------------------------------- */
 
-/* Workspace bytes for lpt_displacements (what = 1) or lpt2_source (what = 2).  The LPT calls
- * below need a base of at least 2^3 cells (MG_EINVAL otherwise). */
+/* Workspace bytes for lpt_displacements (what = 1), lpt2_source (what = 2) or lpt_lla_density
+ * (what = 3).  The LPT calls below need a base of at least 2^3 cells (MG_EINVAL otherwise). */
 size_t lpt_workspace_bytes(const mg_hier* hier, int what);
 
 /* psi_c = scale * G4_c phi on every level (Table 1 fourth-order gradient).  out[3*p + c] is the
@@ -152,6 +152,22 @@ int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* ta
 int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, double* const* out,
                                  double scale, double* const* tau, void* workspace,
                                  size_t workspace_bytes, void* stream);
+
+/* Baryon density of the local Lagrangian approximation (Section 5.3, eq. gasdens):
+ *   delta[p] = rho / rho_bar - 1 = 1 / det(I + dL/dq) - 1,  (dL/dq)_ij = G4_j L_i,
+ * at the Lagrangian cell centres of every level, for the displacement L = disp (+ disp2 when
+ * disp2 is not NULL; e.g. the first- and second-order displacements of a 2LPT set).
+ * disp[3*p + c] (and disp2[3*p + c]) is the c-th component on level p, natural [x][y][z] order,
+ * as lpt_displacements writes it; delta[p] is one array per level.  Inputs are read only.
+ * On patches each component takes width-2 ghosts from its parent as in lpt_displacements (covered
+ * parent cells as the mean of their children).  Then covered coarse cells of delta are replaced
+ * by the mean of their children and the composite mean is subtracted from every level: the
+ * paper's renormalisation that restores the mean density (mass conservation).  Cells past shell
+ * crossing (det <= 0) are not detected: they give delta <= -1 or an infinity.
+ * Workspace: lpt_workspace_bytes(hier, 3) (a few scalars for a single level; three copies of the
+ * displacement and three padded patches for a hierarchy).  Asynchronous. */
+int lpt_lla_density(const mg_hier* hier, const double* const* disp, const double* const* disp2,
+                    double* const* delta, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------------
  * Batched independent periodic solves (many small instances in one persistent launch)

@@ -109,6 +109,51 @@ __global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h
     tau[t] = post == 1.0 ? acc : acc * post;
 }
 
+// LLA baryon density (Section 5.3, eq. gasdens): rho / rho_bar - 1 = 1 / det(I + J) - 1 with
+// J_ij = G4_j L_i, where the displacement L is a (+ b when `sum`, formed per load, the same
+// add a separate pass would make).  The determinant is expanded along the first row of M = I + J.
+template <bool PAD>
+__device__ __forceinline__ double g4_of(const Src<PAD>& a, const Src<PAD>& b, int sum, int x, int y, int z,
+                                        int axis, double den) {
+    const int ex = axis == 0, ey = axis == 1, ez = axis == 2;
+    auto v = [&](int k) {
+        const int X = x + k * ex, Y = y + k * ey, Z = z + k * ez;
+        return sum ? a.at(X, Y, Z) + b.at(X, Y, Z) : a.at(X, Y, Z);
+    };
+    double acc = v(-2);
+    acc = acc + (-8.0) * v(-1);
+    acc = acc + 8.0 * v(1);
+    acc = acc + (-1.0) * v(2);
+    return acc / den;
+}
+
+template <bool PAD>
+__global__ void k_lla(Src<PAD> a0, Src<PAD> a1, Src<PAD> a2, Src<PAD> b0, Src<PAD> b1, Src<PAD> b2, int sum,
+                      Lay B, double h, double* __restrict__ out) {
+    const unsigned t = (unsigned)lpt_block() * blockDim.x + threadIdx.x;
+    if (t >= (unsigned)B.d.cells()) return;
+    int x, y, z;
+    decode3(B, t, x, y, z);
+    const double den = 12.0 * h;
+    const Src<PAD>* A[3] = {&a0, &a1, &a2};
+    const Src<PAD>* Bs[3] = {&b0, &b1, &b2};
+    double m[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) m[i][j] = (i == j ? 1.0 : 0.0) + g4_of(*A[i], *Bs[i], sum, x, y, z, j, den);
+    const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+    const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
+    const double c2 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+    const double det = (m[0][0] * c0 - m[0][1] * c1) + m[0][2] * c2;
+    out[t] = 1.0 / det - 1.0;
+}
+
+__global__ void k_add2(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ dst, size_t n) {
+    for (size_t i = (size_t)lpt_block() * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = a[i] + b[i];
+}
+
 // ----------------------------------------------------------------------------------------------
 // Periodic natural-order arrays, by groups of rows: one workgroup per (x, 8 consecutive y), each
 // thread one z walking the 8 rows with the y-stencil values in a register window.  The blocks of
@@ -288,6 +333,27 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
 void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
                          double* tau, hipStream_t st) {
     k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(g0, g1, g2, d, h, post, tau);
+}
+
+
+void launch_lla(const double* const* a, const double* const* b, int R, Dims d, double h, double* out, hipStream_t st) {
+    const Lay B(d, 0);
+    const int sum = b != nullptr;
+    const double* const* bb = sum ? b : a;
+    if (R == 0)
+        k_lla<false><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{a[0], 0, d}, Src<false>{a[1], 0, d},
+                                                            Src<false>{a[2], 0, d}, Src<false>{bb[0], 0, d},
+                                                            Src<false>{bb[1], 0, d}, Src<false>{bb[2], 0, d}, sum, B,
+                                                            h, out);
+    else
+        k_lla<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{a[0], R, d}, Src<true>{a[1], R, d},
+                                                           Src<true>{a[2], R, d}, Src<true>{bb[0], R, d},
+                                                           Src<true>{bb[1], R, d}, Src<true>{bb[2], R, d}, sum, B, h,
+                                                           out);
+}
+
+void launch_add2(const double* a, const double* b, double* dst, size_t n, hipStream_t st) {
+    k_add2<<<grid_for(n), kBlock, 0, st>>>(a, b, dst, n);
 }
 
 }  // namespace mgic

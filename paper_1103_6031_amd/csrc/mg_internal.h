@@ -283,6 +283,11 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
 // (post = 1 / s^2)
 void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
                           double* tau, hipStream_t st);
+// LLA overdensity 1 / det(I + G4 L) - 1 with L = a (+ b when b is given), three components each,
+// periodic (R = 0) or padded by R >= 2
+void launch_lla(const double* const* a, const double* const* b, int R, Dims d, double h, double* out, hipStream_t st);
+// dst = a + b elementwise
+void launch_add2(const double* a, const double* b, double* dst, size_t n, hipStream_t st);
 
 // ----------------------------------------------------------------------------------------------
 // batched launches: many independent periodic instances in one grid

@@ -689,26 +689,30 @@ static mg_hier single_level(int n, double h) {
 // ----------------------------------------------------------------------------------------------
 struct LptPlan {
     std::vector<double*> phi;  // restricted copies (P > 0) or the user's arrays
-    double* padded = nullptr;
+    double* padded = nullptr;  // one padded level (three, 'padstride' apart, for the LLA density)
+    size_t padstride = 0;
     double* psi = nullptr;     // tau scratch: 3 gradient fields
     double* partials = nullptr;
     double* scal = nullptr;
 };
 
+// what: 1 displacements, 2 tau (and displacements), 3 LLA density (three displacement components
+// per level are copied and padded instead of one potential)
 static size_t lpt_carve(const mg_hier* H, int what, Carver& cv, LptPlan& lp) {
-    const int R = what == 2 ? 4 : 2;
+    const int R = what == 2 ? 4 : 2, nc = what == 3 ? 3 : 1;
     size_t maxpad = 0;
-    lp.phi.assign(H->nlev, nullptr);
+    lp.phi.assign((size_t)nc * H->nlev, nullptr);
     if (H->nlev > 1)
         for (int p = 0; p < H->nlev; ++p) {
             const mg_level& l = H->lev[p];
-            lp.phi[p] = cv.take<double>((size_t)l.n[0] * l.n[1] * l.n[2]);
+            for (int c = 0; c < nc; ++c) lp.phi[(size_t)c * H->nlev + p] = cv.take<double>((size_t)l.n[0] * l.n[1] * l.n[2]);
             if (p > 0) {
                 size_t s = (size_t)(l.n[0] + 2 * R) * (l.n[1] + 2 * R) * (l.n[2] + 2 * R);
                 if (s > maxpad) maxpad = s;
             }
         }
-    if (maxpad) lp.padded = cv.take<double>(maxpad);
+    if (maxpad) lp.padded = cv.take<double>(nc * maxpad);
+    lp.padstride = maxpad;
     if (what == 2) {
         size_t m = (size_t)H->lev[0].n[0] * H->lev[0].n[1] * H->lev[0].n[2];
         for (int p = 1; p < H->nlev; ++p) {
@@ -1604,7 +1608,7 @@ int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* c
 }
 
 size_t lpt_workspace_bytes(const mg_hier* hier, int what) {
-    if (validate_hier(hier) || (what != 1 && what != 2)) return 0;
+    if (validate_hier(hier) || what < 1 || what > 3) return 0;
     Carver cv(nullptr);
     LptPlan lp;
     return lpt_carve(hier, what, cv, lp);
@@ -1700,6 +1704,74 @@ int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, 
         }
     }
     return tau_levels(hier, lp, tau, out, 1.0 / (scale * scale), st);
+}
+
+int lpt_lla_density(const mg_hier* hier, const double* const* disp, const double* const* disp2,
+                    double* const* delta, void* workspace, size_t workspace_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    int rc = validate_hier(hier);
+    if (rc) return rc;
+    if (hier->lev[0].n[0] < 2) return fail(MG_EINVAL, "LPT needs a base of at least 2^3 cells");
+    if (!disp || !delta) return fail(MG_EINVAL, "disp or delta is NULL");
+    const int nl = hier->nlev;
+    for (int k = 0; k < 3 * nl; ++k)
+        if (!disp[k] || (disp2 && !disp2[k])) return fail(MG_EINVAL, "displacement pointer is NULL");
+    for (int p = 0; p < nl; ++p)
+        if (!delta[p]) return fail(MG_EINVAL, "delta level pointer is NULL");
+    Carver sz(nullptr);
+    LptPlan lp;
+    const size_t need = lpt_carve(hier, 3, sz, lp);
+    if (!workspace || workspace_bytes < need) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(need));
+    if (((uintptr_t)workspace) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    Carver cv(workspace);
+    lpt_carve(hier, 3, cv, lp);
+    (void)hipGetLastError();
+    if (nl == 1) {
+        const double* a[3] = {disp[0], disp[1], disp[2]};
+        const double* b[3] = {disp2 ? disp2[0] : nullptr, disp2 ? disp2[1] : nullptr, disp2 ? disp2[2] : nullptr};
+        launch_lla(a, disp2 ? b : nullptr, 0, dims_of(hier, 0), h_of(hier, 0), delta[0], st);
+    } else {
+        // working copies of L (= disp + disp2), covered cells restricted from the finer level
+        auto comp = [&](int c, int p) { return lp.phi[(size_t)c * nl + p]; };
+        for (int p = 0; p < nl; ++p)
+            for (int c = 0; c < 3; ++c) {
+                const size_t n = dims_of(hier, p).cells();
+                if (disp2) launch_add2(disp[3 * p + c], disp2[3 * p + c], comp(c, p), n, st);
+                else MG_HIP(hipMemcpyAsync(comp(c, p), disp[3 * p + c], n * sizeof(double), hipMemcpyDeviceToDevice, st));
+            }
+        for (int p = nl - 1; p >= 1; --p)
+            for (int c = 0; c < 3; ++c)
+                launch_restrict_cov<double>(comp(c, p), mklay(dims_of(hier, p), 0), comp(c, p - 1), parent_of(hier, p), st);
+        for (int p = 0; p < nl; ++p) {
+            const Dims d = dims_of(hier, p);
+            if (p == 0) {
+                const double* a[3] = {comp(0, 0), comp(1, 0), comp(2, 0)};
+                launch_lla(a, nullptr, 0, d, h_of(hier, 0), delta[0], st);
+            } else {
+                const double* a[3];
+                for (int c = 0; c < 3; ++c) {
+                    double* pad = lp.padded + (size_t)c * lp.padstride;
+                    launch_wide_ghost(comp(c, p - 1), comp(c, p), pad, d, parent_of(hier, p), 2, st);
+                    a[c] = pad;
+                }
+                launch_lla(a, nullptr, 2, d, h_of(hier, p), delta[p], st);
+            }
+        }
+    }
+    // renormalisation: covered cells := mean of their children, then the base mean (the composite
+    // volume mean) is subtracted everywhere
+    for (int p = nl - 1; p >= 1; --p)
+        launch_restrict_cov<double>(delta[p], mklay(dims_of(hier, p), 0), delta[p - 1], parent_of(hier, p), st);
+    int np = 0;
+    CovBox none{};
+    launch_sum(delta[0], mklay(dims_of(hier, 0), 0), none, 0, lp.partials, &np, st);
+    SegList s{};
+    s.n = 1; s.off[0] = 0; s.cnt[0] = np; s.w[0] = 1.0;
+    launch_finalize(lp.partials, s, lp.scal, st);
+    const double inv = 1.0 / (double)dims_of(hier, 0).cells();
+    for (int p = 0; p < nl; ++p) launch_sub_mean<double>(delta[p], dims_of(hier, p).cells(), lp.scal, inv, st);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
 }
 
 size_t mg_batch_workspace_bytes(int ninst, const int* n, const mg_opts* opts) {

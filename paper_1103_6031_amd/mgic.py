@@ -72,6 +72,7 @@ _sig = {
     "lpt2_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _P, _sz, _P]),
     "lpt_displacements_and_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_double, _PP, _P,
                                                     _sz, _P]),
+    "lpt_lla_density": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _PP, _P, _sz, _P]),
     "mg_batch_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mg_opts)]),
     "mg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                       _PP, _PP, ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
@@ -304,6 +305,20 @@ def lpt_displacements_and_source(hier: Hier, phi, scale=1.0, out=None, tau=None,
     _check(_lib.lpt_displacements_and_source(ctypes.byref(H), pp, op, float(scale), tp, ctypes.c_void_p(ws.ptr),
                                              ws.nbytes, _stream(stream)))
     return out, tau
+
+
+def lpt_lla_density(hier: Hier, disp, disp2=None, delta=None, workspace=None, stream=None):
+    """LLA baryon overdensity 1 / det(I + G4 L) - 1 per level, L = disp (+ disp2), renormalised to
+    zero composite mean.  disp / disp2: lists of [L_x, L_y, L_z] per level.  Returns delta per level."""
+    if delta is None:
+        delta = [torch.empty_like(lvl[0]) for lvl in disp]
+    H = hier.c_struct()
+    ws = _ws(workspace, lpt_workspace_bytes(hier, 3))
+    ap, _aa = _ptr_array([_dev(c, "disp") for lvl in disp for c in lvl])
+    bp, _ba = (None, None) if disp2 is None else _ptr_array([_dev(c, "disp2") for lvl in disp2 for c in lvl])
+    dp, _da = _ptr_array([_dev(x, "delta") for x in delta])
+    _check(_lib.lpt_lla_density(ctypes.byref(H), ap, bp, dp, ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+    return delta
 
 
 def mg_batch_workspace_bytes(sizes, opts=None) -> int:

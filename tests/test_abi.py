@@ -94,3 +94,25 @@ def test_lpt_rejects_a_single_cell_base_before_any_device_work():
     rc = mgic._lib.lpt_displacements(ctypes.byref(H), ptrs, ptrs, -1.0, ctypes.c_void_p(256), 1 << 20, None)
     assert rc == mgic.MG_EINVAL
     assert b"2^3" in mgic._lib.mg_last_error()
+
+
+def test_lla_validates_its_arguments_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    H = mgic.Hier(8, 1.0)
+    assert mgic.lpt_workspace_bytes(H, 3) > 0
+    ok = mgic.Hier(32, 1.0, [((16, 16, 16), (8, 8, 8))])
+    # a hierarchy copies three components per level and pads three patches
+    assert mgic.lpt_workspace_bytes(ok, 3) > 3 * (32 ** 3 + 16 ** 3) * 8
+    Hc = H.c_struct()
+    good = (ctypes.c_void_p * 3)(16, 16, 16)
+    hole = (ctypes.c_void_p * 3)(16, 0, 16)
+    one = (ctypes.c_void_p * 1)(16)
+    lib = mgic._lib
+    assert lib.lpt_lla_density(ctypes.byref(Hc), None, None, one, ctypes.c_void_p(256), 1 << 20, None) == mgic.MG_EINVAL
+    assert lib.lpt_lla_density(ctypes.byref(Hc), hole, None, one, ctypes.c_void_p(256), 1 << 20, None) == mgic.MG_EINVAL
+    assert lib.lpt_lla_density(ctypes.byref(Hc), good, hole, one, ctypes.c_void_p(256), 1 << 20, None) == mgic.MG_EINVAL
+    assert lib.lpt_lla_density(ctypes.byref(Hc), good, None, None, ctypes.c_void_p(256), 1 << 20, None) == mgic.MG_EINVAL
+    rc = lib.lpt_lla_density(ctypes.byref(Hc), good, None, one, None, 0, None)
+    assert rc == mgic.MG_EINVAL and b"workspace" in lib.mg_last_error()
+    H1 = mgic.Hier(1, 1.0).c_struct()
+    assert lib.lpt_lla_density(ctypes.byref(H1), good, None, one, ctypes.c_void_p(256), 1 << 20, None) == mgic.MG_EINVAL

@@ -1,0 +1,95 @@
+"""LLA baryon density (Section 5.3) on the GPU against the oracle.
+
+The oracle takes the determinant with numpy's LU routine, the kernel by cofactors along the first
+row, both in FP64 on the same Jacobian (the gradients have the same operations in the same
+order).  With |dL/dq| ~ 0.1 the determinant's rounding is a few 1e-16, so 1e-12 of the largest
+overdensity leaves a wide margin while any wrong term (a dropped cofactor, a sign, a
+transposed stencil axis) moves the result by O(0.01).
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import needs_gpu, note, to_dev, to_host, rel_max
+from oracle import lpt, zoom
+from paper_1103_6031_amd import inputs
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_1103_6031_amd import mgic
+    return mgic
+
+
+def _disp(shape, h, seed):
+    """Three displacement components of a smooth random field, |dL/dq| of a few 0.01."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(3):
+        w = rng.standard_normal(shape)
+        for a in range(3):   # a few passes of a [1 2 1] / 4 filter along each axis (not on 2 cells,
+            for _ in range(2 if shape[a] >= 4 else 0):   # which it would make constant)
+                w = 0.25 * np.roll(w, 1, a) + 0.5 * w + 0.25 * np.roll(w, -1, a)
+        out.append(0.03 * h * w / np.std(w))
+    return np.stack(out)
+
+
+# 2: the smallest base (the stencil wraps more than once); 20 and 48: not powers of two
+@pytest.mark.parametrize("N", [2, 8, 20, 48])
+@pytest.mark.parametrize("two", [False, True])
+def test_periodic_lla_matches_oracle(mg, N, two):
+    h = 100.0 / N
+    a = _disp((N, N, N), h, 10 + N)
+    b = _disp((N, N, N), h, 20 + N) if two else None
+    note("LLA periodic N=%d two=%s" % (N, two))
+    Hg = mg.Hier(N, h)
+    d = mg.lpt_lla_density(Hg, [[to_dev(c) for c in a]], None if b is None else [[to_dev(c) for c in b]])[0]
+    want = lpt.lla_density(a if b is None else a + b, h)
+    assert np.all(np.isfinite(want)) and np.min(want) > -1.0
+    assert rel_max(to_host(d), want) <= 1e-12
+    assert abs(float(np.mean(to_host(d)))) <= 1e-15 * np.max(np.abs(want)) * N ** 1.5
+
+
+@pytest.mark.parametrize("layout", [
+    (16, [((12, 12, 12), (2, 3, 2))]),
+    (16, [((16, 16, 16), (4, 4, 4)), ((12, 8, 16), (4, 6, 4))]),
+])
+@pytest.mark.parametrize("two", [False, True])
+def test_hierarchy_lla_matches_oracle(mg, layout, two):
+    N0, patches = layout
+    H = zoom.Hierarchy(N0, 100.0 / N0, patches)
+    Hg = mg.Hier(N0, 100.0 / N0, patches)
+    a = [_disp(n, H.h[p], 30 + p) for p, n in enumerate(H.n)]
+    b = [_disp(n, H.h[p], 40 + p) for p, n in enumerate(H.n)] if two else None
+    note("LLA hierarchy N0=%d P=%d two=%s" % (N0, H.P, two))
+    d = mg.lpt_lla_density(Hg, [[to_dev(c) for c in lvl] for lvl in a],
+                           None if b is None else [[to_dev(c) for c in lvl] for lvl in b])
+    want = zoom.lla_hierarchy(H, a if b is None else [x + y for x, y in zip(a, b)])
+    for p in range(H.P + 1):
+        assert rel_max(to_host(d[p]), want[p]) <= 1e-12, p
+    got = [to_host(x) for x in d]
+    assert abs(zoom.composite_sum(H, got)) <= 1e-13 * zoom.composite_sum(H, [np.abs(x) for x in want])
+
+
+def test_full_size_256_two_sets_matches_oracle(mg):
+    """The benchmark's configuration: one 256^3 periodic level, first- plus second-order sets."""
+    N = 256
+    h = inputs.BOX / N
+    a = _disp((N, N, N), h, 1103)
+    b = 0.1 * _disp((N, N, N), h, 1104)
+    note("LLA 256^3, two sets")
+    Hg = mg.Hier(N, h)
+    d = to_host(mg.lpt_lla_density(Hg, [[to_dev(c) for c in a]], [[to_dev(c) for c in b]])[0])
+    want = lpt.lla_density(a + b, h)
+    assert rel_max(d, want) <= 1e-12
+
+
+def test_lla_rejects_null_arguments(mg):
+    import ctypes
+    H = mg.Hier(8, 1.0).c_struct()
+    ptrs = (ctypes.c_void_p * 3)(16, 16, 0)
+    ws = mg.Workspace(mg.lpt_workspace_bytes(mg.Hier(8, 1.0), 3))
+    rc = mg._lib.lpt_lla_density(ctypes.byref(H), ptrs, None, ptrs, ctypes.c_void_p(ws.ptr), ws.nbytes, None)
+    assert rc == mg.MG_EINVAL
