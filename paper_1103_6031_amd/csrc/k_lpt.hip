@@ -253,6 +253,139 @@ __global__ void __launch_bounds__(256) k_tau_rows(const double* __restrict__ q0,
     }
 }
 
+// LLA overdensity on a periodic level by groups of rows (the layout of k_grad4_rows): each thread
+// takes one z and walks the group's 8 rows; every stencil value is a load at a row base plus z,
+// so the per-load index work of the generic kernel (decode, three wraps) is gone.  The same
+// operations in the same order as k_lla.
+template <bool SUM>
+__global__ void __launch_bounds__(256) k_lla_rows(const double* __restrict__ a0, const double* __restrict__ a1,
+                                                  const double* __restrict__ a2, const double* __restrict__ b0,
+                                                  const double* __restrict__ b1, const double* __restrict__ b2,
+                                                  Dims d, double h, double* __restrict__ out) {
+    const RowGroup g = row_group(d);
+    const double den = 12.0 * h;
+    const unsigned nz = (unsigned)d.z;
+    const double* A[3] = {a0, a1, a2};
+    const double* Bv[3] = {b0, b1, b2};
+    for (int z = threadIdx.x; z < d.z; z += blockDim.x) {
+        const unsigned zo[4] = {wrap1(z - 2, d.z), wrap1(z - 1, d.z), wrap1(z + 1, d.z), wrap1(z + 2, d.z)};
+        for (int k = 0; k < kRowsY; ++k) {
+            if (g.y0 + k >= (unsigned)d.y) break;
+            const unsigned y = g.rowy[k + 2];
+            const unsigned rc = (g.pl[2] + y) * nz;
+            // the four stencil positions along x (planes x-2, x-1, x+1, x+2), y and z
+            const unsigned ix[4] = {(g.pl[0] + y) * nz + z, (g.pl[1] + y) * nz + z, (g.pl[3] + y) * nz + z,
+                                    (g.pl[4] + y) * nz + z};
+            const unsigned iy[4] = {(g.pl[2] + g.rowy[k]) * nz + z, (g.pl[2] + g.rowy[k + 1]) * nz + z,
+                                    (g.pl[2] + g.rowy[k + 3]) * nz + z, (g.pl[2] + g.rowy[k + 4]) * nz + z};
+            const unsigned iz[4] = {rc + zo[0], rc + zo[1], rc + zo[2], rc + zo[3]};
+            double m[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double* ai = A[i];
+                const double* bi = Bv[i];
+                auto v = [&](unsigned q) {
+                    if constexpr (SUM) return ai[q] + bi[q];
+                    else return ai[q];
+                };
+                m[i][0] = 1.0 * (i == 0) + g4v(v(ix[0]), v(ix[1]), v(ix[2]), v(ix[3]), den);
+                m[i][1] = 1.0 * (i == 1) + g4v(v(iy[0]), v(iy[1]), v(iy[2]), v(iy[3]), den);
+                m[i][2] = 1.0 * (i == 2) + g4v(v(iz[0]), v(iz[1]), v(iz[2]), v(iz[3]), den);
+            }
+            const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+            const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
+            const double c2 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+            const double det = (m[0][0] * c0 - m[0][1] * c1) + m[0][2] * c2;
+            out[rc + z] = 1.0 / det - 1.0;
+        }
+    }
+}
+
+// The same on large periodic levels by tiles marched along x: a block owns 8 rows x 64 z of
+// 32 consecutive planes; each thread two cells (rows ty and ty + 4).  The x-stencil values of a
+// thread's cells move through a register window of 5 planes (one new load per plane), and the
+// y / z stencil values come from the plane's slab in LDS (the tile plus 2 cells each side in y
+// and z, loaded once per plane).  The same operations in the same order as k_lla_rows.
+constexpr int kLtY = 8, kLtZ = 64, kLtX = 32;
+
+template <bool SUM>
+__global__ void __launch_bounds__(256) k_lla_tile(const double* __restrict__ a0, const double* __restrict__ a1,
+                                                  const double* __restrict__ a2, const double* __restrict__ b0,
+                                                  const double* __restrict__ b1, const double* __restrict__ b2,
+                                                  Dims d, double h, double* __restrict__ out) {
+    constexpr int SY = kLtY + 4, SZ = kLtZ + 4;
+    __shared__ double sl[3][SY][SZ];
+    const double* A[3] = {a0, a1, a2};
+    const double* Bv[3] = {b0, b1, b2};
+    const unsigned ny = (unsigned)d.y, nz = (unsigned)d.z;
+    const unsigned nty = ny / kLtY, ntz = nz / kLtZ;
+    unsigned b = blockIdx.x;
+    const unsigned zt = b % ntz;
+    b /= ntz;
+    const unsigned yt = b % nty;
+    const unsigned x0 = (b / nty) * kLtX;
+    const int tz = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);   // rows ty and ty + 4
+    const unsigned z = zt * kLtZ + tz, ya = yt * kLtY + ty, yb = ya + 4;
+    auto val = [&](int c, unsigned q) {
+        if constexpr (SUM) return A[c][q] + Bv[c][q];
+        else return A[c][q];
+    };
+    const double den = 12.0 * h;
+    double wa[3][5], wb[3][5];   // x-window of the two cells: planes x - 2 .. x + 2
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned xp = wrap1((int)x0 - 2 + k, d.x);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            wa[c][k + 1] = val(c, (xp * ny + ya) * nz + z);
+            wb[c][k + 1] = val(c, (xp * ny + yb) * nz + z);
+        }
+    }
+    for (int i = 0; i < kLtX; ++i) {
+        const unsigned x = x0 + i, xn = wrap1((int)x + 2, d.x);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                wa[c][k] = wa[c][k + 1];
+                wb[c][k] = wb[c][k + 1];
+            }
+            wa[c][4] = val(c, (xn * ny + ya) * nz + z);
+            wb[c][4] = val(c, (xn * ny + yb) * nz + z);
+        }
+        __syncthreads();   // the previous plane's slab has been read
+        for (int t = (int)threadIdx.x; t < SY * SZ; t += 256) {
+            const int sy = t / SZ, sz = t - sy * SZ;
+            const unsigned yy = wrap1((int)(yt * kLtY) + sy - 2, d.y), zz = wrap1((int)(zt * kLtZ) + sz - 2, d.z);
+            const unsigned q = (x * ny + yy) * nz + zz;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sl[c][sy][sz] = val(c, q);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int sy = ty + 4 * r + 2, sz = tz + 2;
+            double m[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double* w = r ? wb[c] : wa[c];
+                m[c][0] = 1.0 * (c == 0) + g4v(w[0], w[1], w[3], w[4], den);
+                m[c][1] = 1.0 * (c == 1) + g4v(sl[c][sy - 2][sz], sl[c][sy - 1][sz], sl[c][sy + 1][sz], sl[c][sy + 2][sz], den);
+                m[c][2] = 1.0 * (c == 2) + g4v(sl[c][sy][sz - 2], sl[c][sy][sz - 1], sl[c][sy][sz + 1], sl[c][sy][sz + 2], den);
+            }
+            const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+            const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
+            const double c2 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+            const double det = (m[0][0] * c0 - m[0][1] * c1) + m[0][2] * c2;
+            out[(x * ny + (r ? yb : ya)) * nz + z] = 1.0 / det - 1.0;
+        }
+    }
+}
+
+static bool lla_tiled(Dims d) {
+    return d.x % kLtX == 0 && d.y % kLtY == 0 && d.z % kLtZ == 0 && d.cells() >= ((size_t)1 << 21);
+}
+
 static unsigned rows_grid(Dims d) { return (unsigned)d.x * (unsigned)((d.y + kRowsY - 1) / kRowsY); }
 static unsigned rows_block(Dims d) { return d.z >= 256 ? 256u : (unsigned)((d.z + 63) / 64 * 64); }
 
@@ -340,11 +473,17 @@ void launch_lla(const double* const* a, const double* const* b, int R, Dims d, d
     const Lay B(d, 0);
     const int sum = b != nullptr;
     const double* const* bb = sum ? b : a;
-    if (R == 0)
-        k_lla<false><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{a[0], 0, d}, Src<false>{a[1], 0, d},
-                                                            Src<false>{a[2], 0, d}, Src<false>{bb[0], 0, d},
-                                                            Src<false>{bb[1], 0, d}, Src<false>{bb[2], 0, d}, sum, B,
-                                                            h, out);
+    // periodic levels (every base here has at least 2 cells per axis, so a single wrap of an
+    // offset of 2 holds) by x-marched tiles where they divide the level, else by groups of rows;
+    // padded patches by the per-cell kernel
+    if (R == 0 && lla_tiled(d)) {
+        const unsigned grid = (unsigned)(d.x / kLtX) * (unsigned)(d.y / kLtY) * (unsigned)(d.z / kLtZ);
+        if (sum) k_lla_tile<true><<<grid, 256, 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
+        else k_lla_tile<false><<<grid, 256, 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
+    } else if (R == 0 && sum)
+        k_lla_rows<true><<<rows_grid(d), rows_block(d), 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
+    else if (R == 0)
+        k_lla_rows<false><<<rows_grid(d), rows_block(d), 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
     else
         k_lla<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{a[0], R, d}, Src<true>{a[1], R, d},
                                                            Src<true>{a[2], R, d}, Src<true>{bb[0], R, d},

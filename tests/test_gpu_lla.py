@@ -36,8 +36,9 @@ def _disp(shape, h, seed):
     return np.stack(out)
 
 
-# 2: the smallest base (the stencil wraps more than once); 20 and 48: not powers of two
-@pytest.mark.parametrize("N", [2, 8, 20, 48])
+# 2: the smallest base (the stencil wraps more than once); 20 and 48: not powers of two (groups of
+# rows); 128: the x-marched tiles (as at 256^3)
+@pytest.mark.parametrize("N", [2, 8, 20, 48, 128])
 @pytest.mark.parametrize("two", [False, True])
 def test_periodic_lla_matches_oracle(mg, N, two):
     h = 100.0 / N
