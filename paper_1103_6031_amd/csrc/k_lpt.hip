@@ -319,7 +319,10 @@ __global__ void __launch_bounds__(256) k_lla_tile(const double* __restrict__ a0,
     const double* Bv[3] = {b0, b1, b2};
     const unsigned ny = (unsigned)d.y, nz = (unsigned)d.z;
     const unsigned nty = ny / kLtY, ntz = nz / kLtZ;
+    // consecutive blocks go to the 8 XCDs in turn: renumber so that each XCD takes a contiguous
+    // run of tiles, whose halo rows and columns are then its own neighbours' cells (in its L2)
     unsigned b = blockIdx.x;
+    if (gridDim.x % 8 == 0) b = (b % 8) * (gridDim.x / 8) + b / 8;
     const unsigned zt = b % ntz;
     b /= ntz;
     const unsigned yt = b % nty;
