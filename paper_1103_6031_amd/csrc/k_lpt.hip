@@ -114,7 +114,7 @@ __global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h
 // add a separate pass would make).  The determinant is expanded along the first row of M = I + J.
 template <bool PAD>
 __device__ __forceinline__ double g4_of(const Src<PAD>& a, const Src<PAD>& b, int sum, int x, int y, int z,
-                                        int axis, double den) {
+                                        int axis, double inv) {
     const int ex = axis == 0, ey = axis == 1, ez = axis == 2;
     auto v = [&](int k) {
         const int X = x + k * ex, Y = y + k * ey, Z = z + k * ez;
@@ -124,7 +124,7 @@ __device__ __forceinline__ double g4_of(const Src<PAD>& a, const Src<PAD>& b, in
     acc = acc + (-8.0) * v(-1);
     acc = acc + 8.0 * v(1);
     acc = acc + (-1.0) * v(2);
-    return acc / den;
+    return acc * inv;
 }
 
 template <bool PAD>
@@ -134,14 +134,14 @@ __global__ void k_lla(Src<PAD> a0, Src<PAD> a1, Src<PAD> a2, Src<PAD> b0, Src<PA
     if (t >= (unsigned)B.d.cells()) return;
     int x, y, z;
     decode3(B, t, x, y, z);
-    const double den = 12.0 * h;
+    const double inv = 1.0 / (12.0 * h);
     const Src<PAD>* A[3] = {&a0, &a1, &a2};
     const Src<PAD>* Bs[3] = {&b0, &b1, &b2};
     double m[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) m[i][j] = (i == j ? 1.0 : 0.0) + g4_of(*A[i], *Bs[i], sum, x, y, z, j, den);
+        for (int j = 0; j < 3; ++j) m[i][j] = (i == j ? 1.0 : 0.0) + g4_of(*A[i], *Bs[i], sum, x, y, z, j, inv);
     const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
     const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
     const double c2 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
@@ -171,6 +171,16 @@ __device__ __forceinline__ double g4v(double m2, double m1, double p1, double p2
     acc = acc + 8.0 * p1;
     acc = acc + (-1.0) * p2;
     return acc / den;
+}
+
+// the G4 stencil of the LLA kernels: the same sum as g4v, times inv = 1 / (12 h) (a
+// multiplication instead of nine divisions per cell)
+__device__ __forceinline__ double g4m(double m2, double m1, double p1, double p2, double inv) {
+    double acc = m2;
+    acc = acc + (-8.0) * m1;
+    acc = acc + 8.0 * p1;
+    acc = acc + (-1.0) * p2;
+    return acc * inv;
 }
 
 __device__ __forceinline__ unsigned wrap1(int a, int n) { return (unsigned)(a < 0 ? a + n : (a >= n ? a - n : a)); }
@@ -263,7 +273,7 @@ __global__ void __launch_bounds__(256) k_lla_rows(const double* __restrict__ a0,
                                                   const double* __restrict__ b1, const double* __restrict__ b2,
                                                   Dims d, double h, double* __restrict__ out) {
     const RowGroup g = row_group(d);
-    const double den = 12.0 * h;
+    const double inv = 1.0 / (12.0 * h);
     const unsigned nz = (unsigned)d.z;
     const double* A[3] = {a0, a1, a2};
     const double* Bv[3] = {b0, b1, b2};
@@ -288,9 +298,9 @@ __global__ void __launch_bounds__(256) k_lla_rows(const double* __restrict__ a0,
                     if constexpr (SUM) return ai[q] + bi[q];
                     else return ai[q];
                 };
-                m[i][0] = 1.0 * (i == 0) + g4v(v(ix[0]), v(ix[1]), v(ix[2]), v(ix[3]), den);
-                m[i][1] = 1.0 * (i == 1) + g4v(v(iy[0]), v(iy[1]), v(iy[2]), v(iy[3]), den);
-                m[i][2] = 1.0 * (i == 2) + g4v(v(iz[0]), v(iz[1]), v(iz[2]), v(iz[3]), den);
+                m[i][0] = 1.0 * (i == 0) + g4m(v(ix[0]), v(ix[1]), v(ix[2]), v(ix[3]), inv);
+                m[i][1] = 1.0 * (i == 1) + g4m(v(iy[0]), v(iy[1]), v(iy[2]), v(iy[3]), inv);
+                m[i][2] = 1.0 * (i == 2) + g4m(v(iz[0]), v(iz[1]), v(iz[2]), v(iz[3]), inv);
             }
             const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
             const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
@@ -301,87 +311,111 @@ __global__ void __launch_bounds__(256) k_lla_rows(const double* __restrict__ a0,
     }
 }
 
-// The same on large periodic levels by tiles marched along x: a block owns 8 rows x 64 z of
-// 32 consecutive planes; each thread two cells (rows ty and ty + 4).  The x-stencil values of a
-// thread's cells move through a register window of 5 planes (one new load per plane), and the
-// y / z stencil values come from the plane's slab in LDS (the tile plus 2 cells each side in y
-// and z, loaded once per plane).  The same operations in the same order as k_lla_rows.
-constexpr int kLtY = 8, kLtZ = 64, kLtX = 32;
+// The same on large periodic levels by tiles marched along x: a block owns 4 rows x 64 z of 32
+// consecutive planes, one cell per thread and plane.  Each plane's slab (the tile plus 2 cells each
+// side in y and z, all three components) is loaded into LDS once, two planes ahead, into a ring of
+// three slabs: the y / z stencil values of plane x come from its slab, the x-stencil values from a
+// register window of 5 planes filled from the slabs' own cells.  Consecutive blocks go to the 8
+// XCDs in turn, so the tiles are renumbered for each XCD to take a contiguous run (whose halos are
+// then its own neighbours' cells, in its L2).  The same operations in the same order as k_lla_rows.
+constexpr int kLtY = 4, kLtZ = 64, kLtX = 32;
 
 template <bool SUM>
 __global__ void __launch_bounds__(256) k_lla_tile(const double* __restrict__ a0, const double* __restrict__ a1,
                                                   const double* __restrict__ a2, const double* __restrict__ b0,
                                                   const double* __restrict__ b1, const double* __restrict__ b2,
                                                   Dims d, double h, double* __restrict__ out) {
-    constexpr int SY = kLtY + 4, SZ = kLtZ + 4;
-    __shared__ double sl[3][SY][SZ];
+    constexpr int SY = kLtY + 4, SZ = kLtZ + 4, NS = SY * SZ, PER = (NS + 255) / 256;
+    __shared__ double sl[4][3][NS];   // ring slot (plane mod 4), component, y * SZ + z
     const double* A[3] = {a0, a1, a2};
     const double* Bv[3] = {b0, b1, b2};
     const unsigned ny = (unsigned)d.y, nz = (unsigned)d.z;
     const unsigned nty = ny / kLtY, ntz = nz / kLtZ;
-    // consecutive blocks go to the 8 XCDs in turn: renumber so that each XCD takes a contiguous
-    // run of tiles, whose halo rows and columns are then its own neighbours' cells (in its L2)
     unsigned b = blockIdx.x;
     if (gridDim.x % 8 == 0) b = (b % 8) * (gridDim.x / 8) + b / 8;
     const unsigned zt = b % ntz;
     b /= ntz;
     const unsigned yt = b % nty;
     const unsigned x0 = (b / nty) * kLtX;
-    const int tz = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);   // rows ty and ty + 4
-    const unsigned z = zt * kLtZ + tz, ya = yt * kLtY + ty, yb = ya + 4;
+    const int tz = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);
+    const unsigned z = zt * kLtZ + tz, y = yt * kLtY + ty;
     auto val = [&](int c, unsigned q) {
         if constexpr (SUM) return A[c][q] + Bv[c][q];
         else return A[c][q];
     };
-    const double den = 12.0 * h;
-    double wa[3][5], wb[3][5];   // x-window of the two cells: planes x - 2 .. x + 2
+    // this thread's share of a slab: entries t = threadIdx.x + 256 r (r < PER, t < NS); their
+    // in-plane offsets do not depend on the plane
+    unsigned off[PER];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const unsigned xp = wrap1((int)x0 - 2 + k, d.x);
+    for (int r = 0; r < PER; ++r) {
+        const int t = (int)threadIdx.x + 256 * r;
+        const int sy = (t < NS ? t : NS - 1) / SZ, sz = (t < NS ? t : NS - 1) - (t < NS ? t : NS - 1) / SZ * SZ;
+        const unsigned yy = wrap1((int)(yt * kLtY) + sy - 2, d.y), zz = wrap1((int)(zt * kLtZ) + sz - 2, d.z);
+        off[r] = yy * nz + zz;
+    }
+    double reg[PER][3];
+    auto fetch = [&](unsigned xp) {   // global loads of plane xp's slab share into registers
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            wa[c][k + 1] = val(c, (xp * ny + ya) * nz + z);
-            wb[c][k + 1] = val(c, (xp * ny + yb) * nz + z);
+        for (int r = 0; r < PER; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) reg[r][c] = val(c, xp * ny * nz + off[r]);
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int t = (int)threadIdx.x + 256 * r;
+            if (t < NS)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sl[slot][c][t] = reg[r][c];
         }
+    };
+    const double inv = 1.0 / (12.0 * h);
+    const int me = (ty + 2) * SZ + tz + 2;   // this thread's cell in a slab
+    double w[3][5];                          // x-window: planes x - 2 .. x + 2 after the shift
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        w[c][1] = val(c, (wrap1((int)x0 - 2, d.x) * ny + y) * nz + z);
+        w[c][2] = val(c, (wrap1((int)x0 - 1, d.x) * ny + y) * nz + z);
+    }
+    // prologue: planes x0, x0 + 1, x0 + 2 into slots 0, 1, 2
+    for (int k = 0; k < 3; ++k) {
+        fetch(wrap1((int)x0 + k, d.x));
+        store(k);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        w[c][3] = sl[0][c][me];
+        w[c][4] = sl[1][c][me];
     }
     for (int i = 0; i < kLtX; ++i) {
-        const unsigned x = x0 + i, xn = wrap1((int)x + 2, d.x);
+        const unsigned x = x0 + i;
+        const int cur = i & 3;
+        // plane x + 3 into registers while plane x is computed from the slabs of x and x + 2
+        if (i + 3 < kLtX + 2) fetch(wrap1((int)x + 3, d.x));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                wa[c][k] = wa[c][k + 1];
-                wb[c][k] = wb[c][k + 1];
-            }
-            wa[c][4] = val(c, (xn * ny + ya) * nz + z);
-            wb[c][4] = val(c, (xn * ny + yb) * nz + z);
+            for (int k = 0; k < 4; ++k) w[c][k] = w[c][k + 1];
+            w[c][4] = sl[(i + 2) & 3][c][me];
         }
-        __syncthreads();   // the previous plane's slab has been read
-        for (int t = (int)threadIdx.x; t < SY * SZ; t += 256) {
-            const int sy = t / SZ, sz = t - sy * SZ;
-            const unsigned yy = wrap1((int)(yt * kLtY) + sy - 2, d.y), zz = wrap1((int)(zt * kLtZ) + sz - 2, d.z);
-            const unsigned q = (x * ny + yy) * nz + zz;
+        double m[3][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sl[c][sy][sz] = val(c, q);
+        for (int c = 0; c < 3; ++c) {
+            const double* s = sl[cur][c];
+            m[c][0] = 1.0 * (c == 0) + g4m(w[c][0], w[c][1], w[c][3], w[c][4], inv);
+            m[c][1] = 1.0 * (c == 1) + g4m(s[me - 2 * SZ], s[me - SZ], s[me + SZ], s[me + 2 * SZ], inv);
+            m[c][2] = 1.0 * (c == 2) + g4m(s[me - 2], s[me - 1], s[me + 1], s[me + 2], inv);
         }
+        const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+        const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
+        const double c2 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+        const double det = (m[0][0] * c0 - m[0][1] * c1) + m[0][2] * c2;
+        out[(x * ny + y) * nz + z] = 1.0 / det - 1.0;
+        // slot (i + 3) & 3 held plane x - 1, last read in iteration i - 1 (before the previous
+        // barrier); refill it with plane x + 3, which the next iteration reads after this barrier
+        if (i + 3 < kLtX + 2) store((i + 3) & 3);
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int sy = ty + 4 * r + 2, sz = tz + 2;
-            double m[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double* w = r ? wb[c] : wa[c];
-                m[c][0] = 1.0 * (c == 0) + g4v(w[0], w[1], w[3], w[4], den);
-                m[c][1] = 1.0 * (c == 1) + g4v(sl[c][sy - 2][sz], sl[c][sy - 1][sz], sl[c][sy + 1][sz], sl[c][sy + 2][sz], den);
-                m[c][2] = 1.0 * (c == 2) + g4v(sl[c][sy][sz - 2], sl[c][sy][sz - 1], sl[c][sy][sz + 1], sl[c][sy][sz + 2], den);
-            }
-            const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
-            const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
-            const double c2 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
-            const double det = (m[0][0] * c0 - m[0][1] * c1) + m[0][2] * c2;
-            out[(x * ny + (r ? yb : ya)) * nz + z] = 1.0 / det - 1.0;
-        }
     }
 }
 
