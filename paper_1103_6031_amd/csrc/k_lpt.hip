@@ -311,24 +311,33 @@ __global__ void __launch_bounds__(256) k_lla_rows(const double* __restrict__ a0,
     }
 }
 
-// The same on large periodic levels by tiles marched along x: a block owns 4 rows x 64 z of 32
-// consecutive planes, one cell per thread and plane.  Each plane's slab (the tile plus 2 cells each
-// side in y and z, all three components) is loaded into LDS once, two planes ahead, into a ring of
-// three slabs: the y / z stencil values of plane x come from its slab, the x-stencil values from a
-// register window of 5 planes filled from the slabs' own cells.  Consecutive blocks go to the 8
-// XCDs in turn, so the tiles are renumbered for each XCD to take a contiguous run (whose halos are
-// then its own neighbours' cells, in its L2).  The same operations in the same order as k_lla_rows.
+// ----------------------------------------------------------------------------------------------
+// Large periodic levels by tiles marched along x.  A block owns 4 rows x 64 z of 32 consecutive
+// planes, one cell per thread and plane.  Each plane's slab (the tile plus 2 cells each side in y
+// and z, every component the kernel reads) is loaded into LDS once, into a ring of four slabs:
+// the loads of plane x + 3 are issued before plane x is computed and stored into the slot of plane
+// x - 1 after it (one barrier per plane).  The y / z stencil values of plane x come from its slab,
+// the x-stencil values from a register window of 5 planes filled from the slabs' own cells.
+// Consecutive blocks go to the 8 XCDs in turn, so the tiles are renumbered for each XCD to take a
+// contiguous run, whose halos are then its own neighbours' cells (in its L2).  Each kernel has
+// the same operations in the same order as its row-group version (bit-identical results).
+// ----------------------------------------------------------------------------------------------
 constexpr int kLtY = 4, kLtZ = 64, kLtX = 32;
+constexpr int kSZ = kLtZ + 4, kNS = (kLtY + 4) * kSZ, kPer = (kNS + 255) / 256;
 
-template <bool SUM>
-__global__ void __launch_bounds__(256) k_lla_tile(const double* __restrict__ a0, const double* __restrict__ a1,
-                                                  const double* __restrict__ a2, const double* __restrict__ b0,
-                                                  const double* __restrict__ b1, const double* __restrict__ b2,
-                                                  Dims d, double h, double* __restrict__ out) {
-    constexpr int SY = kLtY + 4, SZ = kLtZ + 4, NS = SY * SZ, PER = (NS + 255) / 256;
-    __shared__ double sl[4][3][NS];   // ring slot (plane mod 4), component, y * SZ + z
-    const double* A[3] = {a0, a1, a2};
-    const double* Bv[3] = {b0, b1, b2};
+static bool lpt_tiled(Dims d) {
+    return d.x % kLtX == 0 && d.y % kLtY == 0 && d.z % kLtZ == 0 && d.cells() >= ((size_t)1 << 21);
+}
+static unsigned tiles_grid(Dims d) {
+    return (unsigned)(d.x / kLtX) * (unsigned)(d.y / kLtY) * (unsigned)(d.z / kLtZ);
+}
+
+// Marches the block's tile: val(c, q) is component c at linear index q; NW components (the first
+// ones) keep an x-window; plane(x, y, z, slab, me, w) computes and stores the cell (x, y, z) from
+// its plane's slab (slab[c][me +- k], me = the cell's slab index) and the windows w[c][0..4]
+// (planes x - 2 .. x + 2).
+template <int NC, int NW, class V, class F>
+__device__ __forceinline__ void march_tiles(Dims d, double (*sl)[NC][kNS], V val, F plane) {
     const unsigned ny = (unsigned)d.y, nz = (unsigned)d.z;
     const unsigned nty = ny / kLtY, ntz = nz / kLtZ;
     unsigned b = blockIdx.x;
@@ -339,89 +348,141 @@ __global__ void __launch_bounds__(256) k_lla_tile(const double* __restrict__ a0,
     const unsigned x0 = (b / nty) * kLtX;
     const int tz = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);
     const unsigned z = zt * kLtZ + tz, y = yt * kLtY + ty;
-    auto val = [&](int c, unsigned q) {
-        if constexpr (SUM) return A[c][q] + Bv[c][q];
-        else return A[c][q];
-    };
-    // this thread's share of a slab: entries t = threadIdx.x + 256 r (r < PER, t < NS); their
-    // in-plane offsets do not depend on the plane
-    unsigned off[PER];
+    const int me = (ty + 2) * kSZ + tz + 2;
+    // this thread's share of a slab: entries t = threadIdx.x + 256 r (t < kNS); their in-plane
+    // offsets do not depend on the plane (an index past the end is clamped, its value unused)
+    unsigned off[kPer];
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-        const int t = (int)threadIdx.x + 256 * r;
-        const int sy = (t < NS ? t : NS - 1) / SZ, sz = (t < NS ? t : NS - 1) - (t < NS ? t : NS - 1) / SZ * SZ;
-        const unsigned yy = wrap1((int)(yt * kLtY) + sy - 2, d.y), zz = wrap1((int)(zt * kLtZ) + sz - 2, d.z);
-        off[r] = yy * nz + zz;
+    for (int r = 0; r < kPer; ++r) {
+        const int t = min((int)threadIdx.x + 256 * r, kNS - 1);
+        const int sy = t / kSZ, sz = t - sy * kSZ;
+        off[r] = wrap1((int)(yt * kLtY) + sy - 2, d.y) * nz + wrap1((int)(zt * kLtZ) + sz - 2, d.z);
     }
-    double reg[PER][3];
-    auto fetch = [&](unsigned xp) {   // global loads of plane xp's slab share into registers
+    double reg[kPer][NC];
+    auto fetch = [&](unsigned xp) {
+        const unsigned base = xp * ny * nz;
 #pragma unroll
-        for (int r = 0; r < PER; ++r)
+        for (int r = 0; r < kPer; ++r)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) reg[r][c] = val(c, xp * ny * nz + off[r]);
+            for (int c = 0; c < NC; ++c) reg[r][c] = val(c, base + off[r]);
     };
     auto store = [&](int slot) {
 #pragma unroll
-        for (int r = 0; r < PER; ++r) {
+        for (int r = 0; r < kPer; ++r) {
             const int t = (int)threadIdx.x + 256 * r;
-            if (t < NS)
+            if (t < kNS)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sl[slot][c][t] = reg[r][c];
+                for (int c = 0; c < NC; ++c) sl[slot][c][t] = reg[r][c];
         }
     };
-    const double inv = 1.0 / (12.0 * h);
-    const int me = (ty + 2) * SZ + tz + 2;   // this thread's cell in a slab
-    double w[3][5];                          // x-window: planes x - 2 .. x + 2 after the shift
+    double w[NW][5];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NW; ++c) {
         w[c][1] = val(c, (wrap1((int)x0 - 2, d.x) * ny + y) * nz + z);
         w[c][2] = val(c, (wrap1((int)x0 - 1, d.x) * ny + y) * nz + z);
     }
-    // prologue: planes x0, x0 + 1, x0 + 2 into slots 0, 1, 2
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 3; ++k) {   // planes x0, x0 + 1, x0 + 2 into slots 0, 1, 2
         fetch(wrap1((int)x0 + k, d.x));
         store(k);
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NW; ++c) {
         w[c][3] = sl[0][c][me];
         w[c][4] = sl[1][c][me];
     }
     for (int i = 0; i < kLtX; ++i) {
         const unsigned x = x0 + i;
-        const int cur = i & 3;
-        // plane x + 3 into registers while plane x is computed from the slabs of x and x + 2
-        if (i + 3 < kLtX + 2) fetch(wrap1((int)x + 3, d.x));
+        const bool more = i + 3 < kLtX + 2;   // the slabs run to plane x0 + kLtX + 1
+        if (more) fetch(wrap1((int)x + 3, d.x));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NW; ++c) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) w[c][k] = w[c][k + 1];
             w[c][4] = sl[(i + 2) & 3][c][me];
         }
+        plane(x, y, z, sl[i & 3], me, w);
+        // slot (i + 3) & 3 held plane x - 1, last read in iteration i - 1 (before the previous
+        // barrier); plane x + 3 goes there and is read after this barrier
+        if (more) store((i + 3) & 3);
+        __syncthreads();
+    }
+}
+
+// LLA overdensity (as k_lla_rows)
+template <bool SUM>
+__global__ void __launch_bounds__(256) k_lla_tile(const double* __restrict__ a0, const double* __restrict__ a1,
+                                                  const double* __restrict__ a2, const double* __restrict__ b0,
+                                                  const double* __restrict__ b1, const double* __restrict__ b2,
+                                                  Dims d, double h, double* __restrict__ out) {
+    __shared__ double sl[4][3][kNS];
+    const double* A[3] = {a0, a1, a2};
+    const double* Bv[3] = {b0, b1, b2};
+    const double inv = 1.0 / (12.0 * h);
+    const unsigned ny = (unsigned)d.y, nz = (unsigned)d.z;
+    auto val = [&](int c, unsigned q) {
+        if constexpr (SUM) return A[c][q] + Bv[c][q];
+        else return A[c][q];
+    };
+    march_tiles<3, 3>(d, sl, val, [&](unsigned x, unsigned y, unsigned z, double (*s)[kNS], int me, double (*w)[5]) {
         double m[3][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double* s = sl[cur][c];
             m[c][0] = 1.0 * (c == 0) + g4m(w[c][0], w[c][1], w[c][3], w[c][4], inv);
-            m[c][1] = 1.0 * (c == 1) + g4m(s[me - 2 * SZ], s[me - SZ], s[me + SZ], s[me + 2 * SZ], inv);
-            m[c][2] = 1.0 * (c == 2) + g4m(s[me - 2], s[me - 1], s[me + 1], s[me + 2], inv);
+            m[c][1] = 1.0 * (c == 1) + g4m(s[c][me - 2 * kSZ], s[c][me - kSZ], s[c][me + kSZ], s[c][me + 2 * kSZ], inv);
+            m[c][2] = 1.0 * (c == 2) + g4m(s[c][me - 2], s[c][me - 1], s[c][me + 1], s[c][me + 2], inv);
         }
         const double c0 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
         const double c1 = m[1][0] * m[2][2] - m[1][2] * m[2][0];
         const double c2 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
         const double det = (m[0][0] * c0 - m[0][1] * c1) + m[0][2] * c2;
         out[(x * ny + y) * nz + z] = 1.0 / det - 1.0;
-        // slot (i + 3) & 3 held plane x - 1, last read in iteration i - 1 (before the previous
-        // barrier); refill it with plane x + 3, which the next iteration reads after this barrier
-        if (i + 3 < kLtX + 2) store((i + 3) & 3);
-        __syncthreads();
-    }
+    });
 }
 
-static bool lla_tiled(Dims d) {
-    return d.x % kLtX == 0 && d.y % kLtY == 0 && d.z % kLtZ == 0 && d.cells() >= ((size_t)1 << 21);
+// psi_c = scale * G4_c phi (as k_grad4_rows)
+__global__ void __launch_bounds__(256) k_grad4_tile(const double* __restrict__ p, Dims d, double h, double scale,
+                                                    double* __restrict__ ox, double* __restrict__ oy,
+                                                    double* __restrict__ oz) {
+    __shared__ double sl[4][1][kNS];
+    const double den = 12.0 * h;
+    const unsigned ny = (unsigned)d.y, nz = (unsigned)d.z;
+    march_tiles<1, 1>(d, sl, [&](int, unsigned q) { return p[q]; },
+                      [&](unsigned x, unsigned y, unsigned z, double (*s)[kNS], int me, double (*w)[5]) {
+                          const double gx = g4v(w[0][0], w[0][1], w[0][3], w[0][4], den);
+                          const double gy = g4v(s[0][me - 2 * kSZ], s[0][me - kSZ], s[0][me + kSZ], s[0][me + 2 * kSZ], den);
+                          const double gz = g4v(s[0][me - 2], s[0][me - 1], s[0][me + 1], s[0][me + 2], den);
+                          const unsigned q = (x * ny + y) * nz + z;
+                          ox[q] = scale * gx;
+                          oy[q] = scale * gy;
+                          oz[q] = scale * gz;
+                      });
 }
+
+// tau from the three gradient components (as k_tau_rows)
+__global__ void __launch_bounds__(256) k_tau_tile(const double* __restrict__ q0, const double* __restrict__ q1,
+                                                  const double* __restrict__ q2, Dims d, double h, double post,
+                                                  double* __restrict__ tau) {
+    __shared__ double sl[4][3][kNS];
+    const double* Q[3] = {q0, q1, q2};
+    const double den = 12.0 * h;
+    const unsigned ny = (unsigned)d.y, nz = (unsigned)d.z;
+    march_tiles<3, 1>(d, sl, [&](int c, unsigned q) { return Q[c][q]; },
+                      [&](unsigned x, unsigned y, unsigned z, double (*s)[kNS], int me, double (*w)[5]) {
+                          const double Dxx = g4v(w[0][0], w[0][1], w[0][3], w[0][4], den);
+                          const double Dyy = g4v(s[1][me - 2 * kSZ], s[1][me - kSZ], s[1][me + kSZ], s[1][me + 2 * kSZ], den);
+                          const double Dzz = g4v(s[2][me - 2], s[2][me - 1], s[2][me + 1], s[2][me + 2], den);
+                          const double Dyx = g4v(s[0][me - 2 * kSZ], s[0][me - kSZ], s[0][me + kSZ], s[0][me + 2 * kSZ], den);
+                          const double Dzx = g4v(s[0][me - 2], s[0][me - 1], s[0][me + 1], s[0][me + 2], den);
+                          const double Dzy = g4v(s[1][me - 2], s[1][me - 1], s[1][me + 1], s[1][me + 2], den);
+                          double acc = 0.0;
+                          acc = acc + (Dyy * Dxx - Dyx * Dyx);
+                          acc = acc + (Dzz * Dxx - Dzx * Dzx);
+                          acc = acc + (Dzz * Dyy - Dzy * Dzy);
+                          tau[(x * ny + y) * nz + z] = post == 1.0 ? acc : acc * post;
+                      });
+}
+
 
 static unsigned rows_grid(Dims d) { return (unsigned)d.x * (unsigned)((d.y + kRowsY - 1) / kRowsY); }
 static unsigned rows_block(Dims d) { return d.z >= 256 ? 256u : (unsigned)((d.z + 63) / 64 * 64); }
@@ -477,7 +538,9 @@ void launch_wide_ghost(const double* pu, const double* u, double* padded, Dims d
 void launch_grad4(const double* src, int R, Dims d, double h, double scale, double* ox, double* oy, double* oz,
                   hipStream_t st) {
     const Lay B(d, 0);
-    if (R == 0)
+    if (R == 0 && lpt_tiled(d))
+        k_grad4_tile<<<tiles_grid(d), 256, 0, st>>>(src, d, h, scale, ox, oy, oz);
+    else if (R == 0)
         k_grad4_rows<<<rows_grid(d), rows_block(d), 0, st>>>(src, d, h, scale, ox, oy, oz);
     else
         k_grad4<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, B, h, scale, ox, oy, oz);
@@ -492,7 +555,8 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
     double* p2 = psi + 2 * E.d.cells();
     if (R == 0) {
         k_psi<false><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<false>{src, 0, d}, E, 0, h, p0, p1, p2);
-        k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(p0, p1, p2, d, h, 1.0, tau);
+        if (lpt_tiled(d)) k_tau_tile<<<tiles_grid(d), 256, 0, st>>>(p0, p1, p2, d, h, 1.0, tau);
+        else k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(p0, p1, p2, d, h, 1.0, tau);
     } else {
         k_psi<true><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, E, e, h, p0, p1, p2);
         k_tau_psi<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{p0, e, d}, Src<true>{p1, e, d},
@@ -502,7 +566,8 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
 
 void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
                          double* tau, hipStream_t st) {
-    k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(g0, g1, g2, d, h, post, tau);
+    if (lpt_tiled(d)) k_tau_tile<<<tiles_grid(d), 256, 0, st>>>(g0, g1, g2, d, h, post, tau);
+    else k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(g0, g1, g2, d, h, post, tau);
 }
 
 
@@ -513,10 +578,9 @@ void launch_lla(const double* const* a, const double* const* b, int R, Dims d, d
     // periodic levels (every base here has at least 2 cells per axis, so a single wrap of an
     // offset of 2 holds) by x-marched tiles where they divide the level, else by groups of rows;
     // padded patches by the per-cell kernel
-    if (R == 0 && lla_tiled(d)) {
-        const unsigned grid = (unsigned)(d.x / kLtX) * (unsigned)(d.y / kLtY) * (unsigned)(d.z / kLtZ);
-        if (sum) k_lla_tile<true><<<grid, 256, 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
-        else k_lla_tile<false><<<grid, 256, 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
+    if (R == 0 && lpt_tiled(d)) {
+        if (sum) k_lla_tile<true><<<tiles_grid(d), 256, 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
+        else k_lla_tile<false><<<tiles_grid(d), 256, 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
     } else if (R == 0 && sum)
         k_lla_rows<true><<<rows_grid(d), rows_block(d), 0, st>>>(a[0], a[1], a[2], bb[0], bb[1], bb[2], d, h, out);
     else if (R == 0)

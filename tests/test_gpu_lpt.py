@@ -17,8 +17,8 @@ def mg():
 
 
 # 2: the smallest base (stencil offsets wrap once); 20: a partial group of rows in the row-group
-# kernels; 64: 8 groups per plane
-@pytest.mark.parametrize("N", [2, 4, 8, 16, 20, 48, 64])
+# kernels; 64: 8 groups per plane; 128: the x-marched tiles
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 20, 48, 64, 128])
 def test_periodic_grad_and_tau_bit_exact(mg, N):
     rng = np.random.default_rng(N)
     phi = rng.standard_normal((N, N, N))
@@ -94,12 +94,12 @@ def test_plane_wave_tau_vanishes_on_gpu(mg):
     assert np.max(np.abs(to_host(t))) < 1e-13
 
 
-@pytest.mark.parametrize("layout", ["periodic", "deep"])
+@pytest.mark.parametrize("layout", ["periodic", "periodic128", "deep"])
 def test_displacements_and_source_in_one_call(mg, layout):
     """psi and tau from the combined entry point equal the separate calls: bit for bit with
-    scale -1, within rounding with another scale."""
-    if layout == "periodic":
-        N = 32
+    scale -1, within rounding with another scale (128^3: the x-marched tile kernels)."""
+    if layout.startswith("periodic"):
+        N = 128 if layout == "periodic128" else 32
         Hg = mg.Hier(N, 100.0 / N)
         phi = [to_dev(inputs.gaussian_field(N, 41))]
     else:
