@@ -1,6 +1,7 @@
-// LPT kernels for gfx950 (Hahn & Abel 2011, Section 3.1):
+// LPT kernels for gfx950 (Hahn & Abel 2011, Section 3.1, and the baryon density of Section 5.3):
 //   first order   psi_c = scale * G4_c phi           (Table 1 fourth-order gradient)
 //   second order  tau = sum_{i>j} D_ii D_jj - D_ij^2,  D_ij = G4_i (G4_j phi)
+//   LLA density   rho / rho_bar - 1 = 1 / det(I + G4 L) - 1   (eq. gasdens)
 // plus the post-solve ghost layers of width R (faces, edges and corners) that patches need:
 // coarse-only tri-quadratic interpolation of the parent at the child's position (children sit at
 // -1/4 and +1/4 of the parent cell along each axis).
@@ -10,7 +11,8 @@
 // ((u[-2] - 8 u[-1]) + 8 u[+1]) - u[+2], / (12 h), then scaled.  tau takes two passes:
 // psi_j = G4_j phi is stored (extended by 2 cells on patches), then D_ij = G4_i psi_j is
 // evaluated per cell.  Output cells are decoded from a linear index with multiply-shift
-// division (every array has fewer than 2^31 cells).
+// division (every array has fewer than 2^31 cells).  Periodic levels take groups of rows, and
+// where the tile divides the level, x-marched tiles with a ring of plane slabs in LDS.
 
 #include "mg_internal.h"
 
@@ -111,7 +113,8 @@ __global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h
 
 // LLA baryon density (Section 5.3, eq. gasdens): rho / rho_bar - 1 = 1 / det(I + J) - 1 with
 // J_ij = G4_j L_i, where the displacement L is a (+ b when `sum`, formed per load, the same
-// add a separate pass would make).  The determinant is expanded along the first row of M = I + J.
+// add a separate pass would make).  The stencil sums are multiplied by 1 / (12 h) (as g4m), and
+// the determinant is expanded along the first row of M = I + J.
 template <bool PAD>
 __device__ __forceinline__ double g4_of(const Src<PAD>& a, const Src<PAD>& b, int sum, int x, int y, int z,
                                         int axis, double inv) {
