@@ -653,8 +653,8 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_p2(TailPlan<T> tp) {
 }
 
 // ----------------------------------------------------------------------------------------------
-// coarse-fine ghost zones with flux matching (Section 3.3, Table 2 order-1 flux), one thread per
-// 2x2 group of fine face cells sharing a parent C.  For the low-x face and fine cell (0, j, k):
+// coarse-fine ghost zones with flux matching (Section 3.3, Table 2 order-1 flux), computed per 2x2
+// group of fine face cells sharing a parent C.  For the low-x face and fine cell (0, j, k):
 //   a  = quadratic interpolation in the outside parent layer at the child's transverse position
 //   g0 = 8/15 a + 2/3 u0 - 1/5 u1            (quadratic normal to the face)
 //   g  = g0 + (mean u0 - mean g0) - 1/2 (mean8(children of C) - U[O])
@@ -668,6 +668,11 @@ __device__ __forceinline__ void w2(double t, double w[3]) {
     w[2] = 0.5 * t * (t + 1.0);
 }
 
+// One lane per ghost cell: the four lanes q = 2 jb + kc (jb, kc in {0, 1}) of a group are
+// consecutive, each forms its own g0, and the group means are gathered by lane shuffles in the
+// order ((q0 + q1) + (q2 + q3)), the order of the sums written out over the group (so the bits do
+// not depend on how the group is split over lanes).  Four short chains instead of one long one,
+// and four times the waves, for a launch that is latency-bound.
 template <class T>
 __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, T* __restrict__ g, Lay LF,
                              ParentMap pm, int flux_match) {
@@ -677,9 +682,15 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
     const int a = face >> 1, side = face & 1;
     const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
     const unsigned nc2 = (unsigned)n[c] / 2;
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ((unsigned)n[b] / 2) * nc2) return;
-    const int J = (int)(t / nc2), K = (int)(t - (unsigned)J * nc2);
+    const unsigned lane = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned t = lane >> 2, q = lane & 3;
+    // every lane of a group takes part in the shuffles; lanes past the face compute on a valid
+    // group (the last one) and store nothing
+    const unsigned ngroups = ((unsigned)n[b] / 2) * nc2;
+    const bool live = t < ngroups;
+    const unsigned tg = live ? t : ngroups - 1;
+    const int J = (int)(tg / nc2), K = (int)(tg - (unsigned)J * nc2);
+    const int jb = (int)(q >> 1), kc = (int)(q & 1);
     // fine interior layers and the outside coarse layer along the face normal
     const int i0 = side ? n[a] - 1 : 0, i1 = side ? n[a] - 2 : 1;
     const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
@@ -689,46 +700,45 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
     double L[3][3];
     for (int db = 0; db < 3; ++db)
         for (int dc = 0; dc < 3; ++dc) {
-            int q[3];
-            q[a] = on;
-            q[b] = pm.off[b] + J + db - 1;
-            q[c] = pm.off[c] + K + dc - 1;
+            int qq[3];
+            qq[a] = on;
+            qq[b] = pm.off[b] + J + db - 1;
+            qq[c] = pm.off[c] + K + dc - 1;
             if (pm.periodic)
-                for (int k = 0; k < 3; ++k) q[k] = wrap(q[k], pdim[k]);
-            L[db][dc] = (double)pu[lidx(pm.pl.d, pm.pl.split, q[0], q[1], q[2])];
+                for (int k = 0; k < 3; ++k) qq[k] = wrap(qq[k], pdim[k]);
+            L[db][dc] = (double)pu[lidx(pm.pl.d, pm.pl.split, qq[0], qq[1], qq[2])];
         }
-    double u0[2][2], u1[2][2], g0[2][2];
-    for (int jb = 0; jb < 2; ++jb)
-        for (int kc = 0; kc < 2; ++kc) {
-            int p0[3], p1[3];
-            p0[a] = i0;
-            p1[a] = i1;
-            p0[b] = p1[b] = 2 * J + jb;
-            p0[c] = p1[c] = 2 * K + kc;
-            u0[jb][kc] = (double)u[lidx(LF, p0[0], p0[1], p0[2])];
-            u1[jb][kc] = (double)u[lidx(LF, p1[0], p1[1], p1[2])];
-            double wb[3], wc[3];
-            w2(jb ? 0.25 : -0.25, wb);
-            w2(kc ? 0.25 : -0.25, wc);
-            // parallel to the face: first along b (for each of the 3 c-columns), then along c
-            double Ab[3];
-            for (int dc = 0; dc < 3; ++dc) Ab[dc] = (wb[0] * L[0][dc] + wb[1] * L[1][dc]) + wb[2] * L[2][dc];
-            const double aq = (wc[0] * Ab[0] + wc[1] * Ab[1]) + wc[2] * Ab[2];
-            g0[jb][kc] = ((8.0 / 15.0) * aq + (2.0 / 3.0) * u0[jb][kc]) - 0.2 * u1[jb][kc];
-        }
+    int p0[3], p1[3];
+    p0[a] = i0;
+    p1[a] = i1;
+    p0[b] = p1[b] = 2 * J + jb;
+    p0[c] = p1[c] = 2 * K + kc;
+    const double u0 = (double)u[lidx(LF, p0[0], p0[1], p0[2])];
+    const double u1 = (double)u[lidx(LF, p1[0], p1[1], p1[2])];
+    double wb[3], wc[3];
+    w2(jb ? 0.25 : -0.25, wb);
+    w2(kc ? 0.25 : -0.25, wc);
+    // parallel to the face: first along b (for each of the 3 c-columns), then along c
+    double Ab[3];
+    for (int dc = 0; dc < 3; ++dc) Ab[dc] = (wb[0] * L[0][dc] + wb[1] * L[1][dc]) + wb[2] * L[2][dc];
+    const double aq = (wc[0] * Ab[0] + wc[1] * Ab[1]) + wc[2] * Ab[2];
+    const double g0 = ((8.0 / 15.0) * aq + (2.0 / 3.0) * u0) - 0.2 * u1;
     double shift = 0.0;
     if (flux_match) {
-        const double m_u0 = ((u0[0][0] + u0[0][1]) + (u0[1][0] + u0[1][1])) * 0.25;
-        const double m_u1 = ((u1[0][0] + u1[0][1]) + (u1[1][0] + u1[1][1])) * 0.25;
-        const double m_g0 = ((g0[0][0] + g0[0][1]) + (g0[1][0] + g0[1][1])) * 0.25;
+        const int base = (int)(threadIdx.x & 63) & ~3;
+        auto mean4 = [&](double v) {
+            const double v0 = __shfl(v, base, 64), v1 = __shfl(v, base + 1, 64);
+            const double v2 = __shfl(v, base + 2, 64), v3 = __shfl(v, base + 3, 64);
+            return ((v0 + v1) + (v2 + v3)) * 0.25;
+        };
+        const double m_u0 = mean4(u0), m_u1 = mean4(u1), m_g0 = mean4(g0);
         const double uC = 0.5 * (m_u0 + m_u1);
         shift = (m_u0 - m_g0) - 0.5 * (uC - L[1][1]);
     }
+    if (!live) return;
     const size_t fo = ghost_face_offset(d, face);
     const int nbf = n[c];  // face arrays are [n_b][n_c]
-    for (int jb = 0; jb < 2; ++jb)
-        for (int kc = 0; kc < 2; ++kc)
-            g[fo + (size_t)(2 * J + jb) * nbf + (2 * K + kc)] = (T)(g0[jb][kc] + shift);
+    g[fo + (size_t)(2 * J + jb) * nbf + (2 * K + kc)] = (T)(g0 + shift);
 }
 
 // parent[cov] = mean8(fine), bottom-up composite restriction
@@ -1256,7 +1266,7 @@ void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Lay L, ParentMap pm, 
     const Dims d = L.d;
     const size_t most = std::max({(size_t)(d.y / 2) * (d.z / 2), (size_t)(d.x / 2) * (d.z / 2),
                                   (size_t)(d.x / 2) * (d.y / 2)});
-    k_ghost_fill<T><<<dim3(grid_for(most), 6), kBlock, 0, st>>>(pu, u, ghosts, L, pm, flux_match);
+    k_ghost_fill<T><<<dim3(grid_for(4 * most), 6), kBlock, 0, st>>>(pu, u, ghosts, L, pm, flux_match);
 }
 
 template <class T>
