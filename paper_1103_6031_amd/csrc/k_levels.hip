@@ -362,6 +362,19 @@ __device__ __forceinline__ T lane(const typename Vec16<T>::type& v, int k) {
     else return k == 0 ? v.x : v.y;
 }
 
+// Block order of the 16-byte half-sweeps.  Consecutive blocks go to the 8 XCDs in turn, so the
+// rows at the edges of a block's run were fetched again into another XCD's L2 by the neighbouring
+// blocks (counters: 1.09x the compulsory bytes at 256^3).  Within each group of 32 blocks the
+// order is permuted so that 4 consecutive runs share an XCD (hardware block b takes run
+// 4 (b mod 8) + (b div 8) mod 4); the interleave across XCDs stays fine-grained.  Applied only
+// where an x plane spans a multiple of 32 blocks, so that x-neighbouring planes keep sharing an
+// XCD (at 128^3 a plane is 8 blocks, and the permutation measured slower there).  Measured at
+// 256^3: counters 1.03x, FP32 half-sweep 16.7 -> 16.4 us.
+__device__ __forceinline__ unsigned xcd_quads(unsigned b, unsigned grid, unsigned blocks_per_plane) {
+    if (grid % 32 != 0 || blocks_per_plane % 32 != 0) return b;
+    return (b & ~31u) | (((b & 7u) << 2) | ((b >> 3) & 3u));
+}
+
 template <class T, int CH>
 __global__ void __launch_bounds__(256)
 k_rbgs_vec(T* __restrict__ u, const T* __restrict__ f, int lgx, int lgy, int lgz, T h2, int colour) {
@@ -370,9 +383,10 @@ k_rbgs_vec(T* __restrict__ u, const T* __restrict__ f, int lgx, int lgy, int lgz
     const unsigned lzh = (unsigned)lgz - 1, nzh = 1u << lzh, mx = (1u << lgx) - 1, my = (1u << lgy) - 1;
     const unsigned chunks = 1u << (lgx + lgy + lzh - __builtin_ctz(W));   // W-cell runs of one colour
     const unsigned own = colour ? nzh : 0u, oth = colour ? 0u : nzh;
+    const unsigned bl = xcd_quads(blockIdx.x, gridDim.x, (1u << (lgy + lzh - __builtin_ctz(W))) / (CH * blockDim.x));
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-        const unsigned ch = (blockIdx.x * CH + c) * blockDim.x + threadIdx.x;
+        const unsigned ch = (bl * CH + c) * blockDim.x + threadIdx.x;
         if (ch >= chunks) break;
         const unsigned t = ch * W;                 // first cell of the run in the colour's order
         const unsigned row = t >> lzh, j0 = t & (nzh - 1);
@@ -442,7 +456,8 @@ k_rbgs_vec_corr(T* __restrict__ u, const T* __restrict__ f, int lgx, int lgy, in
     const unsigned lzh = (unsigned)lgz - 1, nzh = 1u << lzh, mx = (1u << lgx) - 1, my = (1u << lgy) - 1;
     const int lc = lgz - 1;                        // the coarse level is a cube of edge 2^(lgz - 1)
     const unsigned chunks = 1u << (lgx + lgy + lzh - __builtin_ctz(W));
-    const unsigned ch = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned bl = xcd_quads(blockIdx.x, gridDim.x, (1u << (lgy + lzh - __builtin_ctz(W))) / blockDim.x);
+    const unsigned ch = bl * blockDim.x + threadIdx.x;
     if (ch >= chunks) return;
     const unsigned t = ch * W, row = t >> lzh, j0 = t & (nzh - 1);
     const unsigned x = row >> lgy, y = row & my;
