@@ -214,6 +214,21 @@ k_level_post(const T* __restrict__ ui, const T* __restrict__ fi, const T* __rest
 // positions of the fine half-rows.
 // ----------------------------------------------------------------------------------------------
 
+// Block order of the power-of-two kernels on large levels (the 16-byte half-sweeps and the
+// residual-restriction).  Consecutive blocks go to the 8 XCDs in turn, so the rows at the edges
+// of a block's run were fetched again into another XCD's L2 by the neighbouring blocks (counters
+// at 256^3: 1.09x the compulsory bytes for the half-sweep, 1.22x for the residual-restriction).
+// Within each group of 32 blocks the order is permuted so that 4 consecutive runs share an XCD
+// (hardware block b takes run 4 (b mod 8) + (b div 8) mod 4); the interleave across XCDs stays
+// fine-grained.  Applied only where an x plane spans a multiple of 32 blocks, so that
+// x-neighbouring planes keep sharing an XCD (at 128^3 a half-sweep plane is 8 blocks, and the
+// permutation measured slower there).  Measured at 256^3: half-sweep counters 1.02x, FP32
+// 16.7 -> 16.4 us; residual-restriction fetch -15%, FP32 26.0 -> 24.8 us.
+__device__ __forceinline__ unsigned xcd_quads(unsigned b, unsigned grid, unsigned blocks_per_plane) {
+    if (grid % 32 != 0 || blocks_per_plane % 32 != 0) return b;
+    return (b & ~31u) | (((b & 7u) << 2) | ((b >> 3) & 3u));
+}
+
 // steps 3-5 for the coarse cell t = (X, Y, Z) (natural order): the 8 children's residuals and
 // values summed in the order (a, b, e).  The children and their neighbours span the fine rows
 // (2X + a, 2Y + b) at z = 2Z - 1 .. 2Z + 2, and the rows one step outside in x and in y at
@@ -225,7 +240,7 @@ k_resid_restrict_p2(const T* __restrict__ u, const T* __restrict__ f, int lg, T 
                     T* __restrict__ pf, T* __restrict__ uold) {
     const int lc = lg - 1;
     const unsigned nc = 1u << lc, mc = nc - 1, m = (1u << lg) - 1, nzh = nc;
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned t = xcd_quads(blockIdx.x, gridDim.x, (1u << (2 * lc)) / blockDim.x) * blockDim.x + threadIdx.x;
     if (t >= 1u << (3 * lc)) return;
     const unsigned X = t >> (2 * lc), Y = (t >> lc) & mc, Z = t & mc;
     const unsigned x0 = 2 * X, y0 = 2 * Y;
@@ -360,19 +375,6 @@ template <class T>
 __device__ __forceinline__ T lane(const typename Vec16<T>::type& v, int k) {
     if constexpr (Vec16<T>::W == 4) return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
     else return k == 0 ? v.x : v.y;
-}
-
-// Block order of the 16-byte half-sweeps.  Consecutive blocks go to the 8 XCDs in turn, so the
-// rows at the edges of a block's run were fetched again into another XCD's L2 by the neighbouring
-// blocks (counters: 1.09x the compulsory bytes at 256^3).  Within each group of 32 blocks the
-// order is permuted so that 4 consecutive runs share an XCD (hardware block b takes run
-// 4 (b mod 8) + (b div 8) mod 4); the interleave across XCDs stays fine-grained.  Applied only
-// where an x plane spans a multiple of 32 blocks, so that x-neighbouring planes keep sharing an
-// XCD (at 128^3 a plane is 8 blocks, and the permutation measured slower there).  Measured at
-// 256^3: counters 1.03x, FP32 half-sweep 16.7 -> 16.4 us.
-__device__ __forceinline__ unsigned xcd_quads(unsigned b, unsigned grid, unsigned blocks_per_plane) {
-    if (grid % 32 != 0 || blocks_per_plane % 32 != 0) return b;
-    return (b & ~31u) | (((b & 7u) << 2) | ((b >> 3) & 3u));
 }
 
 template <class T, int CH>
