@@ -158,7 +158,8 @@ int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, 
  * at the Lagrangian cell centres of every level, for the displacement L = disp (+ disp2 when
  * disp2 is not NULL; e.g. the first- and second-order displacements of a 2LPT set).
  * disp[3*p + c] (and disp2[3*p + c]) is the c-th component on level p, natural [x][y][z] order,
- * as lpt_displacements writes it; delta[p] is one array per level.  Inputs are read only.
+ * as lpt_displacements writes it; delta[p] is one array per level and must not alias any
+ * displacement array.  Inputs are read only.
  * On patches each component takes width-2 ghosts from its parent as in lpt_displacements (covered
  * parent cells as the mean of their children).  Then covered coarse cells of delta are replaced
  * by the mean of their children and the composite mean is subtracted from every level: the
