@@ -56,6 +56,7 @@ def test_periodic_lla_matches_oracle(mg, N, two):
 @pytest.mark.parametrize("layout", [
     (16, [((12, 12, 12), (2, 3, 2))]),
     (16, [((16, 16, 16), (4, 4, 4)), ((12, 8, 16), (4, 6, 4))]),
+    (128, [((64, 64, 64), (48, 40, 32))]),   # the base takes the x-marched tiles
 ])
 @pytest.mark.parametrize("two", [False, True])
 def test_hierarchy_lla_matches_oracle(mg, layout, two):
