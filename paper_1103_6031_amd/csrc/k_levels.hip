@@ -18,6 +18,7 @@
 #include <hip/hip_ext.h>
 
 #include "mg_internal.h"
+#include "vec16.h"
 
 namespace mgic {
 
@@ -367,56 +368,18 @@ void launch_fas_rhs_p2(const T* pu, T* pf, int n, double H, hipStream_t st) {
 // the other half, by the row's parity) is a scalar load.  Each cell is updated with the
 // expression of cell_rbgs_split, so the bits are the same.
 // ----------------------------------------------------------------------------------------------
-template <class T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
-
-template <class T>
-__device__ __forceinline__ T lane(const typename Vec16<T>::type& v, int k) {
-    if constexpr (Vec16<T>::W == 4) return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
-    else return k == 0 ? v.x : v.y;
-}
-
 template <class T, int CH>
 __global__ void __launch_bounds__(256)
 k_rbgs_vec(T* __restrict__ u, const T* __restrict__ f, int lgx, int lgy, int lgz, T h2, int colour) {
-    using V = typename Vec16<T>::type;
     constexpr int W = Vec16<T>::W;
-    const unsigned lzh = (unsigned)lgz - 1, nzh = 1u << lzh, mx = (1u << lgx) - 1, my = (1u << lgy) - 1;
+    const unsigned lzh = (unsigned)lgz - 1;
     const unsigned chunks = 1u << (lgx + lgy + lzh - __builtin_ctz(W));   // W-cell runs of one colour
-    const unsigned own = colour ? nzh : 0u, oth = colour ? 0u : nzh;
     const unsigned bl = xcd_quads(blockIdx.x, gridDim.x, (1u << (lgy + lzh - __builtin_ctz(W))) / (CH * blockDim.x));
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         const unsigned ch = (bl * CH + c) * blockDim.x + threadIdx.x;
         if (ch >= chunks) break;
-        const unsigned t = ch * W;                 // first cell of the run in the colour's order
-        const unsigned row = t >> lzh, j0 = t & (nzh - 1);
-        const unsigned x = row >> lgy, y = row & my;
-        const unsigned q = (x + y + (unsigned)colour) & 1u;   // z parity of this colour in the row
-        const unsigned r0 = row << lgz;
-        const unsigned rxm = ((((x - 1) & mx) << lgy) | y) << lgz, rxp = ((((x + 1) & mx) << lgy) | y) << lgz;
-        const unsigned rym = ((x << lgy) | ((y - 1) & my)) << lgz, ryp = ((x << lgy) | ((y + 1) & my)) << lgz;
-        const V XM = *(const V*)(u + rxm + oth + j0), XP = *(const V*)(u + rxp + oth + j0);
-        const V YM = *(const V*)(u + rym + oth + j0), YP = *(const V*)(u + ryp + oth + j0);
-        const V C = *(const V*)(u + r0 + oth + j0);    // the other colour's entries j0 .. j0 + W - 1
-        const V F = *(const V*)(f + r0 + own + j0);
-        // cell j = j0 + k sits at z = 2j + q; its z-neighbours are the other colour's entries
-        // j - 1 + q and j + q: for q = 0 these are C[k - 1] (entry j0 - 1 for k = 0) and C[k],
-        // for q = 1 C[k] and C[k + 1] (entry j0 + W for k = W - 1)
-        const T edge = u[r0 + oth + (q ? ((j0 + W) & (nzh - 1)) : ((j0 - 1) & (nzh - 1)))];
-        T out[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const T zm = q ? lane<T>(C, k) : (k == 0 ? edge : lane<T>(C, k - 1));
-            const T zp = q ? (k == W - 1 ? edge : lane<T>(C, k + 1)) : lane<T>(C, k);
-            const T s = ((lane<T>(XM, k) + lane<T>(XP, k)) + (lane<T>(YM, k) + lane<T>(YP, k))) + (zm + zp);
-            out[k] = (s - h2 * lane<T>(F, k)) / T(6);
-        }
-        V o;
-        if constexpr (W == 4) o = V{out[0], out[1], out[2], out[3]};
-        else o = V{out[0], out[1]};
-        *(V*)(u + r0 + own + j0) = o;
+        run_rbgs_vec<T>(u, f, lgx, lgy, lgz, h2, colour, ch);
     }
 }
 

@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "mg_internal.h"
+#include "vec16.h"
 
 namespace mgic {
 
@@ -1339,6 +1340,16 @@ __global__ void kb_rbgs(const BSeg* __restrict__ segs, int nseg, const int* __re
     const BSeg& s = seg_of(segs, nseg, lb);
     if (!active[s.inst]) return;
     const Lay L = s.L;
+    // with V = W cells per thread a block covers the same cells as a block of 16-byte runs, so
+    // the power-of-two levels whose half-rows hold whole runs take the 16-byte body (same bits)
+    if constexpr (V == Vec16<T>::W) {
+        if (L.pow2 && L.split && L.lgz >= 1 && ((1u << (L.lgz - 1)) % V) == 0) {
+            const unsigned ch = lb * blockDim.x + threadIdx.x;
+            if (ch < (unsigned)(L.d.cells() / 2 / V))
+                run_rbgs_vec<T>((T*)s.a[0], (const T*)s.a[1], L.lgx, L.lgy, L.lgz, (T)(s.h * s.h), colour, ch);
+            return;
+        }
+    }
     body_rbgs_split<T, V>((T*)s.a[0], (const T*)s.a[1], L, (T)(s.h * s.h), colour, lb);
 }
 
