@@ -53,7 +53,7 @@ def parse():
 # HBM traffic of the finest-level smoother, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # recorded under profiles/; it stands only while the kernel sources hash to the recorded value.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rbgs_vec_f32_256.md")
-KERNEL_SOURCES = ("k_levels.hip", "k_multigrid.hip", "mg_internal.h", "fastdiv.h", "vec16.h")
+KERNEL_SOURCES = ("k_levels.hip", "k_multigrid.hip", "mg_internal.h", "fastdiv.h", "p2_bodies.h")
 
 
 def kernel_source_hash():

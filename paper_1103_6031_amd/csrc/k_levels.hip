@@ -18,17 +18,12 @@
 #include <hip/hip_ext.h>
 
 #include "mg_internal.h"
-#include "vec16.h"
+#include "p2_bodies.h"
 
 namespace mgic {
 
 constexpr int kTile = 8;            // tile edge (cells)
 constexpr int kFusedThreads = 512;  // one thread per tile cell
-
-// position of (x, y, z) in a colour-split power-of-two cube of edge 2^lg
-__device__ __forceinline__ unsigned sidx(int lg, unsigned x, unsigned y, unsigned z) {
-    return ((((x << lg) | y) << lg) + (((x + y + z) & 1u) << (lg - 1))) + (z >> 1);
-}
 
 // Loops over the cells of a region: each thread takes the cells t = threadIdx.x + r * 512; every
 // pass first forms all its values (an index past the end is clamped to the last cell, so every
@@ -230,83 +225,15 @@ __device__ __forceinline__ unsigned xcd_quads(unsigned b, unsigned grid, unsigne
     return (b & ~31u) | (((b & 7u) << 2) | ((b >> 3) & 3u));
 }
 
-// steps 3-5 for the coarse cell t = (X, Y, Z) (natural order): the 8 children's residuals and
-// values summed in the order (a, b, e).  The children and their neighbours span the fine rows
-// (2X + a, 2Y + b) at z = 2Z - 1 .. 2Z + 2, and the rows one step outside in x and in y at
-// z = 2Z, 2Z + 1; in a row whose even-z cells are colour p, z = 2Z and 2Z + 2 are entries Z and
-// Z + 1 of half p, z = 2Z - 1 and 2Z + 1 entries Z - 1 and Z of the other half.
+// steps 3-5, one thread per coarse cell (cell_resid_restrict_p2)
 template <class T>
 __global__ void __launch_bounds__(256)
 k_resid_restrict_p2(const T* __restrict__ u, const T* __restrict__ f, int lg, T h2, T* __restrict__ pu,
                     T* __restrict__ pf, T* __restrict__ uold) {
     const int lc = lg - 1;
-    const unsigned nc = 1u << lc, mc = nc - 1, m = (1u << lg) - 1, nzh = nc;
     const unsigned t = xcd_quads(blockIdx.x, gridDim.x, (1u << (2 * lc)) / blockDim.x) * blockDim.x + threadIdx.x;
     if (t >= 1u << (3 * lc)) return;
-    const unsigned X = t >> (2 * lc), Y = (t >> lc) & mc, Z = t & mc;
-    const unsigned x0 = 2 * X, y0 = 2 * Y;
-    const unsigned Zm = (Z - 1) & mc, Zp = (Z + 1) & mc;
-    auto rowb = [&](unsigned x, unsigned y) { return (((x & m) << lg) | (y & m)) << lg; };
-    auto half = [&](unsigned x, unsigned y, unsigned zpar) {   // offset of the half holding parity zpar
-        return ((x + y + zpar) & 1u) * nzh;
-    };
-    // central rows (a, b): values at z0 - 1, z0, z0 + 1, z0 + 2 and f at z0, z0 + 1
-    T cm[2][2], c0[2][2], c1[2][2], c2[2][2], f0[2][2], f1[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const unsigned x = x0 + a, y = y0 + b, rb = rowb(x, y);
-            const unsigned he = half(x, y, 0), ho = half(x, y, 1);
-            cm[a][b] = u[rb + ho + Zm];
-            c0[a][b] = u[rb + he + Z];
-            c1[a][b] = u[rb + ho + Z];
-            c2[a][b] = u[rb + he + Zp];
-            f0[a][b] = f[rb + he + Z];
-            f1[a][b] = f[rb + ho + Z];
-        }
-    // face rows: x0 - 1 and x0 + 2 (for b = 0, 1), y0 - 1 and y0 + 2 (for a = 0, 1), at z0, z0 + 1
-    T xf[2][2][2], yf[2][2][2];   // [side][b or a][e]
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            {
-                const unsigned x = sd ? x0 + 2 : x0 - 1, y = y0 + k, rb = rowb(x, y);
-                xf[sd][k][0] = u[rb + half(x, y, 0) + Z];
-                xf[sd][k][1] = u[rb + half(x, y, 1) + Z];
-            }
-            {
-                const unsigned x = x0 + k, y = sd ? y0 + 2 : y0 - 1, rb = rowb(x, y);
-                yf[sd][k][0] = u[rb + half(x, y, 0) + Z];
-                yf[sd][k][1] = u[rb + half(x, y, 1) + Z];
-            }
-        }
-    auto val = [&](int a, int b, int e) { return e ? c1[a][b] : c0[a][b]; };
-    T sr = T(0), su = T(0);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const T ui = val(a, b, e);
-                const T xm = a ? val(0, b, e) : xf[0][b][e];
-                const T xp = a ? xf[1][b][e] : val(1, b, e);
-                const T ym = b ? val(a, 0, e) : yf[0][a][e];
-                const T yp = b ? yf[1][a][e] : val(a, 1, e);
-                const T zm = e ? c0[a][b] : cm[a][b];
-                const T zp = e ? c2[a][b] : c1[a][b];
-                const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
-                const T lap = (s - T(6) * ui) / h2;
-                sr = sr + ((e ? f1[a][b] : f0[a][b]) - lap);
-                su = su + ui;
-            }
-    const T uc = su * T(0.125);
-    const unsigned P = sidx(lc, X, Y, Z);
-    pu[P] = uc;
-    pf[P] = sr * T(0.125);
-    uold[t] = uc;
+    cell_resid_restrict_p2<T>(u, f, lg, h2, pu, pf, uold, t);
 }
 
 // step 8 on the black cells: the black cell (row, j) of a fine row lies in the parent (X, Y, j)

@@ -21,7 +21,7 @@
 #include <algorithm>
 
 #include "mg_internal.h"
-#include "vec16.h"
+#include "p2_bodies.h"
 
 namespace mgic {
 
@@ -1361,9 +1361,17 @@ __global__ void kb_resid_restrict(const BSeg* __restrict__ segs, int nseg, const
     const Lay L = s.L, C = s.C;
     const ParentMap pm = s.pm;
     const unsigned t = lb * blockDim.x + threadIdx.x;
-    if (t < (unsigned)C.d.cells())
-        cell_resid_restrict<T, false>((const T*)s.a[0], (const T*)s.a[1], nullptr, L, (T)(s.h * s.h), (T*)s.a[2],
-                                      (T*)s.a[3], (T*)s.a[4], pm, C, t);
+    if (t >= (unsigned)C.d.cells()) return;
+    // a whole power-of-two cube with a colour-split parent: the power-of-two body (one thread per
+    // coarse cell in natural order, as here; same bits)
+    if (L.pow2 && L.split && pm.pl.split && L.d.x == L.d.y && L.d.y == L.d.z && L.d.x >= 4 && pm.periodic &&
+        pm.off[0] == 0 && pm.off[1] == 0 && pm.off[2] == 0) {
+        cell_resid_restrict_p2<T>((const T*)s.a[0], (const T*)s.a[1], L.lgx, (T)(s.h * s.h), (T*)s.a[2], (T*)s.a[3],
+                                  (T*)s.a[4], t);
+        return;
+    }
+    cell_resid_restrict<T, false>((const T*)s.a[0], (const T*)s.a[1], nullptr, L, (T)(s.h * s.h), (T*)s.a[2],
+                                  (T*)s.a[3], (T*)s.a[4], pm, C, t);
 }
 
 template <class T>
