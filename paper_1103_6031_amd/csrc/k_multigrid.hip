@@ -855,6 +855,39 @@ __device__ __forceinline__ double body_residual_split(const T* __restrict__ u, c
     const unsigned n = (unsigned)d.cells(), nz = (unsigned)d.z, nzh = nz >> 1;
     double acc = 0.0;
     const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
+    // FP64, no covered box, no output and even half-rows: pairs of cells with 16-byte runs (the
+    // loads of the outer step's pairs), each cell with the same operations as below
+    if constexpr (sizeof(T) == 8) {
+        if (!rout && (cb.n[0] <= 0 || cb.n[1] <= 0 || cb.n[2] <= 0) && (nzh & 1u) == 0) {
+            for (unsigned p0 = lo; p0 < n; p0 += stride)
+#pragma unroll
+            for (int v = 0; v < kRedV / 2; ++v) {
+                const unsigned t = p0 + 2 * (threadIdx.x + v * blockDim.x);
+                if (t >= n) break;
+                const SplitNb c = split_nb(L, t);
+                const unsigned j = c.j, oth = c.oth, r0 = c.r0, q = (unsigned)c.q;
+                const double2 fv = *(const double2*)(f + t);
+                const unsigned ix[6] = {t, c.rxm + oth + j, c.rxp + oth + j, c.rym + oth + j, c.ryp + oth + j,
+                                        r0 + oth + j};
+                const unsigned jn = q ? j + 2 : j + nzh - 1;
+                const unsigned ie = r0 + oth + (jn >= nzh ? jn - nzh : jn);
+                double2 w[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) w[k] = *(const double2*)(u + ix[k]);
+                const double edge = u[ie];
+                __builtin_amdgcn_sched_barrier(0);
+                const double zm0 = q ? w[5].x : edge, zp0 = q ? w[5].y : w[5].x;
+                const double zm1 = q ? w[5].y : w[5].x, zp1 = q ? edge : w[5].y;
+                const double s0 = ((w[1].x + w[2].x) + (w[3].x + w[4].x)) + (zm0 + zp0);
+                const double s1 = ((w[1].y + w[2].y) + (w[3].y + w[4].y)) + (zm1 + zp1);
+                const double ra = fv.x - (s0 - 6.0 * w[0].x) / (double)h2;
+                const double rb = fv.y - (s1 - 6.0 * w[0].y) / (double)h2;
+                acc += ra * ra;
+                acc += rb * rb;
+            }
+            return acc;
+        }
+    }
     for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV; ++v) {
