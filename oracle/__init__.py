@@ -19,6 +19,8 @@ cosmological simulations" (MNRAS 2011):
                  composite residual, post-solve wide ghosts.
 * ``lpt``      - Section 3.1: first-order displacements from the gradient of
                  the potential and the second-order source term tau.
+* ``highorder``- the fourth- and sixth-order Laplacians of Table 1 (13- and
+                 19-point) and the periodic FAS solve of Section 3.2 with them.
 * ``dense``    - brute-force dense assembly of the periodic and composite
                  linear systems for tiny grids (pins for the iterative solvers).
 
@@ -32,4 +34,4 @@ brute-force dense solves or invariants that do not reuse the oracle's own
 arithmetic.
 """
 
-from . import stencil, periodic, lpt, zoom, dense  # noqa: F401
+from . import stencil, periodic, lpt, zoom, dense, highorder  # noqa: F401
