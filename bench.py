@@ -220,6 +220,44 @@ def time_lla(mg, torch, H, psi1, psi2, reps=10):
                 delta_min=float(delta.min()), delta_max=float(delta.max()), repeats=reps)
 
 
+def time_highorder(mg, torch, ft, h, tol, reps=3):
+    """The solve with the 4th- and 6th-order Laplacians of Table 1 (13 and 19 points), FP64, on the
+    step's density: median of `reps` solves after one warm-up, HIP events on the launch stream,
+    and the finest half-sweep timed by the library's events.  That half-sweep is out of place:
+    per cell it reads the iterate and f and writes every cell, 24 B (the colour-split in-place
+    half-sweep of the 7-point path moves 12 B per cell, its updated half only)."""
+    n = ft.shape[0]
+    res = dict(workload="periodic %d^3 BBKS, FP64 V(2,2) with the order-4 / order-6 Laplacian, tol %g" % (n, tol))
+    for order in (4, 6):
+        o = mg.make_opts(tol=tol, max_cycles=40)
+        ws = mg.Workspace(mg.mg_ho_workspace_bytes(n, order))
+        u = torch.empty_like(ft)
+        ts = []
+        for i in range(reps + 1):
+            if i == 1:
+                mg.mg_kprof_read()
+                mg.mg_kprof_enable(True)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, st = mg.mg_solve_level_ho(ft, h, order, u=u, opts=o, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if i == 1:
+                mg.mg_kprof_enable(False)
+                kms, kn, kb = mg.mg_kprof_read()
+            if i >= 1:
+                ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        us = kms * 1e3 / max(kn, 1)
+        res["order%d" % order] = dict(ms_per_solve=round(ms, 3), cycles=st["cycles"], rel_res=st["rel_res"],
+                                      value=round(st["cell_updates"] / (ms * 1e-3) / 1e6, 1),
+                                      unit="Mcell-updates/s", half_sweep_avg_us=round(us, 2),
+                                      half_sweep_launches=kn,
+                                      half_sweep_gbs=round(kb / max(kn, 1) / (us * 1e-6) / 1e9, 1) if kn else None)
+    return res
+
+
 def time_c3(mg, torch, reps=3):
     """The zoom hierarchy: 128^3 base with three centred 128^3 patches, the 2LPT chain (solve,
     displacements, tau, solve, displacements) in both precisions."""
@@ -341,6 +379,7 @@ def main():
     if a.inner:
         line["config"]["inner"] = a.inner
     line["lla"] = time_lla(mg, torch, H, out_h[1], out_h[4])
+    line["highorder"] = time_highorder(mg, torch, ft, h, a.tol)
     if not a.no_c1c3:
         line["solve_c1"] = time_c1(mg, torch)
         line["zoom_c3"] = time_c3(mg, torch)

@@ -1518,6 +1518,175 @@ static size_t batch_bytes(int ninst, const int* n, const mg_opts* o) {
 // ==============================================================================================
 using namespace mgic;
 
+// ----------------------------------------------------------------------------------------------
+// periodic FAS with the order-2/4/6 Laplacians of Table 1 (Section 3.2): n = 2^lg, FP64
+// ----------------------------------------------------------------------------------------------
+struct HoPlan {
+    int lg = 0, order = 2, nlev = 0;     // levels l = 0..nlev-1 have 2^(lg-l) cells per axis
+    double h = 1.0;
+    double* u[12]{};      // level 0: the caller's array
+    double* f[12]{};      // level 0: f minus its mean; coarser levels: the FAS right-hand side
+    double* uold[12]{};   // the restricted iterate before the coarse solve (levels >= 1)
+    double* tmp[12]{};    // the other buffer of the out-of-place half-sweeps (levels with 2^3+ cells)
+    double* part = nullptr;
+    double* scal = nullptr;   // [0] sum f, [1] sum (f - mean)^2, [2] sum r^2, [3] sum u, [4] unused
+};
+
+static int ho_plan(int n, double h, int order, Carver& cv, double* u, HoPlan& P) {
+    const int lg = log2_exact(n);
+    if (lg < 1 || lg > 10) return fail(MG_EINVAL, "higher-order solve: n must be a power of two in 2..1024");
+    if (order != 2 && order != 4 && order != 6) return fail(MG_EINVAL, "order must be 2, 4 or 6");
+    if (!(h > 0) || !std::isfinite(h)) return fail(MG_EINVAL, "h must be positive and finite");
+    P.lg = lg;
+    P.order = order;
+    P.h = h;
+    P.nlev = lg + 1;
+    for (int l = 0; l < P.nlev; ++l) {
+        const size_t cells = (size_t)1 << (3 * (lg - l));
+        P.u[l] = l == 0 ? u : cv.take<double>(cells);
+        P.f[l] = cv.take<double>(cells);
+        if (l > 0) P.uold[l] = cv.take<double>(cells);
+        if (l < lg) P.tmp[l] = cv.take<double>(cells);
+    }
+    P.part = cv.take<double>(kHoParts);
+    P.scal = cv.take<double>(8);
+    return MG_OK;
+}
+
+static int ho_read(const double* dev, int count, double* out, hipStream_t st) {
+    double* pin = pinned_scratch();
+    if (!pin) return fail(MG_EHIP, "pinned host buffer unavailable");
+    MG_HIP(hipMemcpyAsync(pin, dev, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    MG_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) out[i] = pin[i];
+    return MG_OK;
+}
+
+static void ho_smooth(HoPlan& P, int l, int sweeps, hipStream_t st) {
+    const int lg = P.lg - l;
+    const double h = std::ldexp(P.h, l);
+    const double half_bytes = 3.0 * 8.0 * (double)((size_t)1 << (3 * lg));   // in, f read; out written
+    for (int s = 0; s < sweeps; ++s)
+        for (int c = 0; c < 2; ++c) {
+            KEvents ev(l == 0);
+            const double* in = c == 0 ? P.u[l] : P.tmp[l];
+            double* out = c == 0 ? P.tmp[l] : P.u[l];
+            launch_ho_half(in, out, P.f[l], lg, h, P.order, c, st, ev.a, ev.b);
+            ev.done(half_bytes);
+        }
+}
+
+static void ho_vcycle(HoPlan& P, int nu1, int nu2, hipStream_t st) {
+    const int L = P.nlev - 1;   // the single-cell level
+    for (int l = 0; l < L; ++l) {
+        ho_smooth(P, l, nu1, st);
+        const int lgc = P.lg - l - 1;
+        launch_ho_resid_restrict(P.u[l], P.f[l], P.u[l + 1], P.uold[l + 1], P.f[l + 1], lgc, std::ldexp(P.h, l),
+                                 P.order, st);
+        launch_ho_fas(P.u[l + 1], P.f[l + 1], lgc, std::ldexp(P.h, l + 1), P.order, st);
+    }
+    launch_ho_fill(P.u[L], 0, 0.0, st);   // one cell: u = 0
+    for (int l = L - 1; l >= 0; --l) {
+        launch_ho_prolong(P.u[l], P.u[l + 1], P.uold[l + 1], P.lg - l, st);
+        ho_smooth(P, l, nu2, st);
+    }
+}
+
+extern "C" {
+
+size_t mg_ho_workspace_bytes(int n, int order) {
+    HoPlan P;
+    Carver cv(nullptr);
+    if (ho_plan(n, 1.0, order, cv, nullptr, P)) return 0;
+    return cv.off;
+}
+
+int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, const mg_opts* o, mg_stats* stats,
+                      void* ws, size_t ws_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!o) return fail(MG_EINVAL, "options are NULL");
+    if (!f || !u) return fail(MG_EINVAL, "f or u is NULL");
+    if (o->max_cycles < 0) return fail(MG_EINVAL, "max_cycles < 0");
+    if (o->prec != MG_FP64) return fail(MG_EINVAL, "the higher-order solve runs in FP64 only");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 64) return fail(MG_EINVAL, "nu1/nu2 out of range");
+    if (o->flags & ~(MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES)) return fail(MG_EINVAL, "unknown flags");
+    HoPlan P;
+    Carver size_cv(nullptr);
+    int rc = ho_plan(n, h, order, size_cv, u, P);
+    if (rc) return rc;
+    if (!ws || ws_bytes < size_cv.off) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(size_cv.off));
+    if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    Carver cv(ws);
+    ho_plan(n, h, order, cv, u, P);
+    (void)hipGetLastError();
+
+    const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
+    const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
+    const int lg = P.lg;
+    const double cells = (double)((size_t)1 << (3 * lg));
+    mg_stats S;
+    std::memset(&S, 0, sizeof(S));
+    for (double& v : S.res_hist) v = NAN;
+    launch_ho_sum(f, lg, P.part, P.scal + 0, st);                          // composite mean of f ...
+    launch_ho_sub(f, P.scal + 0, P.f[0], lg, P.part, P.scal + 1, st);      // ... removed, and |f|^2
+    if (!guess) launch_ho_fill(P.u[0], lg, 0.0, st);
+    double fnorm2 = 0.0;
+    if (!fixed) {
+        double fs[2];
+        if ((rc = ho_read(P.scal, 2, fs, st))) return rc;
+        S.f_mean_removed = fs[0] / cells;
+        fnorm2 = fs[1];
+        if (!std::isfinite(fs[0]) || !std::isfinite(fs[1])) {
+            S.rel_res = NAN;
+            if (stats) *stats = S;
+            return fail(MG_EDIVERGED, "right-hand side contains NaN or Inf");
+        }
+    }
+    long long upc = 0;
+    for (int l = 0; l < lg; ++l) upc += (long long)(o->nu1 + o->nu2) << (3 * (lg - l));
+    double rel = NAN, prev = INFINITY;
+    int grow = 0, status = MG_ENOCONV, cycles = 0;
+    auto check = [&]() -> int {
+        double r2;
+        launch_ho_rnorm(P.u[0], P.f[0], lg, h, order, P.part, P.scal + 2, st);
+        if (int e = ho_read(P.scal + 2, 1, &r2, st)) return e;
+        rel = fnorm2 > 0 ? std::sqrt(r2 / fnorm2) : 0.0;
+        if (cycles >= 1 && cycles <= 64) S.res_hist[cycles - 1] = rel;
+        if (!std::isfinite(rel)) return MG_EDIVERGED;
+        grow = rel > prev ? grow + 1 : 0;
+        prev = rel;
+        if (grow >= 3) return MG_EDIVERGED;
+        return rel <= o->tol ? MG_OK : 1;
+    };
+    if (guess && !fixed) {
+        const int c = check();
+        if (c == MG_OK) status = MG_OK;
+        else if (c == MG_EHIP) return c;
+    }
+    while (status != MG_OK && cycles < o->max_cycles) {
+        ho_vcycle(P, o->nu1, o->nu2, st);
+        ++cycles;
+        S.cell_updates += upc;
+        if (fixed) continue;
+        const int c = check();
+        if (c == MG_OK) status = MG_OK;
+        else if (c == MG_EHIP) return c;
+        else if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+    }
+    if (fixed) status = MG_OK;
+    launch_ho_sum(P.u[0], lg, P.part, P.scal + 3, st);                     // zero-mean gauge of u
+    launch_ho_sub(P.u[0], P.scal + 3, P.u[0], lg, P.part, P.scal + 4, st);
+    MG_HIP(hipGetLastError());
+    S.cycles = cycles;
+    S.rel_res = fixed ? NAN : rel;
+    if (stats) *stats = S;
+    if (status == MG_ENOCONV) return fail(MG_ENOCONV, "no convergence within max_cycles");
+    if (status == MG_EDIVERGED) return fail(MG_EDIVERGED, "residual diverged");
+    return MG_OK;
+}
+
+}  // extern "C"
+
 extern "C" {
 
 const char* mg_last_error(void) { return g_err.c_str(); }

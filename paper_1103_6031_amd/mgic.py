@@ -65,6 +65,9 @@ _sig = {
                                       ctypes.POINTER(mg_stats), _P, _sz, _P]),
     "mg_solve_hierarchy": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.POINTER(mg_opts),
                                           ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_ho_workspace_bytes": (_sz, [ctypes.c_int, ctypes.c_int]),
+    "mg_solve_level_ho": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P,
+                                         ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
     "mg_residual_hierarchy": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _PP,
                                              ctypes.POINTER(ctypes.c_double), _P, _sz, _P]),
     "lpt_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier), ctypes.c_int]),
@@ -217,6 +220,32 @@ def mg_solve_level(f, h, u=None, opts=None, workspace=None, stream=None, check=T
     st = mg_stats()
     rc = _lib.mg_solve_level(n, h, _dev(f, "f"), _dev(u, "u"), ctypes.byref(o), ctypes.byref(st),
                              ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream))
+    if check:
+        _check(rc, st.to_dict())
+    return u, st.to_dict()
+
+
+def mg_ho_workspace_bytes(n: int, order: int) -> int:
+    need = _lib.mg_ho_workspace_bytes(int(n), int(order))
+    if need == 0:
+        raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
+    return need
+
+
+def mg_solve_level_ho(f, h, order, u=None, opts=None, workspace=None, stream=None, check=True):
+    """Periodic solve of L_order u = f - mean(f) with the order-2/4/6 Laplacian.  Returns (u, stats dict)."""
+    n = f.shape[0]
+    if f.dim() != 3 or tuple(f.shape) != (n, n, n):
+        raise ValueError("f must be an n^3 cube")
+    o = opts or make_opts()
+    if u is None:
+        u = torch.empty_like(f)
+    if tuple(u.shape) != tuple(f.shape):
+        raise ValueError("u must have the shape of f")
+    ws = _ws(workspace, mg_ho_workspace_bytes(n, order))
+    st = mg_stats()
+    rc = _lib.mg_solve_level_ho(n, h, int(order), _dev(f, "f"), _dev(u, "u"), ctypes.byref(o), ctypes.byref(st),
+                                ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream))
     if check:
         _check(rc, st.to_dict())
     return u, st.to_dict()

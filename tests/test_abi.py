@@ -116,3 +116,31 @@ def test_lla_validates_its_arguments_before_any_device_work():
     assert rc == mgic.MG_EINVAL and b"workspace" in lib.mg_last_error()
     H1 = mgic.Hier(1, 1.0).c_struct()
     assert lib.lpt_lla_density(ctypes.byref(H1), good, None, one, ctypes.c_void_p(256), 1 << 20, None) == mgic.MG_EINVAL
+
+
+def test_higher_order_solve_validates_its_arguments_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    lib = mgic._lib
+    assert lib.mg_ho_workspace_bytes(64, 6) > 2 * 64 ** 3 * 8
+    assert lib.mg_ho_workspace_bytes(64, 4) == lib.mg_ho_workspace_bytes(64, 6)
+    for n, order in ((24, 4), (1, 4), (2048, 4), (64, 3), (64, 8), (0, 2)):
+        assert lib.mg_ho_workspace_bytes(n, order) == 0
+    with pytest.raises(mgic.MGError):
+        mgic.mg_ho_workspace_bytes(48, 6)
+    st = mgic.mg_stats()
+    ws = ctypes.c_void_p(256)
+    big = lib.mg_ho_workspace_bytes(16, 4)
+    p = ctypes.c_void_p(16)
+    for o, n, order, h in ((mgic.make_opts(prec="mixed"), 16, 4, 1.0),   # FP64 only
+                           (mgic.make_opts(), 16, 5, 1.0),
+                           (mgic.make_opts(), 12, 4, 1.0),
+                           (mgic.make_opts(), 16, 4, -1.0),
+                           (mgic.make_opts(nu1=-1), 16, 4, 1.0),
+                           (mgic.make_opts(max_cycles=-1), 16, 4, 1.0)):
+        assert lib.mg_solve_level_ho(n, h, order, p, p, ctypes.byref(o), ctypes.byref(st), ws, big, None) == mgic.MG_EINVAL
+    o = mgic.make_opts()
+    assert lib.mg_solve_level_ho(16, 1.0, 4, None, p, ctypes.byref(o), ctypes.byref(st), ws, big, None) == mgic.MG_EINVAL
+    rc = lib.mg_solve_level_ho(16, 1.0, 4, p, p, ctypes.byref(o), ctypes.byref(st), ws, big - 8, None)
+    assert rc == mgic.MG_EINVAL and b"workspace" in lib.mg_last_error()
+    rc = lib.mg_solve_level_ho(16, 1.0, 4, p, p, ctypes.byref(o), ctypes.byref(st), ctypes.c_void_p(257), big, None)
+    assert rc == mgic.MG_EINVAL and b"aligned" in lib.mg_last_error()

@@ -1,0 +1,120 @@
+"""Higher-order periodic solve (Table 1 Laplacians of order 2, 4, 6) on the GPU against the oracle.
+
+Bar: after a fixed number of V-cycles the GPU iterate equals the oracle's within 1e-12 of its
+largest value (the two differ in summation order only); converged solves are within 1e-9 of the
+exact discrete solution (FFT with the symbols Table 1 prints), and at full size the oracle
+recomputes the GPU solution's relative residual.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import needs_gpu, note, to_dev, to_host
+from oracle import highorder as ho
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_1103_6031_amd import mgic
+    return mgic
+
+
+def _rhs(N, seed, mean=0.3):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((N, N, N)) + mean
+
+
+# 2 and 4 are narrower than the 6th-order stencil (offsets wrap onto the cell itself)
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32])
+@pytest.mark.parametrize("cycles", [1, 3])
+def test_fixed_cycles_match_the_oracle(mg, order, N, cycles):
+    f = _rhs(N, 1000 * order + 10 * N + cycles)
+    h = 50.0 / N
+    note("highorder fixed order=%d N=%d cycles=%d" % (order, N, cycles))
+    ug, st = mg.mg_solve_level_ho(to_dev(f), h, order,
+                                  opts=mg.make_opts(max_cycles=cycles, fixed_cycles=True))
+    uo, info = ho.solve_level(f, h, order, max_cycles=cycles, fixed_cycles=True)
+    u = to_host(ug)
+    assert st["cycles"] == cycles
+    assert np.max(np.abs(u - uo)) <= 1e-12 * np.max(np.abs(uo))
+    assert abs(float(np.mean(u))) <= 1e-13 * np.max(np.abs(uo))
+
+
+@pytest.mark.parametrize("order", [4, 6])
+@pytest.mark.parametrize("nu", [(1, 1), (3, 0), (0, 2)])
+def test_sweep_counts_match_the_oracle(mg, order, nu):
+    N, h = 16, 1.0 / 16
+    f = _rhs(N, 7 + order)
+    note("highorder nu=%s order=%d" % (nu, order))
+    ug, _ = mg.mg_solve_level_ho(to_dev(f), h, order,
+                                 opts=mg.make_opts(max_cycles=2, fixed_cycles=True, nu1=nu[0], nu2=nu[1]))
+    uo, _ = ho.solve_level(f, h, order, max_cycles=2, fixed_cycles=True, nu1=nu[0], nu2=nu[1])
+    assert np.max(np.abs(to_host(ug) - uo)) <= 1e-12 * np.max(np.abs(uo))
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("N", [32, 64])
+def test_converged_solve_reaches_the_exact_solution(mg, order, N):
+    f = _rhs(N, 31 * order + N, mean=-1.25)
+    h = 100.0 / N
+    note("highorder converge order=%d N=%d" % (order, N))
+    ug, st = mg.mg_solve_level_ho(to_dev(f), h, order, opts=mg.make_opts(tol=1e-11))
+    exact = ho.fft_solve(f - f.mean(), h, order)
+    u = to_host(ug)
+    assert st["rel_res"] <= 1e-11
+    assert abs(st["f_mean"] - float(np.mean(f))) <= 1e-14
+    assert np.max(np.abs(u - exact)) <= 1e-9 * np.max(np.abs(exact))
+    # the residual history is the oracle's: same cycle count, and each entry up to the rounding
+    # floor of the residual (about 1e-16 of u times the stencil's 12 / h^2, a few 1e-14 of f here)
+    if N == 32:
+        _, info = ho.solve_level(f, h, order, tol=1e-11)
+        assert st["cycles"] == info["cycles"]
+        assert np.allclose(st["history"], info["history"], rtol=1e-2, atol=1e-13)
+    hist = st["history"]
+    assert all(hist[c + 1] <= 0.1 * hist[c] for c in range(len(hist) - 1))
+
+
+def test_initial_guess_and_errors(mg):
+    N, h, order = 16, 1.0 / 16, 6
+    f = _rhs(N, 5)
+    exact = ho.fft_solve(f - f.mean(), h, order)
+    note("highorder guess and errors")
+    # the exact solution as the guess: no cycle runs, and u keeps it
+    u = to_dev(exact)
+    _, st = mg.mg_solve_level_ho(to_dev(f), h, order, u=u, opts=mg.make_opts(tol=1e-10, initial_guess=True))
+    assert st["cycles"] == 0 and np.max(np.abs(to_host(u) - exact)) <= 1e-13 * np.max(np.abs(exact))
+    # a rough guess converges to the same solution
+    u = to_dev(exact + np.random.default_rng(2).standard_normal(exact.shape))
+    _, st = mg.mg_solve_level_ho(to_dev(f), h, order, u=u, opts=mg.make_opts(tol=1e-11, initial_guess=True))
+    assert np.max(np.abs(to_host(u) - exact)) <= 1e-9 * np.max(np.abs(exact))
+    with pytest.raises(mg.MGError) as e:
+        mg.mg_solve_level_ho(to_dev(f), h, order, opts=mg.make_opts(tol=1e-14, max_cycles=1))
+    assert e.value.code == mg.MG_ENOCONV
+    bad = f.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(mg.MGError) as e:
+        mg.mg_solve_level_ho(to_dev(bad), h, order)
+    assert e.value.code == mg.MG_EDIVERGED
+    with pytest.raises(ValueError):
+        mg.mg_solve_level_ho(to_dev(np.zeros((16, 16, 8))), h, order)
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_full_size_256(mg, order):
+    # the bench workload: 256^3, tol 1e-10; the oracle recomputes the residual and the exact solve
+    N = 256
+    h = 100.0 / N
+    f = _rhs(N, 256 + order, mean=0.0)
+    note("highorder 256^3 order=%d" % order)
+    ug, st = mg.mg_solve_level_ho(to_dev(f), h, order, opts=mg.make_opts(tol=1e-10))
+    u = to_host(ug)
+    fz = f - f.mean()
+    rel = np.sqrt(np.mean(np.square(ho.residual(u, fz, h, order)))) / np.sqrt(np.mean(np.square(fz)))
+    # rounding of u (1e-16 relative) alone moves the residual by about 2e-12 of f at 256^3
+    assert rel <= 1.1e-10 and abs(rel - st["rel_res"]) <= 0.05 * rel + 5e-12
+    exact = ho.fft_solve(fz, h, order)
+    assert np.max(np.abs(u - exact)) <= 1e-8 * np.max(np.abs(exact))
+    assert st["cycles"] <= 12
