@@ -52,15 +52,65 @@ __device__ __forceinline__ double ho_off(const double* __restrict__ u, unsigned 
     return acc;
 }
 
+// Block order: consecutive blocks go to the 8 XCDs in turn.  Blocks that hold x-neighbouring
+// planes are a multiple of 8 apart and already share an XCD's L2; the y-neighbour rows of a
+// block's edge rows belong to the next blocks.  Within groups of 8k blocks, k consecutive ones
+// go to one XCD (k = 8 from 128 blocks per plane, 4 from 32; the order is unchanged below).
+__device__ __forceinline__ unsigned ho_xcd_group(unsigned b, int lgbpp) {
+    if (lgbpp < 5) return b;
+    const int lk = lgbpp >= 7 ? 3 : 2;
+    const unsigned G = 8u << lk;
+    return (b & ~(G - 1)) | ((b & 7u) << lk) | ((b >> 3) & ((1u << lk) - 1));
+}
+
+// one thread per pair of z-neighbours (2p, 2p + 1): exactly one of them has the colour, so every
+// lane computes one update; the pair is read and written as one 16-byte access
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_ho_half(const double* __restrict__ in, double* __restrict__ out,
                                                     const double* __restrict__ f, int lg, double h2, int colour) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (1u << (3 * lg))) return;
-    const unsigned m = (1u << lg) - 1, z = t & m, y = (t >> lg) & m, x = t >> (2 * lg);
-    double v = in[t];
-    if (((x + y + z) & 1u) == (unsigned)colour) v = (h2 * f[t] - ho_off<R>(in, x, y, z, lg, m)) / (3.0 * HoW<R>::w0);
-    out[t] = v;
+    const unsigned p = ho_xcd_group(blockIdx.x, 2 * lg - 9) * blockDim.x + threadIdx.x;
+    if (p >= (1u << (3 * lg - 1))) return;
+    const unsigned t0 = 2 * p, m = (1u << lg) - 1, z0 = t0 & m, y = (t0 >> lg) & m, x = t0 >> (2 * lg);
+    const unsigned q = (x + y + (unsigned)colour) & 1u;   // (x + y + z0 + q) & 1 == colour
+    const double2 cur = *(const double2*)(in + t0);
+    const double v = (h2 * f[t0 + q] - ho_off<R>(in, x, y, z0 + q, lg, m)) / (3.0 * HoW<R>::w0);
+    *(double2*)(out + t0) = q ? make_double2(cur.x, v) : make_double2(v, cur.y);
+}
+
+// r = f - L u for the two cells (x, y, z0) and (x, y, z0 + 1), z0 even, from 16-byte loads: the
+// pairs of the x- and y-neighbour rows hold both cells' neighbours, and one run of pairs from
+// z0 - 2J to z0 + 2J + 1 (J = ceil(R / 2)) holds their z-neighbours.  Same arithmetic as ho_off.
+template <int R>
+__device__ __forceinline__ double2 ho_pair_resid(const double* __restrict__ u, const double* __restrict__ f,
+                                                 unsigned x, unsigned y, unsigned z0, int lg, unsigned m,
+                                                 double h2, double2* own) {
+    constexpr int J = (R + 1) / 2;
+    double zr[4 * J + 2];
+#pragma unroll
+    for (int j = -J; j <= J; ++j) {
+        const double2 v = *(const double2*)(u + ho_idx(x, y, (z0 + 2 * j) & m, lg));
+        zr[2 * (j + J)] = v.x;
+        zr[2 * (j + J) + 1] = v.y;
+    }
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 1; s <= R; ++s) {
+        const double2 xm = *(const double2*)(u + ho_idx((x - s) & m, y, z0, lg));
+        const double2 xp = *(const double2*)(u + ho_idx((x + s) & m, y, z0, lg));
+        const double2 ym = *(const double2*)(u + ho_idx(x, (y - s) & m, z0, lg));
+        const double2 yp = *(const double2*)(u + ho_idx(x, (y + s) & m, z0, lg));
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double px = (c ? xm.y : xm.x) + (c ? xp.y : xp.x);
+            const double py = (c ? ym.y : ym.x) + (c ? yp.y : yp.x);
+            const double pz = zr[2 * J + c - s] + zr[2 * J + c + s];
+            acc[c] += ho_w<R>(s) * ((px + py) + pz);
+        }
+    }
+    const double2 fv = *(const double2*)(f + ho_idx(x, y, z0, lg));
+    const double u0 = zr[2 * J], u1 = zr[2 * J + 1];
+    *own = make_double2(u0, u1);
+    return make_double2(fv.x - (acc[0] + 3.0 * HoW<R>::w0 * u0) / h2, fv.y - (acc[1] + 3.0 * HoW<R>::w0 * u1) / h2);
 }
 
 // steps 3-5 for one coarse cell: the mean of the 8 children's residuals and of their values
@@ -77,14 +127,14 @@ __global__ __launch_bounds__(kBlock) void k_ho_resid_restrict(const double* __re
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const unsigned x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + c, i = ho_idx(x, y, z, lg);
-                const double ui = u[i];
-                rs += f[i] - (ho_off<R>(u, x, y, z, lg, m) + 3.0 * HoW<R>::w0 * ui) / h2;
-                us += ui;
-            }
+        for (int b = 0; b < 2; ++b) {   // children (2X + a, 2Y + b, 2Z + c), c = 0, 1
+            double2 uv;
+            const double2 r = ho_pair_resid<R>(u, f, 2 * X + a, 2 * Y + b, 2 * Z, lg, m, h2, &uv);
+            rs += r.x;
+            us += uv.x;
+            rs += r.y;
+            us += uv.y;
+        }
     const double um = us * 0.125;
     uc[t] = um;
     uold[t] = um;
@@ -136,13 +186,15 @@ __global__ __launch_bounds__(kBlock) void k_ho_psum(const double* __restrict__ a
                                                     int lg, double h2, double* __restrict__ part) {
     const unsigned n = 1u << (3 * lg), m = (1u << lg) - 1;
     double acc = 0.0;
-    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        if (MODE == 0) {
-            acc += a[t];
-        } else {
-            const unsigned z = t & m, y = (t >> lg) & m, x = t >> (2 * lg);
-            const double r = f[t] - (ho_off<R>(a, x, y, z, lg, m) + 3.0 * HoW<R>::w0 * a[t]) / h2;
-            acc += r * r;
+    if (MODE == 0) {
+        for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) acc += a[t];
+    } else {   // pairs of z-neighbours (n is even)
+        for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < n / 2; p += gridDim.x * blockDim.x) {
+            const unsigned t = 2 * p, z = t & m, y = (t >> lg) & m, x = t >> (2 * lg);
+            double2 uv;
+            const double2 r = ho_pair_resid<R>(a, f, x, y, z, lg, m, h2, &uv);
+            acc += r.x * r.x;
+            acc += r.y * r.y;
         }
     }
     const double s = ho_block_sum(acc);
@@ -189,7 +241,7 @@ int ho_parts(int lg) {   // blocks of the reductions: fixed by the size, at most
 
 void launch_ho_half(const double* in, double* out, const double* f, int lg, double h, int order, int colour,
                     hipStream_t st, hipEvent_t ea, hipEvent_t eb) {
-    const int g = grid_for((size_t)1 << (3 * lg));
+    const int g = grid_for((size_t)1 << (3 * lg - 1));   // pairs of cells (lg >= 1)
     if (ea) (void)hipEventRecord(ea, st);
     HO_DISPATCH(order, k_ho_half, g, in, out, f, lg, h * h, colour);
     if (eb) (void)hipEventRecord(eb, st);

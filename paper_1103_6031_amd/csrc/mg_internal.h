@@ -361,7 +361,7 @@ template <class T> void launch_b_zero(const BSeg* segs, int nseg, unsigned grid,
 
 // periodic FAS with the order-2/4/6 Laplacians of Table 1 (k_highorder.hip): n = 2^lg per axis,
 // natural order, FP64.  The half-sweep is out of place (reads in, writes every cell of out).
-constexpr int kHoParts = 1024;   // partial sums of the reductions, at most
+constexpr int kHoParts = 8192;   // partial sums of the reductions, at most
 void launch_ho_half(const double* in, double* out, const double* f, int lg, double h, int order, int colour,
                     hipStream_t st, hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
 void launch_ho_resid_restrict(const double* u, const double* f, double* uc, double* uold, double* rc, int lgc,
