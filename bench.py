@@ -227,7 +227,8 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
     per cell it reads the iterate and f and writes every cell, 24 B (the colour-split in-place
     half-sweep of the 7-point path moves 12 B per cell, its updated half only)."""
     n = ft.shape[0]
-    res = dict(workload="periodic %d^3 BBKS, FP64 V(2,2) with the order-4 / order-6 Laplacian, tol %g" % (n, tol))
+    res = dict(workload="periodic %d^3 BBKS, V(2,2) with the order-4 / order-6 Laplacian, tol %g; FP64, and mixed "
+                        "(FP32 inner cycles inside FP64 defect correction)" % (n, tol))
     for order in (4, 6):
         o = mg.make_opts(tol=tol, max_cycles=40)
         ws = mg.Workspace(mg.mg_ho_workspace_bytes(n, order))
@@ -255,6 +256,20 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
                                       unit="Mcell-updates/s", half_sweep_avg_us=round(us, 2),
                                       half_sweep_launches=kn,
                                       half_sweep_gbs=round(kb / max(kn, 1) / (us * 1e-6) / 1e9, 1) if kn else None)
+        om = mg.make_opts(tol=tol, max_cycles=60, prec="mixed")
+        tm = []
+        for i in range(reps + 1):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, sm = mg.mg_solve_level_ho(ft, h, order, u=u, opts=om, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if i >= 1:
+                tm.append(e0.elapsed_time(e1))
+        msm = sorted(tm)[len(tm) // 2]
+        res["order%d" % order]["mixed"] = dict(ms_per_solve=round(msm, 3), cycles=sm["cycles"], rel_res=sm["rel_res"],
+                                               value=round(sm["cell_updates"] / (msm * 1e-3) / 1e6, 1))
     return res
 
 

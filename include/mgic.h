@@ -119,11 +119,13 @@ int mg_solve_hierarchy(const mg_hier* hier, const double* const* f, double* cons
  * the same FAS V(nu1, nu2) cycle.  With a stencil wider than one cell, red-black is no longer a
  * 2-colouring; each half-sweep updates its colour from the values before it (Jacobi within the
  * colour), so the result does not depend on the update order.
- * n = 2^k with 2 <= n <= 1024 (coarsened to one cell); order = 2, 4 or 6; FP64 only
- * (opts->prec = MG_FP64; opts->inner is ignored).  f and u: n^3 device doubles, [x][y][z], z
+ * n = 2^k with 2 <= n <= 1024 (coarsened to one cell); order = 2, 4 or 6; precision FP64
+ * (opts->prec = MG_FP64), or mixed (MG_MIXED: FP32 V-cycles, opts->inner per FP64 correction, default 3,
+ * inside FP64 defect correction with the same FP64 stopping test).  f and u: n^3 device doubles, [x][y][z], z
  * contiguous; f is read only; u receives the zero-mean solution of L u = f - mean(f) and is read
  * only with MG_USE_INITIAL_GUESS.  stats and the stopping test as for mg_solve_level.
- * Workspace: mg_ho_workspace_bytes(n, order) bytes, 256-byte aligned (about 2.3 n^3 doubles).
+ * Workspace: mg_ho_workspace_bytes(n, order) bytes, 256-byte aligned (about 4.1 n^3 doubles,
+ * the FP32 arrays of the mixed path included whatever the precision).
  * Errors: MG_EINVAL (size, order, h, options, workspace), MG_ENOCONV, MG_EDIVERGED, MG_EHIP. */
 size_t mg_ho_workspace_bytes(int n, int order);   /* 0 for an invalid n or order */
 int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, const mg_opts* opts,

@@ -11,13 +11,27 @@
 // half-sweeps return the iterate to the buffer it started in.  The update solves the cell's own
 // equation for its centre value: u <- (h^2 f - sum_s w_s sum_axes (u[i-s] + u[i+s])) / (3 w_0).
 //
-// FP64 throughout; the arithmetic is the oracle's up to summation order.
+// The V-cycle kernels take the element type T: FP64, or FP32 for the inner cycles of the
+// mixed-precision solve, whose FP64 residual (k_ho_resid32) and correction (k_ho_add32) are
+// separate kernels.  The FP64 arithmetic is the oracle's up to summation order.
 
 #include "mg_internal.h"
 
 namespace mgic {
 
 namespace {
+
+template <class T> struct HoV2;
+template <> struct HoV2<double> { using type = double2; };
+template <> struct HoV2<float> { using type = float2; };
+template <class T> using v2_t = typename HoV2<T>::type;
+template <class T>
+__device__ __forceinline__ v2_t<T> mk2(T a, T b) {
+    v2_t<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
 
 template <int R> struct HoW;
 template <> struct HoW<1> { static constexpr double w0 = -2.0, w1 = 1.0, w2 = 0.0, w3 = 0.0; };
@@ -38,16 +52,16 @@ __device__ __forceinline__ unsigned ho_idx(unsigned x, unsigned y, unsigned z, i
 }
 
 // sum_{s=1..R} w_s (((x-s) + (x+s)) + ((y-s) + (y+s))) + ((z-s) + (z+s))), periodic
-template <int R>
-__device__ __forceinline__ double ho_off(const double* __restrict__ u, unsigned x, unsigned y, unsigned z, int lg,
-                                         unsigned m) {
-    double acc = 0.0;
+template <int R, class T>
+__device__ __forceinline__ T ho_off(const T* __restrict__ u, unsigned x, unsigned y, unsigned z, int lg,
+                                    unsigned m) {
+    T acc = 0;
 #pragma unroll
     for (int s = 1; s <= R; ++s) {
-        const double px = u[ho_idx((x - s) & m, y, z, lg)] + u[ho_idx((x + s) & m, y, z, lg)];
-        const double py = u[ho_idx(x, (y - s) & m, z, lg)] + u[ho_idx(x, (y + s) & m, z, lg)];
-        const double pz = u[ho_idx(x, y, (z - s) & m, lg)] + u[ho_idx(x, y, (z + s) & m, lg)];
-        acc += ho_w<R>(s) * ((px + py) + pz);
+        const T px = u[ho_idx((x - s) & m, y, z, lg)] + u[ho_idx((x + s) & m, y, z, lg)];
+        const T py = u[ho_idx(x, (y - s) & m, z, lg)] + u[ho_idx(x, (y + s) & m, z, lg)];
+        const T pz = u[ho_idx(x, y, (z - s) & m, lg)] + u[ho_idx(x, y, (z + s) & m, lg)];
+        acc += (T)ho_w<R>(s) * ((px + py) + pz);
     }
     return acc;
 }
@@ -65,95 +79,96 @@ __device__ __forceinline__ unsigned ho_xcd_group(unsigned b, int lgbpp) {
 
 // one thread per pair of z-neighbours (2p, 2p + 1): exactly one of them has the colour, so every
 // lane computes one update; the pair is read and written as one 16-byte access
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_ho_half(const double* __restrict__ in, double* __restrict__ out,
-                                                    const double* __restrict__ f, int lg, double h2, int colour) {
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_ho_half(const T* __restrict__ in, T* __restrict__ out,
+                                                    const T* __restrict__ f, int lg, T h2, int colour) {
     const unsigned p = ho_xcd_group(blockIdx.x, 2 * lg - 9) * blockDim.x + threadIdx.x;
     if (p >= (1u << (3 * lg - 1))) return;
     const unsigned t0 = 2 * p, m = (1u << lg) - 1, z0 = t0 & m, y = (t0 >> lg) & m, x = t0 >> (2 * lg);
     const unsigned q = (x + y + (unsigned)colour) & 1u;   // (x + y + z0 + q) & 1 == colour
-    const double2 cur = *(const double2*)(in + t0);
-    const double v = (h2 * f[t0 + q] - ho_off<R>(in, x, y, z0 + q, lg, m)) / (3.0 * HoW<R>::w0);
-    *(double2*)(out + t0) = q ? make_double2(cur.x, v) : make_double2(v, cur.y);
+    const v2_t<T> cur = *(const v2_t<T>*)(in + t0);
+    const T v = (h2 * f[t0 + q] - ho_off<R>(in, x, y, z0 + q, lg, m)) / ((T)3 * (T)HoW<R>::w0);
+    *(v2_t<T>*)(out + t0) = q ? mk2<T>(cur.x, v) : mk2<T>(v, cur.y);
 }
 
 // r = f - L u for the two cells (x, y, z0) and (x, y, z0 + 1), z0 even, from 16-byte loads: the
 // pairs of the x- and y-neighbour rows hold both cells' neighbours, and one run of pairs from
 // z0 - 2J to z0 + 2J + 1 (J = ceil(R / 2)) holds their z-neighbours.  Same arithmetic as ho_off.
-template <int R>
-__device__ __forceinline__ double2 ho_pair_resid(const double* __restrict__ u, const double* __restrict__ f,
+template <int R, class T>
+__device__ __forceinline__ v2_t<T> ho_pair_resid(const T* __restrict__ u, const T* __restrict__ f,
                                                  unsigned x, unsigned y, unsigned z0, int lg, unsigned m,
-                                                 double h2, double2* own) {
+                                                 T h2, v2_t<T>* own) {
     constexpr int J = (R + 1) / 2;
-    double zr[4 * J + 2];
+    T zr[4 * J + 2];
 #pragma unroll
     for (int j = -J; j <= J; ++j) {
-        const double2 v = *(const double2*)(u + ho_idx(x, y, (z0 + 2 * j) & m, lg));
+        const v2_t<T> v = *(const v2_t<T>*)(u + ho_idx(x, y, (z0 + 2 * j) & m, lg));
         zr[2 * (j + J)] = v.x;
         zr[2 * (j + J) + 1] = v.y;
     }
-    double acc[2] = {0.0, 0.0};
+    T acc[2] = {0, 0};
 #pragma unroll
     for (int s = 1; s <= R; ++s) {
-        const double2 xm = *(const double2*)(u + ho_idx((x - s) & m, y, z0, lg));
-        const double2 xp = *(const double2*)(u + ho_idx((x + s) & m, y, z0, lg));
-        const double2 ym = *(const double2*)(u + ho_idx(x, (y - s) & m, z0, lg));
-        const double2 yp = *(const double2*)(u + ho_idx(x, (y + s) & m, z0, lg));
+        const v2_t<T> xm = *(const v2_t<T>*)(u + ho_idx((x - s) & m, y, z0, lg));
+        const v2_t<T> xp = *(const v2_t<T>*)(u + ho_idx((x + s) & m, y, z0, lg));
+        const v2_t<T> ym = *(const v2_t<T>*)(u + ho_idx(x, (y - s) & m, z0, lg));
+        const v2_t<T> yp = *(const v2_t<T>*)(u + ho_idx(x, (y + s) & m, z0, lg));
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const double px = (c ? xm.y : xm.x) + (c ? xp.y : xp.x);
-            const double py = (c ? ym.y : ym.x) + (c ? yp.y : yp.x);
-            const double pz = zr[2 * J + c - s] + zr[2 * J + c + s];
-            acc[c] += ho_w<R>(s) * ((px + py) + pz);
+            const T px = (c ? xm.y : xm.x) + (c ? xp.y : xp.x);
+            const T py = (c ? ym.y : ym.x) + (c ? yp.y : yp.x);
+            const T pz = zr[2 * J + c - s] + zr[2 * J + c + s];
+            acc[c] += (T)ho_w<R>(s) * ((px + py) + pz);
         }
     }
-    const double2 fv = *(const double2*)(f + ho_idx(x, y, z0, lg));
-    const double u0 = zr[2 * J], u1 = zr[2 * J + 1];
-    *own = make_double2(u0, u1);
-    return make_double2(fv.x - (acc[0] + 3.0 * HoW<R>::w0 * u0) / h2, fv.y - (acc[1] + 3.0 * HoW<R>::w0 * u1) / h2);
+    const v2_t<T> fv = *(const v2_t<T>*)(f + ho_idx(x, y, z0, lg));
+    const T u0 = zr[2 * J], u1 = zr[2 * J + 1];
+    const T w0x3 = (T)3 * (T)HoW<R>::w0;
+    *own = mk2<T>(u0, u1);
+    return mk2<T>(fv.x - (acc[0] + w0x3 * u0) / h2, fv.y - (acc[1] + w0x3 * u1) / h2);
 }
 
 // steps 3-5 for one coarse cell: the mean of the 8 children's residuals and of their values
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_ho_resid_restrict(const double* __restrict__ u, const double* __restrict__ f,
-                                                              double* __restrict__ uc, double* __restrict__ uold,
-                                                              double* __restrict__ rc, int lgc, double h2) {
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_ho_resid_restrict(const T* __restrict__ u, const T* __restrict__ f,
+                                                              T* __restrict__ uc, T* __restrict__ uold,
+                                                              T* __restrict__ rc, int lgc, T h2) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (1u << (3 * lgc))) return;
     const int lg = lgc + 1;
     const unsigned mc = (1u << lgc) - 1, m = (1u << lg) - 1;
     const unsigned Z = t & mc, Y = (t >> lgc) & mc, X = t >> (2 * lgc);
-    double rs = 0.0, us = 0.0;
+    T rs = 0, us = 0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {   // children (2X + a, 2Y + b, 2Z + c), c = 0, 1
-            double2 uv;
-            const double2 r = ho_pair_resid<R>(u, f, 2 * X + a, 2 * Y + b, 2 * Z, lg, m, h2, &uv);
+            v2_t<T> uv;
+            const v2_t<T> r = ho_pair_resid<R, T>(u, f, 2 * X + a, 2 * Y + b, 2 * Z, lg, m, h2, &uv);
             rs += r.x;
             us += uv.x;
             rs += r.y;
             us += uv.y;
         }
-    const double um = us * 0.125;
+    const T um = us * (T)0.125;
     uc[t] = um;
     uold[t] = um;
-    rc[t] = rs * 0.125;
+    rc[t] = rs * (T)0.125;
 }
 
 // step 6: fc = rc + L uc, in place over rc
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_ho_fas(const double* __restrict__ uc, double* __restrict__ fc, int lgc,
-                                                   double h2) {
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_ho_fas(const T* __restrict__ uc, T* __restrict__ fc, int lgc, T h2) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (1u << (3 * lgc))) return;
     const unsigned m = (1u << lgc) - 1, z = t & m, y = (t >> lgc) & m, x = t >> (2 * lgc);
-    fc[t] = fc[t] + (ho_off<R>(uc, x, y, z, lgc, m) + 3.0 * HoW<R>::w0 * uc[t]) / h2;
+    fc[t] = fc[t] + (ho_off<R>(uc, x, y, z, lgc, m) + (T)3 * (T)HoW<R>::w0 * uc[t]) / h2;
 }
 
 // step 8: u += inject(uc - uold)
-__global__ __launch_bounds__(kBlock) void k_ho_prolong(double* __restrict__ u, const double* __restrict__ uc,
-                                                       const double* __restrict__ uold, int lg) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ho_prolong(T* __restrict__ u, const T* __restrict__ uc,
+                                                       const T* __restrict__ uold, int lg) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (1u << (3 * lg))) return;
     const int lgc = lg - 1;
@@ -162,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_ho_prolong(double* __restrict__ u, c
     u[t] = u[t] + (uc[p] - uold[p]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ho_fill(double* __restrict__ a, unsigned n, double v) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ho_fill(T* __restrict__ a, unsigned n, T v) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) a[t] = v;
 }
@@ -192,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_ho_psum(const double* __restrict__ a
         for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < n / 2; p += gridDim.x * blockDim.x) {
             const unsigned t = 2 * p, z = t & m, y = (t >> lg) & m, x = t >> (2 * lg);
             double2 uv;
-            const double2 r = ho_pair_resid<R>(a, f, x, y, z, lg, m, h2, &uv);
+            const double2 r = ho_pair_resid<R, double>(a, f, x, y, z, lg, m, h2, &uv);
             acc += r.x * r.x;
             acc += r.y * r.y;
         }
@@ -225,6 +241,31 @@ __global__ __launch_bounds__(kBlock) void k_ho_reduce(const double* __restrict__
     if (threadIdx.x == 0) out[0] = s;
 }
 
+// mixed precision: r32 = (float)(f - L u) in FP64, with the partial sums of r^2 (pairs of cells)
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_ho_resid32(const double* __restrict__ u, const double* __restrict__ f,
+                                                       float* __restrict__ r32, int lg, double h2,
+                                                       double* __restrict__ part) {
+    const unsigned n = 1u << (3 * lg), m = (1u << lg) - 1;
+    double acc = 0.0;
+    for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < n / 2; p += gridDim.x * blockDim.x) {
+        const unsigned t = 2 * p, z = t & m, y = (t >> lg) & m, x = t >> (2 * lg);
+        double2 uv;
+        const double2 r = ho_pair_resid<R, double>(u, f, x, y, z, lg, m, h2, &uv);
+        *(float2*)(r32 + t) = make_float2((float)r.x, (float)r.y);
+        acc += r.x * r.x;
+        acc += r.y * r.y;
+    }
+    const double s = ho_block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// mixed precision: u += e (the FP32 correction)
+__global__ __launch_bounds__(kBlock) void k_ho_add32(double* __restrict__ u, const float* __restrict__ e, int lg) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (1u << (3 * lg))) u[t] = u[t] + (double)e[t];
+}
+
 int ho_parts(int lg) {   // blocks of the reductions: fixed by the size, at most kHoParts
     const size_t n = (size_t)1 << (3 * lg);
     return grid_for(n, kBlock * 8, kHoParts);
@@ -232,37 +273,67 @@ int ho_parts(int lg) {   // blocks of the reductions: fixed by the size, at most
 
 }  // namespace
 
-#define HO_DISPATCH(order, KERNEL, GRID, ...)                                                  \
+#define HO_DISPATCH(order, KERNEL, T, GRID, ...)                                               \
     do {                                                                                       \
-        if ((order) == 2) KERNEL<1><<<(GRID), kBlock, 0, st>>>(__VA_ARGS__);                   \
-        else if ((order) == 4) KERNEL<2><<<(GRID), kBlock, 0, st>>>(__VA_ARGS__);              \
-        else KERNEL<3><<<(GRID), kBlock, 0, st>>>(__VA_ARGS__);                                \
+        if ((order) == 2) KERNEL<1, T><<<(GRID), kBlock, 0, st>>>(__VA_ARGS__);                \
+        else if ((order) == 4) KERNEL<2, T><<<(GRID), kBlock, 0, st>>>(__VA_ARGS__);           \
+        else KERNEL<3, T><<<(GRID), kBlock, 0, st>>>(__VA_ARGS__);                             \
     } while (0)
 
-void launch_ho_half(const double* in, double* out, const double* f, int lg, double h, int order, int colour,
-                    hipStream_t st, hipEvent_t ea, hipEvent_t eb) {
+template <class T>
+void launch_ho_half(const T* in, T* out, const T* f, int lg, double h, int order, int colour, hipStream_t st,
+                    hipEvent_t ea, hipEvent_t eb) {
     const int g = grid_for((size_t)1 << (3 * lg - 1));   // pairs of cells (lg >= 1)
     if (ea) (void)hipEventRecord(ea, st);
-    HO_DISPATCH(order, k_ho_half, g, in, out, f, lg, h * h, colour);
+    HO_DISPATCH(order, k_ho_half, T, g, in, out, f, lg, (T)(h * h), colour);
     if (eb) (void)hipEventRecord(eb, st);
 }
 
-void launch_ho_resid_restrict(const double* u, const double* f, double* uc, double* uold, double* rc, int lgc,
-                              double h, int order, hipStream_t st) {
-    HO_DISPATCH(order, k_ho_resid_restrict, grid_for((size_t)1 << (3 * lgc)), u, f, uc, uold, rc, lgc, h * h);
+template <class T>
+void launch_ho_resid_restrict(const T* u, const T* f, T* uc, T* uold, T* rc, int lgc, double h, int order,
+                              hipStream_t st) {
+    HO_DISPATCH(order, k_ho_resid_restrict, T, grid_for((size_t)1 << (3 * lgc)), u, f, uc, uold, rc, lgc,
+                (T)(h * h));
 }
 
-void launch_ho_fas(const double* uc, double* fc, int lgc, double hc, int order, hipStream_t st) {
-    HO_DISPATCH(order, k_ho_fas, grid_for((size_t)1 << (3 * lgc)), uc, fc, lgc, hc * hc);
+template <class T>
+void launch_ho_fas(const T* uc, T* fc, int lgc, double hc, int order, hipStream_t st) {
+    HO_DISPATCH(order, k_ho_fas, T, grid_for((size_t)1 << (3 * lgc)), uc, fc, lgc, (T)(hc * hc));
 }
 
-void launch_ho_prolong(double* u, const double* uc, const double* uold, int lg, hipStream_t st) {
-    k_ho_prolong<<<grid_for((size_t)1 << (3 * lg)), kBlock, 0, st>>>(u, uc, uold, lg);
+template <class T>
+void launch_ho_prolong(T* u, const T* uc, const T* uold, int lg, hipStream_t st) {
+    k_ho_prolong<T><<<grid_for((size_t)1 << (3 * lg)), kBlock, 0, st>>>(u, uc, uold, lg);
 }
 
-void launch_ho_fill(double* a, int lg, double v, hipStream_t st) {
+template <class T>
+void launch_ho_fill(T* a, int lg, T v, hipStream_t st) {
     const unsigned n = 1u << (3 * lg);
-    k_ho_fill<<<grid_for(n), kBlock, 0, st>>>(a, n, v);
+    k_ho_fill<T><<<grid_for(n), kBlock, 0, st>>>(a, n, v);
+}
+
+#define HO_INST(T)                                                                                          \
+    template void launch_ho_half<T>(const T*, T*, const T*, int, double, int, int, hipStream_t, hipEvent_t,    \
+                                    hipEvent_t);                                                            \
+    template void launch_ho_resid_restrict<T>(const T*, const T*, T*, T*, T*, int, double, int, hipStream_t); \
+    template void launch_ho_fas<T>(const T*, T*, int, double, int, hipStream_t);                              \
+    template void launch_ho_prolong<T>(T*, const T*, const T*, int, hipStream_t);                             \
+    template void launch_ho_fill<T>(T*, int, T, hipStream_t);
+HO_INST(double)
+HO_INST(float)
+
+void launch_ho_resid32(const double* u, const double* f, float* r32, int lg, double h, int order, double* part,
+                       double* out, hipStream_t st) {
+    const int nb = ho_parts(lg);
+    const double h2 = h * h;
+    if (order == 2) k_ho_resid32<1><<<nb, kBlock, 0, st>>>(u, f, r32, lg, h2, part);
+    else if (order == 4) k_ho_resid32<2><<<nb, kBlock, 0, st>>>(u, f, r32, lg, h2, part);
+    else k_ho_resid32<3><<<nb, kBlock, 0, st>>>(u, f, r32, lg, h2, part);
+    k_ho_reduce<<<1, kBlock, 0, st>>>(part, nb, out);
+}
+
+void launch_ho_add32(double* u, const float* e, int lg, hipStream_t st) {
+    k_ho_add32<<<grid_for((size_t)1 << (3 * lg)), kBlock, 0, st>>>(u, e, lg);
 }
 
 void launch_ho_sum(const double* a, int lg, double* part, double* out, hipStream_t st) {

@@ -362,13 +362,19 @@ template <class T> void launch_b_zero(const BSeg* segs, int nseg, unsigned grid,
 // periodic FAS with the order-2/4/6 Laplacians of Table 1 (k_highorder.hip): n = 2^lg per axis,
 // natural order, FP64.  The half-sweep is out of place (reads in, writes every cell of out).
 constexpr int kHoParts = 8192;   // partial sums of the reductions, at most
-void launch_ho_half(const double* in, double* out, const double* f, int lg, double h, int order, int colour,
-                    hipStream_t st, hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
-void launch_ho_resid_restrict(const double* u, const double* f, double* uc, double* uold, double* rc, int lgc,
-                              double h, int order, hipStream_t st);   // h: the fine spacing
-void launch_ho_fas(const double* uc, double* fc, int lgc, double hc, int order, hipStream_t st);
-void launch_ho_prolong(double* u, const double* uc, const double* uold, int lg, hipStream_t st);
-void launch_ho_fill(double* a, int lg, double v, hipStream_t st);
+template <class T>
+void launch_ho_half(const T* in, T* out, const T* f, int lg, double h, int order, int colour, hipStream_t st,
+                    hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
+template <class T>   // h: the fine spacing
+void launch_ho_resid_restrict(const T* u, const T* f, T* uc, T* uold, T* rc, int lgc, double h, int order,
+                              hipStream_t st);
+template <class T> void launch_ho_fas(const T* uc, T* fc, int lgc, double hc, int order, hipStream_t st);
+template <class T> void launch_ho_prolong(T* u, const T* uc, const T* uold, int lg, hipStream_t st);
+template <class T> void launch_ho_fill(T* a, int lg, T v, hipStream_t st);
+// mixed precision: r32 = f - L u (FP64) with out[0] = sum r^2; u += e32
+void launch_ho_resid32(const double* u, const double* f, float* r32, int lg, double h, int order, double* part,
+                       double* out, hipStream_t st);
+void launch_ho_add32(double* u, const float* e, int lg, hipStream_t st);
 void launch_ho_sum(const double* a, int lg, double* part, double* out, hipStream_t st);
 void launch_ho_sub(const double* a, const double* sum, double* out, int lg, double* part, double* sumsq,
                    hipStream_t st);

@@ -1528,9 +1528,17 @@ struct HoPlan {
     double* f[12]{};      // level 0: f minus its mean; coarser levels: the FAS right-hand side
     double* uold[12]{};   // the restricted iterate before the coarse solve (levels >= 1)
     double* tmp[12]{};    // the other buffer of the out-of-place half-sweeps (levels with 2^3+ cells)
+    float* e32[12]{};     // mixed precision: the FP32 correction and its V-cycle arrays, every level
+    float* f32[12]{};     // (level 0: the FP64 residual rounded to FP32)
+    float* uold32[12]{};
+    float* tmp32[12]{};
     double* part = nullptr;
     double* scal = nullptr;   // [0] sum f, [1] sum (f - mean)^2, [2] sum r^2, [3] sum u, [4] unused
 };
+
+template <class T> struct HoArr { T* const* u; T* const* f; T* const* uold; T* const* tmp; };
+static HoArr<double> ho_arr(const HoPlan& P, double) { return {P.u, P.f, P.uold, P.tmp}; }
+static HoArr<float> ho_arr(const HoPlan& P, float) { return {P.e32, P.f32, P.uold32, P.tmp32}; }
 
 static int ho_plan(int n, double h, int order, Carver& cv, double* u, HoPlan& P) {
     const int lg = log2_exact(n);
@@ -1548,6 +1556,13 @@ static int ho_plan(int n, double h, int order, Carver& cv, double* u, HoPlan& P)
         if (l > 0) P.uold[l] = cv.take<double>(cells);
         if (l < lg) P.tmp[l] = cv.take<double>(cells);
     }
+    for (int l = 0; l < P.nlev; ++l) {   // the FP32 arrays are reserved whatever the precision
+        const size_t cells = (size_t)1 << (3 * (lg - l));
+        P.e32[l] = cv.take<float>(cells);
+        P.f32[l] = cv.take<float>(cells);
+        if (l > 0) P.uold32[l] = cv.take<float>(cells);
+        if (l < lg) P.tmp32[l] = cv.take<float>(cells);
+    }
     P.part = cv.take<double>(kHoParts);
     P.scal = cv.take<double>(8);
     return MG_OK;
@@ -1562,33 +1577,36 @@ static int ho_read(const double* dev, int count, double* out, hipStream_t st) {
     return MG_OK;
 }
 
-static void ho_smooth(HoPlan& P, int l, int sweeps, hipStream_t st) {
+template <class T>
+static void ho_smooth(HoPlan& P, const HoArr<T>& A, int l, int sweeps, hipStream_t st) {
     const int lg = P.lg - l;
     const double h = std::ldexp(P.h, l);
-    const double half_bytes = 3.0 * 8.0 * (double)((size_t)1 << (3 * lg));   // in, f read; out written
+    const double half_bytes = 3.0 * sizeof(T) * (double)((size_t)1 << (3 * lg));   // in, f read; out written
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             KEvents ev(l == 0);
-            const double* in = c == 0 ? P.u[l] : P.tmp[l];
-            double* out = c == 0 ? P.tmp[l] : P.u[l];
-            launch_ho_half(in, out, P.f[l], lg, h, P.order, c, st, ev.a, ev.b);
+            const T* in = c == 0 ? A.u[l] : A.tmp[l];
+            T* out = c == 0 ? A.tmp[l] : A.u[l];
+            launch_ho_half<T>(in, out, A.f[l], lg, h, P.order, c, st, ev.a, ev.b);
             ev.done(half_bytes);
         }
 }
 
+template <class T>
 static void ho_vcycle(HoPlan& P, int nu1, int nu2, hipStream_t st) {
+    const HoArr<T> A = ho_arr(P, T(0));
     const int L = P.nlev - 1;   // the single-cell level
     for (int l = 0; l < L; ++l) {
-        ho_smooth(P, l, nu1, st);
+        ho_smooth<T>(P, A, l, nu1, st);
         const int lgc = P.lg - l - 1;
-        launch_ho_resid_restrict(P.u[l], P.f[l], P.u[l + 1], P.uold[l + 1], P.f[l + 1], lgc, std::ldexp(P.h, l),
-                                 P.order, st);
-        launch_ho_fas(P.u[l + 1], P.f[l + 1], lgc, std::ldexp(P.h, l + 1), P.order, st);
+        launch_ho_resid_restrict<T>(A.u[l], A.f[l], A.u[l + 1], A.uold[l + 1], A.f[l + 1], lgc, std::ldexp(P.h, l),
+                                    P.order, st);
+        launch_ho_fas<T>(A.u[l + 1], A.f[l + 1], lgc, std::ldexp(P.h, l + 1), P.order, st);
     }
-    launch_ho_fill(P.u[L], 0, 0.0, st);   // one cell: u = 0
+    launch_ho_fill<T>(A.u[L], 0, T(0), st);   // one cell: u = 0
     for (int l = L - 1; l >= 0; --l) {
-        launch_ho_prolong(P.u[l], P.u[l + 1], P.uold[l + 1], P.lg - l, st);
-        ho_smooth(P, l, nu2, st);
+        launch_ho_prolong<T>(A.u[l], A.u[l + 1], A.uold[l + 1], P.lg - l, st);
+        ho_smooth<T>(P, A, l, nu2, st);
     }
 }
 
@@ -1607,7 +1625,8 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
     if (!o) return fail(MG_EINVAL, "options are NULL");
     if (!f || !u) return fail(MG_EINVAL, "f or u is NULL");
     if (o->max_cycles < 0) return fail(MG_EINVAL, "max_cycles < 0");
-    if (o->prec != MG_FP64) return fail(MG_EINVAL, "the higher-order solve runs in FP64 only");
+    if (o->prec != MG_FP64 && o->prec != MG_MIXED) return fail(MG_EINVAL, "unknown precision");
+    if (o->inner < 0 || o->inner > 16) return fail(MG_EINVAL, "inner cycles out of range (0..16)");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 64) return fail(MG_EINVAL, "nu1/nu2 out of range");
     if (o->flags & ~(MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES)) return fail(MG_EINVAL, "unknown flags");
     HoPlan P;
@@ -1629,7 +1648,7 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
     for (double& v : S.res_hist) v = NAN;
     launch_ho_sum(f, lg, P.part, P.scal + 0, st);                          // composite mean of f ...
     launch_ho_sub(f, P.scal + 0, P.f[0], lg, P.part, P.scal + 1, st);      // ... removed, and |f|^2
-    if (!guess) launch_ho_fill(P.u[0], lg, 0.0, st);
+    if (!guess) launch_ho_fill<double>(P.u[0], lg, 0.0, st);
     double fnorm2 = 0.0;
     if (!fixed) {
         double fs[2];
@@ -1646,9 +1665,11 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
     for (int l = 0; l < lg; ++l) upc += (long long)(o->nu1 + o->nu2) << (3 * (lg - l));
     double rel = NAN, prev = INFINITY;
     int grow = 0, status = MG_ENOCONV, cycles = 0;
+    const bool mixed = o->prec == MG_MIXED;
     auto check = [&]() -> int {
         double r2;
-        launch_ho_rnorm(P.u[0], P.f[0], lg, h, order, P.part, P.scal + 2, st);
+        if (mixed) launch_ho_resid32(P.u[0], P.f[0], P.f32[0], lg, h, order, P.part, P.scal + 2, st);
+        else launch_ho_rnorm(P.u[0], P.f[0], lg, h, order, P.part, P.scal + 2, st);
         if (int e = ho_read(P.scal + 2, 1, &r2, st)) return e;
         rel = fnorm2 > 0 ? std::sqrt(r2 / fnorm2) : 0.0;
         if (cycles >= 1 && cycles <= 64) S.res_hist[cycles - 1] = rel;
@@ -1658,20 +1679,48 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
         if (grow >= 3) return MG_EDIVERGED;
         return rel <= o->tol ? MG_OK : 1;
     };
-    if (guess && !fixed) {
-        const int c = check();
-        if (c == MG_OK) status = MG_OK;
-        else if (c == MG_EHIP) return c;
-    }
-    while (status != MG_OK && cycles < o->max_cycles) {
-        ho_vcycle(P, o->nu1, o->nu2, st);
-        ++cycles;
-        S.cell_updates += upc;
-        if (fixed) continue;
-        const int c = check();
-        if (c == MG_OK) status = MG_OK;
-        else if (c == MG_EHIP) return c;
-        else if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+    if (!mixed) {
+        if (guess && !fixed) {
+            const int c = check();
+            if (c == MG_OK) status = MG_OK;
+            else if (c == MG_EHIP) return c;
+        }
+        while (status != MG_OK && cycles < o->max_cycles) {
+            ho_vcycle<double>(P, o->nu1, o->nu2, st);
+            ++cycles;
+            S.cell_updates += upc;
+            if (fixed) continue;
+            const int c = check();
+            if (c == MG_OK) status = MG_OK;
+            else if (c == MG_EHIP) return c;
+            else if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+        }
+    } else {
+        // defect correction: the FP64 residual (rounded to FP32) is the right-hand side of `inner`
+        // FP32 V-cycles from e = 0, and u += e; the stopping test is on the FP64 residual.  By
+        // default 3 per correction: at 256^3 that measured faster than the 7-point path's rule
+        // chosen from the contraction (7.8 against 9.4 ms at order 4, 13.2 against 12.9 at order 6).
+        const int inner = o->inner > 0 ? o->inner : 3;
+        for (;;) {
+            if (fixed) {
+                if (cycles >= o->max_cycles) break;
+                launch_ho_resid32(P.u[0], P.f[0], P.f32[0], lg, h, order, P.part, P.scal + 2, st);
+            } else {
+                const int c = check();
+                if (c == MG_OK) { status = MG_OK; break; }
+                if (c == MG_EHIP) return c;
+                if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
+                if (cycles >= o->max_cycles) break;
+            }
+            launch_ho_fill<float>(P.e32[0], lg, 0.0f, st);
+            const int k = std::min(inner, o->max_cycles - cycles);
+            for (int i = 0; i < k; ++i) {
+                ho_vcycle<float>(P, o->nu1, o->nu2, st);
+                ++cycles;
+                S.cell_updates += upc;
+            }
+            launch_ho_add32(P.u[0], P.e32[0], lg, st);
+        }
     }
     if (fixed) status = MG_OK;
     launch_ho_sum(P.u[0], lg, P.part, P.scal + 3, st);                     // zero-mean gauge of u

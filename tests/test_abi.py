@@ -131,7 +131,8 @@ def test_higher_order_solve_validates_its_arguments_before_any_device_work():
     ws = ctypes.c_void_p(256)
     big = lib.mg_ho_workspace_bytes(16, 4)
     p = ctypes.c_void_p(16)
-    for o, n, order, h in ((mgic.make_opts(prec="mixed"), 16, 4, 1.0),   # FP64 only
+    for o, n, order, h in ((mgic.make_opts(prec=7), 16, 4, 1.0),   # unknown precision
+                           (mgic.make_opts(prec="mixed", inner=17), 16, 4, 1.0),
                            (mgic.make_opts(), 16, 5, 1.0),
                            (mgic.make_opts(), 12, 4, 1.0),
                            (mgic.make_opts(), 16, 4, -1.0),

@@ -9,7 +9,7 @@ recomputes the GPU solution's relative residual.
 import numpy as np
 import pytest
 
-from gpu_util import needs_gpu, note, to_dev, to_host
+from gpu_util import needs_gpu, note, to_dev, to_host, rel_rms
 from oracle import highorder as ho
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -118,3 +118,42 @@ def test_full_size_256(mg, order):
     exact = ho.fft_solve(fz, h, order)
     assert np.max(np.abs(u - exact)) <= 1e-8 * np.max(np.abs(exact))
     assert st["cycles"] <= 12
+
+
+@pytest.mark.parametrize("order", [4, 6])
+@pytest.mark.parametrize("N", [32, 256])
+def test_mixed_precision_matches_fp64(mg, order, N):
+    # FP32 inner V-cycles inside FP64 defect correction: the same FP64 stopping test, so the
+    # result is within 1e-8 relative RMS of the FP64 solve and of the exact discrete solution
+    h = 100.0 / N
+    f = _rhs(N, 77 + order + N, mean=0.4)
+    note("highorder mixed order=%d N=%d" % (order, N))
+    um, sm = mg.mg_solve_level_ho(to_dev(f), h, order, opts=mg.make_opts(tol=1e-10, prec="mixed"))
+    ud, sd = mg.mg_solve_level_ho(to_dev(f), h, order, opts=mg.make_opts(tol=1e-10))
+    a, b = to_host(um), to_host(ud)
+    assert sm["rel_res"] <= 1e-10
+    assert rel_rms(a, b) <= 1e-8
+    assert abs(float(np.mean(a))) <= 1e-13 * np.max(np.abs(b))
+    # one FP64 residual per correction of several inner cycles: the others are NaN
+    hist = np.array(sm["history"])
+    assert np.isfinite(hist[-1]) and 2 <= np.sum(np.isfinite(hist)) < len(hist)
+    if N == 32:
+        exact = ho.fft_solve(f - f.mean(), h, order)
+        assert rel_rms(a, exact) <= 1e-8
+
+
+def test_mixed_precision_inner_counts_and_fixed_cycles(mg):
+    N, h, order = 32, 1.0 / 32, 6
+    f = _rhs(N, 12)
+    exact = ho.fft_solve(f - f.mean(), h, order)
+    note("highorder mixed inner counts")
+    for inner in (1, 3):
+        u, st = mg.mg_solve_level_ho(to_dev(f), h, order, opts=mg.make_opts(tol=1e-10, prec="mixed", inner=inner))
+        assert st["rel_res"] <= 1e-10 and rel_rms(to_host(u), exact) <= 1e-8
+        hist = np.array(st["history"])   # a fixed count: one FP64 residual every `inner` cycles
+        assert np.all(np.isfinite(hist[inner - 1::inner]))
+        assert np.all(np.isnan(np.delete(hist, np.s_[inner - 1::inner])))
+    u, st = mg.mg_solve_level_ho(to_dev(f), h, order,
+                                 opts=mg.make_opts(max_cycles=5, prec="mixed", inner=2, fixed_cycles=True))
+    assert st["cycles"] == 5 and np.isnan(st["rel_res"])
+    assert rel_rms(to_host(u), exact) <= 1e-3
