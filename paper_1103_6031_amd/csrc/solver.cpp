@@ -1684,8 +1684,9 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
             const int c = check();
             if (c == MG_OK) status = MG_OK;
             else if (c == MG_EHIP) return c;
+            else if (c == MG_EDIVERGED) status = MG_EDIVERGED;   // a NaN or Inf guess
         }
-        while (status != MG_OK && cycles < o->max_cycles) {
+        while (status == MG_ENOCONV && cycles < o->max_cycles) {
             ho_vcycle<double>(P, o->nu1, o->nu2, st);
             ++cycles;
             S.cell_updates += upc;

@@ -3,7 +3,9 @@
 Bar: after a fixed number of V-cycles the GPU iterate equals the oracle's within 1e-12 of its
 largest value (the two differ in summation order only); converged solves are within 1e-9 of the
 exact discrete solution (FFT with the symbols Table 1 prints), and at full size the oracle
-recomputes the GPU solution's relative residual.
+recomputes the GPU solution's relative residual.  The mixed-precision solve (FP32 inner cycles
+inside FP64 defect correction) is within 1e-8 relative RMS of the FP64 solve and of the exact
+solution.
 """
 
 import numpy as np
@@ -100,6 +102,12 @@ def test_initial_guess_and_errors(mg):
     assert e.value.code == mg.MG_EDIVERGED
     with pytest.raises(ValueError):
         mg.mg_solve_level_ho(to_dev(np.zeros((16, 16, 8))), h, order)
+    for prec in ("fp64", "mixed"):   # a NaN in the initial guess is reported, not iterated on
+        g = exact.copy()
+        g[1, 2, 3] = np.nan
+        with pytest.raises(mg.MGError) as e:
+            mg.mg_solve_level_ho(to_dev(f), h, order, u=to_dev(g), opts=mg.make_opts(prec=prec, initial_guess=True))
+        assert e.value.code == mg.MG_EDIVERGED
 
 
 @pytest.mark.parametrize("order", [4, 6])
