@@ -45,6 +45,10 @@ def parse():
                     help="requests of the serving trace (Poisson, 20/s); 0 skips the serving leg")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed", help="headline path")
     ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 V-cycles per FP64 correction (0: library default)")
+    ap.add_argument("--no-roof512", action="store_true", help="skip the 512^3 smoother leg")
+    ap.add_argument("--only", default="",
+                    help="comma-separated legs to run alone, without the headline step (profiling): "
+                         "roof512, c1, c3, c4")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -310,6 +314,56 @@ def time_c3(mg, torch, reps=3):
     return res
 
 
+def time_smoother_512(mg, torch, ft, h, tol):
+    """The finest-level smoother on a working set four times the 256 MB Infinity Cache: the step's
+    256^3 density tiled 2 x 2 x 2 (a periodic 512^3 field with the same spectrum on its even modes),
+    one 1LPT solve per precision after a warm-up solve, every finest-level smoother launch of it
+    timed by the library's dispatch-stamped events.  A plain 1 GiB device copy is timed beside it
+    (HIP events) as the achievable read + write bandwidth."""
+    n = 2 * ft.shape[0]
+    f5 = ft.repeat(2, 2, 2).contiguous()
+    h5 = h / 2.0
+    H5 = mg.Hier(n, h5)
+    res = dict(workload="periodic %d^3 (the %d^3 density tiled 2x2x2), 1LPT solve, tol %g" % (n, n // 2, tol),
+               n=n, u_plus_f_fp32_mb=round(2 * 4 * n ** 3 / 1e6, 1))
+    u = torch.empty_like(f5)
+    for prec, w in (("mixed", 4), ("fp64", 8)):
+        o = mg.make_opts(tol=tol, prec=prec, max_cycles=60)
+        ws = mg.Workspace(mg.mg_workspace_bytes(H5, o))
+        mg.mg_solve_level(f5, h5, u=u, opts=o, workspace=ws)
+        torch.cuda.synchronize()
+        mg.mg_kprof_read()
+        mg.mg_kprof_enable(True)
+        _, st = mg.mg_solve_level(f5, h5, u=u, opts=o, workspace=ws)
+        torch.cuda.synchronize()
+        mg.mg_kprof_enable(False)
+        kms, kn, kb = mg.mg_kprof_read()
+        us = 1e3 * kms / max(kn, 1)
+        gbs = kb / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+        res["fp32" if prec == "mixed" else "fp64"] = dict(
+            avg_launch_us=round(us, 2), launches=kn, algorithmic_bytes_per_launch=int(kb / max(kn, 1)),
+            achieved=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), cycles=st["cycles"], rel_res=st["rel_res"])
+        del ws
+    del u, f5
+    src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    ts = []
+    for i in range(6):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        if i >= 1:
+            ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    res["copy_1gib_gbs"] = round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(f, h):
     """The oracle's FAS V-cycle on the same input: a bounded sample of two cycles."""
     import numpy as np
@@ -329,6 +383,16 @@ def cpu_baseline(f, h):
     return dict(value=ups / dt / 1e6, unit="Mcell-updates/s", cores=1, kind="oracle",
                 sample="%d FAS V(2,2) cycles of the numpy oracle on the same %d^3 input (%.1f s); "
                        "single-threaded numpy, 1 core used of %d" % (ncyc, f.shape[0], dt, affinity))
+
+
+def calib_copies(torch):
+    """Three plain 256 MiB device-to-device copies: the counter calibration of the traffic profiles."""
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def main():
@@ -354,6 +418,24 @@ def main():
     ft = torch.from_numpy(f).to("cuda:0")
     H = mg.Hier(N, h)
     torch.cuda.synchronize()
+
+    if a.only:
+        line = {}
+        for leg in a.only.split(","):
+            if leg == "roof512":
+                line["roofline_512"] = time_smoother_512(mg, torch, ft, h, a.tol)
+            elif leg == "c1":
+                line["solve_c1"] = time_c1(mg, torch)
+            elif leg == "c3":
+                line["zoom_c3"] = time_c3(mg, torch)
+            elif leg == "c4":
+                line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
+            else:
+                raise SystemExit("unknown leg " + leg)
+        if a.pmc_calib:
+            calib_copies(torch)
+        print(json.dumps(line), flush=True)
+        return
 
     other = "fp64" if a.prec == "mixed" else "mixed"
     head, out_h = time_path(mg, torch, H, ft, h, a.prec, a.tol, a.steps, a.warmup, a.inner)
@@ -393,6 +475,9 @@ def main():
                                  smoother_avg_launch_us=round(side["kernel"]["avg_us"], 2))
     if a.inner:
         line["config"]["inner"] = a.inner
+    if roof is not None and not a.no_roof512 and N == 256:
+        r5 = time_smoother_512(mg, torch, ft, h, a.tol)
+        roof["beyond_infinity_cache"] = r5
     line["lla"] = time_lla(mg, torch, H, out_h[1], out_h[4])
     line["highorder"] = time_highorder(mg, torch, ft, h, a.tol)
     if not a.no_c1c3:
@@ -406,12 +491,7 @@ def main():
                                            "{64,96,128}^3, 1LPT/2LPT 50/50, mixed, tol 1e-10" % len(reqs),
                                   **summary)
     if a.pmc_calib:
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calib_copies(torch)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f, h)
     print(json.dumps(line), flush=True)

@@ -573,10 +573,11 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             composite_residual<double>(P, nullptr, false, st);
             double r2;
             if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
-            int c = check(r2);
+            const int c = check(r2);
             if (c == MG_OK) status = MG_OK;
+            else if (c == MG_EDIVERGED) status = MG_EDIVERGED;   // NaN/Inf in the initial guess
         }
-        while (status != MG_OK && cycles < o->max_cycles) {
+        while (status == MG_ENOCONV && cycles < o->max_cycles) {
             vcycle<double>(P, 0, st);
             ++cycles;
             S.cell_updates += upc;
@@ -1421,11 +1422,14 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
             launch_b_finalize(B.fins_dev + F_RNORM * ni, ni, act, st);
             MG_HIP(hipMemcpyAsync(pin, B.bscal, nscal * sizeof(double), hipMemcpyDeviceToHost, st));
             MG_HIP(hipStreamSynchronize(st));
-            for (int i = 0; i < ni; ++i)
-                if (S[i].active && check(i, pin[(size_t)i * S_COUNT + S_RNORM]) == MG_OK) {
-                    S[i].status = MG_OK;
+            for (int i = 0; i < ni; ++i) {
+                if (!S[i].active) continue;
+                const int c = check(i, pin[(size_t)i * S_COUNT + S_RNORM]);
+                if (c != 1) {   // converged already, or NaN/Inf in the initial guess
+                    S[i].status = c;
                     S[i].active = false;
                 }
+            }
             if ((rc = upload_flags())) return rc;
         }
         for (int i = 0; i < ni; ++i)

@@ -1,6 +1,8 @@
 """Shared helpers for the GPU parity tests (not collected by pytest: no test_ prefix)."""
 
+import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -11,9 +13,15 @@ needs_gpu = pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 
 
 def note(msg):
-    """Print what the next GPU step is, flushed, so a fault names its case."""
+    """Print what the next GPU step is, flushed, so a fault names its case.  With
+    MGIC_PROGRESS_FILE set, the line is also appended to that file (pytest captures stdout, so
+    long steps leave their progress there)."""
     print("[gpu-step] " + msg, flush=True)
     sys.stdout.flush()
+    path = os.environ.get("MGIC_PROGRESS_FILE")
+    if path:
+        with open(path, "a") as fh:
+            fh.write("%.1f %s\n" % (time.time(), msg))
 
 
 def to_dev(a):

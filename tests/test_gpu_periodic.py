@@ -129,6 +129,42 @@ def test_errors_are_reported(mg):
     assert st["rel_res"] <= 1e-10
 
 
+def test_nan_initial_guess_is_reported(mg):
+    # a NaN in the initial guess ends the solve before any cycle runs on it, in both precisions,
+    # on a single level (16^3: generic path, 32^3: fused mixed path), on a hierarchy and in a batch
+    for prec in ("fp64", "mixed"):
+        o = mg.make_opts(prec=prec, initial_guess=True, max_cycles=40)
+        for N in (16, 32):
+            h = 100.0 / N
+            f = inputs.gaussian_field(N, 6)
+            g = np.zeros_like(f)
+            g[1, 2, 3] = np.nan
+            note("NaN initial guess, level %d^3, %s" % (N, prec))
+            with pytest.raises(mg.MGError) as e:
+                mg.mg_solve_level(to_dev(f), h, u=to_dev(g), opts=o)
+            assert e.value.code == mg.MG_EDIVERGED and e.value.stats["cycles"] == 0
+        Hg = mg.Hier(N, h, [((8, 8, 8), (4, 4, 4))])
+        fl = [to_dev(f), to_dev(np.ones((8, 8, 8)))]
+        ul = [to_dev(g), to_dev(np.zeros((8, 8, 8)))]
+        note("NaN initial guess, hierarchy, %s" % prec)
+        with pytest.raises(mg.MGError) as e:
+            mg.mg_solve_hierarchy(Hg, fl, u=ul, opts=o)
+        assert e.value.code == mg.MG_EDIVERGED and e.value.stats["cycles"] == 0
+        fb = inputs.gaussian_field(32, 7)
+
+        def guesses():
+            ub = [to_dev(np.zeros_like(fb)), to_dev(np.zeros_like(fb))]
+            ub[1][0, 0, 1] = float("nan")
+            return ub
+
+        note("NaN initial guess, batch, %s" % prec)
+        with pytest.raises(mg.MGError) as e:
+            mg.mg_solve_batch([to_dev(fb), to_dev(fb)], [100.0 / 32] * 2, u=guesses(), opts=o)
+        assert e.value.code == mg.MG_EDIVERGED
+        _, sts = mg.mg_solve_batch([to_dev(fb), to_dev(fb)], [100.0 / 32] * 2, u=guesses(), opts=o, check=False)
+        assert sts[1]["cycles"] == 0 and sts[0]["rel_res"] <= 1e-10
+
+
 def test_warm_start_resumes(mg):
     N = 32
     h = 100.0 / N
