@@ -114,6 +114,21 @@ int mg_solve_hierarchy(const mg_hier* hier, const double* const* f, double* cons
                        const mg_opts* opts, mg_stats* stats, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/* Allocation-free variant of mg_solve_hierarchy, for callers that cannot allocate: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * operation, results (bit for bit) and errors as mg_solve_hierarchy, without the workspace: the
+ * library's static device array of MG_SCRATCH_BYTES bytes serves as the workspace (one copy per
+ * GPU, held until the process ends; the current device must be the stream's device).  Problems
+ * whose mg_workspace_bytes exceed MG_SCRATCH_BYTES are rejected with MG_EINVAL (e.g. a 128^3
+ * level fits in both precisions, 160^3 only in FP64).  The call makes no device, pinned-host or
+ * event allocation: per-cycle residuals are read back into host stack memory, and kernel timing
+ * (mg_kprof_enable) is ignored for its duration.  Every call on one GPU shares its array, which
+ * keeps the last call's contents (nothing in it needs to start at zero): calls that overlap on
+ * one GPU, from several host threads or streams, race and must be serialised by the caller. */
+#define MG_SCRATCH_BYTES ((size_t)96 << 20)
+int mg_solve_hierarchy_noalloc(const mg_hier* hier, const double* const* f, double* const* u,
+                               const mg_opts* opts, mg_stats* stats, void* stream);
+
 /* Periodic single level with the higher-order Laplacians of Table 1 (Section 3.2): the 1-D
  * stencil of order 2, 4 or 6 summed over the three axes (7, 13 or 19 points), on every level of
  * the same FAS V(nu1, nu2) cycle.  With a stencil wider than one cell, red-black is no longer a

@@ -224,6 +224,10 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
 // ----------------------------------------------------------------------------------------------
 // optional timing of the finest-level smoother launches (HIP events on the launch stream)
 // ----------------------------------------------------------------------------------------------
+// set for the duration of an allocation-free call: no timing events, and residual readbacks go
+// to host stack memory instead of the pinned buffer below
+static thread_local bool g_noalloc = false;
+
 struct KProf {
     bool on = false;
     long long period = 1, count = 0;   // time the launches with count % period == 0
@@ -243,7 +247,7 @@ static thread_local KProf g_kprof;
 struct KEvents {
     hipEvent_t a = nullptr, b = nullptr;
     KEvents(bool time_it) {
-        if (!time_it || !g_kprof.on) return;
+        if (!time_it || !g_kprof.on || g_noalloc) return;
         if (g_kprof.count++ % g_kprof.period) return;
         a = g_kprof.get();
         b = g_kprof.get();
@@ -477,6 +481,14 @@ static void gauge_u(Plan& P, hipStream_t st) {
 }
 
 static int read_scalars(Plan& P, int first, int count, double* out, hipStream_t st) {
+    if (g_noalloc) {   // pageable destination: the copy is complete once the stream has drained
+        double tmp[S_COUNT];
+        if (count > S_COUNT) return fail(MG_EINVAL, "internal: scalar readback too long");
+        MG_HIP(hipMemcpyAsync(tmp, P.scal + first, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        MG_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < count; ++i) out[i] = tmp[i];
+        return MG_OK;
+    }
     double* pin = pinned_scratch();
     if (!pin) return fail(MG_EHIP, "pinned host buffer unavailable");
     MG_HIP(hipMemcpyAsync(pin, P.scal + first, count * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -674,6 +686,53 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     if (status == MG_ENOCONV) return fail(MG_ENOCONV, "not converged after " + std::to_string(cycles) + " cycles");
     if (status == MG_EDIVERGED) return fail(MG_EDIVERGED, "residual diverged (NaN/Inf or growth)");
     return MG_OK;
+}
+
+// ----------------------------------------------------------------------------------------------
+// allocation-free solve: the workspace is a static device array, one copy per GPU
+// ----------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MG_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's copy of `scratch`, looked up once per device with that
+// device current (host code never passes the symbol itself: on the host it is only a stand-in)
+static int scratch_address(void** out) {
+    int dev = -1;
+    MG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MG_EINVAL, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        MG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) return fail(MG_EHIP, "scratch array has no aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MG_OK;
+}
+
+struct NoAllocScope {
+    NoAllocScope() { g_noalloc = true; }
+    ~NoAllocScope() { g_noalloc = false; }
+};
+
+static int solve_noalloc(const mg_hier* H, const double* const* f, double* const* u, const mg_opts* o,
+                         mg_stats* stats, hipStream_t st) {
+    if (!o) return fail(MG_EINVAL, "options are NULL");
+    if (int v = validate_hier(H)) return v;
+    Plan P;
+    Carver size_cv(nullptr);
+    if (int rc = build_plan(H, o, size_cv, nullptr, P)) return rc;
+    if (size_cv.off > (size_t)MG_SCRATCH_BYTES)
+        return fail(MG_EINVAL, "problem needs " + std::to_string(size_cv.off) + " workspace bytes, above the " +
+                                   std::to_string((size_t)MG_SCRATCH_BYTES) + " of the static scratch array");
+    void* ws = nullptr;
+    if (int rc = scratch_address(&ws)) return rc;
+    NoAllocScope scope;
+    return solve(H, f, u, o, stats, ws, (size_t)MG_SCRATCH_BYTES, st);
 }
 
 static mg_hier single_level(int n, double h) {
@@ -1791,6 +1850,11 @@ int mg_solve_level(int n, double h, const double* f, double* u, const mg_opts* o
 int mg_solve_hierarchy(const mg_hier* hier, const double* const* f, double* const* u, const mg_opts* opts,
                        mg_stats* stats, void* workspace, size_t workspace_bytes, void* stream) {
     return solve(hier, f, u, opts, stats, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+int mg_solve_hierarchy_noalloc(const mg_hier* hier, const double* const* f, double* const* u, const mg_opts* opts,
+                               mg_stats* stats, void* stream) {
+    return solve_noalloc(hier, f, u, opts, stats, (hipStream_t)stream);
 }
 
 int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* const* u, double* const* r,

@@ -65,6 +65,8 @@ _sig = {
                                       ctypes.POINTER(mg_stats), _P, _sz, _P]),
     "mg_solve_hierarchy": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.POINTER(mg_opts),
                                           ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_solve_hierarchy_noalloc": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.POINTER(mg_opts),
+                                                  ctypes.POINTER(mg_stats), _P]),
     "mg_ho_workspace_bytes": (_sz, [ctypes.c_int, ctypes.c_int]),
     "mg_solve_level_ho": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P,
                                          ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
@@ -265,6 +267,26 @@ def mg_solve_hierarchy(hier: Hier, f: Sequence[torch.Tensor], u=None, opts=None,
     st = mg_stats()
     rc = _lib.mg_solve_hierarchy(ctypes.byref(H), fp, up, ctypes.byref(o), ctypes.byref(st),
                                  ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream))
+    if check:
+        _check(rc, st.to_dict())
+    return u, st.to_dict()
+
+
+MG_SCRATCH_BYTES = 96 << 20   # the library's static scratch array (mgic.h)
+
+
+def mg_solve_hierarchy_noalloc(hier: Hier, f: Sequence[torch.Tensor], u: Sequence[torch.Tensor], opts=None,
+                               stream=None, check=True):
+    """mg_solve_hierarchy without a workspace argument: the library's static device scratch array
+    serves as the workspace, and the call allocates nothing.  u must be given (outputs are the
+    caller's).  Returns (u list, stats dict)."""
+    o = opts or make_opts()
+    H = hier.c_struct()
+    fp, _fa = _ptr_array([_dev(x, "f") for x in f])
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    st = mg_stats()
+    rc = _lib.mg_solve_hierarchy_noalloc(ctypes.byref(H), fp, up, ctypes.byref(o), ctypes.byref(st),
+                                         _stream(stream))
     if check:
         _check(rc, st.to_dict())
     return u, st.to_dict()

@@ -145,3 +145,21 @@ def test_higher_order_solve_validates_its_arguments_before_any_device_work():
     assert rc == mgic.MG_EINVAL and b"workspace" in lib.mg_last_error()
     rc = lib.mg_solve_level_ho(16, 1.0, 4, p, p, ctypes.byref(o), ctypes.byref(st), ctypes.c_void_p(257), big, None)
     assert rc == mgic.MG_EINVAL and b"aligned" in lib.mg_last_error()
+
+
+def test_allocation_free_solve_rejects_problems_above_its_scratch_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    lib = mgic._lib
+    o = mgic.make_opts(prec="mixed")
+    st = mgic.mg_stats()
+    big = mgic.Hier(256, 100.0 / 256)
+    assert mgic.mg_workspace_bytes(big, o) > mgic.MG_SCRATCH_BYTES
+    Hc = big.c_struct()
+    p = (ctypes.c_void_p * 1)(16)
+    rc = lib.mg_solve_hierarchy_noalloc(ctypes.byref(Hc), p, p, ctypes.byref(o), ctypes.byref(st), None)
+    assert rc == mgic.MG_EINVAL and b"scratch" in lib.mg_last_error()
+    # the sizes the header names: 128^3 fits in both precisions, 160^3 in FP64 only
+    for n, prec, fits in ((128, "fp64", True), (128, "mixed", True), (160, "fp64", True), (160, "mixed", False)):
+        need = mgic.mg_workspace_bytes(mgic.Hier(n, 1.0), mgic.make_opts(prec=prec))
+        assert (need <= mgic.MG_SCRATCH_BYTES) == fits, (n, prec, need)
+    assert lib.mg_solve_hierarchy_noalloc(ctypes.byref(Hc), p, p, None, ctypes.byref(st), None) == mgic.MG_EINVAL
