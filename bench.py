@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed", help="headline path")
     ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 V-cycles per FP64 correction (0: library default)")
     ap.add_argument("--no-roof512", action="store_true", help="skip the 512^3 smoother leg")
+    ap.add_argument("--no-graph", action="store_true", help="launch every kernel directly (no graph replay)")
     ap.add_argument("--only", default="",
                     help="comma-separated legs to run alone, without the headline step (profiling): "
                          "roof512, c1, c3, c4")
@@ -86,6 +87,11 @@ def recorded_traffic():
 
 
 KPROF_STEPS = 1   # timed steps whose finest smoother launches carry events
+GRAPH = True      # replay repeating launch sequences as HIP graphs (--no-graph: direct launches)
+
+
+def _opts(mg, **kw):
+    return mg.make_opts(graph=GRAPH, **kw)
 
 
 def run_step(mg, H, ft, h, opts, ws):
@@ -98,7 +104,7 @@ def run_step(mg, H, ft, h, opts, ws):
 
 
 def time_path(mg, torch, H, ft, h, prec, tol, steps, warmup, inner=0):
-    opts = mg.make_opts(tol=tol, prec=prec, max_cycles=60, inner=inner)
+    opts = _opts(mg, tol=tol, prec=prec, max_cycles=60, inner=inner)
     ws = {"solve": mg.Workspace(mg.mg_workspace_bytes(H, opts)),
           "lpt1": mg.Workspace(mg.lpt_workspace_bytes(H, 1)),
           "lpt2": mg.Workspace(mg.lpt_workspace_bytes(H, 2))}
@@ -138,7 +144,7 @@ def time_batch(mg, torch, reps):
     sizes = [N for N, _, _ in inst]
     hs = [inputs.BOX / N for N in sizes]
     fs = [torch.from_numpy(inputs.c4_field(N, s, seed)).to("cuda:0") for N, s, seed in inst]
-    o = mg.make_opts(tol=1e-10, prec="mixed", max_cycles=40)
+    o = _opts(mg, tol=1e-10, prec="mixed", max_cycles=40)
     ws = mg.Workspace(mg.mg_batch_workspace_bytes(sizes, o))
     u = [torch.empty_like(f) for f in fs]
     mg.mg_solve_batch(fs, hs, u=u, opts=o, workspace=ws)     # warm-up (autotuning, graph capture)
@@ -175,7 +181,7 @@ def time_c1(mg, torch, reps=10):
     h = inputs.BOX / N
     H = mg.Hier(N, h)
     ft = torch.from_numpy(inputs.c1_input()).to("cuda:0")
-    o = mg.make_opts(tol=1e-10, prec="fp64", max_cycles=60)
+    o = _opts(mg, tol=1e-10, prec="fp64", max_cycles=60)
     ws = mg.Workspace(mg.mg_workspace_bytes(H, o))
     wl = mg.Workspace(mg.lpt_workspace_bytes(H, 1))
     u = torch.empty_like(ft)
@@ -234,7 +240,7 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
     res = dict(workload="periodic %d^3 BBKS, V(2,2) with the order-4 / order-6 Laplacian, tol %g; FP64, and mixed "
                         "(FP32 inner cycles inside FP64 defect correction)" % (n, tol))
     for order in (4, 6):
-        o = mg.make_opts(tol=tol, max_cycles=40)
+        o = _opts(mg, tol=tol, max_cycles=40)
         ws = mg.Workspace(mg.mg_ho_workspace_bytes(n, order))
         u = torch.empty_like(ft)
         ts = []
@@ -260,7 +266,7 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
                                       unit="Mcell-updates/s", half_sweep_avg_us=round(us, 2),
                                       half_sweep_launches=kn,
                                       half_sweep_gbs=round(kb / max(kn, 1) / (us * 1e-6) / 1e9, 1) if kn else None)
-        om = mg.make_opts(tol=tol, max_cycles=60, prec="mixed")
+        om = _opts(mg, tol=tol, max_cycles=60, prec="mixed")
         tm = []
         for i in range(reps + 1):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -289,7 +295,7 @@ def time_c3(mg, torch, reps=3):
     res = dict(workload="128^3 base + 3 nested 128^3 patches (1024^3 effective), 2LPT, tol 1e-10",
                cells=int(128 ** 3 * 4))
     for prec in ("mixed", "fp64"):
-        o = mg.make_opts(tol=1e-10, prec=prec, max_cycles=60)
+        o = _opts(mg, tol=1e-10, prec=prec, max_cycles=60)
         ws = mg.Workspace(mg.mg_workspace_bytes(H, o))
 
         def step():
@@ -328,7 +334,7 @@ def time_smoother_512(mg, torch, ft, h, tol):
                n=n, u_plus_f_fp32_mb=round(2 * 4 * n ** 3 / 1e6, 1))
     u = torch.empty_like(f5)
     for prec, w in (("mixed", 4), ("fp64", 8)):
-        o = mg.make_opts(tol=tol, prec=prec, max_cycles=60)
+        o = _opts(mg, tol=tol, prec=prec, max_cycles=60)
         ws = mg.Workspace(mg.mg_workspace_bytes(H5, o))
         mg.mg_solve_level(f5, h5, u=u, opts=o, workspace=ws)
         torch.cuda.synchronize()
@@ -397,6 +403,8 @@ def calib_copies(torch):
 
 def main():
     a = parse()
+    global GRAPH
+    GRAPH = not a.no_graph
     if a.gpus != 1:
         print("bench.py measures one GPU only: the multigrid hot path here runs on a single device "
               "(sharding across GPUs is not built); run with --gpus 1", file=sys.stderr)

@@ -60,7 +60,7 @@ enum { MG_FP64 = 0, MG_MIXED = 1 };
 /* option flags */
 #define MG_USE_INITIAL_GUESS 0x1u  /* start from the caller's u instead of 0                    */
 #define MG_FIXED_CYCLES      0x2u  /* run exactly max_cycles cycles, no per-cycle host readback */
-#define MG_NO_GRAPH          0x4u  /* mg_solve_batch: launch directly instead of replaying graphs */
+#define MG_NO_GRAPH          0x4u  /* launch every kernel directly instead of replaying graphs    */
 
 typedef struct {
     int n[3];       /* cells per axis (base: all three equal)                 */
@@ -98,6 +98,16 @@ typedef struct {
 
 /* Workspace bytes for mg_solve_level / mg_solve_hierarchy / mg_solve_batch member, exact. */
 size_t mg_workspace_bytes(const mg_hier* hier, const mg_opts* opts);
+
+/* Graph replay (mg_solve_level, mg_solve_hierarchy): the launch sequences a solve repeats - a
+ * V-cycle with its residual norm, an outer step of the mixed-precision loop, the source
+ * preparation and the final gauge - are captured as HIP graphs the second time one is met for a
+ * workspace address and plan (shapes, spacings, sweep counts; for the preparation and gauge also
+ * the f and u pointers) and replayed after that, with the same kernels in the same order, so the
+ * same bits.  The graphs are cached per host thread for the life of the thread (at most 256); a
+ * workspace freed and reused at the same address for the same plan replays them correctly.
+ * Not used with MG_NO_GRAPH, with kernel timing on (mg_kprof_enable), or by the allocation-free
+ * call. */
 
 /* Periodic single level: solve L u = f - mean(f) on n^3 cells of size h.
  * n = 2^k * m with m in {1, 3, 5, 7} and n >= 2.  f (n^3 doubles) is read only.  u (n^3

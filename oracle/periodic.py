@@ -29,7 +29,7 @@ Readings (where the paper is silent, ambiguous or garbled):
 
 import numpy as np
 
-from .stencil import neighbour_sum, lap7, lap7_symbol, restrict_mean8, inject, red_mask
+from .stencil import neighbour_sum, lap7, restrict_mean8, inject, red_mask
 
 
 def rbgs_half(u, f, h, colour):
@@ -141,4 +141,4 @@ def cell_updates(N, cycles, nu1=2, nu2=2):
 
 
 __all__ = ["rbgs_half", "rbgs_sweep", "residual", "vcycle", "solve_level", "fft_solve",
-           "rms", "cell_updates", "lap7_symbol"]
+           "rms", "cell_updates"]

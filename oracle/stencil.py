@@ -36,17 +36,6 @@ def lap7(u, h):
     return (neighbour_sum(u) - 6.0 * u) / (h * h)
 
 
-def lap7_symbol(m, N, h):
-    """Eigenvalue of ``lap7`` for the Fourier mode exp(2 pi i m.x/N).
-
-    Table 1, order 2: the 1-D symbol is -2 (1 - cos k) with k = 2 pi m_i / N in
-    grid units; the 3-D symbol is the sum over axes, divided by h^2.
-    """
-    m = np.asarray(m, dtype=np.float64)
-    k = 2.0 * np.pi * m / N
-    return -(2.0 / (h * h)) * np.sum(1.0 - np.cos(k), axis=0)
-
-
 G4_WEIGHTS = (1.0, -8.0, 0.0, 8.0, -1.0)  # Table 1, order 4, offsets -2..+2, times 1/12
 
 
@@ -60,11 +49,6 @@ def grad4(u, h, axis):
         if w != 0.0:
             acc = acc + w * np.roll(u, -off, axis)
     return acc / (12.0 * h)
-
-
-def grad4_symbol(k):
-    """Table 1 order-4 gradient symbol without the -i factor: (8 sin k - sin 2k)/6."""
-    return (8.0 * np.sin(k) - np.sin(2.0 * k)) / 6.0
 
 
 def restrict_mean8(v):

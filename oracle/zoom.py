@@ -300,12 +300,6 @@ def solve_hierarchy(H, f, tol=1e-10, max_cycles=40, nu1=2, nu2=2, flux_match=Tru
     return u, dict(cycles=cycles, rel_res=rel, f_mean=f_mean, history=hist)
 
 
-def cell_updates(H, cycles, nu1=2, nu2=2):
-    """Smoother cell-updates of a hierarchy solve (patches, base and its coarsenings)."""
-    per = sum(int(np.prod(n)) for n in H.n[1:]) * (nu1 + nu2)
-    return per * cycles + periodic.cell_updates(H.N0, cycles, nu1, nu2)
-
-
 # ----------------------------------------------------------------------------- post-solve ghosts, LPT
 
 def wide_ghosted(H, v, p, R):

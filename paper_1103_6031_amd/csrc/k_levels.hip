@@ -468,12 +468,21 @@ void launch_rbgs_vec(T* u, const T* f, const Lay& L, double h, int colour, hipSt
     const T h2 = (T)(h * h);
     // measured: 1 run per thread is best for FP32 at 128^3 and 256^3 and for FP64 at 128^3; FP64
     // at 256^3 and above is 5% faster with 2
-    if (sizeof(T) == 8 && chunks >= (1u << 22))
-        hipExtLaunchKernelGGL(k_rbgs_vec<T, 2>, dim3((chunks + 511) / 512), dim3(256), 0, st, ev0, ev1, 0, u, f, L.lgx,
-                              L.lgy, L.lgz, h2, colour);
-    else
-        hipExtLaunchKernelGGL(k_rbgs_vec<T, 1>, dim3((chunks + 255) / 256), dim3(256), 0, st, ev0, ev1, 0, u, f, L.lgx,
-                              L.lgy, L.lgz, h2, colour);
+    // stamped by the events when they are given (kernel timing), else a plain launch (the form
+    // captured into graphs)
+    if (sizeof(T) == 8 && chunks >= (1u << 22)) {
+        if (ev0)
+            hipExtLaunchKernelGGL(k_rbgs_vec<T, 2>, dim3((chunks + 511) / 512), dim3(256), 0, st, ev0, ev1, 0, u, f,
+                                  L.lgx, L.lgy, L.lgz, h2, colour);
+        else
+            k_rbgs_vec<T, 2><<<(chunks + 511) / 512, 256, 0, st>>>(u, f, L.lgx, L.lgy, L.lgz, h2, colour);
+    } else {
+        if (ev0)
+            hipExtLaunchKernelGGL(k_rbgs_vec<T, 1>, dim3((chunks + 255) / 256), dim3(256), 0, st, ev0, ev1, 0, u, f,
+                                  L.lgx, L.lgy, L.lgz, h2, colour);
+        else
+            k_rbgs_vec<T, 1><<<(chunks + 255) / 256, 256, 0, st>>>(u, f, L.lgx, L.lgy, L.lgz, h2, colour);
+    }
 }
 
 bool level_fusable(int n, int nu1, int nu2) {

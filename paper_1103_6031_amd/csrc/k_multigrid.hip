@@ -669,29 +669,21 @@ __device__ __forceinline__ void w2(double t, double w[3]) {
     w[2] = 0.5 * t * (t + 1.0);
 }
 
-// One lane per ghost cell: the four lanes q = 2 jb + kc (jb, kc in {0, 1}) of a group are
-// consecutive, each forms its own g0, and the group means are gathered by lane shuffles in the
-// order ((q0 + q1) + (q2 + q3)), the order of the sums written out over the group (so the bits do
-// not depend on how the group is split over lanes).  Four short chains instead of one long one,
-// and four times the waves, for a launch that is latency-bound.
+// The ghost value of lane q = 2 jb + kc (jb, kc in {0, 1}) of group (J, K) on face `face` of a
+// patch: the group is the 2 x 2 fine ghost cells in front of parent cell (J, K) of the face (J
+// along axis b, K along axis c; a is the normal).  Each lane forms its own g0; the group means
+// are gathered by lane shuffles in the order ((q0 + q1) + (q2 + q3)), the order of the sums
+// written out over the group, so the bits do not depend on how the group is split over lanes.
+// The four lanes of a group must be consecutive lanes of one wave starting at a multiple of 4,
+// and every lane of the wave must take part (lanes with no group of their own repeat a valid one).
 template <class T>
-__global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, T* __restrict__ g, Lay LF,
-                             ParentMap pm, int flux_match) {
+__device__ __forceinline__ double ghost_lane(const T* __restrict__ pu, const T* __restrict__ u, const Lay& LF,
+                                             const ParentMap& pm, int face, int J, int K, int q, int flux_match) {
     const Dims d = LF.d;
     const int n[3] = {d.x, d.y, d.z};
-    const int face = (int)blockIdx.y;
     const int a = face >> 1, side = face & 1;
     const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
-    const unsigned nc2 = (unsigned)n[c] / 2;
-    const unsigned lane = blockIdx.x * blockDim.x + threadIdx.x;
-    const unsigned t = lane >> 2, q = lane & 3;
-    // every lane of a group takes part in the shuffles; lanes past the face compute on a valid
-    // group (the last one) and store nothing
-    const unsigned ngroups = ((unsigned)n[b] / 2) * nc2;
-    const bool live = t < ngroups;
-    const unsigned tg = live ? t : ngroups - 1;
-    const int J = (int)(tg / nc2), K = (int)(tg - (unsigned)J * nc2);
-    const int jb = (int)(q >> 1), kc = (int)(q & 1);
+    const int jb = q >> 1, kc = q & 1;
     // fine interior layers and the outside coarse layer along the face normal
     const int i0 = side ? n[a] - 1 : 0, i1 = side ? n[a] - 2 : 1;
     const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
@@ -736,10 +728,33 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
         const double uC = 0.5 * (m_u0 + m_u1);
         shift = (m_u0 - m_g0) - 0.5 * (uC - L[1][1]);
     }
+    return g0 + shift;
+}
+
+// One lane per ghost cell, four lanes per group (ghost_lane), one launch row per face.  Four
+// short chains instead of one long one, and four times the waves, for a launch that is
+// latency-bound.
+template <class T>
+__global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, T* __restrict__ g, Lay LF,
+                             ParentMap pm, int flux_match) {
+    const Dims d = LF.d;
+    const int n[3] = {d.x, d.y, d.z};
+    const int face = (int)blockIdx.y;
+    const int a = face >> 1;
+    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    const unsigned nc2 = (unsigned)n[c] / 2;
+    const unsigned lane = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned t = lane >> 2, q = lane & 3;
+    // lanes past the face compute on a valid group (the last one) and store nothing
+    const unsigned ngroups = ((unsigned)n[b] / 2) * nc2;
+    const bool live = t < ngroups;
+    const unsigned tg = live ? t : ngroups - 1;
+    const int J = (int)(tg / nc2), K = (int)(tg - (unsigned)J * nc2);
+    const double v = ghost_lane<T>(pu, u, LF, pm, face, J, K, (int)q, flux_match);
     if (!live) return;
     const size_t fo = ghost_face_offset(d, face);
     const int nbf = n[c];  // face arrays are [n_b][n_c]
-    g[fo + (size_t)(2 * J + jb) * nbf + (2 * K + kc)] = (T)(g0 + shift);
+    g[fo + (size_t)(2 * J + (int)(q >> 1)) * nbf + (2 * K + (int)(q & 1))] = (T)v;
 }
 
 // parent[cov] = mean8(fine), bottom-up composite restriction
@@ -1233,29 +1248,52 @@ void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h, int co
                       hipEvent_t ev0, hipEvent_t ev1) {
     const size_t n = (size_t)L.d.x * L.d.y * (L.d.z / 2);
     const T h2 = (T)(h * h);
-    if (ghosts)
-        hipExtLaunchKernelGGL(k_rbgs_ghost<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, ghosts, L,
-                              h2, colour);
-    else if (sizeof(T) == 4 && n >= ((size_t)1 << 22))   // measured: 4 cells per thread for FP32 at 256^3+
-        hipExtLaunchKernelGGL(k_rbgs_split<T, 4>, dim3(grid_for((n + 3) / 4)), dim3(kBlock), 0, st, ev0, ev1, 0, u,
-                              f, L, h2, colour);
-    else if (n >= (size_t)kBlock * 64 * 2)
-        hipExtLaunchKernelGGL(k_rbgs_split<T, 2>, dim3(grid_for((n + 1) / 2)), dim3(kBlock), 0, st, ev0, ev1, 0, u,
-                              f, L, h2, colour);
-    else
-        hipExtLaunchKernelGGL(k_rbgs_split<T, 1>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, L, h2,
-                              colour);
+    // stamped by the events when they are given (kernel timing), else a plain launch (the form
+    // captured into graphs)
+    if (ghosts) {
+        if (ev0)
+            hipExtLaunchKernelGGL(k_rbgs_ghost<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, ghosts,
+                                  L, h2, colour);
+        else
+            k_rbgs_ghost<T><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, colour);
+    } else if (sizeof(T) == 4 && n >= ((size_t)1 << 22)) {   // measured: 4 cells per thread for FP32 at 256^3+
+        if (ev0)
+            hipExtLaunchKernelGGL(k_rbgs_split<T, 4>, dim3(grid_for((n + 3) / 4)), dim3(kBlock), 0, st, ev0, ev1, 0,
+                                  u, f, L, h2, colour);
+        else
+            k_rbgs_split<T, 4><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(u, f, L, h2, colour);
+    } else if (n >= (size_t)kBlock * 64 * 2) {
+        if (ev0)
+            hipExtLaunchKernelGGL(k_rbgs_split<T, 2>, dim3(grid_for((n + 1) / 2)), dim3(kBlock), 0, st, ev0, ev1, 0,
+                                  u, f, L, h2, colour);
+        else
+            k_rbgs_split<T, 2><<<grid_for((n + 1) / 2), kBlock, 0, st>>>(u, f, L, h2, colour);
+    } else {
+        if (ev0)
+            hipExtLaunchKernelGGL(k_rbgs_split<T, 1>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, L,
+                                  h2, colour);
+        else
+            k_rbgs_split<T, 1><<<grid_for(n), kBlock, 0, st>>>(u, f, L, h2, colour);
+    }
+}
+
+// dynamic LDS above the default for the tail kernels; set once, before any graph capture
+hipError_t tail_kernel_setup() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    const void* fns[4] = {(const void*)k_tail<float>, (const void*)k_tail<double>, (const void*)k_tail_p2<float>,
+                          (const void*)k_tail_p2<double>};
+    for (const void* fn : fns) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
+        if (e != hipSuccess) return e;
+    }
+    done = true;
+    return hipSuccess;
 }
 
 template <class T>
 void launch_tail(const TailPlan<T>& tp, hipStream_t st) {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailMaxLds);
-        (void)hipFuncSetAttribute((const void*)k_tail_p2<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kTailMaxLds);
-        attr = true;
-    }
+    (void)tail_kernel_setup();
     bool p2 = tp.n >= 2 && tp.lev[tp.n - 1].lay.d.cells() == 1;
     for (int k = 0; p2 && k + 1 < tp.n; ++k) {
         const Lay& A = tp.lev[k].lay;

@@ -335,6 +335,7 @@ template <class T> void launch_b_prolong(const BSeg* segs, int nseg, unsigned gr
                                          int black_only, hipStream_t st);
 // sets the batched kernels' function attributes (LDS size); call before any graph capture
 hipError_t batch_kernel_setup();
+hipError_t tail_kernel_setup();
 // the single-workgroup tails of n instances, one workgroup each
 template <class T> void launch_b_tail(const TailPlan<T>* plans, int n, unsigned lds_bytes, const int* active,
                                       hipStream_t st);

@@ -266,6 +266,64 @@ static double* pinned_scratch() {
     return p;
 }
 
+// ---- graphs ------------------------------------------------------------------------------------
+// Instantiated graphs live until the thread ends; they are deliberately not destroyed at exit,
+// when the HIP runtime may already be gone.
+struct GraphCache {
+    std::map<std::string, hipGraphExec_t> exec;
+    std::map<std::string, int> seen;   // uses of keys not captured yet
+    hipStream_t cap = nullptr;  // capture stream (capture is illegal on the null stream)
+};
+static thread_local GraphCache g_graphs;
+
+// kernel attributes that must be set before any capture
+static int graph_setup() {
+    static thread_local bool done = false;
+    if (done) return MG_OK;
+    MG_HIP(tail_kernel_setup());
+    MG_HIP(batch_kernel_setup());
+    done = true;
+    return MG_OK;
+}
+
+// runs `body` on st, or replays its graph, captured under `key` at the capture_at-th use of the
+// key (1: the first), so that launch sequences run once are never captured
+template <class F>
+static int run_graph(bool use_graph, const std::string& key, hipStream_t st, F body, int capture_at = 1) {
+    if (!use_graph) {
+        body(st);
+        MG_HIP(hipGetLastError());
+        return MG_OK;
+    }
+    auto it = g_graphs.exec.find(key);
+    if (it == g_graphs.exec.end()) {
+        if (capture_at > 1 && ++g_graphs.seen[key] < capture_at) {
+            body(st);
+            MG_HIP(hipGetLastError());
+            return MG_OK;
+        }
+        g_graphs.seen.erase(key);
+        if (int rc = graph_setup()) return rc;
+        if (!g_graphs.cap) MG_HIP(hipStreamCreateWithFlags(&g_graphs.cap, hipStreamNonBlocking));
+        if (g_graphs.exec.size() >= 256) {
+            for (auto& kv : g_graphs.exec) (void)hipGraphExecDestroy(kv.second);
+            g_graphs.exec.clear();
+        }
+        if (g_graphs.seen.size() >= 4096) g_graphs.seen.clear();
+        MG_HIP(hipStreamBeginCapture(g_graphs.cap, hipStreamCaptureModeThreadLocal));
+        body(g_graphs.cap);
+        hipGraph_t g = nullptr;
+        MG_HIP(hipStreamEndCapture(g_graphs.cap, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        MG_HIP(e);
+        it = g_graphs.exec.emplace(key, ex).first;
+    }
+    MG_HIP(hipGraphLaunch(it->second, st));
+    return MG_OK;
+}
+
 // ----------------------------------------------------------------------------------------------
 // V-cycle schedule
 // ----------------------------------------------------------------------------------------------
@@ -515,6 +573,29 @@ static int inner_count(int opt, bool fixed, double rel, double prev_rel, int pre
     return (int)std::min<double>(kInnerMax, std::max(1.0, m));
 }
 
+// graph key of a solve's plan: every kernel argument of its cycles and outer steps follows from
+// the workspace address, the shapes, spacings and sweep counts (and the caller's u where a level
+// is solved in place); the steps that read f or write u add those pointers
+static std::string plan_key(const Plan& P, const void* ws) {
+    std::string k = "solo|" + std::to_string((uintptr_t)ws) + "|" + std::to_string(P.nu1) + "," +
+                    std::to_string(P.nu2) + "," + std::to_string((int)P.mixed) + "," + std::to_string(P.tail);
+    for (const Level& L : P.L) {
+        uint64_t hb;
+        std::memcpy(&hb, &L.h, sizeof(hb));
+        k += "|" + std::to_string(L.d.x) + "," + std::to_string(L.d.y) + "," + std::to_string(L.d.z) + "," +
+             std::to_string(L.pm.off[0]) + "," + std::to_string(L.pm.off[1]) + "," + std::to_string(L.pm.off[2]) +
+             "," + std::to_string(hb) + "," + std::to_string((int)L.fusable);
+        if (L.u && L.u == L.u_user) k += "," + std::to_string((uintptr_t)L.u_user);
+    }
+    return k;
+}
+
+static std::string user_key(const mg_hier* H, const double* const* f, double* const* u) {
+    std::string k;
+    for (int p = 0; p < H->nlev; ++p) k += "|" + std::to_string((uintptr_t)f[p]) + "," + std::to_string((uintptr_t)u[p]);
+    return k;
+}
+
 static int solve(const mg_hier* H, const double* const* f, double* const* u, const mg_opts* o, mg_stats* stats,
                  void* ws, size_t ws_bytes, hipStream_t st) {
     if (!o) return fail(MG_EINVAL, "options are NULL");
@@ -535,30 +616,58 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     build_plan(H, o, cv, u, P);
     (void)hipGetLastError();
 
-    rc = prepare_f(P, f, st);
-    if (rc) return rc;
     const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
     const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
+    // Launch sequences that repeat (a cycle, an outer step) are replayed as HIP graphs, captured
+    // the second time a sequence is met for this workspace and plan; not with kernel timing (its
+    // events are recorded by the dispatches) nor in the allocation-free call.
+    const bool use_graph = (o->flags & MG_NO_GRAPH) == 0 && !g_noalloc && !g_kprof.on;
+    const std::string gkey = use_graph ? plan_key(P, ws) : std::string();
+    const std::string ukey = use_graph ? user_key(H, f, u) : std::string();
+    double* pin = nullptr;
+    if (!g_noalloc && !(pin = pinned_scratch())) return fail(MG_EHIP, "pinned host buffer unavailable");
+    // one step of the solve: `launches`, then (count > 0) the copy of scal[first .. first + count)
+    // to the host and a wait for the stream
+    auto step = [&](const std::string& var, auto&& launches, int first, int count, double* out) -> int {
+        if (!use_graph) {
+            launches(st);
+            MG_HIP(hipGetLastError());
+            return count ? read_scalars(P, first, count, out, st) : MG_OK;
+        }
+        const int rcg = run_graph(true, gkey + var, st, [&](hipStream_t s) {
+            launches(s);
+            if (count) (void)hipMemcpyAsync(pin, P.scal + first, count * sizeof(double), hipMemcpyDeviceToHost, s);
+        }, 2);
+        if (rcg) return rcg;
+        if (count) {
+            MG_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < count; ++i) out[i] = pin[i];
+        }
+        return MG_OK;
+    };
+
     // a zero start of the fused mixed-precision path needs no fill: its first outer step takes
     // u as zero without reading it and writes the zero iterate itself
     const bool zero_start = !guess && P.mixed && P.L[0].ualt;
-    for (int l = 0; l < P.nh; ++l) {
-        Level& L = P.L[l];
-        if (zero_start) continue;
-        if (!guess) launch_fill<double>(L.u, L.d.cells(), 0.0, st);
-        else if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, mklay(L.d, 0), L.u, L.lay, st);
-    }
+    double fs[2] = {0, 0};
+    rc = step(std::string("|prep") + (guess ? "g" : "z") + ukey, [&](hipStream_t s) {
+        prepare_f(P, f, s);
+        for (int l = 0; l < P.nh; ++l) {
+            Level& L = P.L[l];
+            if (zero_start) continue;
+            if (!guess) launch_fill<double>(L.u, L.d.cells(), 0.0, s);
+            else if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, mklay(L.d, 0), L.u, L.lay, s);
+        }
+    }, S_FSUM, fixed ? 0 : 2, fs);
+    if (rc) return rc;
 
     mg_stats S;
     std::memset(&S, 0, sizeof(S));
     for (double& v : S.res_hist) v = NAN;
     double check_prev = NAN;   // relative residual at the previous FP64 correction
     int last_inner = 0;        // inner cycles run since it
-    double fs[2] = {0, 0};
     double fnorm2 = 0;
     if (!fixed) {
-        rc = read_scalars(P, S_FSUM, 2, fs, st);
-        if (rc) return rc;
         S.f_mean_removed = fs[0] / (double)P.L[P.nh - 1].d.cells();
         fnorm2 = fs[1];
         if (!std::isfinite(fnorm2) || !std::isfinite(fs[0])) {
@@ -579,25 +688,28 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
         if (grow >= 3) return MG_EDIVERGED;
         return rel <= o->tol ? MG_OK : 1;
     };
+    auto ptag = [](const void* q) { return std::to_string((uintptr_t)q); };
 
     if (!P.mixed) {
         if (guess && !fixed) {
-            composite_residual<double>(P, nullptr, false, st);
             double r2;
-            if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
+            rc = step("|g64", [&](hipStream_t s) { composite_residual<double>(P, nullptr, false, s); }, S_RNORM, 1, &r2);
+            if (rc) return rc;
             const int c = check(r2);
             if (c == MG_OK) status = MG_OK;
             else if (c == MG_EDIVERGED) status = MG_EDIVERGED;   // NaN/Inf in the initial guess
         }
         while (status == MG_ENOCONV && cycles < o->max_cycles) {
-            vcycle<double>(P, 0, st);
+            double r2 = 0;
+            rc = step(fixed ? "|c64f" : "|c64", [&](hipStream_t s) {
+                vcycle<double>(P, 0, s);
+                if (!fixed) composite_residual<double>(P, nullptr, false, s);
+            }, S_RNORM, fixed ? 0 : 1, &r2);
+            if (rc) return rc;
             ++cycles;
             S.cell_updates += upc;
             if (fixed) continue;
-            composite_residual<double>(P, nullptr, false, st);
-            double r2;
-            if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
-            int c = check(r2);
+            const int c = check(r2);
             if (c == MG_OK) status = MG_OK;
             else if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
         }
@@ -608,18 +720,21 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
         bool pending = false;
         bool u_zero = zero_start;   // the iterate is +0 and not stored (a zero start, before its first correction)
         for (;;) {
-            int np = 0;
-            launch_outer_split(u_zero ? nullptr : L.u, pending ? L.u32 : nullptr, L.f, L.ualt, L.f32, L.ealt, L.lay,
-                               L.h, P.partials, &np, st);
+            double r2 = 0;
+            rc = step("|o" + std::to_string((int)u_zero) + std::to_string((int)pending) + ptag(L.u) + ptag(L.u32),
+                      [&](hipStream_t s) {
+                          int np = 0;
+                          launch_outer_split(u_zero ? nullptr : L.u, pending ? L.u32 : nullptr, L.f, L.ualt, L.f32,
+                                             L.ealt, L.lay, L.h, P.partials, &np, s);
+                          SegList sg{};
+                          sg.n = 1; sg.off[0] = 0; sg.cnt[0] = np; sg.w[0] = L.h * L.h * L.h;
+                          launch_finalize(P.partials, sg, P.scal + S_RNORM, s);
+                      }, S_RNORM, fixed ? 0 : 1, &r2);
+            if (rc) return rc;
             if (pending) u_zero = false;   // this step stored u = 0 + e
             std::swap(L.u, L.ualt);
             std::swap(L.u32, L.ealt);
-            SegList sg{};
-            sg.n = 1; sg.off[0] = 0; sg.cnt[0] = np; sg.w[0] = L.h * L.h * L.h;
-            launch_finalize(P.partials, sg, P.scal + S_RNORM, st);
             if (!fixed) {
-                double r2;
-                if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
                 int c = check(r2);
                 if (c == MG_OK) { status = MG_OK; break; }
                 if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
@@ -629,7 +744,9 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             check_prev = rel;
             last_inner = 0;
             for (int k = 0; k < nin && cycles < o->max_cycles; ++k) {
-                vcycle<float>(P, 0, st, /*skip_first_red=*/k == 0);
+                rc = step("|i" + std::to_string((int)(k == 0)) + ptag(L.u32),
+                          [&](hipStream_t s) { vcycle<float>(P, 0, s, /*skip_first_red=*/k == 0); }, 0, 0, nullptr);
+                if (rc) return rc;
                 ++cycles;
                 ++last_inner;
                 S.cell_updates += upc;
@@ -640,41 +757,56 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     } else {
         std::vector<float*> rhs(P.nh);
         for (int l = 0; l < P.nh; ++l) rhs[l] = P.L[l].f32;
+        bool pending = false;   // FP32 corrections not yet added to u
         for (;;) {
-            composite_residual<float>(P, rhs.data(), false, st);
+            double r2 = 0;
+            rc = step(pending ? "|r1" : "|r0", [&](hipStream_t s) {
+                if (pending)
+                    for (int l = 0; l < P.nh; ++l) launch_add_f32_to_f64(P.L[l].u, P.L[l].u32, P.L[l].d.cells(), s);
+                composite_residual<float>(P, rhs.data(), false, s);
+            }, S_RNORM, fixed ? 0 : 1, &r2);
+            if (rc) return rc;
+            pending = false;
             if (!fixed) {
-                double r2;
-                if ((rc = read_scalars(P, S_RNORM, 1, &r2, st))) return rc;
                 int c = check(r2);
                 if (c == MG_OK) { status = MG_OK; break; }
                 if (c == MG_EDIVERGED) { status = MG_EDIVERGED; break; }
             }
             if (cycles >= o->max_cycles) break;
-            for (int l = 0; l < P.nh; ++l) launch_fill<float>(P.L[l].u32, P.L[l].d.cells(), 0.0f, st);
             const int nin = inner_count(o->inner, fixed, rel, check_prev, last_inner, o->tol);
             check_prev = rel;
             last_inner = 0;
             for (int k = 0; k < nin && cycles < o->max_cycles; ++k) {
-                vcycle<float>(P, 0, st);
+                rc = step(k == 0 ? "|j1" : "|j0", [&](hipStream_t s) {
+                    if (k == 0)
+                        for (int l = 0; l < P.nh; ++l) launch_fill<float>(P.L[l].u32, P.L[l].d.cells(), 0.0f, s);
+                    vcycle<float>(P, 0, s);
+                }, 0, 0, nullptr);
+                if (rc) return rc;
                 ++cycles;
                 ++last_inner;
                 S.cell_updates += upc;
             }
+            pending = true;
+        }
+        if (pending)
             for (int l = 0; l < P.nh; ++l) launch_add_f32_to_f64(P.L[l].u, P.L[l].u32, P.L[l].d.cells(), st);
-        }
     }
-    if (P.nh == 1 && P.L[0].u != P.L[0].u_user) {
-        // one periodic level: its sum, then the copy back with the mean removed
-        Level& L = P.L[0];
-        base_sum(P, L.u, S_USUM, st);
-        launch_relayout_sub(L.u, L.lay, L.u_user, mklay(L.d, 0), P.scal + S_USUM, 1.0 / (double)L.d.cells(), st);
-    } else {
-        gauge_u(P, st);
-        for (int l = 0; l < P.nh; ++l) {
-            Level& L = P.L[l];
-            if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, mklay(L.d, 0), st);
+    rc = step("|fin" + ptag(P.L[0].u) + ukey, [&](hipStream_t s) {   // P.L[0].u: where the fused path ended
+        if (P.nh == 1 && P.L[0].u != P.L[0].u_user) {
+            // one periodic level: its sum, then the copy back with the mean removed
+            Level& L = P.L[0];
+            base_sum(P, L.u, S_USUM, s);
+            launch_relayout_sub(L.u, L.lay, L.u_user, mklay(L.d, 0), P.scal + S_USUM, 1.0 / (double)L.d.cells(), s);
+        } else {
+            gauge_u(P, s);
+            for (int l = 0; l < P.nh; ++l) {
+                Level& L = P.L[l];
+                if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, mklay(L.d, 0), s);
+            }
         }
-    }
+    }, 0, 0, nullptr);
+    if (rc) return rc;
     MG_HIP(hipGetLastError());
     if (fixed) {
         MG_HIP(hipStreamSynchronize(st));  // surface asynchronous faults at the API boundary
@@ -1099,44 +1231,6 @@ static int tune_smoother(BatchPlan& B, int ti, hipStream_t st, std::vector<Smoot
     MG_HIP(hipGetLastError());
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[key] = out;
-    return MG_OK;
-}
-
-// ---- graphs ------------------------------------------------------------------------------------
-// Instantiated graphs live until the thread ends; they are deliberately not destroyed at exit,
-// when the HIP runtime may already be gone.
-struct GraphCache {
-    std::map<std::string, hipGraphExec_t> exec;
-    hipStream_t cap = nullptr;  // capture stream (capture is illegal on the null stream)
-};
-static thread_local GraphCache g_graphs;
-
-// runs `body` on st, or replays its graph (captured on first use under `key`)
-template <class F>
-static int run_graph(bool use_graph, const std::string& key, hipStream_t st, F body) {
-    if (!use_graph) {
-        body(st);
-        MG_HIP(hipGetLastError());
-        return MG_OK;
-    }
-    auto it = g_graphs.exec.find(key);
-    if (it == g_graphs.exec.end()) {
-        if (!g_graphs.cap) MG_HIP(hipStreamCreateWithFlags(&g_graphs.cap, hipStreamNonBlocking));
-        if (g_graphs.exec.size() >= 256) {
-            for (auto& kv : g_graphs.exec) (void)hipGraphExecDestroy(kv.second);
-            g_graphs.exec.clear();
-        }
-        MG_HIP(hipStreamBeginCapture(g_graphs.cap, hipStreamCaptureModeThreadLocal));
-        body(g_graphs.cap);
-        hipGraph_t g = nullptr;
-        MG_HIP(hipStreamEndCapture(g_graphs.cap, &g));
-        hipGraphExec_t ex = nullptr;
-        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        MG_HIP(e);
-        it = g_graphs.exec.emplace(key, ex).first;
-    }
-    MG_HIP(hipGraphLaunch(it->second, st));
     return MG_OK;
 }
 

@@ -122,3 +122,19 @@ def test_repeated_hierarchy_solves_are_bit_identical(mg, name):
         if ref is None:
             ref = out
         assert np.array_equal(out, ref), "solve %d differs" % rep
+
+
+@pytest.mark.parametrize("name", ["one", "rect", "deep", "c3small"])
+@pytest.mark.parametrize("cycles", [1, 2])
+def test_fixed_cycle_iterates_match_oracle(mg, name, cycles):
+    """After a fixed number of FP64 V-cycles from zero, every level of the GPU iterate equals the
+    oracle's adaptive FAS iterate (ghosts refreshed before each patch half-sweep, Section 3.3) to
+    rounding: a mistake in any ghost group, face or colour would show at once."""
+    H, Hg, f = _case(name)
+    note("fixed-cycle iterate %s, %d cycles" % (name, cycles))
+    u, _ = mg.mg_solve_hierarchy(Hg, [to_dev(a) for a in f], opts=mg.make_opts(max_cycles=cycles,
+                                                                               fixed_cycles=True))
+    ue, info = zoom.solve_hierarchy(H, f, tol=0.0, max_cycles=cycles)
+    assert info["cycles"] == cycles
+    for p in range(H.P + 1):
+        assert rel_max(to_host(u[p]), ue[p]) <= 1e-12, p
