@@ -260,6 +260,7 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
             if i >= 1:
                 ts.append(e0.elapsed_time(e1))
         ms = sorted(ts)[len(ts) // 2]
+        u64 = u.clone()
         us = kms * 1e3 / max(kn, 1)
         res["order%d" % order] = dict(ms_per_solve=round(ms, 3), cycles=st["cycles"], rel_res=st["rel_res"],
                                       value=round(st["cell_updates"] / (ms * 1e-3) / 1e6, 1),
@@ -278,8 +279,10 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
             if i >= 1:
                 tm.append(e0.elapsed_time(e1))
         msm = sorted(tm)[len(tm) // 2]
+        dev = float(torch.sqrt(torch.mean((u - u64) ** 2)) / torch.sqrt(torch.mean(u64 ** 2)))
         res["order%d" % order]["mixed"] = dict(ms_per_solve=round(msm, 3), cycles=sm["cycles"], rel_res=sm["rel_res"],
-                                               value=round(sm["cell_updates"] / (msm * 1e-3) / 1e6, 1))
+                                               value=round(sm["cell_updates"] / (msm * 1e-3) / 1e6, 1),
+                                               rel_rms_vs_fp64=dev)
     return res
 
 

@@ -148,7 +148,8 @@ int mg_solve_hierarchy_noalloc(const mg_hier* hier, const double* const* f, doub
  * (opts->prec = MG_FP64), or mixed (MG_MIXED: FP32 V-cycles, opts->inner per FP64 correction, default 3,
  * inside FP64 defect correction with the same FP64 stopping test).  f and u: n^3 device doubles, [x][y][z], z
  * contiguous; f is read only; u receives the zero-mean solution of L u = f - mean(f) and is read
- * only with MG_USE_INITIAL_GUESS.  stats and the stopping test as for mg_solve_level.
+ * only with MG_USE_INITIAL_GUESS.  The solve iterates in u itself, which the kernels access as
+ * 16-byte pairs of cells: u must be 16-byte aligned (MG_EINVAL otherwise).  stats and the stopping test as for mg_solve_level.
  * Workspace: mg_ho_workspace_bytes(n, order) bytes, 256-byte aligned (about 4.1 n^3 doubles,
  * the FP32 arrays of the mixed path included whatever the precision).
  * Errors: MG_EINVAL (size, order, h, options, workspace), MG_ENOCONV, MG_EDIVERGED, MG_EHIP. */

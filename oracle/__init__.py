@@ -21,6 +21,9 @@ cosmological simulations" (MNRAS 2011):
                  the potential and the second-order source term tau.
 * ``highorder``- the fourth- and sixth-order Laplacians of Table 1 (13- and
                  19-point) and the periodic FAS solve of Section 3.2 with them.
+* ``zoom_ho``  - the adaptive multigrid with the order-4 / order-6 Laplacians:
+                 ghost zones of width order / 2 by polynomials of that degree,
+                 flux matching with the Table 2 operators of order 3 and 5.
 * ``dense``    - brute-force dense assembly of the periodic and composite
                  linear systems for tiny grids (pins for the iterative solvers).
 
@@ -34,4 +37,4 @@ brute-force dense solves or invariants that do not reuse the oracle's own
 arithmetic.
 """
 
-from . import stencil, periodic, lpt, zoom, dense, highorder  # noqa: F401
+from . import stencil, periodic, lpt, zoom, zoom_ho, dense, highorder  # noqa: F401

@@ -11,12 +11,13 @@ Test infrastructure only (see ``oracle/__init__.py``).
   multigrid (Section 3.3) column by column, by applying ``oracle.zoom``'s
   operator to unit vectors.  It pins the iterative adaptive FAS to the fixed
   point of that operator (the reading of the ghost formula itself is pinned
-  separately by exactness and conservation tests).
+  separately by exactness and conservation tests).  With ``order`` 4 or 6 it
+  assembles the operator of ``oracle.zoom_ho`` the same way.
 """
 
 import numpy as np
 
-from . import zoom
+from . import zoom, zoom_ho
 
 
 def circulant_second_difference(N):
@@ -61,8 +62,14 @@ def _gather(H, masks, v):
     return np.concatenate([v[p][masks[p]] for p in range(H.P + 1)])
 
 
-def composite_matrix(H, flux_match=True):
-    """Dense matrix of u -> L_composite u over the composite unknowns."""
+def _residual(H, u, f, flux_match, order):
+    if order == 2:
+        return zoom.composite_residual(H, u, f, flux_match)
+    return zoom_ho.composite_residual(H, u, f, order, flux_match)
+
+
+def composite_matrix(H, flux_match=True, order=2):
+    """Dense matrix of u -> L_composite u over the composite unknowns (Laplacian of `order`)."""
     masks = _unknown_masks(H)
     nunk = sum(int(m.sum()) for m in masks)
     zero_f = H.zeros()
@@ -71,15 +78,15 @@ def composite_matrix(H, flux_match=True):
         e = np.zeros(nunk)
         e[k] = 1.0
         u = _scatter(H, masks, e)
-        r = zoom.composite_residual(H, u, zero_f, flux_match)     # = -L u on unknowns
+        r = _residual(H, u, zero_f, flux_match, order)            # = -L u on unknowns
         A[:, k] = -_gather(H, masks, r)
     return A, masks
 
 
-def composite_solve(H, f, flux_match=True):
+def composite_solve(H, f, flux_match=True, order=2):
     """Zero-composite-mean solution of the composite system by a dense solve."""
     f, _ = zoom.composite_zero_mean(H, f)
-    A, masks = composite_matrix(H, flux_match)
+    A, masks = composite_matrix(H, flux_match, order)
     vol = np.concatenate([np.full(int(masks[p].sum()), H.h[p] ** 3) for p in range(H.P + 1)])
     b = _gather(H, masks, f)
     Aa = np.vstack([A, vol[None, :]])

@@ -1786,6 +1786,8 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
     if (o->inner < 0 || o->inner > 16) return fail(MG_EINVAL, "inner cycles out of range (0..16)");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 64) return fail(MG_EINVAL, "nu1/nu2 out of range");
     if (o->flags & ~(MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES)) return fail(MG_EINVAL, "unknown flags");
+    // the finest level iterates in the caller's u, which the kernels access as 16-byte pairs
+    if ((uintptr_t)u & 15) return fail(MG_EINVAL, "u must be 16-byte aligned");
     HoPlan P;
     Carver size_cv(nullptr);
     int rc = ho_plan(n, h, order, size_cv, u, P);

@@ -145,6 +145,8 @@ def test_higher_order_solve_validates_its_arguments_before_any_device_work():
     assert rc == mgic.MG_EINVAL and b"workspace" in lib.mg_last_error()
     rc = lib.mg_solve_level_ho(16, 1.0, 4, p, p, ctypes.byref(o), ctypes.byref(st), ctypes.c_void_p(257), big, None)
     assert rc == mgic.MG_EINVAL and b"aligned" in lib.mg_last_error()
+    rc = lib.mg_solve_level_ho(16, 1.0, 4, p, ctypes.c_void_p(24), ctypes.byref(o), ctypes.byref(st), ws, big, None)
+    assert rc == mgic.MG_EINVAL and b"16-byte" in lib.mg_last_error()
 
 
 def test_allocation_free_solve_rejects_problems_above_its_scratch_before_any_device_work():

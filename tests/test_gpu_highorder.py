@@ -165,3 +165,22 @@ def test_mixed_precision_inner_counts_and_fixed_cycles(mg):
                                  opts=mg.make_opts(max_cycles=5, prec="mixed", inner=2, fixed_cycles=True))
     assert st["cycles"] == 5 and np.isnan(st["rel_res"])
     assert rel_rms(to_host(u), exact) <= 1e-3
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_bench_density_256_against_the_exact_solve(mg, order):
+    # the benchmark's input (BBKS density, 256^3, tol 1e-10), as the bench times it: the FP64
+    # solve within 1e-10 and the mixed solve within 1e-8 relative RMS of the exact discrete
+    # solution with Table 1's symbols
+    from paper_1103_6031_amd import inputs
+    N = 256
+    h = inputs.BOX / N
+    f = inputs.c2_input()
+    exact = ho.fft_solve(f - f.mean(), h, order)
+    for prec, bar in (("fp64", 1e-10), ("mixed", 1e-8)):
+        note("highorder bench density order=%d %s" % (order, prec))
+        u, st = mg.mg_solve_level_ho(to_dev(f), h, order, opts=mg.make_opts(tol=1e-10, prec=prec, max_cycles=60))
+        err = rel_rms(to_host(u), exact)
+        note("highorder bench density order=%d %s: %d cycles, rel. RMS vs exact %.2e" % (order, prec, st["cycles"],
+                                                                                          err))
+        assert st["rel_res"] <= 1e-10 and err <= bar
