@@ -157,6 +157,27 @@ size_t mg_ho_workspace_bytes(int n, int order);   /* 0 for an invalid n or order
 int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, const mg_opts* opts,
                       mg_stats* stats, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Nested hierarchy with the higher-order Laplacians of Table 1 (Section 3.3 with Tables 1 and 2):
+ * the composite system of mg_solve_hierarchy with the operator of order 2, 4 or 6 on every level.
+ * A patch reads R = order / 2 ghost layers on each face, refreshed before every half-sweep and
+ * residual: a polynomial of degree `order` parallel to the face through the 2R + 1 parent cells
+ * around the fine cell's parent (for each of the R parent layers outside the face), then one of
+ * degree `order` normal to the face through those R values and the first R + 1 fine cells; the
+ * ghosts of the 2 x 2 fine cells in front of one parent face are then shifted together so that the
+ * mean of their fluxes (the Table 2 operator of order - 1) equals the parent's flux through that
+ * face, whose covered cells are the means of their current children.  Half-sweeps update a colour
+ * from the values before them (Jacobi within the colour), as in mg_solve_level_ho.
+ * Arrays as in mg_solve_hierarchy (natural [x][y][z] order, one per level); the base n must be a
+ * power of two (2..1024), patches at least `order` cells per axis, and the base must leave at
+ * least order / 2 cells uncovered per axis.  FP64 only (opts->prec = MG_FP64).  On return covered
+ * coarse cells of u hold the mean of their children and the composite mean of u is zero.
+ * Workspace: mg_ho_hierarchy_workspace_bytes(hier, order) (0 for an invalid hierarchy or order).
+ * Errors: MG_EINVAL, MG_ENOCONV, MG_EDIVERGED, MG_EHIP. */
+size_t mg_ho_hierarchy_workspace_bytes(const mg_hier* hier, int order);
+int mg_solve_hierarchy_ho(const mg_hier* hier, int order, const double* const* f, double* const* u,
+                          const mg_opts* opts, mg_stats* stats, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
 /* Composite residual r = f - L u of a hierarchy (covered coarse cells of r set to 0), with
  * f's composite mean removed first; u's covered coarse cells are first replaced by the mean of
  * their children (u is modified only there).  Writes sqrt(sum r^2 vol) / sqrt(sum f^2 vol)
@@ -254,6 +275,14 @@ int mg_smooth_level(int n, double h, const double* f, double* u, int half_sweeps
  * z-high ([nx][ny]).  flux_match = 0 gives the interpolated guess without flux matching. */
 int mg_ghost_fill(const mg_hier* hier, int p, const double* const* u, double* ghosts,
                   int flux_match, void* stream);
+
+/* The R = order / 2 ghost layers of patch p for the operator of this order (Section 3.3, Tables 1
+ * and 2; the construction of mg_solve_hierarchy_ho) from u[p-1] and u[p] (natural order, as the
+ * caller holds them).  ghosts receives the 6 faces back to back: x-low, x-high ([R][ny][nz] each,
+ * layer 0 next to the face), y-low, y-high ([R][nx][nz]), z-low, z-high ([R][nx][ny]).
+ * flux_match = 0 gives the interpolated values without the flux shift. */
+int mg_ghost_fill_ho(const mg_hier* hier, int order, int p, const double* const* u, double* ghosts,
+                     int flux_match, void* stream);
 
 /* ----------------------------------------------------------------------------------------------
  * Measurement support

@@ -15,6 +15,8 @@
 // mixed-precision solve, whose FP64 residual (k_ho_resid32) and correction (k_ho_add32) are
 // separate kernels.  The FP64 arithmetic is the oracle's up to summation order.
 
+#include <algorithm>
+
 #include "mg_internal.h"
 
 namespace mgic {
@@ -357,6 +359,350 @@ void launch_ho_rnorm(const double* u, const double* f, int lg, double h, int ord
     else if (order == 4) k_ho_psum<2, 1><<<nb, kBlock, 0, st>>>(u, f, lg, h2, part);
     else k_ho_psum<3, 1><<<nb, kBlock, 0, st>>>(u, f, lg, h2, part);
     k_ho_reduce<<<1, kBlock, 0, st>>>(part, nb, out);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Higher-order Laplacians on nested patches (Section 3.3 with Tables 1 and 2), natural order, FP64.
+// A patch keeps R = order / 2 ghost layers per face (hoz_face_off), refreshed before each
+// half-sweep and residual by k_hoz_ghost: for every fine column in front of a face, a polynomial
+// of degree 2R through the 2R + 1 parent cells J - R .. J + R around its parent, along each
+// transverse axis in turn (the first, then the second), for each of the R parent layers outside
+// the face; then a polynomial of degree 2R normal to the face through those R values and the
+// first R + 1 fine cells, at the R ghost centres; then the ghosts of the 2 x 2 columns in front of
+// one parent face are shifted together so that the mean of their Table 2 fluxes equals the
+// parent's flux through that face, whose covered cells are the live means of their children.
+// ----------------------------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ size_t hoz_nat(const int* n, int x, int y, int z) {
+    return ((size_t)x * n[1] + y) * n[2] + z;
+}
+
+// value at (x, y, z) of a patch, with at most one coordinate outside [0, n): inside from v,
+// outside from the ghost layers
+__device__ __forceinline__ double hoz_val(const double* __restrict__ v, const double* __restrict__ g, const int* n,
+                                          int R, int x, int y, int z) {
+    const int q[3] = {x, y, z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (q[a] < 0 || q[a] >= n[a]) {
+            const int side = q[a] >= n[a];
+            const int layer = side ? q[a] - n[a] : -q[a] - 1;
+            const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+            return g[hoz_face_off(n, R, 2 * a + side) + ((size_t)layer * n[b] + q[b]) * n[c] + q[c]];
+        }
+    }
+    return v[hoz_nat(n, x, y, z)];
+}
+
+// sum_{s=1..R} w_s (((x-s) + (x+s)) + ((y-s) + (y+s))) + ((z-s) + (z+s))) on a patch with ghosts
+template <int R>
+__device__ __forceinline__ double hoz_off(const double* __restrict__ v, const double* __restrict__ g, const int* n,
+                                          int x, int y, int z) {
+    double acc = 0;
+#pragma unroll
+    for (int s = 1; s <= R; ++s) {
+        const double px = hoz_val(v, g, n, R, x - s, y, z) + hoz_val(v, g, n, R, x + s, y, z);
+        const double py = hoz_val(v, g, n, R, x, y - s, z) + hoz_val(v, g, n, R, x, y + s, z);
+        const double pz = hoz_val(v, g, n, R, x, y, z - s) + hoz_val(v, g, n, R, x, y, z + s);
+        acc += ho_w<R>(s) * ((px + py) + pz);
+    }
+    return acc;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__ pu, const double* __restrict__ u,
+                                                      double* __restrict__ g, HozPatch P, HozW W, int flux_match) {
+    const int* n = P.n;
+    const int face = (int)blockIdx.y;
+    const int a = face >> 1, side = face & 1;
+    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    const unsigned nc2 = (unsigned)n[c] / 2;
+    const unsigned lane = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned t = lane >> 2, q = lane & 3;
+    // every lane of a group takes part in the shuffles; lanes past the face repeat the last group
+    const unsigned ngroups = ((unsigned)n[b] / 2) * nc2;
+    const bool live = t < ngroups;
+    const unsigned tg = live ? t : ngroups - 1;
+    const int J = (int)(tg / nc2), K = (int)(tg - (unsigned)J * nc2);
+    const int jb = (int)(q >> 1), kc = (int)(q & 1);
+    const int Jp = P.off[b] + J, Kp = P.off[c] + K;
+    auto parent = [&](int ia, int ib, int ic) {
+        int qq[3];
+        qq[a] = ia;
+        qq[b] = ib;
+        qq[c] = ic;
+        if (P.pper)
+            for (int k = 0; k < 3; ++k) qq[k] = qq[k] < 0 ? qq[k] + P.pn[k] : (qq[k] >= P.pn[k] ? qq[k] - P.pn[k] : qq[k]);
+        return pu[hoz_nat(P.pn, qq[0], qq[1], qq[2])];
+    };
+    // parallel step on each outside parent layer (layer k at normal index on_k)
+    double A[R], O[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int on = side ? P.off[a] + n[a] / 2 + k : P.off[a] - 1 - k;
+        double acc = 0.0;
+        for (int dc = 0; dc <= 2 * R; ++dc) {
+            double ab = 0.0;
+            for (int db = 0; db <= 2 * R; ++db) ab += W.par[jb][db] * parent(on, Jp + db - R, Kp + dc - R);
+            acc += W.par[kc][dc] * ab;
+        }
+        A[k] = acc;
+        O[k] = parent(on, Jp, Kp);
+    }
+    // fine cells of the column inwards from the face: layers 0 .. 2R - 1
+    double v[2 * R];
+#pragma unroll
+    for (int i = 0; i < 2 * R; ++i) {
+        int p3[3];
+        p3[a] = side ? n[a] - 1 - i : i;
+        p3[b] = 2 * J + jb;
+        p3[c] = 2 * K + kc;
+        v[i] = u[hoz_nat(n, p3[0], p3[1], p3[2])];
+    }
+    double g0[R];
+#pragma unroll
+    for (int gl = 0; gl < R; ++gl) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < R; ++m) acc += W.nor[gl][m] * A[m];
+#pragma unroll
+        for (int i = 0; i <= R; ++i) acc += W.nor[gl][R + i] * v[i];
+        g0[gl] = acc;
+    }
+    double delta = 0.0;
+    if (flux_match) {
+        const double h = P.h;
+        double ff = 0.0;
+#pragma unroll
+        for (int m = 0; m < R; ++m) ff += W.F[m] * g0[R - 1 - m];
+#pragma unroll
+        for (int i = 0; i < R; ++i) ff += W.F[R + i] * v[i];
+        ff /= h;
+        const int base = (int)(threadIdx.x & 63) & ~3;
+        auto mean4 = [&](double x) {
+            const double x0 = __shfl(x, base, 64), x1 = __shfl(x, base + 1, 64);
+            const double x2 = __shfl(x, base + 2, 64), x3 = __shfl(x, base + 3, 64);
+            return ((x0 + x1) + (x2 + x3)) * 0.25;
+        };
+        const double mff = mean4(ff);
+        double fc = 0.0;
+#pragma unroll
+        for (int m = 0; m < R; ++m) fc += W.F[m] * O[R - 1 - m];
+#pragma unroll
+        for (int k = 0; k < R; ++k) fc += W.F[R + k] * (0.5 * mean4(v[2 * k] + v[2 * k + 1]));
+        fc /= 2.0 * h;
+        delta = (fc - mff) * h / W.S;
+    }
+    if (!live) return;
+    const size_t fo = hoz_face_off(n, R, face);
+#pragma unroll
+    for (int gl = 0; gl < R; ++gl)
+        g[fo + ((size_t)gl * n[b] + (2 * J + jb)) * n[c] + (2 * K + kc)] = g0[gl] + delta;
+}
+
+__device__ __forceinline__ void hoz_decode(const int* n, size_t t, int& x, int& y, int& z) {
+    z = (int)(t % (size_t)n[2]);
+    const size_t r = t / (size_t)n[2];
+    y = (int)(r % (size_t)n[1]);
+    x = (int)(r / (size_t)n[1]);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_hoz_half(const double* __restrict__ in, double* __restrict__ out,
+                                                     const double* __restrict__ f, const double* __restrict__ g,
+                                                     HozPatch P, double h2, int colour) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t cells = (size_t)P.n[0] * P.n[1] * P.n[2];
+    if (t >= cells) return;
+    int x, y, z;
+    hoz_decode(P.n, t, x, y, z);
+    if (((x + y + z) & 1) != colour) {
+        out[t] = in[t];
+        return;
+    }
+    out[t] = (h2 * f[t] - hoz_off<R>(in, g, P.n, x, y, z)) / (3.0 * HoW<R>::w0);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_hoz_rr(const double* __restrict__ u, const double* __restrict__ f,
+                                                   const double* __restrict__ g, HozPatch P, double h2,
+                                                   double* __restrict__ pu, double* __restrict__ pf,
+                                                   double* __restrict__ uold) {
+    const int cn[3] = {P.n[0] / 2, P.n[1] / 2, P.n[2] / 2};
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)cn[0] * cn[1] * cn[2]) return;
+    int X, Y, Z;
+    hoz_decode(cn, t, X, Y, Z);
+    double rs = 0.0, us = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e) {
+                const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + e;
+                const double uv = u[hoz_nat(P.n, x, y, z)];
+                const double lap = (hoz_off<R>(u, g, P.n, x, y, z) + 3.0 * HoW<R>::w0 * uv) / h2;
+                rs += f[hoz_nat(P.n, x, y, z)] - lap;
+                us += uv;
+            }
+    const size_t pi = hoz_nat(P.pn, P.off[0] + X, P.off[1] + Y, P.off[2] + Z);
+    const double um = us * 0.125;
+    pu[pi] = um;
+    uold[t] = um;
+    pf[pi] = rs * 0.125;
+}
+
+// FAS right-hand side on the covered box: periodic power-of-two level (PER) or a patch interior
+template <int R, bool PER>
+__global__ __launch_bounds__(kBlock) void k_hoz_fas(const double* __restrict__ u, double* __restrict__ f, int n0,
+                                                    int n1, int n2, int lo0, int lo1, int lo2, int c0, int c1, int c2,
+                                                    double h2) {
+    const int cn[3] = {c0, c1, c2}, n[3] = {n0, n1, n2};
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)c0 * c1 * c2) return;
+    int X, Y, Z;
+    hoz_decode(cn, t, X, Y, Z);
+    const int x = lo0 + X, y = lo1 + Y, z = lo2 + Z;
+    const size_t i = hoz_nat(n, x, y, z);
+    double off;
+    if constexpr (PER) {
+        const int lg = __builtin_ctz((unsigned)n0);
+        off = ho_off<R, double>(u, (unsigned)x, (unsigned)y, (unsigned)z, lg, (unsigned)n0 - 1);
+    } else {
+        off = hoz_off<R>(u, nullptr, n, x, y, z);   // the covered box keeps >= R cells from the faces
+    }
+    f[i] = f[i] + (off + 3.0 * HoW<R>::w0 * u[i]) / h2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hoz_prolong(double* __restrict__ u, HozPatch P,
+                                                        const double* __restrict__ pu,
+                                                        const double* __restrict__ uold) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)P.n[0] * P.n[1] * P.n[2]) return;
+    int x, y, z;
+    hoz_decode(P.n, t, x, y, z);
+    const int cn[3] = {P.n[0] / 2, P.n[1] / 2, P.n[2] / 2};
+    const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+    u[t] = u[t] + (pu[hoz_nat(P.pn, P.off[0] + X, P.off[1] + Y, P.off[2] + Z)] - uold[hoz_nat(cn, X, Y, Z)]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_hoz_restrict(const double* __restrict__ v, HozPatch P,
+                                                         double* __restrict__ pv) {
+    const int cn[3] = {P.n[0] / 2, P.n[1] / 2, P.n[2] / 2};
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)cn[0] * cn[1] * cn[2]) return;
+    int X, Y, Z;
+    hoz_decode(cn, t, X, Y, Z);
+    double s = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e) s += v[hoz_nat(P.n, 2 * X + a, 2 * Y + b, 2 * Z + e)];
+    pv[hoz_nat(P.pn, P.off[0] + X, P.off[1] + Y, P.off[2] + Z)] = s * 0.125;
+}
+
+template <int R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_hoz_psum(const double* __restrict__ v, const double* __restrict__ f,
+                                                     const double* __restrict__ g, int n0, int n1, int n2, int lo0,
+                                                     int lo1, int lo2, int c0, int c1, int c2, double h2,
+                                                     double* __restrict__ part) {
+    const int n[3] = {n0, n1, n2};
+    const size_t cells = (size_t)n0 * n1 * n2;
+    double acc = 0.0;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        hoz_decode(n, t, x, y, z);
+        if (x >= lo0 && x < lo0 + c0 && y >= lo1 && y < lo1 + c1 && z >= lo2 && z < lo2 + c2) continue;
+        double val;
+        if constexpr (MODE == 0) {
+            val = v[t];
+        } else if constexpr (MODE == 1) {
+            val = f[t] - (hoz_off<R>(v, g, n, x, y, z) + 3.0 * HoW<R>::w0 * v[t]) / h2;
+        } else {
+            const int lg = __builtin_ctz((unsigned)n0);
+            val = f[t] - (ho_off<R, double>(v, (unsigned)x, (unsigned)y, (unsigned)z, lg, (unsigned)n0 - 1) +
+                          3.0 * HoW<R>::w0 * v[t]) / h2;
+        }
+        acc += val * val;
+    }
+    const double s = ho_block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+}  // namespace
+
+#define HOZ_R(order, STMT1, STMT2, STMT3) \
+    do {                                  \
+        if ((order) == 2) { STMT1; }      \
+        else if ((order) == 4) { STMT2; } \
+        else { STMT3; }                   \
+    } while (0)
+
+void launch_hoz_ghost(const double* pu, const double* u, double* g, const HozPatch& P, const HozW& W, int order,
+                      int flux_match, hipStream_t st) {
+    const size_t most = std::max({(size_t)(P.n[1] / 2) * (P.n[2] / 2), (size_t)(P.n[0] / 2) * (P.n[2] / 2),
+                                  (size_t)(P.n[0] / 2) * (P.n[1] / 2)});
+    const dim3 grid(grid_for(4 * most), 6);
+    HOZ_R(order, (k_hoz_ghost<1><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)),
+          (k_hoz_ghost<2><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)),
+          (k_hoz_ghost<3><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)));
+}
+
+void launch_hoz_half(const double* in, double* out, const double* f, const double* g, const HozPatch& P, int order,
+                     int colour, hipStream_t st) {
+    const int grid = grid_for((size_t)P.n[0] * P.n[1] * P.n[2]);
+    const double h2 = P.h * P.h;
+    HOZ_R(order, (k_hoz_half<1><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)),
+          (k_hoz_half<2><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)),
+          (k_hoz_half<3><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)));
+}
+
+void launch_hoz_resid_restrict(const double* u, const double* f, const double* g, const HozPatch& P, int order,
+                               double* pu, double* pf, double* uold, hipStream_t st) {
+    const int grid = grid_for((size_t)(P.n[0] / 2) * (P.n[1] / 2) * (P.n[2] / 2));
+    const double h2 = P.h * P.h;
+    HOZ_R(order, (k_hoz_rr<1><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
+          (k_hoz_rr<2><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
+          (k_hoz_rr<3><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)));
+}
+
+void launch_hoz_fas(const double* u, double* f, const int* n, int periodic, const int* lo, const int* cn, double h,
+                    int order, hipStream_t st) {
+    const int grid = grid_for((size_t)cn[0] * cn[1] * cn[2]);
+    const double h2 = h * h;
+#define HOZ_FAS_ARGS u, f, n[0], n[1], n[2], lo[0], lo[1], lo[2], cn[0], cn[1], cn[2], h2
+    if (periodic)
+        HOZ_R(order, (k_hoz_fas<1, true><<<grid, kBlock, 0, st>>>(HOZ_FAS_ARGS)),
+              (k_hoz_fas<2, true><<<grid, kBlock, 0, st>>>(HOZ_FAS_ARGS)),
+              (k_hoz_fas<3, true><<<grid, kBlock, 0, st>>>(HOZ_FAS_ARGS)));
+    else
+        HOZ_R(order, (k_hoz_fas<1, false><<<grid, kBlock, 0, st>>>(HOZ_FAS_ARGS)),
+              (k_hoz_fas<2, false><<<grid, kBlock, 0, st>>>(HOZ_FAS_ARGS)),
+              (k_hoz_fas<3, false><<<grid, kBlock, 0, st>>>(HOZ_FAS_ARGS)));
+#undef HOZ_FAS_ARGS
+}
+
+void launch_hoz_prolong(double* u, const HozPatch& P, const double* pu, const double* uold, hipStream_t st) {
+    k_hoz_prolong<<<grid_for((size_t)P.n[0] * P.n[1] * P.n[2]), kBlock, 0, st>>>(u, P, pu, uold);
+}
+
+void launch_hoz_restrict(const double* v, const HozPatch& P, double* pv, hipStream_t st) {
+    k_hoz_restrict<<<grid_for((size_t)(P.n[0] / 2) * (P.n[1] / 2) * (P.n[2] / 2)), kBlock, 0, st>>>(v, P, pv);
+}
+
+void launch_hoz_psum(int mode, const double* v, const double* f, const double* g, const int* n, const int* lo,
+                     const int* cn, double h, int order, double* part, hipStream_t st) {
+    const int nb = kHozParts;
+    const double h2 = h * h;
+#define HOZ_PS_ARGS v, f, g, n[0], n[1], n[2], lo[0], lo[1], lo[2], cn[0], cn[1], cn[2], h2, part
+    if (mode == 0) k_hoz_psum<1, 0><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS);
+    else if (mode == 1)
+        HOZ_R(order, (k_hoz_psum<1, 1><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)),
+              (k_hoz_psum<2, 1><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)),
+              (k_hoz_psum<3, 1><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)));
+    else
+        HOZ_R(order, (k_hoz_psum<1, 2><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)),
+              (k_hoz_psum<2, 2><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)),
+              (k_hoz_psum<3, 2><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)));
+#undef HOZ_PS_ARGS
 }
 
 }  // namespace mgic

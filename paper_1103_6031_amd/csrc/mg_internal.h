@@ -382,4 +382,50 @@ void launch_ho_sub(const double* a, const double* sum, double* out, int lg, doub
 void launch_ho_rnorm(const double* u, const double* f, int lg, double h, int order, double* part, double* out,
                      hipStream_t st);
 
+// ----------------------------------------------------------------------------------------------
+// higher-order Laplacians on nested patches (k_highorder.hip): natural order, FP64.  A patch of
+// radius-R operator keeps R ghost layers per face: x-low, x-high [R][ny][nz], y-low, y-high
+// [R][nx][nz], z-low, z-high [R][nx][ny], layer 0 next to the face.
+// ----------------------------------------------------------------------------------------------
+struct HozPatch {
+    int n[3];      // cells per axis (even)
+    int off[3];    // first covered parent cell
+    int pn[3];     // parent dims
+    int pper;      // the parent is the periodic base
+    double h;      // spacing (the parent's is 2h)
+};
+// ghost-zone weights for radius R: Lagrange weights of the parallel step (nodes -R..R, at child
+// offsets -1/4 and +1/4), of the normal step for each ghost layer (R coarse nodes, then R + 1 fine
+// ones) and the Table 2 flux operator with the sum of its R ghost-side weights
+struct HozW {
+    double par[2][7];
+    double nor[3][7];
+    double F[6];
+    double S;
+};
+__host__ __device__ inline size_t hoz_face_off(const int* n, int R, int face) {
+    const size_t fx = (size_t)R * n[1] * n[2], fy = (size_t)R * n[0] * n[2], fz = (size_t)R * n[0] * n[1];
+    const size_t o[7] = {0, fx, 2 * fx, 2 * fx + fy, 2 * fx + 2 * fy, 2 * fx + 2 * fy + fz, 2 * fx + 2 * fy + 2 * fz};
+    return o[face];
+}
+void launch_hoz_ghost(const double* pu, const double* u, double* g, const HozPatch& P, const HozW& W, int order,
+                      int flux_match, hipStream_t st);
+void launch_hoz_half(const double* in, double* out, const double* f, const double* g, const HozPatch& P, int order,
+                     int colour, hipStream_t st);
+// steps 3-5: parent u and f on the covered cells := the means of the children's u and residual,
+// uold := the same mean of u
+void launch_hoz_resid_restrict(const double* u, const double* f, const double* g, const HozPatch& P, int order,
+                               double* pu, double* pf, double* uold, hipStream_t st);
+// step 6 on the covered box of a level: f += L u (periodic power-of-two base, or a patch whose
+// covered box keeps >= R cells from its faces)
+void launch_hoz_fas(const double* u, double* f, const int* n, int periodic, const int* lo, const int* cn, double h,
+                    int order, hipStream_t st);
+void launch_hoz_prolong(double* u, const HozPatch& P, const double* pu, const double* uold, hipStream_t st);
+void launch_hoz_restrict(const double* v, const HozPatch& P, double* pv, hipStream_t st);
+// partial sums over the cells outside the box lo + [0, cn) (cn = 0: every cell) into
+// part[0 .. kHozParts): MODE 0 v^2; MODE 1 r^2 of a patch (g its ghosts); MODE 2 r^2 of the base
+constexpr int kHozParts = 2048;
+void launch_hoz_psum(int mode, const double* v, const double* f, const double* g, const int* n, const int* lo,
+                     const int* cn, double h, int order, double* part, hipStream_t st);
+
 }  // namespace mgic

@@ -1896,6 +1896,317 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
 
 }  // extern "C"
 
+// ----------------------------------------------------------------------------------------------
+// higher-order Laplacians on nested patches (Section 3.3 with Tables 1 and 2), FP64: patches in
+// natural order with R = order / 2 ghost layers per face; the base and its coarsenings run the
+// periodic higher-order V-cycle above
+// ----------------------------------------------------------------------------------------------
+struct HozLevel {
+    HozPatch P{};
+    double *u = nullptr, *f = nullptr, *tmp = nullptr, *g = nullptr, *uold = nullptr;
+    int cov_lo[3] = {0, 0, 0}, cov_n[3] = {0, 0, 0};   // box covered by the next patch (n = 0: none)
+};
+
+struct HozPlan {
+    int order = 4, R = 2, np = 0, N0 = 0;
+    double h0 = 1.0;
+    double* ubase = nullptr;
+    HoPlan base;                      // base.u[0] = ubase, base.f[0] = the base right-hand side
+    std::vector<HozLevel> pat;        // pat[p - 1] = patch p
+    int base_cov_lo[3] = {0, 0, 0}, base_cov_n[3] = {0, 0, 0};
+    HozW W{};
+    double* part = nullptr;           // kHozParts per level (at least kHoParts)
+    double* scal = nullptr;           // [0] sum f, [1] |f|^2, [2] |r|^2, [3] sum u
+};
+
+static std::vector<double> lagrange_w(const std::vector<double>& nodes, double x) {
+    std::vector<double> w;
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        double num = 1.0, den = 1.0;
+        for (size_t j = 0; j < nodes.size(); ++j)
+            if (j != i) {
+                num *= x - nodes[j];
+                den *= nodes[i] - nodes[j];
+            }
+        w.push_back(num / den);
+    }
+    return w;
+}
+
+static HozW hoz_weights(int order) {
+    const int R = order / 2;
+    HozW W{};
+    std::vector<double> par;
+    for (int k = -R; k <= R; ++k) par.push_back(k);
+    for (int side = 0; side < 2; ++side) {
+        const std::vector<double> w = lagrange_w(par, side ? 0.25 : -0.25);
+        for (size_t i = 0; i < w.size(); ++i) W.par[side][i] = w[i];
+    }
+    std::vector<double> nodes;
+    for (int k = 0; k < R; ++k) nodes.push_back(-(2.0 * k + 1.0));
+    for (int i = 0; i <= R; ++i) nodes.push_back(i + 0.5);
+    for (int gl = 0; gl < R; ++gl) {
+        const std::vector<double> w = lagrange_w(nodes, -(gl + 0.5));
+        for (size_t i = 0; i < w.size(); ++i) W.nor[gl][i] = w[i];
+    }
+    // Table 2: flux operators of order 1, 3, 5 over the 2R cells around a face, outside first
+    static const int F1[2] = {-1, 1}, F3[4] = {-1, 15, -15, 1}, F5[6] = {2, -25, 245, -245, 25, -2};
+    const int* F = R == 1 ? F1 : (R == 2 ? F3 : F5);
+    const double den = R == 1 ? 1.0 : (R == 2 ? 12.0 : 180.0);
+    W.S = 0.0;
+    for (int m = 0; m < 2 * R; ++m) {
+        W.F[m] = F[m] / den;
+        if (m < R) W.S += W.F[m];
+    }
+    return W;
+}
+
+static int hoz_plan(const mg_hier* H, int order, Carver& cv, HozPlan& Z) {
+    if (int v = validate_hier(H)) return v;
+    if (order != 2 && order != 4 && order != 6) return fail(MG_EINVAL, "order must be 2, 4 or 6");
+    const int R = order / 2;
+    Z.order = order;
+    Z.R = R;
+    Z.np = H->nlev - 1;
+    Z.N0 = H->lev[0].n[0];
+    Z.h0 = H->lev[0].h;
+    if (log2_exact(Z.N0) < 1 || Z.N0 > 1024) return fail(MG_EINVAL, "higher-order hierarchy: base n must be a power of two in 2..1024");
+    for (int p = 1; p <= Z.np; ++p)
+        for (int a = 0; a < 3; ++a) {
+            if (H->lev[p].n[a] < 2 * R) return fail(MG_EINVAL, "higher-order hierarchy: patch sizes must be >= order");
+            if (p == 1 && Z.N0 - H->lev[1].n[a] / 2 < R)
+                return fail(MG_EINVAL, "higher-order hierarchy: the base must leave >= order/2 cells uncovered per axis");
+        }
+    const size_t nb = (size_t)Z.N0 * Z.N0 * Z.N0;
+    Z.ubase = cv.take<double>(nb);
+    if (int rc = ho_plan(Z.N0, Z.h0, order, cv, Z.ubase, Z.base)) return rc;
+    Z.pat.assign(Z.np, HozLevel{});
+    for (int p = 1; p <= Z.np; ++p) {
+        HozLevel& L = Z.pat[p - 1];
+        for (int a = 0; a < 3; ++a) {
+            L.P.n[a] = H->lev[p].n[a];
+            L.P.off[a] = H->lev[p].off[a];
+            L.P.pn[a] = H->lev[p - 1].n[a];
+        }
+        L.P.pper = p == 1;
+        L.P.h = Z.h0 / (double)(1 << p);
+        const size_t c = (size_t)L.P.n[0] * L.P.n[1] * L.P.n[2];
+        L.u = cv.take<double>(c);
+        L.f = cv.take<double>(c);
+        L.tmp = cv.take<double>(c);
+        L.g = cv.take<double>(hoz_face_off(L.P.n, R, 6));
+        L.uold = cv.take<double>(c / 8);
+    }
+    for (int p = 1; p <= Z.np; ++p) {   // the box of level p - 1 covered by patch p
+        int* lo = p == 1 ? Z.base_cov_lo : Z.pat[p - 2].cov_lo;
+        int* cn = p == 1 ? Z.base_cov_n : Z.pat[p - 2].cov_n;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = H->lev[p].off[a];
+            cn[a] = H->lev[p].n[a] / 2;
+        }
+    }
+    Z.W = hoz_weights(order);
+    // partial sums: kHozParts per level for the composite sums, kHoParts for the base sums
+    Z.part = cv.take<double>(std::max((size_t)kHozParts * (Z.np + 1), (size_t)kHoParts));
+    Z.scal = cv.take<double>(8);
+    return MG_OK;
+}
+
+static double* hoz_pu(HozPlan& Z, int p) { return p == 1 ? Z.base.u[0] : Z.pat[p - 2].u; }
+static double* hoz_pf(HozPlan& Z, int p) { return p == 1 ? Z.base.f[0] : Z.pat[p - 2].f; }
+
+// covered cells of every level := the mean of their children, finest first (u or f arrays)
+static void hoz_restrict_up(HozPlan& Z, bool of_f, hipStream_t st) {
+    for (int p = Z.np; p >= 1; --p) {
+        HozLevel& L = Z.pat[p - 1];
+        launch_hoz_restrict(of_f ? L.f : L.u, L.P, of_f ? hoz_pf(Z, p) : hoz_pu(Z, p), st);
+    }
+}
+
+// composite sum of squares (mode 0: v = f; mode 1: the residual) over the uncovered cells of every
+// level, volume-weighted, into scal[slot]
+static void hoz_composite_sq(HozPlan& Z, int mode, int slot, hipStream_t st) {
+    SegList sg{};
+    sg.n = Z.np + 1;
+    const int nb3[3] = {Z.N0, Z.N0, Z.N0};
+    for (int p = 0; p <= Z.np; ++p) {
+        double* part = Z.part + (size_t)p * kHozParts;
+        if (p == 0) {
+            launch_hoz_psum(mode == 0 ? 0 : 2, mode == 0 ? Z.base.f[0] : Z.base.u[0], Z.base.f[0], nullptr, nb3,
+                            Z.base_cov_lo, Z.base_cov_n, Z.h0, Z.order, part, st);
+        } else {
+            HozLevel& L = Z.pat[p - 1];
+            if (mode == 1) launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st);
+            launch_hoz_psum(mode == 0 ? 0 : 1, mode == 0 ? L.f : L.u, L.f, L.g, L.P.n, L.cov_lo, L.cov_n, L.P.h,
+                            Z.order, part, st);
+        }
+        const double h = p == 0 ? Z.h0 : Z.pat[p - 1].P.h;
+        sg.off[p] = p * kHozParts;
+        sg.cnt[p] = kHozParts;
+        sg.w[p] = h * h * h;
+    }
+    launch_finalize(Z.part, sg, Z.scal + slot, st);
+}
+
+static void hoz_smooth(HozPlan& Z, int p, int sweeps, hipStream_t st) {
+    HozLevel& L = Z.pat[p - 1];
+    for (int s = 0; s < sweeps; ++s)
+        for (int c = 0; c < 2; ++c) {
+            const double* in = c == 0 ? L.u : L.tmp;
+            double* out = c == 0 ? L.tmp : L.u;
+            launch_hoz_ghost(hoz_pu(Z, p), in, L.g, L.P, Z.W, Z.order, 1, st);
+            launch_hoz_half(in, out, L.f, L.g, L.P, Z.order, c, st);
+        }
+}
+
+static void hoz_vcycle(HozPlan& Z, int p, int nu1, int nu2, hipStream_t st) {
+    if (p == 0) {
+        ho_vcycle<double>(Z.base, nu1, nu2, st);
+        return;
+    }
+    HozLevel& L = Z.pat[p - 1];
+    hoz_smooth(Z, p, nu1, st);                                                     // step 2
+    launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st);
+    launch_hoz_resid_restrict(L.u, L.f, L.g, L.P, Z.order, hoz_pu(Z, p), hoz_pf(Z, p), L.uold, st);   // 3-5
+    const int* lo = p == 1 ? Z.base_cov_lo : Z.pat[p - 2].cov_lo;
+    const int* cn = p == 1 ? Z.base_cov_n : Z.pat[p - 2].cov_n;
+    const int nb3[3] = {Z.N0, Z.N0, Z.N0};
+    launch_hoz_fas(hoz_pu(Z, p), hoz_pf(Z, p), p == 1 ? nb3 : Z.pat[p - 2].P.n, p == 1, lo, cn, 2.0 * L.P.h, Z.order,
+                   st);                                                            // step 6
+    hoz_vcycle(Z, p - 1, nu1, nu2, st);                                            // step 7
+    launch_hoz_prolong(L.u, L.P, hoz_pu(Z, p), L.uold, st);                        // step 8
+    hoz_smooth(Z, p, nu2, st);                                                     // step 9
+}
+
+static int hoz_read(const double* dev, int count, double* out, hipStream_t st) { return ho_read(dev, count, out, st); }
+
+extern "C" {
+
+size_t mg_ho_hierarchy_workspace_bytes(const mg_hier* hier, int order) {
+    HozPlan Z;
+    Carver cv(nullptr);
+    if (hoz_plan(hier, order, cv, Z)) return 0;
+    return cv.off;
+}
+
+int mg_solve_hierarchy_ho(const mg_hier* hier, int order, const double* const* f, double* const* u,
+                          const mg_opts* o, mg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (!o) return fail(MG_EINVAL, "options are NULL");
+    if (!f || !u) return fail(MG_EINVAL, "f/u pointer arrays are NULL");
+    if (o->max_cycles < 0) return fail(MG_EINVAL, "max_cycles < 0");
+    if (o->prec != MG_FP64) return fail(MG_EINVAL, "the higher-order hierarchy solve is FP64 only");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 64) return fail(MG_EINVAL, "nu1/nu2 out of range");
+    if (o->flags & ~(MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES | MG_NO_GRAPH)) return fail(MG_EINVAL, "unknown flags");
+    HozPlan Z;
+    Carver size_cv(nullptr);
+    int rc = hoz_plan(hier, order, size_cv, Z);
+    if (rc) return rc;
+    for (int p = 0; p < hier->nlev; ++p)
+        if (!f[p] || !u[p]) return fail(MG_EINVAL, "level pointer is NULL");
+    if (!ws || ws_bytes < size_cv.off) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(size_cv.off));
+    if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    Carver cv(ws);
+    hoz_plan(hier, order, cv, Z);
+    (void)hipGetLastError();
+    const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
+    const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
+    const size_t nbase = (size_t)Z.N0 * Z.N0 * Z.N0;
+    auto cells = [&](int p) {
+        return p == 0 ? nbase : (size_t)Z.pat[p - 1].P.n[0] * Z.pat[p - 1].P.n[1] * Z.pat[p - 1].P.n[2];
+    };
+    auto uarr = [&](int p) { return p == 0 ? Z.base.u[0] : Z.pat[p - 1].u; };
+    auto farr = [&](int p) { return p == 0 ? Z.base.f[0] : Z.pat[p - 1].f; };
+    // source preparation: working copies, covered cells from their children, composite mean removed
+    for (int p = 0; p <= Z.np; ++p)
+        MG_HIP(hipMemcpyAsync(farr(p), f[p], cells(p) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hoz_restrict_up(Z, true, st);
+    launch_ho_sum(Z.base.f[0], Z.base.lg, Z.part, Z.scal + 0, st);
+    for (int p = 0; p <= Z.np; ++p) launch_sub_mean<double>(farr(p), cells(p), Z.scal + 0, 1.0 / (double)nbase, st);
+    hoz_composite_sq(Z, 0, 1, st);
+    for (int p = 0; p <= Z.np; ++p) {
+        if (guess) MG_HIP(hipMemcpyAsync(uarr(p), u[p], cells(p) * sizeof(double), hipMemcpyDeviceToDevice, st));
+        else launch_fill<double>(uarr(p), cells(p), 0.0, st);
+    }
+    mg_stats S;
+    std::memset(&S, 0, sizeof(S));
+    for (double& v : S.res_hist) v = NAN;
+    double fnorm2 = 0.0;
+    if (!fixed) {
+        double fs[2];
+        if ((rc = hoz_read(Z.scal, 2, fs, st))) return rc;
+        S.f_mean_removed = fs[0] / (double)nbase;
+        fnorm2 = fs[1];
+        if (!std::isfinite(fs[0]) || !std::isfinite(fs[1])) {
+            S.rel_res = NAN;
+            if (stats) *stats = S;
+            return fail(MG_EDIVERGED, "right-hand side contains NaN or Inf");
+        }
+    }
+    long long upc = 0;
+    for (int l = 0; l < Z.base.lg; ++l) upc += (long long)(o->nu1 + o->nu2) << (3 * (Z.base.lg - l));
+    for (int p = 1; p <= Z.np; ++p) upc += (long long)(o->nu1 + o->nu2) * (long long)cells(p);
+    double rel = NAN, prev = INFINITY;
+    int grow = 0, status = MG_ENOCONV, cycles = 0;
+    auto check = [&]() -> int {
+        hoz_restrict_up(Z, false, st);
+        hoz_composite_sq(Z, 1, 2, st);
+        double r2;
+        if (int e = hoz_read(Z.scal + 2, 1, &r2, st)) return e;
+        rel = fnorm2 > 0 ? std::sqrt(r2 / fnorm2) : 0.0;
+        if (cycles >= 1 && cycles <= 64) S.res_hist[cycles - 1] = rel;
+        if (!std::isfinite(rel)) return MG_EDIVERGED;
+        grow = rel > prev ? grow + 1 : 0;
+        prev = rel;
+        if (grow >= 3) return MG_EDIVERGED;
+        return rel <= o->tol ? MG_OK : 1;
+    };
+    if (guess && !fixed) {
+        const int c = check();
+        if (c == MG_EHIP) return c;
+        if (c == MG_OK || c == MG_EDIVERGED) status = c;
+    }
+    while (status == MG_ENOCONV && cycles < o->max_cycles) {
+        hoz_vcycle(Z, Z.np, o->nu1, o->nu2, st);
+        ++cycles;
+        S.cell_updates += upc;
+        if (fixed) continue;
+        const int c = check();
+        if (c == MG_EHIP) return c;
+        if (c == MG_OK || c == MG_EDIVERGED) status = c;
+    }
+    if (fixed) status = MG_OK;
+    // gauge: covered cells from their children, composite (= base) mean removed, copy back
+    hoz_restrict_up(Z, false, st);
+    launch_ho_sum(Z.base.u[0], Z.base.lg, Z.part, Z.scal + 3, st);
+    for (int p = 0; p <= Z.np; ++p) {
+        launch_sub_mean<double>(uarr(p), cells(p), Z.scal + 3, 1.0 / (double)nbase, st);
+        MG_HIP(hipMemcpyAsync(u[p], uarr(p), cells(p) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    MG_HIP(hipGetLastError());
+    if (fixed) MG_HIP(hipStreamSynchronize(st));
+    S.cycles = cycles;
+    S.rel_res = fixed ? NAN : rel;
+    if (stats) *stats = S;
+    if (status == MG_ENOCONV) return fail(MG_ENOCONV, "no convergence within max_cycles");
+    if (status == MG_EDIVERGED) return fail(MG_EDIVERGED, "residual diverged");
+    return MG_OK;
+}
+
+int mg_ghost_fill_ho(const mg_hier* hier, int order, int p, const double* const* u, double* ghosts, int flux_match,
+                     void* stream) {
+    HozPlan Z;
+    Carver cv(nullptr);
+    if (int rc = hoz_plan(hier, order, cv, Z)) return rc;
+    if (p < 1 || p >= hier->nlev) return fail(MG_EINVAL, "p must name a patch");
+    if (!u || !u[p] || !u[p - 1] || !ghosts) return fail(MG_EINVAL, "NULL argument");
+    launch_hoz_ghost(u[p - 1], u[p], ghosts, Z.pat[p - 1].P, Z.W, order, flux_match ? 1 : 0, (hipStream_t)stream);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
+}  // extern "C"
+
 extern "C" {
 
 const char* mg_last_error(void) { return g_err.c_str(); }

@@ -70,6 +70,11 @@ _sig = {
     "mg_ho_workspace_bytes": (_sz, [ctypes.c_int, ctypes.c_int]),
     "mg_solve_level_ho": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P,
                                          ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_ho_hierarchy_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier), ctypes.c_int]),
+    "mg_solve_hierarchy_ho": (ctypes.c_int, [ctypes.POINTER(mg_hier), ctypes.c_int, _PP, _PP, ctypes.POINTER(mg_opts),
+                                             ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_ghost_fill_ho": (ctypes.c_int, [ctypes.POINTER(mg_hier), ctypes.c_int, ctypes.c_int, _PP, _P, ctypes.c_int,
+                                        _P]),
     "mg_residual_hierarchy": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _PP,
                                              ctypes.POINTER(ctypes.c_double), _P, _sz, _P]),
     "lpt_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier), ctypes.c_int]),
@@ -290,6 +295,58 @@ def mg_solve_hierarchy_noalloc(hier: Hier, f: Sequence[torch.Tensor], u: Sequenc
     if check:
         _check(rc, st.to_dict())
     return u, st.to_dict()
+
+
+def mg_ho_hierarchy_workspace_bytes(hier: Hier, order: int) -> int:
+    H = hier.c_struct()
+    n = _lib.mg_ho_hierarchy_workspace_bytes(ctypes.byref(H), int(order))
+    if n == 0:
+        raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
+    return n
+
+
+def mg_solve_hierarchy_ho(hier: Hier, order: int, f: Sequence[torch.Tensor], u=None, opts=None, workspace=None,
+                          stream=None, check=True):
+    """Composite solve with the order-2/4/6 Laplacian on a nested hierarchy.  Returns (u list, stats dict)."""
+    o = opts or make_opts()
+    if u is None:
+        u = [torch.empty_like(x) for x in f]
+    H = hier.c_struct()
+    ws = _ws(workspace, mg_ho_hierarchy_workspace_bytes(hier, order))
+    fp, _fa = _ptr_array([_dev(x, "f") for x in f])
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    st = mg_stats()
+    rc = _lib.mg_solve_hierarchy_ho(ctypes.byref(H), int(order), fp, up, ctypes.byref(o), ctypes.byref(st),
+                                    ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream))
+    if check:
+        _check(rc, st.to_dict())
+    return u, st.to_dict()
+
+
+def mg_ghost_fill_ho(hier: Hier, order: int, p: int, u, flux_match=True, ghosts=None, stream=None):
+    """The order/2 ghost layers of patch p (faces back to back, see split_ghosts_ho)."""
+    R = order // 2
+    nx, ny, nz = hier.dims(p)
+    total = 2 * R * (ny * nz + nx * nz + nx * ny)
+    if ghosts is None:
+        ghosts = torch.empty(total, dtype=torch.float64, device=u[0].device)
+    H = hier.c_struct()
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    _check(_lib.mg_ghost_fill_ho(ctypes.byref(H), int(order), int(p), up, _dev(ghosts, "ghosts"),
+                                 1 if flux_match else 0, _stream(stream)))
+    return ghosts
+
+
+def split_ghosts_ho(hier: Hier, order: int, p: int, g):
+    """View the 6 ghost faces as [(R,ny,nz), (R,ny,nz), (R,nx,nz), (R,nx,nz), (R,nx,ny), (R,nx,ny)]."""
+    R = order // 2
+    nx, ny, nz = hier.dims(p)
+    shapes = [(R, ny, nz), (R, ny, nz), (R, nx, nz), (R, nx, nz), (R, nx, ny), (R, nx, ny)]
+    out, o = [], 0
+    for s in shapes:
+        out.append(g[o:o + s[0] * s[1] * s[2]].view(*s))
+        o += s[0] * s[1] * s[2]
+    return out
 
 
 def mg_residual_hierarchy(hier: Hier, f, u, r=None, workspace=None, stream=None):
