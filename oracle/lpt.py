@@ -10,6 +10,9 @@ Section 3.1 of the paper:
   tau = -1/2 sum_{i,j} [ (Phi_,ij)^2 - Phi_,ii Phi_,jj ], evaluated "using finite
   differences".
 
+The gradient is Table 1's stencil of order 4 (the default) or 6; the same order is used for the
+second derivatives of tau.
+
 Readings:
 * Stencil for the second derivatives: D_ij = G_i o G_j (the fourth-order
   gradient applied twice) for all i, j including i = j.  This makes tau the
@@ -33,23 +36,24 @@ Readings:
 
 import numpy as np
 
-from .stencil import grad4
+from .stencil import grad4, grad
 
 
-def displacement(phi, h, scale=1.0):
-    """psi_c = scale * G4_c phi for c = x, y, z (periodic); returns (3, ...) array."""
-    return np.stack([scale * grad4(phi, h, a) for a in range(3)])
+def displacement(phi, h, scale=1.0, order=4):
+    """psi_c = scale * G_c phi for c = x, y, z (periodic; Table 1 gradient of order 4 or 6);
+    returns (3, ...) array."""
+    return np.stack([scale * grad(phi, h, a, order) for a in range(3)])
 
 
-def second_derivatives(phi, h):
-    """D[i][j] = G4_i (G4_j phi) for all i, j (periodic)."""
-    g = [grad4(phi, h, j) for j in range(3)]
-    return [[grad4(g[j], h, i) for j in range(3)] for i in range(3)]
+def second_derivatives(phi, h, order=4):
+    """D[i][j] = G_i (G_j phi) for all i, j (periodic)."""
+    g = [grad(phi, h, j, order) for j in range(3)]
+    return [[grad(g[j], h, i, order) for j in range(3)] for i in range(3)]
 
 
-def tau(phi, h):
+def tau(phi, h, order=4):
     """Second-order source: sum_{i>j} (D_ii D_jj - D_ij^2)."""
-    D = second_derivatives(phi, h)
+    D = second_derivatives(phi, h, order)
     t = np.zeros_like(phi)
     for i in range(3):
         for j in range(i):

@@ -3,8 +3,9 @@
 Test infrastructure only (see ``oracle/__init__.py``).
 
 Sources in the paper:
-* Table 1 (Section 3.2): 1-D second-order Laplacian [1 -2 1] / h^2 and
-  fourth-order gradient [1 -8 0 8 -1] / (12 h), with their Fourier symbols.
+* Table 1 (Section 3.2): 1-D second-order Laplacian [1 -2 1] / h^2, the
+  fourth-order gradient [1 -8 0 8 -1] / (12 h) and the sixth-order gradient
+  [-1 9 -45 0 45 -9 1] / (60 h).
 * Section 3.4: three-dimensional operators are built from the 1-D ones along
   the three axes.  Reading: the 3-D Laplacian is the SUM of the 1-D second
   differences over the axes (the 7-point Laplacian); the gradient component
@@ -49,6 +50,30 @@ def grad4(u, h, axis):
         if w != 0.0:
             acc = acc + w * np.roll(u, -off, axis)
     return acc / (12.0 * h)
+
+
+G6_WEIGHTS = (-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0)  # Table 1, order 6, offsets -3..+3, times 1/60
+
+
+def grad6(u, h, axis):
+    """Sixth-order central gradient along ``axis`` (Table 1, order 6), periodic.
+
+    (-u[i-3] + 9 u[i-2] - 45 u[i-1] + 45 u[i+1] - 9 u[i+2] + u[i+3]) / (60 h)
+    """
+    acc = np.zeros_like(u)
+    for off, w in zip(range(-3, 4), G6_WEIGHTS):
+        if w != 0.0:
+            acc = acc + w * np.roll(u, -off, axis)
+    return acc / (60.0 * h)
+
+
+def grad(u, h, axis, order=4):
+    """Table 1 gradient of order 4 or 6 along ``axis``, periodic."""
+    if order == 4:
+        return grad4(u, h, axis)
+    if order == 6:
+        return grad6(u, h, axis)
+    raise ValueError("gradient order must be 4 or 6")
 
 
 def restrict_mean8(v):

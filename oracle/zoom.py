@@ -43,9 +43,10 @@ Readings (the paper is silent or ambiguous here):
   Covered coarse cells are the mean of their children; the composite mean of
   f is removed first; the residual norm is
   sqrt(sum_fine r^2 h^3 + sum_uncovered r^2 H^3) / (same for f).
-* Post-solve ghosts for gradients (width 2) and for tau (width 4), edges and
-  corners included, are coarse-only tri-quadratic interpolations of the parent
-  (whose covered cells hold the mean of their children).
+* Post-solve ghosts for gradients (width 2, or 3 with the sixth-order gradient)
+  and for tau (width 4, or 6), edges and corners included, are coarse-only
+  tri-quadratic interpolations of the parent (whose covered cells hold the mean
+  of their children).
 """
 
 import numpy as np
@@ -326,37 +327,44 @@ def wide_ghosted(H, v, p, R):
     return vp
 
 
-def _grad_padded(vp, h, axis, R):
-    """Table 1 order-4 gradient of a padded array on its interior shrunk by R."""
+def _grad_padded(vp, h, axis, R, order=4):
+    """Table 1 gradient (order 4 or 6) of a padded array on its interior shrunk by R."""
+    weights, den = ((1.0, -8.0, 0.0, 8.0, -1.0), 12.0) if order == 4 else \
+        ((-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0), 60.0)
+    half = len(weights) // 2
     n = [s - 2 * R for s in vp.shape]
     out = np.zeros(n)
-    for off, w in zip(range(-2, 3), (1.0, -8.0, 0.0, 8.0, -1.0)):
+    for off, w in zip(range(-half, half + 1), weights):
         if w == 0.0:
             continue
         sl = [slice(R, R + n[a]) for a in range(3)]
         sl[axis] = slice(R + off, R + off + n[axis])
         out = out + w * vp[tuple(sl)]
-    return out / (12.0 * h)
+    return out / (den * h)
 
 
-def displacement_hierarchy(H, phi, scale=1.0):
-    """psi = scale * G4 phi on every level (base periodic; patches via width-2 ghosts)."""
+def displacement_hierarchy(H, phi, scale=1.0, order=4):
+    """psi = scale * G phi on every level (Table 1 gradient of order 4 or 6; base periodic;
+    patches via ghosts of width order / 2)."""
+    from .stencil import grad
+    rg = order // 2
     phi = [a.copy() for a in phi]
     restrict_bottom_up(H, phi)
     out = []
     for p in range(H.P + 1):
         if p == 0:
-            out.append(np.stack([scale * grad4(phi[0], H.h[0], a) for a in range(3)]))
+            out.append(np.stack([scale * grad(phi[0], H.h[0], a, order) for a in range(3)]))
         else:
-            vp = wide_ghosted(H, phi, p, 2)
-            out.append(np.stack([scale * _grad_padded(vp, H.h[p], a, 2) for a in range(3)]))
+            vp = wide_ghosted(H, phi, p, rg)
+            out.append(np.stack([scale * _grad_padded(vp, H.h[p], a, rg, order) for a in range(3)]))
     return out
 
 
-def _tau_padded(vp, h, R):
-    """tau = sum_{i>j} D_ii D_jj - D_ij^2, D = G4 o G4, on the interior (needs R = 4)."""
-    g = [_grad_padded(vp, h, j, 2) for j in range(3)]          # valid on interior +- (R-2)
-    D = [[_grad_padded(g[j], h, i, R - 2) for j in range(3)] for i in range(3)]
+def _tau_padded(vp, h, R, order=4):
+    """tau = sum_{i>j} D_ii D_jj - D_ij^2, D = G o G, on the interior (needs R = order)."""
+    rg = order // 2
+    g = [_grad_padded(vp, h, j, rg, order) for j in range(3)]          # valid on interior +- (R - rg)
+    D = [[_grad_padded(g[j], h, i, R - rg, order) for j in range(3)] for i in range(3)]
     t = np.zeros_like(D[0][0])
     for i in range(3):
         for j in range(i):
@@ -364,17 +372,18 @@ def _tau_padded(vp, h, R):
     return t
 
 
-def tau_hierarchy(H, phi):
-    """Second-order source on every level, composite mean removed (Section 3.1)."""
+def tau_hierarchy(H, phi, order=4):
+    """Second-order source on every level, composite mean removed (Section 3.1); D = G o G with
+    the Table 1 gradient of order 4 or 6 (patch ghosts of width = order)."""
     from .lpt import tau as tau_periodic
     phi = [a.copy() for a in phi]
     restrict_bottom_up(H, phi)
     out = []
     for p in range(H.P + 1):
         if p == 0:
-            out.append(tau_periodic(phi[0], H.h[0]))
+            out.append(tau_periodic(phi[0], H.h[0], order))
         else:
-            out.append(_tau_padded(wide_ghosted(H, phi, p, 4), H.h[p], 4))
+            out.append(_tau_padded(wide_ghosted(H, phi, p, order), H.h[p], order, order))
     out, _ = composite_zero_mean(H, out)
     return out
 

@@ -181,3 +181,36 @@ def test_zoom_error_is_localised_at_the_coarse_fine_boundary():
                err[:, :, -1].max())
     centre = err[12:20, 12:20, 12:20].max()
     assert face > 3 * centre
+
+
+def test_hierarchy_sixth_order_plane_wave_displacement_and_tau():
+    """Sixth-order gradient on a hierarchy: the patch interior (>= 3 cells from every face) equals
+    the printed symbol; tau is one constant away from the faces (>= 6 cells)."""
+    N0 = 16
+    H = zoom.Hierarchy(N0, 1.0, [((16, 16, 16), (4, 4, 4))])
+    m = (1, 1, 0)
+
+    def field(p, off):
+        c = _centres(H.n[p], off, H.h[p])
+        return 0.2 * np.cos(2 * np.pi * (m[0] * c[0] + m[1] * c[1]) / N0)
+    phi = [field(0, (0, 0, 0)), field(1, (8, 8, 8))]
+    psi = zoom.displacement_hierarchy(H, phi, scale=1.0, order=6)
+    c = _centres(H.n[1], (8, 8, 8), H.h[1])
+    ph = 2 * np.pi * (m[0] * c[0] + m[1] * c[1]) / N0
+    kx = 2 * np.pi * m[0] * H.h[1] / N0
+    g = -0.2 * (np.sin(3 * kx) - 9 * np.sin(2 * kx) + 45 * np.sin(kx)) / 30 / H.h[1]
+    assert np.allclose(psi[1][0][3:-3, 3:-3, 3:-3], (g * np.sin(ph))[3:-3, 3:-3, 3:-3], atol=1e-14)
+    t = zoom.tau_hierarchy(H, phi, order=6)
+    assert abs(zoom.composite_sum(H, t)) < 1e-14
+    assert np.ptp(t[1][6:-6, 6:-6, 6:-6]) < 1e-14
+
+
+def test_wide_ghosts_width_six_exact_for_quadratics():
+    H = zoom.Hierarchy(16, 1 / 16, [((16, 16, 16), (4, 4, 4)), ((8, 8, 8), (4, 4, 4))])
+    coef = [0.3, 1.0, -2.0, 0.5, 3.0, -1.5, 2.0, 0.7, -0.4, 1.1]
+    offs = [(0, 0, 0), (8, 8, 8), (24, 24, 24)]
+    v = [_poly(_centres(H.n[p], offs[p], H.h[p]), coef) for p in range(3)]
+    for p, R in ((1, 3), (2, 6)):
+        vp = zoom.wide_ghosted(H, v, p, R)
+        exp = _poly(_centres(vp.shape, tuple(o - R for o in offs[p]), H.h[p]), coef)
+        assert np.allclose(vp, exp, atol=1e-12)
