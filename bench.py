@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel directly (no graph replay)")
     ap.add_argument("--only", default="",
                     help="comma-separated legs to run alone, without the headline step (profiling): "
-                         "roof512, c1, c3, c4")
+                         "roof512, c1, c3, hoz, c4")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -286,6 +286,42 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
     return res
 
 
+def time_highorder_zoom(mg, torch, reps=2):
+    """The zoom hierarchy with the sixth-order operators throughout (the order of the paper's own
+    nested results): 128^3 base with three centred 128^3 patches, FP64 solve with the order-6
+    Laplacian (Table 1) and order-5 flux matching (Table 2), sixth-order displacements, tau with
+    D = G6 o G6, the second solve and its displacements."""
+    from paper_1103_6031_amd import inputs
+    patches, fl = inputs.c3_input()
+    H = mg.Hier(128, inputs.BOX / 128, patches)
+    f = [torch.from_numpy(a).to("cuda:0") for a in fl]
+    o = _opts(mg, tol=1e-10, max_cycles=60)
+    ws = mg.Workspace(mg.mg_ho_hierarchy_workspace_bytes(H, 6))
+    wl1 = mg.Workspace(mg.lpt_workspace_bytes(H, 1))
+    wl2 = mg.Workspace(mg.lpt_workspace_bytes(H, 2))
+
+    def step():
+        phi, s1 = mg.mg_solve_hierarchy_ho(H, 6, f, opts=o, workspace=ws)
+        mg.lpt_displacements(H, phi, scale=-1.0, workspace=wl1, grad_order=6)
+        tau = mg.lpt2_source(H, phi, workspace=wl2, grad_order=6)
+        phi2, s2 = mg.mg_solve_hierarchy_ho(H, 6, tau, opts=o, workspace=ws)
+        mg.lpt_displacements(H, phi2, scale=-3.0 / 7.0, workspace=wl1, grad_order=6)
+        return s1, s2
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s1, s2 = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return dict(workload="128^3 base + 3 nested 128^3 patches, order-6 Laplacian / order-5 flux matching / "
+                         "sixth-order gradient, 2LPT, FP64, tol 1e-10",
+                ms_per_step=round(dt * 1e3, 3), cycles=[s1["cycles"], s2["cycles"]],
+                rel_res=[s1["rel_res"], s2["rel_res"]],
+                value=round((s1["cell_updates"] + s2["cell_updates"]) / dt / 1e6, 1), unit="Mcell-updates/s")
+
+
 def time_c3(mg, torch, reps=3):
     """The zoom hierarchy: 128^3 base with three centred 128^3 patches, the 2LPT chain (solve,
     displacements, tau, solve, displacements) in both precisions."""
@@ -439,6 +475,8 @@ def main():
                 line["solve_c1"] = time_c1(mg, torch)
             elif leg == "c3":
                 line["zoom_c3"] = time_c3(mg, torch)
+            elif leg == "hoz":
+                line["highorder_zoom"] = time_highorder_zoom(mg, torch)
             elif leg == "c4":
                 line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
             else:
@@ -494,6 +532,7 @@ def main():
     if not a.no_c1c3:
         line["solve_c1"] = time_c1(mg, torch)
         line["zoom_c3"] = time_c3(mg, torch)
+        line["highorder_zoom"] = time_highorder_zoom(mg, torch)
     if not a.no_batch:
         line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
     if serve_host is not None:

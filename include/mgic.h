@@ -11,7 +11,7 @@
  *     normal to the coarse-fine face, flux matching with Table 2's order-1
  *     flux operator);
  *   - first-order (Zel'dovich) displacements  psi = scale * G phi  with the
- *     fourth-order gradient G of Table 1 (Section 3.1, eq. "zeldovich");
+ *     fourth- or sixth-order gradient G of Table 1 (Section 3.1, eq. "zeldovich");
  *   - the second-order source  tau = sum_{i>j} (D_ii D_jj - D_ij^2),
  *     D_ij = G_i G_j phi  (Section 3.1, second-order perturbations), whose
  *     Poisson solve gives the second-order potential.
@@ -191,30 +191,33 @@ int mg_residual_hierarchy(const mg_hier* hier, const double* const* f, double* c
  * -------------------------------------------------------------------------------------------- */
 
 /* Workspace bytes for lpt_displacements (what = 1), lpt2_source (what = 2) or lpt_lla_density
- * (what = 3).  The LPT calls below need a base of at least 2^3 cells (MG_EINVAL otherwise). */
+ * (what = 3), for either gradient order.  The LPT calls below need a base of at least 2^3 cells
+ * (3^3 with the sixth-order gradient; MG_EINVAL otherwise). */
 size_t lpt_workspace_bytes(const mg_hier* hier, int what);
 
-/* psi_c = scale * G4_c phi on every level (Table 1 fourth-order gradient).  out[3*p + c] is the
- * c-th component on level p.  The base wraps periodically; patch cells next to a face use
- * width-2 ghosts interpolated tri-quadratically from the parent (covered parent cells taken as
- * the mean of their children).  Covered coarse cells get the gradient of that mean.  phi is
- * read only.  Asynchronous. */
+/* psi_c = scale * G_c phi on every level, G the Table 1 gradient of order grad_order (4 or 6;
+ * MG_EINVAL otherwise).  out[3*p + c] is the c-th component on level p.  The base wraps
+ * periodically; patch cells next to a face use ghosts of width grad_order / 2 interpolated
+ * tri-quadratically from the parent (covered parent cells taken as the mean of their children).
+ * Covered coarse cells get the gradient of that mean.  phi is read only.  Asynchronous. */
 int lpt_displacements(const mg_hier* hier, const double* const* phi, double* const* out,
-                      double scale, void* workspace, size_t workspace_bytes, void* stream);
+                      int grad_order, double scale, void* workspace, size_t workspace_bytes,
+                      void* stream);
 
-/* tau[p] = sum_{i>j} (D_ii D_jj - D_ij^2) with D_ij = G4_i G4_j phi on every level (width-4
- * ghosts on patches), then covered coarse cells replaced by the mean of their children and the
- * composite mean removed, so tau is a compatible Poisson source.  Asynchronous. */
-int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau,
+/* tau[p] = sum_{i>j} (D_ii D_jj - D_ij^2) with D_ij = G_i G_j phi, G of order grad_order (4 or
+ * 6), on every level (ghosts of width grad_order on patches), then covered coarse cells replaced
+ * by the mean of their children and the composite mean removed, so tau is a compatible Poisson
+ * source.  Asynchronous. */
+int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau, int grad_order,
                 void* workspace, size_t workspace_bytes, void* stream);
 
 /* Both of the above in one call (Section 3.1): out as lpt_displacements with this scale, tau as
- * lpt2_source.  On the periodic base the second derivatives are taken from out itself,
- * D_ij = G4_i out_j / scale, which saves one pass over the base; with scale = +-1 tau is
- * bit-identical to lpt2_source's, otherwise it differs by rounding.  scale must be finite and
- * non-zero.  Workspace: lpt_workspace_bytes(hier, 2).  Asynchronous. */
+ * lpt2_source, both with the gradient of order grad_order.  On the periodic base the second
+ * derivatives are taken from out itself, D_ij = G_i out_j / scale, which saves one pass over the
+ * base; with scale = +-1 tau is bit-identical to lpt2_source's, otherwise it differs by rounding.
+ * scale must be finite and non-zero.  Workspace: lpt_workspace_bytes(hier, 2).  Asynchronous. */
 int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, double* const* out,
-                                 double scale, double* const* tau, void* workspace,
+                                 int grad_order, double scale, double* const* tau, void* workspace,
                                  size_t workspace_bytes, void* stream);
 
 /* Baryon density of the local Lagrangian approximation (Section 5.3, eq. gasdens):

@@ -1,6 +1,6 @@
 // LPT kernels for gfx950 (Hahn & Abel 2011, Section 3.1, and the baryon density of Section 5.3):
-//   first order   psi_c = scale * G4_c phi           (Table 1 fourth-order gradient)
-//   second order  tau = sum_{i>j} D_ii D_jj - D_ij^2,  D_ij = G4_i (G4_j phi)
+//   first order   psi_c = scale * G_c phi            (Table 1 gradient, fourth or sixth order)
+//   second order  tau = sum_{i>j} D_ii D_jj - D_ij^2,  D_ij = G_i (G_j phi)
 //   LLA density   rho / rho_bar - 1 = 1 / det(I + G4 L) - 1   (eq. gasdens)
 // plus the post-solve ghost layers of width R (faces, edges and corners) that patches need:
 // coarse-only tri-quadratic interpolation of the parent at the child's position (children sit at
@@ -47,6 +47,26 @@ __device__ __forceinline__ double g4(const Src<PAD>& s, int x, int y, int z, int
     return acc / den;
 }
 
+// sixth-order gradient of s along `axis`, Table 1 weights (-1, 9, -45, 0, 45, -9, 1) / 60
+template <bool PAD>
+__device__ __forceinline__ double g6(const Src<PAD>& s, int x, int y, int z, int axis, double den) {
+    const int ex = axis == 0, ey = axis == 1, ez = axis == 2;
+    double acc = (-1.0) * s.at(x - 3 * ex, y - 3 * ey, z - 3 * ez);
+    acc = acc + 9.0 * s.at(x - 2 * ex, y - 2 * ey, z - 2 * ez);
+    acc = acc + (-45.0) * s.at(x - ex, y - ey, z - ez);
+    acc = acc + 45.0 * s.at(x + ex, y + ey, z + ez);
+    acc = acc + (-9.0) * s.at(x + 2 * ex, y + 2 * ey, z + 2 * ez);
+    acc = acc + s.at(x + 3 * ex, y + 3 * ey, z + 3 * ez);
+    return acc / den;
+}
+
+// the gradient of order G (4 or 6) with its denominator (12 h or 60 h)
+template <bool PAD, int G>
+__device__ __forceinline__ double gG(const Src<PAD>& s, int x, int y, int z, int axis, double h) {
+    if constexpr (G == 4) return g4(s, x, y, z, axis, 12.0 * h);
+    else return g6(s, x, y, z, axis, 60.0 * h);
+}
+
 // linear index -> (x, y, z) of a box, natural order
 __device__ __forceinline__ void decode3(const Lay& B, unsigned t, int& x, int& y, int& z) {
     const unsigned row = B.dz.div(t);
@@ -56,22 +76,21 @@ __device__ __forceinline__ void decode3(const Lay& B, unsigned t, int& x, int& y
     x = (int)xq;
 }
 
-template <bool PAD>
+template <bool PAD, int G = 4>
 __global__ void k_grad4(Src<PAD> s, Lay B, double h, double scale, double* __restrict__ ox,
                         double* __restrict__ oy, double* __restrict__ oz) {
     const unsigned t = (unsigned)lpt_block() * blockDim.x + threadIdx.x;
     if (t >= (unsigned)B.d.cells()) return;
     int x, y, z;
     decode3(B, t, x, y, z);
-    const double den = 12.0 * h;
-    ox[t] = scale * g4(s, x, y, z, 0, den);
-    oy[t] = scale * g4(s, x, y, z, 1, den);
-    oz[t] = scale * g4(s, x, y, z, 2, den);
+    ox[t] = scale * gG<PAD, G>(s, x, y, z, 0, h);
+    oy[t] = scale * gG<PAD, G>(s, x, y, z, 1, h);
+    oz[t] = scale * gG<PAD, G>(s, x, y, z, 2, h);
 }
 
-// psi_j = G4_j phi on the interior extended by e cells (e <= R - 2), unscaled; the output box B
-// is (d + 2e)^3, padded by e
-template <bool PAD>
+// psi_j = G_j phi on the interior extended by e cells (e <= R - G / 2), unscaled; the output box
+// B is (d + 2e)^3, padded by e
+template <bool PAD, int G = 4>
 __global__ void k_psi(Src<PAD> s, Lay B, int e, double h, double* __restrict__ p0, double* __restrict__ p1,
                       double* __restrict__ p2) {
     const unsigned t = (unsigned)lpt_block() * blockDim.x + threadIdx.x;
@@ -81,29 +100,27 @@ __global__ void k_psi(Src<PAD> s, Lay B, int e, double h, double* __restrict__ p
     x -= e;
     y -= e;
     z -= e;
-    const double den = 12.0 * h;
-    p0[t] = g4(s, x, y, z, 0, den);
-    p1[t] = g4(s, x, y, z, 1, den);
-    p2[t] = g4(s, x, y, z, 2, den);
+    p0[t] = gG<PAD, G>(s, x, y, z, 0, h);
+    p1[t] = gG<PAD, G>(s, x, y, z, 1, h);
+    p2[t] = gG<PAD, G>(s, x, y, z, 2, h);
 }
 
-// tau = sum_{i>j} D_ii D_jj - D_ij^2 with D_ij = G4_i psi_j; psi periodic or padded by e.  When
-// psi is a scaled gradient s G4 phi, post = 1 / s^2 brings tau back to the one of phi (post = 1:
-// not applied, so s = +-1 gives the same bits as psi = G4 phi)
-template <bool PAD>
+// tau = sum_{i>j} D_ii D_jj - D_ij^2 with D_ij = G_i psi_j; psi periodic or padded by e.  When
+// psi is a scaled gradient s G phi, post = 1 / s^2 brings tau back to the one of phi (post = 1:
+// not applied, so s = +-1 gives the same bits as psi = G phi)
+template <bool PAD, int G = 4>
 __global__ void k_tau_psi(Src<PAD> q0, Src<PAD> q1, Src<PAD> q2, Lay B, double h, double post,
                           double* __restrict__ tau) {
     const unsigned t = (unsigned)lpt_block() * blockDim.x + threadIdx.x;
     if (t >= (unsigned)B.d.cells()) return;
     int x, y, z;
     decode3(B, t, x, y, z);
-    const double den = 12.0 * h;
-    const double Dxx = g4(q0, x, y, z, 0, den);
-    const double Dyy = g4(q1, x, y, z, 1, den);
-    const double Dzz = g4(q2, x, y, z, 2, den);
-    const double Dyx = g4(q0, x, y, z, 1, den);
-    const double Dzx = g4(q0, x, y, z, 2, den);
-    const double Dzy = g4(q1, x, y, z, 2, den);
+    const double Dxx = gG<PAD, G>(q0, x, y, z, 0, h);
+    const double Dyy = gG<PAD, G>(q1, x, y, z, 1, h);
+    const double Dzz = gG<PAD, G>(q2, x, y, z, 2, h);
+    const double Dyx = gG<PAD, G>(q0, x, y, z, 1, h);
+    const double Dzx = gG<PAD, G>(q0, x, y, z, 2, h);
+    const double Dzy = gG<PAD, G>(q1, x, y, z, 2, h);
     double acc = 0.0;
     acc = acc + (Dyy * Dxx - Dyx * Dyx);
     acc = acc + (Dzz * Dxx - Dzx * Dzx);
@@ -539,8 +556,15 @@ void launch_wide_ghost(const double* pu, const double* u, double* padded, Dims d
 }
 
 void launch_grad4(const double* src, int R, Dims d, double h, double scale, double* ox, double* oy, double* oz,
-                  hipStream_t st) {
+                  hipStream_t st, int order) {
     const Lay B(d, 0);
+    if (order == 6) {   // the sixth-order gradient: one thread per cell (periodic, or padded by R >= 3)
+        if (R == 0)
+            k_grad4<false, 6><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{src, 0, d}, B, h, scale, ox, oy, oz);
+        else
+            k_grad4<true, 6><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, B, h, scale, ox, oy, oz);
+        return;
+    }
     if (R == 0 && lpt_tiled(d))
         k_grad4_tile<<<tiles_grid(d), 256, 0, st>>>(src, d, h, scale, ox, oy, oz);
     else if (R == 0)
@@ -549,13 +573,26 @@ void launch_grad4(const double* src, int R, Dims d, double h, double scale, doub
         k_grad4<true><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, B, h, scale, ox, oy, oz);
 }
 
-void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st) {
-    const int e = R >= 2 ? R - 2 : 0;
+void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st, int order) {
+    const int rg = order / 2;   // the gradient's radius
+    const int e = R >= rg ? R - rg : 0;
     const Lay E(Dims{d.x + 2 * e, d.y + 2 * e, d.z + 2 * e}, 0);
     const Lay B(d, 0);
     double* p0 = psi;
     double* p1 = psi + E.d.cells();
     double* p2 = psi + 2 * E.d.cells();
+    if (order == 6) {   // the sixth-order gradient twice: one thread per cell
+        if (R == 0) {
+            k_psi<false, 6><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<false>{src, 0, d}, E, 0, h, p0, p1, p2);
+            k_tau_psi<false, 6><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{p0, 0, d}, Src<false>{p1, 0, d},
+                                                                        Src<false>{p2, 0, d}, B, h, 1.0, tau);
+        } else {
+            k_psi<true, 6><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<true>{src, R, d}, E, e, h, p0, p1, p2);
+            k_tau_psi<true, 6><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<true>{p0, e, d}, Src<true>{p1, e, d},
+                                                                       Src<true>{p2, e, d}, B, h, 1.0, tau);
+        }
+        return;
+    }
     if (R == 0) {
         k_psi<false><<<grid_for(E.d.cells()), kBlock, 0, st>>>(Src<false>{src, 0, d}, E, 0, h, p0, p1, p2);
         if (lpt_tiled(d)) k_tau_tile<<<tiles_grid(d), 256, 0, st>>>(p0, p1, p2, d, h, 1.0, tau);
@@ -568,7 +605,12 @@ void launch_tau(const double* src, int R, Dims d, double h, double* tau, double*
 }
 
 void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
-                         double* tau, hipStream_t st) {
+                         double* tau, hipStream_t st, int order) {
+    if (order == 6) {
+        k_tau_psi<false, 6><<<grid_for(d.cells()), kBlock, 0, st>>>(Src<false>{g0, 0, d}, Src<false>{g1, 0, d},
+                                                                    Src<false>{g2, 0, d}, Lay(d, 0), h, post, tau);
+        return;
+    }
     if (lpt_tiled(d)) k_tau_tile<<<tiles_grid(d), 256, 0, st>>>(g0, g1, g2, d, h, post, tau);
     else k_tau_rows<<<rows_grid(d), rows_block(d), 0, st>>>(g0, g1, g2, d, h, post, tau);
 }

@@ -273,16 +273,18 @@ void launch_relayout_sub(const double* src, Lay ls, double* dst, Lay ld, const d
 // must already hold the mean of their children)
 void launch_wide_ghost(const double* pu, const double* u, double* padded, Dims d, ParentMap pm, int R,
                        hipStream_t st);
-// psi_c = scale * G4_c phi ; src is periodic (R = 0) or padded by R
+// psi_c = scale * G_c phi with the Table 1 gradient of `order` (4 or 6); src is periodic (R = 0)
+// or padded by R >= order / 2
 void launch_grad4(const double* src, int R, Dims d, double h, double scale, double* ox, double* oy,
-                  double* oz, hipStream_t st);
-// tau = sum_{i>j} D_ii D_jj - D_ij^2 ; src periodic (R = 0) or padded by R >= 4; psi is scratch
-// for 3 arrays of (d + 2(R-2))^3 (d^3 when periodic)
-void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st);
-// tau on a periodic level from the three components g_c = s G4_c phi of a scaled gradient
+                  double* oz, hipStream_t st, int order = 4);
+// tau = sum_{i>j} D_ii D_jj - D_ij^2, D = G o G of `order`; src periodic (R = 0) or padded by
+// R >= order; psi is scratch for 3 arrays of (d + 2(R - order/2))^3 (d^3 when periodic)
+void launch_tau(const double* src, int R, Dims d, double h, double* tau, double* psi, hipStream_t st,
+                int order = 4);
+// tau on a periodic level from the three components g_c = s G_c phi of a scaled gradient
 // (post = 1 / s^2)
 void launch_tau_from_grad(const double* g0, const double* g1, const double* g2, Dims d, double h, double post,
-                          double* tau, hipStream_t st);
+                          double* tau, hipStream_t st, int order = 4);
 // LLA overdensity 1 / det(I + G4 L) - 1 with L = a (+ b when b is given), three components each,
 // periodic (R = 0) or padded by R >= 2
 void launch_lla(const double* const* a, const double* const* b, int R, Dims d, double h, double* out, hipStream_t st);

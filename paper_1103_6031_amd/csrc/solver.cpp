@@ -891,7 +891,9 @@ struct LptPlan {
 // what: 1 displacements, 2 tau (and displacements), 3 LLA density (three displacement components
 // per level are copied and padded instead of one potential)
 static size_t lpt_carve(const mg_hier* H, int what, Carver& cv, LptPlan& lp) {
-    const int R = what == 2 ? 4 : 2, nc = what == 3 ? 3 : 1;
+    // patch padding for either gradient order: 3 for the displacements (sixth order; 2 for the
+    // fourth), 6 for tau (4), 2 for the LLA density
+    const int R = what == 2 ? 6 : (what == 1 ? 3 : 2), nc = what == 3 ? 3 : 1;
     size_t maxpad = 0;
     lp.phi.assign((size_t)nc * H->nlev, nullptr);
     if (H->nlev > 1)
@@ -909,7 +911,7 @@ static size_t lpt_carve(const mg_hier* H, int what, Carver& cv, LptPlan& lp) {
         size_t m = (size_t)H->lev[0].n[0] * H->lev[0].n[1] * H->lev[0].n[2];
         for (int p = 1; p < H->nlev; ++p) {
             const mg_level& l = H->lev[p];
-            const size_t s = (size_t)(l.n[0] + 4) * (l.n[1] + 4) * (l.n[2] + 4);
+            const size_t s = (size_t)(l.n[0] + 6) * (l.n[1] + 6) * (l.n[2] + 6);
             if (s > m) m = s;
         }
         lp.psi = cv.take<double>(3 * m);
@@ -929,11 +931,13 @@ static Dims dims_of(const mg_hier* H, int p) { return Dims{H->lev[p].n[0], H->le
 static double h_of(const mg_hier* H, int p) { return H->lev[0].h / (double)(1 << p); }
 
 static int lpt_common(const mg_hier* H, int what, const double* const* phi, void* ws, size_t ws_bytes,
-                      hipStream_t st, LptPlan& lp) {
+                      hipStream_t st, LptPlan& lp, int order = 4) {
     int rc = validate_hier(H);
     if (rc) return rc;
-    // the periodic stencils wrap an offset of up to 2 cells once
+    if (order != 4 && order != 6) return fail(MG_EINVAL, "grad_order must be 4 or 6");
+    // the periodic stencils wrap an offset of up to order / 2 cells once
     if (H->lev[0].n[0] < 2) return fail(MG_EINVAL, "LPT needs a base of at least 2^3 cells");
+    if (order == 6 && H->lev[0].n[0] < 3) return fail(MG_EINVAL, "the sixth-order gradient needs a base of at least 3^3 cells");
     if (!phi) return fail(MG_EINVAL, "phi is NULL");
     for (int p = 0; p < H->nlev; ++p)
         if (!phi[p]) return fail(MG_EINVAL, "phi level pointer is NULL");
@@ -2308,22 +2312,23 @@ size_t lpt_workspace_bytes(const mg_hier* hier, int what) {
     return lpt_carve(hier, what, cv, lp);
 }
 
-int lpt_displacements(const mg_hier* hier, const double* const* phi, double* const* out, double scale,
-                      void* workspace, size_t workspace_bytes, void* stream) {
+int lpt_displacements(const mg_hier* hier, const double* const* phi, double* const* out, int grad_order,
+                      double scale, void* workspace, size_t workspace_bytes, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     if (!out) return fail(MG_EINVAL, "out is NULL");
     LptPlan lp;
-    int rc = lpt_common(hier, 1, phi, workspace, workspace_bytes, st, lp);
+    int rc = lpt_common(hier, 1, phi, workspace, workspace_bytes, st, lp, grad_order);
     if (rc) return rc;
+    const int rg = grad_order / 2;
     for (int p = 0; p < hier->nlev; ++p) {
         if (!out[3 * p] || !out[3 * p + 1] || !out[3 * p + 2]) return fail(MG_EINVAL, "output pointer is NULL");
         const Dims d = dims_of(hier, p);
         const double h = h_of(hier, p);
         if (p == 0) {
-            launch_grad4(lp.phi[0], 0, d, h, scale, out[0], out[1], out[2], st);
+            launch_grad4(lp.phi[0], 0, d, h, scale, out[0], out[1], out[2], st, grad_order);
         } else {
-            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 2, st);
-            launch_grad4(lp.padded, 2, d, h, scale, out[3 * p], out[3 * p + 1], out[3 * p + 2], st);
+            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), rg, st);
+            launch_grad4(lp.padded, rg, d, h, scale, out[3 * p], out[3 * p + 1], out[3 * p + 2], st, grad_order);
         }
     }
     MG_HIP(hipGetLastError());
@@ -2336,18 +2341,18 @@ namespace mgic {
 // tau on every level (composite mean removed); on the base from base_grad (s G4 phi, post =
 // 1 / s^2) when given, else from phi
 static int tau_levels(const mg_hier* hier, LptPlan& lp, double* const* tau, double* const* base_grad, double post,
-                      hipStream_t st) {
+                      hipStream_t st, int order) {
     for (int p = 0; p < hier->nlev; ++p) {
         if (!tau[p]) return fail(MG_EINVAL, "tau level pointer is NULL");
         const Dims d = dims_of(hier, p);
         const double h = h_of(hier, p);
         if (p == 0 && base_grad) {
-            launch_tau_from_grad(base_grad[0], base_grad[1], base_grad[2], d, h, post, tau[0], st);
+            launch_tau_from_grad(base_grad[0], base_grad[1], base_grad[2], d, h, post, tau[0], st, order);
         } else if (p == 0) {
-            launch_tau(lp.phi[0], 0, d, h, tau[0], lp.psi, st);
-        } else {
-            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 4, st);
-            launch_tau(lp.padded, 4, d, h, tau[p], lp.psi, st);
+            launch_tau(lp.phi[0], 0, d, h, tau[0], lp.psi, st, order);
+        } else {   // ghosts of width `order`: D = G o G reaches order / 2 twice
+            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), order, st);
+            launch_tau(lp.padded, order, d, h, tau[p], lp.psi, st, order);
         }
     }
     // composite mean: covered cells := mean of children, then subtract the base mean everywhere
@@ -2368,36 +2373,38 @@ static int tau_levels(const mg_hier* hier, LptPlan& lp, double* const* tau, doub
 
 extern "C" {
 
-int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau, void* workspace,
+int lpt2_source(const mg_hier* hier, const double* const* phi, double* const* tau, int grad_order, void* workspace,
                 size_t workspace_bytes, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     if (!tau) return fail(MG_EINVAL, "tau is NULL");
     LptPlan lp;
-    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp);
+    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp, grad_order);
     if (rc) return rc;
-    return tau_levels(hier, lp, tau, nullptr, 1.0, st);
+    return tau_levels(hier, lp, tau, nullptr, 1.0, st, grad_order);
 }
 
-int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, double* const* out, double scale,
-                                 double* const* tau, void* workspace, size_t workspace_bytes, void* stream) {
+int lpt_displacements_and_source(const mg_hier* hier, const double* const* phi, double* const* out, int grad_order,
+                                 double scale, double* const* tau, void* workspace, size_t workspace_bytes,
+                                 void* stream) {
     hipStream_t st = (hipStream_t)stream;
     if (!out || !tau) return fail(MG_EINVAL, "out or tau is NULL");
     if (!(scale != 0.0) || !std::isfinite(scale)) return fail(MG_EINVAL, "scale must be finite and non-zero");
     LptPlan lp;
-    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp);
+    int rc = lpt_common(hier, 2, phi, workspace, workspace_bytes, st, lp, grad_order);
     if (rc) return rc;
+    const int rg = grad_order / 2;
     for (int p = 0; p < hier->nlev; ++p) {
         if (!out[3 * p] || !out[3 * p + 1] || !out[3 * p + 2]) return fail(MG_EINVAL, "output pointer is NULL");
         const Dims d = dims_of(hier, p);
         const double h = h_of(hier, p);
         if (p == 0) {
-            launch_grad4(lp.phi[0], 0, d, h, scale, out[0], out[1], out[2], st);
+            launch_grad4(lp.phi[0], 0, d, h, scale, out[0], out[1], out[2], st, grad_order);
         } else {
-            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), 2, st);
-            launch_grad4(lp.padded, 2, d, h, scale, out[3 * p], out[3 * p + 1], out[3 * p + 2], st);
+            launch_wide_ghost(lp.phi[p - 1], lp.phi[p], lp.padded, d, parent_of(hier, p), rg, st);
+            launch_grad4(lp.padded, rg, d, h, scale, out[3 * p], out[3 * p + 1], out[3 * p + 2], st, grad_order);
         }
     }
-    return tau_levels(hier, lp, tau, out, 1.0 / (scale * scale), st);
+    return tau_levels(hier, lp, tau, out, 1.0 / (scale * scale), st, grad_order);
 }
 
 int lpt_lla_density(const mg_hier* hier, const double* const* disp, const double* const* disp2,

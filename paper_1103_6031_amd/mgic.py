@@ -78,10 +78,11 @@ _sig = {
     "mg_residual_hierarchy": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _PP,
                                              ctypes.POINTER(ctypes.c_double), _P, _sz, _P]),
     "lpt_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier), ctypes.c_int]),
-    "lpt_displacements": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_double, _P, _sz, _P]),
-    "lpt2_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _P, _sz, _P]),
-    "lpt_displacements_and_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_double, _PP, _P,
-                                                    _sz, _P]),
+    "lpt_displacements": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_int, ctypes.c_double, _P, _sz,
+                                         _P]),
+    "lpt2_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_int, _P, _sz, _P]),
+    "lpt_displacements_and_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_int, ctypes.c_double,
+                                                    _PP, _P, _sz, _P]),
     "lpt_lla_density": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _PP, _P, _sz, _P]),
     "mg_batch_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mg_opts)]),
     "mg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
@@ -373,32 +374,35 @@ def lpt_workspace_bytes(hier: Hier, what: int) -> int:
     return n
 
 
-def lpt_displacements(hier: Hier, phi, scale=1.0, out=None, workspace=None, stream=None):
-    """psi_c = scale * G4_c phi per level.  Returns a list of [psi_x, psi_y, psi_z] per level."""
+def lpt_displacements(hier: Hier, phi, scale=1.0, out=None, workspace=None, stream=None, grad_order=4):
+    """psi_c = scale * G_c phi per level (Table 1 gradient of order 4 or 6).  Returns a list of
+    [psi_x, psi_y, psi_z] per level."""
     if out is None:
         out = [[torch.empty_like(x) for _ in range(3)] for x in phi]
     H = hier.c_struct()
     ws = _ws(workspace, lpt_workspace_bytes(hier, 1))
     pp, _pa = _ptr_array([_dev(x, "phi") for x in phi])
     op, _oa = _ptr_array([_dev(c, "out") for lvl in out for c in lvl])
-    _check(_lib.lpt_displacements(ctypes.byref(H), pp, op, float(scale), ctypes.c_void_p(ws.ptr), ws.nbytes,
-                                  _stream(stream)))
+    _check(_lib.lpt_displacements(ctypes.byref(H), pp, op, int(grad_order), float(scale), ctypes.c_void_p(ws.ptr),
+                                  ws.nbytes, _stream(stream)))
     return out
 
 
-def lpt2_source(hier: Hier, phi, tau=None, workspace=None, stream=None):
-    """Second-order source tau per level (composite mean removed)."""
+def lpt2_source(hier: Hier, phi, tau=None, workspace=None, stream=None, grad_order=4):
+    """Second-order source tau per level (composite mean removed), D = G o G of grad_order."""
     if tau is None:
         tau = [torch.empty_like(x) for x in phi]
     H = hier.c_struct()
     ws = _ws(workspace, lpt_workspace_bytes(hier, 2))
     pp, _pa = _ptr_array([_dev(x, "phi") for x in phi])
     tp, _ta = _ptr_array([_dev(x, "tau") for x in tau])
-    _check(_lib.lpt2_source(ctypes.byref(H), pp, tp, ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+    _check(_lib.lpt2_source(ctypes.byref(H), pp, tp, int(grad_order), ctypes.c_void_p(ws.ptr), ws.nbytes,
+                            _stream(stream)))
     return tau
 
 
-def lpt_displacements_and_source(hier: Hier, phi, scale=1.0, out=None, tau=None, workspace=None, stream=None):
+def lpt_displacements_and_source(hier: Hier, phi, scale=1.0, out=None, tau=None, workspace=None, stream=None,
+                                 grad_order=4):
     """Displacements (as lpt_displacements) and tau (as lpt2_source) in one call.
     Returns (list of [psi_x, psi_y, psi_z] per level, list of tau per level)."""
     if out is None:
@@ -410,8 +414,8 @@ def lpt_displacements_and_source(hier: Hier, phi, scale=1.0, out=None, tau=None,
     pp, _pa = _ptr_array([_dev(x, "phi") for x in phi])
     op, _oa = _ptr_array([_dev(c, "out") for lvl in out for c in lvl])
     tp, _ta = _ptr_array([_dev(x, "tau") for x in tau])
-    _check(_lib.lpt_displacements_and_source(ctypes.byref(H), pp, op, float(scale), tp, ctypes.c_void_p(ws.ptr),
-                                             ws.nbytes, _stream(stream)))
+    _check(_lib.lpt_displacements_and_source(ctypes.byref(H), pp, op, int(grad_order), float(scale), tp,
+                                             ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
     return out, tau
 
 

@@ -91,9 +91,23 @@ def test_lpt_rejects_a_single_cell_base_before_any_device_work():
     from paper_1103_6031_amd import mgic
     H = mgic.Hier(1, 1.0).c_struct()
     ptrs = (ctypes.c_void_p * 3)(16, 16, 16)
-    rc = mgic._lib.lpt_displacements(ctypes.byref(H), ptrs, ptrs, -1.0, ctypes.c_void_p(256), 1 << 20, None)
+    rc = mgic._lib.lpt_displacements(ctypes.byref(H), ptrs, ptrs, 4, -1.0, ctypes.c_void_p(256), 1 << 20, None)
     assert rc == mgic.MG_EINVAL
     assert b"2^3" in mgic._lib.mg_last_error()
+
+
+def test_lpt_rejects_a_gradient_order_other_than_four_or_six_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    H = mgic.Hier(8, 1.0).c_struct()
+    ptrs = (ctypes.c_void_p * 3)(16, 16, 16)
+    for order in (2, 5, 8):
+        rc = mgic._lib.lpt_displacements(ctypes.byref(H), ptrs, ptrs, order, -1.0, ctypes.c_void_p(256), 1 << 20, None)
+        assert rc == mgic.MG_EINVAL and b"grad_order" in mgic._lib.mg_last_error()
+        rc = mgic._lib.lpt2_source(ctypes.byref(H), ptrs, ptrs, order, ctypes.c_void_p(256), 1 << 20, None)
+        assert rc == mgic.MG_EINVAL
+    H2 = mgic.Hier(2, 1.0).c_struct()
+    rc = mgic._lib.lpt_displacements(ctypes.byref(H2), ptrs, ptrs, 6, -1.0, ctypes.c_void_p(256), 1 << 20, None)
+    assert rc == mgic.MG_EINVAL and b"3^3" in mgic._lib.mg_last_error()
 
 
 def test_lla_validates_its_arguments_before_any_device_work():

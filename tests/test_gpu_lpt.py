@@ -119,3 +119,53 @@ def test_displacements_and_source_in_one_call(mg, layout):
                 assert np.array_equal(to_host(tau[p]), to_host(tau_s[p]))
             else:
                 assert rel_max(to_host(tau[p]), to_host(tau_s[p])) <= 1e-13
+
+
+# the sixth-order gradient of Table 1 (grad_order = 6)
+@pytest.mark.parametrize("N", [4, 8, 20, 64, 128])
+def test_periodic_sixth_order_grad_and_tau(mg, N):
+    rng = np.random.default_rng(600 + N)
+    phi = rng.standard_normal((N, N, N))
+    h = 100.0 / N
+    note("periodic sixth-order grad/tau N=%d" % N)
+    Hg = mg.Hier(N, h)
+    psi = mg.lpt_displacements(Hg, [to_dev(phi)], scale=-0.7, grad_order=6)[0]
+    pe = lpt.displacement(phi, h, scale=-0.7, order=6)
+    for c in range(3):
+        assert rel_max(to_host(psi[c]), pe[c]) < 1e-14
+    t = mg.lpt2_source(Hg, [to_dev(phi)], grad_order=6)[0]
+    te = lpt.tau(phi, h, order=6)
+    te = te - te.mean()
+    assert rel_max(to_host(t), te) < 1e-13
+    # the combined call, its tau from the displacements themselves
+    psi2, t2 = mg.lpt_displacements_and_source(Hg, [to_dev(phi)], scale=-1.0, grad_order=6)
+    assert rel_max(to_host(t2[0]), te) < 1e-13
+    for c in range(3):
+        assert rel_max(to_host(psi2[0][c]), lpt.displacement(phi, h, -1.0, order=6)[c]) < 1e-14
+
+
+@pytest.mark.parametrize("layout", [
+    (16, [((16, 16, 16), (4, 4, 4))]),
+    (32, [((32, 32, 32), (8, 8, 8)), ((24, 16, 32), (4, 8, 8))]),
+])
+def test_hierarchy_sixth_order_grad_and_tau_match_oracle(mg, layout):
+    N0, patches = layout
+    H = zoom.Hierarchy(N0, 100.0 / N0, patches)
+    Hg = mg.Hier(N0, 100.0 / N0, patches)
+    rng = np.random.default_rng(14)
+    phi = [rng.standard_normal(n) for n in H.n]
+    note("hierarchy sixth-order grad/tau N0=%d P=%d" % (N0, H.P))
+    psi = mg.lpt_displacements(Hg, [to_dev(a) for a in phi], scale=1.5, grad_order=6)
+    pe = zoom.displacement_hierarchy(H, phi, scale=1.5, order=6)
+    for p in range(H.P + 1):
+        for c in range(3):
+            assert rel_max(to_host(psi[p][c]), pe[p][c]) < 1e-13
+    t = mg.lpt2_source(Hg, [to_dev(a) for a in phi], grad_order=6)
+    te = zoom.tau_hierarchy(H, phi, order=6)
+    for p in range(H.P + 1):
+        assert rel_max(to_host(t[p]), te[p]) < 1e-12
+    psi2, t2 = mg.lpt_displacements_and_source(Hg, [to_dev(a) for a in phi], scale=1.5, grad_order=6)
+    for p in range(H.P + 1):
+        assert rel_max(to_host(t2[p]), te[p]) < 1e-12
+        for c in range(3):
+            assert np.array_equal(to_host(psi2[p][c]), to_host(psi[p][c]))
