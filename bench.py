@@ -536,10 +536,18 @@ def main():
     if not a.no_batch:
         line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
     if serve_host is not None:
+        wl = ("%d requests, Poisson %g/s, base {64,128,256}^3 with 0-3 patches of {64,96,128}^3, 1LPT/2LPT 50/50, "
+              "%s, tol 1e-10, %d slots, %g GB budget")
         summary, _, _ = serve.serve_trace(reqs, slots=4, budget_gb=16.0, prec="mixed", host=serve_host)
-        line["serving_c5"] = dict(workload="%d requests, Poisson 20/s, base {64,128,256}^3 with 0-3 patches of "
-                                           "{64,96,128}^3, 1LPT/2LPT 50/50, mixed, tol 1e-10" % len(reqs),
-                                  **summary)
+        line["serving_c5"] = dict(workload=wl % (len(reqs), 20.0, "mixed", 4, 16.0), **summary)
+        # the plain FP64 path on the same trace, as the reference beside the mixed one
+        summary, _, _ = serve.serve_trace(reqs, slots=4, budget_gb=16.0, prec="fp64", host=serve_host)
+        line["serving_c5_fp64"] = dict(workload=wl % (len(reqs), 20.0, "fp64", 4, 16.0), **summary)
+        # under load: the same requests arriving ten times faster with a 4 GB budget, so that
+        # admission by footprint binds (a 256^3-base request holds about 1.5-2.5 GB)
+        fast = serve.trace(a.serve_requests, 200.0)
+        summary, _, _ = serve.serve_trace(fast, slots=4, budget_gb=4.0, prec="mixed", host=serve_host)
+        line["serving_c5_loaded"] = dict(workload=wl % (len(fast), 200.0, "mixed", 4, 4.0), **summary)
     if a.pmc_calib:
         calib_copies(torch)
     if not a.no_cpu:

@@ -18,7 +18,9 @@ def _reqs():
             Request(3, 0.0, 64, [c(64, 16), c(32, 8)], 1, 1.01),
             Request(4, 0.0, 32, [c(32, 8), c(32, 8)], 2, 0.99),
             Request(5, 0.0, 64, [], 2, 1.03),
-            Request(6, 0.0, 48, [c(32, 16)], 1, 1.04)]
+            Request(6, 0.0, 48, [c(32, 16)], 1, 1.04),
+            # the largest shape of the serving trace: a 256^3 base with 128^3, 96^3 and 64^3 patches
+            Request(7, 0.0, 256, [c(128, 96), c(96, 40), c(64, 32)], 2, 0.98)]
 
 
 def test_alone_equals_mix():
@@ -28,7 +30,7 @@ def test_alone_equals_mix():
     fields = serve.device_fields(serve.host_fields(reqs, workers=1))
     note("serve: %d requests in a burst over 3 slots" % len(reqs))
     mix = serve.GpuExecutor(fields, 3, keep=ids)
-    srv = serve.Server(mix, lambda r: serve.footprint_bytes(r), slots=3, budget_bytes=8 << 30)
+    srv = serve.Server(mix, lambda r: serve.footprint_bytes(r), slots=3, budget_bytes=12 << 30)
     recs = srv.run(reqs)
     assert all(r.error is None for r in recs.values()), [r.error for r in recs.values()]
     assert srv.peak_inflight >= 2

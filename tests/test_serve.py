@@ -69,6 +69,25 @@ def test_budget_forces_queueing():
     assert q[-1] >= 0.08
 
 
+def test_waits_are_attributed_to_memory_or_slots():
+    # a large request at the head of the queue waits for memory while a slot is free, and the
+    # small ones behind it wait too (first come, first served); with memory to spare and one slot,
+    # requests wait for the slot instead
+    fp = lambda r: 8 if r.id == 1 else 2          # noqa: E731
+    ex = FakeExec(lambda r: 0.03, fp)
+    reqs = [Request(0, 0.0, 32), Request(1, 0.001, 32), Request(2, 0.002, 32)]
+    srv = Server(ex, fp, slots=4, budget_bytes=9)
+    recs = srv.run(reqs)
+    assert recs[1].waited_for_memory and not recs[1].waited_for_slot
+    assert recs[2].admitted >= recs[1].admitted
+    s = summarize(recs, srv)
+    assert s["waited_for_memory"] >= 1 and s["queue_max_ms"] >= 20
+    ex = FakeExec(lambda r: 0.02, lambda r: 1)
+    recs = Server(ex, lambda r: 1, slots=1, budget_bytes=100).run([Request(i, 0.0, 32) for i in range(3)])
+    assert sum(r.waited_for_slot for r in recs.values()) == 2
+    assert not any(r.waited_for_memory for r in recs.values())
+
+
 def test_overlap_when_resources_allow():
     fp = lambda r: 1                              # noqa: E731
     ex = FakeExec(lambda r: 0.05, fp)
