@@ -262,6 +262,17 @@ int mg_solve_batch(int ninst, const int* n, const double* h, const double* const
                    double* const* u, const mg_opts* opts, mg_stats* stats, void* workspace,
                    size_t workspace_bytes, void* stream);
 
+/* Autotuning of the batched smoother (block size and cells per thread, per level depth).
+ * mg_batch_tune_candidates: the number of candidate shapes.  mg_batch_force_shape(i): every
+ * later mg_solve_batch in the process uses candidate i at every depth without timing (i = -1:
+ * back to timing; MG_EINVAL out of range); every candidate gives the same bits.
+ * mg_tune_cache(path): the tuned shapes persist in a JSON file at path - entries already in it
+ * are loaded (the return value is their number; MG_EINVAL if the file is not a tuning cache), and
+ * every new tuning rewrites it; NULL or "" stops the persistence (returns 0).  Process-wide. */
+int mg_batch_tune_candidates(void);
+int mg_batch_force_shape(int index);
+int mg_tune_cache(const char* path);
+
 /* ----------------------------------------------------------------------------------------------
  * Single steps, exposed for kernel-level parity checks
  * -------------------------------------------------------------------------------------------- */

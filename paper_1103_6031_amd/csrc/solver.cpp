@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -634,7 +635,10 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
             MG_HIP(hipGetLastError());
             return count ? read_scalars(P, first, count, out, st) : MG_OK;
         }
-        const int rcg = run_graph(true, gkey + var, st, [&](hipStream_t s) {
+        // the key names the copy too: a step captured without it (fixed cycles) must never be
+        // replayed where the host reads its result
+        const std::string key = gkey + var + "|c" + std::to_string(first) + "," + std::to_string(count);
+        const int rcg = run_graph(true, key, st, [&](hipStream_t s) {
             launches(s);
             if (count) (void)hipMemcpyAsync(pin, P.scal + first, count * sizeof(double), hipMemcpyDeviceToHost, s);
         }, 2);
@@ -1178,14 +1182,79 @@ static std::string batch_key(const BatchPlan& B, int ti) {
 }
 
 static const SmoothShape kShapes[] = {{256, 1}, {256, 2}, {256, 4}, {128, 2}, {128, 4}, {512, 1}, {512, 2}};
+constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+static int g_force_shape = -1;        // >= 0: every depth takes kShapes[g_force_shape], no timing
+static std::string g_tune_path;       // JSON file the tuned shapes persist in ("" = none)
+
+// The tuning cache file: {"format": "mgic-batch-smoother-tuning-1", "entries": [{"key": "...",
+// "shapes": [[block, cells per thread], ...]}, ...]}, one entry per batch shape and precision.
+static bool parse_tune_file(const std::string& text, std::map<std::string, std::vector<SmoothShape>>& out) {
+    if (text.find("\"mgic-batch-smoother-tuning-1\"") == std::string::npos) return false;
+    size_t pos = 0;
+    while ((pos = text.find("\"key\"", pos)) != std::string::npos) {
+        size_t q0 = text.find('"', text.find(':', pos) + 1);
+        if (q0 == std::string::npos) return false;
+        size_t q1 = text.find('"', q0 + 1);
+        if (q1 == std::string::npos) return false;
+        const std::string key = text.substr(q0 + 1, q1 - q0 - 1);
+        size_t a = text.find("\"shapes\"", q1);
+        if (a == std::string::npos) return false;
+        a = text.find('[', a);
+        const size_t end = text.find("]]", a);
+        if (a == std::string::npos || end == std::string::npos) return false;
+        std::vector<SmoothShape> v;
+        size_t i = a + 1;
+        while (i < end) {
+            const size_t b = text.find('[', i);
+            if (b == std::string::npos || b > end) break;
+            int blk = 0, cpt = 0;
+            if (std::sscanf(text.c_str() + b, "[%d ,%d", &blk, &cpt) != 2 &&
+                std::sscanf(text.c_str() + b, "[%d, %d", &blk, &cpt) != 2)
+                return false;
+            bool known = false;
+            for (const SmoothShape& sh : kShapes) known = known || (sh.block == blk && sh.V == cpt);
+            if (!known) return false;
+            v.push_back(SmoothShape{blk, cpt});
+            i = text.find(']', b) + 1;
+        }
+        out[key] = v;
+        pos = end;
+    }
+    return true;
+}
+
+static void save_tune_file() {   // under g_tune_mu
+    if (g_tune_path.empty()) return;
+    std::string t = "{\"format\": \"mgic-batch-smoother-tuning-1\", \"entries\": [";
+    bool first = true;
+    for (auto& kv : g_tune) {
+        t += first ? "\n" : ",\n";
+        first = false;
+        t += "  {\"key\": \"" + kv.first + "\", \"shapes\": [";
+        for (size_t i = 0; i < kv.second.size(); ++i)
+            t += (i ? ", [" : "[") + std::to_string(kv.second[i].block) + ", " + std::to_string(kv.second[i].V) + "]";
+        t += "]}";
+    }
+    t += "\n]}\n";
+    const std::string tmp = g_tune_path + ".tmp";
+    if (FILE* fh = std::fopen(tmp.c_str(), "w")) {
+        const bool ok = std::fwrite(t.data(), 1, t.size(), fh) == t.size();
+        std::fclose(fh);
+        if (ok) std::rename(tmp.c_str(), g_tune_path.c_str());
+    }
+}
 
 template <class T>
 static int tune_smoother(BatchPlan& B, int ti, hipStream_t st, std::vector<SmoothShape>& out) {
     const std::string key = batch_key(B, ti);
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
+        if (g_force_shape >= 0) {
+            out.assign(B.D, kShapes[g_force_shape]);
+            return MG_OK;
+        }
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) {
+        if (it != g_tune.end() && (int)it->second.size() == B.D) {
             out = it->second;
             return MG_OK;
         }
@@ -1235,6 +1304,7 @@ static int tune_smoother(BatchPlan& B, int ti, hipStream_t st, std::vector<Smoot
     MG_HIP(hipGetLastError());
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[key] = out;
+    save_tune_file();
     return MG_OK;
 }
 
@@ -1524,7 +1594,9 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
             }
         }
     };
-    const std::string wkey = std::to_string((uintptr_t)ws) + "|" + batch_key(B, B.mixed ? 0 : 1) + "|" +
+    std::string shape_tag;
+    for (const SmoothShape& sh : B.mixed ? shf : shd) shape_tag += std::to_string(sh.block) + "x" + std::to_string(sh.V) + ",";
+    const std::string wkey = std::to_string((uintptr_t)ws) + "|" + batch_key(B, B.mixed ? 0 : 1) + "|" + shape_tag + "|" +
                              std::to_string(o->nu2) + "|" +
                              std::to_string(B.segs.size()) + "|" + (fixed ? "f" : "c");
     if (B.mixed) {
@@ -2214,6 +2286,36 @@ int mg_ghost_fill_ho(const mg_hier* hier, int order, int p, const double* const*
 extern "C" {
 
 const char* mg_last_error(void) { return g_err.c_str(); }
+
+int mg_batch_tune_candidates(void) { return kNumShapes; }
+
+int mg_batch_force_shape(int index) {
+    if (index < -1 || index >= kNumShapes) return fail(MG_EINVAL, "shape index out of range");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_force_shape = index;
+    return MG_OK;
+}
+
+int mg_tune_cache(const char* path) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (!path || !*path) {
+        g_tune_path.clear();
+        return 0;
+    }
+    std::map<std::string, std::vector<SmoothShape>> loaded;
+    if (FILE* fh = std::fopen(path, "r")) {
+        std::string text;
+        char buf[4096];
+        size_t k;
+        while ((k = std::fread(buf, 1, sizeof(buf), fh)) > 0) text.append(buf, k);
+        std::fclose(fh);
+        if (!parse_tune_file(text, loaded)) return fail(MG_EINVAL, std::string("not a tuning cache file: ") + path);
+    }
+    for (auto& kv : loaded) g_tune[kv.first] = kv.second;
+    g_tune_path = path;
+    if (!g_tune.empty()) save_tune_file();   // the file holds every shape known to the process
+    return (int)loaded.size();
+}
 
 int mg_kprof_enable(int period) {
     if (period < 0) return fail(MG_EINVAL, "kernel timing period < 0");

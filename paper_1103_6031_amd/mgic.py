@@ -90,6 +90,9 @@ _sig = {
     "mg_smooth_level": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.c_int,
                                        _P, _sz, _P]),
     "mg_ghost_fill": (ctypes.c_int, [ctypes.POINTER(mg_hier), ctypes.c_int, _PP, _P, ctypes.c_int, _P]),
+    "mg_batch_tune_candidates": (ctypes.c_int, []),
+    "mg_batch_force_shape": (ctypes.c_int, [ctypes.c_int]),
+    "mg_tune_cache": (ctypes.c_int, [ctypes.c_char_p]),
     "mg_kprof_enable": (ctypes.c_int, [ctypes.c_int]),
     "mg_kprof_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
                                      ctypes.POINTER(ctypes.c_double)]),
@@ -463,6 +466,24 @@ def mg_solve_batch(f: Sequence[torch.Tensor], h: Sequence[float], u=None, opts=N
     if check:
         _check(rc, stats)
     return u, stats
+
+
+def mg_batch_tune_candidates() -> int:
+    return _lib.mg_batch_tune_candidates()
+
+
+def mg_batch_force_shape(index: int):
+    """Force candidate `index` of the batched smoother at every depth (-1: back to timing)."""
+    _check(_lib.mg_batch_force_shape(int(index)))
+
+
+def mg_tune_cache(path) -> int:
+    """Persist the batched smoother's tuned shapes in a JSON file (None: stop); returns the
+    number of entries loaded from it."""
+    rc = _lib.mg_tune_cache(None if path is None else os.fsencode(path))
+    if rc < 0:
+        _check(rc)
+    return rc
 
 
 def mg_smooth_level(f, u, h, half_sweeps, prec="fp64", workspace=None, stream=None):

@@ -179,3 +179,26 @@ def test_allocation_free_solve_rejects_problems_above_its_scratch_before_any_dev
         need = mgic.mg_workspace_bytes(mgic.Hier(n, 1.0), mgic.make_opts(prec=prec))
         assert (need <= mgic.MG_SCRATCH_BYTES) == fits, (n, prec, need)
     assert lib.mg_solve_hierarchy_noalloc(ctypes.byref(Hc), p, p, None, ctypes.byref(st), None) == mgic.MG_EINVAL
+
+
+def test_tuning_cache_file_round_trip_and_validation(tmp_path):
+    from paper_1103_6031_amd import mgic
+    assert mgic.mg_batch_tune_candidates() == 7
+    with pytest.raises(mgic.MGError):
+        mgic.mg_batch_force_shape(7)
+    mgic.mg_batch_force_shape(-1)
+    good = tmp_path / "tune.json"
+    good.write_text('{"format": "mgic-batch-smoother-tuning-1", "entries": [\n'
+                    '  {"key": "0:2:64,64,", "shapes": [[256, 1], [128, 2]]},\n'
+                    '  {"key": "1:2:32,", "shapes": [[512, 2]]}\n]}\n')
+    assert mgic.mg_tune_cache(str(good)) == 2
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"format": "mgic-batch-smoother-tuning-1", "entries": [{"key": "x", "shapes": [[100, 3]]}]}')
+    with pytest.raises(mgic.MGError):
+        mgic.mg_tune_cache(str(bad))
+    other = tmp_path / "other.json"
+    other.write_text('{"something": "else"}')
+    with pytest.raises(mgic.MGError):
+        mgic.mg_tune_cache(str(other))
+    assert mgic.mg_tune_cache(str(tmp_path / "absent.json")) == 0   # created on the next tuning
+    assert mgic.mg_tune_cache(None) == 0

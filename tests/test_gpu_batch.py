@@ -165,3 +165,38 @@ def test_c4_batch_matches_oracle(mg):
         worst = max(worst, rel_rms(to_host(u), ue))
     note("C4 worst rel RMS vs exact solve: %.3e" % worst)
     assert worst <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_every_tuning_candidate_gives_the_same_bits(mg, prec, tmp_path):
+    """The autotuner only picks a launch shape: each of its candidates (block size, cells per
+    thread), forced at every depth, gives every instance the bits of its solo solve; the tuned
+    shapes then persist in the JSON cache."""
+    import json
+    sizes = [32, 48, 64, 96, 128]
+    fs, hs = _fields(sizes, seed0=700)
+    o = mg.make_opts(tol=1e-10, prec=prec, max_cycles=40)
+    solo = [mg.mg_solve_level(to_dev(f), h, opts=o) for f, h in zip(fs, hs)]
+    ws = mg.Workspace(mg.mg_batch_workspace_bytes(sizes, o))
+    try:
+        for k in range(mg.mg_batch_tune_candidates()):
+            note("batch %s forced candidate %d" % (prec, k))
+            mg.mg_batch_force_shape(k)
+            ub, sts = mg.mg_solve_batch([to_dev(f) for f in fs], hs, opts=o, workspace=ws)
+            for (us, ss), u, s in zip(solo, ub, sts):
+                _same_stats(s, ss)
+                assert np.array_equal(to_host(u), to_host(us)), k
+    finally:
+        mg.mg_batch_force_shape(-1)
+    cache = tmp_path / "tune.json"
+    assert mg.mg_tune_cache(str(cache)) == 0
+    try:
+        note("batch %s tuned, with the cache file" % prec)
+        ub, sts = mg.mg_solve_batch([to_dev(f) for f in fs], hs, opts=o, workspace=ws)
+        for (us, ss), u in zip(solo, ub):
+            assert np.array_equal(to_host(u), to_host(us))
+        doc = json.loads(cache.read_text())
+        assert doc["format"] == "mgic-batch-smoother-tuning-1" and len(doc["entries"]) >= 1
+        assert mg.mg_tune_cache(str(cache)) == len(doc["entries"])   # loads back
+    finally:
+        mg.mg_tune_cache(None)

@@ -89,3 +89,26 @@ def test_graph_replay_with_initial_guess(mg):
             u.copy_(u0)
             got, sg = mg.mg_solve_level(f, h, u=u, opts=og, workspace=ws)
             _same([got], sg, [ref], sref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fixed_cycle_graphs_are_not_replayed_by_a_converging_solve(mg, prec):
+    """Regression: a fixed-cycle solve captures its steps without the residual readback; a later
+    solve with a stopping test on the same workspace must not replay those (it would read a
+    stale host value - here the NaN a failed solve left behind)."""
+    N = 32
+    h = inputs.BOX / N
+    f = to_dev(inputs.gaussian_field(N, 1103220))
+    ws = mg.Workspace(mg.mg_workspace_bytes(mg.Hier(N, h), mg.make_opts(prec=prec)))
+    fixed = mg.make_opts(prec=prec, fixed_cycles=True, max_cycles=4)
+    for _ in range(3):
+        mg.mg_solve_level(f, h, opts=fixed, workspace=ws)
+    bad = f.clone()
+    bad[1, 2, 3] = float("nan")
+    with pytest.raises(mg.MGError):
+        mg.mg_solve_level(bad, h, opts=mg.make_opts(prec=prec))
+    ref, sref = mg.mg_solve_level(f, h, opts=mg.make_opts(prec=prec, graph=False), workspace=ws)
+    for _ in range(3):
+        got, sg = mg.mg_solve_level(f, h, opts=mg.make_opts(prec=prec), workspace=ws)
+        _same([got], sg, [ref], sref)
+        assert sg["rel_res"] <= 1e-10
