@@ -93,6 +93,50 @@ __global__ __launch_bounds__(kBlock) void k_ho_half(const T* __restrict__ in, T*
     *(v2_t<T>*)(out + t0) = q ? mk2<T>(cur.x, v) : mk2<T>(v, cur.y);
 }
 
+// The same half-sweep with the y and z neighbours from LDS: a block owns rows y0 .. y0 + kHoTy - 1
+// of one x plane and stages them with R halo rows on each side (all z, wrapped in y) in LDS; the
+// 2R x-neighbours and f come from memory.  About 2R + 3 global loads per update instead of
+// 6R + 2; the sums are formed in the order of ho_off, so the bits are the same.  Blocks of one
+// plane are consecutive; the blocks of x-neighbouring planes are n / kHoTy apart, a multiple of 8,
+// so they share an XCD (and its L2).  For 16 <= n <= 256.
+constexpr int kHoTy = 16;
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_ho_half_lds(const T* __restrict__ in, T* __restrict__ out,
+                                                        const T* __restrict__ f, int lg, T h2, int colour) {
+    extern __shared__ __align__(16) unsigned char ho_smem[];
+    T* rows = (T*)ho_smem;                          // [kHoTy + 2R][n]
+    const unsigned n = 1u << lg, m = n - 1, nh = n >> 1;
+    const unsigned tiles = n / kHoTy;
+    const unsigned x = blockIdx.x / tiles, y0 = (blockIdx.x - x * tiles) * kHoTy;
+    // stage rows y0 - R .. y0 + kHoTy + R - 1 as 16-byte pairs
+    const unsigned npairs = (unsigned)(kHoTy + 2 * R) * nh;
+    for (unsigned t = threadIdx.x; t < npairs; t += blockDim.x) {
+        const unsigned r = t / nh, pz = t - r * nh;
+        const unsigned y = (y0 + r - R) & m;
+        *(v2_t<T>*)(rows + r * n + 2 * pz) = *(const v2_t<T>*)(in + ho_idx(x, y, 2 * pz, lg));
+    }
+    __syncthreads();
+    const unsigned pairs = (unsigned)kHoTy * nh;
+    for (unsigned t = threadIdx.x; t < pairs; t += blockDim.x) {
+        const unsigned ry = t / nh, pz = t - ry * nh;
+        const unsigned y = y0 + ry, z0 = 2 * pz;
+        const unsigned q = (x + y + (unsigned)colour) & 1u;
+        const unsigned z = z0 + q;
+        const T* row = rows + (ry + R) * n;
+        T acc = 0;
+#pragma unroll
+        for (int s = 1; s <= R; ++s) {
+            const T px = in[ho_idx((x - s) & m, y, z, lg)] + in[ho_idx((x + s) & m, y, z, lg)];
+            const T py = row[(int)z - s * (int)n] + row[(int)z + s * (int)n];   // rows y - s, y + s
+            const T pz_ = row[(z - s) & m] + row[(z + s) & m];
+            acc += (T)ho_w<R>(s) * ((px + py) + pz_);
+        }
+        const v2_t<T> cur = *(const v2_t<T>*)(row + z0);
+        const T v = (h2 * f[ho_idx(x, y, z, lg)] - acc) / ((T)3 * (T)HoW<R>::w0);
+        *(v2_t<T>*)(out + ho_idx(x, y, z0, lg)) = q ? mk2<T>(cur.x, v) : mk2<T>(v, cur.y);
+    }
+}
+
 // r = f - L u for the two cells (x, y, z0) and (x, y, z0 + 1), z0 even, from 16-byte loads: the
 // pairs of the x- and y-neighbour rows hold both cells' neighbours, and one run of pairs from
 // z0 - 2J to z0 + 2J + 1 (J = ceil(R / 2)) holds their z-neighbours.  Same arithmetic as ho_off.
@@ -285,9 +329,20 @@ int ho_parts(int lg) {   // blocks of the reductions: fixed by the size, at most
 template <class T>
 void launch_ho_half(const T* in, T* out, const T* f, int lg, double h, int order, int colour, hipStream_t st,
                     hipEvent_t ea, hipEvent_t eb) {
-    const int g = grid_for((size_t)1 << (3 * lg - 1));   // pairs of cells (lg >= 1)
     if (ea) (void)hipEventRecord(ea, st);
-    HO_DISPATCH(order, k_ho_half, T, g, in, out, f, lg, (T)(h * h), colour);
+    if (lg >= 4 && lg <= 8) {   // 16^3 .. 256^3: y and z neighbours from LDS
+        const unsigned n = 1u << lg;
+        const unsigned blocks = n * (n / kHoTy);
+        const T h2 = (T)(h * h);
+        const int R = order / 2;
+        const size_t lds = (size_t)(kHoTy + 2 * R) * n * sizeof(T);
+        if (order == 2) k_ho_half_lds<1, T><<<blocks, kBlock, lds, st>>>(in, out, f, lg, h2, colour);
+        else if (order == 4) k_ho_half_lds<2, T><<<blocks, kBlock, lds, st>>>(in, out, f, lg, h2, colour);
+        else k_ho_half_lds<3, T><<<blocks, kBlock, lds, st>>>(in, out, f, lg, h2, colour);
+    } else {
+        const int g = grid_for((size_t)1 << (3 * lg - 1));   // pairs of cells (lg >= 1)
+        HO_DISPATCH(order, k_ho_half, T, g, in, out, f, lg, (T)(h * h), colour);
+    }
     if (eb) (void)hipEventRecord(eb, st);
 }
 
