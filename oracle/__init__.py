@@ -24,6 +24,9 @@ cosmological simulations" (MNRAS 2011):
 * ``zoom_ho``  - the adaptive multigrid with the order-4 / order-6 Laplacians:
                  ghost zones of width order / 2 by polynomials of that degree,
                  flux matching with the Table 2 operators of order 3 and 5.
+* ``spectral`` - Section 3.5: finite-volume (cell-average) and sub-grid deconvolution, and the
+                 hybrid Poisson correction (k-space exact displacement on the finest grid,
+                 periodic or zero-padded isolated), by numpy FFTs.
 * ``dense``    - brute-force dense assembly of the periodic and composite
                  linear systems for tiny grids (pins for the iterative solvers).
 
@@ -37,4 +40,4 @@ brute-force dense solves or invariants that do not reuse the oracle's own
 arithmetic.
 """
 
-from . import stencil, periodic, lpt, zoom, zoom_ho, dense, highorder  # noqa: F401
+from . import stencil, periodic, lpt, zoom, zoom_ho, dense, highorder, spectral  # noqa: F401
