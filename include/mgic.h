@@ -238,6 +238,44 @@ int lpt_lla_density(const mg_hier* hier, const double* const* disp, const double
                     double* const* delta, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------------
+ * Spectral corrections that recover small-scale power (Section 3.5)
+ *
+ * Fields are real FP64 arrays of n[0] x n[1] x n[2] cells, natural [x][y][z] order, z contiguous,
+ * device memory owned by the caller.  A periodic grid (isolated = 0) is transformed on its own
+ * n points per axis (each n a power of two, 2..1024).  An isolated grid (isolated = 1: a patch,
+ * with the field taken as zero outside it) is zero-padded at its origin corner to the smallest
+ * power of two >= 2 n per axis (n <= 512), the paper's twice-the-size padding for power-of-two
+ * patches; the padding is implicit (never stored).  Mode m of an axis of P points has wave number
+ * k = 2 pi m / (P h), m in -P/2 .. P/2 - 1.
+ * -------------------------------------------------------------------------------------------- */
+
+#define SPEC_FV_DECONV 1   /* Section 3.5.1: divide by prod_i sinc(k_i h / 2), the cell average */
+#define SPEC_SG_DECONV 2   /* Section 3.5.3: divide by prod_i cos(k_i h / 4), the 8-sub-cell mean */
+
+/* Workspace bytes of spec_deconvolve and lpt_hybrid_correction for this shape (0 if invalid). */
+size_t spec_workspace_bytes(const int n[3], int isolated);
+
+/* out = the deconvolution of f (kind SPEC_FV_DECONV or SPEC_SG_DECONV): f's transform divided by
+ * the window's transform, back-transformed.  The mean (k = 0) is unchanged.  out may alias f.
+ * MG_EINVAL for an unknown kind, a NULL pointer, a shape outside the limits above or a workspace
+ * that is too small or not 256-byte aligned.  Asynchronous on stream. */
+int spec_deconvolve(const int n[3], int kind, int isolated, const double* f, double* out,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Hybrid Poisson solver (Section 3.5.2): ADDS to out3[c] (c = x, y, z) the correction that turns
+ * the finite-difference displacement scale * G_c phi, L phi = f (L the Table 1 Laplacian of
+ * lap_order 2, 4 or 6, G the gradient of grad_order 4 or 6), into the k-space exact
+ * scale * d_c (laplacian^-1 f):
+ *   out3[c] += IFFT( i scale [ -k_c / k^2 - g_c / lambda ] h FFT(f) ),
+ * g_c and lambda the gradient and Laplacian symbols in grid units.  k = 0 and the Nyquist plane
+ * of axis c get no correction.  On the periodic base of a single-level setup this makes the
+ * result a pure FFT Poisson solve; on the finest patch (isolated = 1) f is zero outside the patch.
+ * f is read only and must not alias an output.  Asynchronous on stream. */
+int lpt_hybrid_correction(const int n[3], double h, int isolated, int lap_order, int grad_order,
+                          double scale, const double* f, double* const* out3, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
  * Batched independent periodic solves (many small instances in one persistent launch)
  * -------------------------------------------------------------------------------------------- */
 

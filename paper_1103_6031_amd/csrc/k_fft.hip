@@ -1,0 +1,361 @@
+// Three-dimensional complex FFTs for gfx950 and the spectral multipliers of Section 3.5 (finite-
+// volume and sub-grid deconvolution, the hybrid Poisson correction) and of the real-space
+// transfer-function convolution of Section 2.2, fused into the transform's middle pass.
+//
+// A 3-D transform is three launches of batched 1-D transforms, one per axis.  A workgroup loads a
+// tile of nl lines into LDS, zero-extending lines that are stored shorter than the transform (the
+// zero padding of isolated boundaries is never materialised), runs a Stockham autosort FFT
+// (radix 4, plus one radix-2 stage when log2 N is odd; Govindaraju et al. 2008, "High performance
+// discrete Fourier transforms on graphics processors") with an LDS exchange between stages, and
+// stores the first m_out points of each line.  Lines along z are contiguous in memory: the tile
+// loads each line as one run.  Along y and x a tile holds nl lines that are consecutive in z, so
+// every global access is a run of nl consecutive elements.  In LDS the tile is interleaved, point
+// i of line l at i * (nl + 1) + l: lane-consecutive lines are address-consecutive during the
+// stages, and the odd stride keeps the contiguous-line loads free of bank conflicts.
+//
+// The x pass can run forward, multiply every element by a multiplier of its (kx, ky, kz), and
+// run the inverse in the same launch: the spectrum of the x pass never goes to memory.
+
+#include "mg_internal.h"
+
+namespace mgic {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// radix-R DFT in registers; forward uses e^{-2 pi i rk/R}, inverse e^{+2 pi i rk/R}
+template <int R, bool INV>
+__device__ __forceinline__ void dft(double2* v) {
+    if (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else {
+        const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const double2 s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+        // -i * d13 = (d13.y, -d13.x)
+        const double2 mi = INV ? make_double2(-d13.y, d13.x) : make_double2(d13.y, -d13.x);
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, mi);
+        v[3] = csub(d02, mi);
+    }
+}
+
+// One Stockham stage on a tile of nl interleaved lines of length N = 2^lgN.  Butterfly j of a
+// line reads points j + r N/R, twiddles them by w^(r k N / (Ns R)) with k = j mod Ns, and writes
+// the radix-R DFT to points (j - k) R + k + r Ns.  tw holds e^{-2 pi i t / Ntw}, Ntw = 2^lgtw.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_stage(double2* lds, int lgN, int lgnl, int lgNs, const double2* __restrict__ tw,
+                                          int lgtw) {
+    constexpr int kIt = kFftTile / (R * kBlock);
+    constexpr int lgR = R == 4 ? 2 : 1;
+    const int nl = 1 << lgnl, LS = nl + 1;
+    const int P = 1 << (lgN - lgR);
+    const int items = nl * P;
+    const int Ns = 1 << lgNs;
+    const int tws = lgtw - lgNs - lgR;   // k * Ntw / (Ns R) = k << tws
+    double2 v[kIt][R];
+    int dst[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int q = (int)threadIdx.x + it * kBlock;
+        if (q < items) {
+            const int l = q & (nl - 1), j = q >> lgnl;
+            const int k = j & (Ns - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = lds[(j + r * P) * LS + l];
+            const int step = k << tws;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                double2 w = tw[r * step];
+                if (INV) w.y = -w.y;
+                v[it][r] = cmul(v[it][r], w);
+            }
+            dft<R, INV>(v[it]);
+            dst[it] = ((j - k) << lgR) + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int q = (int)threadIdx.x + it * kBlock;
+        if (q < items) {
+            const int l = q & (nl - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[(dst[it] + r * Ns) * LS + l] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool INV>
+__device__ void fft_tile(double2* lds, int lgN, int lgnl, const double2* __restrict__ tw, int lgtw) {
+    int lgNs = 0;
+    if (lgN & 1) {
+        fft_stage<2, INV>(lds, lgN, lgnl, 0, tw, lgtw);
+        lgNs = 1;
+    }
+    for (; lgNs < lgN; lgNs += 2) fft_stage<4, INV>(lds, lgN, lgnl, lgNs, tw, lgtw);
+}
+
+template <int IN>
+__device__ __forceinline__ double2 load_in(const FftPass& A, long long idx) {
+    if (IN == kFftInCplx) return ((const double2*)A.in0)[idx];
+    if (IN == kFftInRe) return make_double2(((const double*)A.in0)[idx], 0.0);
+    return make_double2(((const double*)A.in0)[idx], ((const double*)A.in1)[idx]);
+}
+
+template <int OUT>
+__device__ __forceinline__ void store_out(const FftPass& A, long long idx, double2 v) {
+    if (OUT == kFftOutCplx) {
+        ((double2*)A.out0)[idx] = v;
+    } else if (OUT == kFftOutRe) {
+        ((double*)A.out0)[idx] = v.x;
+    } else if (OUT == kFftOutRePairStore) {
+        ((double*)A.out0)[idx] = v.x;
+        if (A.out1) ((double*)A.out1)[idx] = v.y;
+    } else {   // kFftOutRePairAdd
+        double* o0 = (double*)A.out0;
+        o0[idx] = o0[idx] + v.x;
+        if (A.out1) {
+            double* o1 = (double*)A.out1;
+            o1[idx] = o1[idx] + v.y;
+        }
+    }
+}
+
+// the multiplier of spectral element (kx, ky, kz) = (i, a, b), applied to v
+template <int SYM>
+__device__ __forceinline__ double2 apply_sym(const FftPass& A, int i, int a, int b, double2 v) {
+    const double c = A.sym_scale;
+    if (SYM == kSymSeparable) {
+        const double m = ((A.tab_x[i] * A.tab_y[a]) * A.tab_z[b]) * c;
+        return make_double2(v.x * m, v.y * m);
+    }
+    if (SYM == kSymTable) {
+        const double m = A.tab[(long long)i * A.tab_si + (long long)a * A.tab_sa + b] * c;
+        return make_double2(v.x * m, v.y * m);
+    }
+    // hybrid correction: per-axis blocks [k^2 | lambda_1d | k (0 on Nyquist) | g (0 on Nyquist)]
+    const double* X = A.tab_x;
+    const double* Y = A.tab_y;
+    const double* Z = A.tab_z;
+    const int px = A.sym_n[0], py = A.sym_n[1], pz = A.sym_n[2];
+    const double k2 = (X[i] + Y[a]) + Z[b];
+    if (k2 == 0.0) return make_double2(0.0, 0.0);
+    const double lam = (X[px + i] + Y[py + a]) + Z[pz + b];
+    if (SYM == kSymHybridXY) {
+        // components x and y packed as one complex field: (i s_x - s_y) f~
+        const double sx = -X[2 * px + i] / k2 - X[3 * px + i] / lam;
+        const double sy = -Y[2 * py + a] / k2 - Y[3 * py + a] / lam;
+        return cmul(v, make_double2(-sy * c, sx * c));
+    }
+    const double sz = -Z[2 * pz + b] / k2 - Z[3 * pz + b] / lam;
+    return cmul(v, make_double2(0.0, sz * c));
+}
+
+// One pass of 1-D transforms of length N = 2^lgN over the lines (a, b) of a 3-D array.
+// CONTIG: lines are contiguous (si = 1), a tile is nl consecutive a (b unused).
+// Otherwise: a tile is one a and nl consecutive b (sb = 1).
+template <bool CONTIG, int IN, int OUT, int OP, int SYM>
+__global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass A) {
+    extern __shared__ __align__(16) unsigned char fft_smem[];
+    double2* lds = (double2*)fft_smem;
+    const int lgnl = A.lgnl, nl = 1 << lgnl, LS = nl + 1, N = 1 << A.lgN;
+    int a, b0;
+    if (CONTIG) {
+        a = (int)blockIdx.x << lgnl;
+        b0 = 0;
+    } else {
+        const int nbt = (A.nb + nl - 1) >> lgnl;
+        a = (int)blockIdx.x / nbt;
+        b0 = ((int)blockIdx.x - a * nbt) << lgnl;
+    }
+    // load (zero beyond m_in and for lines past the end)
+    if (CONTIG) {
+        for (int l = 0; l < nl; ++l) {
+            const bool ok = a + l < A.na;
+            const long long base = (long long)(a + l) * A.in_sa;
+            for (int i = (int)threadIdx.x; i < N; i += kBlock)
+                lds[i * LS + l] = (ok && i < A.m_in) ? load_in<IN>(A, base + i) : make_double2(0.0, 0.0);
+        }
+    } else {
+        const long long base = (long long)a * A.in_sa + b0;
+        for (int e = (int)threadIdx.x; e < nl * N; e += kBlock) {
+            const int l = e & (nl - 1), i = e >> lgnl;
+            lds[i * LS + l] = (b0 + l < A.nb && i < A.m_in) ? load_in<IN>(A, base + l + (long long)i * A.in_si)
+                                                             : make_double2(0.0, 0.0);
+        }
+    }
+    __syncthreads();
+    if (OP == kFftInverse) {
+        fft_tile<true>(lds, A.lgN, lgnl, A.tw, A.lgtw);
+    } else {
+        fft_tile<false>(lds, A.lgN, lgnl, A.tw, A.lgtw);
+        if (OP == kFftFwdSymInv) {
+            for (int e = (int)threadIdx.x; e < nl * N; e += kBlock) {
+                const int l = e & (nl - 1), i = e >> lgnl;
+                if (b0 + l < A.nb) lds[i * LS + l] = apply_sym<SYM>(A, i, a, b0 + l, lds[i * LS + l]);
+            }
+            __syncthreads();
+            fft_tile<true>(lds, A.lgN, lgnl, A.tw, A.lgtw);
+        }
+    }
+    // store the first m_out points of every line
+    if (CONTIG) {
+        for (int l = 0; l < nl; ++l) {
+            if (a + l >= A.na) break;
+            const long long base = (long long)(a + l) * A.out_sa;
+            for (int i = (int)threadIdx.x; i < A.m_out; i += kBlock) store_out<OUT>(A, base + i, lds[i * LS + l]);
+        }
+    } else {
+        const long long base = (long long)a * A.out_sa + b0;
+        for (int e = (int)threadIdx.x; e < nl * A.m_out; e += kBlock) {
+            const int l = e & (nl - 1), i = e >> lgnl;
+            if (b0 + l < A.nb) store_out<OUT>(A, base + l + (long long)i * A.out_si, lds[i * LS + l]);
+        }
+    }
+}
+
+// e^{-2 pi i t / 2^lg} for t < 2^lg
+__global__ void k_fft_twiddles(double2* tw, int lg) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= (1 << lg)) return;
+    double s, c;
+    sincospi(2.0 * (double)t / (double)(1 << lg), &s, &c);
+    tw[t] = make_double2(c, -s);
+}
+
+// Per-axis multiplier tables.  Mode m of an axis of P points (m = t for t < P/2, t - P above) has
+// kh = 2 pi m / P.  kind kSymFv: 1 / sinc(kh/2); kSymSg: 1 / cos(kh/4); hybrid: the four blocks
+// [kh^2 | Laplacian symbol of the order | kh, 0 on Nyquist | gradient symbol g, 0 on Nyquist].
+__global__ void k_spec_tables(double* t0, double* t1, double* t2, int p0, int p1, int p2, int kind, int lap_order,
+                              int grad_order) {
+    int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    double* tab;
+    int P;
+    if (t < p0) {
+        tab = t0;
+        P = p0;
+    } else if (t < p0 + p1) {
+        tab = t1;
+        P = p1;
+        t -= p0;
+    } else if (t < p0 + p1 + p2) {
+        tab = t2;
+        P = p2;
+        t -= p0 + p1;
+    } else {
+        return;
+    }
+    const int m = t < P / 2 ? t : t - P;
+    const double q = 2.0 * (double)m / (double)P;   // kh / pi
+    const double kh = 3.14159265358979323846 * q;
+    if (kind == kSpecFv) {
+        double s, c;
+        sincospi(0.5 * q, &s, &c);
+        tab[t] = m == 0 ? 1.0 : (0.5 * kh) / s;
+        return;
+    }
+    if (kind == kSpecSg) {
+        tab[t] = 1.0 / cospi(0.25 * q);
+        return;
+    }
+    double s1, c1, s2, c2, s3, c3;
+    sincospi(q, &s1, &c1);
+    sincospi(2.0 * q, &s2, &c2);
+    sincospi(3.0 * q, &s3, &c3);
+    double lam;
+    if (lap_order == 2) lam = -2.0 * (1.0 - c1);
+    else if (lap_order == 4) lam = -(c2 - 16.0 * c1 + 15.0) / 6.0;
+    else lam = -(-2.0 * c3 + 27.0 * c2 - 270.0 * c1 + 245.0) / 90.0;
+    double g;
+    if (grad_order == 4) g = (8.0 * s1 - s2) / 6.0;
+    else g = (45.0 * s1 - 9.0 * s2 + s3) / 30.0;
+    const bool nyq = 2 * t == P;
+    tab[t] = kh * kh;
+    tab[P + t] = lam;
+    tab[2 * P + t] = nyq ? 0.0 : kh;
+    tab[3 * P + t] = nyq ? 0.0 : g;
+}
+
+template <bool CONTIG, int IN, int OUT, int OP, int SYM>
+hipError_t run_pass(const FftPass& A, hipStream_t st) {
+    const int nl = 1 << A.lgnl;
+    const unsigned lds = (unsigned)((1u << A.lgN) * (unsigned)(nl + 1) * sizeof(double2));
+    const void* fn = (const void*)k_fft_pass<CONTIG, IN, OUT, OP, SYM>;
+    static bool raised = false;
+    if (!raised) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftMaxLds);
+        if (e != hipSuccess) return e;
+        raised = true;
+    }
+    unsigned blocks;
+    if (CONTIG) blocks = (unsigned)((A.na + nl - 1) / nl);
+    else blocks = (unsigned)A.na * (unsigned)((A.nb + nl - 1) / nl);
+    if (blocks == 0) return hipSuccess;
+    k_fft_pass<CONTIG, IN, OUT, OP, SYM><<<blocks, kBlock, lds, st>>>(A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int fft_lines_per_tile(int lgN) {   // log2 of the tile's line count: nl * N <= kFftTile, nl <= 16
+    int lg = 4;
+    while (lg > 0 && (1 << (lg + lgN)) > kFftTile) --lg;
+    return lg;
+}
+
+hipError_t launch_fft_twiddles(double2* tw, int lg, hipStream_t st) {
+    k_fft_twiddles<<<((1 << lg) + kBlock - 1) / kBlock, kBlock, 0, st>>>(tw, lg);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_tables(double* t0, double* t1, double* t2, const int P[3], int kind, int lap_order,
+                              int grad_order, hipStream_t st) {
+    const int total = P[0] + P[1] + P[2];
+    k_spec_tables<<<(total + kBlock - 1) / kBlock, kBlock, 0, st>>>(t0, t1, t2, P[0], P[1], P[2], kind, lap_order,
+                                                                     grad_order);
+    return hipGetLastError();
+}
+
+// dispatch on the combinations the host pipelines use
+hipError_t launch_fft_pass(const FftPass& A, bool contig, int in, int out, int op, int sym, hipStream_t st) {
+    if (contig) {
+        if (op == kFftForward && in == kFftInRe && out == kFftOutCplx)
+            return run_pass<true, kFftInRe, kFftOutCplx, kFftForward, 0>(A, st);
+        if (op == kFftForward && in == kFftInRePair && out == kFftOutCplx)
+            return run_pass<true, kFftInRePair, kFftOutCplx, kFftForward, 0>(A, st);
+        if (op == kFftForward && in == kFftInCplx && out == kFftOutCplx)
+            return run_pass<true, kFftInCplx, kFftOutCplx, kFftForward, 0>(A, st);
+        if (op == kFftInverse && in == kFftInCplx && out == kFftOutRePairStore)
+            return run_pass<true, kFftInCplx, kFftOutRePairStore, kFftInverse, 0>(A, st);
+        if (op == kFftInverse && in == kFftInCplx && out == kFftOutRePairAdd)
+            return run_pass<true, kFftInCplx, kFftOutRePairAdd, kFftInverse, 0>(A, st);
+        if (op == kFftInverse && in == kFftInCplx && out == kFftOutCplx)
+            return run_pass<true, kFftInCplx, kFftOutCplx, kFftInverse, 0>(A, st);
+        return hipErrorInvalidValue;
+    }
+    if (in != kFftInCplx) return hipErrorInvalidValue;
+    if (op == kFftForward && out == kFftOutCplx) return run_pass<false, kFftInCplx, kFftOutCplx, kFftForward, 0>(A, st);
+    if (op == kFftForward && out == kFftOutRe) return run_pass<false, kFftInCplx, kFftOutRe, kFftForward, 0>(A, st);
+    if (op == kFftInverse && out == kFftOutCplx) return run_pass<false, kFftInCplx, kFftOutCplx, kFftInverse, 0>(A, st);
+    if (op == kFftFwdSymInv && out == kFftOutCplx) {
+        switch (sym) {
+            case kSymSeparable: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymSeparable>(A, st);
+            case kSymTable: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymTable>(A, st);
+            case kSymHybridXY: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymHybridXY>(A, st);
+            case kSymHybridZ: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymHybridZ>(A, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mgic

@@ -430,4 +430,43 @@ constexpr int kHozParts = 2048;
 void launch_hoz_psum(int mode, const double* v, const double* f, const double* g, const int* n, const int* lo,
                      const int* cn, double h, int order, double* part, hipStream_t st);
 
+// ---- three-dimensional FFTs (k_fft.hip) -------------------------------------------------------
+constexpr int kFftTile = 4096;                       // complex points per workgroup tile
+constexpr int kFftMaxLgN = 10;                       // transforms of length 2 .. 1024
+constexpr unsigned kFftMaxLds = 1024u * 5u * 16u;    // N (nl + 1) 16 B at N = 1024, nl = 4
+enum { kFftInCplx = 0, kFftInRe = 1, kFftInRePair = 2 };
+enum { kFftOutCplx = 0, kFftOutRe = 1, kFftOutRePairStore = 2, kFftOutRePairAdd = 3 };
+enum { kFftForward = 0, kFftInverse = 1, kFftFwdSymInv = 2 };
+enum { kSymSeparable = 1, kSymTable = 2, kSymHybridXY = 3, kSymHybridZ = 4 };
+enum { kSpecFv = 1, kSpecSg = 2, kSpecHybrid = 3 };
+// one pass of batched 1-D transforms: line (a, b) holds point i at a*sa + b + i*si (strided
+// passes) or a*sa + i (contiguous passes); the input line has m_in points (the rest is zero),
+// the first m_out points of the output line are stored
+struct FftPass {
+    int lgN = 0, lgnl = 0, lgtw = 0;
+    int m_in = 0, m_out = 0;
+    int na = 0, nb = 1;
+    long long in_sa = 0, in_si = 1, out_sa = 0, out_si = 1;
+    const void* in0 = nullptr;
+    const void* in1 = nullptr;
+    void* out0 = nullptr;
+    void* out1 = nullptr;
+    const double2* tw = nullptr;
+    // multiplier of the fused x pass: element (kx, ky, kz) = (point, a, b)
+    const double* tab_x = nullptr;
+    const double* tab_y = nullptr;
+    const double* tab_z = nullptr;
+    int sym_n[3] = {0, 0, 0};
+    const double* tab = nullptr;
+    long long tab_si = 0, tab_sa = 0;
+    double sym_scale = 1.0;
+};
+int fft_lines_per_tile(int lgN);
+hipError_t launch_fft_twiddles(double2* tw, int lg, hipStream_t st);
+hipError_t launch_spec_tables(double* t0, double* t1, double* t2, const int P[3], int kind, int lap_order,
+                              int grad_order, hipStream_t st);
+hipError_t launch_fft_pass(const FftPass& A, bool contig, int in, int out, int op, int sym, hipStream_t st);
+// error reporting shared by the host translation units (sets mg_last_error's message)
+int report_error(int code, const char* msg);
+
 }  // namespace mgic

@@ -29,6 +29,8 @@ static int fail(int code, const std::string& msg) {
     return code;
 }
 
+int report_error(int code, const char* msg) { return fail(code, msg); }
+
 // on failure the runtime's last-error state is cleared as well, so that a failed call here is
 // not reported again by the caller's next, unrelated HIP call
 #define MG_HIP(call)                                                                           \

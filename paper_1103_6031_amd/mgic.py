@@ -84,6 +84,11 @@ _sig = {
     "lpt_displacements_and_source": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.c_int, ctypes.c_double,
                                                     _PP, _P, _sz, _P]),
     "lpt_lla_density": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, _PP, _P, _sz, _P]),
+    "spec_workspace_bytes": (_sz, [ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "spec_deconvolve": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, _P, _P, _P, _sz,
+                                       _P]),
+    "lpt_hybrid_correction": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, _PP, _P, _sz, _P]),
     "mg_batch_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mg_opts)]),
     "mg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                       _PP, _PP, ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
@@ -434,6 +439,45 @@ def lpt_lla_density(hier: Hier, disp, disp2=None, delta=None, workspace=None, st
     dp, _da = _ptr_array([_dev(x, "delta") for x in delta])
     _check(_lib.lpt_lla_density(ctypes.byref(H), ap, bp, dp, ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
     return delta
+
+
+SPEC_FV_DECONV = 1
+SPEC_SG_DECONV = 2
+
+
+def _shape3(shape):
+    n = tuple(int(v) for v in shape)
+    if len(n) != 3:
+        raise ValueError("fields must be 3-D")
+    return (ctypes.c_int * 3)(*n)
+
+
+def spec_workspace_bytes(shape, isolated=False) -> int:
+    need = _lib.spec_workspace_bytes(_shape3(shape), 1 if isolated else 0)
+    if need == 0:
+        raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
+    return need
+
+
+def spec_deconvolve(f, kind, isolated=False, out=None, workspace=None, stream=None):
+    """Section 3.5.1 (kind SPEC_FV_DECONV) or 3.5.3 (SPEC_SG_DECONV) deconvolution of f."""
+    if out is None:
+        out = torch.empty_like(f)
+    ws = _ws(workspace, spec_workspace_bytes(f.shape, isolated))
+    _check(_lib.spec_deconvolve(_shape3(f.shape), int(kind), 1 if isolated else 0, _dev(f, "f"), _dev(out, "out"),
+                                ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+    return out
+
+
+def lpt_hybrid_correction(f, h, out, isolated=False, lap_order=2, grad_order=4, scale=1.0, workspace=None,
+                          stream=None):
+    """Section 3.5.2: adds the hybrid Poisson correction of source f to out = [psi_x, psi_y, psi_z]."""
+    ws = _ws(workspace, spec_workspace_bytes(f.shape, isolated))
+    op, _oa = _ptr_array([_dev(c, "out") for c in out])
+    _check(_lib.lpt_hybrid_correction(_shape3(f.shape), float(h), 1 if isolated else 0, int(lap_order),
+                                      int(grad_order), float(scale), _dev(f, "f"), op, ctypes.c_void_p(ws.ptr),
+                                      ws.nbytes, _stream(stream)))
+    return out
 
 
 def mg_batch_workspace_bytes(sizes, opts=None) -> int:

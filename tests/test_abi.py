@@ -202,3 +202,26 @@ def test_tuning_cache_file_round_trip_and_validation(tmp_path):
         mgic.mg_tune_cache(str(other))
     assert mgic.mg_tune_cache(str(tmp_path / "absent.json")) == 0   # created on the next tuning
     assert mgic.mg_tune_cache(None) == 0
+
+
+def test_spectral_calls_validate_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    n = (ctypes.c_int * 3)(16, 16, 16)
+    assert mgic.spec_workspace_bytes((16, 16, 16)) > 3 * 16 ** 3 * 16
+    # isolated 96^3 pads to 256 per axis; 513 cells exceed the 1024-point transforms
+    assert mgic.spec_workspace_bytes((96, 96, 96), isolated=True) > 2 * 96 * 256 * 256 * 16
+    for shape, iso in (((12, 16, 16), False), ((16, 16, 2048), False), ((0, 4, 4), True), ((513, 8, 8), True)):
+        with pytest.raises(mgic.MGError):
+            mgic.spec_workspace_bytes(shape, iso)
+    fake = ctypes.c_void_p(256)
+    outs = (ctypes.c_void_p * 3)(256, 256, 256)
+    op = ctypes.cast(outs, mgic._PP)
+    assert mgic._lib.spec_deconvolve(n, 3, 0, fake, fake, fake, 1 << 30, None) == mgic.MG_EINVAL
+    assert mgic._lib.spec_deconvolve(n, 1, 0, fake, fake, None, 0, None) == mgic.MG_EINVAL
+    assert b"workspace" in mgic._lib.mg_last_error()
+    assert mgic._lib.spec_deconvolve(n, 1, 0, fake, fake, ctypes.c_void_p(257), 1 << 30, None) == mgic.MG_EINVAL
+    assert b"aligned" in mgic._lib.mg_last_error()
+    for lap, grad, h in ((3, 4, 1.0), (2, 5, 1.0), (2, 4, 0.0), (2, 4, float("nan"))):
+        assert mgic._lib.lpt_hybrid_correction(n, h, 0, lap, grad, 1.0, fake, op, fake, 1 << 30,
+                                               None) == mgic.MG_EINVAL
+    assert mgic._lib.lpt_hybrid_correction(n, 1.0, 0, 2, 4, 1.0, None, op, fake, 1 << 30, None) == mgic.MG_EINVAL
