@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel directly (no graph replay)")
     ap.add_argument("--only", default="",
                     help="comma-separated legs to run alone, without the headline step (profiling): "
-                         "roof512, c1, c3, hoz, c4")
+                         "roof512, c1, c3, hoz, c4, spectral")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -322,6 +322,71 @@ def time_highorder_zoom(mg, torch, reps=2):
                 value=round((s1["cell_updates"] + s2["cell_updates"]) / dt / 1e6, 1), unit="Mcell-updates/s")
 
 
+def spectral_bytes(n, P, what):
+    """Algorithmic HBM bytes of one call of the three-pass FFT pipeline on an n-cell field
+    transformed on P points per axis (P = n periodic, the padded length isolated): every pass
+    reads and writes each stored complex point once (16 B); the first pass reads the real field
+    (8 B), the last writes real outputs (8 B each, read and written when added).  what: "deconv"
+    (one multiplier, one output) or "hybrid" (two multiplier passes: x+iy and z, added to three
+    outputs)."""
+    n0, n1, n2 = n
+    p0, p1, p2 = P
+    w1 = n0 * n1 * p2
+    w2 = n0 * p1 * p2
+    cells = n0 * n1 * n2
+    fwd = 8 * cells + 16 * w1 + 16 * w1 + 16 * w2          # z pass (real in), y pass
+    mid = 16 * w2 + 16 * w2 + 16 * w2 + 16 * w1            # x pass fused, y inverse
+    if what == "deconv":
+        return fwd + mid + 16 * w1 + 8 * cells
+    return fwd + 2 * mid + (16 * w1 + 32 * cells) + (16 * w1 + 16 * cells)
+
+
+def time_spectral(mg, torch, ft, reps=5):
+    """Section 3.5 on the GPU: the hybrid Poisson correction on the periodic 256^3 base (a pure
+    FFT Poisson displacement when added to the multigrid one) and on a 128^3 patch zero-padded to
+    256^3 (the finest level of the zoom hierarchy), and the cell-average deconvolution of the
+    256^3 density.  Median of `reps` calls after one warm-up, HIP events on the launch stream;
+    GB/s from the algorithmic bytes of spectral_bytes."""
+    from paper_1103_6031_amd import inputs
+    n = ft.shape[0]
+    h = inputs.BOX / n
+    res = {}
+
+    def clock(fn):
+        ts = []
+        for i in range(reps + 1):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if i:
+                ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    out = [torch.zeros_like(ft) for _ in range(3)]
+    ws = mg.Workspace(mg.spec_workspace_bytes(ft.shape))
+    ms = clock(lambda: mg.lpt_hybrid_correction(ft, h, out, workspace=ws))
+    b = spectral_bytes(ft.shape, ft.shape, "hybrid")
+    res["hybrid_periodic_%d" % n] = dict(ms=round(ms, 3), gbs=round(b / (ms * 1e-3) / 1e9, 1),
+                                         algorithmic_bytes=b, transforms="1 forward + 2 inverse complex %d^3" % n)
+    patch = ft[64:192, 64:192, 64:192].contiguous()
+    outp = [torch.zeros_like(patch) for _ in range(3)]
+    wsp = mg.Workspace(mg.spec_workspace_bytes(patch.shape, isolated=True))
+    ms = clock(lambda: mg.lpt_hybrid_correction(patch, h / 2, outp, isolated=True, workspace=wsp))
+    b = spectral_bytes(patch.shape, (256, 256, 256), "hybrid")
+    res["hybrid_isolated_128_pad256"] = dict(ms=round(ms, 3), gbs=round(b / (ms * 1e-3) / 1e9, 1),
+                                             algorithmic_bytes=b)
+    dec = torch.empty_like(ft)
+    ms = clock(lambda: mg.spec_deconvolve(ft, mg.SPEC_FV_DECONV, out=dec, workspace=ws))
+    b = spectral_bytes(ft.shape, ft.shape, "deconv")
+    res["fv_deconvolve_%d" % n] = dict(ms=round(ms, 3), gbs=round(b / (ms * 1e-3) / 1e9, 1), algorithmic_bytes=b)
+    res["workload"] = ("Section 3.5 on the %d^3 BBKS density: hybrid correction periodic, the same on a 128^3 patch "
+                       "isolated (zero-padded to 256^3), cell-average deconvolution; FP64" % n)
+    return res
+
+
 def time_c3(mg, torch, reps=3):
     """The zoom hierarchy: 128^3 base with three centred 128^3 patches, the 2LPT chain (solve,
     displacements, tau, solve, displacements) in both precisions."""
@@ -479,6 +544,8 @@ def main():
                 line["highorder_zoom"] = time_highorder_zoom(mg, torch)
             elif leg == "c4":
                 line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
+            elif leg == "spectral":
+                line["spectral"] = time_spectral(mg, torch, ft)
             else:
                 raise SystemExit("unknown leg " + leg)
         if a.pmc_calib:
@@ -529,6 +596,7 @@ def main():
         roof["beyond_infinity_cache"] = r5
     line["lla"] = time_lla(mg, torch, H, out_h[1], out_h[4])
     line["highorder"] = time_highorder(mg, torch, ft, h, a.tol)
+    line["spectral"] = time_spectral(mg, torch, ft)
     if not a.no_c1c3:
         line["solve_c1"] = time_c1(mg, torch)
         line["zoom_c3"] = time_c3(mg, torch)

@@ -27,6 +27,9 @@ cosmological simulations" (MNRAS 2011):
 * ``spectral`` - Section 3.5: finite-volume (cell-average) and sub-grid deconvolution, and the
                  hybrid Poisson correction (k-space exact displacement on the finest grid,
                  periodic or zero-padded isolated), by numpy FFTs.
+* ``density``  - Sections 2.1-2.3: the multi-scale Gaussian density on nested grids (kernels
+                 per level, mode-preserving white-noise refinement, nested FFT convolutions
+                 with conservative tri-cubic interpolation of the coarse contributions).
 * ``dense``    - brute-force dense assembly of the periodic and composite
                  linear systems for tiny grids (pins for the iterative solvers).
 
@@ -40,4 +43,4 @@ brute-force dense solves or invariants that do not reuse the oracle's own
 arithmetic.
 """
 
-from . import stencil, periodic, lpt, zoom, zoom_ho, dense, highorder, spectral  # noqa: F401
+from . import stencil, periodic, lpt, zoom, zoom_ho, dense, highorder, spectral, density  # noqa: F401

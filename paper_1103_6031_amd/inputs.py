@@ -149,6 +149,57 @@ def nested_fields(N0, patches, seed, box=BOX, spectrum=spectrum_bbks, rms=DELTA_
     return out
 
 
+# ----------------------------------------------------------------------------- multi-scale convolution inputs
+
+def radial_transfer_table(alpha, h_finest, spectrum=spectrum_bbks, r_max=192.0, count=1 << 18):
+    """The real-space transfer function T(r) = (1 / 2 pi^2) int T~(k) k^2 sin(kr) / (kr) dk of
+    T~(k) = alpha sqrt(P(k)) exp(-(k / k_c)^2 / 2), tabulated at r = i dr (i < count,
+    dr = r_max / count); returns (table, dr).
+
+    This is input data, like P(k) itself: the paper obtains T(r) once from a Boltzmann code's
+    transfer function with FFTlog.  Here a discrete sine transform on the uniform k grid
+    k_j = j pi / r_max does the one-dimensional integral; the Gaussian cut at k_c = 2 pi / h_finest
+    (the sub-cell Nyquist of the finest grid) keeps the integral finite.
+    """
+    dr = r_max / count
+    dk = np.pi / r_max
+    k = np.arange(count) * dk
+    kc = 2.0 * np.pi / h_finest
+    g = alpha * np.sqrt(np.maximum(spectrum(k), 0.0)) * np.exp(-0.5 * (k / kc) ** 2)
+    g[0] = 0.0
+    a = g * k
+    ext = np.zeros(2 * count)
+    ext[:count] = a
+    ext[count + 1:] = -a[1:][::-1]
+    s = -0.5 * np.imag(np.fft.fft(ext))[:count]          # sum_j a_j sin(pi i j / count)
+    r = np.arange(count) * dr
+    table = np.empty(count)
+    table[1:] = s[1:] * dk / (2.0 * np.pi ** 2 * r[1:])
+    table[0] = np.sum(g * k * k) * dk / (2.0 * np.pi ** 2)
+    return table, dr
+
+
+def multiscale_noise(N0, patches, seed):
+    """Unit normals for the multi-scale convolution: N0^3 on the base, (2 n)^3 on every patch's
+    padded domain (the patch centred in twice its size)."""
+    rng = np.random.default_rng(seed)
+    out = [rng.standard_normal((N0,) * 3)]
+    for n, _ in patches:
+        out.append(rng.standard_normal(tuple(2 * int(v) for v in n)))
+    return out
+
+
+def c3_multiscale_input(n_base=128, n_patch=128, depth=3, seed=SEED_C3):
+    """The C3 geometry with the inputs of the multi-scale convolution: (patches, table, dr, xi).
+    The amplitude is the one that gives the k-space sampled base field of this spectrum the rms
+    DELTA_RMS."""
+    patches = c3_layout(n_base, n_patch, depth)
+    _, alpha = gaussian_field(n_base, seed, return_alpha=True)
+    h_finest = BOX / n_base / 2 ** depth
+    table, dr = radial_transfer_table(alpha, h_finest)
+    return patches, table, dr, multiscale_noise(n_base, patches, seed + 17)
+
+
 # ----------------------------------------------------------------------------- workloads
 
 def c1_input():
