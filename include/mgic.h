@@ -238,6 +238,39 @@ int lpt_lla_density(const mg_hier* hier, const double* const* disp, const double
                     double* const* delta, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------------
+ * Multi-scale Gaussian density on nested grids (Sections 2.1-2.3; sub-grid kernel mean of 3.5.3)
+ *
+ * delta = T * mu on every level of hier, with
+ *   - T the real-space transfer function, given as radial[i] = T(i dr) (i < nradial, linear
+ *     interpolation in r; the paper's FFTlog output), sampled on each level's displacement grid:
+ *     the finest level directly or (subgrid != 0) as the mean over the 8 sub-cell centres at
+ *     +-h/4; each coarser level as the mean over child pairs of the finer level's kernel (eq.
+ *     transfer_average: fine displacements 2J-1, 2J, 2J+1 weighted 1/4, 1/2, 1/4 per axis) where
+ *     the finer kernel grid reaches, T(|D|) elsewhere;
+ *   - mu the white noise: xi[0] holds N^3 unit normals for the base, xi[p] (2 n_p)^3 unit normals
+ *     on patch p's padded domain D'_p (twice the patch per axis, the patch centred at
+ *     [n_p/2, 3 n_p/2)); level l's noise is xi / h_l^(3/2).  Each patch's noise keeps the modes of
+ *     its parent below the parent's Nyquist (its coefficients replaced by 8 C(m) times the phase of
+ *     the quarter-cell offset, C the DFT of the parent cells under D'), top down; then every
+ *     covered parent cell's noise becomes the mean of its 8 children, finest first;
+ *   - per patch: delta_self + delta_bnd (the noise inside the patch, and the noise minus its
+ *     parent's value on the padding, convolved circularly on D') plus the conservative tri-cubic
+ *     interpolation of the coarse contributions: the parent's noise outside the patch (the base:
+ *     periodic; a parent patch: its own cells only) convolved with the parent's kernel, added to
+ *     what the parent itself received.  delta_bnd's 8-child means are added to the parent's
+ *     density on the parent cells under D' outside the patch.  Finally every covered coarse cell
+ *     of delta is the mean of its children.
+ * Geometry: a power-of-two cubic base (2..1024) and power-of-two patch sizes (4..512 per axis)
+ * with the usual nesting (mg_workspace_bytes' rules); D'_p must lie inside the parent patch (the
+ * base wraps; the first patch needs n <= N).  radial must reach every sampled radius (MG_EINVAL
+ * names the radius otherwise).  xi and radial are read only; delta[l] is the level's own cells
+ * (N^3, n_p^3).  All pointers are device memory; asynchronous on stream. */
+size_t ic_density_workspace_bytes(const mg_hier* hier);
+int ic_multiscale_density(const mg_hier* hier, const double* radial, int nradial, double dr,
+                          int subgrid, const double* const* xi, double* const* delta,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
  * Spectral corrections that recover small-scale power (Section 3.5)
  *
  * Fields are real FP64 arrays of n[0] x n[1] x n[2] cells, natural [x][y][z] order, z contiguous,

@@ -21,8 +21,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
 ]
-SOURCES = ["k_multigrid.hip", "k_levels.hip", "k_lpt.hip", "k_highorder.hip", "k_fft.hip", "solver.cpp",
-           "spectral.cpp"]
+SOURCES = ["k_multigrid.hip", "k_levels.hip", "k_lpt.hip", "k_highorder.hip", "k_fft.hip", "k_density.hip",
+           "solver.cpp", "spectral.cpp", "density.cpp"]
 
 
 def _compile(args):

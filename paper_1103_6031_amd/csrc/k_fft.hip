@@ -142,6 +142,23 @@ __device__ __forceinline__ double2 apply_sym(const FftPass& A, int i, int a, int
         const double m = A.tab[(long long)i * A.tab_si + (long long)a * A.tab_sa + b] * c;
         return make_double2(v.x * m, v.y * m);
     }
+    if (SYM == kSymReplace) {
+        // modes below the coarse grid's Nyquist on every axis take 8 C(m) prod_a e^{-i pi m_a / P_a}
+        // (per-axis phase tables hold cos, sin pairs); the rest keep the fine spectrum
+        const int px = A.sym_n[0], py = A.sym_n[1], pz = A.sym_n[2];
+        const int mx = i < px / 2 ? i : i - px, my = a < py / 2 ? a : a - py, mz = b < pz / 2 ? b : b - pz;
+        const int cx = A.cn[0], cy = A.cn[1], cz = A.cn[2];
+        if (2 * abs(mx) < cx && 2 * abs(my) < cy && 2 * abs(mz) < cz) {
+            const int ix = mx < 0 ? mx + cx : mx, iy = my < 0 ? my + cy : my, iz = mz < 0 ? mz + cz : mz;
+            const double2 C = A.csp[((long long)ix * cy + iy) * cz + iz];
+            double2 w = make_double2(8.0 * C.x, 8.0 * C.y);
+            w = cmul(w, make_double2(A.tab_x[2 * i], A.tab_x[2 * i + 1]));
+            w = cmul(w, make_double2(A.tab_y[2 * a], A.tab_y[2 * a + 1]));
+            w = cmul(w, make_double2(A.tab_z[2 * b], A.tab_z[2 * b + 1]));
+            v = w;
+        }
+        return make_double2(v.x * c, v.y * c);
+    }
     // hybrid correction: per-axis blocks [k^2 | lambda_1d | k (0 on Nyquist) | g (0 on Nyquist)]
     const double* X = A.tab_x;
     const double* Y = A.tab_y;
@@ -267,6 +284,13 @@ __global__ void k_spec_tables(double* t0, double* t1, double* t2, int p0, int p1
         tab[t] = 1.0 / cospi(0.25 * q);
         return;
     }
+    if (kind == kSpecReplace) {   // e^{-i pi m / P}: the fine centres sit a quarter coarse cell off
+        double s, c;
+        sincospi((double)m / (double)P, &s, &c);
+        tab[2 * t] = c;
+        tab[2 * t + 1] = -s;
+        return;
+    }
     double s1, c1, s2, c2, s3, c3;
     sincospi(q, &s1, &c1);
     sincospi(2.0 * q, &s2, &c2);
@@ -352,6 +376,7 @@ hipError_t launch_fft_pass(const FftPass& A, bool contig, int in, int out, int o
             case kSymTable: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymTable>(A, st);
             case kSymHybridXY: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymHybridXY>(A, st);
             case kSymHybridZ: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymHybridZ>(A, st);
+            case kSymReplace: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymReplace>(A, st);
             default: return hipErrorInvalidValue;
         }
     }

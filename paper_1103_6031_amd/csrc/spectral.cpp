@@ -40,24 +40,54 @@ int pad_len(int n) {
     return p;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+FftPass pass_base(const SpecGrid& S, int axis) {
+    FftPass A;
+    A.lgN = S.lg[axis];
+    A.lgnl = fft_lines_per_tile(A.lgN);
+    A.lgtw = S.lgtw;
+    A.tw = S.tw;
+    return A;
+}
+
 struct SpecPlan {
-    int n[3] = {0, 0, 0};
-    int P[3] = {0, 0, 0};
-    int lg[3] = {0, 0, 0};
-    int lgtw = 0;
-    // workspace
-    double2* tw = nullptr;
-    double* tab[3] = {nullptr, nullptr, nullptr};
-    double2* W1 = nullptr;
-    double2* W2 = nullptr;
-    double2* W3 = nullptr;
+    SpecGrid G;
     size_t bytes = 0;
 };
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 // validates the shape and carves the workspace (ws == nullptr: sizes only)
 int spec_plan(const int* n, int isolated, void* ws, SpecPlan& S) {
+    int rc = spec_grid_init(n, isolated, S.G);
+    if (rc) return rc;
+    size_t off = 0;
+    spec_grid_carve(S.G, (char*)ws, off);
+    size_t w1, w2;
+    spec_grid_work(S.G, w1, w2);
+    char* base = (char*)ws;
+    auto take = [&](size_t bytes) -> void* {
+        off = align256(off);
+        void* p = base ? (void*)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    S.G.W1 = (double2*)take(sizeof(double2) * w1);
+    S.G.W2 = (double2*)take(sizeof(double2) * w2);
+    S.G.W3 = (double2*)take(sizeof(double2) * w2);
+    S.bytes = align256(off);
+    return MG_OK;
+}
+
+int check_ws(const SpecPlan& S, void* ws, size_t ws_bytes) {
+    if (!ws || ws_bytes < S.bytes)
+        return report_error(MG_EINVAL, ("workspace too small: need " + std::to_string(S.bytes)).c_str());
+    if (((uintptr_t)ws) & 255) return report_error(MG_EINVAL, "workspace must be 256-byte aligned");
+    return MG_OK;
+}
+
+}  // namespace
+
+int spec_grid_init(const int* n, int isolated, SpecGrid& S) {
     if (!n) return report_error(MG_EINVAL, "shape is NULL");
     for (int a = 0; a < 3; ++a) {
         if (n[a] < 1) return report_error(MG_EINVAL, "every axis needs at least one cell");
@@ -71,8 +101,10 @@ int spec_plan(const int* n, int isolated, void* ws, SpecPlan& S) {
         S.lg[a] = lg;
     }
     S.lgtw = std::max(S.lg[0], std::max(S.lg[1], S.lg[2]));
-    size_t off = 0;
-    char* base = (char*)ws;
+    return MG_OK;
+}
+
+void spec_grid_carve(SpecGrid& S, char* base, size_t& off) {
     auto take = [&](size_t bytes) -> void* {
         off = align256(off);
         void* p = base ? (void*)(base + off) : nullptr;
@@ -81,26 +113,23 @@ int spec_plan(const int* n, int isolated, void* ws, SpecPlan& S) {
     };
     S.tw = (double2*)take(sizeof(double2) << S.lgtw);
     for (int a = 0; a < 3; ++a) S.tab[a] = (double*)take(4 * sizeof(double) * (size_t)S.P[a]);
-    const size_t w1 = (size_t)S.n[0] * S.n[1] * S.P[2], w2 = (size_t)S.n[0] * S.P[1] * S.P[2];
-    S.W1 = (double2*)take(sizeof(double2) * w1);
-    S.W2 = (double2*)take(sizeof(double2) * w2);
-    S.W3 = (double2*)take(sizeof(double2) * w2);
-    S.bytes = align256(off);
-    return MG_OK;
 }
 
-FftPass pass_base(const SpecPlan& S, int axis) {
-    FftPass A;
-    A.lgN = S.lg[axis];
-    A.lgnl = fft_lines_per_tile(A.lgN);
-    A.lgtw = S.lgtw;
-    A.tw = S.tw;
-    return A;
+void spec_grid_work(const SpecGrid& S, size_t& w1, size_t& w2) {
+    w1 = (size_t)S.n[0] * S.n[1] * S.P[2];
+    w2 = (size_t)S.n[0] * S.P[1] * S.P[2];
+}
+
+hipError_t spec_grid_prepare(const SpecGrid& S, int kind, int lap_order, int grad_order, hipStream_t st) {
+    hipError_t e = launch_fft_twiddles(S.tw, S.lgtw, st);
+    if (e != hipSuccess) return e;
+    if (kind == 0) return hipSuccess;
+    return launch_spec_tables(S.tab[0], S.tab[1], S.tab[2], S.P, kind, lap_order, grad_order, st);
 }
 
 // z then y forward passes of a real field (in1 != nullptr: a second real field as the imaginary
 // part) into W2
-hipError_t forward_zy(const SpecPlan& S, const double* in0, const double* in1, hipStream_t st) {
+hipError_t spec_forward_zy(const SpecGrid& S, const double* in0, const double* in1, hipStream_t st) {
     FftPass z = pass_base(S, 2);
     z.na = S.n[0] * S.n[1];
     z.m_in = S.n[2];
@@ -126,19 +155,22 @@ hipError_t forward_zy(const SpecPlan& S, const double* in0, const double* in1, h
     return launch_fft_pass(y, false, kFftInCplx, kFftOutCplx, kFftForward, 0, st);
 }
 
-// x pass: forward, multiply, inverse, W2 -> W3 (the first n0 points of every x line)
-hipError_t x_multiply(const SpecPlan& S, int sym, double scale, const double* tab, hipStream_t st) {
+// x pass on W2.  op kFftFwdSymInv: forward, multiply (sym), inverse, the first n0 points of every
+// line into W3.  op kFftForward: the spectrum itself (every point) into out, complex
+// (out_kind kFftOutCplx) or its real part (kFftOutRe), layout [P0][P1][P2].
+hipError_t spec_x_pass(const SpecGrid& S, int op, int out_kind, int sym, double scale, const double* tab,
+                       const double2* csp, const int* cn, void* out, hipStream_t st) {
     FftPass x = pass_base(S, 0);
     x.na = S.P[1];
     x.nb = S.P[2];
     x.m_in = S.n[0];
-    x.m_out = S.n[0];
+    x.m_out = op == kFftFwdSymInv ? S.n[0] : S.P[0];
     x.in_sa = S.P[2];
     x.in_si = (long long)S.P[1] * S.P[2];
     x.out_sa = S.P[2];
     x.out_si = x.in_si;
     x.in0 = S.W2;
-    x.out0 = S.W3;
+    x.out0 = op == kFftFwdSymInv ? (void*)S.W3 : out;
     x.tab_x = S.tab[0];
     x.tab_y = S.tab[1];
     x.tab_z = S.tab[2];
@@ -146,13 +178,16 @@ hipError_t x_multiply(const SpecPlan& S, int sym, double scale, const double* ta
     x.tab = tab;
     x.tab_si = (long long)S.P[1] * S.P[2];
     x.tab_sa = S.P[2];
+    x.csp = csp;
+    if (cn)
+        for (int a = 0; a < 3; ++a) x.cn[a] = cn[a];
     // the inverse transform's 1 / (P0 P1 P2) rides on the multiplier
     x.sym_scale = scale / ((double)S.P[0] * (double)S.P[1] * (double)S.P[2]);
-    return launch_fft_pass(x, false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, sym, st);
+    return launch_fft_pass(x, false, kFftInCplx, op == kFftFwdSymInv ? kFftOutCplx : out_kind, op, sym, st);
 }
 
 // y then z inverse passes, W3 -> real output(s) [n0][n1][n2] (real part -> out0, imaginary -> out1)
-hipError_t inverse_yz(const SpecPlan& S, double* out0, double* out1, bool add, hipStream_t st) {
+hipError_t spec_inverse_yz(const SpecGrid& S, double* out0, double* out1, bool add, hipStream_t st) {
     FftPass y = pass_base(S, 1);
     y.na = S.n[0];
     y.nb = S.P[2];
@@ -178,15 +213,6 @@ hipError_t inverse_yz(const SpecPlan& S, double* out0, double* out1, bool add, h
     return launch_fft_pass(z, true, kFftInCplx, add ? kFftOutRePairAdd : kFftOutRePairStore, kFftInverse, 0, st);
 }
 
-int check_ws(const SpecPlan& S, void* ws, size_t ws_bytes) {
-    if (!ws || ws_bytes < S.bytes)
-        return report_error(MG_EINVAL, ("workspace too small: need " + std::to_string(S.bytes)).c_str());
-    if (((uintptr_t)ws) & 255) return report_error(MG_EINVAL, "workspace must be 256-byte aligned");
-    return MG_OK;
-}
-
-}  // namespace
-
 }  // namespace mgic
 
 using namespace mgic;
@@ -209,12 +235,11 @@ int spec_deconvolve(const int n[3], int kind, int isolated, const double* f, dou
     if (rc) return rc;
     if ((rc = check_ws(S, ws, ws_bytes))) return rc;
     spec_plan(n, isolated, ws, S);
-    SP_HIP(launch_fft_twiddles(S.tw, S.lgtw, st));
-    SP_HIP(launch_spec_tables(S.tab[0], S.tab[1], S.tab[2], S.P, kind == SPEC_FV_DECONV ? kSpecFv : kSpecSg, 2, 4,
-                              st));
-    SP_HIP(forward_zy(S, f, nullptr, st));
-    SP_HIP(x_multiply(S, kSymSeparable, 1.0, nullptr, st));
-    SP_HIP(inverse_yz(S, out, nullptr, false, st));
+    const SpecGrid& G = S.G;
+    SP_HIP(spec_grid_prepare(G, kind == SPEC_FV_DECONV ? kSpecFv : kSpecSg, 2, 4, st));
+    SP_HIP(spec_forward_zy(G, f, nullptr, st));
+    SP_HIP(spec_x_pass(G, kFftFwdSymInv, 0, kSymSeparable, 1.0, nullptr, nullptr, nullptr, nullptr, st));
+    SP_HIP(spec_inverse_yz(G, out, nullptr, false, st));
     return MG_OK;
 }
 
@@ -232,14 +257,14 @@ int lpt_hybrid_correction(const int n[3], double h, int isolated, int lap_order,
     if (rc) return rc;
     if ((rc = check_ws(S, ws, ws_bytes))) return rc;
     spec_plan(n, isolated, ws, S);
-    SP_HIP(launch_fft_twiddles(S.tw, S.lgtw, st));
-    SP_HIP(launch_spec_tables(S.tab[0], S.tab[1], S.tab[2], S.P, kSpecHybrid, lap_order, grad_order, st));
-    SP_HIP(forward_zy(S, f, nullptr, st));
+    const SpecGrid& G = S.G;
+    SP_HIP(spec_grid_prepare(G, kSpecHybrid, lap_order, grad_order, st));
+    SP_HIP(spec_forward_zy(G, f, nullptr, st));
     // components x and y in one complex field, then z
-    SP_HIP(x_multiply(S, kSymHybridXY, scale * h, nullptr, st));
-    SP_HIP(inverse_yz(S, out3[0], out3[1], true, st));
-    SP_HIP(x_multiply(S, kSymHybridZ, scale * h, nullptr, st));
-    SP_HIP(inverse_yz(S, out3[2], nullptr, true, st));
+    SP_HIP(spec_x_pass(G, kFftFwdSymInv, 0, kSymHybridXY, scale * h, nullptr, nullptr, nullptr, nullptr, st));
+    SP_HIP(spec_inverse_yz(G, out3[0], out3[1], true, st));
+    SP_HIP(spec_x_pass(G, kFftFwdSymInv, 0, kSymHybridZ, scale * h, nullptr, nullptr, nullptr, nullptr, st));
+    SP_HIP(spec_inverse_yz(G, out3[2], nullptr, true, st));
     return MG_OK;
 }
 

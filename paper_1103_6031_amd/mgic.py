@@ -89,6 +89,9 @@ _sig = {
                                        _P]),
     "lpt_hybrid_correction": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, _PP, _P, _sz, _P]),
+    "ic_density_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier)]),
+    "ic_multiscale_density": (ctypes.c_int, [ctypes.POINTER(mg_hier), _P, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_int, _PP, _PP, _P, _sz, _P]),
     "mg_batch_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mg_opts)]),
     "mg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                       _PP, _PP, ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
@@ -478,6 +481,29 @@ def lpt_hybrid_correction(f, h, out, isolated=False, lap_order=2, grad_order=4, 
                                       int(grad_order), float(scale), _dev(f, "f"), op, ctypes.c_void_p(ws.ptr),
                                       ws.nbytes, _stream(stream)))
     return out
+
+
+def ic_density_workspace_bytes(hier: Hier) -> int:
+    H = hier.c_struct()
+    need = _lib.ic_density_workspace_bytes(ctypes.byref(H))
+    if need == 0:
+        raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
+    return need
+
+
+def ic_multiscale_density(hier: Hier, radial, dr, xi, subgrid=True, delta=None, workspace=None, stream=None):
+    """Sections 2.1-2.3: the density on every level from the radial transfer function table and
+    the unit normals xi (base N^3, patch p (2 n_p)^3 on its padded domain)."""
+    if delta is None:
+        delta = [torch.empty(hier.dims(p), dtype=torch.float64, device=xi[0].device) for p in range(hier.nlev)]
+    H = hier.c_struct()
+    ws = _ws(workspace, ic_density_workspace_bytes(hier))
+    xp, _xa = _ptr_array([_dev(x, "xi") for x in xi])
+    dp, _da = _ptr_array([_dev(d, "delta") for d in delta])
+    _check(_lib.ic_multiscale_density(ctypes.byref(H), _dev(radial, "radial"), int(radial.numel()), float(dr),
+                                      1 if subgrid else 0, xp, dp, ctypes.c_void_p(ws.ptr), ws.nbytes,
+                                      _stream(stream)))
+    return delta
 
 
 def mg_batch_workspace_bytes(sizes, opts=None) -> int:

@@ -225,3 +225,24 @@ def test_spectral_calls_validate_before_any_device_work():
         assert mgic._lib.lpt_hybrid_correction(n, h, 0, lap, grad, 1.0, fake, op, fake, 1 << 30,
                                                None) == mgic.MG_EINVAL
     assert mgic._lib.lpt_hybrid_correction(n, 1.0, 0, 2, 4, 1.0, None, op, fake, 1 << 30, None) == mgic.MG_EINVAL
+
+
+def test_density_validates_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    ok = mgic.Hier(32, 1.0, [((16, 16, 16), (8, 8, 8))])
+    assert mgic.ic_density_workspace_bytes(ok) > 0
+    for bad in (mgic.Hier(48, 1.0), mgic.Hier(32, 1.0, [((12, 12, 12), (8, 8, 8))]),
+                mgic.Hier(64, 1.0, [((32,) * 3, (16,) * 3), ((32,) * 3, (4,) * 3)])):
+        with pytest.raises(mgic.MGError):
+            mgic.ic_density_workspace_bytes(bad)
+    H = ok.c_struct()
+    fake = ctypes.c_void_p(256)
+    ptrs = (ctypes.c_void_p * 2)(256, 256)
+    pp = ctypes.cast(ptrs, mgic._PP)
+    assert mgic._lib.ic_multiscale_density(ctypes.byref(H), fake, 1 << 20, 0.01, 1, pp, pp, None, 0,
+                                           None) == mgic.MG_EINVAL
+    assert b"workspace" in mgic._lib.mg_last_error()
+    # a table too short for the base's corners
+    assert mgic._lib.ic_multiscale_density(ctypes.byref(H), fake, 100, 0.01, 1, pp, pp, fake, 1 << 40,
+                                           None) == mgic.MG_EINVAL
+    assert b"radial table" in mgic._lib.mg_last_error()
