@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel directly (no graph replay)")
     ap.add_argument("--only", default="",
                     help="comma-separated legs to run alone, without the headline step (profiling): "
-                         "roof512, c1, c3, hoz, c4, spectral")
+                         "roof512, c1, c3, hoz, c4, spectral, density")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -424,6 +424,64 @@ def time_c3(mg, torch, reps=3):
     return res
 
 
+def time_density(mg, torch, reps=3):
+    """Sections 2.1-2.3 on the zoom workload's geometry (128^3 base, three nested 128^3 patches,
+    padded domains of 256^3): kernels per level, noise refinement and nested convolutions from the
+    tabulated BBKS real-space transfer function and seeded unit normals already in HBM; median of
+    `reps` calls after one warm-up.  Then the 2LPT chain (mixed precision, tol 1e-10) on that
+    density, with the hybrid correction (Section 3.5.2) of the first-order displacement on the
+    finest patch, zero-padded to 256^3."""
+    from paper_1103_6031_amd import inputs
+    patches, table, dr, xi = inputs.c3_multiscale_input()
+    H = mg.Hier(128, inputs.BOX / 128, patches)
+    tab = torch.from_numpy(table).to("cuda:0")
+    xd = [torch.from_numpy(x).to("cuda:0") for x in xi]
+    ws = mg.Workspace(mg.ic_density_workspace_bytes(H))
+    delta = [torch.empty(H.dims(p), dtype=torch.float64, device="cuda:0") for p in range(H.nlev)]
+    ts = []
+    for i in range(reps + 1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mg.ic_multiscale_density(H, tab, dr, xd, delta=delta, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        if i:
+            ts.append(e0.elapsed_time(e1))
+    res = dict(workload="128^3 base + 3 nested 128^3 patches: multi-scale density (BBKS real-space kernel, "
+                        "sub-grid kernel mean), then the mixed-precision 2LPT chain on it",
+               density_ms=round(sorted(ts)[len(ts) // 2], 3),
+               density_rms=[round(float(torch.sqrt(torch.mean(d * d))), 5) for d in delta])
+    del ws
+    o = _opts(mg, tol=1e-10, prec="mixed", max_cycles=60)
+    wsm = mg.Workspace(mg.mg_workspace_bytes(H, o))
+    wl1 = mg.Workspace(mg.lpt_workspace_bytes(H, 1))
+    wl2 = mg.Workspace(mg.lpt_workspace_bytes(H, 2))
+    top = H.nlev - 1
+    wsh = mg.Workspace(mg.spec_workspace_bytes(H.dims(top), isolated=True))
+
+    def step():
+        phi, s1 = mg.mg_solve_hierarchy(H, delta, opts=o, workspace=wsm)
+        psi = mg.lpt_displacements(H, phi, scale=-1.0, workspace=wl1)
+        mg.lpt_hybrid_correction(delta[top], H.h(top), psi[top], isolated=True, scale=-1.0, workspace=wsh)
+        tau = mg.lpt2_source(H, phi, workspace=wl2)
+        phi2, s2 = mg.mg_solve_hierarchy(H, tau, opts=o, workspace=wsm)
+        mg.lpt_displacements(H, phi2, scale=-3.0 / 7.0, workspace=wl1)
+        return s1, s2
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s1, s2 = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    res["two_lpt_mixed"] = dict(ms_per_step=round(dt * 1e3, 3), cycles=[s1["cycles"], s2["cycles"]],
+                                rel_res=[s1["rel_res"], s2["rel_res"]],
+                                note="includes the hybrid correction of psi_1 on the finest patch")
+    return res
+
+
 def time_smoother_512(mg, torch, ft, h, tol):
     """The finest-level smoother on a working set four times the 256 MB Infinity Cache: the step's
     256^3 density tiled 2 x 2 x 2 (a periodic 512^3 field with the same spectrum on its even modes),
@@ -546,6 +604,8 @@ def main():
                 line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
             elif leg == "spectral":
                 line["spectral"] = time_spectral(mg, torch, ft)
+            elif leg == "density":
+                line["density_c3"] = time_density(mg, torch)
             else:
                 raise SystemExit("unknown leg " + leg)
         if a.pmc_calib:
@@ -597,6 +657,8 @@ def main():
     line["lla"] = time_lla(mg, torch, H, out_h[1], out_h[4])
     line["highorder"] = time_highorder(mg, torch, ft, h, a.tol)
     line["spectral"] = time_spectral(mg, torch, ft)
+    if not a.no_c1c3:
+        line["density_c3"] = time_density(mg, torch)
     if not a.no_c1c3:
         line["solve_c1"] = time_c1(mg, torch)
         line["zoom_c3"] = time_c3(mg, torch)

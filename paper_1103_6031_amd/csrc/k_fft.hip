@@ -11,7 +11,8 @@
 // loads each line as one run.  Along y and x a tile holds nl lines that are consecutive in z, so
 // every global access is a run of nl consecutive elements.  In LDS the tile is interleaved, point
 // i of line l at i * (nl + 1) + l: lane-consecutive lines are address-consecutive during the
-// stages, and the odd stride keeps the contiguous-line loads free of bank conflicts.
+// stages, and the odd stride keeps the contiguous-line loads free of bank conflicts.  The N
+// twiddles of the transform length follow the tile in LDS.
 //
 // The x pass can run forward, multiply every element by a multiplier of its (kx, ky, kz), and
 // run the inverse in the same launch: the spectrum of the x pass never goes to memory.
@@ -49,17 +50,16 @@ __device__ __forceinline__ void dft(double2* v) {
 
 // One Stockham stage on a tile of nl interleaved lines of length N = 2^lgN.  Butterfly j of a
 // line reads points j + r N/R, twiddles them by w^(r k N / (Ns R)) with k = j mod Ns, and writes
-// the radix-R DFT to points (j - k) R + k + r Ns.  tw holds e^{-2 pi i t / Ntw}, Ntw = 2^lgtw.
+// the radix-R DFT to points (j - k) R + k + r Ns.  twl holds e^{-2 pi i t / N}, t < N, in LDS.
 template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(double2* lds, int lgN, int lgnl, int lgNs, const double2* __restrict__ tw,
-                                          int lgtw) {
+__device__ __forceinline__ void fft_stage(double2* lds, const double2* twl, int lgN, int lgnl, int lgNs) {
     constexpr int kIt = kFftTile / (R * kBlock);
     constexpr int lgR = R == 4 ? 2 : 1;
     const int nl = 1 << lgnl, LS = nl + 1;
     const int P = 1 << (lgN - lgR);
     const int items = nl * P;
     const int Ns = 1 << lgNs;
-    const int tws = lgtw - lgNs - lgR;   // k * Ntw / (Ns R) = k << tws
+    const int tws = lgN - lgNs - lgR;   // k * N / (Ns R) = k << tws
     double2 v[kIt][R];
     int dst[kIt];
 #pragma unroll
@@ -73,7 +73,7 @@ __device__ __forceinline__ void fft_stage(double2* lds, int lgN, int lgnl, int l
             const int step = k << tws;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                double2 w = tw[r * step];
+                double2 w = twl[r * step];
                 if (INV) w.y = -w.y;
                 v[it][r] = cmul(v[it][r], w);
             }
@@ -95,13 +95,13 @@ __device__ __forceinline__ void fft_stage(double2* lds, int lgN, int lgnl, int l
 }
 
 template <bool INV>
-__device__ void fft_tile(double2* lds, int lgN, int lgnl, const double2* __restrict__ tw, int lgtw) {
+__device__ __forceinline__ void fft_tile(double2* lds, const double2* twl, int lgN, int lgnl) {
     int lgNs = 0;
     if (lgN & 1) {
-        fft_stage<2, INV>(lds, lgN, lgnl, 0, tw, lgtw);
+        fft_stage<2, INV>(lds, twl, lgN, lgnl, 0);
         lgNs = 1;
     }
-    for (; lgNs < lgN; lgNs += 2) fft_stage<4, INV>(lds, lgN, lgnl, lgNs, tw, lgtw);
+    for (; lgNs < lgN; lgNs += 2) fft_stage<4, INV>(lds, twl, lgN, lgnl, lgNs);
 }
 
 template <int IN>
@@ -180,11 +180,27 @@ __device__ __forceinline__ double2 apply_sym(const FftPass& A, int i, int a, int
 // One pass of 1-D transforms of length N = 2^lgN over the lines (a, b) of a 3-D array.
 // CONTIG: lines are contiguous (si = 1), a tile is nl consecutive a (b unused).
 // Otherwise: a tile is one a and nl consecutive b (sb = 1).
+// Tile point e (of nl N) is line e >> lgN, point e & (N - 1) (CONTIG), or line e & (nl - 1), point
+// e >> lgnl: consecutive lanes touch consecutive global addresses either way.  Every lane issues
+// all of its loads before it writes any of them to LDS.
+template <bool CONTIG>
+__device__ __forceinline__ void tile_coords(int e, int lgN, int lgnl, int& l, int& i) {
+    if (CONTIG) {
+        l = e >> lgN;
+        i = e & ((1 << lgN) - 1);
+    } else {
+        l = e & ((1 << lgnl) - 1);
+        i = e >> lgnl;
+    }
+}
+
 template <bool CONTIG, int IN, int OUT, int OP, int SYM>
 __global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass A) {
     extern __shared__ __align__(16) unsigned char fft_smem[];
+    constexpr int kLd = kFftTile / kBlock;
+    const int lgnl = A.lgnl, nl = 1 << lgnl, LS = nl + 1, lgN = A.lgN, N = 1 << lgN;
     double2* lds = (double2*)fft_smem;
-    const int lgnl = A.lgnl, nl = 1 << lgnl, LS = nl + 1, N = 1 << A.lgN;
+    double2* twl = lds + N * LS;
     int a, b0;
     if (CONTIG) {
         a = (int)blockIdx.x << lgnl;
@@ -194,48 +210,69 @@ __global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass A) {
         a = (int)blockIdx.x / nbt;
         b0 = ((int)blockIdx.x - a * nbt) << lgnl;
     }
-    // load (zero beyond m_in and for lines past the end)
-    if (CONTIG) {
-        for (int l = 0; l < nl; ++l) {
-            const bool ok = a + l < A.na;
-            const long long base = (long long)(a + l) * A.in_sa;
-            for (int i = (int)threadIdx.x; i < N; i += kBlock)
-                lds[i * LS + l] = (ok && i < A.m_in) ? load_in<IN>(A, base + i) : make_double2(0.0, 0.0);
+    const int total = nl << lgN;
+    // load (zero beyond m_in and for lines past the end), with this length's twiddles
+    {
+        double2 r[kLd];
+#pragma unroll
+        for (int k = 0; k < kLd; ++k) {
+            const int e = (int)threadIdx.x + k * kBlock;
+            r[k] = make_double2(0.0, 0.0);
+            if (e < total) {
+                int l, i;
+                tile_coords<CONTIG>(e, lgN, lgnl, l, i);
+                if (CONTIG) {
+                    if (a + l < A.na && i < A.m_in) r[k] = load_in<IN>(A, (long long)(a + l) * A.in_sa + i);
+                } else {
+                    if (b0 + l < A.nb && i < A.m_in)
+                        r[k] = load_in<IN>(A, (long long)a * A.in_sa + b0 + l + (long long)i * A.in_si);
+                }
+            }
         }
-    } else {
-        const long long base = (long long)a * A.in_sa + b0;
-        for (int e = (int)threadIdx.x; e < nl * N; e += kBlock) {
-            const int l = e & (nl - 1), i = e >> lgnl;
-            lds[i * LS + l] = (b0 + l < A.nb && i < A.m_in) ? load_in<IN>(A, base + l + (long long)i * A.in_si)
-                                                             : make_double2(0.0, 0.0);
+        for (int t = (int)threadIdx.x; t < N; t += kBlock) twl[t] = A.tw[t << (A.lgtw - lgN)];
+#pragma unroll
+        for (int k = 0; k < kLd; ++k) {
+            const int e = (int)threadIdx.x + k * kBlock;
+            if (e < total) {
+                int l, i;
+                tile_coords<CONTIG>(e, lgN, lgnl, l, i);
+                lds[i * LS + l] = r[k];
+            }
         }
     }
     __syncthreads();
     if (OP == kFftInverse) {
-        fft_tile<true>(lds, A.lgN, lgnl, A.tw, A.lgtw);
+        fft_tile<true>(lds, twl, lgN, lgnl);
     } else {
-        fft_tile<false>(lds, A.lgN, lgnl, A.tw, A.lgtw);
+        fft_tile<false>(lds, twl, lgN, lgnl);
         if (OP == kFftFwdSymInv) {
-            for (int e = (int)threadIdx.x; e < nl * N; e += kBlock) {
-                const int l = e & (nl - 1), i = e >> lgnl;
-                if (b0 + l < A.nb) lds[i * LS + l] = apply_sym<SYM>(A, i, a, b0 + l, lds[i * LS + l]);
+#pragma unroll
+            for (int k = 0; k < kLd; ++k) {
+                const int e = (int)threadIdx.x + k * kBlock;
+                if (e < total) {
+                    const int l = e & (nl - 1), i = e >> lgnl;
+                    if (b0 + l < A.nb) lds[i * LS + l] = apply_sym<SYM>(A, i, a, b0 + l, lds[i * LS + l]);
+                }
             }
             __syncthreads();
-            fft_tile<true>(lds, A.lgN, lgnl, A.tw, A.lgtw);
+            fft_tile<true>(lds, twl, lgN, lgnl);
         }
     }
     // store the first m_out points of every line
-    if (CONTIG) {
-        for (int l = 0; l < nl; ++l) {
-            if (a + l >= A.na) break;
-            const long long base = (long long)(a + l) * A.out_sa;
-            for (int i = (int)threadIdx.x; i < A.m_out; i += kBlock) store_out<OUT>(A, base + i, lds[i * LS + l]);
-        }
-    } else {
-        const long long base = (long long)a * A.out_sa + b0;
-        for (int e = (int)threadIdx.x; e < nl * A.m_out; e += kBlock) {
-            const int l = e & (nl - 1), i = e >> lgnl;
-            if (b0 + l < A.nb) store_out<OUT>(A, base + l + (long long)i * A.out_si, lds[i * LS + l]);
+#pragma unroll
+    for (int k = 0; k < kLd; ++k) {
+        const int e = (int)threadIdx.x + k * kBlock;
+        if (e < total) {
+            int l, i;
+            tile_coords<CONTIG>(e, lgN, lgnl, l, i);
+            if (i < A.m_out) {
+                if (CONTIG) {
+                    if (a + l < A.na) store_out<OUT>(A, (long long)(a + l) * A.out_sa + i, lds[i * LS + l]);
+                } else {
+                    if (b0 + l < A.nb)
+                        store_out<OUT>(A, (long long)a * A.out_sa + b0 + l + (long long)i * A.out_si, lds[i * LS + l]);
+                }
+            }
         }
     }
 }
@@ -312,7 +349,7 @@ __global__ void k_spec_tables(double* t0, double* t1, double* t2, int p0, int p1
 template <bool CONTIG, int IN, int OUT, int OP, int SYM>
 hipError_t run_pass(const FftPass& A, hipStream_t st) {
     const int nl = 1 << A.lgnl;
-    const unsigned lds = (unsigned)((1u << A.lgN) * (unsigned)(nl + 1) * sizeof(double2));
+    const unsigned lds = (unsigned)((1u << A.lgN) * (unsigned)(nl + 2) * sizeof(double2));
     const void* fn = (const void*)k_fft_pass<CONTIG, IN, OUT, OP, SYM>;
     static bool raised = false;
     if (!raised) {
