@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel directly (no graph replay)")
     ap.add_argument("--only", default="",
                     help="comma-separated legs to run alone, without the headline step (profiling): "
-                         "roof512, c1, c3, hoz, c4, spectral, density")
+                         "roof512, c1, c3, hoz, c4, spectral, density, ho")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -58,7 +58,7 @@ def parse():
 # HBM traffic of the finest-level smoother, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # recorded under profiles/; it stands only while the kernel sources hash to the recorded value.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rbgs_vec_f32_256.md")
-KERNEL_SOURCES = ("k_levels.hip", "k_multigrid.hip", "mg_internal.h", "fastdiv.h", "p2_bodies.h")
+KERNEL_SOURCES = ("k_levels.hip", "mg_internal.h", "fastdiv.h", "p2_bodies.h")   # the smoother's sources
 
 
 def kernel_source_hash():
@@ -606,6 +606,8 @@ def main():
                 line["spectral"] = time_spectral(mg, torch, ft)
             elif leg == "density":
                 line["density_c3"] = time_density(mg, torch)
+            elif leg == "ho":
+                line["highorder"] = time_highorder(mg, torch, ft, h, a.tol)
             else:
                 raise SystemExit("unknown leg " + leg)
         if a.pmc_calib:

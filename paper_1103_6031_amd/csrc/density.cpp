@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "mg_internal.h"
+#include "spec_internal.h"
 #include "mgic.h"
 
 namespace mgic {

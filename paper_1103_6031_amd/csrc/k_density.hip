@@ -6,7 +6,7 @@
 // of P points is the displacement j (j < P/2) or j - P cells.  A patch's padded domain D' has 2n
 // cells per axis and holds the patch itself at [n/2, 3n/2).
 
-#include "mg_internal.h"
+#include "spec_internal.h"
 
 namespace mgic {
 

@@ -17,7 +17,7 @@
 // The x pass can run forward, multiply every element by a multiplier of its (kx, ky, kz), and
 // run the inverse in the same launch: the spectrum of the x pass never goes to memory.
 
-#include "mg_internal.h"
+#include "spec_internal.h"
 
 namespace mgic {
 

@@ -18,7 +18,7 @@
 #include <cmath>
 #include <string>
 
-#include "mg_internal.h"
+#include "spec_internal.h"
 #include "mgic.h"
 
 namespace mgic {
