@@ -421,6 +421,18 @@ def time_c3(mg, torch, reps=3):
                          rel_res=[s1["rel_res"], s2["rel_res"]],
                          value=round((s1["cell_updates"] + s2["cell_updates"]) / dt / 1e6, 1),
                          unit="Mcell-updates/s")
+        if prec == "mixed":
+            # the inner-cycle tuner on this shape (outside the timed region), then the step again
+            best, ms = mg.mg_tune_inner(H, f, opts=o, workspace=ws)
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s1, s2 = step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            res["mixed_tuned"] = dict(inner=best, solve_ms_per_count=[round(m, 3) for m in ms],
+                                      ms_per_step=round(dt * 1e3, 3), cycles=[s1["cycles"], s2["cycles"]])
     return res
 
 

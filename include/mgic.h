@@ -344,6 +344,19 @@ int mg_batch_tune_candidates(void);
 int mg_batch_force_shape(int index);
 int mg_tune_cache(const char* path);
 
+/* Autotuning of the mixed-precision solo solve's FP32 inner cycles per FP64 correction: solves
+ * hier (f -> u, zero start) with every count 0..4 (0: the contraction rule of the default), each
+ * twice after a graph-capturing first call, timed with events on stream; *best gets the fastest
+ * count and ms[k] (5 entries, or NULL) each count's time in ms (-1 where the solve failed).  The
+ * choice is recorded for the problem's shape (level sizes and offsets, nu1, nu2 and the decade of
+ * tol) and persists through mg_tune_cache; from then on every mixed mg_solve_level /
+ * mg_solve_hierarchy / mg_solve_hierarchy_noalloc of that shape with opts->inner = 0 uses it.
+ * u is left holding the last candidate's solution.  MG_EINVAL for an FP64 opts or a bad
+ * hierarchy; the last solve error if no count converged.  Synchronises the stream. */
+int mg_tune_inner(const mg_hier* hier, const double* const* f, double* const* u,
+                  const mg_opts* opts, int* best, double* ms, void* workspace,
+                  size_t workspace_bytes, void* stream);
+
 /* ----------------------------------------------------------------------------------------------
  * Single steps, exposed for kernel-level parity checks
  * -------------------------------------------------------------------------------------------- */

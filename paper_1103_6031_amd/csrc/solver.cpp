@@ -599,6 +599,9 @@ static std::string user_key(const mg_hier* H, const double* const* f, double* co
     return k;
 }
 
+// the tuned inner-cycle count for this problem shape (0: none recorded; defined with the tuner)
+static int tuned_inner(const mg_hier* H, const mg_opts* o);
+
 static int solve(const mg_hier* H, const double* const* f, double* const* u, const mg_opts* o, mg_stats* stats,
                  void* ws, size_t ws_bytes, hipStream_t st) {
     if (!o) return fail(MG_EINVAL, "options are NULL");
@@ -609,6 +612,15 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     if (int v = validate_hier(H)) return v;
     for (int p = 0; p < H->nlev; ++p)
         if (!u[p] || !f[p]) return fail(MG_EINVAL, "level pointer is NULL");
+    mg_opts tuned;
+    if (o->prec == MG_MIXED && o->inner == 0) {   // a count the tuner recorded for this shape
+        const int k = tuned_inner(H, o);
+        if (k > 0) {
+            tuned = *o;
+            tuned.inner = k;
+            o = &tuned;
+        }
+    }
     Plan P;
     Carver size_cv(nullptr);
     int rc = build_plan(H, o, size_cv, u, P);
@@ -1187,11 +1199,41 @@ static const SmoothShape kShapes[] = {{256, 1}, {256, 2}, {256, 4}, {128, 2}, {1
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 static int g_force_shape = -1;        // >= 0: every depth takes kShapes[g_force_shape], no timing
 static std::string g_tune_path;       // JSON file the tuned shapes persist in ("" = none)
+// tuned FP32 inner-cycle counts of mixed-precision solo solves, per problem shape (0: the rule)
+static std::map<std::string, int> g_inner;
 
-// The tuning cache file: {"format": "mgic-batch-smoother-tuning-1", "entries": [{"key": "...",
-// "shapes": [[block, cells per thread], ...]}, ...]}, one entry per batch shape and precision.
-static bool parse_tune_file(const std::string& text, std::map<std::string, std::vector<SmoothShape>>& out) {
-    if (text.find("\"mgic-batch-smoother-tuning-1\"") == std::string::npos) return false;
+// shape of a solo solve for the inner-cycle table: the levels (sizes, offsets), the sweeps and the
+// decade of the tolerance; spacings do not change the iteration's contraction
+static std::string inner_key(const mg_hier* H, const mg_opts* o) {
+    std::string k = "inner:" + std::to_string(o->nu1) + "," + std::to_string(o->nu2) + ":" +
+                    std::to_string((int)std::lround(std::log10(o->tol > 0 ? o->tol : 1.0))) + ":";
+    for (int p = 0; p < H->nlev; ++p) {
+        const mg_level& l = H->lev[p];
+        k += std::to_string(l.n[0]) + "," + std::to_string(l.n[1]) + "," + std::to_string(l.n[2]);
+        if (p) k += "@" + std::to_string(l.off[0]) + "," + std::to_string(l.off[1]) + "," + std::to_string(l.off[2]);
+        k += ";";
+    }
+    return k;
+}
+
+static thread_local bool g_tuning_inner = false;   // set while the tuner times the candidates
+
+static int tuned_inner(const mg_hier* H, const mg_opts* o) {
+    if (g_tuning_inner) return 0;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_inner.find(inner_key(H, o));
+    return it == g_inner.end() ? 0 : it->second;
+}
+
+// The tuning cache file: {"format": "mgic-tuning-2", "entries": [{"key": "...", "shapes":
+// [[block, cells per thread], ...]}, ..., {"key": "inner:...", "inner": k}, ...]}: the batched
+// smoother's shapes per batch shape and precision, and the inner-cycle count per solo problem shape.
+// Files of the earlier format "mgic-batch-smoother-tuning-1" (shapes only) are read as well.
+static bool parse_tune_file(const std::string& text, std::map<std::string, std::vector<SmoothShape>>& out,
+                            std::map<std::string, int>& inner) {
+    if (text.find("\"mgic-batch-smoother-tuning-1\"") == std::string::npos &&
+        text.find("\"mgic-tuning-2\"") == std::string::npos)
+        return false;
     size_t pos = 0;
     while ((pos = text.find("\"key\"", pos)) != std::string::npos) {
         size_t q0 = text.find('"', text.find(':', pos) + 1);
@@ -1199,8 +1241,17 @@ static bool parse_tune_file(const std::string& text, std::map<std::string, std::
         size_t q1 = text.find('"', q0 + 1);
         if (q1 == std::string::npos) return false;
         const std::string key = text.substr(q0 + 1, q1 - q0 - 1);
+        const size_t next = text.find("\"key\"", q1);
+        const size_t ai = text.find("\"inner\"", q1);
+        if (ai != std::string::npos && ai < next) {
+            int k = -1;
+            if (std::sscanf(text.c_str() + text.find(':', ai) + 1, " %d", &k) != 1 || k < 0 || k > 16) return false;
+            inner[key] = k;
+            pos = ai;
+            continue;
+        }
         size_t a = text.find("\"shapes\"", q1);
-        if (a == std::string::npos) return false;
+        if (a == std::string::npos || a > next) return false;
         a = text.find('[', a);
         const size_t end = text.find("]]", a);
         if (a == std::string::npos || end == std::string::npos) return false;
@@ -1227,7 +1278,7 @@ static bool parse_tune_file(const std::string& text, std::map<std::string, std::
 
 static void save_tune_file() {   // under g_tune_mu
     if (g_tune_path.empty()) return;
-    std::string t = "{\"format\": \"mgic-batch-smoother-tuning-1\", \"entries\": [";
+    std::string t = "{\"format\": \"mgic-tuning-2\", \"entries\": [";
     bool first = true;
     for (auto& kv : g_tune) {
         t += first ? "\n" : ",\n";
@@ -1236,6 +1287,11 @@ static void save_tune_file() {   // under g_tune_mu
         for (size_t i = 0; i < kv.second.size(); ++i)
             t += (i ? ", [" : "[") + std::to_string(kv.second[i].block) + ", " + std::to_string(kv.second[i].V) + "]";
         t += "]}";
+    }
+    for (auto& kv : g_inner) {
+        t += first ? "\n" : ",\n";
+        first = false;
+        t += "  {\"key\": \"" + kv.first + "\", \"inner\": " + std::to_string(kv.second) + "}";
     }
     t += "\n]}\n";
     const std::string tmp = g_tune_path + ".tmp";
@@ -2305,18 +2361,74 @@ int mg_tune_cache(const char* path) {
         return 0;
     }
     std::map<std::string, std::vector<SmoothShape>> loaded;
+    std::map<std::string, int> loaded_inner;
     if (FILE* fh = std::fopen(path, "r")) {
         std::string text;
         char buf[4096];
         size_t k;
         while ((k = std::fread(buf, 1, sizeof(buf), fh)) > 0) text.append(buf, k);
         std::fclose(fh);
-        if (!parse_tune_file(text, loaded)) return fail(MG_EINVAL, std::string("not a tuning cache file: ") + path);
+        if (!parse_tune_file(text, loaded, loaded_inner))
+            return fail(MG_EINVAL, std::string("not a tuning cache file: ") + path);
     }
     for (auto& kv : loaded) g_tune[kv.first] = kv.second;
+    for (auto& kv : loaded_inner) g_inner[kv.first] = kv.second;
     g_tune_path = path;
-    if (!g_tune.empty()) save_tune_file();   // the file holds every shape known to the process
-    return (int)loaded.size();
+    if (!g_tune.empty() || !g_inner.empty()) save_tune_file();   // the file holds every entry the process knows
+    return (int)(loaded.size() + loaded_inner.size());
+}
+
+int mg_tune_inner(const mg_hier* hier, const double* const* f, double* const* u, const mg_opts* opts, int* best,
+                  double* ms, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!opts || !best) return fail(MG_EINVAL, "NULL argument");
+    if (opts->prec != MG_MIXED) return fail(MG_EINVAL, "inner cycles are tuned for mixed-precision solves");
+    if (int v = validate_hier(hier)) return v;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MG_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return fail(MG_EHIP, "hipEventCreate failed");
+    }
+    int best_k = -1, last_rc = MG_OK;
+    double best_ms = 0.0;
+    std::string last_err;
+    g_tuning_inner = true;
+    for (int k = 0; k <= kInnerMax; ++k) {   // 0: the contraction rule
+        mg_opts o = *opts;
+        o.inner = k;
+        o.flags &= ~MG_USE_INITIAL_GUESS;
+        double t = -1.0;
+        int rc = MG_OK;
+        for (int rep = 0; rep < 3 && rc == MG_OK; ++rep) {   // the first call captures the graphs
+            mg_stats sdummy;
+            (void)hipEventRecord(e0, st);
+            rc = solve(hier, f, u, &o, &sdummy, workspace, workspace_bytes, st);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float m = 0.f;
+            if (rc == MG_OK && rep && hipEventElapsedTime(&m, e0, e1) == hipSuccess && (t < 0 || m < t)) t = m;
+        }
+        if (ms) ms[k] = rc == MG_OK ? t : -1.0;
+        if (rc == MG_OK && t >= 0 && (best_k < 0 || t < best_ms)) {
+            best_k = k;
+            best_ms = t;
+        } else if (rc != MG_OK) {
+            last_rc = rc;
+            last_err = g_err;
+        }
+    }
+    g_tuning_inner = false;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipGetLastError();
+    if (best_k < 0) return fail(last_rc ? last_rc : MG_EHIP, "no inner-cycle count solved the problem: " + last_err);
+    *best = best_k;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_inner[inner_key(hier, opts)] = best_k;
+    save_tune_file();
+    return MG_OK;
 }
 
 int mg_kprof_enable(int period) {

@@ -101,6 +101,8 @@ _sig = {
     "mg_batch_tune_candidates": (ctypes.c_int, []),
     "mg_batch_force_shape": (ctypes.c_int, [ctypes.c_int]),
     "mg_tune_cache": (ctypes.c_int, [ctypes.c_char_p]),
+    "mg_tune_inner": (ctypes.c_int, [ctypes.POINTER(mg_hier), _PP, _PP, ctypes.POINTER(mg_opts),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _P, _sz, _P]),
     "mg_kprof_enable": (ctypes.c_int, [ctypes.c_int]),
     "mg_kprof_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
                                      ctypes.POINTER(ctypes.c_double)]),
@@ -554,6 +556,23 @@ def mg_tune_cache(path) -> int:
     if rc < 0:
         _check(rc)
     return rc
+
+
+def mg_tune_inner(hier: Hier, f, opts=None, u=None, workspace=None, stream=None):
+    """Time the mixed solve of hier with 0..4 FP32 inner cycles per correction and record the
+    fastest for this problem shape.  Returns (best, [ms per count])."""
+    o = opts or make_opts(prec="mixed")
+    if u is None:
+        u = [torch.empty_like(x) for x in f]
+    H = hier.c_struct()
+    ws = _ws(workspace, mg_workspace_bytes(hier, o))
+    fp, _fa = _ptr_array([_dev(x, "f") for x in f])
+    up, _ua = _ptr_array([_dev(x, "u") for x in u])
+    best = ctypes.c_int(-1)
+    ms = (ctypes.c_double * 5)()
+    _check(_lib.mg_tune_inner(ctypes.byref(H), fp, up, ctypes.byref(o), ctypes.byref(best), ms,
+                              ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+    return best.value, list(ms)
 
 
 def mg_smooth_level(f, u, h, half_sweeps, prec="fp64", workspace=None, stream=None):

@@ -202,6 +202,29 @@ def test_tuning_cache_file_round_trip_and_validation(tmp_path):
         mgic.mg_tune_cache(str(other))
     assert mgic.mg_tune_cache(str(tmp_path / "absent.json")) == 0   # created on the next tuning
     assert mgic.mg_tune_cache(None) == 0
+    # the current format carries inner-cycle counts of solo solves beside the batch shapes, and a
+    # loaded file is rewritten with every entry the process knows
+    v2 = tmp_path / "tune2.json"
+    v2.write_text('{"format": "mgic-tuning-2", "entries": [\n'
+                  '  {"key": "0:2:64,", "shapes": [[256, 4]]},\n'
+                  '  {"key": "inner:2,2:-10:64,64,64;", "inner": 3}\n]}\n')
+    assert mgic.mg_tune_cache(str(v2)) == 2
+    text = v2.read_text()
+    assert '"mgic-tuning-2"' in text and '"inner": 3' in text and "[256, 4]" in text
+    bad2 = tmp_path / "bad2.json"
+    bad2.write_text('{"format": "mgic-tuning-2", "entries": [{"key": "inner:x", "inner": 99}]}')
+    with pytest.raises(mgic.MGError):
+        mgic.mg_tune_cache(str(bad2))
+    assert mgic.mg_tune_cache(None) == 0
+    # the tuner rejects an FP64 problem before any device work
+    H = mgic.Hier(16, 1.0).c_struct()
+    o = mgic.make_opts(prec="fp64")
+    best = ctypes.c_int(-1)
+    fake = ctypes.c_void_p(256)
+    ptrs = (ctypes.c_void_p * 1)(256)
+    pp = ctypes.cast(ptrs, mgic._PP)
+    assert mgic._lib.mg_tune_inner(ctypes.byref(H), pp, pp, ctypes.byref(o), ctypes.byref(best), None, fake, 1 << 30,
+                                   None) == mgic.MG_EINVAL
 
 
 def test_spectral_calls_validate_before_any_device_work():

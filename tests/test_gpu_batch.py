@@ -196,7 +196,7 @@ def test_every_tuning_candidate_gives_the_same_bits(mg, prec, tmp_path):
         for (us, ss), u in zip(solo, ub):
             assert np.array_equal(to_host(u), to_host(us))
         doc = json.loads(cache.read_text())
-        assert doc["format"] == "mgic-batch-smoother-tuning-1" and len(doc["entries"]) >= 1
+        assert doc["format"] == "mgic-tuning-2" and len(doc["entries"]) >= 1
         assert mg.mg_tune_cache(str(cache)) == len(doc["entries"])   # loads back
     finally:
         mg.mg_tune_cache(None)
