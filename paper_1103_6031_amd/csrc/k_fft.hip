@@ -5,9 +5,10 @@
 // A 3-D transform is three launches of batched 1-D transforms, one per axis.  A workgroup loads a
 // tile of nl lines into LDS, zero-extending lines that are stored shorter than the transform (the
 // zero padding of isolated boundaries is never materialised), runs a Stockham autosort FFT
-// (radix 4, plus one radix-2 stage when log2 N is odd; Govindaraju et al. 2008, "High performance
-// discrete Fourier transforms on graphics processors") with an LDS exchange between stages, and
-// stores the first m_out points of each line.  Lines along z are contiguous in memory: the tile
+// (radix 8, with one radix-2 or radix-4 stage first when log2 N is not a multiple of 3;
+// Govindaraju et al. 2008, "High performance discrete Fourier transforms on graphics
+// processors") with an LDS exchange between stages, and stores the first m_out points of each
+// line.  Lines along z are contiguous in memory: the tile
 // loads each line as one run.  Along y and x a tile holds nl lines that are consecutive in z, so
 // every global access is a run of nl consecutive elements.  In LDS the tile is interleaved, point
 // i of line l at i * (nl + 1) + l: lane-consecutive lines are address-consecutive during the
@@ -29,22 +30,49 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-// radix-R DFT in registers; forward uses e^{-2 pi i rk/R}, inverse e^{+2 pi i rk/R}
+// radix-4 DFT in registers; forward uses e^{-2 pi i rk/4}, inverse e^{+2 pi i rk/4}
+template <bool INV>
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+    const double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    const double2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+    // -i * d13 = (d13.y, -d13.x)
+    const double2 mi = INV ? make_double2(-d13.y, d13.x) : make_double2(d13.y, -d13.x);
+    a0 = cadd(s02, s13);
+    a2 = csub(s02, s13);
+    a1 = cadd(d02, mi);
+    a3 = csub(d02, mi);
+}
+
+// radix-R DFT in registers (R = 2, 4, 8); the radix-8 one is two radix-4 DFTs of the even and odd
+// points combined with the eighth roots of unity
 template <int R, bool INV>
 __device__ __forceinline__ void dft(double2* v) {
     if (R == 2) {
         const double2 a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
+    } else if (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
     } else {
-        const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-        const double2 s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
-        // -i * d13 = (d13.y, -d13.x)
-        const double2 mi = INV ? make_double2(-d13.y, d13.x) : make_double2(d13.y, -d13.x);
-        v[0] = cadd(s02, s13);
-        v[2] = csub(s02, s13);
-        v[1] = cadd(d02, mi);
-        v[3] = csub(d02, mi);
+        double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<INV>(e0, e1, e2, e3);
+        dft4<INV>(o0, o1, o2, o3);
+        const double r2 = 0.70710678118654752440;
+        // w^k o_k, w = e^{-i pi / 4} (forward) or e^{+i pi / 4} (inverse)
+        const double2 t1 = INV ? make_double2((o1.x - o1.y) * r2, (o1.x + o1.y) * r2)
+                               : make_double2((o1.x + o1.y) * r2, (o1.y - o1.x) * r2);
+        const double2 t2 = INV ? make_double2(-o2.y, o2.x) : make_double2(o2.y, -o2.x);
+        const double2 t3 = INV ? make_double2((-o3.x - o3.y) * r2, (o3.x - o3.y) * r2)
+                               : make_double2((o3.y - o3.x) * r2, (-o3.x - o3.y) * r2);
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, t1);
+        v[5] = csub(e1, t1);
+        v[2] = cadd(e2, t2);
+        v[6] = csub(e2, t2);
+        v[3] = cadd(e3, t3);
+        v[7] = csub(e3, t3);
     }
 }
 
@@ -54,7 +82,7 @@ __device__ __forceinline__ void dft(double2* v) {
 template <int R, bool INV>
 __device__ __forceinline__ void fft_stage(double2* lds, const double2* twl, int lgN, int lgnl, int lgNs) {
     constexpr int kIt = kFftTile / (R * kBlock);
-    constexpr int lgR = R == 4 ? 2 : 1;
+    constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
     const int nl = 1 << lgnl, LS = nl + 1;
     const int P = 1 << (lgN - lgR);
     const int items = nl * P;
@@ -97,11 +125,15 @@ __device__ __forceinline__ void fft_stage(double2* lds, const double2* twl, int 
 template <bool INV>
 __device__ __forceinline__ void fft_tile(double2* lds, const double2* twl, int lgN, int lgnl) {
     int lgNs = 0;
-    if (lgN & 1) {
+    const int rem = lgN % 3;
+    if (rem == 1) {
         fft_stage<2, INV>(lds, twl, lgN, lgnl, 0);
         lgNs = 1;
+    } else if (rem == 2) {
+        fft_stage<4, INV>(lds, twl, lgN, lgnl, 0);
+        lgNs = 2;
     }
-    for (; lgNs < lgN; lgNs += 2) fft_stage<4, INV>(lds, twl, lgN, lgnl, lgNs);
+    for (; lgNs < lgN; lgNs += 3) fft_stage<8, INV>(lds, twl, lgN, lgnl, lgNs);
 }
 
 template <int IN>
