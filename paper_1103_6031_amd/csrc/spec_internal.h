@@ -8,9 +8,9 @@
 namespace mgic {
 
 // ---- three-dimensional FFTs (k_fft.hip) -------------------------------------------------------
-constexpr int kFftTile = 4096;                       // complex points per workgroup tile
+constexpr int kFftTile = 2048;                       // complex points per workgroup tile
 constexpr int kFftMaxLgN = 10;                       // transforms of length 2 .. 1024
-constexpr unsigned kFftMaxLds = 1024u * 6u * 16u;    // N (nl + 2) 16 B at N = 1024, nl = 4
+constexpr unsigned kFftMaxLds = 1024u * 4u * 16u;    // N (nl + 2) 16 B, largest at N = 1024, nl = 2
 enum { kFftInCplx = 0, kFftInRe = 1, kFftInRePair = 2 };
 enum { kFftOutCplx = 0, kFftOutRe = 1, kFftOutRePairStore = 2, kFftOutRePairAdd = 3 };
 enum { kFftForward = 0, kFftInverse = 1, kFftFwdSymInv = 2 };
