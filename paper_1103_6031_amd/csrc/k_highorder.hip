@@ -97,9 +97,11 @@ __global__ __launch_bounds__(kBlock) void k_ho_half(const T* __restrict__ in, T*
 // of one x plane and stages them with R halo rows on each side (all z, wrapped in y) in LDS; the
 // 2R x-neighbours and f come from memory.  About 2R + 3 global loads per update instead of
 // 6R + 2; the sums are formed in the order of ho_off, so the bits are the same.  Blocks of one
-// plane are consecutive; the blocks of x-neighbouring planes are n / kHoTy apart, a multiple of 8,
-// so they share an XCD (and its L2).  For 16 <= n <= 256.
-constexpr int kHoTy = 16;
+// plane are consecutive; the blocks of x-neighbouring planes are n / kHoTy apart, a multiple of 8
+// from n = 64 on, so they share an XCD (and its L2).  For 16 <= n <= 256.  Eight rows per block
+// (29 KB of LDS at 256^3 FP64, order 6) measured best: 16 rows 116 us, 8 rows 109 us, 4 rows
+// 111 us at 256^3 (order 6, FP64): the halo rows cost less than the blocks per CU gained.
+constexpr int kHoTy = 8;
 template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_ho_half_lds(const T* __restrict__ in, T* __restrict__ out,
                                                         const T* __restrict__ f, int lg, T h2, int colour) {
