@@ -239,7 +239,12 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
     n = ft.shape[0]
     res = dict(workload="periodic %d^3 BBKS, V(2,2) with the order-4 / order-6 Laplacian, tol %g; FP64, and mixed "
                         "(FP32 inner cycles inside FP64 defect correction)" % (n, tol))
+    fz = ft - ft.mean()
+    wsp = mg.Workspace(mg.spec_workspace_bytes(ft.shape))
     for order in (4, 6):
+        # the exact discrete solution of this order (eigenvalue division by the FFT), the fixed
+        # point both solves converge to
+        exact = mg.spec_poisson(fz, h, order, workspace=wsp)
         o = _opts(mg, tol=tol, max_cycles=40)
         ws = mg.Workspace(mg.mg_ho_workspace_bytes(n, order))
         u = torch.empty_like(ft)
@@ -263,6 +268,7 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
         u64 = u.clone()
         us = kms * 1e3 / max(kn, 1)
         res["order%d" % order] = dict(ms_per_solve=round(ms, 3), cycles=st["cycles"], rel_res=st["rel_res"],
+                                      rel_rms_vs_exact=_rel_zero_mean(torch, u64, exact),
                                       value=round(st["cell_updates"] / (ms * 1e-3) / 1e6, 1),
                                       unit="Mcell-updates/s", half_sweep_avg_us=round(us, 2),
                                       half_sweep_launches=kn,
@@ -282,8 +288,16 @@ def time_highorder(mg, torch, ft, h, tol, reps=3):
         dev = float(torch.sqrt(torch.mean((u - u64) ** 2)) / torch.sqrt(torch.mean(u64 ** 2)))
         res["order%d" % order]["mixed"] = dict(ms_per_solve=round(msm, 3), cycles=sm["cycles"], rel_res=sm["rel_res"],
                                                value=round(sm["cell_updates"] / (msm * 1e-3) / 1e6, 1),
-                                               rel_rms_vs_fp64=dev)
+                                               rel_rms_vs_fp64=dev, rel_rms_vs_exact=_rel_zero_mean(torch, u, exact))
+        del exact
     return res
+
+
+def _rel_zero_mean(torch, x, exact):
+    """Relative RMS of x (its mean removed: the periodic solution is fixed up to a constant)
+    against the zero-mean exact solution."""
+    d = (x - x.mean()) - exact
+    return float(torch.sqrt(torch.mean(d * d)) / torch.sqrt(torch.mean(exact * exact)))
 
 
 def time_highorder_zoom(mg, torch, reps=2):
@@ -639,6 +653,17 @@ def main():
                tau=rel(out_m[2], out_d[2]), phi2=rel(out_m[3], out_d[3]),
                psi2=max(rel(out_m[4][c], out_d[4][c]) for c in range(3)))
 
+    # each path's two solves against the exact discrete solution of the same right-hand side (the
+    # 7-point symbol divided out by the FFT): phi1 from the density, phi2 from that path's tau
+    wsp = mg.Workspace(mg.spec_workspace_bytes(ft.shape))
+    e1 = mg.spec_poisson(ft - ft.mean(), h, 2, workspace=wsp)
+    vs_exact = {}
+    for name, out in (("mixed", out_m), ("fp64", out_d)):
+        e2 = mg.spec_poisson(out[2] - out[2].mean(), h, 2, workspace=wsp)
+        vs_exact[name] = dict(phi1=_rel_zero_mean(torch, out[0], e1), phi2=_rel_zero_mean(torch, out[3], e2))
+        del e2
+    del e1, wsp
+
     k = head["kernel"]
     roof = None
     if k["achieved_gbs"]:
@@ -658,7 +683,7 @@ def main():
                 roofline=roof,
                 cycles=dict(zip(("solve1", "solve2"), head["cycles"])),
                 rel_res=head["rel_res"],
-                mixed_vs_fp64_rel_rms=acc)
+                mixed_vs_fp64_rel_rms=acc, rel_rms_vs_exact_solve=vs_exact)
     line[other + "_path"] = dict(value=round(side["value"], 1), ms_per_step=round(side["ms_per_step"], 3),
                                  cycles=side["cycles"],
                                  smoother_gbs=round(side["kernel"]["achieved_gbs"] or 0.0, 1),

@@ -295,6 +295,15 @@ size_t spec_workspace_bytes(const int n[3], int isolated);
 int spec_deconvolve(const int n[3], int kind, int isolated, const double* f, double* out,
                     void* workspace, size_t workspace_bytes, void* stream);
 
+/* The exact discrete periodic Poisson solve by eigenvalue division (Section 3.2 with Table 1's
+ * symbols): u~ = f~ / lambda(k), lambda the symbol of the order-2, 4 or 6 Laplacian summed over
+ * the axes, the k = 0 mode zero (the zero-mean solution of L u = f - mean f).  This is the fixed
+ * point the periodic multigrid solves converge to; the bench measures their error against it.
+ * Periodic only (n[a] powers of two, 2..1024); workspace spec_workspace_bytes(n, 0); u may alias
+ * f.  Asynchronous on stream. */
+int spec_poisson(const int n[3], double h, int order, const double* f, double* u,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
 /* Hybrid Poisson solver (Section 3.5.2): ADDS to out3[c] (c = x, y, z) the correction that turns
  * the finite-difference displacement scale * G_c phi, L phi = f (L the Table 1 Laplacian of
  * lap_order 2, 4 or 6, G the gradient of grad_order 4 or 6), into the k-space exact

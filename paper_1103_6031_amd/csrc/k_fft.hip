@@ -174,6 +174,13 @@ __device__ __forceinline__ double2 apply_sym(const FftPass& A, int i, int a, int
         const double m = A.tab[(long long)i * A.tab_si + (long long)a * A.tab_sa + b] * c;
         return make_double2(v.x * m, v.y * m);
     }
+    if (SYM == kSymInvLap) {
+        // 1 / lambda(k), lambda = sum_axes of the per-axis Laplacian symbol; the k = 0 mode -> 0
+        const double lam = (A.tab_x[i] + A.tab_y[a]) + A.tab_z[b];
+        if (i == 0 && a == 0 && b == 0) return make_double2(0.0, 0.0);
+        const double m = c / lam;
+        return make_double2(v.x * m, v.y * m);
+    }
     if (SYM == kSymReplace) {
         // modes below the coarse grid's Nyquist on every axis take 8 C(m) prod_a e^{-i pi m_a / P_a}
         // (per-axis phase tables hold cos, sin pairs); the rest keep the fine spectrum
@@ -353,6 +360,16 @@ __global__ void k_spec_tables(double* t0, double* t1, double* t2, int p0, int p1
         tab[t] = 1.0 / cospi(0.25 * q);
         return;
     }
+    if (kind == kSpecPoisson) {   // the 1-D Laplacian symbol of the order, in grid units
+        double s1, c1, s2, c2, s3, c3;
+        sincospi(q, &s1, &c1);
+        sincospi(2.0 * q, &s2, &c2);
+        sincospi(3.0 * q, &s3, &c3);
+        if (lap_order == 2) tab[t] = -2.0 * (1.0 - c1);
+        else if (lap_order == 4) tab[t] = -(c2 - 16.0 * c1 + 15.0) / 6.0;
+        else tab[t] = -(-2.0 * c3 + 27.0 * c2 - 270.0 * c1 + 245.0) / 90.0;
+        return;
+    }
     if (kind == kSpecReplace) {   // e^{-i pi m / P}: the fine centres sit a quarter coarse cell off
         double s, c;
         sincospi((double)m / (double)P, &s, &c);
@@ -446,6 +463,7 @@ hipError_t launch_fft_pass(const FftPass& A, bool contig, int in, int out, int o
             case kSymHybridXY: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymHybridXY>(A, st);
             case kSymHybridZ: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymHybridZ>(A, st);
             case kSymReplace: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymReplace>(A, st);
+            case kSymInvLap: return run_pass<false, kFftInCplx, kFftOutCplx, kFftFwdSymInv, kSymInvLap>(A, st);
             default: return hipErrorInvalidValue;
         }
     }

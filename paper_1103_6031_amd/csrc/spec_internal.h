@@ -14,8 +14,8 @@ constexpr unsigned kFftMaxLds = 1024u * 4u * 16u;    // N (nl + 2) 16 B, largest
 enum { kFftInCplx = 0, kFftInRe = 1, kFftInRePair = 2 };
 enum { kFftOutCplx = 0, kFftOutRe = 1, kFftOutRePairStore = 2, kFftOutRePairAdd = 3 };
 enum { kFftForward = 0, kFftInverse = 1, kFftFwdSymInv = 2 };
-enum { kSymSeparable = 1, kSymTable = 2, kSymHybridXY = 3, kSymHybridZ = 4, kSymReplace = 5 };
-enum { kSpecFv = 1, kSpecSg = 2, kSpecHybrid = 3, kSpecReplace = 4 };
+enum { kSymSeparable = 1, kSymTable = 2, kSymHybridXY = 3, kSymHybridZ = 4, kSymReplace = 5, kSymInvLap = 6 };
+enum { kSpecFv = 1, kSpecSg = 2, kSpecHybrid = 3, kSpecReplace = 4, kSpecPoisson = 5 };
 // one pass of batched 1-D transforms: line (a, b) holds point i at a*sa + b + i*si (strided
 // passes) or a*sa + i (contiguous passes); the input line has m_in points (the rest is zero),
 // the first m_out points of the output line are stored

@@ -243,6 +243,25 @@ int spec_deconvolve(const int n[3], int kind, int isolated, const double* f, dou
     return MG_OK;
 }
 
+int spec_poisson(const int n[3], double h, int order, const double* f, double* u, void* ws, size_t ws_bytes,
+                 void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (order != 2 && order != 4 && order != 6) return report_error(MG_EINVAL, "order must be 2, 4 or 6");
+    if (!(h > 0) || !std::isfinite(h)) return report_error(MG_EINVAL, "h must be positive and finite");
+    if (!f || !u) return report_error(MG_EINVAL, "f or u is NULL");
+    SpecPlan S;
+    int rc = spec_plan(n, 0, nullptr, S);
+    if (rc) return rc;
+    if ((rc = check_ws(S, ws, ws_bytes))) return rc;
+    spec_plan(n, 0, ws, S);
+    const SpecGrid& G = S.G;
+    SP_HIP(spec_grid_prepare(G, kSpecPoisson, order, 4, st));
+    SP_HIP(spec_forward_zy(G, f, nullptr, st));
+    SP_HIP(spec_x_pass(G, kFftFwdSymInv, 0, kSymInvLap, h * h, nullptr, nullptr, nullptr, nullptr, st));
+    SP_HIP(spec_inverse_yz(G, u, nullptr, false, st));
+    return MG_OK;
+}
+
 int lpt_hybrid_correction(const int n[3], double h, int isolated, int lap_order, int grad_order, double scale,
                           const double* f, double* const* out3, void* ws, size_t ws_bytes, void* stream) {
     hipStream_t st = (hipStream_t)stream;

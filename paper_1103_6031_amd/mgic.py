@@ -87,6 +87,8 @@ _sig = {
     "spec_workspace_bytes": (_sz, [ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "spec_deconvolve": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, _P, _P, _P, _sz,
                                        _P]),
+    "spec_poisson": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int, _P, _P, _P, _sz,
+                                    _P]),
     "lpt_hybrid_correction": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, _PP, _P, _sz, _P]),
     "ic_density_workspace_bytes": (_sz, [ctypes.POINTER(mg_hier)]),
@@ -472,6 +474,16 @@ def spec_deconvolve(f, kind, isolated=False, out=None, workspace=None, stream=No
     _check(_lib.spec_deconvolve(_shape3(f.shape), int(kind), 1 if isolated else 0, _dev(f, "f"), _dev(out, "out"),
                                 ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
     return out
+
+
+def spec_poisson(f, h, order=2, u=None, workspace=None, stream=None):
+    """Exact discrete periodic solve of L u = f - mean(f) with the Table 1 Laplacian of this order."""
+    if u is None:
+        u = torch.empty_like(f)
+    ws = _ws(workspace, spec_workspace_bytes(f.shape))
+    _check(_lib.spec_poisson(_shape3(f.shape), float(h), int(order), _dev(f, "f"), _dev(u, "u"),
+                             ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+    return u
 
 
 def lpt_hybrid_correction(f, h, out, isolated=False, lap_order=2, grad_order=4, scale=1.0, workspace=None,

@@ -248,6 +248,11 @@ def test_spectral_calls_validate_before_any_device_work():
         assert mgic._lib.lpt_hybrid_correction(n, h, 0, lap, grad, 1.0, fake, op, fake, 1 << 30,
                                                None) == mgic.MG_EINVAL
     assert mgic._lib.lpt_hybrid_correction(n, 1.0, 0, 2, 4, 1.0, None, op, fake, 1 << 30, None) == mgic.MG_EINVAL
+    for order, h in ((3, 1.0), (2, 0.0), (4, float("inf"))):
+        assert mgic._lib.spec_poisson(n, h, order, fake, fake, fake, 1 << 30, None) == mgic.MG_EINVAL
+    assert mgic._lib.spec_poisson(n, 1.0, 2, fake, None, fake, 1 << 30, None) == mgic.MG_EINVAL
+    assert mgic._lib.spec_poisson((ctypes.c_int * 3)(12, 16, 16), 1.0, 2, fake, fake, fake, 1 << 30,
+                                  None) == mgic.MG_EINVAL
 
 
 def test_density_validates_before_any_device_work():

@@ -103,3 +103,15 @@ def test_periodic_hybrid_solve_is_the_fft_solve():
     want = spectral.exact_displacement(f, h, scale)
     for c in range(3):
         _close(to_host(psi[c]), want[c], tol=1e-9)
+
+
+@pytest.mark.parametrize("shape,order", [((8, 8, 8), 2), ((16, 32, 8), 4), ((32, 32, 32), 6), ((256, 256, 256), 2)])
+def test_fft_poisson_solve_matches_oracle(shape, order):
+    """The exact discrete periodic solve with Table 1's symbols against the oracle's."""
+    from oracle import highorder
+    from paper_1103_6031_amd import mgic
+    f = _field(shape, 31 + order)
+    h = 0.71
+    note("spectral: FFT Poisson solve shape %s order %d" % (shape, order))
+    got = to_host(mgic.spec_poisson(to_dev(f), h, order))
+    _close(got, highorder.fft_solve(f, h, order))
