@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel directly (no graph replay)")
     ap.add_argument("--only", default="",
                     help="comma-separated legs to run alone, without the headline step (profiling): "
-                         "roof512, c1, c3, hoz, c4, spectral, density, ho")
+                         "roof512, c1, c3, hoz, c4, bh, spectral, density, ho")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -171,6 +171,46 @@ def time_batch(mg, torch, reps):
                 cells=int(sum(N ** 3 for N in sizes)), ms_per_solve=round(dt * 1e3, 3),
                 value=round(ups / dt / 1e6, 1), unit="Mcell-updates/s", cycles=[min(cyc), max(cyc)],
                 sequential_ms=round(dts * 1e3, 3), speedup=round(dts / dt, 2), bit_identical_to_solo=same)
+
+
+def time_batch_hier(mg, torch, reps=3, count=8):
+    """Independent zoom hierarchies in one call (each a 128^3 base with three nested 128^3
+    patches, its own nested BBKS density), mixed precision: the batched call against the same
+    solves one after another on one stream.  Every instance's bits equal its solo solve."""
+    from paper_1103_6031_amd import inputs
+    patches = inputs.c3_layout(128, 128, 3)
+    hs = [mg.Hier(128, inputs.BOX / 128, patches) for _ in range(count)]
+    fs = [[torch.from_numpy(a).to("cuda:0") for a in inputs.nested_fields(128, patches, inputs.SEED_C3 + 17 * k)]
+          for k in range(count)]
+    o = _opts(mg, tol=1e-10, prec="mixed", max_cycles=60)
+    ws = mg.Workspace(mg.mg_batch_hier_workspace_bytes(hs, o))
+    u = [[torch.empty_like(x) for x in fi] for fi in fs]
+    mg.mg_solve_batch_hier(hs, fs, u=u, opts=o, workspace=ws)     # warm-up (graph capture per lane)
+    mg.mg_solve_batch_hier(hs, fs, u=u, opts=o, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = mg.mg_solve_batch_hier(hs, fs, u=u, opts=o, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ups = sum(x["cell_updates"] for x in st)
+    wss = [mg.Workspace(mg.mg_workspace_bytes(H, o)) for H in hs]
+    us = [[torch.empty_like(x) for x in fi] for fi in fs]
+    for _ in range(2):
+        for H, fi, ui, w in zip(hs, fs, us, wss):
+            mg.mg_solve_hierarchy(H, fi, u=ui, opts=o, workspace=w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for H, fi, ui, w in zip(hs, fs, us, wss):
+            mg.mg_solve_hierarchy(H, fi, u=ui, opts=o, workspace=w)
+    torch.cuda.synchronize()
+    dts = (time.perf_counter() - t0) / reps
+    same = all(bool(torch.equal(a, b)) for ai, bi in zip(u, us) for a, b in zip(ai, bi))
+    return dict(workload="%d independent hierarchies of 128^3 + 3 nested 128^3 patches, mixed, tol 1e-10" % count,
+                ms_per_batch=round(dt * 1e3, 3), value=round(ups / dt / 1e6, 1), unit="Mcell-updates/s",
+                cycles=[x["cycles"] for x in st], sequential_ms=round(dts * 1e3, 3), speedup=round(dts / dt, 2),
+                bit_identical_to_solo=same)
 
 
 def time_c1(mg, torch, reps=10):
@@ -628,6 +668,8 @@ def main():
                 line["highorder_zoom"] = time_highorder_zoom(mg, torch)
             elif leg == "c4":
                 line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
+            elif leg == "bh":
+                line["batch_hier"] = time_batch_hier(mg, torch)
             elif leg == "spectral":
                 line["spectral"] = time_spectral(mg, torch, ft)
             elif leg == "density":
@@ -704,6 +746,7 @@ def main():
         line["highorder_zoom"] = time_highorder_zoom(mg, torch)
     if not a.no_batch:
         line["batch_c4"] = time_batch(mg, torch, max(2, a.steps // 2))
+        line["batch_hier"] = time_batch_hier(mg, torch)
     if serve_host is not None:
         wl = ("%d requests, Poisson %g/s, base {64,128,256}^3 with 0-3 patches of {64,96,128}^3, 1LPT/2LPT 50/50, "
               "%s, tol 1e-10, %d slots, %g GB budget")

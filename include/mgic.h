@@ -61,6 +61,16 @@ enum { MG_FP64 = 0, MG_MIXED = 1 };
 #define MG_USE_INITIAL_GUESS 0x1u  /* start from the caller's u instead of 0                    */
 #define MG_FIXED_CYCLES      0x2u  /* run exactly max_cycles cycles, no per-cycle host readback */
 #define MG_NO_GRAPH          0x4u  /* launch every kernel directly instead of replaying graphs    */
+/* MG_NO_MEAN_FIX: f is taken as given, with no composite mean removed, and u is returned in the
+ * gauge the iteration leaves it (no final zero-mean shift); stats.f_mean_removed is 0.  For a
+ * caller whose f already has zero composite mean (tau from lpt2_source does): it saves the sum
+ * and subtraction passes over f and the final pass over u.  The periodic problem needs that zero
+ * mean (Section 3.2): with a nonzero mean the residual stalls at the mean's share of ||f|| and
+ * the solve ends without converging (MG_ENOCONV at max_cycles, or MG_EDIVERGED once rounding
+ * makes the stalled residual grow three cycles in a row).  Accepted by mg_solve_level, mg_solve_hierarchy, their
+ * allocation-free variant and mg_solve_batch_hier; mg_solve_batch and the higher-order solves
+ * reject it (MG_EINVAL). */
+#define MG_NO_MEAN_FIX       0x8u
 
 typedef struct {
     int n[3];       /* cells per axis (base: all three equal)                 */
@@ -78,7 +88,7 @@ typedef struct {
     int max_cycles;     /* V-cycles at most (FP64 cycles, or FP32 inner cycles when mixed)            */
     int nu1, nu2;       /* pre / post red-black Gauss-Seidel sweeps (the paper uses 2 / 2)            */
     int prec;           /* MG_FP64 or MG_MIXED                                                        */
-    unsigned flags;     /* MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES                                     */
+    unsigned flags;     /* MG_USE_INITIAL_GUESS | MG_FIXED_CYCLES | MG_NO_GRAPH | MG_NO_MEAN_FIX        */
     int inner;          /* mixed only: FP32 V-cycles per FP64 correction (1..16); 0 = chosen per      */
                         /* correction from the measured contraction, at most 4                      */
 } mg_opts;
@@ -341,6 +351,27 @@ size_t mg_batch_workspace_bytes(int ninst, const int* n, const mg_opts* opts);
 int mg_solve_batch(int ninst, const int* n, const double* h, const double* const* f,
                    double* const* u, const mg_opts* opts, mg_stats* stats, void* workspace,
                    size_t workspace_bytes, void* stream);
+
+/* Workspace bytes for mg_solve_batch_hier over these instances (exact; 0 with the reason in
+ * mg_last_error when an instance or the options are invalid). */
+size_t mg_batch_hier_workspace_bytes(int ninst, const mg_hier* const* hier, const mg_opts* opts);
+
+/* Solve ninst independent problems, each a hierarchy (Sections 3.2-3.3: a periodic base with
+ * 0..7 nested patches).  hier[i] describes instance i; f[i][p], u[i][p] are the device arrays of
+ * its level p (the pointer arrays are host arrays); stats (host array of ninst, may be NULL) per
+ * instance.  Each instance's result, cycle count and residual history are bit-identical to
+ * mg_solve_hierarchy with the same options.  Single-level instances share the batched launches
+ * of mg_solve_batch on `stream` (with MG_NO_MEAN_FIX they are solved like the others); the
+ * instances with patches run concurrently, up to three at a time, largest first, each as its own solve on a library-owned stream of default priority
+ * driven by a library worker thread (created on first use, kept until the process ends).  Those
+ * streams start after the work already queued on `stream`, and later work on `stream` waits for
+ * them.  Calls are serialised: one hierarchy batch at a time per process.  Returns MG_EINVAL
+ * (arguments, before any device work) or MG_EHIP if any part failed, else the first instance, in
+ * instance order, that did not converge (MG_ENOCONV) or diverged (MG_EDIVERGED); all instances
+ * are still solved and their stats filled. */
+int mg_solve_batch_hier(int ninst, const mg_hier* const* hier, const double* const* const* f,
+                        double* const* const* u, const mg_opts* opts, mg_stats* stats, void* workspace,
+                        size_t workspace_bytes, void* stream);
 
 /* Autotuning of the batched smoother (block size and cells per thread, per level depth).
  * mg_batch_tune_candidates: the number of candidate shapes.  mg_batch_force_shape(i): every

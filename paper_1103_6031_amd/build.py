@@ -22,7 +22,7 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
 ]
 SOURCES = ["k_multigrid.hip", "k_levels.hip", "k_lpt.hip", "k_highorder.hip", "k_fft.hip", "k_density.hip",
-           "solver.cpp", "spectral.cpp", "density.cpp"]
+           "solver.cpp", "spectral.cpp", "density.cpp", "batch_hier.cpp"]
 
 
 def _compile(args):
@@ -46,7 +46,7 @@ def build(verbose=True, out=LIB, defines=(), csrc=CSRC):
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, [(s, objdir, list(defines), csrc) for s in SOURCES]))
     tmp = out + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))

@@ -498,9 +498,10 @@ static void composite_residual(Plan& P, R* const* rout, bool rout_natural, hipSt
     launch_finalize(P.partials, s, P.scal + S_RNORM, st);
 }
 
-// f working copies: copy, restrict bottom-up, subtract the composite mean; |f|^2 -> scal[S_FNORM]
-static int prepare_f(Plan& P, const double* const* f_user, hipStream_t st) {
-    if (P.nh == 1 && P.L[0].lay.split) {
+// f working copies: copy, restrict bottom-up, subtract the composite mean (unless fix_mean is
+// false: the caller's f is taken as it is); |f|^2 -> scal[S_FNORM]
+static int prepare_f(Plan& P, const double* const* f_user, hipStream_t st, bool fix_mean = true) {
+    if (fix_mean && P.nh == 1 && P.L[0].lay.split) {
         // one periodic level: copy-in with the sum, then mean removal with the sum of squares
         // (the same partial sums, so the same bits, as the separate passes below)
         Level& L = P.L[0];
@@ -523,18 +524,22 @@ static int prepare_f(Plan& P, const double* const* f_user, hipStream_t st) {
     std::vector<double*> f(P.nh);
     for (int l = 0; l < P.nh; ++l) f[l] = P.L[l].f;
     restrict_up<double>(P, f.data(), st);
-    const Level& base = P.L[P.nh - 1];
-    base_sum(P, base.f, S_FSUM, st);
-    const double inv = 1.0 / (double)base.d.cells();
-    for (int l = 0; l < P.nh; ++l) launch_sub_mean<double>(P.L[l].f, P.L[l].d.cells(), P.scal + S_FSUM, inv, st);
+    if (fix_mean) {
+        const Level& base = P.L[P.nh - 1];
+        base_sum(P, base.f, S_FSUM, st);
+        const double inv = 1.0 / (double)base.d.cells();
+        for (int l = 0; l < P.nh; ++l) launch_sub_mean<double>(P.L[l].f, P.L[l].d.cells(), P.scal + S_FSUM, inv, st);
+    }
     composite_sq(P, f.data(), S_FNORM, st);
     return MG_OK;
 }
 
-static void gauge_u(Plan& P, hipStream_t st) {
+// covered cells of u := the mean of their children; then (fix_mean) the composite mean removed
+static void gauge_u(Plan& P, hipStream_t st, bool fix_mean = true) {
     std::vector<double*> u(P.nh);
     for (int l = 0; l < P.nh; ++l) u[l] = P.L[l].u;
     restrict_up<double>(P, u.data(), st);
+    if (!fix_mean) return;
     const Level& base = P.L[P.nh - 1];
     base_sum(P, base.u, S_USUM, st);
     const double inv = 1.0 / (double)base.d.cells();
@@ -633,6 +638,8 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
 
     const bool fixed = (o->flags & MG_FIXED_CYCLES) != 0;
     const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
+    const bool fix_mean = (o->flags & MG_NO_MEAN_FIX) == 0;
+    const std::string mtag = fix_mean ? "" : "|nomean";
     // Launch sequences that repeat (a cycle, an outer step) are replayed as HIP graphs, captured
     // the second time a sequence is met for this workspace and plan; not with kernel timing (its
     // events are recorded by the dispatches) nor in the allocation-free call.
@@ -668,15 +675,16 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     // u as zero without reading it and writes the zero iterate itself
     const bool zero_start = !guess && P.mixed && P.L[0].ualt;
     double fs[2] = {0, 0};
-    rc = step(std::string("|prep") + (guess ? "g" : "z") + ukey, [&](hipStream_t s) {
-        prepare_f(P, f, s);
+    // without the mean fix only |f|^2 is read back (the mean removed is reported as 0)
+    rc = step(std::string("|prep") + (guess ? "g" : "z") + mtag + ukey, [&](hipStream_t s) {
+        prepare_f(P, f, s, fix_mean);
         for (int l = 0; l < P.nh; ++l) {
             Level& L = P.L[l];
             if (zero_start) continue;
             if (!guess) launch_fill<double>(L.u, L.d.cells(), 0.0, s);
             else if (L.u != L.u_user) launch_relayout<double, double>(L.u_user, mklay(L.d, 0), L.u, L.lay, s);
         }
-    }, S_FSUM, fixed ? 0 : 2, fs);
+    }, fix_mean ? S_FSUM : S_FNORM, fixed ? 0 : (fix_mean ? 2 : 1), fix_mean ? fs : fs + 1);
     if (rc) return rc;
 
     mg_stats S;
@@ -810,14 +818,14 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
         if (pending)
             for (int l = 0; l < P.nh; ++l) launch_add_f32_to_f64(P.L[l].u, P.L[l].u32, P.L[l].d.cells(), st);
     }
-    rc = step("|fin" + ptag(P.L[0].u) + ukey, [&](hipStream_t s) {   // P.L[0].u: where the fused path ended
-        if (P.nh == 1 && P.L[0].u != P.L[0].u_user) {
+    rc = step("|fin" + ptag(P.L[0].u) + mtag + ukey, [&](hipStream_t s) {   // P.L[0].u: where the fused path ended
+        if (fix_mean && P.nh == 1 && P.L[0].u != P.L[0].u_user) {
             // one periodic level: its sum, then the copy back with the mean removed
             Level& L = P.L[0];
             base_sum(P, L.u, S_USUM, s);
             launch_relayout_sub(L.u, L.lay, L.u_user, mklay(L.d, 0), P.scal + S_USUM, 1.0 / (double)L.d.cells(), s);
         } else {
-            gauge_u(P, s);
+            gauge_u(P, s, fix_mean);
             for (int l = 0; l < P.nh; ++l) {
                 Level& L = P.L[l];
                 if (L.u != L.u_user) launch_relayout<double, double>(L.u, L.lay, L.u_user, mklay(L.d, 0), s);
@@ -1422,12 +1430,16 @@ struct InstState {
     bool early = false;   // stopped before the first cycle (non-finite source): u is not written
 };
 
+// codes (optional, ninst entries): each instance's own result (MG_OK / MG_ENOCONV / MG_EDIVERGED),
+// filled when the call returns one of those
 static int solve_batch(int ninst, const int* n, const double* h, const double* const* f, double* const* u,
-                       const mg_opts* o, mg_stats* stats, void* ws, size_t ws_bytes, hipStream_t st) {
+                       const mg_opts* o, mg_stats* stats, void* ws, size_t ws_bytes, hipStream_t st,
+                       int* codes = nullptr) {
     if (ninst < 1 || !n || !h || !f || !u || !o) return fail(MG_EINVAL, "NULL argument");
     if (o->max_cycles < 0) return fail(MG_EINVAL, "max_cycles < 0");
     if (o->prec != MG_FP64 && o->prec != MG_MIXED) return fail(MG_EINVAL, "unknown precision");
     if (o->inner < 0 || o->inner > 16) return fail(MG_EINVAL, "inner cycles out of range (0..16)");
+    if (o->flags & MG_NO_MEAN_FIX) return fail(MG_EINVAL, "the batched solve always removes the mean (MG_NO_MEAN_FIX)");
     for (int i = 0; i < ninst; ++i)
         if (!f[i] || !u[i]) return fail(MG_EINVAL, "instance pointer is NULL");
     BatchPlan B;
@@ -1450,6 +1462,7 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
         const int rc = solve(&H, fp, up, o, stats ? stats + i : nullptr, (char*)ws + slice[i], sbytes[i], st);
         if (rc == MG_EINVAL || rc == MG_EHIP) return rc;
         if (rc && !worst) worst = rc;
+        if (codes) codes[i] = rc;
     }
     const int ni = (int)B.P.size();
     if (!ni) return worst;
@@ -1785,11 +1798,20 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
     // the first failure in instance order decides the return code
     std::vector<int> code(ninst, MG_OK);
     for (int i = 0; i < ni; ++i) code[B.ids[i]] = S[i].status;
+    if (codes)
+        for (int i = 0; i < ninst; ++i)
+            if (in_batch[i]) codes[i] = code[i];
     for (int i = 0; i < ninst; ++i)
         if (in_batch[i] && code[i] != MG_OK && !worst) worst = code[i];
     if (worst == MG_ENOCONV) return fail(MG_ENOCONV, "an instance did not converge within max_cycles");
     if (worst == MG_EDIVERGED) return fail(MG_EDIVERGED, "an instance diverged (NaN/Inf or growth)");
     return worst;
+}
+
+// the batched periodic solves with each instance's own result code (for the hierarchy batch)
+int solve_batch_codes(int ninst, const int* n, const double* h, const double* const* f, double* const* u,
+                      const mg_opts* o, mg_stats* stats, int* codes, void* ws, size_t ws_bytes, hipStream_t st) {
+    return solve_batch(ninst, n, h, f, u, o, stats, ws, ws_bytes, st, codes);
 }
 
 static size_t batch_bytes(int ninst, const int* n, const mg_opts* o) {

@@ -28,6 +28,7 @@ MG_FP64, MG_MIXED = 0, 1
 MG_USE_INITIAL_GUESS = 0x1
 MG_FIXED_CYCLES = 0x2
 MG_NO_GRAPH = 0x4
+MG_NO_MEAN_FIX = 0x8
 
 _ERRNAMES = {MG_EINVAL: "MG_EINVAL", MG_ENOCONV: "MG_ENOCONV", MG_EDIVERGED: "MG_EDIVERGED", MG_EHIP: "MG_EHIP"}
 
@@ -97,6 +98,9 @@ _sig = {
     "mg_batch_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mg_opts)]),
     "mg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                       _PP, _PP, ctypes.POINTER(mg_opts), ctypes.POINTER(mg_stats), _P, _sz, _P]),
+    "mg_batch_hier_workspace_bytes": (_sz, [ctypes.c_int, _P, ctypes.POINTER(mg_opts)]),
+    "mg_solve_batch_hier": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, ctypes.POINTER(mg_opts),
+                                           ctypes.POINTER(mg_stats), _P, _sz, _P]),
     "mg_smooth_level": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.c_int,
                                        _P, _sz, _P]),
     "mg_ghost_fill": (ctypes.c_int, [ctypes.POINTER(mg_hier), ctypes.c_int, _PP, _P, ctypes.c_int, _P]),
@@ -167,7 +171,7 @@ class Hier:
 
 
 def make_opts(tol=1e-10, max_cycles=50, nu1=2, nu2=2, prec="fp64", fixed_cycles=False, initial_guess=False,
-              inner=0, graph=True):
+              inner=0, graph=True, mean_fix=True):
     o = mg_opts()
     o.inner = inner
     o.tol = tol
@@ -176,7 +180,7 @@ def make_opts(tol=1e-10, max_cycles=50, nu1=2, nu2=2, prec="fp64", fixed_cycles=
     o.nu2 = nu2
     o.prec = {"fp64": MG_FP64, "mixed": MG_MIXED}[prec] if isinstance(prec, str) else int(prec)
     o.flags = ((MG_FIXED_CYCLES if fixed_cycles else 0) | (MG_USE_INITIAL_GUESS if initial_guess else 0)
-               | (0 if graph else MG_NO_GRAPH))
+               | (0 if graph else MG_NO_GRAPH) | (0 if mean_fix else MG_NO_MEAN_FIX))
     return o
 
 
@@ -527,6 +531,48 @@ def mg_batch_workspace_bytes(sizes, opts=None) -> int:
     if b == 0:
         raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
     return b
+
+
+def _hier_array(hiers):
+    """Host array of pointers to mg_hier structs (the structs are kept alive with it)."""
+    structs = [h.c_struct() for h in hiers]
+    arr = (ctypes.POINTER(mg_hier) * len(structs))(*[ctypes.pointer(H) for H in structs])
+    return ctypes.cast(arr, ctypes.c_void_p), (arr, structs)
+
+
+def mg_batch_hier_workspace_bytes(hiers: Sequence[Hier], opts=None) -> int:
+    o = opts or make_opts()
+    hp, _keep = _hier_array(hiers)
+    b = _lib.mg_batch_hier_workspace_bytes(len(hiers), hp, ctypes.byref(o))
+    if b == 0:
+        raise MGError(MG_EINVAL, _lib.mg_last_error().decode())
+    return b
+
+
+def mg_solve_batch_hier(hiers: Sequence[Hier], f: Sequence[Sequence[torch.Tensor]], u=None, opts=None,
+                        workspace=None, stream=None, check=True):
+    """Independent hierarchy solves in one call.  f[i][p]: level p of instance i.  Returns
+    (u as a list of per-instance level lists, list of stats dicts)."""
+    o = opts or make_opts()
+    k = len(hiers)
+    if len(f) != k:
+        raise ValueError("one list of level fields per hierarchy")
+    if u is None:
+        u = [[torch.empty_like(x) for x in fi] for fi in f]
+    need = mg_batch_hier_workspace_bytes(hiers, o)
+    ws = _ws(workspace, need)
+    hp, keep = _hier_array(hiers)
+    fl = [_ptr_array([_dev(x, "f") for x in fi]) for fi in f]
+    ul = [_ptr_array([_dev(x, "u") for x in ui]) for ui in u]
+    fa = (_PP * k)(*[p for p, _ in fl])
+    ua = (_PP * k)(*[p for p, _ in ul])
+    st = (mg_stats * k)()
+    rc = _lib.mg_solve_batch_hier(k, hp, ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ua, ctypes.c_void_p),
+                                  ctypes.byref(o), st, ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream))
+    stats = [st[i].to_dict() for i in range(k)]
+    if check:
+        _check(rc, stats)
+    return u, stats
 
 
 def mg_solve_batch(f: Sequence[torch.Tensor], h: Sequence[float], u=None, opts=None, workspace=None, stream=None,

@@ -151,7 +151,8 @@ def test_higher_order_solve_validates_its_arguments_before_any_device_work():
                            (mgic.make_opts(), 12, 4, 1.0),
                            (mgic.make_opts(), 16, 4, -1.0),
                            (mgic.make_opts(nu1=-1), 16, 4, 1.0),
-                           (mgic.make_opts(max_cycles=-1), 16, 4, 1.0)):
+                           (mgic.make_opts(max_cycles=-1), 16, 4, 1.0),
+                           (mgic.make_opts(mean_fix=False), 16, 4, 1.0)):   # the mean is always fixed here
         assert lib.mg_solve_level_ho(n, h, order, p, p, ctypes.byref(o), ctypes.byref(st), ws, big, None) == mgic.MG_EINVAL
     o = mgic.make_opts()
     assert lib.mg_solve_level_ho(16, 1.0, 4, None, p, ctypes.byref(o), ctypes.byref(st), ws, big, None) == mgic.MG_EINVAL
@@ -274,3 +275,56 @@ def test_density_validates_before_any_device_work():
     assert mgic._lib.ic_multiscale_density(ctypes.byref(H), fake, 100, 0.01, 1, pp, pp, fake, 1 << 40,
                                            None) == mgic.MG_EINVAL
     assert b"radial table" in mgic._lib.mg_last_error()
+
+
+def test_hierarchy_batch_validates_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    o = mgic.make_opts()
+    a = mgic.Hier(32, 1.0, [((16, 16, 16), (8, 8, 8))])
+    b = mgic.Hier(16, 2.0)
+    need = mgic.mg_batch_hier_workspace_bytes([a, b], o)
+    # the two parts, each rounded up to 256 bytes
+    up = lambda x: (x + 255) // 256 * 256
+    assert need == up(mgic.mg_batch_workspace_bytes([16], o)) + up(mgic.mg_workspace_bytes(a, o))
+    assert mgic.mg_batch_hier_workspace_bytes([a], o) == up(mgic.mg_workspace_bytes(a, o))
+    with pytest.raises(mgic.MGError, match="instance 1"):
+        mgic.mg_batch_hier_workspace_bytes([a, mgic.Hier(32, 1.0, [((14, 16, 16), (8, 8, 8)), ((8, 8, 8), (1, 1, 1))])], o)
+    with pytest.raises(mgic.MGError):
+        mgic.mg_batch_hier_workspace_bytes([mgic.Hier(32, 1.0, [((13, 16, 16), (8, 8, 8))])], o)
+    fake = ctypes.c_void_p(256)
+    hp, _keep = mgic._hier_array([a, b])
+    fl = [mgic._ptr_array([256, 256]), mgic._ptr_array([256])]
+    fa = (mgic._PP * 2)(*[p for p, _ in fl])
+    fa_p = ctypes.cast(fa, ctypes.c_void_p)
+    st = (mgic.mg_stats * 2)()
+    call = mgic._lib.mg_solve_batch_hier
+    assert call(2, hp, None, fa_p, ctypes.byref(o), st, fake, need, None) == mgic.MG_EINVAL
+    assert call(0, hp, fa_p, fa_p, ctypes.byref(o), st, fake, need, None) == mgic.MG_EINVAL
+    assert call(2, hp, fa_p, fa_p, ctypes.byref(o), st, fake, need - 1, None) == mgic.MG_EINVAL
+    assert b"workspace too small" in mgic._lib.mg_last_error()
+    assert call(2, hp, fa_p, fa_p, ctypes.byref(o), st, ctypes.c_void_p(257), need, None) == mgic.MG_EINVAL
+    assert b"aligned" in mgic._lib.mg_last_error()
+    bad_lvl = [mgic._ptr_array([256, 0]), mgic._ptr_array([256])]
+    fb = (mgic._PP * 2)(*[p for p, _ in bad_lvl])
+    assert call(2, hp, ctypes.cast(fb, ctypes.c_void_p), fa_p, ctypes.byref(o), st, fake, need,
+                None) == mgic.MG_EINVAL
+    assert b"instance 0" in mgic._lib.mg_last_error()
+    bad = mgic.make_opts(max_cycles=-1)
+    assert call(2, hp, fa_p, fa_p, ctypes.byref(bad), st, fake, need, None) == mgic.MG_EINVAL
+
+
+def test_batched_solve_rejects_no_mean_fix_before_any_device_work():
+    from paper_1103_6031_amd import mgic
+    o = mgic.make_opts(mean_fix=False)
+    assert o.flags & mgic.MG_NO_MEAN_FIX
+    n = (ctypes.c_int * 2)(32, 64)
+    h = (ctypes.c_double * 2)(1.0, 0.5)
+    fp, _k1 = mgic._ptr_array([256, 512])
+    st = (mgic.mg_stats * 2)()
+    need = mgic.mg_batch_workspace_bytes([32, 64], o)
+    rc = mgic._lib.mg_solve_batch(2, n, h, fp, fp, ctypes.byref(o), st, ctypes.c_void_p(256), need, None)
+    assert rc == mgic.MG_EINVAL and b"MG_NO_MEAN_FIX" in mgic._lib.mg_last_error()
+    # the hierarchy batch solves such instances on its lanes instead: its workspace has no batched part
+    H = [mgic.Hier(32, 1.0), mgic.Hier(64, 0.5)]
+    up = lambda x: (x + 255) // 256 * 256
+    assert mgic.mg_batch_hier_workspace_bytes(H, o) == sum(up(mgic.mg_workspace_bytes(x, o)) for x in H)
