@@ -1038,6 +1038,9 @@ struct BatchPlan {
     std::vector<float*> Ae, Be;
 };
 
+// blocks of a batched half-sweep segment (the kernels' own block order decides it)
+unsigned rbgs_split_blocks(const Lay& L, int block, int V);
+
 static bool batchable(int n) { return n % 2 == 0 && (size_t)n * n * n > kTailMaxCells; }
 
 static BLaunch add_launch(std::vector<BSeg>& tab, std::vector<BSeg> segs, int block = kBlock, int V = 1) {
@@ -1094,7 +1097,7 @@ static void vcycle_tables(BatchPlan& B, int ti, int par, const std::vector<T*>& 
             T* u = d == 0 ? fine_u[i] : b.u;
             const size_t cells = L.d.cells();
             const Lay C(Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, 0);
-            BSeg s = seg0(i, cdiv(cells / 2, (size_t)sh.block * sh.V));
+            BSeg s = seg0(i, rbgs_split_blocks(L.lay, sh.block, sh.V));
             s.L = L.lay;
             s.h = L.h;
             s.a[0] = u;
@@ -1340,7 +1343,7 @@ static int tune_smoother(BatchPlan& B, int ti, hipStream_t st, std::vector<Smoot
                 Plan& P = B.P[i];
                 if (d >= P.tail) continue;
                 Level& L = P.L[d];
-                BSeg s = seg0(i, cdiv(L.d.cells() / 2, (size_t)sh.block * sh.V));
+                BSeg s = seg0(i, rbgs_split_blocks(L.lay, sh.block, sh.V));
                 s.L = L.lay;
                 s.h = L.h;
                 s.a[0] = ubuf<T>(L);

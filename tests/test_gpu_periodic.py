@@ -21,8 +21,9 @@ def mg():
 
 
 # power-of-two sizes take the 16-byte-access half-sweep (4: one run is the whole half-row, its
-# z-edge wraps onto itself), 48 and 96 the scalar one
-@pytest.mark.parametrize("N,half", [(4, 2), (8, 1), (16, 2), (32, 3), (48, 4), (96, 2), (128, 4)])
+# z-edge wraps onto itself), 48 and 160 the scalar one in flat block order, 96 the scalar one in
+# plane-chunk order (8 blocks per x plane)
+@pytest.mark.parametrize("N,half", [(4, 2), (8, 1), (16, 2), (32, 3), (48, 4), (96, 2), (128, 4), (160, 3)])
 def test_smoother_bit_exact_fp64(mg, N, half):
     rng = np.random.default_rng(N + half)
     u0 = rng.standard_normal((N, N, N))
