@@ -273,11 +273,26 @@ void launch_resid_restrict_p2(const T* u, const T* f, int n, double h, T* pu, T*
     k_resid_restrict_p2<T><<<(cells + 255) / 256, 256, 0, st>>>(u, f, lg, (T)(h * h), pu, pf, uold);
 }
 
+// step 8 on the black cells, W at a time with 16-byte accesses (run_prolong_black_vec)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_prolong_black_vec(T* __restrict__ u, int lg, const T* __restrict__ pu, const T* __restrict__ uold) {
+    constexpr int W = Vec16<T>::W;
+    const unsigned ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch < (1u << (3 * lg - 1 - __builtin_ctz(W)))) run_prolong_black_vec<T>(u, lg, pu, uold, ch);
+}
+
 template <class T>
 void launch_prolong_black_p2(T* u, int n, const T* pu, const T* uold, hipStream_t st) {
+    constexpr int W = Vec16<T>::W;
     const int lg = __builtin_ctz((unsigned)n);
     const unsigned cells = 1u << (3 * lg - 1);
-    k_prolong_black_p2<T><<<(cells + 255) / 256, 256, 0, st>>>(u, lg, pu, uold);
+    if ((1u << (lg - 1)) % W == 0) {   // half-rows hold whole runs
+        const unsigned runs = cells / W;
+        k_prolong_black_vec<T><<<(runs + 255) / 256, 256, 0, st>>>(u, lg, pu, uold);
+    } else {
+        k_prolong_black_p2<T><<<(cells + 255) / 256, 256, 0, st>>>(u, lg, pu, uold);
+    }
 }
 
 template <class T>
@@ -404,47 +419,15 @@ void launch_rbgs_vec_corr(T* u, const T* f, const Lay& L, double h, const T* pu,
     k_rbgs_vec_corr<T><<<(chunks + 255) / 256, 256, 0, st>>>(u, f, L.lgx, L.lgy, L.lgz, (T)(h * h), pu, uold);
 }
 
-// Step 6 on a whole periodic colour-split power-of-two level with 16-byte accesses: a thread
-// takes the runs j0 .. j0 + W - 1 of both colours of one row (the red run's neighbours are the
-// black runs of the 4 neighbour rows and the black run of its own row, and the other way round),
-// and updates pf += (nsum(pu) - 6 pu) / H2 for the 2W cells with the arithmetic of k_fas_rhs_p2.
+// Step 6 on a whole periodic colour-split power-of-two level with 16-byte accesses (run_fas_vec:
+// a thread takes the runs j0 .. j0 + W - 1 of both colours of one row).
 template <class T>
 __global__ void __launch_bounds__(256)
 k_fas_vec(const T* __restrict__ pu, T* __restrict__ pf, int lg, T H2) {
-    using V = typename Vec16<T>::type;
     constexpr int W = Vec16<T>::W;
-    const unsigned lzh = (unsigned)lg - 1, nzh = 1u << lzh, m = (1u << lg) - 1;
-    const unsigned chunks = 1u << (2 * lg + lzh - __builtin_ctz(W));   // runs per colour
+    const unsigned chunks = 1u << (3 * lg - 1 - __builtin_ctz(W));   // runs per colour
     const unsigned ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= chunks) return;
-    const unsigned t = ch * W, row = t >> lzh, j0 = t & (nzh - 1);
-    const unsigned x = row >> lg, y = row & m;
-    const unsigned r0 = row << lg;
-    const unsigned rxm = ((((x - 1) & m) << lg) | y) << lg, rxp = ((((x + 1) & m) << lg) | y) << lg;
-    const unsigned rym = ((x << lg) | ((y - 1) & m)) << lg, ryp = ((x << lg) | ((y + 1) & m)) << lg;
-    const V own[2] = {*(const V*)(pu + r0 + j0), *(const V*)(pu + r0 + nzh + j0)};   // red, black runs
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const unsigned oth = c ? 0u : nzh, mine = c ? nzh : 0u;
-        const unsigned q = (x + y + (unsigned)c) & 1u;   // z parity of colour c in the row
-        const V XM = *(const V*)(pu + rxm + oth + j0), XP = *(const V*)(pu + rxp + oth + j0);
-        const V YM = *(const V*)(pu + rym + oth + j0), YP = *(const V*)(pu + ryp + oth + j0);
-        const V& C = own[1 - c];
-        const T edge = pu[r0 + oth + (q ? ((j0 + W) & (nzh - 1)) : ((j0 - 1) & (nzh - 1)))];
-        const V Fv = *(const V*)(pf + r0 + mine + j0);
-        T out[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const T zm = q ? lane<T>(C, k) : (k == 0 ? edge : lane<T>(C, k - 1));
-            const T zp = q ? (k == W - 1 ? edge : lane<T>(C, k + 1)) : lane<T>(C, k);
-            const T s = ((lane<T>(XM, k) + lane<T>(XP, k)) + (lane<T>(YM, k) + lane<T>(YP, k))) + (zm + zp);
-            out[k] = lane<T>(Fv, k) + (s - T(6) * lane<T>(own[c], k)) / H2;
-        }
-        V o;
-        if constexpr (W == 4) o = V{out[0], out[1], out[2], out[3]};
-        else o = V{out[0], out[1]};
-        *(V*)(pf + r0 + mine + j0) = o;
-    }
+    if (ch < chunks) run_fas_vec<T>(pu, pf, lg, H2, ch);
 }
 
 template <class T>

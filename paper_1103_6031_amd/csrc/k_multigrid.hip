@@ -1426,6 +1426,35 @@ void launch_finalize(const double* partials, SegList segs, double* out, hipStrea
 // and then runs the plain kernel's body with its block index inside the instance.
 // ----------------------------------------------------------------------------------------------
 
+// A whole periodic colour-split power-of-two cube whose half-rows hold whole runs of W cells
+// (16 bytes): its FAS right-hand side and black prolongation take the run bodies.
+__host__ __device__ inline bool p2_runs(const Lay& L, unsigned W) {
+    return L.pow2 && L.split && L.lgx == L.lgy && L.lgy == L.lgz && L.lgz >= 2 && ((1u << (L.lgz - 1)) % W) == 0;
+}
+__host__ __device__ inline bool whole_periodic(const ParentMap& pm) {
+    return pm.periodic && pm.off[0] == 0 && pm.off[1] == 0 && pm.off[2] == 0;
+}
+// FAS on the covered box C of parent pm: the whole parent
+__host__ __device__ inline bool fas_runs(const Lay& C, const ParentMap& pm, unsigned W) {
+    return p2_runs(pm.pl, W) && whole_periodic(pm) && C.d.x == pm.pl.d.x && C.d.y == pm.pl.d.y && C.d.z == pm.pl.d.z;
+}
+// black prolongation of level L from its whole coarsening pm
+__host__ __device__ inline bool prolong_runs(const Lay& L, const ParentMap& pm, unsigned W) {
+    return p2_runs(L, W) && pm.pl.pow2 && pm.pl.split && whole_periodic(pm) && pm.pl.lgx == L.lgx - 1 &&
+           pm.pl.lgy == L.lgy - 1 && pm.pl.lgz == L.lgz - 1;
+}
+// blocks of kBlock threads for a batched FAS / black-prolongation segment
+unsigned fas_blocks(const Lay& C, const ParentMap& pm, int elem) {
+    const unsigned W = 16u / (unsigned)elem;
+    const size_t n = fas_runs(C, pm, W) ? C.d.cells() / 2 / W : C.d.cells();
+    return (unsigned)((n + kBlock - 1) / kBlock);
+}
+unsigned prolong_black_blocks(const Lay& L, const ParentMap& pm, int elem) {
+    const unsigned W = 16u / (unsigned)elem;
+    const size_t n = prolong_runs(L, pm, W) ? L.d.cells() / 2 / W : L.d.cells() / 2;
+    return (unsigned)((n + kBlock - 1) / kBlock);
+}
+
 __device__ __forceinline__ const BSeg& seg_of(const BSeg* __restrict__ segs, int nseg, unsigned& lb) {
     const unsigned b = blockIdx.x;
     int lo = 0, hi = nseg - 1;
@@ -1486,6 +1515,10 @@ __global__ void kb_fas(const BSeg* __restrict__ segs, int nseg, const int* __res
     const Lay C = s.C;
     const ParentMap pm = s.pm;
     const unsigned t = lb * blockDim.x + threadIdx.x;
+    if (fas_runs(C, pm, Vec16<T>::W)) {   // 16-byte runs of both colours (same bits)
+        if (t < (unsigned)(C.d.cells() / 2 / Vec16<T>::W)) run_fas_vec<T>((const T*)s.a[0], (T*)s.a[1], pm.pl.lgx, (T)(s.h * s.h), t);
+        return;
+    }
     if (t < (unsigned)C.d.cells()) cell_fas<T>((const T*)s.a[0], (T*)s.a[1], pm, C, (T)(s.h * s.h), t);
 }
 
@@ -1498,6 +1531,11 @@ __global__ void kb_prolong(const BSeg* __restrict__ segs, int nseg, const int* _
     const ParentMap pm = s.pm;
     const unsigned t = lb * blockDim.x + threadIdx.x;
     if constexpr (BLACK) {
+        if (prolong_runs(L, pm, Vec16<T>::W)) {   // 16-byte runs of black cells (same bits)
+            if (t < (unsigned)(L.d.cells() / 2 / Vec16<T>::W))
+                run_prolong_black_vec<T>((T*)s.a[0], L.lgx, (const T*)s.a[1], (const T*)s.a[2], t);
+            return;
+        }
         if (t < (unsigned)(L.d.cells() >> 1))
             cell_prolong_black<T>((T*)s.a[0], L, (const T*)s.a[1], (const T*)s.a[2], pm, t);
     } else {

@@ -1,6 +1,7 @@
 // Per-thread bodies for colour-split power-of-two periodic levels (Section 3.2), shared by the
 // solo kernels (k_levels.hip) and the batched ones (k_multigrid.hip): the red-black half-sweep
-// on 16-byte runs and the residual + restriction of one coarse cell.
+// and the FAS right-hand side on 16-byte runs, the black-cell prolongation on 16-byte runs, and
+// the residual + restriction of one coarse cell.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -140,6 +141,83 @@ __device__ __forceinline__ void cell_resid_restrict_p2(const T* __restrict__ u, 
     pu[P] = uc;
     pf[P] = sr * T(0.125);
     uold[t] = uc;
+}
+
+// Step 6 on a whole periodic colour-split power-of-two level (edge 2^lg) for the run ch: the
+// cells j0 .. j0 + W - 1 of both colours of one row (the red run's neighbours are the black runs
+// of the 4 neighbour rows and the black run of its own row, and the other way round) take
+// pf += (nsum(pu) - 6 pu) / H2 with the arithmetic of the one-cell-per-thread kernel.
+template <class T>
+__device__ __forceinline__ void run_fas_vec(const T* __restrict__ pu, T* __restrict__ pf, int lg, T H2, unsigned ch) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
+    const unsigned lzh = (unsigned)lg - 1, nzh = 1u << lzh, m = (1u << lg) - 1;
+    const unsigned t = ch * W, row = t >> lzh, j0 = t & (nzh - 1);
+    const unsigned x = row >> lg, y = row & m;
+    const unsigned r0 = row << lg;
+    const unsigned rxm = ((((x - 1) & m) << lg) | y) << lg, rxp = ((((x + 1) & m) << lg) | y) << lg;
+    const unsigned rym = ((x << lg) | ((y - 1) & m)) << lg, ryp = ((x << lg) | ((y + 1) & m)) << lg;
+    const V own[2] = {*(const V*)(pu + r0 + j0), *(const V*)(pu + r0 + nzh + j0)};   // red, black runs
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const unsigned oth = c ? 0u : nzh, mine = c ? nzh : 0u;
+        const unsigned q = (x + y + (unsigned)c) & 1u;   // z parity of colour c in the row
+        const V XM = *(const V*)(pu + rxm + oth + j0), XP = *(const V*)(pu + rxp + oth + j0);
+        const V YM = *(const V*)(pu + rym + oth + j0), YP = *(const V*)(pu + ryp + oth + j0);
+        const V& C = own[1 - c];
+        const T edge = pu[r0 + oth + (q ? ((j0 + W) & (nzh - 1)) : ((j0 - 1) & (nzh - 1)))];
+        const V Fv = *(const V*)(pf + r0 + mine + j0);
+        T out[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const T zm = q ? lane<T>(C, k) : (k == 0 ? edge : lane<T>(C, k - 1));
+            const T zp = q ? (k == W - 1 ? edge : lane<T>(C, k + 1)) : lane<T>(C, k);
+            const T s = ((lane<T>(XM, k) + lane<T>(XP, k)) + (lane<T>(YM, k) + lane<T>(YP, k))) + (zm + zp);
+            out[k] = lane<T>(Fv, k) + (s - T(6) * lane<T>(own[c], k)) / H2;
+        }
+        V o;
+        if constexpr (W == 4) o = V{out[0], out[1], out[2], out[3]};
+        else o = V{out[0], out[1]};
+        *(V*)(pf + r0 + mine + j0) = o;
+    }
+}
+
+// Step 8 on the black cells of a periodic colour-split power-of-two level (edge 2^lg, half-rows a
+// multiple of W) for the run ch: black cells j0 .. j0 + W - 1 of one fine row.  The black cell j
+// of fine row (x, y) lies in the parent cell (x / 2, y / 2, j), so the run's parents are W
+// consecutive cells of one coarse row: consecutive in uold (natural order), alternating between
+// the two colour halves of the colour-split parent (even z in the half of parity x/2 + y/2).
+// Each cell takes u += pu - uold as the one-cell-per-thread kernel does.
+template <class T>
+__device__ __forceinline__ void run_prolong_black_vec(T* __restrict__ u, int lg, const T* __restrict__ pu,
+                                                      const T* __restrict__ uold, unsigned ch) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
+    const unsigned lzh = (unsigned)lg - 1, nzh = 1u << lzh, m = (1u << lg) - 1;
+    const int lc = lg - 1;
+    const unsigned t = ch * W, row = t >> lzh, j0 = t & (nzh - 1);
+    const unsigned x = row >> lg, y = row & m, X = x >> 1, Y = y >> 1;
+    const unsigned crow = ((X << lc) | Y) << lc;
+    const unsigned ev = ((X + Y) & 1u) << (lc - 1), od = (((X + Y) & 1u) ^ 1u) << (lc - 1);
+    T* const ur = u + (row << lg) + nzh + j0;
+    const V U = *(const V*)ur;
+    const V O = *(const V*)(uold + crow + j0);
+    T pe[W / 2], po[W / 2];   // parents at z = j0 + 2i and j0 + 2i + 1
+    if constexpr (W == 4) {
+        const float2 a = *(const float2*)(pu + crow + ev + (j0 >> 1));
+        const float2 b = *(const float2*)(pu + crow + od + (j0 >> 1));
+        pe[0] = a.x; pe[1] = a.y; po[0] = b.x; po[1] = b.y;
+    } else {
+        pe[0] = pu[crow + ev + (j0 >> 1)];
+        po[0] = pu[crow + od + (j0 >> 1)];
+    }
+    T out[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) out[k] = lane<T>(U, k) + ((k & 1 ? po[k >> 1] : pe[k >> 1]) - lane<T>(O, k));
+    V o;
+    if constexpr (W == 4) o = V{out[0], out[1], out[2], out[3]};
+    else o = V{out[0], out[1]};
+    *(V*)ur = o;
 }
 
 }  // namespace mgic

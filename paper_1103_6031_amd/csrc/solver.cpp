@@ -1038,8 +1038,11 @@ struct BatchPlan {
     std::vector<float*> Ae, Be;
 };
 
-// blocks of a batched half-sweep segment (the kernels' own block order decides it)
+// blocks of batched half-sweep, FAS and black-prolongation segments (the kernels' own work
+// decomposition decides them)
 unsigned rbgs_split_blocks(const Lay& L, int block, int V);
+unsigned fas_blocks(const Lay& C, const ParentMap& pm, int elem);
+unsigned prolong_black_blocks(const Lay& L, const ParentMap& pm, int elem);
 
 static bool batchable(int n) { return n % 2 == 0 && (size_t)n * n * n > kTailMaxCells; }
 
@@ -1110,13 +1113,13 @@ static void vcycle_tables(BatchPlan& B, int ti, int par, const std::vector<T*>& 
             s.h = L.h;
             s.a[0] = u; s.a[1] = b.f; s.a[2] = q.u; s.a[3] = q.f; s.a[4] = b.uold;
             rr.push_back(s);
-            s = seg0(i, cdiv(C.d.cells(), kBlock));
+            s = seg0(i, fas_blocks(C, L.pm, (int)sizeof(T)));
             s.C = C;
             s.pm = L.pm;
             s.h = Q.h;
             s.a[0] = q.u; s.a[1] = q.f;
             fa.push_back(s);
-            s = seg0(i, cdiv(B.P[i].nu2 > 0 ? cells / 2 : cells, kBlock));
+            s = seg0(i, B.P[i].nu2 > 0 ? prolong_black_blocks(L.lay, L.pm, (int)sizeof(T)) : cdiv(cells, kBlock));
             s.L = L.lay;
             s.pm = L.pm;
             s.a[0] = u; s.a[1] = q.u; s.a[2] = b.uold;
