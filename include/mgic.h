@@ -60,6 +60,14 @@ enum { MG_FP64 = 0, MG_MIXED = 1 };
 /* option flags */
 #define MG_USE_INITIAL_GUESS 0x1u  /* start from the caller's u instead of 0                    */
 #define MG_FIXED_CYCLES      0x2u  /* run exactly max_cycles cycles, no per-cycle host readback */
+/* Graph capture: mg_solve_level, mg_solve_hierarchy and mg_solve_hierarchy_noalloc may be called
+ * on a stream that the caller is capturing into a HIP graph, with MG_FIXED_CYCLES (without it
+ * they return MG_EINVAL before any device work: a converging solve reads its residual back).
+ * They then launch their kernels into the capture, replay no graphs of their own and make no
+ * host call that waits; rel_res is NaN as for any fixed-cycle solve.  Make one call outside the
+ * capture first with the same shapes (it sets kernel attributes and, for the allocation-free
+ * call, looks up the scratch array).  The other solves (batched, higher-order) return MG_EINVAL
+ * under capture. */
 #define MG_NO_GRAPH          0x4u  /* launch every kernel directly instead of replaying graphs    */
 /* MG_NO_MEAN_FIX: f is taken as given, with no composite mean removed, and u is returned in the
  * gauge the iteration leaves it (no final zero-mean shift); stats.f_mean_removed is 0.  For a

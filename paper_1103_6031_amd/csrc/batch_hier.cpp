@@ -195,6 +195,10 @@ int solve_batch_hier(int ninst, const mg_hier* const* hier, const double* const*
     if (!ws || ws_bytes < need)
         return report_error(MG_EINVAL, ("workspace too small: need " + std::to_string(need)).c_str());
     if (((uintptr_t)ws) & 255) return report_error(MG_EINVAL, "workspace must be 256-byte aligned");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess) return report_error(MG_EHIP, "stream query failed");
+    if (cap != hipStreamCaptureStatusNone)
+        return report_error(MG_EINVAL, "the hierarchy batch cannot run under stream capture (its lanes wait on the host)");
 
     std::vector<int> code(ninst, MG_OK);
     std::vector<mg_stats> S(ninst);

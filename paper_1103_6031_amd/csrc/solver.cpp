@@ -269,6 +269,15 @@ static double* pinned_scratch() {
     return p;
 }
 
+// MG_EINVAL (with the reason) when st is being captured into a graph: for entry points whose
+// work includes host readbacks, uploads or waits
+static int refuse_capture(hipStream_t st, const char* what) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    MG_HIP(hipStreamIsCapturing(st, &cap));
+    if (cap != hipStreamCaptureStatusNone) return fail(MG_EINVAL, std::string(what) + " cannot run under stream capture");
+    return MG_OK;
+}
+
 // ---- graphs ------------------------------------------------------------------------------------
 // Instantiated graphs live until the thread ends; they are deliberately not destroyed at exit,
 // when the HIP runtime may already be gone.
@@ -640,14 +649,21 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     const bool guess = (o->flags & MG_USE_INITIAL_GUESS) != 0;
     const bool fix_mean = (o->flags & MG_NO_MEAN_FIX) == 0;
     const std::string mtag = fix_mean ? "" : "|nomean";
+    // A caller capturing the stream into a graph gets the launches themselves: no graphs of our
+    // own, no host readback, no wait at the end.  Only a fixed number of cycles can run so.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    MG_HIP(hipStreamIsCapturing(st, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing && !fixed)
+        return fail(MG_EINVAL, "under stream capture only MG_FIXED_CYCLES solves run (a converging solve reads its residual back)");
     // Launch sequences that repeat (a cycle, an outer step) are replayed as HIP graphs, captured
     // the second time a sequence is met for this workspace and plan; not with kernel timing (its
     // events are recorded by the dispatches) nor in the allocation-free call.
-    const bool use_graph = (o->flags & MG_NO_GRAPH) == 0 && !g_noalloc && !g_kprof.on;
+    const bool use_graph = (o->flags & MG_NO_GRAPH) == 0 && !g_noalloc && !g_kprof.on && !capturing;
     const std::string gkey = use_graph ? plan_key(P, ws) : std::string();
     const std::string ukey = use_graph ? user_key(H, f, u) : std::string();
-    double* pin = nullptr;
-    if (!g_noalloc && !(pin = pinned_scratch())) return fail(MG_EHIP, "pinned host buffer unavailable");
+    double* pin = nullptr;   // the readback buffer (a fixed-cycle solve reads nothing back)
+    if (!g_noalloc && !fixed && !(pin = pinned_scratch())) return fail(MG_EHIP, "pinned host buffer unavailable");
     // one step of the solve: `launches`, then (count > 0) the copy of scal[first .. first + count)
     // to the host and a wait for the stream
     auto step = [&](const std::string& var, auto&& launches, int first, int count, double* out) -> int {
@@ -835,7 +851,7 @@ static int solve(const mg_hier* H, const double* const* f, double* const* u, con
     if (rc) return rc;
     MG_HIP(hipGetLastError());
     if (fixed) {
-        MG_HIP(hipStreamSynchronize(st));  // surface asynchronous faults at the API boundary
+        if (!capturing) MG_HIP(hipStreamSynchronize(st));  // surface asynchronous faults at the API boundary
         status = MG_OK;
     }
     S.cycles = cycles;
@@ -1454,6 +1470,7 @@ static int solve_batch(int ninst, const int* n, const double* h, const double* c
     if (!need) return MG_EINVAL;   // build_plan reported the reason
     if (!ws || ws_bytes < need) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(need));
     if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    if (int rc = refuse_capture(st, "the batched solve (it uploads tables and reads flags back)")) return rc;
     batch_layout(ninst, n, h, o, (char*)ws, B, slice, sbytes);
     (void)hipGetLastError();
     int worst = MG_OK;
@@ -1956,6 +1973,7 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
     if (rc) return rc;
     if (!ws || ws_bytes < size_cv.off) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(size_cv.off));
     if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    if ((rc = refuse_capture(st, "the higher-order solve"))) return rc;
     Carver cv(ws);
     ho_plan(n, h, order, cv, u, P);
     (void)hipGetLastError();
@@ -2268,6 +2286,7 @@ int mg_solve_hierarchy_ho(const mg_hier* hier, int order, const double* const* f
         if (!f[p] || !u[p]) return fail(MG_EINVAL, "level pointer is NULL");
     if (!ws || ws_bytes < size_cv.off) return fail(MG_EINVAL, "workspace too small: need " + std::to_string(size_cv.off));
     if (((uintptr_t)ws) & 255) return fail(MG_EINVAL, "workspace must be 256-byte aligned");
+    if ((rc = refuse_capture(st, "the higher-order hierarchy solve"))) return rc;
     Carver cv(ws);
     hoz_plan(hier, order, cv, Z);
     (void)hipGetLastError();
