@@ -76,6 +76,7 @@ __device__ __forceinline__ unsigned ho_xcd_group(unsigned b, int lgbpp) {
     if (lgbpp < 5) return b;
     const int lk = lgbpp >= 7 ? 3 : 2;
     const unsigned G = 8u << lk;
+    if (gridDim.x & (G - 1)) return b;   // the permutation needs whole groups
     return (b & ~(G - 1)) | ((b & 7u) << lk) | ((b >> 3) & ((1u << lk) - 1));
 }
 
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_ho_half_lds(const T* __restrict__ in
     T* rows = (T*)ho_smem;                          // [kHoTy + 2R][n]
     const unsigned n = 1u << lg, m = n - 1, nh = n >> 1;
     const unsigned tiles = n / kHoTy;
-    const unsigned x = blockIdx.x / tiles, y0 = (blockIdx.x - x * tiles) * kHoTy;
+    const unsigned bl = ho_xcd_group(blockIdx.x, lg - 3);   // consecutive tiles of a plane on one XCD
+    const unsigned x = bl / tiles, y0 = (bl - x * tiles) * kHoTy;
     // stage rows y0 - R .. y0 + kHoTy + R - 1 as 16-byte pairs
     const unsigned npairs = (unsigned)(kHoTy + 2 * R) * nh;
     for (unsigned t = threadIdx.x; t < npairs; t += blockDim.x) {
@@ -181,7 +183,7 @@ template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_ho_resid_restrict(const T* __restrict__ u, const T* __restrict__ f,
                                                               T* __restrict__ uc, T* __restrict__ uold,
                                                               T* __restrict__ rc, int lgc, T h2) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned t = ho_xcd_group(blockIdx.x, 2 * lgc - 8) * blockDim.x + threadIdx.x;
     if (t >= (1u << (3 * lgc))) return;
     const int lg = lgc + 1;
     const unsigned mc = (1u << lgc) - 1, m = (1u << lg) - 1;
@@ -250,10 +252,13 @@ __global__ __launch_bounds__(kBlock) void k_ho_psum(const double* __restrict__ a
                                                     int lg, double h2, double* __restrict__ part) {
     const unsigned n = 1u << (3 * lg), m = (1u << lg) - 1;
     double acc = 0.0;
+    // block bl takes the pairs (and stores the partial) of block bl in dispatch order, so the
+    // partial sums are the same; bl groups consecutive rows of a plane on one XCD
+    const unsigned bl = MODE == 0 ? blockIdx.x : ho_xcd_group(blockIdx.x, 2 * lg - 9);
     if (MODE == 0) {
         for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) acc += a[t];
     } else {   // pairs of z-neighbours (n is even)
-        for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < n / 2; p += gridDim.x * blockDim.x) {
+        for (unsigned p = bl * blockDim.x + threadIdx.x; p < n / 2; p += gridDim.x * blockDim.x) {
             const unsigned t = 2 * p, z = t & m, y = (t >> lg) & m, x = t >> (2 * lg);
             double2 uv;
             const double2 r = ho_pair_resid<R, double>(a, f, x, y, z, lg, m, h2, &uv);
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_ho_psum(const double* __restrict__ a
         }
     }
     const double s = ho_block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[bl] = s;
 }
 
 // out = a - (*sum) / n, with the partial sums of out^2
@@ -296,7 +301,8 @@ __global__ __launch_bounds__(kBlock) void k_ho_resid32(const double* __restrict_
                                                        double* __restrict__ part) {
     const unsigned n = 1u << (3 * lg), m = (1u << lg) - 1;
     double acc = 0.0;
-    for (unsigned p = blockIdx.x * blockDim.x + threadIdx.x; p < n / 2; p += gridDim.x * blockDim.x) {
+    const unsigned bl = ho_xcd_group(blockIdx.x, 2 * lg - 9);   // as in k_ho_psum
+    for (unsigned p = bl * blockDim.x + threadIdx.x; p < n / 2; p += gridDim.x * blockDim.x) {
         const unsigned t = 2 * p, z = t & m, y = (t >> lg) & m, x = t >> (2 * lg);
         double2 uv;
         const double2 r = ho_pair_resid<R, double>(u, f, x, y, z, lg, m, h2, &uv);
@@ -305,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_ho_resid32(const double* __restrict_
         acc += r.y * r.y;
     }
     const double s = ho_block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[bl] = s;
 }
 
 // mixed precision: u += e (the FP32 correction)
