@@ -53,6 +53,46 @@ __global__ void k_kernel_direct(double* __restrict__ T, int p0, int p1, int p2, 
     T[idx] = acc / 8.0;
 }
 
+// T is even in each displacement component (a radial function; the sub-cell centres and the
+// child-pair weights are symmetric), so on a grid with even extents one octant of displacements
+// c in [0, P/2] per axis is evaluated and written to its mirror images: index c and, for
+// 0 < c < P/2, index P - c (index P/2 holds -P/2, whose value is that of +P/2).  An eighth of the
+// evaluations, the same values up to the order of the sums.
+__device__ __forceinline__ void write_mirrors(double* __restrict__ T, int p0, int p1, int p2, int cx, int cy, int cz,
+                                              double v) {
+    const int xs[2] = {cx, p0 - cx}, ys[2] = {cy, p1 - cy}, zs[2] = {cz, p2 - cz};
+    const int nx = (cx > 0 && 2 * cx != p0) ? 2 : 1, ny = (cy > 0 && 2 * cy != p1) ? 2 : 1,
+              nz = (cz > 0 && 2 * cz != p2) ? 2 : 1;
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < ny; ++b)
+            for (int c = 0; c < nz; ++c) T[((size_t)xs[a] * p1 + ys[b]) * p2 + zs[c]] = v;
+}
+
+__global__ void k_kernel_direct_oct(double* __restrict__ T, int p0, int p1, int p2, double h,
+                                    const double* __restrict__ table, double dr, int subgrid) {
+    const int q1 = p1 / 2 + 1, q2 = p2 / 2 + 1;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)(p0 / 2 + 1) * q1 * q2) return;
+    int cx, cy, cz;
+    unflat(idx, q1, q2, cx, cy, cz);
+    const double dx = (double)cx * h, dy = (double)cy * h, dz = (double)cz * h;
+    double v;
+    if (!subgrid) {
+        v = radial_at(table, dr, sqrt(dx * dx + dy * dy + dz * dz));
+    } else {
+        double acc = 0.0;
+        for (int sx = 0; sx < 2; ++sx)
+            for (int sy = 0; sy < 2; ++sy)
+                for (int sz = 0; sz < 2; ++sz) {
+                    const double X = dx + (sx ? 0.25 : -0.25) * h, Y = dy + (sy ? 0.25 : -0.25) * h,
+                                 Z = dz + (sz ? 0.25 : -0.25) * h;
+                    acc = acc + radial_at(table, dr, sqrt(X * X + Y * Y + Z * Z));
+                }
+        v = acc / 8.0;
+    }
+    write_mirrors(T, p0, p1, p2, cx, cy, cz, v);
+}
+
 // coarse kernel from the finer level's grid: the 1/4, 1/2, 1/4 child-pair mean over the fine
 // displacements 2J - 1, 2J, 2J + 1 where all exist (|J| <= Pf / 4 - 1 per axis), T(|D|) elsewhere
 __global__ void k_kernel_restrict(double* __restrict__ Tc, int p0, int p1, int p2, double h,
@@ -82,6 +122,38 @@ __global__ void k_kernel_restrict(double* __restrict__ Tc, int p0, int p1, int p
         }
     }
     Tc[idx] = acc;
+}
+
+// k_kernel_restrict on one octant (even extents), written to the mirror images
+__global__ void k_kernel_restrict_oct(double* __restrict__ Tc, int p0, int p1, int p2, double h,
+                                      const double* __restrict__ Tf, int f0, int f1, int f2,
+                                      const double* __restrict__ table, double dr) {
+    const int q1 = p1 / 2 + 1, q2 = p2 / 2 + 1;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)(p0 / 2 + 1) * q1 * q2) return;
+    int Jx, Jy, Jz;
+    unflat(idx, q1, q2, Jx, Jy, Jz);
+    const bool inside = Jx <= f0 / 4 - 1 && Jy <= f1 / 4 - 1 && Jz <= f2 / 4 - 1;
+    double v;
+    if (!inside) {
+        const double dx = (double)Jx * h, dy = (double)Jy * h, dz = (double)Jz * h;
+        v = radial_at(table, dr, sqrt(dx * dx + dy * dy + dz * dz));
+    } else {
+        const double w[3] = {0.25, 0.5, 0.25};
+        double acc = 0.0;
+        for (int sx = -1; sx <= 1; ++sx) {
+            const int ix = (2 * Jx + sx + f0) % f0;
+            for (int sy = -1; sy <= 1; ++sy) {
+                const int iy = (2 * Jy + sy + f1) % f1;
+                for (int sz = -1; sz <= 1; ++sz) {
+                    const int iz = (2 * Jz + sz + f2) % f2;
+                    acc = acc + ((w[sx + 1] * w[sy + 1]) * w[sz + 1]) * Tf[((size_t)ix * f1 + iy) * f2 + iz];
+                }
+            }
+        }
+        v = acc;
+    }
+    write_mirrors(Tc, p0, p1, p2, Jx, Jy, Jz, v);
 }
 
 __global__ void k_divide(double* __restrict__ out, const double* __restrict__ in, size_t n, double d) {
@@ -247,17 +319,30 @@ __global__ void k_restrict_add(double* __restrict__ parent, Box B, const double*
 
 }  // namespace
 
+static bool all_even(const int* P) { return P[0] % 2 == 0 && P[1] % 2 == 0 && P[2] % 2 == 0; }
+static size_t octant(const int* P) { return (size_t)(P[0] / 2 + 1) * (P[1] / 2 + 1) * (P[2] / 2 + 1); }
+
 hipError_t launch_kernel_direct(double* T, const int* P, double h, const double* table, double dr, int subgrid,
                                 hipStream_t st) {
-    const size_t n = (size_t)P[0] * P[1] * P[2];
-    k_kernel_direct<<<grid_for(n), kBlock, 0, st>>>(T, P[0], P[1], P[2], h, table, dr, subgrid);
+    if (all_even(P)) {
+        k_kernel_direct_oct<<<grid_for(octant(P)), kBlock, 0, st>>>(T, P[0], P[1], P[2], h, table, dr, subgrid);
+    } else {
+        const size_t n = (size_t)P[0] * P[1] * P[2];
+        k_kernel_direct<<<grid_for(n), kBlock, 0, st>>>(T, P[0], P[1], P[2], h, table, dr, subgrid);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_kernel_restrict(double* Tc, const int* P, double h, const double* Tf, const int* Pf,
                                   const double* table, double dr, hipStream_t st) {
-    const size_t n = (size_t)P[0] * P[1] * P[2];
-    k_kernel_restrict<<<grid_for(n), kBlock, 0, st>>>(Tc, P[0], P[1], P[2], h, Tf, Pf[0], Pf[1], Pf[2], table, dr);
+    if (all_even(P)) {
+        k_kernel_restrict_oct<<<grid_for(octant(P)), kBlock, 0, st>>>(Tc, P[0], P[1], P[2], h, Tf, Pf[0], Pf[1],
+                                                                     Pf[2], table, dr);
+    } else {
+        const size_t n = (size_t)P[0] * P[1] * P[2];
+        k_kernel_restrict<<<grid_for(n), kBlock, 0, st>>>(Tc, P[0], P[1], P[2], h, Tf, Pf[0], Pf[1], Pf[2], table,
+                                                          dr);
+    }
     return hipGetLastError();
 }
 
