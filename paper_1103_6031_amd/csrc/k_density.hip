@@ -244,40 +244,54 @@ __global__ void k_conv_prep(double* __restrict__ a, double* __restrict__ b, doub
 }
 
 // Section 2.3.4: conservative tri-cubic interpolation of the parent field U (box B gives the
-// parent cell of the patch's first child) onto the patch (n per axis), one thread per parent cell
+// parent cell of the patch's first child) onto the patch (n per axis), one thread per parent cell.
+// Child (cx, cy, cz) takes the cubic Lagrange interpolant through the 4 parent nodes on its side
+// along each axis (x innermost, then y, then z).  The 8 children share the 5^3 parents around the
+// cell, so the thread walks them once: for each (oz, oy) the 5 values along x give both children's
+// x-sums, which are added into the y-sums of the children whose nodes include oy, and those, once
+// complete for an oz, into the z-sums: the same operations in the same order for every child.
 __global__ void k_interp_cons(double* __restrict__ out, int n0, int n1, int n2, const double* __restrict__ U, Box B) {
     const int m0 = n0 / 2, m1 = n1 / 2, m2 = n2 / 2;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)m0 * m1 * m2) return;
     int X, Y, Z;
     unflat(idx, m1, m2, X, Y, Z);
-    // cubic Lagrange weights at +1/4 through nodes -1, 0, 1, 2; the even child mirrors them
+    // cubic Lagrange weights at +1/4 through nodes -1, 0, 1, 2; the even child mirrors them: child
+    // c on an axis uses node offsets o = k - 2 + c (k = 0..3) with weight w[k] (c = 1) or w[3 - k]
     const double w[4] = {-7.0 / 128.0, 105.0 / 128.0, 35.0 / 128.0, -5.0 / 128.0};
+    auto wt = [&](int c, int k) { return c ? w[k] : w[3 - k]; };
+    double tz[2][2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) tz[a][b][c] = 0.0;
+    for (int oz = -2; oz <= 2; ++oz) {
+        double ty[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int oy = -2; oy <= 2; ++oy) {
+            double u[5];
+            for (int ox = -2; ox <= 2; ++ox) u[ox + 2] = U[box_at(B, X + ox, Y + oy, Z + oz)];
+            for (int cx = 0; cx < 2; ++cx) {
+                double tx = 0.0;
+                for (int kx = 0; kx < 4; ++kx) tx = tx + wt(cx, kx) * u[kx + cx];   // ox = kx - 2 + cx
+                for (int cy = 0; cy < 2; ++cy) {
+                    const int ky = oy + 2 - cy;
+                    if (ky >= 0 && ky < 4) ty[cx][cy] = ty[cx][cy] + wt(cy, ky) * tx;
+                }
+            }
+        }
+        for (int cz = 0; cz < 2; ++cz) {
+            const int kz = oz + 2 - cz;
+            if (kz < 0 || kz > 3) continue;
+            for (int cx = 0; cx < 2; ++cx)
+                for (int cy = 0; cy < 2; ++cy) tz[cx][cy][cz] = tz[cx][cy][cz] + wt(cz, kz) * ty[cx][cy];
+        }
+    }
     double v[8];
     double mean = 0.0;
     for (int cx = 0; cx < 2; ++cx)
         for (int cy = 0; cy < 2; ++cy)
             for (int cz = 0; cz < 2; ++cz) {
-                double tz = 0.0;
-                for (int kz = 0; kz < 4; ++kz) {
-                    const int oz = cz ? kz - 1 : kz - 2;          // node offset along z
-                    const double wz = cz ? w[kz] : w[3 - kz];
-                    double ty = 0.0;
-                    for (int ky = 0; ky < 4; ++ky) {
-                        const int oy = cy ? ky - 1 : ky - 2;
-                        const double wy = cy ? w[ky] : w[3 - ky];
-                        double tx = 0.0;
-                        for (int kx = 0; kx < 4; ++kx) {
-                            const int ox = cx ? kx - 1 : kx - 2;
-                            const double wx = cx ? w[kx] : w[3 - kx];
-                            tx = tx + wx * U[box_at(B, X + ox, Y + oy, Z + oz)];
-                        }
-                        ty = ty + wy * tx;
-                    }
-                    tz = tz + wz * ty;
-                }
-                v[(cx * 2 + cy) * 2 + cz] = tz;
-                mean = mean + tz;
+                v[(cx * 2 + cy) * 2 + cz] = tz[cx][cy][cz];
+                mean = mean + tz[cx][cy][cz];
             }
     const double shift = U[box_at(B, X, Y, Z)] - mean / 8.0;
     for (int cx = 0; cx < 2; ++cx)
