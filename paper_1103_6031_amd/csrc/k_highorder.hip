@@ -571,20 +571,39 @@ __device__ __forceinline__ void hoz_decode(const int* n, size_t t, int& x, int& 
     x = (int)(r / (size_t)n[1]);
 }
 
+// One thread per pair of z-neighbours (z0, z0 + 1), z0 even: exactly one of them has the colour,
+// so every lane computes one update; the pair is read and written as one 16-byte access (the
+// patch arrays are workspace arrays, 256-byte aligned, with an even z extent).  Cells whose whole
+// stencil lies inside the patch read their neighbours directly; the others through the ghost
+// layers.  The sums have the order of hoz_off, so the bits do not depend on the path.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_hoz_half(const double* __restrict__ in, double* __restrict__ out,
                                                      const double* __restrict__ f, const double* __restrict__ g,
                                                      HozPatch P, double h2, int colour) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t cells = (size_t)P.n[0] * P.n[1] * P.n[2];
-    if (t >= cells) return;
-    int x, y, z;
-    hoz_decode(P.n, t, x, y, z);
-    if (((x + y + z) & 1) != colour) {
-        out[t] = in[t];
-        return;
+    const unsigned n0 = (unsigned)P.n[0], n1 = (unsigned)P.n[1], n2 = (unsigned)P.n[2], n2h = n2 >> 1;
+    const unsigned p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n0 * n1 * n2h) return;
+    const unsigned row = p / n2h, zp = p - row * n2h;
+    const unsigned x = row / n1, y = row - x * n1, z0 = 2 * zp;
+    const unsigned q = (x + y + z0 + (unsigned)colour) & 1u;   // the pair's cell of the colour
+    const unsigned z = z0 + q;
+    const size_t t0 = (size_t)row * n2 + z0, t = t0 + q;
+    const double2 cur = *(const double2*)(in + t0);
+    double acc = 0;
+    if (x >= (unsigned)R && x + R < n0 && y >= (unsigned)R && y + R < n1 && z >= (unsigned)R && z + R < n2) {
+        const size_t sx = (size_t)n1 * n2;
+#pragma unroll
+        for (int s = 1; s <= R; ++s) {
+            const double px = in[t - s * sx] + in[t + s * sx];
+            const double py = in[t - (size_t)s * n2] + in[t + (size_t)s * n2];
+            const double pz = in[t - s] + in[t + s];
+            acc += ho_w<R>(s) * ((px + py) + pz);
+        }
+    } else {
+        acc = hoz_off<R>(in, g, P.n, (int)x, (int)y, (int)z);
     }
-    out[t] = (h2 * f[t] - hoz_off<R>(in, g, P.n, x, y, z)) / (3.0 * HoW<R>::w0);
+    const double v = (h2 * f[t] - acc) / (3.0 * HoW<R>::w0);
+    *(double2*)(out + t0) = q ? make_double2(cur.x, v) : make_double2(v, cur.y);
 }
 
 template <int R>
@@ -711,7 +730,7 @@ void launch_hoz_ghost(const double* pu, const double* u, double* g, const HozPat
 
 void launch_hoz_half(const double* in, double* out, const double* f, const double* g, const HozPatch& P, int order,
                      int colour, hipStream_t st) {
-    const int grid = grid_for((size_t)P.n[0] * P.n[1] * P.n[2]);
+    const int grid = grid_for((size_t)P.n[0] * P.n[1] * (P.n[2] / 2));   // pairs of z-neighbours
     const double h2 = P.h * P.h;
     HOZ_R(order, (k_hoz_half<1><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)),
           (k_hoz_half<2><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)),
