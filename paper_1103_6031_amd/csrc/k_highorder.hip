@@ -564,11 +564,14 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
         g[fo + ((size_t)gl * n[b] + (2 * J + jb)) * n[c] + (2 * K + kc)] = g0[gl] + delta;
 }
 
+// position t of an array of n[0] x n[1] x n[2] cells (fewer than 2^32) in natural order
 __device__ __forceinline__ void hoz_decode(const int* n, size_t t, int& x, int& y, int& z) {
-    z = (int)(t % (size_t)n[2]);
-    const size_t r = t / (size_t)n[2];
-    y = (int)(r % (size_t)n[1]);
-    x = (int)(r / (size_t)n[1]);
+    const unsigned tt = (unsigned)t, n1 = (unsigned)n[1], n2 = (unsigned)n[2];
+    const unsigned r = tt / n2;
+    z = (int)(tt - r * n2);
+    const unsigned xq = r / n1;
+    y = (int)(r - xq * n1);
+    x = (int)xq;
 }
 
 // One thread per pair of z-neighbours (z0, z0 + 1), z0 even: exactly one of them has the colour,
