@@ -473,23 +473,26 @@ __device__ __forceinline__ double hoz_off(const double* __restrict__ v, const do
     return acc;
 }
 
+// One block per row J of ghost groups of a face (blockIdx.y = face), 64 groups of 4 lanes per pass
+// over the row.  The R outside parent layers that a pass's groups read - (2R + 1) rows around J by
+// the pass's columns and R on either side - are staged in LDS once, instead of 4 (2R + 1)^2 R
+// loads per group; each lane then forms its ghost values as before, in the same order.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__ pu, const double* __restrict__ u,
                                                       double* __restrict__ g, HozPatch P, HozW W, int flux_match) {
+    constexpr int kG = kBlock / 4;            // groups per pass
+    constexpr int kW = kG + 2 * R;            // staged columns
+    __shared__ double S[R][2 * R + 1][kW];
     const int* n = P.n;
     const int face = (int)blockIdx.y;
     const int a = face >> 1, side = face & 1;
     const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
-    const unsigned nc2 = (unsigned)n[c] / 2;
-    const unsigned lane = blockIdx.x * blockDim.x + threadIdx.x;
-    const unsigned t = lane >> 2, q = lane & 3;
-    // every lane of a group takes part in the shuffles; lanes past the face repeat the last group
-    const unsigned ngroups = ((unsigned)n[b] / 2) * nc2;
-    const bool live = t < ngroups;
-    const unsigned tg = live ? t : ngroups - 1;
-    const int J = (int)(tg / nc2), K = (int)(tg - (unsigned)J * nc2);
-    const int jb = (int)(q >> 1), kc = (int)(q & 1);
-    const int Jp = P.off[b] + J, Kp = P.off[c] + K;
+    const int J = (int)blockIdx.x;
+    if (J >= n[b] / 2) return;                // rows of this face (the grid covers the longest)
+    const int nc2 = n[c] / 2;
+    const int tg = (int)threadIdx.x >> 2, q = (int)threadIdx.x & 3;
+    const int jb = q >> 1, kc = q & 1;
+    const int Jp = P.off[b] + J;
     auto parent = [&](int ia, int ib, int ic) {
         int qq[3];
         qq[a] = ia;
@@ -499,69 +502,85 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
             for (int k = 0; k < 3; ++k) qq[k] = qq[k] < 0 ? qq[k] + P.pn[k] : (qq[k] >= P.pn[k] ? qq[k] - P.pn[k] : qq[k]);
         return pu[hoz_nat(P.pn, qq[0], qq[1], qq[2])];
     };
-    // parallel step on each outside parent layer (layer k at normal index on_k)
-    double A[R], O[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int on = side ? P.off[a] + n[a] / 2 + k : P.off[a] - 1 - k;
-        double acc = 0.0;
-        for (int dc = 0; dc <= 2 * R; ++dc) {
-            double ab = 0.0;
-            for (int db = 0; db <= 2 * R; ++db) ab += W.par[jb][db] * parent(on, Jp + db - R, Kp + dc - R);
-            acc += W.par[kc][dc] * ab;
+    for (int K0 = 0; K0 < nc2; K0 += kG) {
+        const int cnt = nc2 - K0 < kG ? nc2 - K0 : kG;
+        const int Kp0 = P.off[c] + K0;
+        if (K0) __syncthreads();              // the previous pass has read S
+        const int nst = R * (2 * R + 1) * (cnt + 2 * R);
+        for (int i = (int)threadIdx.x; i < nst; i += (int)blockDim.x) {
+            const int col = i % (cnt + 2 * R), r = i / (cnt + 2 * R);
+            const int db = r % (2 * R + 1), k = r / (2 * R + 1);
+            const int on = side ? P.off[a] + n[a] / 2 + k : P.off[a] - 1 - k;
+            S[k][db][col] = parent(on, Jp + db - R, Kp0 + col - R);
         }
-        A[k] = acc;
-        O[k] = parent(on, Jp, Kp);
+        __syncthreads();
+        // every lane of a group takes part in the shuffles; lanes past the row repeat its last group
+        const bool live = tg < cnt;
+        const int Kl = live ? tg : cnt - 1;
+        const int K = K0 + Kl;
+        double A[R], O[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            double acc = 0.0;
+            for (int dc = 0; dc <= 2 * R; ++dc) {
+                double ab = 0.0;
+                for (int db = 0; db <= 2 * R; ++db) ab += W.par[jb][db] * S[k][db][Kl + dc];
+                acc += W.par[kc][dc] * ab;
+            }
+            A[k] = acc;
+            O[k] = S[k][R][Kl + R];
+        }
+        // fine cells of the column inwards from the face: layers 0 .. 2R - 1
+        double v[2 * R];
+#pragma unroll
+        for (int i = 0; i < 2 * R; ++i) {
+            int p3[3];
+            p3[a] = side ? n[a] - 1 - i : i;
+            p3[b] = 2 * J + jb;
+            p3[c] = 2 * K + kc;
+            v[i] = u[hoz_nat(n, p3[0], p3[1], p3[2])];
+        }
+        double g0[R];
+#pragma unroll
+        for (int gl = 0; gl < R; ++gl) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < R; ++m) acc += W.nor[gl][m] * A[m];
+#pragma unroll
+            for (int i = 0; i <= R; ++i) acc += W.nor[gl][R + i] * v[i];
+            g0[gl] = acc;
+        }
+        double delta = 0.0;
+        if (flux_match) {
+            const double h = P.h;
+            double ff = 0.0;
+#pragma unroll
+            for (int m = 0; m < R; ++m) ff += W.F[m] * g0[R - 1 - m];
+#pragma unroll
+            for (int i = 0; i < R; ++i) ff += W.F[R + i] * v[i];
+            ff /= h;
+            const int base = (int)(threadIdx.x & 63) & ~3;
+            auto mean4 = [&](double x) {
+                const double x0 = __shfl(x, base, 64), x1 = __shfl(x, base + 1, 64);
+                const double x2 = __shfl(x, base + 2, 64), x3 = __shfl(x, base + 3, 64);
+                return ((x0 + x1) + (x2 + x3)) * 0.25;
+            };
+            const double mff = mean4(ff);
+            double fc = 0.0;
+#pragma unroll
+            for (int m = 0; m < R; ++m) fc += W.F[m] * O[R - 1 - m];
+#pragma unroll
+            for (int k = 0; k < R; ++k) fc += W.F[R + k] * (0.5 * mean4(v[2 * k] + v[2 * k + 1]));
+            fc /= 2.0 * h;
+            delta = (fc - mff) * h / W.S;
+        }
+        if (live) {
+            const size_t fo = hoz_face_off(n, R, face);
+#pragma unroll
+            for (int gl = 0; gl < R; ++gl)
+                g[fo + ((size_t)gl * n[b] + (2 * J + jb)) * n[c] + (2 * K + kc)] = g0[gl] + delta;
+        }
     }
-    // fine cells of the column inwards from the face: layers 0 .. 2R - 1
-    double v[2 * R];
-#pragma unroll
-    for (int i = 0; i < 2 * R; ++i) {
-        int p3[3];
-        p3[a] = side ? n[a] - 1 - i : i;
-        p3[b] = 2 * J + jb;
-        p3[c] = 2 * K + kc;
-        v[i] = u[hoz_nat(n, p3[0], p3[1], p3[2])];
-    }
-    double g0[R];
-#pragma unroll
-    for (int gl = 0; gl < R; ++gl) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < R; ++m) acc += W.nor[gl][m] * A[m];
-#pragma unroll
-        for (int i = 0; i <= R; ++i) acc += W.nor[gl][R + i] * v[i];
-        g0[gl] = acc;
-    }
-    double delta = 0.0;
-    if (flux_match) {
-        const double h = P.h;
-        double ff = 0.0;
-#pragma unroll
-        for (int m = 0; m < R; ++m) ff += W.F[m] * g0[R - 1 - m];
-#pragma unroll
-        for (int i = 0; i < R; ++i) ff += W.F[R + i] * v[i];
-        ff /= h;
-        const int base = (int)(threadIdx.x & 63) & ~3;
-        auto mean4 = [&](double x) {
-            const double x0 = __shfl(x, base, 64), x1 = __shfl(x, base + 1, 64);
-            const double x2 = __shfl(x, base + 2, 64), x3 = __shfl(x, base + 3, 64);
-            return ((x0 + x1) + (x2 + x3)) * 0.25;
-        };
-        const double mff = mean4(ff);
-        double fc = 0.0;
-#pragma unroll
-        for (int m = 0; m < R; ++m) fc += W.F[m] * O[R - 1 - m];
-#pragma unroll
-        for (int k = 0; k < R; ++k) fc += W.F[R + k] * (0.5 * mean4(v[2 * k] + v[2 * k + 1]));
-        fc /= 2.0 * h;
-        delta = (fc - mff) * h / W.S;
-    }
-    if (!live) return;
-    const size_t fo = hoz_face_off(n, R, face);
-#pragma unroll
-    for (int gl = 0; gl < R; ++gl)
-        g[fo + ((size_t)gl * n[b] + (2 * J + jb)) * n[c] + (2 * K + kc)] = g0[gl] + delta;
 }
 
 // position t of an array of n[0] x n[1] x n[2] cells (fewer than 2^32) in natural order
@@ -723,9 +742,8 @@ __global__ __launch_bounds__(kBlock) void k_hoz_psum(const double* __restrict__ 
 
 void launch_hoz_ghost(const double* pu, const double* u, double* g, const HozPatch& P, const HozW& W, int order,
                       int flux_match, hipStream_t st) {
-    const size_t most = std::max({(size_t)(P.n[1] / 2) * (P.n[2] / 2), (size_t)(P.n[0] / 2) * (P.n[2] / 2),
-                                  (size_t)(P.n[0] / 2) * (P.n[1] / 2)});
-    const dim3 grid(grid_for(4 * most), 6);
+    // one block per row of groups: n[b] / 2 rows on a face normal to a (b = 1 for a = 0, else 0)
+    const dim3 grid((unsigned)std::max(P.n[1] / 2, P.n[0] / 2), 6);
     HOZ_R(order, (k_hoz_ghost<1><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)),
           (k_hoz_ghost<2><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)),
           (k_hoz_ghost<3><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)));
