@@ -628,6 +628,56 @@ __global__ __launch_bounds__(kBlock) void k_hoz_half(const double* __restrict__ 
     *(double2*)(out + t0) = q ? make_double2(cur.x, v) : make_double2(v, cur.y);
 }
 
+// The same half-sweep with the y and z neighbours from LDS (as k_ho_half_lds on periodic levels):
+// a block owns rows y0 .. y0 + kHoTy - 1 of one x plane and stages them with R rows on each side in
+// y and R cells on each side in z, taking what lies outside the patch from the ghost layers (the
+// corners, which no stencil reads, are zero); the 2R x-neighbours and f come from memory.  The
+// sums have the order of hoz_off, so the bits are those of k_hoz_half.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_hoz_half_lds(const double* __restrict__ in, double* __restrict__ out,
+                                                         const double* __restrict__ f, const double* __restrict__ g,
+                                                         HozPatch P, double h2, int colour) {
+    extern __shared__ __align__(16) unsigned char hz_smem[];
+    double* rows = (double*)hz_smem;           // [kHoTy + 2R][n2 + 2R]
+    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+    const int W = n2 + 2 * R;
+    const int tiles = (n1 + kHoTy - 1) / kHoTy;
+    const int x = (int)blockIdx.x / tiles, y0 = ((int)blockIdx.x - x * tiles) * kHoTy;
+    const int ny = n1 - y0 < kHoTy ? n1 - y0 : kHoTy;
+    const int nst = (ny + 2 * R) * W;
+    for (int i = (int)threadIdx.x; i < nst; i += (int)blockDim.x) {
+        const int r = i / W, cz = i - r * W;
+        const int y = y0 + r - R, z = cz - R;
+        const bool yin = y >= 0 && y < n1, zin = z >= 0 && z < n2;
+        double v = 0.0;
+        if (yin && zin) v = in[hoz_nat(P.n, x, y, z)];
+        else if (yin || zin) v = hoz_val(in, g, P.n, R, x, y, z);
+        rows[i] = v;
+    }
+    __syncthreads();
+    const int n2h = n2 >> 1;
+    const size_t sx = (size_t)n1 * n2;
+    for (int t = (int)threadIdx.x; t < ny * n2h; t += (int)blockDim.x) {
+        const int ry = t / n2h, zp = t - ry * n2h;
+        const int y = y0 + ry, z0 = 2 * zp;
+        const int q = (x + y + z0 + colour) & 1, z = z0 + q;
+        const double* row = rows + (ry + R) * W + R;   // row[k] = value at (x, y, k)
+        const size_t i0 = hoz_nat(P.n, x, y, z0), i = i0 + q;
+        double acc = 0;
+#pragma unroll
+        for (int s = 1; s <= R; ++s) {
+            const double xm = x - s >= 0 ? in[i - s * sx] : hoz_val(in, g, P.n, R, x - s, y, z);
+            const double xp = x + s < n0 ? in[i + s * sx] : hoz_val(in, g, P.n, R, x + s, y, z);
+            const double px = xm + xp;
+            const double py = row[z - s * W] + row[z + s * W];
+            const double pz = row[z - s] + row[z + s];
+            acc += ho_w<R>(s) * ((px + py) + pz);
+        }
+        const double v = (h2 * f[i] - acc) / (3.0 * HoW<R>::w0);
+        *(double2*)(out + i0) = q ? make_double2(row[z0], v) : make_double2(v, row[z0 + 1]);
+    }
+}
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_hoz_rr(const double* __restrict__ u, const double* __restrict__ f,
                                                    const double* __restrict__ g, HozPatch P, double h2,
@@ -751,8 +801,17 @@ void launch_hoz_ghost(const double* pu, const double* u, double* g, const HozPat
 
 void launch_hoz_half(const double* in, double* out, const double* f, const double* g, const HozPatch& P, int order,
                      int colour, hipStream_t st) {
-    const int grid = grid_for((size_t)P.n[0] * P.n[1] * (P.n[2] / 2));   // pairs of z-neighbours
     const double h2 = P.h * P.h;
+    const int R = order / 2;
+    const size_t lds = (size_t)(kHoTy + 2 * R) * (P.n[2] + 2 * R) * sizeof(double);
+    if (lds <= 64u * 1024u) {   // rows staged in LDS (within the default limit: n_z up to 570)
+        const unsigned grid = (unsigned)P.n[0] * (unsigned)((P.n[1] + kHoTy - 1) / kHoTy);
+        HOZ_R(order, (k_hoz_half_lds<1><<<grid, kBlock, lds, st>>>(in, out, f, g, P, h2, colour)),
+              (k_hoz_half_lds<2><<<grid, kBlock, lds, st>>>(in, out, f, g, P, h2, colour)),
+              (k_hoz_half_lds<3><<<grid, kBlock, lds, st>>>(in, out, f, g, P, h2, colour)));
+        return;
+    }
+    const int grid = grid_for((size_t)P.n[0] * P.n[1] * (P.n[2] / 2));   // pairs of z-neighbours
     HOZ_R(order, (k_hoz_half<1><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)),
           (k_hoz_half<2><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)),
           (k_hoz_half<3><<<grid, kBlock, 0, st>>>(in, out, f, g, P, h2, colour)));
