@@ -781,6 +781,62 @@ __global__ __launch_bounds__(kBlock) void k_hoz_psum(const double* __restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// MODE 1 of k_hoz_psum with the y and z neighbours from LDS: each block takes tiles of kHoTy rows
+// of one x plane in turn (tile blockIdx.x, then + gridDim.x, ...) and stages them as
+// k_hoz_half_lds does; every cell outside the covered box adds r^2, r = f - L u with the operations
+// of hoz_off.  The partial sums run over other cells than in k_hoz_psum, so their last bits differ.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_hoz_psum_lds(const double* __restrict__ v, const double* __restrict__ f,
+                                                         const double* __restrict__ g, HozPatch P, int lo0, int lo1,
+                                                         int lo2, int c0, int c1, int c2, double h2,
+                                                         double* __restrict__ part) {
+    extern __shared__ __align__(16) unsigned char hz_smem[];
+    double* rows = (double*)hz_smem;           // [kHoTy + 2R][n2 + 2R]
+    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+    const int W = n2 + 2 * R;
+    const int tiles = (n1 + kHoTy - 1) / kHoTy;
+    const size_t sx = (size_t)n1 * n2;
+    const double w0x3 = 3.0 * HoW<R>::w0;
+    double acc = 0.0;
+    for (int tile = (int)blockIdx.x; tile < n0 * tiles; tile += (int)gridDim.x) {
+        const int x = tile / tiles, y0 = (tile - x * tiles) * kHoTy;
+        const int ny = n1 - y0 < kHoTy ? n1 - y0 : kHoTy;
+        __syncthreads();                       // the previous tile has been read
+        const int nst = (ny + 2 * R) * W;
+        for (int i = (int)threadIdx.x; i < nst; i += (int)blockDim.x) {
+            const int r = i / W, cz = i - r * W;
+            const int y = y0 + r - R, z = cz - R;
+            const bool yin = y >= 0 && y < n1, zin = z >= 0 && z < n2;
+            double val = 0.0;
+            if (yin && zin) val = v[hoz_nat(P.n, x, y, z)];
+            else if (yin || zin) val = hoz_val(v, g, P.n, R, x, y, z);
+            rows[i] = val;
+        }
+        __syncthreads();
+        const bool xcov = x >= lo0 && x < lo0 + c0;
+        for (int t = (int)threadIdx.x; t < ny * n2; t += (int)blockDim.x) {
+            const int ry = t / n2, z = t - ry * n2, y = y0 + ry;
+            if (xcov && y >= lo1 && y < lo1 + c1 && z >= lo2 && z < lo2 + c2) continue;
+            const double* row = rows + (ry + R) * W + R;
+            const size_t i = hoz_nat(P.n, x, y, z);
+            double off = 0;
+#pragma unroll
+            for (int s = 1; s <= R; ++s) {
+                const double xm = x - s >= 0 ? v[i - s * sx] : hoz_val(v, g, P.n, R, x - s, y, z);
+                const double xp = x + s < n0 ? v[i + s * sx] : hoz_val(v, g, P.n, R, x + s, y, z);
+                const double px = xm + xp;
+                const double py = row[z - s * W] + row[z + s * W];
+                const double pz = row[z - s] + row[z + s];
+                off += ho_w<R>(s) * ((px + py) + pz);
+            }
+            const double val = f[i] - (off + w0x3 * row[z]) / h2;
+            acc += val * val;
+        }
+    }
+    const double s = ho_block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 }  // namespace
 
 #define HOZ_R(order, STMT1, STMT2, STMT3) \
@@ -855,8 +911,18 @@ void launch_hoz_psum(int mode, const double* v, const double* f, const double* g
     const int nb = kHozParts;
     const double h2 = h * h;
 #define HOZ_PS_ARGS v, f, g, n[0], n[1], n[2], lo[0], lo[1], lo[2], cn[0], cn[1], cn[2], h2, part
+    const int R = order / 2;
+    const size_t lds = (size_t)(kHoTy + 2 * R) * (n[2] + 2 * R) * sizeof(double);
     if (mode == 0) k_hoz_psum<1, 0><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS);
-    else if (mode == 1)
+    else if (mode == 1 && lds <= 64u * 1024u) {
+        HozPatch P{};
+        for (int a = 0; a < 3; ++a) P.n[a] = n[a];
+#define HOZ_PL_ARGS v, f, g, P, lo[0], lo[1], lo[2], cn[0], cn[1], cn[2], h2, part
+        HOZ_R(order, (k_hoz_psum_lds<1><<<nb, kBlock, lds, st>>>(HOZ_PL_ARGS)),
+              (k_hoz_psum_lds<2><<<nb, kBlock, lds, st>>>(HOZ_PL_ARGS)),
+              (k_hoz_psum_lds<3><<<nb, kBlock, lds, st>>>(HOZ_PL_ARGS)));
+#undef HOZ_PL_ARGS
+    } else if (mode == 1)
         HOZ_R(order, (k_hoz_psum<1, 1><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)),
               (k_hoz_psum<2, 1><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)),
               (k_hoz_psum<3, 1><<<nb, kBlock, 0, st>>>(HOZ_PS_ARGS)));
