@@ -20,6 +20,10 @@ LAYOUTS = {
     "one": (16, [((16, 16, 16), (4, 4, 4))]),
     "rect": (16, [((12, 16, 20), (5, 3, 2))]),
     "deep": (32, [((32, 32, 32), (8, 8, 8)), ((24, 16, 32), (4, 8, 8)), ((12, 12, 12), (5, 6, 8))]),
+    # long thin patches: at order 6 the rows of the 584-long finest patch exceed the 64 KB of LDS a
+    # block may stage, so its half-sweep and residual norm read every neighbour from memory, while
+    # the 484-long patch above it stages its rows
+    "long": (128, [((16, 16, 250), (56, 56, 3)), ((16, 16, 484), (4, 4, 4)), ((8, 8, 584), (4, 4, 4))]),
 }
 
 
@@ -46,7 +50,7 @@ def _crms(H, a, b):
 
 
 @pytest.mark.parametrize("order", [2, 4, 6])
-@pytest.mark.parametrize("name", ["one", "rect", "deep"])
+@pytest.mark.parametrize("name", ["one", "rect", "deep", "long"])
 def test_ghost_layers_match_oracle(mg, name, order):
     H, Hg, _ = _case(mg, name)
     R = order // 2
@@ -69,7 +73,7 @@ def test_ghost_layers_match_oracle(mg, name, order):
 
 
 @pytest.mark.parametrize("order", [4, 6])
-@pytest.mark.parametrize("name", ["one", "rect", "deep"])
+@pytest.mark.parametrize("name", ["one", "rect", "deep", "long"])
 @pytest.mark.parametrize("cycles", [1, 2])
 def test_fixed_cycle_iterates_match_oracle(mg, name, order, cycles):
     H, Hg, f = _case(mg, name)
