@@ -476,13 +476,17 @@ __device__ __forceinline__ double hoz_off(const double* __restrict__ v, const do
 // One block per row J of ghost groups of a face (blockIdx.y = face), 64 groups of 4 lanes per pass
 // over the row.  The R outside parent layers that a pass's groups read - (2R + 1) rows around J by
 // the pass's columns and R on either side - are staged in LDS once, instead of 4 (2R + 1)^2 R
-// loads per group; each lane then forms its ghost values as before, in the same order.
+// loads per group.  The parallel step is a tensor product: its sums along b (one per layer, fine
+// row parity jb and staged column) go to LDS in a second stage, and each lane then takes 2R + 1
+// of them along c, so every value is formed with the operations of the direct double sum.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__ pu, const double* __restrict__ u,
                                                       double* __restrict__ g, HozPatch P, HozW W, int flux_match) {
     constexpr int kG = kBlock / 4;            // groups per pass
     constexpr int kW = kG + 2 * R;            // staged columns
+    constexpr int kIt = (R * (2 * R + 1) * kW + kBlock - 1) / kBlock;   // staging loads per lane
     __shared__ double S[R][2 * R + 1][kW];
+    __shared__ double T[R][2][kW];            // T[k][jb][col] = sum_db par[jb][db] S[k][db][col]
     const int* n = P.n;
     const int face = (int)blockIdx.y;
     const int a = face >> 1, side = face & 1;
@@ -505,32 +509,26 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
     for (int K0 = 0; K0 < nc2; K0 += kG) {
         const int cnt = nc2 - K0 < kG ? nc2 - K0 : kG;
         const int Kp0 = P.off[c] + K0;
-        if (K0) __syncthreads();              // the previous pass has read S
-        const int nst = R * (2 * R + 1) * (cnt + 2 * R);
-        for (int i = (int)threadIdx.x; i < nst; i += (int)blockDim.x) {
-            const int col = i % (cnt + 2 * R), r = i / (cnt + 2 * R);
-            const int db = r % (2 * R + 1), k = r / (2 * R + 1);
-            const int on = side ? P.off[a] + n[a] / 2 + k : P.off[a] - 1 - k;
-            S[k][db][col] = parent(on, Jp + db - R, Kp0 + col - R);
-        }
-        __syncthreads();
+        const int ws = cnt + 2 * R;            // staged columns of this pass
+        const int nst = R * (2 * R + 1) * ws;
         // every lane of a group takes part in the shuffles; lanes past the row repeat its last group
         const bool live = tg < cnt;
         const int Kl = live ? tg : cnt - 1;
         const int K = K0 + Kl;
-        double A[R], O[R];
+        // all loads of the pass first: the staged parents, then the fine cells of the column
+        // inwards from the face (layers 0 .. 2R - 1)
+        double st[kIt];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            double acc = 0.0;
-            for (int dc = 0; dc <= 2 * R; ++dc) {
-                double ab = 0.0;
-                for (int db = 0; db <= 2 * R; ++db) ab += W.par[jb][db] * S[k][db][Kl + dc];
-                acc += W.par[kc][dc] * ab;
+        for (int it = 0; it < kIt; ++it) {
+            const int i = (int)threadIdx.x + it * kBlock;
+            st[it] = 0.0;
+            if (i < nst) {
+                const int col = i % ws, r = i / ws;
+                const int db = r % (2 * R + 1), k = r / (2 * R + 1);
+                const int on = side ? P.off[a] + n[a] / 2 + k : P.off[a] - 1 - k;
+                st[it] = parent(on, Jp + db - R, Kp0 + col - R);
             }
-            A[k] = acc;
-            O[k] = S[k][R][Kl + R];
         }
-        // fine cells of the column inwards from the face: layers 0 .. 2R - 1
         double v[2 * R];
 #pragma unroll
         for (int i = 0; i < 2 * R; ++i) {
@@ -539,6 +537,33 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
             p3[b] = 2 * J + jb;
             p3[c] = 2 * K + kc;
             v[i] = u[hoz_nat(n, p3[0], p3[1], p3[2])];
+        }
+        if (K0) __syncthreads();              // the previous pass has read S and T
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int i = (int)threadIdx.x + it * kBlock;
+            if (i < nst) {
+                const int col = i % ws, r = i / ws;
+                S[r / (2 * R + 1)][r % (2 * R + 1)][col] = st[it];
+            }
+        }
+        __syncthreads();
+        for (int i = (int)threadIdx.x; i < R * 2 * ws; i += (int)blockDim.x) {
+            const int col = i % ws, r = i / ws, pj = r & 1, k = r >> 1;
+            double ab = 0.0;
+#pragma unroll
+            for (int db = 0; db <= 2 * R; ++db) ab += W.par[pj][db] * S[k][db][col];
+            T[k][pj][col] = ab;
+        }
+        __syncthreads();
+        double A[R], O[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int dc = 0; dc <= 2 * R; ++dc) acc += W.par[kc][dc] * T[k][jb][Kl + dc];
+            A[k] = acc;
+            O[k] = S[k][R][Kl + R];
         }
         double g0[R];
 #pragma unroll
