@@ -370,6 +370,75 @@ __global__ void k_rbgs_ghost(T* __restrict__ u, const T* __restrict__ f, const T
     u[r0 + own + j] = (s - h2 * f[r0 + own + j]) / T(6);
 }
 
+// k_rbgs_ghost on runs of W cells of the colour in one half-row (W = 4 in FP32, 2 in FP64), as
+// run_rbgs_vec on periodic levels: the x- and y-neighbour runs, f and the other colour's entries
+// of the own row are 16-byte loads.  In rows on a face the neighbours outside the patch come from
+// that face's ghosts (the run's cells sit at every second z), and the two ends of a row from the
+// z faces.  Half-rows hold a multiple of W cells and the arrays are 16-byte aligned.  Each cell
+// has the operations of k_rbgs_ghost, so the bits are the same.
+template <class T>
+__global__ void k_rbgs_ghost_vec(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g, Lay L, T h2,
+                                 int colour) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
+    const Dims d = L.d;
+    const unsigned nzh = (unsigned)d.z >> 1;
+    const unsigned ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= (unsigned)d.x * d.y * (nzh / W)) return;
+    const unsigned t = ch * W;                 // first cell of the run in the colour's order
+    const unsigned row = L.dzh.div(t);
+    const unsigned j0 = t - row * nzh;
+    const unsigned xq = L.dy.div(row);
+    const int y = (int)(row - xq * (unsigned)d.y), x = (int)xq;
+    const unsigned q = (unsigned)(x + y + colour) & 1u;
+    const unsigned own = colour ? nzh : 0u, oth = colour ? 0u : nzh;
+    const unsigned rs = (unsigned)d.z, r0 = row * rs;
+    const unsigned zb = 2 * j0 + q;            // z of the run's cell k is zb + 2k
+    auto face_run = [&](int face, size_t line) {
+        const T* p = g + ghost_face_offset(d, face) + line + zb;
+        T v[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) v[k] = p[2 * k];
+        if constexpr (W == 4) return V{v[0], v[1], v[2], v[3]};
+        else return V{v[0], v[1]};
+    };
+    const V C = *(const V*)(u + r0 + oth + j0);
+    const V F = *(const V*)(f + r0 + own + j0);
+    // the z-neighbour outside the run: entry j0 - 1 (q = 0) or j0 + W (q = 1) of the other colour,
+    // or the z face's ghost at the ends of the row (one load from either address)
+    const bool zin = q ? j0 + W < nzh : j0 > 0;
+    const T* ep = zin ? u + (r0 + oth + (q ? j0 + W : j0 - 1))
+                      : g + ghost_face_offset(d, 4 + (int)q) + (size_t)x * d.y + y;
+    const T edge = *ep;
+    auto sweep = [&](const V& XM, const V& XP, const V& YM, const V& YP) {
+        T out[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const T zm = q ? lane<T>(C, k) : (k == 0 ? edge : lane<T>(C, k - 1));
+            const T zp = q ? (k == W - 1 ? edge : lane<T>(C, k + 1)) : lane<T>(C, k);
+            const T s = ((lane<T>(XM, k) + lane<T>(XP, k)) + (lane<T>(YM, k) + lane<T>(YP, k))) + (zm + zp);
+            out[k] = (s - h2 * lane<T>(F, k)) / T(6);
+        }
+        V o;
+        if constexpr (W == 4) o = V{out[0], out[1], out[2], out[3]};
+        else o = V{out[0], out[1]};
+        *(V*)(u + r0 + own + j0) = o;
+    };
+    if (x > 0 && x < d.x - 1 && y > 0 && y < d.y - 1) {   // rows off the x and y faces: no branch
+        const V XM = *(const V*)(u + r0 - (unsigned)d.y * rs + oth + j0);
+        const V XP = *(const V*)(u + r0 + (unsigned)d.y * rs + oth + j0);
+        const V YM = *(const V*)(u + r0 - rs + oth + j0);
+        const V YP = *(const V*)(u + r0 + rs + oth + j0);
+        sweep(XM, XP, YM, YP);
+        return;
+    }
+    const V XM = x > 0 ? *(const V*)(u + r0 - (unsigned)d.y * rs + oth + j0) : face_run(0, (size_t)y * d.z);
+    const V XP = x < d.x - 1 ? *(const V*)(u + r0 + (unsigned)d.y * rs + oth + j0) : face_run(1, (size_t)y * d.z);
+    const V YM = y > 0 ? *(const V*)(u + r0 - rs + oth + j0) : face_run(2, (size_t)x * d.z);
+    const V YP = y < d.y - 1 ? *(const V*)(u + r0 + rs + oth + j0) : face_run(3, (size_t)x * d.z);
+    sweep(XM, XP, YM, YP);
+}
+
 template <class T, bool GH>
 __global__ void k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g,
                                  Lay L, T h2, T* __restrict__ pu, T* __restrict__ pf, T* __restrict__ uold,
@@ -1283,7 +1352,16 @@ void launch_rbgs_half(T* u, const T* f, const T* ghosts, Lay L, double h, int co
     const T h2 = (T)(h * h);
     // stamped by the events when they are given (kernel timing), else a plain launch (the form
     // captured into graphs)
-    if (ghosts) {
+    constexpr int W = Vec16<T>::W;
+    const bool vec = (L.d.z / 2) % W == 0 && (((uintptr_t)u | (uintptr_t)f) & 15u) == 0;
+    if (ghosts && vec) {   // runs of W cells (same bits)
+        const unsigned g = grid_for(n / W);
+        if (ev0)
+            hipExtLaunchKernelGGL(k_rbgs_ghost_vec<T>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, ghosts, L, h2,
+                                  colour);
+        else
+            k_rbgs_ghost_vec<T><<<g, kBlock, 0, st>>>(u, f, ghosts, L, h2, colour);
+    } else if (ghosts) {
         if (ev0)
             hipExtLaunchKernelGGL(k_rbgs_ghost<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, ev0, ev1, 0, u, f, ghosts,
                                   L, h2, colour);
