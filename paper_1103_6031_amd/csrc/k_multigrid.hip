@@ -778,9 +778,13 @@ __device__ __forceinline__ void w2(double t, double w[3]) {
 // written out over the group, so the bits do not depend on how the group is split over lanes.
 // The four lanes of a group must be consecutive lanes of one wave starting at a multiple of 4,
 // and every lane of the wave must take part (lanes with no group of their own repeat a valid one).
-template <class T>
+// The parent's part of the value - the interpolation aq in the outside parent layer and the
+// parent cell O in front of the group - does not change while the patch alone is smoothed:
+// MODE 1 also returns it in pa = {aq, O}, MODE 2 takes it from pa instead of the parent.
+template <class T, int MODE>
 __device__ __forceinline__ double ghost_lane(const T* __restrict__ pu, const T* __restrict__ u, const Lay& LF,
-                                             const ParentMap& pm, int face, int J, int K, int q, int flux_match) {
+                                             const ParentMap& pm, int face, int J, int K, int q, int flux_match,
+                                             double2& pa) {
     const Dims d = LF.d;
     const int n[3] = {d.x, d.y, d.z};
     const int a = face >> 1, side = face & 1;
@@ -788,21 +792,6 @@ __device__ __forceinline__ double ghost_lane(const T* __restrict__ pu, const T* 
     const int jb = q >> 1, kc = q & 1;
     // fine interior layers and the outside coarse layer along the face normal
     const int i0 = side ? n[a] - 1 : 0, i1 = side ? n[a] - 2 : 1;
-    const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
-    const int pdim[3] = {pm.pl.d.x, pm.pl.d.y, pm.pl.d.z};
-
-    // 3x3 outside coarse layer around O
-    double L[3][3];
-    for (int db = 0; db < 3; ++db)
-        for (int dc = 0; dc < 3; ++dc) {
-            int qq[3];
-            qq[a] = on;
-            qq[b] = pm.off[b] + J + db - 1;
-            qq[c] = pm.off[c] + K + dc - 1;
-            if (pm.periodic)
-                for (int k = 0; k < 3; ++k) qq[k] = wrap(qq[k], pdim[k]);
-            L[db][dc] = (double)pu[lidx(pm.pl.d, pm.pl.split, qq[0], qq[1], qq[2])];
-        }
     int p0[3], p1[3];
     p0[a] = i0;
     p1[a] = i1;
@@ -810,13 +799,35 @@ __device__ __forceinline__ double ghost_lane(const T* __restrict__ pu, const T* 
     p0[c] = p1[c] = 2 * K + kc;
     const double u0 = (double)u[lidx(LF, p0[0], p0[1], p0[2])];
     const double u1 = (double)u[lidx(LF, p1[0], p1[1], p1[2])];
-    double wb[3], wc[3];
-    w2(jb ? 0.25 : -0.25, wb);
-    w2(kc ? 0.25 : -0.25, wc);
-    // parallel to the face: first along b (for each of the 3 c-columns), then along c
-    double Ab[3];
-    for (int dc = 0; dc < 3; ++dc) Ab[dc] = (wb[0] * L[0][dc] + wb[1] * L[1][dc]) + wb[2] * L[2][dc];
-    const double aq = (wc[0] * Ab[0] + wc[1] * Ab[1]) + wc[2] * Ab[2];
+    double aq, O;
+    if constexpr (MODE == 2) {
+        aq = pa.x;
+        O = pa.y;
+    } else {
+        const int on = side ? pm.off[a] + n[a] / 2 : pm.off[a] - 1;
+        const int pdim[3] = {pm.pl.d.x, pm.pl.d.y, pm.pl.d.z};
+        // 3x3 outside coarse layer around O
+        double L[3][3];
+        for (int db = 0; db < 3; ++db)
+            for (int dc = 0; dc < 3; ++dc) {
+                int qq[3];
+                qq[a] = on;
+                qq[b] = pm.off[b] + J + db - 1;
+                qq[c] = pm.off[c] + K + dc - 1;
+                if (pm.periodic)
+                    for (int k = 0; k < 3; ++k) qq[k] = wrap(qq[k], pdim[k]);
+                L[db][dc] = (double)pu[lidx(pm.pl.d, pm.pl.split, qq[0], qq[1], qq[2])];
+            }
+        double wb[3], wc[3];
+        w2(jb ? 0.25 : -0.25, wb);
+        w2(kc ? 0.25 : -0.25, wc);
+        // parallel to the face: first along b (for each of the 3 c-columns), then along c
+        double Ab[3];
+        for (int dc = 0; dc < 3; ++dc) Ab[dc] = (wb[0] * L[0][dc] + wb[1] * L[1][dc]) + wb[2] * L[2][dc];
+        aq = (wc[0] * Ab[0] + wc[1] * Ab[1]) + wc[2] * Ab[2];
+        O = L[1][1];
+        if constexpr (MODE == 1) pa = make_double2(aq, O);
+    }
     const double g0 = ((8.0 / 15.0) * aq + (2.0 / 3.0) * u0) - 0.2 * u1;
     double shift = 0.0;
     if (flux_match) {
@@ -828,17 +839,18 @@ __device__ __forceinline__ double ghost_lane(const T* __restrict__ pu, const T* 
         };
         const double m_u0 = mean4(u0), m_u1 = mean4(u1), m_g0 = mean4(g0);
         const double uC = 0.5 * (m_u0 + m_u1);
-        shift = (m_u0 - m_g0) - 0.5 * (uC - L[1][1]);
+        shift = (m_u0 - m_g0) - 0.5 * (uC - O);
     }
     return g0 + shift;
 }
 
 // One lane per ghost cell, four lanes per group (ghost_lane), one launch row per face.  Four
 // short chains instead of one long one, and four times the waves, for a launch that is
-// latency-bound.
-template <class T>
-__global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, T* __restrict__ g, Lay LF,
-                             ParentMap pm, int flux_match) {
+// latency-bound.  MODE 1 stores each cell's parent part in pa (indexed as the ghosts), MODE 2
+// reads it back: the fills after the first of a smoothing pass skip the parent layer.
+template <class T, int MODE>
+__global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, T* __restrict__ g,
+                             double2* __restrict__ pa, Lay LF, ParentMap pm, int flux_match) {
     const Dims d = LF.d;
     const int n[3] = {d.x, d.y, d.z};
     const int face = (int)blockIdx.y;
@@ -852,11 +864,13 @@ __global__ void k_ghost_fill(const T* __restrict__ pu, const T* __restrict__ u, 
     const bool live = t < ngroups;
     const unsigned tg = live ? t : ngroups - 1;
     const int J = (int)(tg / nc2), K = (int)(tg - (unsigned)J * nc2);
-    const double v = ghost_lane<T>(pu, u, LF, pm, face, J, K, (int)q, flux_match);
+    const size_t gi = ghost_face_offset(d, face) + (size_t)(2 * J + (int)(q >> 1)) * n[c] + (2 * K + (int)(q & 1));
+    double2 part = make_double2(0.0, 0.0);
+    if constexpr (MODE == 2) part = pa[gi];
+    const double v = ghost_lane<T, MODE>(pu, u, LF, pm, face, J, K, (int)q, flux_match, part);
     if (!live) return;
-    const size_t fo = ghost_face_offset(d, face);
-    const int nbf = n[c];  // face arrays are [n_b][n_c]
-    g[fo + (size_t)(2 * J + (int)(q >> 1)) * nbf + (2 * K + (int)(q & 1))] = (T)v;
+    g[gi] = (T)v;   // face arrays are [n_b][n_c]
+    if constexpr (MODE == 1) pa[gi] = part;
 }
 
 // parent[cov] = mean8(fine), bottom-up composite restriction
@@ -1445,11 +1459,16 @@ void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st) {
 }
 
 template <class T>
-void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Lay L, ParentMap pm, int flux_match, hipStream_t st) {
+void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Lay L, ParentMap pm, int flux_match, hipStream_t st,
+                       double* part, int mode) {
     const Dims d = L.d;
     const size_t most = std::max({(size_t)(d.y / 2) * (d.z / 2), (size_t)(d.x / 2) * (d.z / 2),
                                   (size_t)(d.x / 2) * (d.y / 2)});
-    k_ghost_fill<T><<<dim3(grid_for(4 * most), 6), kBlock, 0, st>>>(pu, u, ghosts, L, pm, flux_match);
+    const dim3 grid(grid_for(4 * most), 6);
+    double2* pa = (double2*)part;
+    if (!pa || mode == 0) k_ghost_fill<T, 0><<<grid, kBlock, 0, st>>>(pu, u, ghosts, nullptr, L, pm, flux_match);
+    else if (mode == 1) k_ghost_fill<T, 1><<<grid, kBlock, 0, st>>>(pu, u, ghosts, pa, L, pm, flux_match);
+    else k_ghost_fill<T, 2><<<grid, kBlock, 0, st>>>(pu, u, ghosts, pa, L, pm, flux_match);
 }
 
 template <class T>
@@ -1839,7 +1858,7 @@ template void launch_sub_mean<double>(double*, size_t, const double*, double, hi
     template void launch_fas_rhs<T>(const T*, T*, ParentMap, Dims, double, hipStream_t);                    \
     template void launch_prolong<T>(T*, Lay, const T*, const T*, ParentMap, int, hipStream_t);                   \
     template void launch_coarsest<T>(T*, const T*, int, double, hipStream_t);                               \
-    template void launch_ghost_fill<T>(const T*, const T*, T*, Lay, ParentMap, int, hipStream_t);            \
+    template void launch_ghost_fill<T>(const T*, const T*, T*, Lay, ParentMap, int, hipStream_t, double*, int); \
     template void launch_restrict_cov<T>(const T*, Lay, T*, ParentMap, hipStream_t);                \
     template void launch_tail<T>(const TailPlan<T>&, hipStream_t);
 MGIC_INST(double)

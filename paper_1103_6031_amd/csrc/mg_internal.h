@@ -240,9 +240,13 @@ void launch_level_post(const T* ui, const T* fi, const T* uc, const T* uold, T* 
 // exact coarsest solve on an odd periodic M^3 grid (M = 1: u = 0)
 template <class T> void launch_coarsest(T* u, const T* f, int M, double h, hipStream_t st);
 
-// flux-matched ghost layer of a patch (arithmetic in double, stored as T)
+// flux-matched ghost layer of a patch (arithmetic in double, stored as T).  part (2 doubles per
+// ghost cell, or null) holds the parent's part of each value between the fills of one smoothing
+// pass: mode 1 computes and stores it, mode 2 reuses it (valid while the parent is unchanged and
+// the last mode-1 fill used the same parent array), mode 0 neither.
 template <class T> void launch_ghost_fill(const T* pu, const T* u, T* ghosts, Lay L, ParentMap pm,
-                                          int flux_match, hipStream_t st);
+                                          int flux_match, hipStream_t st, double* part = nullptr,
+                                          int mode = 0);
 // parent[cov] = mean8(fine)
 template <class T> void launch_restrict_cov(const T* fine, Lay L, T* parent, ParentMap pm, hipStream_t st);
 

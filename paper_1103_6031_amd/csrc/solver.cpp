@@ -68,6 +68,7 @@ struct Level {
     CovBox child{};         // region of this level covered by L[l-1]
     double* u_user = nullptr;  // caller's array of a hierarchy level (natural rows)
     double *u = nullptr, *f = nullptr, *g = nullptr, *uold = nullptr;   // working arrays (lay)
+    double* gpart = nullptr;   // patches: the parent's part of each ghost value, 2 per ghost cell
     float *u32 = nullptr, *f32 = nullptr, *g32 = nullptr, *uold32 = nullptr;
     double* ualt = nullptr;  // second u of the fused mixed-precision outer step (ping-pong)
     float* ealt = nullptr;   // second e of the same
@@ -179,6 +180,7 @@ static int build_plan(const mg_hier* H, const mg_opts* o, Carver& cv, double* co
         L.u = (hier && !L.lay.split) ? L.u_user : cv.take<double>(n);
         L.f = cv.take<double>(n);
         if (!L.periodic) L.g = cv.take<double>(ghost_cells(L.d));
+        if (!L.periodic) L.gpart = cv.take<double>(2 * ghost_cells(L.d));
         if (l < P.last) L.uold = cv.take<double>(n / 8);
         if (P.mixed) {
             L.u32 = cv.take<float>(n);
@@ -339,20 +341,24 @@ static int run_graph(bool use_graph, const std::string& key, hipStream_t st, F b
 // ----------------------------------------------------------------------------------------------
 // V-cycle schedule
 // ----------------------------------------------------------------------------------------------
+// mode 1: compute the parent's part of the ghosts and keep it; mode 2: reuse the part kept by the
+// last mode-1 fill of this level in the same precision, with the parent unchanged since
 template <class T>
-static void ghosts(Plan& P, int l, hipStream_t st) {
+static void ghosts(Plan& P, int l, hipStream_t st, int mode = 0) {
     Level& L = P.L[l];
     B<T> b = bufs<T>(L), pb = bufs<T>(P.L[l + 1]);
-    launch_ghost_fill<T>(pb.u, b.u, b.g, L.lay, L.pm, 1, st);
+    launch_ghost_fill<T>(pb.u, b.u, b.g, L.lay, L.pm, 1, st, L.gpart, mode);
 }
 
+// returns whether a patch's ghosts were filled (then the parent's part of them is kept)
 template <class T>
-static void smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_red = false,
+static bool smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_red = false,
                    const T* corr_pu = nullptr) {
     Level& L = P.L[l];
     B<T> b = bufs<T>(L);
     const bool timed = l == 0;
     const double half_bytes = 0.5 * (double)L.d.cells() * 3.0 * sizeof(T);  // 3 words per update
+    bool filled = false;
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             if (skip_first_red && s == 0 && c == 0) continue;  // already done by the fused outer step
@@ -360,7 +366,9 @@ static void smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_r
                 launch_rbgs_vec_corr<T>(b.u, b.f, L.lay, L.h, corr_pu, b.uold, st);
                 continue;
             }
-            if (!L.periodic) ghosts<T>(P, l, st);
+            // only the patch changes during the pass: the parent's part is formed once
+            if (!L.periodic) ghosts<T>(P, l, st, filled ? 2 : 1);
+            filled = !L.periodic;
             KEvents ev(timed);
             if (L.periodic && rbgs_vec_ok(L.lay, sizeof(T)))
                 launch_rbgs_vec<T>(b.u, b.f, L.lay, L.h, c, st, ev.a, ev.b);
@@ -368,6 +376,7 @@ static void smooth(Plan& P, int l, int sweeps, hipStream_t st, bool skip_first_r
                 launch_rbgs_half<T>(b.u, b.f, L.periodic ? nullptr : b.g, L.lay, L.h, c, st, ev.a, ev.b);
             ev.done(half_bytes);
         }
+    return filled;
 }
 
 // level l runs as the two fused tile launches (its arrays for them are reserved and the sweep
@@ -417,8 +426,8 @@ static void vcycle(Plan& P, int l, hipStream_t st, bool skip_first_red = false) 
         launch_level_post<T>(b.ua, b.fa, q.u, b.uold, b.u, L.d.x, L.h, P.nu2, st);
         return;
     }
-    smooth<T>(P, l, P.nu1, st, skip_first_red);  // step 2
-    if (!L.periodic) ghosts<T>(P, l, st);
+    const bool filled = smooth<T>(P, l, P.nu1, st, skip_first_red);  // step 2
+    if (!L.periodic) ghosts<T>(P, l, st, filled ? 2 : 0);
     // steps 3-5, then step 6 on the covered region of the parent (a fused parent does its own)
     const bool p2 = p2lev(L);
     if (p2) launch_resid_restrict_p2<T>(b.u, b.f, L.d.x, L.h, q.u, q.f, b.uold, st);
