@@ -479,9 +479,14 @@ __device__ __forceinline__ double hoz_off(const double* __restrict__ v, const do
 // loads per group.  The parallel step is a tensor product: its sums along b (one per layer, fine
 // row parity jb and staged column) go to LDS in a second stage, and each lane then takes 2R + 1
 // of them along c, so every value is formed with the operations of the direct double sum.
-template <int R>
+// The parent's part of a ghost column - its R parallel values A and the R parent cells O in
+// front of its group - does not change while the patch alone is smoothed: MODE 1 also stores it
+// in part (2R planes of one value per face column, [m][column]), MODE 2 reads it from there and
+// stages nothing.
+template <int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__ pu, const double* __restrict__ u,
-                                                      double* __restrict__ g, HozPatch P, HozW W, int flux_match) {
+                                                      double* __restrict__ g, double* __restrict__ part, HozPatch P,
+                                                      HozW W, int flux_match) {
     constexpr int kG = kBlock / 4;            // groups per pass
     constexpr int kW = kG + 2 * R;            // staged columns
     constexpr int kIt = (R * (2 * R + 1) * kW + kBlock - 1) / kBlock;   // staging loads per lane
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
         for (int it = 0; it < kIt; ++it) {
             const int i = (int)threadIdx.x + it * kBlock;
             st[it] = 0.0;
-            if (i < nst) {
+            if (MODE != 2 && i < nst) {
                 const int col = i % ws, r = i / ws;
                 const int db = r % (2 * R + 1), k = r / (2 * R + 1);
                 const int on = side ? P.off[a] + n[a] / 2 + k : P.off[a] - 1 - k;
@@ -538,6 +543,17 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
             p3[c] = 2 * K + kc;
             v[i] = u[hoz_nat(n, p3[0], p3[1], p3[2])];
         }
+        // position of this lane's column among the face's columns (the ghost layers' indexing)
+        const size_t ncol = hoz_face_off(n, 1, 6);
+        const size_t ci = hoz_face_off(n, 1, face) + (size_t)(2 * J + jb) * n[c] + (2 * K + kc);
+        double A[R], O[R];
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                A[k] = part[(size_t)k * ncol + ci];
+                O[k] = part[(size_t)(R + k) * ncol + ci];
+            }
+        } else {
         if (K0) __syncthreads();              // the previous pass has read S and T
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
@@ -556,7 +572,6 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
             T[k][pj][col] = ab;
         }
         __syncthreads();
-        double A[R], O[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             double acc = 0.0;
@@ -564,6 +579,13 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
             for (int dc = 0; dc <= 2 * R; ++dc) acc += W.par[kc][dc] * T[k][jb][Kl + dc];
             A[k] = acc;
             O[k] = S[k][R][Kl + R];
+        }
+        if (MODE == 1 && live)
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                part[(size_t)k * ncol + ci] = A[k];
+                part[(size_t)(R + k) * ncol + ci] = O[k];
+            }
         }
         double g0[R];
 #pragma unroll
@@ -872,12 +894,18 @@ __global__ __launch_bounds__(kBlock) void k_hoz_psum_lds(const double* __restric
     } while (0)
 
 void launch_hoz_ghost(const double* pu, const double* u, double* g, const HozPatch& P, const HozW& W, int order,
-                      int flux_match, hipStream_t st) {
+                      int flux_match, hipStream_t st, double* part, int mode) {
     // one block per row of groups: n[b] / 2 rows on a face normal to a (b = 1 for a = 0, else 0)
     const dim3 grid((unsigned)std::max(P.n[1] / 2, P.n[0] / 2), 6);
-    HOZ_R(order, (k_hoz_ghost<1><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)),
-          (k_hoz_ghost<2><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)),
-          (k_hoz_ghost<3><<<grid, kBlock, 0, st>>>(pu, u, g, P, W, flux_match)));
+    if (!part) mode = 0;
+#define HOZ_GH(R)                                                                                    \
+    do {                                                                                             \
+        if (mode == 0) k_hoz_ghost<R, 0><<<grid, kBlock, 0, st>>>(pu, u, g, part, P, W, flux_match); \
+        else if (mode == 1) k_hoz_ghost<R, 1><<<grid, kBlock, 0, st>>>(pu, u, g, part, P, W, flux_match); \
+        else k_hoz_ghost<R, 2><<<grid, kBlock, 0, st>>>(pu, u, g, part, P, W, flux_match);        \
+    } while (0)
+    HOZ_R(order, HOZ_GH(1), HOZ_GH(2), HOZ_GH(3));
+#undef HOZ_GH
 }
 
 void launch_hoz_half(const double* in, double* out, const double* f, const double* g, const HozPatch& P, int order,

@@ -414,8 +414,12 @@ __host__ __device__ inline size_t hoz_face_off(const int* n, int R, int face) {
     const size_t o[7] = {0, fx, 2 * fx, 2 * fx + fy, 2 * fx + 2 * fy, 2 * fx + 2 * fy + fz, 2 * fx + 2 * fy + 2 * fz};
     return o[face];
 }
+// ghost layers of a patch; part (2R doubles per face column, hoz_face_off(n, 1, 6) columns, or
+// null) holds the parent's part of the values between the fills of one smoothing pass: mode 1
+// computes and stores it, mode 2 reuses it (parent unchanged since the last mode-1 fill), mode 0
+// neither
 void launch_hoz_ghost(const double* pu, const double* u, double* g, const HozPatch& P, const HozW& W, int order,
-                      int flux_match, hipStream_t st);
+                      int flux_match, hipStream_t st, double* part = nullptr, int mode = 0);
 void launch_hoz_half(const double* in, double* out, const double* f, const double* g, const HozPatch& P, int order,
                      int colour, hipStream_t st);
 // steps 3-5: parent u and f on the covered cells := the means of the children's u and residual,

@@ -2093,6 +2093,7 @@ int mg_solve_level_ho(int n, double h, int order, const double* f, double* u, co
 struct HozLevel {
     HozPatch P{};
     double *u = nullptr, *f = nullptr, *tmp = nullptr, *g = nullptr, *uold = nullptr;
+    double* gpart = nullptr;   // the parent's part of the ghosts, kept between the fills of a pass
     int cov_lo[3] = {0, 0, 0}, cov_n[3] = {0, 0, 0};   // box covered by the next patch (n = 0: none)
 };
 
@@ -2184,6 +2185,7 @@ static int hoz_plan(const mg_hier* H, int order, Carver& cv, HozPlan& Z) {
         L.f = cv.take<double>(c);
         L.tmp = cv.take<double>(c);
         L.g = cv.take<double>(hoz_face_off(L.P.n, R, 6));
+        L.gpart = cv.take<double>(2 * (size_t)R * hoz_face_off(L.P.n, 1, 6));
         L.uold = cv.take<double>(c / 8);
     }
     for (int p = 1; p <= Z.np; ++p) {   // the box of level p - 1 covered by patch p
@@ -2237,13 +2239,15 @@ static void hoz_composite_sq(HozPlan& Z, int mode, int slot, hipStream_t st) {
     launch_finalize(Z.part, sg, Z.scal + slot, st);
 }
 
+// only the patch changes during a smoothing pass: the parent's part of its ghosts is formed by
+// the pass's first fill and reused by the later ones
 static void hoz_smooth(HozPlan& Z, int p, int sweeps, hipStream_t st) {
     HozLevel& L = Z.pat[p - 1];
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             const double* in = c == 0 ? L.u : L.tmp;
             double* out = c == 0 ? L.tmp : L.u;
-            launch_hoz_ghost(hoz_pu(Z, p), in, L.g, L.P, Z.W, Z.order, 1, st);
+            launch_hoz_ghost(hoz_pu(Z, p), in, L.g, L.P, Z.W, Z.order, 1, st, L.gpart, s + c == 0 ? 1 : 2);
             launch_hoz_half(in, out, L.f, L.g, L.P, Z.order, c, st);
         }
 }
@@ -2255,7 +2259,7 @@ static void hoz_vcycle(HozPlan& Z, int p, int nu1, int nu2, hipStream_t st) {
     }
     HozLevel& L = Z.pat[p - 1];
     hoz_smooth(Z, p, nu1, st);                                                     // step 2
-    launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st);
+    launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st, L.gpart, nu1 > 0 ? 2 : 0);
     launch_hoz_resid_restrict(L.u, L.f, L.g, L.P, Z.order, hoz_pu(Z, p), hoz_pf(Z, p), L.uold, st);   // 3-5
     const int* lo = p == 1 ? Z.base_cov_lo : Z.pat[p - 2].cov_lo;
     const int* cn = p == 1 ? Z.base_cov_n : Z.pat[p - 2].cov_n;
