@@ -448,6 +448,89 @@ __global__ void k_resid_restrict(const T* __restrict__ u, const T* __restrict__ 
     if (t < n) cell_resid_restrict<T, GH>(u, f, g, L, h2, pu, pf, uold, pm, C, t);
 }
 
+// Steps 3-5 of a colour-split patch for covered cell t (natural order of the covered box), with
+// every load of the 8 children issued before any sum, as cell_resid_restrict_p2 on periodic
+// levels: the four central rows (x0 + a, y0 + b) at z0 - 1 .. z0 + 2, f at z0 and z0 + 1, and the
+// rows one step outside in x and in y at z0, z0 + 1.  A neighbour outside the patch is read from
+// its face's ghosts instead (one load from either address).  The children and their sums are
+// taken in the order of cell_resid_restrict, so the bits are the same.
+template <class T>
+__global__ void k_resid_restrict_gh(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ g,
+                                    Lay L, T h2, T* __restrict__ pu, T* __restrict__ pf, T* __restrict__ uold,
+                                    ParentMap pm, Lay C) {
+    const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= (unsigned)C.d.cells()) return;
+    int X, Y, Z;
+    ldecode(C, t, X, Y, Z);
+    const Dims d = L.d;
+    const int nzh = d.z >> 1;
+    const int x0 = 2 * X, y0 = 2 * Y;
+    auto rowb = [&](int x, int y) { return ((size_t)x * d.y + y) * d.z; };
+    auto half = [&](int x, int y, int zpar) { return (size_t)((x + y + zpar) & 1) * nzh; };
+    const size_t f4 = ghost_face_offset(d, 4), f5 = ghost_face_offset(d, 5);
+    T cm[2][2], c0[2][2], c1[2][2], c2[2][2], f0[2][2], f1[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int x = x0 + a, y = y0 + b;
+            const size_t rb = rowb(x, y), he = half(x, y, 0), ho = half(x, y, 1);
+            const size_t gz = (size_t)x * d.y + y;
+            cm[a][b] = *(Z > 0 ? u + (rb + ho + Z - 1) : g + (f4 + gz));
+            c0[a][b] = u[rb + he + Z];
+            c1[a][b] = u[rb + ho + Z];
+            c2[a][b] = *(Z + 1 < nzh ? u + (rb + he + Z + 1) : g + (f5 + gz));
+            f0[a][b] = f[rb + he + Z];
+            f1[a][b] = f[rb + ho + Z];
+        }
+    T xf[2][2][2], yf[2][2][2];   // [side][b or a][e]
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int z = 2 * Z + e;
+                {
+                    const int x = sd ? x0 + 2 : x0 - 1, y = y0 + k;
+                    const bool in = sd ? x < d.x : x >= 0;
+                    xf[sd][k][e] = *(in ? u + (rowb(x, y) + half(x, y, e) + Z)
+                                        : g + (ghost_face_offset(d, sd) + (size_t)y * d.z + z));
+                }
+                {
+                    const int x = x0 + k, y = sd ? y0 + 2 : y0 - 1;
+                    const bool in = sd ? y < d.y : y >= 0;
+                    yf[sd][k][e] = *(in ? u + (rowb(x, y) + half(x, y, e) + Z)
+                                        : g + (ghost_face_offset(d, 2 + sd) + (size_t)x * d.z + z));
+                }
+            }
+    auto val = [&](int a, int b, int e) { return e ? c1[a][b] : c0[a][b]; };
+    T sr = T(0), su = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const T ui = val(a, b, e);
+                const T xm = a ? val(0, b, e) : xf[0][b][e];
+                const T xp = a ? xf[1][b][e] : val(1, b, e);
+                const T ym = b ? val(a, 0, e) : yf[0][a][e];
+                const T yp = b ? yf[1][a][e] : val(a, 1, e);
+                const T zm = e ? c0[a][b] : cm[a][b];
+                const T zp = e ? c2[a][b] : c1[a][b];
+                const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
+                const T lap = (s - T(6) * ui) / h2;
+                sr = sr + ((e ? f1[a][b] : f0[a][b]) - lap);
+                su = su + ui;
+            }
+    const T uc = su * T(0.125);
+    const size_t P = pidx(pm, X, Y, Z);
+    pu[P] = uc;
+    pf[P] = sr * T(0.125);
+    uold[t] = uc;
+}
+
 template <class T>
 __global__ void k_fas_rhs(const T* __restrict__ pu, T* __restrict__ pf, ParentMap pm, Lay C, T H2) {
     const unsigned t = (unsigned)xcd_block() * blockDim.x + threadIdx.x;
@@ -1434,7 +1517,9 @@ void launch_resid_restrict(const T* u, const T* f, const T* ghosts, Lay L, doubl
     const Lay C = mklay(Dims{L.d.x / 2, L.d.y / 2, L.d.z / 2}, 0);
     const size_t n = C.d.cells();
     const T h2 = (T)(h * h);
-    if (ghosts)
+    if (ghosts && L.split)   // colour-split patch: all loads of a coarse cell issued at once (same bits)
+        k_resid_restrict_gh<T><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, pu, pf, uold, pm, C);
+    else if (ghosts)
         k_resid_restrict<T, true><<<grid_for(n), kBlock, 0, st>>>(u, f, ghosts, L, h2, pu, pf, uold, pm, C);
     else
         k_resid_restrict<T, false><<<grid_for(n), kBlock, 0, st>>>(u, f, nullptr, L, h2, pu, pf, uold, pm, C);
