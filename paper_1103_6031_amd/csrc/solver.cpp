@@ -284,10 +284,19 @@ static int refuse_capture(hipStream_t st, const char* what) {
 // Instantiated graphs live until the thread ends; they are deliberately not destroyed at exit,
 // when the HIP runtime may already be gone.
 struct GraphCache {
-    std::map<std::string, hipGraphExec_t> exec;
+    struct Entry {
+        hipGraphExec_t ex = nullptr;
+        unsigned long long last = 0;   // tick of the last replay
+    };
+    std::map<std::string, Entry> exec;
     std::map<std::string, int> seen;   // uses of keys not captured yet
+    unsigned long long tick = 0;
     hipStream_t cap = nullptr;  // capture stream (capture is illegal on the null stream)
 };
+// instantiated graphs kept per thread; beyond this the least recently replayed one is dropped
+// (dropping them all at once made a workload re-capture its whole working set after other
+// workloads had filled the cache)
+constexpr size_t kMaxGraphs = 256;
 static thread_local GraphCache g_graphs;
 
 // kernel attributes that must be set before any capture
@@ -319,9 +328,12 @@ static int run_graph(bool use_graph, const std::string& key, hipStream_t st, F b
         g_graphs.seen.erase(key);
         if (int rc = graph_setup()) return rc;
         if (!g_graphs.cap) MG_HIP(hipStreamCreateWithFlags(&g_graphs.cap, hipStreamNonBlocking));
-        if (g_graphs.exec.size() >= 256) {
-            for (auto& kv : g_graphs.exec) (void)hipGraphExecDestroy(kv.second);
-            g_graphs.exec.clear();
+        if (g_graphs.exec.size() >= kMaxGraphs) {
+            auto old = g_graphs.exec.begin();
+            for (auto e = g_graphs.exec.begin(); e != g_graphs.exec.end(); ++e)
+                if (e->second.last < old->second.last) old = e;
+            (void)hipGraphExecDestroy(old->second.ex);
+            g_graphs.exec.erase(old);
         }
         if (g_graphs.seen.size() >= 4096) g_graphs.seen.clear();
         MG_HIP(hipStreamBeginCapture(g_graphs.cap, hipStreamCaptureModeThreadLocal));
@@ -332,9 +344,10 @@ static int run_graph(bool use_graph, const std::string& key, hipStream_t st, F b
         const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         MG_HIP(e);
-        it = g_graphs.exec.emplace(key, ex).first;
+        it = g_graphs.exec.emplace(key, GraphCache::Entry{ex, 0}).first;
     }
-    MG_HIP(hipGraphLaunch(it->second, st));
+    it->second.last = ++g_graphs.tick;
+    MG_HIP(hipGraphLaunch(it->second.ex, st));
     return MG_OK;
 }
 
@@ -1411,7 +1424,7 @@ static thread_local double* g_bpin = nullptr;
 static thread_local size_t g_bpin_n = 0;
 static double* batch_pinned(size_t n) {
     if (n <= g_bpin_n) return g_bpin;
-    for (auto& kv : g_graphs.exec) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : g_graphs.exec) (void)hipGraphExecDestroy(kv.second.ex);
     g_graphs.exec.clear();
     if (g_bpin) (void)hipHostFree(g_bpin);
     g_bpin = nullptr;
