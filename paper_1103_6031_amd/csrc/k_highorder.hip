@@ -725,27 +725,51 @@ __global__ __launch_bounds__(kBlock) void k_hoz_half_lds(const double* __restric
     }
 }
 
+// Steps 3-5 on a patch with 8 lanes per coarse cell (lanes 8k .. 8k + 7 of a wave hold the
+// children (a, b, e) in the order a, b, e): each lane forms one child's residual, reading its
+// neighbours directly where the whole stencil lies inside the patch and through the ghost layers
+// otherwise, all loads of a lane independent of each other; the first lane of the eight gathers
+// the residuals and values by shuffles and sums them in the order (a, b, e).
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_hoz_rr(const double* __restrict__ u, const double* __restrict__ f,
-                                                   const double* __restrict__ g, HozPatch P, double h2,
-                                                   double* __restrict__ pu, double* __restrict__ pf,
-                                                   double* __restrict__ uold) {
-    const int cn[3] = {P.n[0] / 2, P.n[1] / 2, P.n[2] / 2};
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (size_t)cn[0] * cn[1] * cn[2]) return;
-    int X, Y, Z;
-    hoz_decode(cn, t, X, Y, Z);
+__global__ __launch_bounds__(kBlock) void k_hoz_rr8(const double* __restrict__ u, const double* __restrict__ f,
+                                                    const double* __restrict__ g, HozPatch P, double h2,
+                                                    double* __restrict__ pu, double* __restrict__ pf,
+                                                    double* __restrict__ uold) {
+    const unsigned n0 = (unsigned)P.n[0], n1 = (unsigned)P.n[1], n2 = (unsigned)P.n[2];
+    const unsigned c1 = n1 >> 1, c2 = n2 >> 1, nc = (n0 >> 1) * c1 * c2;
+    const unsigned gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned l = gt & 7u;
+    // lanes past the last coarse cell repeat it (every lane takes part in the shuffles)
+    const bool live = (gt >> 3) < nc;
+    const unsigned t = live ? gt >> 3 : nc - 1;
+    const unsigned rw = t / c2, Z = t - rw * c2, X = rw / c1, Y = rw - X * c1;
+    const unsigned x = 2 * X + (l >> 2), y = 2 * Y + ((l >> 1) & 1u), z = 2 * Z + (l & 1u);
+    const size_t i = ((size_t)x * n1 + y) * n2 + z;
+    const double uv = u[i];
+    double off = 0;
+    if (x >= (unsigned)R && x + R < n0 && y >= (unsigned)R && y + R < n1 && z >= (unsigned)R && z + R < n2) {
+        const size_t sx = (size_t)n1 * n2;
+#pragma unroll
+        for (int s = 1; s <= R; ++s) {
+            const double px = u[i - s * sx] + u[i + s * sx];
+            const double py = u[i - (size_t)s * n2] + u[i + (size_t)s * n2];
+            const double pz = u[i - s] + u[i + s];
+            off += ho_w<R>(s) * ((px + py) + pz);
+        }
+    } else {
+        off = hoz_off<R>(u, g, P.n, (int)x, (int)y, (int)z);
+    }
+    const double lap = (off + 3.0 * HoW<R>::w0 * uv) / h2;
+    const double rr = f[i] - lap;
+    const int base = (int)(threadIdx.x & 63) & ~7;
     double rs = 0.0, us = 0.0;
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int e = 0; e < 2; ++e) {
-                const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + e;
-                const double uv = u[hoz_nat(P.n, x, y, z)];
-                const double lap = (hoz_off<R>(u, g, P.n, x, y, z) + 3.0 * HoW<R>::w0 * uv) / h2;
-                rs += f[hoz_nat(P.n, x, y, z)] - lap;
-                us += uv;
-            }
-    const size_t pi = hoz_nat(P.pn, P.off[0] + X, P.off[1] + Y, P.off[2] + Z);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        rs += __shfl(rr, base + k, 64);
+        us += __shfl(uv, base + k, 64);
+    }
+    if (l != 0 || !live) return;
+    const size_t pi = hoz_nat(P.pn, P.off[0] + (int)X, P.off[1] + (int)Y, P.off[2] + (int)Z);
     const double um = us * 0.125;
     pu[pi] = um;
     uold[t] = um;
@@ -928,11 +952,11 @@ void launch_hoz_half(const double* in, double* out, const double* f, const doubl
 
 void launch_hoz_resid_restrict(const double* u, const double* f, const double* g, const HozPatch& P, int order,
                                double* pu, double* pf, double* uold, hipStream_t st) {
-    const int grid = grid_for((size_t)(P.n[0] / 2) * (P.n[1] / 2) * (P.n[2] / 2));
+    const int grid = grid_for((size_t)8 * (P.n[0] / 2) * (P.n[1] / 2) * (P.n[2] / 2));   // 8 lanes per coarse cell
     const double h2 = P.h * P.h;
-    HOZ_R(order, (k_hoz_rr<1><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
-          (k_hoz_rr<2><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
-          (k_hoz_rr<3><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)));
+    HOZ_R(order, (k_hoz_rr8<1><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
+          (k_hoz_rr8<2><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
+          (k_hoz_rr8<3><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)));
 }
 
 void launch_hoz_fas(const double* u, double* f, const int* n, int periodic, const int* lo, const int* cn, double h,
