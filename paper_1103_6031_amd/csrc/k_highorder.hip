@@ -675,6 +675,40 @@ __global__ __launch_bounds__(kBlock) void k_hoz_half(const double* __restrict__ 
     *(double2*)(out + t0) = q ? make_double2(cur.x, v) : make_double2(v, cur.y);
 }
 
+// Rows y0 - R .. y0 + ny + R - 1 of x plane x of a patch, with R cells on each side in z, into
+// rows[(ny + 2R) x (n2 + 2R)]: the cells outside the patch from the ghost layers, the corners
+// (which no stencil reads) zero.  Each thread issues its loads in batches of 8 before writing
+// them to LDS, so that they are in flight together.
+template <int R>
+__device__ __forceinline__ void hoz_stage_rows(double* __restrict__ rows, const double* __restrict__ in,
+                                               const double* __restrict__ g, const HozPatch& P, int x, int y0,
+                                               int ny) {
+    constexpr int kBatch = 8;
+    const int n1 = P.n[1], n2 = P.n[2];
+    const int W = n2 + 2 * R;
+    const int nst = (ny + 2 * R) * W;
+    for (int i0 = (int)threadIdx.x; i0 < nst; i0 += kBatch * (int)blockDim.x) {
+        double v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = i0 + k * (int)blockDim.x;
+            v[k] = 0.0;
+            if (i < nst) {
+                const int r = i / W, cz = i - r * W;
+                const int y = y0 + r - R, z = cz - R;
+                const bool yin = y >= 0 && y < n1, zin = z >= 0 && z < n2;
+                if (yin && zin) v[k] = in[hoz_nat(P.n, x, y, z)];
+                else if (yin || zin) v[k] = hoz_val(in, g, P.n, R, x, y, z);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = i0 + k * (int)blockDim.x;
+            if (i < nst) rows[i] = v[k];
+        }
+    }
+}
+
 // The same half-sweep with the y and z neighbours from LDS (as k_ho_half_lds on periodic levels):
 // a block owns rows y0 .. y0 + kHoTy - 1 of one x plane and stages them with R rows on each side in
 // y and R cells on each side in z, taking what lies outside the patch from the ghost layers (the
@@ -691,16 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_hoz_half_lds(const double* __restric
     const int tiles = (n1 + kHoTy - 1) / kHoTy;
     const int x = (int)blockIdx.x / tiles, y0 = ((int)blockIdx.x - x * tiles) * kHoTy;
     const int ny = n1 - y0 < kHoTy ? n1 - y0 : kHoTy;
-    const int nst = (ny + 2 * R) * W;
-    for (int i = (int)threadIdx.x; i < nst; i += (int)blockDim.x) {
-        const int r = i / W, cz = i - r * W;
-        const int y = y0 + r - R, z = cz - R;
-        const bool yin = y >= 0 && y < n1, zin = z >= 0 && z < n2;
-        double v = 0.0;
-        if (yin && zin) v = in[hoz_nat(P.n, x, y, z)];
-        else if (yin || zin) v = hoz_val(in, g, P.n, R, x, y, z);
-        rows[i] = v;
-    }
+    hoz_stage_rows<R>(rows, in, g, P, x, y0, ny);
     __syncthreads();
     const int n2h = n2 >> 1;
     const size_t sx = (size_t)n1 * n2;
@@ -873,16 +898,7 @@ __global__ __launch_bounds__(kBlock) void k_hoz_psum_lds(const double* __restric
         const int x = tile / tiles, y0 = (tile - x * tiles) * kHoTy;
         const int ny = n1 - y0 < kHoTy ? n1 - y0 : kHoTy;
         __syncthreads();                       // the previous tile has been read
-        const int nst = (ny + 2 * R) * W;
-        for (int i = (int)threadIdx.x; i < nst; i += (int)blockDim.x) {
-            const int r = i / W, cz = i - r * W;
-            const int y = y0 + r - R, z = cz - R;
-            const bool yin = y >= 0 && y < n1, zin = z >= 0 && z < n2;
-            double val = 0.0;
-            if (yin && zin) val = v[hoz_nat(P.n, x, y, z)];
-            else if (yin || zin) val = hoz_val(v, g, P.n, R, x, y, z);
-            rows[i] = val;
-        }
+        hoz_stage_rows<R>(rows, v, g, P, x, y0, ny);
         __syncthreads();
         const bool xcov = x >= lo0 && x < lo0 + c0;
         for (int t = (int)threadIdx.x; t < ny * n2; t += (int)blockDim.x) {
