@@ -112,12 +112,30 @@ __global__ __launch_bounds__(kBlock) void k_ho_half_lds(const T* __restrict__ in
     const unsigned tiles = n / kHoTy;
     const unsigned bl = ho_xcd_group(blockIdx.x, lg - 3);   // consecutive tiles of a plane on one XCD
     const unsigned x = bl / tiles, y0 = (bl - x * tiles) * kHoTy;
-    // stage rows y0 - R .. y0 + kHoTy + R - 1 as 16-byte pairs
+    // stage rows y0 - R .. y0 + kHoTy + R - 1 as 16-byte pairs, each thread's loads in batches
+    // of 8 before their LDS writes (so that they are in flight together)
+    constexpr int kBatch = 8;
     const unsigned npairs = (unsigned)(kHoTy + 2 * R) * nh;
-    for (unsigned t = threadIdx.x; t < npairs; t += blockDim.x) {
-        const unsigned r = t / nh, pz = t - r * nh;
-        const unsigned y = (y0 + r - R) & m;
-        *(v2_t<T>*)(rows + r * n + 2 * pz) = *(const v2_t<T>*)(in + ho_idx(x, y, 2 * pz, lg));
+    for (unsigned t0 = threadIdx.x; t0 < npairs; t0 += kBatch * blockDim.x) {
+        v2_t<T> v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const unsigned t = t0 + k * blockDim.x;
+            v[k] = mk2<T>((T)0, (T)0);
+            if (t < npairs) {
+                const unsigned r = t / nh, pz = t - r * nh;
+                const unsigned y = (y0 + r - R) & m;
+                v[k] = *(const v2_t<T>*)(in + ho_idx(x, y, 2 * pz, lg));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const unsigned t = t0 + k * blockDim.x;
+            if (t < npairs) {
+                const unsigned r = t / nh, pz = t - r * nh;
+                *(v2_t<T>*)(rows + r * n + 2 * pz) = v[k];
+            }
+        }
     }
     __syncthreads();
     const unsigned pairs = (unsigned)kHoTy * nh;
