@@ -695,35 +695,56 @@ __global__ __launch_bounds__(kBlock) void k_hoz_half(const double* __restrict__ 
 
 // Rows y0 - R .. y0 + ny + R - 1 of x plane x of a patch, with R cells on each side in z, into
 // rows[(ny + 2R) x (n2 + 2R)]: the cells outside the patch from the ghost layers, the corners
-// (which no stencil reads) zero.  Each thread issues its loads in batches of 8 before writing
-// them to LDS, so that they are in flight together.
+// (which no stencil reads) zero.  The n2 cells of a row come as 16-byte pairs (from the patch, or
+// from a y face's ghost layer; the arrays are workspace arrays with even rows), each thread's
+// loads in batches of 4 before their LDS writes, so that they are in flight together; then the
+// 2R z-halo cells of each row.
 template <int R>
 __device__ __forceinline__ void hoz_stage_rows(double* __restrict__ rows, const double* __restrict__ in,
                                                const double* __restrict__ g, const HozPatch& P, int x, int y0,
                                                int ny) {
-    constexpr int kBatch = 8;
-    const int n1 = P.n[1], n2 = P.n[2];
+    constexpr int kBatch = 4;
+    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2], n2h = n2 >> 1;
     const int W = n2 + 2 * R;
-    const int nst = (ny + 2 * R) * W;
-    for (int i0 = (int)threadIdx.x; i0 < nst; i0 += kBatch * (int)blockDim.x) {
-        double v[kBatch];
+    const int nr = ny + 2 * R;
+    const int np = nr * n2h;
+    for (int i0 = (int)threadIdx.x; i0 < np; i0 += kBatch * (int)blockDim.x) {
+        double2 v[kBatch];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const int i = i0 + k * (int)blockDim.x;
-            v[k] = 0.0;
-            if (i < nst) {
-                const int r = i / W, cz = i - r * W;
-                const int y = y0 + r - R, z = cz - R;
-                const bool yin = y >= 0 && y < n1, zin = z >= 0 && z < n2;
-                if (yin && zin) v[k] = in[hoz_nat(P.n, x, y, z)];
-                else if (yin || zin) v[k] = hoz_val(in, g, P.n, R, x, y, z);
+            v[k] = make_double2(0.0, 0.0);
+            if (i < np) {
+                const int r = i / n2h, pz = i - r * n2h;
+                const int y = y0 + r - R;
+                const double* src;
+                if (y >= 0 && y < n1) {
+                    src = in + hoz_nat(P.n, x, y, 2 * pz);
+                } else {
+                    const int side = y >= n1, layer = side ? y - n1 : -y - 1;
+                    src = g + hoz_face_off(P.n, R, 2 + side) + ((size_t)layer * n0 + x) * n2 + 2 * pz;
+                }
+                v[k] = *(const double2*)src;
             }
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const int i = i0 + k * (int)blockDim.x;
-            if (i < nst) rows[i] = v[k];
+            if (i < np) {
+                const int r = i / n2h, pz = i - r * n2h;
+                double* d = rows + r * W + R + 2 * pz;
+                d[0] = v[k].x;
+                d[1] = v[k].y;
+            }
         }
+    }
+    for (int i = (int)threadIdx.x; i < nr * 2 * R; i += (int)blockDim.x) {
+        const int r = i / (2 * R), k = i - r * (2 * R);
+        const int y = y0 + r - R;
+        const int cz = k < R ? k : n2 + k;     // z = cz - R: -R .. -1, or n2 .. n2 + R - 1
+        double v = 0.0;
+        if (y >= 0 && y < n1) v = hoz_val(in, g, P.n, R, x, y, cz - R);
+        rows[r * W + cz] = v;
     }
 }
 
