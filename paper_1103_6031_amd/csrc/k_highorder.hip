@@ -840,6 +840,64 @@ __global__ __launch_bounds__(kBlock) void k_hoz_rr8(const double* __restrict__ u
     pf[pi] = rs * 0.125;
 }
 
+// Steps 3-5 on a patch with the y and z neighbours from LDS: a block owns coarse plane X and coarse
+// rows Y0 .. Y0 + kHoTy / 2 - 1, stages both fine planes 2X and 2X + 1 over their kHoTy fine rows
+// (hoz_stage_rows), and each thread takes one coarse cell, its 8 children in the order (a, b, e);
+// the 2R x-neighbours and f come from memory.  The same values and sums as k_hoz_rr8.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_hoz_rr_lds(const double* __restrict__ u, const double* __restrict__ f,
+                                                       const double* __restrict__ g, HozPatch P, double h2,
+                                                       double* __restrict__ pu, double* __restrict__ pf,
+                                                       double* __restrict__ uold) {
+    extern __shared__ __align__(16) unsigned char hz_smem[];
+    double* rows = (double*)hz_smem;           // [2][kHoTy + 2R][n2 + 2R]
+    constexpr int kTc = kHoTy / 2;             // coarse rows per block
+    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+    const int c1 = n1 / 2, c2 = n2 / 2;
+    const int W = n2 + 2 * R, PS = (kHoTy + 2 * R) * W;
+    const int tiles = (c1 + kTc - 1) / kTc;
+    const int X = (int)blockIdx.x / tiles, Y0 = ((int)blockIdx.x - X * tiles) * kTc;
+    const int nyc = c1 - Y0 < kTc ? c1 - Y0 : kTc;
+    hoz_stage_rows<R>(rows, u, g, P, 2 * X, 2 * Y0, 2 * nyc);
+    hoz_stage_rows<R>(rows + PS, u, g, P, 2 * X + 1, 2 * Y0, 2 * nyc);
+    __syncthreads();
+    const size_t sx = (size_t)n1 * n2;
+    const double w0x3 = 3.0 * HoW<R>::w0;
+    for (int t = (int)threadIdx.x; t < nyc * c2; t += (int)blockDim.x) {
+        const int ry = t / c2, Z = t - ry * c2, Y = Y0 + ry;
+        double rs = 0.0, us = 0.0;
+        // one (a, b) column at a time (its two children unrolled): all 8 at once needed 348 VGPRs
+#pragma unroll 1
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int a = ab >> 1, b = ab & 1;
+                    const int x = 2 * X + a, y = 2 * Y + b, z = 2 * Z + e;
+                    const double* row = rows + a * PS + (2 * ry + b + R) * W + R;   // row[k] = u(x, y, k)
+                    const size_t i = hoz_nat(P.n, x, y, z);
+                    const double uv = row[z];
+                    double off = 0;
+#pragma unroll
+                    for (int s = 1; s <= R; ++s) {
+                        const double xm = x - s >= 0 ? u[i - s * sx] : hoz_val(u, g, P.n, R, x - s, y, z);
+                        const double xp = x + s < n0 ? u[i + s * sx] : hoz_val(u, g, P.n, R, x + s, y, z);
+                        const double px = xm + xp;
+                        const double py = row[z - s * W] + row[z + s * W];
+                        const double pz = row[z - s] + row[z + s];
+                        off += ho_w<R>(s) * ((px + py) + pz);
+                    }
+                    const double lap = (off + w0x3 * uv) / h2;
+                    rs += f[i] - lap;
+                    us += uv;
+                }
+        const size_t pi = hoz_nat(P.pn, P.off[0] + X, P.off[1] + Y, P.off[2] + Z);
+        const double um = us * 0.125;
+        pu[pi] = um;
+        uold[((size_t)X * c1 + Y) * c2 + Z] = um;
+        pf[pi] = rs * 0.125;
+    }
+}
+
 // FAS right-hand side on the covered box: periodic power-of-two level (PER) or a patch interior
 template <int R, bool PER>
 __global__ __launch_bounds__(kBlock) void k_hoz_fas(const double* __restrict__ u, double* __restrict__ f, int n0,
@@ -1007,8 +1065,18 @@ void launch_hoz_half(const double* in, double* out, const double* f, const doubl
 
 void launch_hoz_resid_restrict(const double* u, const double* f, const double* g, const HozPatch& P, int order,
                                double* pu, double* pf, double* uold, hipStream_t st) {
-    const int grid = grid_for((size_t)8 * (P.n[0] / 2) * (P.n[1] / 2) * (P.n[2] / 2));   // 8 lanes per coarse cell
     const double h2 = P.h * P.h;
+    const int R = order / 2;
+    const size_t lds = (size_t)2 * (kHoTy + 2 * R) * (P.n[2] + 2 * R) * sizeof(double);
+    if (lds <= 64u * 1024u) {   // both fine planes of a coarse plane staged (n_z up to 280)
+        const int tc = kHoTy / 2;
+        const unsigned grid = (unsigned)(P.n[0] / 2) * (unsigned)((P.n[1] / 2 + tc - 1) / tc);
+        HOZ_R(order, (k_hoz_rr_lds<1><<<grid, kBlock, lds, st>>>(u, f, g, P, h2, pu, pf, uold)),
+              (k_hoz_rr_lds<2><<<grid, kBlock, lds, st>>>(u, f, g, P, h2, pu, pf, uold)),
+              (k_hoz_rr_lds<3><<<grid, kBlock, lds, st>>>(u, f, g, P, h2, pu, pf, uold)));
+        return;
+    }
+    const int grid = grid_for((size_t)8 * (P.n[0] / 2) * (P.n[1] / 2) * (P.n[2] / 2));   // 8 lanes per coarse cell
     HOZ_R(order, (k_hoz_rr8<1><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
           (k_hoz_rr8<2><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)),
           (k_hoz_rr8<3><<<grid, kBlock, 0, st>>>(u, f, g, P, h2, pu, pf, uold)));
