@@ -2228,8 +2228,9 @@ static void hoz_restrict_up(HozPlan& Z, bool of_f, hipStream_t st) {
 }
 
 // composite sum of squares (mode 0: v = f; mode 1: the residual) over the uncovered cells of every
-// level, volume-weighted, into scal[slot]
-static void hoz_composite_sq(HozPlan& Z, int mode, int slot, hipStream_t st) {
+// level, volume-weighted, into scal[slot]; kept: every patch's parent part of its ghosts is still
+// the one its last smoothing pass kept (right after a V-cycle with post-smoothing)
+static void hoz_composite_sq(HozPlan& Z, int mode, int slot, hipStream_t st, bool kept = false) {
     SegList sg{};
     sg.n = Z.np + 1;
     const int nb3[3] = {Z.N0, Z.N0, Z.N0};
@@ -2240,7 +2241,7 @@ static void hoz_composite_sq(HozPlan& Z, int mode, int slot, hipStream_t st) {
                             Z.base_cov_lo, Z.base_cov_n, Z.h0, Z.order, part, st);
         } else {
             HozLevel& L = Z.pat[p - 1];
-            if (mode == 1) launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st);
+            if (mode == 1) launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st, L.gpart, kept ? 2 : 0);
             launch_hoz_psum(mode == 0 ? 0 : 1, mode == 0 ? L.f : L.u, L.f, L.g, L.P.n, L.cov_lo, L.cov_n, L.P.h,
                             Z.order, part, st);
         }
@@ -2253,33 +2254,36 @@ static void hoz_composite_sq(HozPlan& Z, int mode, int slot, hipStream_t st) {
 }
 
 // only the patch changes during a smoothing pass: the parent's part of its ghosts is formed by
-// the pass's first fill and reused by the later ones
-static void hoz_smooth(HozPlan& Z, int p, int sweeps, hipStream_t st) {
+// the pass's first fill (or taken as kept: first = 2) and reused by the later ones
+static void hoz_smooth(HozPlan& Z, int p, int sweeps, hipStream_t st, int first = 1) {
     HozLevel& L = Z.pat[p - 1];
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             const double* in = c == 0 ? L.u : L.tmp;
             double* out = c == 0 ? L.tmp : L.u;
-            launch_hoz_ghost(hoz_pu(Z, p), in, L.g, L.P, Z.W, Z.order, 1, st, L.gpart, s + c == 0 ? 1 : 2);
+            launch_hoz_ghost(hoz_pu(Z, p), in, L.g, L.P, Z.W, Z.order, 1, st, L.gpart, s + c == 0 ? first : 2);
             launch_hoz_half(in, out, L.f, L.g, L.P, Z.order, c, st);
         }
 }
 
-static void hoz_vcycle(HozPlan& Z, int p, int nu1, int nu2, hipStream_t st) {
+// kept: every patch's parent part is still the one kept by its post-smoothing in the previous
+// V-cycle (a patch's parent changes only between its pre- and post-smoothing: by the parent's own
+// smoothing and correction; restrictions write covered parent cells, which no ghost reads)
+static void hoz_vcycle(HozPlan& Z, int p, int nu1, int nu2, hipStream_t st, bool kept = false) {
     if (p == 0) {
         ho_vcycle<double>(Z.base, nu1, nu2, st);
         return;
     }
     HozLevel& L = Z.pat[p - 1];
-    hoz_smooth(Z, p, nu1, st);                                                     // step 2
-    launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st, L.gpart, nu1 > 0 ? 2 : 0);
+    hoz_smooth(Z, p, nu1, st, kept ? 2 : 1);                                       // step 2
+    launch_hoz_ghost(hoz_pu(Z, p), L.u, L.g, L.P, Z.W, Z.order, 1, st, L.gpart, nu1 > 0 || kept ? 2 : 0);
     launch_hoz_resid_restrict(L.u, L.f, L.g, L.P, Z.order, hoz_pu(Z, p), hoz_pf(Z, p), L.uold, st);   // 3-5
     const int* lo = p == 1 ? Z.base_cov_lo : Z.pat[p - 2].cov_lo;
     const int* cn = p == 1 ? Z.base_cov_n : Z.pat[p - 2].cov_n;
     const int nb3[3] = {Z.N0, Z.N0, Z.N0};
     launch_hoz_fas(hoz_pu(Z, p), hoz_pf(Z, p), p == 1 ? nb3 : Z.pat[p - 2].P.n, p == 1, lo, cn, 2.0 * L.P.h, Z.order,
                    st);                                                            // step 6
-    hoz_vcycle(Z, p - 1, nu1, nu2, st);                                            // step 7
+    hoz_vcycle(Z, p - 1, nu1, nu2, st, kept);                                      // step 7
     launch_hoz_prolong(L.u, L.P, hoz_pu(Z, p), L.uold, st);                        // step 8
     hoz_smooth(Z, p, nu2, st);                                                     // step 9
 }
@@ -2355,9 +2359,10 @@ int mg_solve_hierarchy_ho(const mg_hier* hier, int order, const double* const* f
     for (int p = 1; p <= Z.np; ++p) upc += (long long)(o->nu1 + o->nu2) * (long long)cells(p);
     double rel = NAN, prev = INFINITY;
     int grow = 0, status = MG_ENOCONV, cycles = 0;
+    bool kept = false;   // the parent parts kept by the last V-cycle's post-smoothing are current
     auto check = [&]() -> int {
         hoz_restrict_up(Z, false, st);
-        hoz_composite_sq(Z, 1, 2, st);
+        hoz_composite_sq(Z, 1, 2, st, kept);
         double r2;
         if (int e = hoz_read(Z.scal + 2, 1, &r2, st)) return e;
         rel = fnorm2 > 0 ? std::sqrt(r2 / fnorm2) : 0.0;
@@ -2374,7 +2379,8 @@ int mg_solve_hierarchy_ho(const mg_hier* hier, int order, const double* const* f
         if (c == MG_OK || c == MG_EDIVERGED) status = c;
     }
     while (status == MG_ENOCONV && cycles < o->max_cycles) {
-        hoz_vcycle(Z, Z.np, o->nu1, o->nu2, st);
+        hoz_vcycle(Z, Z.np, o->nu1, o->nu2, st, kept);
+        kept = o->nu2 > 0;
         ++cycles;
         S.cell_updates += upc;
         if (fixed) continue;
