@@ -499,8 +499,8 @@ __device__ __forceinline__ double hoz_off(const double* __restrict__ v, const do
 // of them along c, so every value is formed with the operations of the direct double sum.
 // The parent's part of a ghost column - its R parallel values A and the R parent cells O in
 // front of its group - does not change while the patch alone is smoothed: MODE 1 also stores it
-// in part (2R planes of one value per face column, [m][column]), MODE 2 reads it from there and
-// stages nothing.
+// in part (2R doubles per face column, [column][m]), MODE 2 reads it from there and stages
+// nothing.
 template <int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__ pu, const double* __restrict__ u,
                                                       double* __restrict__ g, double* __restrict__ part, HozPatch P,
@@ -553,23 +553,49 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
             }
         }
         double v[2 * R];
+        if (MODE != 0 && a == 2) {
+            // z faces of the workspace arrays (modes 1 and 2): the column's 2R cells are contiguous
+            // in z and come as R 16-byte pairs (rows of even length)
+            const double* col = u + hoz_nat(n, 2 * J + jb, 2 * K + kc, 0);
 #pragma unroll
-        for (int i = 0; i < 2 * R; ++i) {
-            int p3[3];
-            p3[a] = side ? n[a] - 1 - i : i;
-            p3[b] = 2 * J + jb;
-            p3[c] = 2 * K + kc;
-            v[i] = u[hoz_nat(n, p3[0], p3[1], p3[2])];
+            for (int m = 0; m < R; ++m) {
+                if (side) {
+                    const double2 pr = *(const double2*)(col + (n[2] - 2 - 2 * m));
+                    v[2 * m] = pr.y;
+                    v[2 * m + 1] = pr.x;
+                } else {
+                    const double2 pr = *(const double2*)(col + 2 * m);
+                    v[2 * m] = pr.x;
+                    v[2 * m + 1] = pr.y;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) {
+                int p3[3];
+                p3[a] = side ? n[a] - 1 - i : i;
+                p3[b] = 2 * J + jb;
+                p3[c] = 2 * K + kc;
+                v[i] = u[hoz_nat(n, p3[0], p3[1], p3[2])];
+            }
         }
-        // position of this lane's column among the face's columns (the ghost layers' indexing)
-        const size_t ncol = hoz_face_off(n, 1, 6);
+        // this lane's column among the face's columns (the ghost layers' indexing); its part is
+        // the 2R doubles A[0 .. R), O[0 .. R) at part + 2R ci, read and written as R pairs
         const size_t ci = hoz_face_off(n, 1, face) + (size_t)(2 * J + jb) * n[c] + (2 * K + kc);
+        double* pc = part + 2 * R * ci;
         double A[R], O[R];
         if constexpr (MODE == 2) {
+            double e[2 * R];
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const double2 pr = *(const double2*)(pc + 2 * m);
+                e[2 * m] = pr.x;
+                e[2 * m + 1] = pr.y;
+            }
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                A[k] = part[(size_t)k * ncol + ci];
-                O[k] = part[(size_t)(R + k) * ncol + ci];
+                A[k] = e[k];
+                O[k] = e[R + k];
             }
         } else {
         if (K0) __syncthreads();              // the previous pass has read S and T
@@ -598,12 +624,16 @@ __global__ __launch_bounds__(kBlock) void k_hoz_ghost(const double* __restrict__
             A[k] = acc;
             O[k] = S[k][R][Kl + R];
         }
-        if (MODE == 1 && live)
+        if (MODE == 1 && live) {
+            double e[2 * R];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                part[(size_t)k * ncol + ci] = A[k];
-                part[(size_t)(R + k) * ncol + ci] = O[k];
+                e[k] = A[k];
+                e[R + k] = O[k];
             }
+#pragma unroll
+            for (int m = 0; m < R; ++m) *(double2*)(pc + 2 * m) = make_double2(e[2 * m], e[2 * m + 1]);
+        }
         }
         double g0[R];
 #pragma unroll
