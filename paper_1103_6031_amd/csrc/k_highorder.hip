@@ -103,17 +103,14 @@ __global__ __launch_bounds__(kBlock) void k_ho_half(const T* __restrict__ in, T*
 // (29 KB of LDS at 256^3 FP64, order 6) measured best: 16 rows 116 us, 8 rows 109 us, 4 rows
 // 111 us at 256^3 (order 6, FP64): the halo rows cost less than the blocks per CU gained.
 constexpr int kHoTy = 8;
+
+// Rows y0 - R .. y0 + kHoTy + R - 1 of plane x (all z, wrapped in y) into rows[kHoTy + 2R][n], as
+// 16-byte pairs; each thread's loads go in batches of 8 before their LDS writes (so that they
+// are in flight together).  The caller synchronises the block afterwards.
 template <int R, class T>
-__global__ __launch_bounds__(kBlock) void k_ho_half_lds(const T* __restrict__ in, T* __restrict__ out,
-                                                        const T* __restrict__ f, int lg, T h2, int colour) {
-    extern __shared__ __align__(16) unsigned char ho_smem[];
-    T* rows = (T*)ho_smem;                          // [kHoTy + 2R][n]
+__device__ __forceinline__ void ho_stage_rows(T* __restrict__ rows, const T* __restrict__ in, unsigned x,
+                                              unsigned y0, int lg) {
     const unsigned n = 1u << lg, m = n - 1, nh = n >> 1;
-    const unsigned tiles = n / kHoTy;
-    const unsigned bl = ho_xcd_group(blockIdx.x, lg - 3);   // consecutive tiles of a plane on one XCD
-    const unsigned x = bl / tiles, y0 = (bl - x * tiles) * kHoTy;
-    // stage rows y0 - R .. y0 + kHoTy + R - 1 as 16-byte pairs, each thread's loads in batches
-    // of 8 before their LDS writes (so that they are in flight together)
     constexpr int kBatch = 8;
     const unsigned npairs = (unsigned)(kHoTy + 2 * R) * nh;
     for (unsigned t0 = threadIdx.x; t0 < npairs; t0 += kBatch * blockDim.x) {
@@ -137,6 +134,18 @@ __global__ __launch_bounds__(kBlock) void k_ho_half_lds(const T* __restrict__ in
             }
         }
     }
+}
+
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_ho_half_lds(const T* __restrict__ in, T* __restrict__ out,
+                                                        const T* __restrict__ f, int lg, T h2, int colour) {
+    extern __shared__ __align__(16) unsigned char ho_smem[];
+    T* rows = (T*)ho_smem;                          // [kHoTy + 2R][n]
+    const unsigned n = 1u << lg, m = n - 1, nh = n >> 1;
+    const unsigned tiles = n / kHoTy;
+    const unsigned bl = ho_xcd_group(blockIdx.x, lg - 3);   // consecutive tiles of a plane on one XCD
+    const unsigned x = bl / tiles, y0 = (bl - x * tiles) * kHoTy;
+    ho_stage_rows<R, T>(rows, in, x, y0, lg);
     __syncthreads();
     const unsigned pairs = (unsigned)kHoTy * nh;
     for (unsigned t = threadIdx.x; t < pairs; t += blockDim.x) {
@@ -196,6 +205,44 @@ __device__ __forceinline__ v2_t<T> ho_pair_resid(const T* __restrict__ u, const 
     return mk2<T>(fv.x - (acc[0] + w0x3 * u0) / h2, fv.y - (acc[1] + w0x3 * u1) / h2);
 }
 
+// ho_pair_resid with the y and z neighbours from rows staged by ho_stage_rows: `row` is the
+// staged row of y (R rows after the first staged one); the 2R x-neighbour pairs and f come from
+// memory.  The same arithmetic in the same order, so the same bits.
+template <int R, class T>
+__device__ __forceinline__ v2_t<T> ho_pair_resid_lds(const T* __restrict__ row, const T* __restrict__ u,
+                                                     const T* __restrict__ f, unsigned x, unsigned y,
+                                                     unsigned z0, int lg, T h2, v2_t<T>* own) {
+    constexpr int J = (R + 1) / 2;
+    const unsigned n = 1u << lg, m = n - 1;
+    T zr[4 * J + 2];
+#pragma unroll
+    for (int j = -J; j <= J; ++j) {
+        const v2_t<T> v = *(const v2_t<T>*)(row + ((z0 + 2 * j) & m));
+        zr[2 * (j + J)] = v.x;
+        zr[2 * (j + J) + 1] = v.y;
+    }
+    T acc[2] = {0, 0};
+#pragma unroll
+    for (int s = 1; s <= R; ++s) {
+        const v2_t<T> xm = *(const v2_t<T>*)(u + ho_idx((x - s) & m, y, z0, lg));
+        const v2_t<T> xp = *(const v2_t<T>*)(u + ho_idx((x + s) & m, y, z0, lg));
+        const v2_t<T> ym = *(const v2_t<T>*)(row - s * (int)n + z0);   // rows y - s, y + s
+        const v2_t<T> yp = *(const v2_t<T>*)(row + s * (int)n + z0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const T px = (c ? xm.y : xm.x) + (c ? xp.y : xp.x);
+            const T py = (c ? ym.y : ym.x) + (c ? yp.y : yp.x);
+            const T pz = zr[2 * J + c - s] + zr[2 * J + c + s];
+            acc[c] += (T)ho_w<R>(s) * ((px + py) + pz);
+        }
+    }
+    const v2_t<T> fv = *(const v2_t<T>*)(f + ho_idx(x, y, z0, lg));
+    const T u0 = zr[2 * J], u1 = zr[2 * J + 1];
+    const T w0x3 = (T)3 * (T)HoW<R>::w0;
+    *own = mk2<T>(u0, u1);
+    return mk2<T>(fv.x - (acc[0] + w0x3 * u0) / h2, fv.y - (acc[1] + w0x3 * u1) / h2);
+}
+
 // steps 3-5 for one coarse cell: the mean of the 8 children's residuals and of their values
 template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_ho_resid_restrict(const T* __restrict__ u, const T* __restrict__ f,
@@ -222,6 +269,65 @@ __global__ __launch_bounds__(kBlock) void k_ho_resid_restrict(const T* __restric
     uc[t] = um;
     uold[t] = um;
     rc[t] = rs * (T)0.125;
+}
+
+// k_ho_resid_restrict with the fine rows staged in LDS: a block owns coarse plane X and coarse
+// rows Y0 .. Y0 + kHoTy / 2 - 1 (fine rows y0 = 2 Y0 .. y0 + kHoTy - 1), stages fine plane 2X, then
+// 2X + 1, into the same rows (ho_stage_rows), and each thread keeps the sums of its coarse cells
+// over both planes: children in the order of k_ho_resid_restrict, so the same bits.  For fine
+// sizes 16 <= n <= 256 (at most 2 coarse cells per thread).
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_ho_resid_restrict_lds(const T* __restrict__ u, const T* __restrict__ f,
+                                                                  T* __restrict__ uc, T* __restrict__ uold,
+                                                                  T* __restrict__ rc, int lgc, T h2) {
+    extern __shared__ __align__(16) unsigned char ho_smem[];
+    T* rows = (T*)ho_smem;                           // [kHoTy + 2R][n]
+    constexpr int kC = 2;
+    const int lg = lgc + 1;
+    const unsigned n = 1u << lg, nc = n >> 1;
+    const unsigned tiles = n / kHoTy;
+    const unsigned bl = ho_xcd_group(blockIdx.x, lg - 3);
+    const unsigned X = bl / tiles, y0 = (bl - X * tiles) * kHoTy;
+    const unsigned cells = (unsigned)(kHoTy / 2) * nc;
+    T rs[kC], us[kC];
+#pragma unroll
+    for (int k = 0; k < kC; ++k) rs[k] = us[k] = (T)0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (a) __syncthreads();                      // every read of plane 2X done
+        ho_stage_rows<R, T>(rows, u, 2 * X + a, y0, lg);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kC; ++k) {
+            const unsigned c = threadIdx.x + k * blockDim.x;
+            if (c < cells) {
+                const unsigned yl = c / nc, Z = c - yl * nc;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const unsigned ry = 2 * yl + b;
+                    v2_t<T> uv;
+                    const v2_t<T> r = ho_pair_resid_lds<R, T>(rows + (ry + R) * n, u, f, 2 * X + a, y0 + ry,
+                                                              2 * Z, lg, h2, &uv);
+                    rs[k] += r.x;
+                    us[k] += uv.x;
+                    rs[k] += r.y;
+                    us[k] += uv.y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kC; ++k) {
+        const unsigned c = threadIdx.x + k * blockDim.x;
+        if (c < cells) {
+            const unsigned yl = c / nc, Z = c - yl * nc;
+            const unsigned t = ho_idx(X, y0 / 2 + yl, Z, lgc);
+            const T um = us[k] * (T)0.125;
+            uc[t] = um;
+            uold[t] = um;
+            rc[t] = rs[k] * (T)0.125;
+        }
+    }
 }
 
 // step 6: fc = rc + L uc, in place over rc
@@ -332,6 +438,39 @@ __global__ __launch_bounds__(kBlock) void k_ho_resid32(const double* __restrict_
     if (threadIdx.x == 0) part[bl] = s;
 }
 
+// r = f - L u over a block's rows, staged as in k_ho_half_lds (rows y0 - R .. y0 + kHoTy + R - 1 of
+// plane x in LDS; the 2R x-neighbour pairs and f from memory), with the arithmetic of
+// ho_pair_resid, so every r has the same bits.  The block's sum of r^2 goes to part at its tile
+// index (kHoTy rows of a plane, n^2 / kHoTy tiles in all); kR32 also writes r as FP32 (the
+// right-hand side of the mixed-precision inner cycles).  For 16 <= n <= 256, like the half-sweep.
+template <int R, bool kR32>
+__global__ __launch_bounds__(kBlock) void k_ho_resid_lds(const double* __restrict__ u, const double* __restrict__ f,
+                                                         float* __restrict__ r32, int lg, double h2,
+                                                         double* __restrict__ part) {
+    extern __shared__ __align__(16) unsigned char ho_smem[];
+    double* rows = (double*)ho_smem;                 // [kHoTy + 2R][n]
+    const unsigned n = 1u << lg, nh = n >> 1;
+    const unsigned tiles = n / kHoTy;
+    const unsigned bl = ho_xcd_group(blockIdx.x, lg - 3);
+    const unsigned x = bl / tiles, y0 = (bl - x * tiles) * kHoTy;
+    ho_stage_rows<R, double>(rows, u, x, y0, lg);
+    __syncthreads();
+    double acc2 = 0.0;
+    const unsigned pairs = (unsigned)kHoTy * nh;
+    for (unsigned t = threadIdx.x; t < pairs; t += blockDim.x) {
+        const unsigned ry = t / nh, pz = t - ry * nh;
+        const unsigned y = y0 + ry, z0 = 2 * pz;
+        double2 uv;
+        const double2 r = ho_pair_resid_lds<R, double>(rows + (ry + R) * n, u, f, x, y, z0, lg, h2, &uv);
+        const double r0 = r.x, r1 = r.y;
+        if constexpr (kR32) *(float2*)(r32 + ho_idx(x, y, z0, lg)) = make_float2((float)r0, (float)r1);
+        acc2 += r0 * r0;
+        acc2 += r1 * r1;
+    }
+    const double s = ho_block_sum(acc2);
+    if (threadIdx.x == 0) part[bl] = s;
+}
+
 // mixed precision: u += e (the FP32 correction)
 __global__ __launch_bounds__(kBlock) void k_ho_add32(double* __restrict__ u, const float* __restrict__ e, int lg) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -375,6 +514,17 @@ void launch_ho_half(const T* in, T* out, const T* f, int lg, double h, int order
 template <class T>
 void launch_ho_resid_restrict(const T* u, const T* f, T* uc, T* uold, T* rc, int lgc, double h, int order,
                               hipStream_t st) {
+    if (lgc >= 3 && lgc <= 7) {   // fine 16^3 .. 256^3: rows staged in LDS
+        const unsigned n = 2u << lgc;
+        const unsigned blocks = (n / 2) * (n / kHoTy);
+        const T h2 = (T)(h * h);
+        const int R = order / 2;
+        const size_t lds = (size_t)(kHoTy + 2 * R) * n * sizeof(T);
+        if (order == 2) k_ho_resid_restrict_lds<1, T><<<blocks, kBlock, lds, st>>>(u, f, uc, uold, rc, lgc, h2);
+        else if (order == 4) k_ho_resid_restrict_lds<2, T><<<blocks, kBlock, lds, st>>>(u, f, uc, uold, rc, lgc, h2);
+        else k_ho_resid_restrict_lds<3, T><<<blocks, kBlock, lds, st>>>(u, f, uc, uold, rc, lgc, h2);
+        return;
+    }
     HO_DISPATCH(order, k_ho_resid_restrict, T, grid_for((size_t)1 << (3 * lgc)), u, f, uc, uold, rc, lgc,
                 (T)(h * h));
 }
@@ -405,10 +555,29 @@ void launch_ho_fill(T* a, int lg, T v, hipStream_t st) {
 HO_INST(double)
 HO_INST(float)
 
+// The residual and its squared sum by the staged kernel on 16^3 .. 256^3 (n^2 / kHoTy <= kHoParts
+// partial sums); false (nothing launched) on other sizes.
+static_assert(256 * (256 / kHoTy) <= kHoParts, "one partial sum per staged tile at 256^3");
+template <bool kR32>
+static bool launch_ho_resid_lds(const double* u, const double* f, float* r32, int lg, double h2, int order,
+                                double* part, double* out, hipStream_t st) {
+    if (lg < 4 || lg > 8) return false;
+    const unsigned n = 1u << lg;
+    const unsigned blocks = n * (n / kHoTy);
+    const int R = order / 2;
+    const size_t lds = (size_t)(kHoTy + 2 * R) * n * sizeof(double);
+    if (order == 2) k_ho_resid_lds<1, kR32><<<blocks, kBlock, lds, st>>>(u, f, r32, lg, h2, part);
+    else if (order == 4) k_ho_resid_lds<2, kR32><<<blocks, kBlock, lds, st>>>(u, f, r32, lg, h2, part);
+    else k_ho_resid_lds<3, kR32><<<blocks, kBlock, lds, st>>>(u, f, r32, lg, h2, part);
+    k_ho_reduce<<<1, kBlock, 0, st>>>(part, (int)blocks, out);
+    return true;
+}
+
 void launch_ho_resid32(const double* u, const double* f, float* r32, int lg, double h, int order, double* part,
                        double* out, hipStream_t st) {
-    const int nb = ho_parts(lg);
     const double h2 = h * h;
+    if (launch_ho_resid_lds<true>(u, f, r32, lg, h2, order, part, out, st)) return;
+    const int nb = ho_parts(lg);
     if (order == 2) k_ho_resid32<1><<<nb, kBlock, 0, st>>>(u, f, r32, lg, h2, part);
     else if (order == 4) k_ho_resid32<2><<<nb, kBlock, 0, st>>>(u, f, r32, lg, h2, part);
     else k_ho_resid32<3><<<nb, kBlock, 0, st>>>(u, f, r32, lg, h2, part);
@@ -434,8 +603,9 @@ void launch_ho_sub(const double* a, const double* sum, double* out, int lg, doub
 
 void launch_ho_rnorm(const double* u, const double* f, int lg, double h, int order, double* part, double* out,
                      hipStream_t st) {
-    const int nb = ho_parts(lg);
     const double h2 = h * h;
+    if (launch_ho_resid_lds<false>(u, f, nullptr, lg, h2, order, part, out, st)) return;
+    const int nb = ho_parts(lg);
     if (order == 2) k_ho_psum<1, 1><<<nb, kBlock, 0, st>>>(u, f, lg, h2, part);
     else if (order == 4) k_ho_psum<2, 1><<<nb, kBlock, 0, st>>>(u, f, lg, h2, part);
     else k_ho_psum<3, 1><<<nb, kBlock, 0, st>>>(u, f, lg, h2, part);
