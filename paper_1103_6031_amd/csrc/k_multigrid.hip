@@ -77,6 +77,20 @@ __device__ __forceinline__ size_t pidx(const ParentMap& pm, int X, int Y, int Z)
 // chunk instead was no faster.)
 __device__ __forceinline__ unsigned red_lo(unsigned blk) { return blk * blockDim.x * kRedV; }
 __device__ __forceinline__ unsigned red_stride(unsigned nblk) { return nblk * blockDim.x * kRedV; }
+// The reductions that read neighbours (residuals, the outer step) give each block one contiguous
+// range of whole passes (blockDim.x * kRedV cells each) instead of striding over the grid: the
+// rows above and below a block's rows are its own, and the neighbour planes are read by blocks a
+// plane's range away, dispatched at about the same time (on the same XCD when that distance is a
+// multiple of 8), so they are still in L2.  Fixed by (blk, nblk, n), so the sums stay deterministic.
+struct RedRange {
+    unsigned lo, hi, stride;
+};
+__device__ __forceinline__ RedRange red_range(unsigned blk, unsigned nblk, unsigned n) {
+    const unsigned per = blockDim.x * kRedV;
+    const unsigned passes = ((n + per - 1) / per + nblk - 1) / nblk;
+    const unsigned lo = blk * passes * per;
+    return RedRange{lo, lo < n ? min(n, lo + passes * per) : n, per};
+}
 
 // ----------------------------------------------------------------------------------------------
 // deterministic block reduction (wave64 shuffle, then the waves in order)
@@ -1035,7 +1049,8 @@ __device__ __forceinline__ double body_residual(const T* __restrict__ u, const T
                                                 R* __restrict__ rout, const Lay& LR, unsigned blk, unsigned nblk) {
     double acc = 0.0;
     const size_t n = L.d.cells();
-    const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
+    const RedRange rr = red_range(blk, nblk, (unsigned)n);
+    const unsigned lo = rr.lo, hi = rr.hi, stride = rr.stride;
     for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV; ++v) {
@@ -1068,16 +1083,17 @@ __device__ __forceinline__ double body_residual_split(const T* __restrict__ u, c
     const Dims d = L.d;
     const unsigned n = (unsigned)d.cells(), nz = (unsigned)d.z, nzh = nz >> 1;
     double acc = 0.0;
-    const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
+    const RedRange rr = red_range(blk, nblk, (unsigned)n);
+    const unsigned lo = rr.lo, hi = rr.hi, stride = rr.stride;
     // FP64, no covered box, no output and even half-rows: pairs of cells with 16-byte runs (the
     // loads of the outer step's pairs), each cell with the same operations as below
     if constexpr (sizeof(T) == 8) {
         if (!rout && (cb.n[0] <= 0 || cb.n[1] <= 0 || cb.n[2] <= 0) && (nzh & 1u) == 0) {
-            for (unsigned p0 = lo; p0 < n; p0 += stride)
+            for (unsigned p0 = lo; p0 < hi; p0 += stride)
 #pragma unroll
             for (int v = 0; v < kRedV / 2; ++v) {
                 const unsigned t = p0 + 2 * (threadIdx.x + v * blockDim.x);
-                if (t >= n) break;
+                if (t >= hi) break;
                 const SplitNb c = split_nb(L, t);
                 const unsigned j = c.j, oth = c.oth, r0 = c.r0, q = (unsigned)c.q;
                 const double2 fv = *(const double2*)(f + t);
@@ -1151,7 +1167,8 @@ __device__ __forceinline__ double body_outer_split(const double* __restrict__ u_
     const Dims d = L.d;
     const unsigned n = (unsigned)d.cells();
     double acc = 0.0;
-    const unsigned lo = red_lo(blk), hi = (unsigned)n, stride = red_stride(nblk);
+    const RedRange rr = red_range(blk, nblk, (unsigned)n);
+    const unsigned lo = rr.lo, hi = rr.hi, stride = rr.stride;
     for (unsigned b0 = lo + threadIdx.x; b0 < hi; b0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV; ++v) {
@@ -1195,12 +1212,13 @@ __device__ __forceinline__ double body_outer_pairs(const double* __restrict__ u_
                                                    const Lay& L, double h2, float h2f, unsigned blk, unsigned nblk) {
     const unsigned n = (unsigned)L.d.cells(), nzh = (unsigned)L.d.z >> 1;
     double acc = 0.0;
-    const unsigned lo = red_lo(blk), stride = red_stride(nblk);
-    for (unsigned p0 = lo; p0 < n; p0 += stride)
+    const RedRange rr = red_range(blk, nblk, n);
+    const unsigned lo = rr.lo, hi = rr.hi, stride = rr.stride;
+    for (unsigned p0 = lo; p0 < hi; p0 += stride)
 #pragma unroll
     for (int v = 0; v < kRedV / 2; ++v) {
         const unsigned t = p0 + 2 * (threadIdx.x + v * blockDim.x);
-        if (t >= n) break;
+        if (t >= hi) break;
         const SplitNb c = split_nb(L, t);
         const unsigned j = c.j, oth = c.oth, r0 = c.r0, q = (unsigned)c.q;
         // every load of the pair is issued before the first value is formed (a scheduling barrier
